@@ -1,0 +1,172 @@
+/*
+ * dfmi.h -- C ABI of the density-fitting contraction library for AMD MI355X (gfx950).
+ *
+ * The library evaluates the contractions of the packed three-index Cholesky
+ * tensor b^P_{mu nu} that density-fitted LASSCF spends its time in
+ * (Agarawal et al., arXiv 2505.03755, Sec. "Identification of computational
+ * bottlenecks" and "Analysis of computational bottlenecks"):
+ *
+ *   df_half_transform   Eq. (ao2mo_1), optionally followed by Eq. (ao2mo_2)
+ *   df_jk               the "JK call": Eqs. (J_1), (J_2), (K_1), (K_2)
+ *   df_active_eri       (uv|wx), the active-space ERIs of the recombination step (Eq. flas)
+ *   df_papa             (pu|vw), the g^{p a}_{a a} pattern of the orbital gradient (Eq. MO_conv);
+ *                       with DF_PAPA_FULL the (pu|qv) block of Eq. (papa)
+ *   df_step             all of the above from one shared half transform
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every array argument is a DEVICE pointer (memory of the context's GPU), holding
+ *    IEEE float64 values, row major and contiguous.  Sizes are int64_t.
+ *  - B is the packed Cholesky tensor, shape [naux][nao*(nao+1)/2], P-major:
+ *        B[P*npair + i*(i+1)/2 + j] = b^P_{ij} = b^P_{ji},   i >= j
+ *    (the lower-triangular storage of the paper, Sec. "Calculation of effective potentials").
+ *  - Densities are passed in factored form, D = C diag(w) C^T, C [nao][nocc].  No spin
+ *    factor is applied anywhere: J = J[D] and K = K[D] exactly as in Eqs. (J_1)-(K_2).
+ *  - The caller owns every buffer.  Calls that need scratch memory take it from the
+ *    workspace attached with df_set_workspace; its size comes from df_workspace_size.
+ *    The library never allocates device memory during a call.
+ *  - Calls are asynchronous on the context's stream: they return once the work is
+ *    enqueued, and every buffer must stay valid until the stream has drained.
+ *    Two calls that share one context (and hence one workspace) must not overlap.
+ *  - Outputs are overwritten.  Inputs, outputs and the workspace must not overlap.
+ *  - All arguments are checked before anything is enqueued; on an error return no
+ *    output and no workspace byte has been touched, and df_last_error() describes it.
+ *  - nocc = 0 or nac = 0 are valid and give zero-sized or zero-valued outputs;
+ *    nao >= 1 and naux >= 1 are required.
+ */
+#ifndef DFMI_H
+#define DFMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct df_ctx df_ctx;
+
+typedef enum df_status {
+  DF_OK = 0,
+  DF_ERR_ARG = -1,          /* null pointer where one is required, overlap, bad context */
+  DF_ERR_SHAPE = -2,        /* negative or unsupported size */
+  DF_ERR_WORKSPACE = -3,    /* no workspace attached, or smaller than df_workspace_size */
+  DF_ERR_HIP = -4,          /* a HIP runtime call failed (message has the HIP error) */
+  DF_ERR_UNSUPPORTED = -5   /* unknown flag bit or operation */
+} df_status;
+
+/* Operations, for df_workspace_size. */
+typedef enum df_op {
+  DF_OP_HALF_TRANSFORM = 1,
+  DF_OP_JK = 2,
+  DF_OP_ACTIVE_ERI = 3,
+  DF_OP_PAPA = 4,
+  DF_OP_STEP = 5
+} df_op;
+
+/* Flag bits. */
+#define DF_PAPA_FULL 0x1   /* df_papa: return (pu|qv) of Eq. (papa) instead of (pu|vw) */
+
+/* Problem sizes for df_workspace_size; fields an operation does not use are ignored. */
+typedef struct df_dims {
+  int64_t naux, nao;
+  int64_t ndm;    /* number of densities in a JK call (>= 1) */
+  int64_t nocc;   /* columns of each density factor */
+  int64_t nac;    /* active orbitals */
+  int64_t np;     /* columns of Cp (MO space p) */
+  int64_t nq;     /* columns of Cq (DF_PAPA_FULL only) */
+  int64_t ncol;   /* columns of C in df_half_transform */
+  int64_t n2;     /* columns of C2 in df_half_transform (0 if no second transform) */
+  int flags;
+} df_dims;
+
+/* Create a context on HIP device `device` that enqueues onto `stream`
+ * (a hipStream_t; NULL means the null stream).  *ctx is set on success.  No HIP call is
+ * made here: the device is selected by the first call that enqueues work, and an invalid
+ * device is reported there as DF_ERR_HIP. */
+df_status df_create(df_ctx** ctx, int device, void* stream);
+
+/* Destroy a context (NULL is allowed).  Does not free the attached workspace. */
+df_status df_destroy(df_ctx* ctx);
+
+/* Message of the last error on this context ("" if none).  The string is owned by the
+ * context and valid until its next call.  With ctx == NULL: the last df_create error. */
+const char* df_last_error(const df_ctx* ctx);
+
+/* Change the stream later calls enqueue onto. */
+df_status df_set_stream(df_ctx* ctx, void* stream);
+
+/* Attach caller-owned device memory of `bytes` bytes as the workspace (NULL, 0 detaches). */
+df_status df_set_workspace(df_ctx* ctx, void* ptr, size_t bytes);
+
+/* Bytes of workspace that operation `op` needs for the sizes in *dims. */
+df_status df_workspace_size(df_op op, const df_dims* dims, size_t* bytes);
+
+/*
+ * Half transform, Eq. (ao2mo_1):       X[P][mu][c] = sum_nu b^P_{mu nu} C[nu][c]
+ * and optionally Eq. (ao2mo_2):        Y[P][p][c]  = sum_mu C2[mu][p] X[P][mu][c]
+ *
+ *   B  [naux][npair]      packed Cholesky vectors (input)
+ *   C  [nao][ncol]        coefficients (input), ncol >= 1
+ *   X  [naux][nao][ncol]  output; the untransformed AO index comes first, as in b^P_{e2 p1}
+ *   C2 [nao][n2], Y [naux][n2][ncol]  both NULL (n2 = 0) or both given
+ * Workspace: none.
+ */
+df_status df_half_transform(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
+                            const double* C, int64_t ncol, double* X,
+                            const double* C2, int64_t n2, double* Y, int flags);
+
+/*
+ * JK call for ndm densities D_k = C_k diag(w_k) C_k^T (Eqs. J_1, J_2, K_1, K_2):
+ *   v[k][P] = sum_{ij} b^P_{ij} (D_k)_{ij}
+ *   J[k]    = sum_P v[k][P] b^P
+ *   K[k]    = sum_P (b^P C_k) diag(w_k) (b^P C_k)^T      (= sum_P b^P D_k b^P)
+ *
+ *   Cocc [ndm][nao][nocc]  density factors (input)
+ *   w    [ndm][nocc]       signed occupation weights, or NULL for all ones
+ *   J, K [ndm][nao][nao]   outputs (symmetric, both triangles written); either may be NULL
+ *   v    [ndm][naux]       output, or NULL
+ * Workspace: df_workspace_size(DF_OP_JK, {naux, nao, ndm, nocc}).
+ */
+df_status df_jk(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int64_t ndm,
+                const double* Cocc, int64_t nocc, const double* w,
+                double* J, double* K, double* v, int flags);
+
+/*
+ * Active-space ERIs:  b_uv[P][u][v] = (Cact^T b^P Cact)_{uv},
+ *                     eri[u][v][w][x] = sum_P b_uv[P][u][v] b_uv[P][w][x]
+ *   Cact [nao][nac] (input); eri [nac]^4 (output); buv [naux][nac][nac] (output or NULL)
+ * Workspace: df_workspace_size(DF_OP_ACTIVE_ERI, {naux, nao, nac}).
+ */
+df_status df_active_eri(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
+                        const double* Cact, int64_t nac, double* eri, double* buv, int flags);
+
+/*
+ * papa block.  b_pu[P] = Cp^T b^P Cact, b_vw[P] = Cact^T b^P Cact.
+ *   default:       out[p][u][v][w] = (pu|vw) = sum_P b_pu[P][p][u] b_vw[P][v][w]
+ *                  (Cq must be NULL, nq = 0);  out is [np][nac][nac][nac]
+ *   DF_PAPA_FULL:  out[p][u][q][v] = (pu|qv) = sum_P b_pu[P][p][u] b_qv[P][q][v]   (Eq. papa)
+ *                  with b_qv[P] = Cq^T b^P Cact;  out is [np][nac][nq][nac]
+ *   Cp [nao][np], Cact [nao][nac], Cq [nao][nq] (inputs)
+ * Workspace: df_workspace_size(DF_OP_PAPA, {naux, nao, nac, np, nq, flags}).
+ */
+df_status df_papa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
+                  const double* Cp, int64_t np, const double* Cact, int64_t nac,
+                  const double* Cq, int64_t nq, double* out, int flags);
+
+/*
+ * One forward pass of the whole path from a single half transform X = b^P [Cocc | Cact]:
+ * J, K and v of D = Cocc diag(w) Cocc^T (as df_jk with ndm = 1), eri = (uv|wx) and
+ * papa = (pu|vw) (as df_active_eri and df_papa).  Any output pointer may be NULL.
+ * Workspace: df_workspace_size(DF_OP_STEP, {naux, nao, 1, nocc, nac, np}).
+ */
+df_status df_step(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
+                  const double* Cocc, int64_t nocc, const double* w,
+                  const double* Cact, int64_t nac, const double* Cp, int64_t np,
+                  double* J, double* K, double* v, double* eri, double* papa, int flags);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DFMI_H */

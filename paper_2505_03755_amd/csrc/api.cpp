@@ -1,0 +1,502 @@
+// C-ABI entry points of libdfmi: argument checks, workspace planning, kernel orchestration.
+#include "dfmi.h"
+#include "kernels.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+struct df_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+constexpr int64_t kMaxNao = 46340;   // keeps packed row offsets i(i+1)/2 + j inside 31 bits
+constexpr size_t kAlign = 256;
+
+df_status fail(df_ctx* c, df_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+std::string hip_msg(hipError_t e, const char* what) {
+  return std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+}
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// A byte range of device memory the call reads or writes.
+struct Range {
+  const void* p;
+  size_t bytes;
+  const char* name;
+  bool out;
+};
+
+// Inputs may share memory with each other; an output may overlap nothing else.
+bool check_overlap(df_ctx* c, const std::vector<Range>& rs) {
+  for (size_t a = 0; a < rs.size(); ++a)
+    for (size_t b = a + 1; b < rs.size(); ++b) {
+      if (!rs[a].out && !rs[b].out) continue;
+      if (!rs[a].p || !rs[b].p || rs[a].bytes == 0 || rs[b].bytes == 0) continue;
+      const char* x0 = (const char*)rs[a].p;
+      const char* y0 = (const char*)rs[b].p;
+      if (x0 < y0 + rs[b].bytes && y0 < x0 + rs[a].bytes) {
+        c->err = std::string(rs[a].name) + " overlaps " + rs[b].name;
+        return false;
+      }
+    }
+  return true;
+}
+
+// Workspace carve-out, in the order the plan lists its pieces.
+struct Plan {
+  size_t total = 0;
+  size_t take(int64_t ndoubles) {
+    const size_t off = total;
+    total += align_up((size_t)std::max<int64_t>(ndoubles, 0) * sizeof(double));
+    return off;
+  }
+};
+
+// Offsets of the workspace pieces of each operation.
+struct JkPlan {
+  size_t ccat, x, kpart, vtmp;
+  int nsplit;
+};
+struct ActPlan {
+  size_t x, buv;
+};
+struct PapaPlan {
+  size_t x, bpu, bvw, bqv;
+};
+struct StepPlan {
+  size_t ccat, x, kpart, vtmp, bpu, buv;
+  int nsplit;
+};
+
+JkPlan plan_jk(Plan& pl, int64_t naux, int64_t nao, int64_t ndm, int64_t nocc) {
+  JkPlan p{};
+  const int64_t ncol = ndm * nocc;
+  p.ccat = pl.take(ndm > 1 ? nao * ncol : 0);
+  p.x = pl.take(naux * nao * ncol);
+  p.nsplit = dfk::syrk_splits(nao, naux, ndm);
+  p.kpart = pl.take((int64_t)p.nsplit * ndm * nao * nao);
+  p.vtmp = pl.take(ndm * naux);
+  return p;
+}
+
+ActPlan plan_act(Plan& pl, int64_t naux, int64_t nao, int64_t nac) {
+  ActPlan p{};
+  p.x = pl.take(naux * nao * nac);
+  p.buv = pl.take(naux * nac * nac);
+  return p;
+}
+
+PapaPlan plan_papa(Plan& pl, int64_t naux, int64_t nao, int64_t nac, int64_t np, int64_t nq, bool full) {
+  PapaPlan p{};
+  p.x = pl.take(naux * nao * nac);
+  p.bpu = pl.take(naux * np * nac);
+  p.bvw = pl.take(full ? 0 : naux * nac * nac);
+  p.bqv = pl.take(full ? naux * nq * nac : 0);
+  return p;
+}
+
+StepPlan plan_step(Plan& pl, int64_t naux, int64_t nao, int64_t nocc, int64_t nac, int64_t np) {
+  StepPlan p{};
+  const int64_t ncol = nocc + nac;
+  p.ccat = pl.take(nao * ncol);
+  p.x = pl.take(naux * nao * ncol);
+  p.nsplit = dfk::syrk_splits(nao, naux, 1);
+  p.kpart = pl.take((int64_t)p.nsplit * nao * nao);
+  p.vtmp = pl.take(naux);
+  p.bpu = pl.take(naux * np * nac);
+  p.buv = pl.take(naux * nac * nac);
+  return p;
+}
+
+df_status check_ctx(df_ctx* c) {
+  if (!c) return DF_ERR_ARG;
+  c->err.clear();
+  return DF_OK;
+}
+
+df_status check_core(df_ctx* c, const double* B, int64_t naux, int64_t nao) {
+  if (!B) return fail(c, DF_ERR_ARG, "B is NULL");
+  if (naux < 1 || nao < 1) return fail(c, DF_ERR_SHAPE, "naux and nao must be >= 1");
+  if (nao > kMaxNao) return fail(c, DF_ERR_SHAPE, "nao exceeds 46340");
+  return DF_OK;
+}
+
+df_status need_ws(df_ctx* c, size_t bytes) {
+  if (bytes == 0) return DF_OK;
+  if (!c->ws) return fail(c, DF_ERR_WORKSPACE, "no workspace attached (need " + std::to_string(bytes) + " bytes)");
+  if (c->ws_bytes < bytes)
+    return fail(c, DF_ERR_WORKSPACE, "workspace has " + std::to_string(c->ws_bytes) + " bytes, need " +
+                                          std::to_string(bytes));
+  return DF_OK;
+}
+
+df_status enter(df_ctx* c) {
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return fail(c, DF_ERR_HIP, hip_msg(e, "hipSetDevice"));
+  return DF_OK;
+}
+
+#define DF_HIP(call, what)                                             \
+  do {                                                                 \
+    hipError_t e_ = (call);                                            \
+    if (e_ != hipSuccess) return fail(c, DF_ERR_HIP, hip_msg(e_, what)); \
+  } while (0)
+
+size_t dbytes(int64_t n) { return (size_t)std::max<int64_t>(n, 0) * sizeof(double); }
+
+// ---- building blocks on the device ----
+
+// X (ldx columns, first ncol used) = b^P C
+df_status run_half(df_ctx* c, const double* B, int64_t naux, int64_t nao, const double* C, int64_t ldc,
+                   int64_t ncol, double* X, int64_t ldx) {
+  DF_HIP(dfk::launch_half_transform(B, naux, nao, C, ldc, ncol, X, ldx, c->stream), "half transform launch");
+  return DF_OK;
+}
+
+// out[P][p][u] = sum_mu Cl[mu][p] X[P][mu][xoff + u]  (Cl is [nao][nl], X row stride ldx)
+df_status run_mo(df_ctx* c, const double* Cl, int64_t nl, const double* X, int64_t naux, int64_t nao,
+                 int64_t ldx, int64_t xoff, int64_t nr, double* out) {
+  if (nl == 0 || nr == 0) return DF_OK;
+  dfk::OpMap A{Cl, nl, nl, 0, 1, 1, nao, 0, nl, 0, nullptr, 0};
+  dfk::OpMap Bm{X + xoff, naux * nr, nr, nao * ldx, 1, 1, nao, 0, ldx, 0, nullptr, 0};
+  dfk::OutMap O{out, nl, naux * nr, nl, 0, nr, nr, nl * nr, 1, 0};
+  DF_HIP(dfk::launch_gemm(A, Bm, O, 1, c->stream), "second transform launch");
+  return DF_OK;
+}
+
+// out[m][n] = sum_P L[P][m] R[P][n]
+df_status run_pgemm(df_ctx* c, const double* L, int64_t M, const double* R, int64_t N, int64_t naux,
+                    double* out) {
+  if (M == 0 || N == 0) return DF_OK;
+  dfk::OpMap A{L, M, M, 0, 1, 1, naux, 0, M, 0, nullptr, 0};
+  dfk::OpMap Bm{R, N, N, 0, 1, 1, naux, 0, N, 0, nullptr, 0};
+  dfk::OutMap O = dfk::out_plain(out, M, N, N);
+  DF_HIP(dfk::launch_gemm(A, Bm, O, 1, c->stream), "aux contraction launch");
+  return DF_OK;
+}
+
+// K[z] = sum_P X_z[P] diag(w_z) X_z[P]^T with X_z[P][i][c] = X[P][i][z*nocc + c]  (w may be NULL)
+df_status run_k(df_ctx* c, const double* X, const double* w, int64_t naux, int64_t nao, int64_t ldx,
+                int64_t nocc, int64_t nz, int nsplit, double* kpart, double* K) {
+  dfk::OpMap A{X, nao, nao, 0, ldx, naux, nocc, nao * ldx, 1, nocc, nullptr, 0};
+  dfk::OpMap Bw = A;
+  Bw.ks = w;
+  Bw.s_ksz = nocc;
+  DF_HIP(dfk::launch_syrk_partial(A, Bw, nao, nz, nsplit, kpart, c->stream), "K tiles launch");
+  DF_HIP(dfk::launch_syrk_reduce(kpart, nsplit, nao, nz, K, c->stream), "K reduce launch");
+  return DF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+df_status df_create(df_ctx** ctx, int device, void* stream) {
+  // No HIP call here: the device is selected (and checked) by the first call that
+  // enqueues work, so a context can be created and its argument checks exercised
+  // on a machine without a GPU.
+  g_create_err.clear();
+  if (!ctx) {
+    g_create_err = "ctx is NULL";
+    return DF_ERR_ARG;
+  }
+  *ctx = nullptr;
+  if (device < 0) {
+    g_create_err = "device must be >= 0";
+    return DF_ERR_ARG;
+  }
+  df_ctx* c = new df_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  *ctx = c;
+  return DF_OK;
+}
+
+df_status df_destroy(df_ctx* ctx) {
+  delete ctx;
+  return DF_OK;
+}
+
+const char* df_last_error(const df_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+df_status df_set_stream(df_ctx* ctx, void* stream) {
+  if (!ctx) return DF_ERR_ARG;
+  ctx->stream = (hipStream_t)stream;
+  return DF_OK;
+}
+
+df_status df_set_workspace(df_ctx* ctx, void* ptr, size_t bytes) {
+  if (!ctx) return DF_ERR_ARG;
+  if ((ptr == nullptr) != (bytes == 0)) return fail(ctx, DF_ERR_ARG, "workspace pointer and size disagree");
+  if (((uintptr_t)ptr) % kAlign != 0) return fail(ctx, DF_ERR_ARG, "workspace must be 256-byte aligned");
+  ctx->ws = (char*)ptr;
+  ctx->ws_bytes = bytes;
+  return DF_OK;
+}
+
+df_status df_workspace_size(df_op op, const df_dims* d, size_t* bytes) {
+  if (!d || !bytes) return DF_ERR_ARG;
+  *bytes = 0;
+  if (d->naux < 1 || d->nao < 1 || d->nao > kMaxNao) return DF_ERR_SHAPE;
+  if (d->ndm < 0 || d->nocc < 0 || d->nac < 0 || d->np < 0 || d->nq < 0 || d->ncol < 0 || d->n2 < 0)
+    return DF_ERR_SHAPE;
+  Plan pl;
+  switch (op) {
+    case DF_OP_HALF_TRANSFORM: break;
+    case DF_OP_JK: plan_jk(pl, d->naux, d->nao, std::max<int64_t>(d->ndm, 1), d->nocc); break;
+    case DF_OP_ACTIVE_ERI: plan_act(pl, d->naux, d->nao, d->nac); break;
+    case DF_OP_PAPA:
+      plan_papa(pl, d->naux, d->nao, d->nac, d->np, d->nq, (d->flags & DF_PAPA_FULL) != 0);
+      break;
+    case DF_OP_STEP: plan_step(pl, d->naux, d->nao, d->nocc, d->nac, d->np); break;
+    default: return DF_ERR_UNSUPPORTED;
+  }
+  *bytes = pl.total;
+  return DF_OK;
+}
+
+df_status df_half_transform(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const double* C,
+                            int64_t ncol, double* X, const double* C2, int64_t n2, double* Y, int flags) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (df_status s = check_core(c, B, naux, nao)) return s;
+  if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_half_transform takes no flags");
+  if (!C || !X) return fail(c, DF_ERR_ARG, "C and X are required");
+  if (ncol < 1) return fail(c, DF_ERR_SHAPE, "ncol must be >= 1");
+  if ((C2 == nullptr) != (Y == nullptr)) return fail(c, DF_ERR_ARG, "C2 and Y must be given together");
+  if (C2 && n2 < 1) return fail(c, DF_ERR_SHAPE, "n2 must be >= 1 when C2 is given");
+  if (!C2 && n2 != 0) return fail(c, DF_ERR_SHAPE, "n2 must be 0 without C2");
+  const int64_t npair = nao * (nao + 1) / 2;
+  std::vector<Range> rs = {{B, dbytes(naux * npair), "B", false},
+                           {C, dbytes(nao * ncol), "C", false},
+                           {X, dbytes(naux * nao * ncol), "X", true},
+                           {C2, dbytes(nao * n2), "C2", false},
+                           {Y, dbytes(naux * n2 * ncol), "Y", true}};
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (df_status s = enter(c)) return s;
+  if (df_status s = run_half(c, B, naux, nao, C, ncol, ncol, X, ncol)) return s;
+  if (C2) return run_mo(c, C2, n2, X, naux, nao, ncol, 0, ncol, Y);
+  return DF_OK;
+}
+
+df_status df_jk(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int64_t ndm, const double* Cocc,
+                int64_t nocc, const double* w, double* J, double* K, double* v, int flags) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (df_status s = check_core(c, B, naux, nao)) return s;
+  if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_jk takes no flags");
+  if (ndm < 1 || ndm > 65535) return fail(c, DF_ERR_SHAPE, "ndm must be in [1, 65535]");
+  if (nocc < 0) return fail(c, DF_ERR_SHAPE, "nocc must be >= 0");
+  if (nocc > 0 && !Cocc) return fail(c, DF_ERR_ARG, "Cocc is NULL");
+  const int64_t npair = nao * (nao + 1) / 2;
+  std::vector<Range> rs = {{B, dbytes(naux * npair), "B", false},
+                           {Cocc, dbytes(ndm * nao * nocc), "Cocc", false},
+                           {w, dbytes(ndm * nocc), "w", false},
+                           {J, dbytes(ndm * nao * nao), "J", true},
+                           {K, dbytes(ndm * nao * nao), "K", true},
+                           {v, dbytes(ndm * naux), "v", true}};
+  Plan pl;
+  const JkPlan p = plan_jk(pl, naux, nao, ndm, nocc);
+  if (nocc > 0 && (J || K || v)) {
+    if (!check_overlap(c, rs)) return DF_ERR_ARG;
+    if (df_status s = need_ws(c, pl.total)) return s;
+    rs.push_back({c->ws, pl.total, "workspace", true});
+  }
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (df_status s = enter(c)) return s;
+  if (nocc == 0) {
+    if (J) DF_HIP(dfk::launch_fill_zero(J, ndm * nao * nao, c->stream), "fill");
+    if (K) DF_HIP(dfk::launch_fill_zero(K, ndm * nao * nao, c->stream), "fill");
+    if (v) DF_HIP(dfk::launch_fill_zero(v, ndm * naux, c->stream), "fill");
+    return DF_OK;
+  }
+  if (!J && !K && !v) return DF_OK;
+  const int64_t ncol = ndm * nocc;
+  double* X = (double*)(c->ws + p.x);
+  const double* Ccat = Cocc;
+  if (ndm > 1) {
+    double* cc = (double*)(c->ws + p.ccat);
+    for (int64_t z = 0; z < ndm; ++z)
+      DF_HIP(hipMemcpy2DAsync(cc + z * nocc, ncol * sizeof(double), Cocc + z * nao * nocc, nocc * sizeof(double),
+                              nocc * sizeof(double), nao, hipMemcpyDeviceToDevice, c->stream),
+             "density factor gather");
+    Ccat = cc;
+  }
+  if (df_status s = run_half(c, B, naux, nao, Ccat, ncol, ncol, X, ncol)) return s;
+  if (J || v) {
+    double* vv = v ? v : (double*)(c->ws + p.vtmp);
+    DF_HIP(dfk::launch_jvec(X, naux, nao, ncol, Cocc, w, nocc, ndm, vv, c->stream), "J-vector launch");
+    if (J) DF_HIP(dfk::launch_coulomb(B, naux, nao, vv, ndm, J, c->stream), "Coulomb launch");
+  }
+  if (K)
+    if (df_status s = run_k(c, X, w, naux, nao, ncol, nocc, ndm, p.nsplit, (double*)(c->ws + p.kpart), K))
+      return s;
+  return DF_OK;
+}
+
+df_status df_active_eri(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const double* Cact, int64_t nac,
+                        double* eri, double* buv, int flags) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (df_status s = check_core(c, B, naux, nao)) return s;
+  if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_active_eri takes no flags");
+  if (nac < 0) return fail(c, DF_ERR_SHAPE, "nac must be >= 0");
+  if (nac > 0 && (!Cact || !eri)) return fail(c, DF_ERR_ARG, "Cact and eri are required");
+  const int64_t npair = nao * (nao + 1) / 2;
+  std::vector<Range> rs = {{B, dbytes(naux * npair), "B", false},
+                           {Cact, dbytes(nao * nac), "Cact", false},
+                           {eri, dbytes(nac * nac * nac * nac), "eri", true},
+                           {buv, dbytes(naux * nac * nac), "buv", true}};
+  Plan pl;
+  const ActPlan p = plan_act(pl, naux, nao, nac);
+  if (nac > 0) {
+    if (!check_overlap(c, rs)) return DF_ERR_ARG;
+    if (df_status s = need_ws(c, pl.total)) return s;
+    rs.push_back({c->ws, pl.total, "workspace", true});
+  }
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (nac == 0) return DF_OK;
+  if (df_status s = enter(c)) return s;
+  double* X = (double*)(c->ws + p.x);
+  double* bu = buv ? buv : (double*)(c->ws + p.buv);
+  if (df_status s = run_half(c, B, naux, nao, Cact, nac, nac, X, nac)) return s;
+  if (df_status s = run_mo(c, Cact, nac, X, naux, nao, nac, 0, nac, bu)) return s;
+  return run_pgemm(c, bu, nac * nac, bu, nac * nac, naux, eri);
+}
+
+df_status df_papa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const double* Cp, int64_t np,
+                  const double* Cact, int64_t nac, const double* Cq, int64_t nq, double* out, int flags) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (df_status s = check_core(c, B, naux, nao)) return s;
+  if (flags & ~DF_PAPA_FULL) return fail(c, DF_ERR_UNSUPPORTED, "unknown flag bits");
+  const bool full = (flags & DF_PAPA_FULL) != 0;
+  if (np < 0 || nac < 0 || nq < 0) return fail(c, DF_ERR_SHAPE, "sizes must be >= 0");
+  if (full) {
+    if (nq > 0 && !Cq) return fail(c, DF_ERR_ARG, "DF_PAPA_FULL needs Cq");
+  } else {
+    if (Cq || nq != 0) return fail(c, DF_ERR_ARG, "Cq/nq are only used with DF_PAPA_FULL");
+  }
+  const int64_t nout = full ? np * nac * nq * nac : np * nac * nac * nac;
+  if (nout > 0 && (!Cp || !Cact || !out)) return fail(c, DF_ERR_ARG, "Cp, Cact and out are required");
+  const int64_t npair = nao * (nao + 1) / 2;
+  std::vector<Range> rs = {{B, dbytes(naux * npair), "B", false},
+                           {Cp, dbytes(nao * np), "Cp", false},
+                           {Cact, dbytes(nao * nac), "Cact", false},
+                           {Cq, dbytes(nao * nq), "Cq", false},
+                           {out, dbytes(nout), "out", true}};
+  Plan pl;
+  const PapaPlan p = plan_papa(pl, naux, nao, nac, np, nq, full);
+  if (nout > 0) {
+    if (!check_overlap(c, rs)) return DF_ERR_ARG;
+    if (df_status s = need_ws(c, pl.total)) return s;
+    rs.push_back({c->ws, pl.total, "workspace", true});
+  }
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (nout == 0) return DF_OK;
+  if (df_status s = enter(c)) return s;
+  double* X = (double*)(c->ws + p.x);
+  double* bpu = (double*)(c->ws + p.bpu);
+  if (df_status s = run_half(c, B, naux, nao, Cact, nac, nac, X, nac)) return s;
+  if (df_status s = run_mo(c, Cp, np, X, naux, nao, nac, 0, nac, bpu)) return s;
+  if (full) {
+    double* bqv = (double*)(c->ws + p.bqv);
+    if (df_status s = run_mo(c, Cq, nq, X, naux, nao, nac, 0, nac, bqv)) return s;
+    return run_pgemm(c, bpu, np * nac, bqv, nq * nac, naux, out);
+  }
+  double* bvw = (double*)(c->ws + p.bvw);
+  if (df_status s = run_mo(c, Cact, nac, X, naux, nao, nac, 0, nac, bvw)) return s;
+  return run_pgemm(c, bpu, np * nac, bvw, nac * nac, naux, out);
+}
+
+df_status df_step(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const double* Cocc, int64_t nocc,
+                  const double* w, const double* Cact, int64_t nac, const double* Cp, int64_t np, double* J,
+                  double* K, double* v, double* eri, double* papa, int flags) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (df_status s = check_core(c, B, naux, nao)) return s;
+  if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_step takes no flags");
+  if (nocc < 0 || nac < 0 || np < 0) return fail(c, DF_ERR_SHAPE, "sizes must be >= 0");
+  if (nocc > 0 && !Cocc) return fail(c, DF_ERR_ARG, "Cocc is NULL");
+  if (nac > 0 && !Cact) return fail(c, DF_ERR_ARG, "Cact is NULL");
+  if (np > 0 && !Cp) return fail(c, DF_ERR_ARG, "Cp is NULL");
+  const int64_t npair = nao * (nao + 1) / 2;
+  std::vector<Range> rs = {{B, dbytes(naux * npair), "B", false},
+                           {Cocc, dbytes(nao * nocc), "Cocc", false},
+                           {w, dbytes(nocc), "w", false},
+                           {Cact, dbytes(nao * nac), "Cact", false},
+                           {Cp, dbytes(nao * np), "Cp", false},
+                           {J, dbytes(nao * nao), "J", true},
+                           {K, dbytes(nao * nao), "K", true},
+                           {v, dbytes(naux), "v", true},
+                           {eri, dbytes(nac * nac * nac * nac), "eri", true},
+                           {papa, dbytes(np * nac * nac * nac), "papa", true}};
+  Plan pl;
+  const StepPlan p = plan_step(pl, naux, nao, nocc, nac, np);
+  const int64_t ncol = nocc + nac;
+  if (ncol > 0) {
+    if (!check_overlap(c, rs)) return DF_ERR_ARG;
+    if (df_status s = need_ws(c, pl.total)) return s;
+    rs.push_back({c->ws, pl.total, "workspace", true});
+  }
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (df_status s = enter(c)) return s;
+  if (nocc == 0) {
+    if (J) DF_HIP(dfk::launch_fill_zero(J, nao * nao, c->stream), "fill");
+    if (K) DF_HIP(dfk::launch_fill_zero(K, nao * nao, c->stream), "fill");
+    if (v) DF_HIP(dfk::launch_fill_zero(v, naux, c->stream), "fill");
+  }
+  if (ncol == 0) return DF_OK;
+  double* cc = (double*)(c->ws + p.ccat);
+  if (nocc > 0)
+    DF_HIP(hipMemcpy2DAsync(cc, ncol * sizeof(double), Cocc, nocc * sizeof(double), nocc * sizeof(double), nao,
+                            hipMemcpyDeviceToDevice, c->stream),
+           "Cocc gather");
+  if (nac > 0)
+    DF_HIP(hipMemcpy2DAsync(cc + nocc, ncol * sizeof(double), Cact, nac * sizeof(double), nac * sizeof(double), nao,
+                            hipMemcpyDeviceToDevice, c->stream),
+           "Cact gather");
+  double* X = (double*)(c->ws + p.x);
+  if (df_status s = run_half(c, B, naux, nao, cc, ncol, ncol, X, ncol)) return s;
+  if (nocc > 0) {
+    if (J || v) {
+      double* vv = v ? v : (double*)(c->ws + p.vtmp);
+      DF_HIP(dfk::launch_jvec(X, naux, nao, ncol, Cocc, w, nocc, 1, vv, c->stream), "J-vector launch");
+      if (J) DF_HIP(dfk::launch_coulomb(B, naux, nao, vv, 1, J, c->stream), "Coulomb launch");
+    }
+    if (K)
+      if (df_status s = run_k(c, X, w, naux, nao, ncol, nocc, 1, p.nsplit, (double*)(c->ws + p.kpart), K))
+        return s;
+  }
+  if (nac > 0 && (eri || papa)) {
+    double* buv = (double*)(c->ws + p.buv);
+    if (df_status s = run_mo(c, Cact, nac, X, naux, nao, ncol, nocc, nac, buv)) return s;
+    if (eri)
+      if (df_status s = run_pgemm(c, buv, nac * nac, buv, nac * nac, naux, eri)) return s;
+    if (papa && np > 0) {
+      double* bpu = (double*)(c->ws + p.bpu);
+      if (df_status s = run_mo(c, Cp, np, X, naux, nao, ncol, nocc, nac, bpu)) return s;
+      if (df_status s = run_pgemm(c, bpu, np * nac, buv, nac * nac, naux, papa)) return s;
+    }
+  }
+  return DF_OK;
+}
+
+}  // extern "C"

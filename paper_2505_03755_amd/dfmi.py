@@ -1,0 +1,292 @@
+"""Python binding of libdfmi (ctypes over the C ABI in include/dfmi.h).
+
+Argument marshalling only: torch tensors provide device memory and the current
+stream; every contraction runs in the library's HIP kernels.  There is no
+fallback path: if libdfmi.so is missing or no GPU is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdfmi.so")
+
+DF_OK = 0
+DF_ERR_ARG = -1
+DF_ERR_SHAPE = -2
+DF_ERR_WORKSPACE = -3
+DF_ERR_HIP = -4
+DF_ERR_UNSUPPORTED = -5
+STATUS_NAMES = {0: "DF_OK", -1: "DF_ERR_ARG", -2: "DF_ERR_SHAPE", -3: "DF_ERR_WORKSPACE",
+                -4: "DF_ERR_HIP", -5: "DF_ERR_UNSUPPORTED"}
+
+DF_OP_HALF_TRANSFORM = 1
+DF_OP_JK = 2
+DF_OP_ACTIVE_ERI = 3
+DF_OP_PAPA = 4
+DF_OP_STEP = 5
+
+DF_PAPA_FULL = 0x1
+
+EXPORTED = ["df_create", "df_destroy", "df_last_error", "df_set_stream", "df_set_workspace",
+            "df_workspace_size", "df_half_transform", "df_jk", "df_active_eri", "df_papa", "df_step"]
+
+
+class DFError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("naux", ctypes.c_int64), ("nao", ctypes.c_int64), ("ndm", ctypes.c_int64),
+                ("nocc", ctypes.c_int64), ("nac", ctypes.c_int64), ("np", ctypes.c_int64),
+                ("nq", ctypes.c_int64), ("ncol", ctypes.c_int64), ("n2", ctypes.c_int64),
+                ("flags", ctypes.c_int)]
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libdfmi.so and declare its signatures (raises if it is not built)."""
+    global _lib
+    with _lib_lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is not built (run __graft_entry__.build())")
+        # torch brings its own HIP runtime (same soname as ROCm's).  Loading it first makes
+        # libdfmi bind to that one runtime instead of pulling a second copy into the process.
+        import torch  # noqa: F401
+        L = ctypes.CDLL(path)
+        vp, i64, i32, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
+        L.df_create.argtypes = [ctypes.POINTER(vp), i32, vp]
+        L.df_destroy.argtypes = [vp]
+        L.df_last_error.argtypes = [vp]
+        L.df_last_error.restype = ctypes.c_char_p
+        L.df_set_stream.argtypes = [vp, vp]
+        L.df_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
+        L.df_workspace_size.argtypes = [i32, ctypes.POINTER(Dims), ctypes.POINTER(ctypes.c_size_t)]
+        L.df_half_transform.argtypes = [vp, dp, i64, i64, dp, i64, dp, dp, i64, dp, i32]
+        L.df_jk.argtypes = [vp, dp, i64, i64, i64, dp, i64, dp, dp, dp, dp, i32]
+        L.df_active_eri.argtypes = [vp, dp, i64, i64, dp, i64, dp, dp, i32]
+        L.df_papa.argtypes = [vp, dp, i64, i64, dp, i64, dp, i64, dp, i64, dp, i32]
+        L.df_step.argtypes = [vp, dp, i64, i64, dp, i64, dp, dp, i64, dp, i64, dp, dp, dp, dp, dp, i32]
+        for name in EXPORTED:
+            if name != "df_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+        return L
+
+
+def workspace_size(op: int, **dims) -> int:
+    L = load_library()
+    d = Dims(**{k: int(v) for k, v in dims.items()})
+    out = ctypes.c_size_t(0)
+    st = L.df_workspace_size(op, ctypes.byref(d), ctypes.byref(out))
+    if st != DF_OK:
+        raise DFError(st, "df_workspace_size")
+    return out.value
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One library context on one device; owns a growable workspace tensor."""
+
+    def __init__(self, device=None):
+        import torch
+        L = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("dfmi needs a GPU (torch.cuda is not available)")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        h = ctypes.c_void_p()
+        st = L.df_create(ctypes.byref(h), self.device.index, None)
+        if st != DF_OK:
+            raise DFError(st, L.df_last_error(None).decode())
+        self._h = h
+        self._ws = None
+        self._lib = L
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.df_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def check(self, st: int):
+        if st != DF_OK:
+            raise DFError(st, self._lib.df_last_error(self._h).decode())
+
+    def prepare(self, op: int, **dims):
+        """Bind the current torch stream and a workspace big enough for `op`."""
+        import torch
+        stream = torch.cuda.current_stream(self.device)
+        self.check(self._lib.df_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)))
+        need = workspace_size(op, **dims)
+        if need and (self._ws is None or self._ws.numel() < need):
+            self._ws = None
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        if self._ws is not None:
+            self.check(self._lib.df_set_workspace(self._h, ctypes.c_void_p(self._ws.data_ptr()),
+                                                  self._ws.numel()))
+
+    def release_workspace(self):
+        self._ws = None
+        self.check(self._lib.df_set_workspace(self._h, None, 0))
+
+
+_contexts: dict = {}
+
+
+def context(device=None) -> Context:
+    import torch
+    idx = torch.cuda.current_device() if device is None else (torch.device(device).index or 0)
+    c = _contexts.get(idx)
+    if c is None:
+        c = Context(idx)
+        _contexts[idx] = c
+    return c
+
+
+def _check_tensor(name, t, device, ndim=None):
+    import torch
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device != device or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 tensor on {device}")
+    if ndim is not None and t.dim() not in ndim:
+        raise ValueError(f"{name} has {t.dim()} dims, expected {ndim}")
+
+
+def _npair(nao):
+    return nao * (nao + 1) // 2
+
+
+def _naux_of(B, nao):
+    if B.dim() != 2 or B.shape[1] != _npair(nao):
+        raise ValueError("B must be [naux, nao*(nao+1)/2]")
+    return B.shape[0]
+
+
+def half_transform(B, nao: int, C, C2=None, ctx: Context | None = None):
+    """X[P] = b^P C (Eq. ao2mo_1); with C2 also Y[P] = C2^T X[P] (Eq. ao2mo_2)."""
+    import torch
+    ctx = ctx or context(B.device)
+    for n, t in (("B", B), ("C", C), ("C2", C2)):
+        _check_tensor(n, t, ctx.device)
+    naux = _naux_of(B, nao)
+    ncol = C.shape[1]
+    X = torch.empty((naux, nao, ncol), dtype=torch.float64, device=ctx.device)
+    Y = None
+    n2 = 0
+    if C2 is not None:
+        n2 = C2.shape[1]
+        Y = torch.empty((naux, n2, ncol), dtype=torch.float64, device=ctx.device)
+    ctx.prepare(DF_OP_HALF_TRANSFORM, naux=naux, nao=nao, ncol=ncol, n2=n2)
+    ctx.check(ctx._lib.df_half_transform(ctx.handle, _ptr(B), naux, nao, _ptr(C), ncol, _ptr(X),
+                                         _ptr(C2), n2, _ptr(Y), 0))
+    return (X, Y) if C2 is not None else X
+
+
+def jk(B, nao: int, Cocc, w=None, want_j=True, want_k=True, want_v=True, ctx: Context | None = None):
+    """JK call for D_k = C_k diag(w_k) C_k^T; Cocc is [nao, nocc] or [ndm, nao, nocc]."""
+    import torch
+    ctx = ctx or context(B.device)
+    for n, t in (("B", B), ("Cocc", Cocc), ("w", w)):
+        _check_tensor(n, t, ctx.device)
+    naux = _naux_of(B, nao)
+    single = Cocc.dim() == 2
+    C3 = Cocc.unsqueeze(0) if single else Cocc
+    ndm, nocc = C3.shape[0], C3.shape[2]
+    if C3.shape[1] != nao:
+        raise ValueError("Cocc rows must equal nao")
+    if w is not None and w.numel() != ndm * nocc:
+        raise ValueError("w must have ndm*nocc entries")
+    J = torch.empty((ndm, nao, nao), dtype=torch.float64, device=ctx.device) if want_j else None
+    K = torch.empty((ndm, nao, nao), dtype=torch.float64, device=ctx.device) if want_k else None
+    v = torch.empty((ndm, naux), dtype=torch.float64, device=ctx.device) if want_v else None
+    ctx.prepare(DF_OP_JK, naux=naux, nao=nao, ndm=ndm, nocc=nocc)
+    ctx.check(ctx._lib.df_jk(ctx.handle, _ptr(B), naux, nao, ndm, _ptr(C3), nocc, _ptr(w),
+                             _ptr(J), _ptr(K), _ptr(v), 0))
+    if single:
+        J = J[0] if J is not None else None
+        K = K[0] if K is not None else None
+        v = v[0] if v is not None else None
+    return J, K, v
+
+
+def active_eri(B, nao: int, Cact, return_buv=False, ctx: Context | None = None):
+    """(uv|wx) = sum_P b^P_uv b^P_wx with b^P_uv = (Cact^T b^P Cact)_uv."""
+    import torch
+    ctx = ctx or context(B.device)
+    for n, t in (("B", B), ("Cact", Cact)):
+        _check_tensor(n, t, ctx.device)
+    naux = _naux_of(B, nao)
+    nac = Cact.shape[1]
+    eri = torch.empty((nac,) * 4, dtype=torch.float64, device=ctx.device)
+    buv = torch.empty((naux, nac, nac), dtype=torch.float64, device=ctx.device) if return_buv else None
+    ctx.prepare(DF_OP_ACTIVE_ERI, naux=naux, nao=nao, nac=nac)
+    ctx.check(ctx._lib.df_active_eri(ctx.handle, _ptr(B), naux, nao, _ptr(Cact), nac, _ptr(eri), _ptr(buv), 0))
+    return (eri, buv) if return_buv else eri
+
+
+def papa(B, nao: int, Cp, Cact, Cq=None, ctx: Context | None = None):
+    """(pu|vw) by default; with Cq the (pu|qv) block of Eq. (papa)."""
+    import torch
+    ctx = ctx or context(B.device)
+    for n, t in (("B", B), ("Cp", Cp), ("Cact", Cact), ("Cq", Cq)):
+        _check_tensor(n, t, ctx.device)
+    naux = _naux_of(B, nao)
+    np_, nac = Cp.shape[1], Cact.shape[1]
+    flags, nq = 0, 0
+    if Cq is not None:
+        flags, nq = DF_PAPA_FULL, Cq.shape[1]
+        out = torch.empty((np_, nac, nq, nac), dtype=torch.float64, device=ctx.device)
+    else:
+        out = torch.empty((np_, nac, nac, nac), dtype=torch.float64, device=ctx.device)
+    ctx.prepare(DF_OP_PAPA, naux=naux, nao=nao, nac=nac, np=np_, nq=nq, flags=flags)
+    ctx.check(ctx._lib.df_papa(ctx.handle, _ptr(B), naux, nao, _ptr(Cp), np_, _ptr(Cact), nac, _ptr(Cq), nq,
+                               _ptr(out), flags))
+    return out
+
+
+def step(B, nao: int, Cocc, Cact, Cp, w=None, outputs=None, ctx: Context | None = None):
+    """J, K, v, (uv|wx) and (pu|vw) from one shared half transform (df_step)."""
+    import torch
+    ctx = ctx or context(B.device)
+    for n, t in (("B", B), ("Cocc", Cocc), ("w", w), ("Cact", Cact), ("Cp", Cp)):
+        _check_tensor(n, t, ctx.device)
+    naux = _naux_of(B, nao)
+    nocc, nac, np_ = Cocc.shape[1], Cact.shape[1], Cp.shape[1]
+    if outputs is None:
+        dev = ctx.device
+        outputs = {
+            "J": torch.empty((nao, nao), dtype=torch.float64, device=dev),
+            "K": torch.empty((nao, nao), dtype=torch.float64, device=dev),
+            "v": torch.empty((naux,), dtype=torch.float64, device=dev),
+            "eri": torch.empty((nac,) * 4, dtype=torch.float64, device=dev),
+            "papa": torch.empty((np_, nac, nac, nac), dtype=torch.float64, device=dev),
+        }
+    ctx.prepare(DF_OP_STEP, naux=naux, nao=nao, ndm=1, nocc=nocc, nac=nac, np=np_)
+    o = outputs
+    ctx.check(ctx._lib.df_step(ctx.handle, _ptr(B), naux, nao, _ptr(Cocc), nocc, _ptr(w), _ptr(Cact), nac,
+                               _ptr(Cp), np_, _ptr(o.get("J")), _ptr(o.get("K")), _ptr(o.get("v")),
+                               _ptr(o.get("eri")), _ptr(o.get("papa")), 0))
+    return outputs

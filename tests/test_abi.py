@@ -1,0 +1,146 @@
+"""C-ABI contract, checked without a GPU.
+
+The library must load, export every entry point include/dfmi.h declares, size
+workspaces, and reject bad arguments with the documented status code before
+it makes any HIP call (so these checks run on a machine with no device).
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2505_03755_amd import dfmi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "dfmi.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:df_status|const char\*)\s+(df_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(dfmi.LIB_PATH):
+        pytest.skip("libdfmi.so not built")
+    return dfmi.load_library()
+
+
+@pytest.fixture()
+def ctx(L):
+    h = ctypes.c_void_p()
+    assert L.df_create(ctypes.byref(h), 0, None) == dfmi.DF_OK
+    yield h
+    L.df_destroy(h)
+
+
+def test_exports_every_declared_symbol(L):
+    names = _header_functions()
+    assert set(names) == set(dfmi.EXPORTED)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_create_rejects_bad_arguments(L):
+    assert L.df_create(None, 0, None) == dfmi.DF_ERR_ARG
+    h = ctypes.c_void_p()
+    assert L.df_create(ctypes.byref(h), -1, None) == dfmi.DF_ERR_ARG
+    assert b"device" in L.df_last_error(None)
+    assert L.df_destroy(None) == dfmi.DF_OK
+
+
+def test_workspace_size(L):
+    n = dfmi.workspace_size(dfmi.DF_OP_HALF_TRANSFORM, naux=10, nao=7, ncol=3)
+    assert n == 0
+    jk = dfmi.workspace_size(dfmi.DF_OP_JK, naux=10, nao=7, ndm=1, nocc=3)
+    assert jk >= 10 * 7 * 3 * 8
+    step = dfmi.workspace_size(dfmi.DF_OP_STEP, naux=10, nao=7, nocc=3, nac=2, np=7)
+    assert step >= 10 * 7 * 5 * 8 + 10 * 7 * 2 * 8
+    full = dfmi.workspace_size(dfmi.DF_OP_PAPA, naux=10, nao=7, nac=2, np=7, nq=5, flags=dfmi.DF_PAPA_FULL)
+    assert full >= 10 * 5 * 2 * 8
+    with pytest.raises(dfmi.DFError):
+        dfmi.workspace_size(dfmi.DF_OP_JK, naux=0, nao=7, ndm=1, nocc=3)
+    with pytest.raises(dfmi.DFError):
+        dfmi.workspace_size(99, naux=10, nao=7)
+
+
+P = ctypes.c_void_p
+
+
+def fake(addr):
+    """A pointer value that is never dereferenced: argument checks fail before any use."""
+    return ctypes.c_void_p(addr)
+
+
+def test_null_context(L):
+    assert L.df_half_transform(None, fake(4096), 4, 3, fake(8192), 2, fake(16384), None, 0, None, 0) == dfmi.DF_ERR_ARG
+
+
+def test_half_transform_argument_errors(L, ctx):
+    B, C, X = fake(1 << 20), fake(2 << 20), fake(3 << 20)
+    assert L.df_half_transform(ctx, None, 4, 3, C, 2, X, None, 0, None, 0) == dfmi.DF_ERR_ARG
+    assert L.df_half_transform(ctx, B, 0, 3, C, 2, X, None, 0, None, 0) == dfmi.DF_ERR_SHAPE
+    assert L.df_half_transform(ctx, B, 4, -1, C, 2, X, None, 0, None, 0) == dfmi.DF_ERR_SHAPE
+    assert L.df_half_transform(ctx, B, 4, 3, C, 0, X, None, 0, None, 0) == dfmi.DF_ERR_SHAPE
+    assert L.df_half_transform(ctx, B, 4, 3, C, 2, X, None, 0, None, 7) == dfmi.DF_ERR_UNSUPPORTED
+    assert L.df_half_transform(ctx, B, 4, 3, C, 2, X, fake(4 << 20), 3, None, 0) == dfmi.DF_ERR_ARG
+    assert L.df_half_transform(ctx, B, 4, 3, C, 2, X, None, 3, None, 0) == dfmi.DF_ERR_SHAPE
+    # output overlapping an input
+    assert L.df_half_transform(ctx, B, 4, 3, C, 2, fake((1 << 20) + 8), None, 0, None, 0) == dfmi.DF_ERR_ARG
+    assert b"overlaps" in L.df_last_error(ctx)
+    # nao too large for 31-bit packed offsets
+    assert L.df_half_transform(ctx, B, 4, 50000, C, 2, X, None, 0, None, 0) == dfmi.DF_ERR_SHAPE
+
+
+def test_jk_argument_errors(L, ctx):
+    B, C, J, K = fake(1 << 30), fake(2 << 30), fake(3 << 30), fake(4 << 30)
+    assert L.df_jk(ctx, B, 10, 7, 0, C, 3, None, J, K, None, 0) == dfmi.DF_ERR_SHAPE
+    assert L.df_jk(ctx, B, 10, 7, 1, None, 3, None, J, K, None, 0) == dfmi.DF_ERR_ARG
+    assert L.df_jk(ctx, B, 10, 7, 1, C, -2, None, J, K, None, 0) == dfmi.DF_ERR_SHAPE
+    assert L.df_jk(ctx, B, 10, 7, 1, C, 3, None, J, K, None, 1) == dfmi.DF_ERR_UNSUPPORTED
+    assert L.df_jk(ctx, B, 10, 7, 1, C, 3, None, J, J, None, 0) == dfmi.DF_ERR_ARG   # J and K alias
+    # no workspace attached
+    assert L.df_jk(ctx, B, 10, 7, 1, C, 3, None, J, K, None, 0) == dfmi.DF_ERR_WORKSPACE
+    need = dfmi.workspace_size(dfmi.DF_OP_JK, naux=10, nao=7, ndm=1, nocc=3)
+    assert L.df_set_workspace(ctx, fake(5 << 30), need - 256) == dfmi.DF_OK
+    assert L.df_jk(ctx, B, 10, 7, 1, C, 3, None, J, K, None, 0) == dfmi.DF_ERR_WORKSPACE
+    assert L.df_set_workspace(ctx, fake((5 << 30) + 8), need) == dfmi.DF_ERR_ARG  # misaligned
+    assert L.df_set_workspace(ctx, fake((3 << 30)), need) == dfmi.DF_OK
+    assert L.df_jk(ctx, B, 10, 7, 1, C, 3, None, J, K, None, 0) == dfmi.DF_ERR_ARG   # workspace overlaps J
+
+
+def test_active_eri_and_papa_argument_errors(L, ctx):
+    B, C, E = fake(1 << 30), fake(2 << 30), fake(3 << 30)
+    assert L.df_active_eri(ctx, B, 10, 7, None, 2, E, None, 0) == dfmi.DF_ERR_ARG
+    assert L.df_active_eri(ctx, B, 10, 7, C, -1, E, None, 0) == dfmi.DF_ERR_SHAPE
+    assert L.df_active_eri(ctx, B, 10, 7, C, 2, E, None, 4) == dfmi.DF_ERR_UNSUPPORTED
+    # nac = 0: nothing to compute, no workspace needed, no device touched
+    assert L.df_active_eri(ctx, B, 10, 7, None, 0, None, None, 0) == dfmi.DF_OK
+    Cp, Ca, O = fake(4 << 30), fake(5 << 30), fake(6 << 30)
+    assert L.df_papa(ctx, B, 10, 7, Cp, 7, Ca, 2, fake(7 << 30), 3, O, 0) == dfmi.DF_ERR_ARG   # Cq without FULL
+    assert L.df_papa(ctx, B, 10, 7, Cp, 7, Ca, 2, None, 3, O, dfmi.DF_PAPA_FULL) == dfmi.DF_ERR_ARG
+    assert L.df_papa(ctx, B, 10, 7, Cp, 7, Ca, 2, None, 0, O, 2) == dfmi.DF_ERR_UNSUPPORTED
+    assert L.df_papa(ctx, B, 10, 7, Cp, 7, Ca, 2, None, 0, O, 0) == dfmi.DF_ERR_WORKSPACE
+    assert L.df_papa(ctx, B, 10, 7, Cp, 0, Ca, 2, None, 0, O, 0) == dfmi.DF_OK      # empty output
+
+
+def test_step_argument_errors(L, ctx):
+    B, Co, Ca, Cp = fake(1 << 30), fake(2 << 30), fake(3 << 30), fake(4 << 30)
+    J, K = fake(5 << 30), fake(6 << 30)
+    assert L.df_step(ctx, B, 10, 7, None, 3, None, Ca, 2, Cp, 7, J, K, None, None, None, 0) == dfmi.DF_ERR_ARG
+    assert L.df_step(ctx, B, 10, 7, Co, 3, None, None, 2, Cp, 7, J, K, None, None, None, 0) == dfmi.DF_ERR_ARG
+    assert L.df_step(ctx, B, 10, 7, Co, 3, None, Ca, 2, Cp, 7, J, K, None, None, None, 8) == dfmi.DF_ERR_UNSUPPORTED
+    assert L.df_step(ctx, B, 10, 7, Co, 3, None, Ca, 2, Cp, 7, J, J, None, None, None, 0) == dfmi.DF_ERR_ARG
+    assert L.df_step(ctx, B, 10, 7, Co, 3, None, Ca, 2, Cp, 7, J, K, None, None, None, 0) == dfmi.DF_ERR_WORKSPACE
+
+
+def test_valid_call_without_device_fails_loudly(L, ctx):
+    """With arguments valid but no usable GPU, the first device call reports DF_ERR_HIP."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    B, C, X = fake(1 << 30), fake(2 << 30), fake(3 << 30)
+    st = L.df_half_transform(ctx, B, 4, 3, C, 2, X, None, 0, None, 0)
+    assert st == dfmi.DF_ERR_HIP
+    assert b"hipSetDevice" in L.df_last_error(ctx)
