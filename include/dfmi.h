@@ -64,6 +64,20 @@ typedef enum df_op {
   DF_OP_STEP = 5
 } df_op;
 
+/* Kernel classes reported by df_timing_read. */
+typedef enum df_kernel_kind {
+  DF_KERNEL_HALF_TRANSFORM = 0,  /* X = b^P C, Eq. (ao2mo_1) */
+  DF_KERNEL_JVEC = 1,            /* v_P, Eq. (J_1) */
+  DF_KERNEL_COULOMB = 2,         /* J = sum_P v_P b^P, Eq. (J_2) */
+  DF_KERNEL_K_SYRK = 3,          /* K tiles, Eqs. (K_1)-(K_2) in factored form */
+  DF_KERNEL_K_REDUCE = 4,        /* fixed-order sum of the K split partials */
+  DF_KERNEL_MO_TRANSFORM = 5,    /* b^P_{pu} = Cp^T X, Eq. (ao2mo_2) */
+  DF_KERNEL_PAPA = 6,            /* (pu|vw) / (pu|qv) contraction over P */
+  DF_KERNEL_ERI = 7,             /* (uv|wx) contraction over P */
+  DF_KERNEL_OTHER = 8,           /* fills and coefficient gathers */
+  DF_NUM_KERNEL_KINDS = 9
+} df_kernel_kind;
+
 /* Flag bits. */
 #define DF_PAPA_FULL 0x1   /* df_papa: return (pu|qv) of Eq. (papa) instead of (pu|vw) */
 
@@ -98,6 +112,14 @@ df_status df_set_stream(df_ctx* ctx, void* stream);
 
 /* Attach caller-owned device memory of `bytes` bytes as the workspace (NULL, 0 detaches). */
 df_status df_set_workspace(df_ctx* ctx, void* ptr, size_t bytes);
+
+/* Per-kernel timing.  While enabled, every launch the context makes is bracketed by two HIP
+ * events recorded on the context's stream (so each interval is that kernel's duration).
+ * df_timing_read waits for the recorded events, writes the summed milliseconds and launch
+ * counts per df_kernel_kind into ms[0..n) and launches[0..n) (kinds >= n are dropped), and
+ * starts a new interval.  Timing adds two event records per launch; leave it off otherwise. */
+df_status df_set_timing(df_ctx* ctx, int enable);
+df_status df_timing_read(df_ctx* ctx, double* ms, int64_t* launches, int n);
 
 /* Bytes of workspace that operation `op` needs for the sizes in *dims. */
 df_status df_workspace_size(df_op op, const df_dims* dims, size_t* bytes);

@@ -15,6 +15,15 @@ struct df_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   std::string err;
+  // per-kernel timing (df_set_timing): events recorded on the context's stream
+  struct Timed {
+    int kind;
+    hipEvent_t a, b;
+  };
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<Timed> pending;
+  hipEvent_t cur_a = nullptr;
 };
 
 namespace {
@@ -159,6 +168,41 @@ df_status enter(df_ctx* c) {
     if (e_ != hipSuccess) return fail(c, DF_ERR_HIP, hip_msg(e_, what)); \
   } while (0)
 
+df_status take_event(df_ctx* c, hipEvent_t* ev) {
+  if (!c->ev_pool.empty()) {
+    *ev = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return DF_OK;
+  }
+  DF_HIP(hipEventCreate(ev), "hipEventCreate");
+  return DF_OK;
+}
+
+df_status timing_begin(df_ctx* c) {
+  if (!c->timing) return DF_OK;
+  if (df_status s = take_event(c, &c->cur_a)) return s;
+  DF_HIP(hipEventRecord(c->cur_a, c->stream), "hipEventRecord");
+  return DF_OK;
+}
+
+df_status timing_end(df_ctx* c, int kind) {
+  if (!c->timing) return DF_OK;
+  hipEvent_t b;
+  if (df_status s = take_event(c, &b)) return s;
+  DF_HIP(hipEventRecord(b, c->stream), "hipEventRecord");
+  c->pending.push_back({kind, c->cur_a, b});
+  return DF_OK;
+}
+
+// A kernel launch, bracketed by timing events when timing is on.
+#define DF_LAUNCH(kind, call, what)                                      \
+  do {                                                                   \
+    if (df_status s_ = timing_begin(c)) return s_;                      \
+    hipError_t e_ = (call);                                              \
+    if (e_ != hipSuccess) return fail(c, DF_ERR_HIP, hip_msg(e_, what)); \
+    if (df_status s_ = timing_end(c, kind)) return s_;                  \
+  } while (0)
+
 size_t dbytes(int64_t n) { return (size_t)std::max<int64_t>(n, 0) * sizeof(double); }
 
 // ---- building blocks on the device ----
@@ -166,29 +210,31 @@ size_t dbytes(int64_t n) { return (size_t)std::max<int64_t>(n, 0) * sizeof(doubl
 // X (ldx columns, first ncol used) = b^P C
 df_status run_half(df_ctx* c, const double* B, int64_t naux, int64_t nao, const double* C, int64_t ldc,
                    int64_t ncol, double* X, int64_t ldx) {
-  DF_HIP(dfk::launch_half_transform(B, naux, nao, C, ldc, ncol, X, ldx, c->stream), "half transform launch");
+  DF_LAUNCH(DF_KERNEL_HALF_TRANSFORM, dfk::launch_half_transform(B, naux, nao, C, ldc, ncol, X, ldx, c->stream),
+            "half transform launch");
   return DF_OK;
 }
 
 // out[P][p][u] = sum_mu Cl[mu][p] X[P][mu][xoff + u]  (Cl is [nao][nl], X row stride ldx)
 df_status run_mo(df_ctx* c, const double* Cl, int64_t nl, const double* X, int64_t naux, int64_t nao,
                  int64_t ldx, int64_t xoff, int64_t nr, double* out) {
+  const int kind = DF_KERNEL_MO_TRANSFORM;
   if (nl == 0 || nr == 0) return DF_OK;
   dfk::OpMap A{Cl, nl, nl, 0, 1, 1, nao, 0, nl, 0, nullptr, 0};
   dfk::OpMap Bm{X + xoff, naux * nr, nr, nao * ldx, 1, 1, nao, 0, ldx, 0, nullptr, 0};
   dfk::OutMap O{out, nl, naux * nr, nl, 0, nr, nr, nl * nr, 1, 0};
-  DF_HIP(dfk::launch_gemm(A, Bm, O, 1, c->stream), "second transform launch");
+  DF_LAUNCH(kind, dfk::launch_gemm(A, Bm, O, 1, c->stream), "second transform launch");
   return DF_OK;
 }
 
 // out[m][n] = sum_P L[P][m] R[P][n]
-df_status run_pgemm(df_ctx* c, const double* L, int64_t M, const double* R, int64_t N, int64_t naux,
+df_status run_pgemm(df_ctx* c, int kind, const double* L, int64_t M, const double* R, int64_t N, int64_t naux,
                     double* out) {
   if (M == 0 || N == 0) return DF_OK;
   dfk::OpMap A{L, M, M, 0, 1, 1, naux, 0, M, 0, nullptr, 0};
   dfk::OpMap Bm{R, N, N, 0, 1, 1, naux, 0, N, 0, nullptr, 0};
   dfk::OutMap O = dfk::out_plain(out, M, N, N);
-  DF_HIP(dfk::launch_gemm(A, Bm, O, 1, c->stream), "aux contraction launch");
+  DF_LAUNCH(kind, dfk::launch_gemm(A, Bm, O, 1, c->stream), "aux contraction launch");
   return DF_OK;
 }
 
@@ -199,8 +245,8 @@ df_status run_k(df_ctx* c, const double* X, const double* w, int64_t naux, int64
   dfk::OpMap Bw = A;
   Bw.ks = w;
   Bw.s_ksz = nocc;
-  DF_HIP(dfk::launch_syrk_partial(A, Bw, nao, nz, nsplit, kpart, c->stream), "K tiles launch");
-  DF_HIP(dfk::launch_syrk_reduce(kpart, nsplit, nao, nz, K, c->stream), "K reduce launch");
+  DF_LAUNCH(DF_KERNEL_K_SYRK, dfk::launch_syrk_partial(A, Bw, nao, nz, nsplit, kpart, c->stream), "K tiles launch");
+  DF_LAUNCH(DF_KERNEL_K_REDUCE, dfk::launch_syrk_reduce(kpart, nsplit, nao, nz, K, c->stream), "K reduce launch");
   return DF_OK;
 }
 
@@ -230,7 +276,46 @@ df_status df_create(df_ctx** ctx, int device, void* stream) {
 }
 
 df_status df_destroy(df_ctx* ctx) {
+  if (!ctx) return DF_OK;
+  for (auto& t : ctx->pending) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;
+  return DF_OK;
+}
+
+df_status df_set_timing(df_ctx* ctx, int enable) {
+  if (!ctx) return DF_ERR_ARG;
+  ctx->timing = enable != 0;
+  return DF_OK;
+}
+
+df_status df_timing_read(df_ctx* ctx, double* ms, int64_t* launches, int n) {
+  df_ctx* c = ctx;
+  if (!c) return DF_ERR_ARG;
+  if (n < 0 || (n > 0 && (!ms || !launches))) return fail(c, DF_ERR_ARG, "ms and launches need n entries");
+  for (int i = 0; i < n; ++i) {
+    ms[i] = 0.0;
+    launches[i] = 0;
+  }
+  for (size_t i = 0; i < c->pending.size(); ++i) {
+    const auto& t = c->pending[i];
+    hipError_t e = hipEventSynchronize(t.b);
+    float el = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&el, t.a, t.b);
+    if (e != hipSuccess) return fail(c, DF_ERR_HIP, hip_msg(e, "reading timing events"));
+    if (t.kind >= 0 && t.kind < n) {
+      ms[t.kind] += el;
+      launches[t.kind] += 1;
+    }
+  }
+  for (auto& t : c->pending) {
+    c->ev_pool.push_back(t.a);
+    c->ev_pool.push_back(t.b);
+  }
+  c->pending.clear();
   return DF_OK;
 }
 
@@ -322,9 +407,9 @@ df_status df_jk(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int64_t
   if (!check_overlap(c, rs)) return DF_ERR_ARG;
   if (df_status s = enter(c)) return s;
   if (nocc == 0) {
-    if (J) DF_HIP(dfk::launch_fill_zero(J, ndm * nao * nao, c->stream), "fill");
-    if (K) DF_HIP(dfk::launch_fill_zero(K, ndm * nao * nao, c->stream), "fill");
-    if (v) DF_HIP(dfk::launch_fill_zero(v, ndm * naux, c->stream), "fill");
+    if (J) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(J, ndm * nao * nao, c->stream), "fill");
+    if (K) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(K, ndm * nao * nao, c->stream), "fill");
+    if (v) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(v, ndm * naux, c->stream), "fill");
     return DF_OK;
   }
   if (!J && !K && !v) return DF_OK;
@@ -334,7 +419,7 @@ df_status df_jk(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int64_t
   if (ndm > 1) {
     double* cc = (double*)(c->ws + p.ccat);
     for (int64_t z = 0; z < ndm; ++z)
-      DF_HIP(hipMemcpy2DAsync(cc + z * nocc, ncol * sizeof(double), Cocc + z * nao * nocc, nocc * sizeof(double),
+      DF_LAUNCH(DF_KERNEL_OTHER, hipMemcpy2DAsync(cc + z * nocc, ncol * sizeof(double), Cocc + z * nao * nocc, nocc * sizeof(double),
                               nocc * sizeof(double), nao, hipMemcpyDeviceToDevice, c->stream),
              "density factor gather");
     Ccat = cc;
@@ -342,8 +427,8 @@ df_status df_jk(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int64_t
   if (df_status s = run_half(c, B, naux, nao, Ccat, ncol, ncol, X, ncol)) return s;
   if (J || v) {
     double* vv = v ? v : (double*)(c->ws + p.vtmp);
-    DF_HIP(dfk::launch_jvec(X, naux, nao, ncol, Cocc, w, nocc, ndm, vv, c->stream), "J-vector launch");
-    if (J) DF_HIP(dfk::launch_coulomb(B, naux, nao, vv, ndm, J, c->stream), "Coulomb launch");
+    DF_LAUNCH(DF_KERNEL_JVEC, dfk::launch_jvec(X, naux, nao, ncol, Cocc, w, nocc, ndm, vv, c->stream), "J-vector launch");
+    if (J) DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_coulomb(B, naux, nao, vv, ndm, J, c->stream), "Coulomb launch");
   }
   if (K)
     if (df_status s = run_k(c, X, w, naux, nao, ncol, nocc, ndm, p.nsplit, (double*)(c->ws + p.kpart), K))
@@ -378,7 +463,7 @@ df_status df_active_eri(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
   double* bu = buv ? buv : (double*)(c->ws + p.buv);
   if (df_status s = run_half(c, B, naux, nao, Cact, nac, nac, X, nac)) return s;
   if (df_status s = run_mo(c, Cact, nac, X, naux, nao, nac, 0, nac, bu)) return s;
-  return run_pgemm(c, bu, nac * nac, bu, nac * nac, naux, eri);
+  return run_pgemm(c, DF_KERNEL_ERI, bu, nac * nac, bu, nac * nac, naux, eri);
 }
 
 df_status df_papa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const double* Cp, int64_t np,
@@ -419,11 +504,11 @@ df_status df_papa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const
   if (full) {
     double* bqv = (double*)(c->ws + p.bqv);
     if (df_status s = run_mo(c, Cq, nq, X, naux, nao, nac, 0, nac, bqv)) return s;
-    return run_pgemm(c, bpu, np * nac, bqv, nq * nac, naux, out);
+    return run_pgemm(c, DF_KERNEL_PAPA, bpu, np * nac, bqv, nq * nac, naux, out);
   }
   double* bvw = (double*)(c->ws + p.bvw);
   if (df_status s = run_mo(c, Cact, nac, X, naux, nao, nac, 0, nac, bvw)) return s;
-  return run_pgemm(c, bpu, np * nac, bvw, nac * nac, naux, out);
+  return run_pgemm(c, DF_KERNEL_PAPA, bpu, np * nac, bvw, nac * nac, naux, out);
 }
 
 df_status df_step(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const double* Cocc, int64_t nocc,
@@ -459,18 +544,18 @@ df_status df_step(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const
   if (!check_overlap(c, rs)) return DF_ERR_ARG;
   if (df_status s = enter(c)) return s;
   if (nocc == 0) {
-    if (J) DF_HIP(dfk::launch_fill_zero(J, nao * nao, c->stream), "fill");
-    if (K) DF_HIP(dfk::launch_fill_zero(K, nao * nao, c->stream), "fill");
-    if (v) DF_HIP(dfk::launch_fill_zero(v, naux, c->stream), "fill");
+    if (J) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(J, nao * nao, c->stream), "fill");
+    if (K) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(K, nao * nao, c->stream), "fill");
+    if (v) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(v, naux, c->stream), "fill");
   }
   if (ncol == 0) return DF_OK;
   double* cc = (double*)(c->ws + p.ccat);
   if (nocc > 0)
-    DF_HIP(hipMemcpy2DAsync(cc, ncol * sizeof(double), Cocc, nocc * sizeof(double), nocc * sizeof(double), nao,
+    DF_LAUNCH(DF_KERNEL_OTHER, hipMemcpy2DAsync(cc, ncol * sizeof(double), Cocc, nocc * sizeof(double), nocc * sizeof(double), nao,
                             hipMemcpyDeviceToDevice, c->stream),
            "Cocc gather");
   if (nac > 0)
-    DF_HIP(hipMemcpy2DAsync(cc + nocc, ncol * sizeof(double), Cact, nac * sizeof(double), nac * sizeof(double), nao,
+    DF_LAUNCH(DF_KERNEL_OTHER, hipMemcpy2DAsync(cc + nocc, ncol * sizeof(double), Cact, nac * sizeof(double), nac * sizeof(double), nao,
                             hipMemcpyDeviceToDevice, c->stream),
            "Cact gather");
   double* X = (double*)(c->ws + p.x);
@@ -478,8 +563,8 @@ df_status df_step(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const
   if (nocc > 0) {
     if (J || v) {
       double* vv = v ? v : (double*)(c->ws + p.vtmp);
-      DF_HIP(dfk::launch_jvec(X, naux, nao, ncol, Cocc, w, nocc, 1, vv, c->stream), "J-vector launch");
-      if (J) DF_HIP(dfk::launch_coulomb(B, naux, nao, vv, 1, J, c->stream), "Coulomb launch");
+      DF_LAUNCH(DF_KERNEL_JVEC, dfk::launch_jvec(X, naux, nao, ncol, Cocc, w, nocc, 1, vv, c->stream), "J-vector launch");
+      if (J) DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_coulomb(B, naux, nao, vv, 1, J, c->stream), "Coulomb launch");
     }
     if (K)
       if (df_status s = run_k(c, X, w, naux, nao, ncol, nocc, 1, p.nsplit, (double*)(c->ws + p.kpart), K))
@@ -489,11 +574,11 @@ df_status df_step(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const
     double* buv = (double*)(c->ws + p.buv);
     if (df_status s = run_mo(c, Cact, nac, X, naux, nao, ncol, nocc, nac, buv)) return s;
     if (eri)
-      if (df_status s = run_pgemm(c, buv, nac * nac, buv, nac * nac, naux, eri)) return s;
+      if (df_status s = run_pgemm(c, DF_KERNEL_ERI, buv, nac * nac, buv, nac * nac, naux, eri)) return s;
     if (papa && np > 0) {
       double* bpu = (double*)(c->ws + p.bpu);
       if (df_status s = run_mo(c, Cp, np, X, naux, nao, ncol, nocc, nac, bpu)) return s;
-      if (df_status s = run_pgemm(c, bpu, np * nac, buv, nac * nac, naux, papa)) return s;
+      if (df_status s = run_pgemm(c, DF_KERNEL_PAPA, bpu, np * nac, buv, nac * nac, naux, papa)) return s;
     }
   }
   return DF_OK;

@@ -30,8 +30,12 @@ DF_OP_STEP = 5
 
 DF_PAPA_FULL = 0x1
 
+KERNEL_KINDS = ["half_transform", "jvec", "coulomb", "k_syrk", "k_reduce", "mo_transform", "papa", "eri",
+                "other"]
+
 EXPORTED = ["df_create", "df_destroy", "df_last_error", "df_set_stream", "df_set_workspace",
-            "df_workspace_size", "df_half_transform", "df_jk", "df_active_eri", "df_papa", "df_step"]
+            "df_set_timing", "df_timing_read", "df_workspace_size", "df_half_transform", "df_jk",
+            "df_active_eri", "df_papa", "df_step"]
 
 
 class DFError(RuntimeError):
@@ -71,6 +75,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         L.df_set_stream.argtypes = [vp, vp]
         L.df_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
         L.df_workspace_size.argtypes = [i32, ctypes.POINTER(Dims), ctypes.POINTER(ctypes.c_size_t)]
+        L.df_set_timing.argtypes = [vp, i32]
+        L.df_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), i32]
         L.df_half_transform.argtypes = [vp, dp, i64, i64, dp, i64, dp, dp, i64, dp, i32]
         L.df_jk.argtypes = [vp, dp, i64, i64, i64, dp, i64, dp, dp, dp, dp, i32]
         L.df_active_eri.argtypes = [vp, dp, i64, i64, dp, i64, dp, dp, i32]
@@ -146,6 +152,17 @@ class Context:
         if self._ws is not None:
             self.check(self._lib.df_set_workspace(self._h, ctypes.c_void_p(self._ws.data_ptr()),
                                                   self._ws.numel()))
+
+    def set_timing(self, on: bool):
+        self.check(self._lib.df_set_timing(self._h, 1 if on else 0))
+
+    def timing_read(self) -> dict:
+        """{kernel kind: (milliseconds, launches)} since the last read (waits for the GPU)."""
+        n = len(KERNEL_KINDS)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        self.check(self._lib.df_timing_read(self._h, ms, cnt, n))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_KINDS)}
 
     def release_workspace(self):
         self._ws = None
