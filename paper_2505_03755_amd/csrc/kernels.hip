@@ -1,10 +1,16 @@
 // HIP kernels for gfx950 (MI355X): FP64 contractions of the packed Cholesky tensor.
 //
 // Every dense contraction runs on the FP64 matrix cores (v_mfma_f64_16x16x4_f64,
-// 64 cycles per issue per SIMD).  Operand tiles are staged through LDS in a
-// [row][k] layout with a row stride of 17 doubles: both the "k fastest" and the
-// "row fastest" global-load mappings then write, and the MFMA operand reads
-// then read, 32 lanes per LDS cycle without bank conflicts.
+// 64 cycles per issue per SIMD; one wave per SIMD can keep the unit busy).  Operand
+// tiles go global -> registers -> LDS in a [row][k] layout with a row stride of 17
+// doubles: the "k fastest" and "row fastest" global-load mappings both write, and the
+// MFMA operand reads read, 32 lanes per LDS cycle without bank conflicts.
+//
+// Main loop: two LDS stages; the global loads of slab s+1 are issued before the MFMAs
+// of slab s and written to the other stage after them, one barrier per slab.  Loads
+// are branch-free (out-of-range elements read a valid address and are replaced by 0
+// with a select), so no wait on outstanding loads sits between the prefetch and the
+// MFMA block.
 //
 // Operand layout of v_mfma_f64_16x16x4_f64 (measured on gfx950):
 //   A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
@@ -23,12 +29,16 @@ struct Cfg {
   static constexpr int NT = 64 * WM * WN;
   static constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN, BK = 16;
   static constexpr int LD = BK + 1;
-  static constexpr int LDS_A = BM * LD, LDS_B = BN * LD;
+  static constexpr int LDS_A = BM * LD, LDS_B = BN * LD, STAGE = LDS_A + LDS_B;
   static_assert((BM * BK) % NT == 0 && (BN * BK) % NT == 0, "tile must split evenly over threads");
 };
 
-// 128 x 128 output tile, 4 waves of 64 x 64 (4 x 4 MFMA blocks each).
-typedef Cfg<2, 2, 4, 4> CfgBig;
+// generic products and the K SYRK: 128 x 128 tiles, 2 x 2 waves of 64 x 64
+typedef Cfg<2, 2, 4, 4> CfgSq;
+// half transform: 128 rows x {176, 96, 48} columns, 4 waves stacked along the rows
+typedef Cfg<4, 1, 2, 11> CfgH176;
+typedef Cfg<4, 1, 2, 6> CfgH96;
+typedef Cfg<4, 1, 2, 3> CfgH48;
 
 // ---------------------------------------------------------------------------------------
 // Block index -> work item, keeping runs of consecutive work items on one XCD.  The
@@ -67,6 +77,29 @@ __device__ __forceinline__ void zero_acc(d4 (&acc)[C::TM][C::TN]) {
     for (int j = 0; j < C::TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 }
 
+// Two-stage software pipeline over nslab k-slabs.  load(s) fetches slab s into registers,
+// store(stage) writes those registers into LDS stage `stage`.
+template <class C, class FLoad, class FStore>
+__device__ __forceinline__ void pipeline(double* smem, int64_t nslab, d4 (&acc)[C::TM][C::TN], int wm, int wn,
+                                         int lane, FLoad&& load, FStore&& store) {
+  if (nslab > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t s = 0; s < nslab; ++s) {
+    const int cur = (int)(s & 1);
+    const bool more = s + 1 < nslab;
+    if (more) load(s + 1);
+    // keep the prefetch ahead of, and its consumers behind, the MFMA block
+    __builtin_amdgcn_sched_barrier(0);
+    mma_slab<C>(smem + cur * C::STAGE, smem + cur * C::STAGE + C::LDS_A, acc, wm, wn, lane);
+    __builtin_amdgcn_sched_barrier(0);
+    if (more) store(cur ^ 1);
+    __syncthreads();
+  }
+}
+
 template <class C>
 __device__ __forceinline__ void store_tile(const OutMap& o, int64_t z, int64_t m0, int64_t n0,
                                            const d4 (&acc)[C::TM][C::TN], int wm, int wn, int lane) {
@@ -76,13 +109,15 @@ __device__ __forceinline__ void store_tile(const OutMap& o, int64_t z, int64_t m
   for (int j = 0; j < C::TN; ++j) {
     const int64_t n = n0 + (wn * C::TN + j) * 16 + lr;
     if (n >= o.N) continue;
-    const int64_t noff = (n / o.nl) * o.s_nh + (n % o.nl) * o.s_nl;
+    const uint32_t nh = o.s_nh ? (uint32_t)n / (uint32_t)o.nl : 0u;
+    const int64_t noff = (int64_t)nh * o.s_nh + (n - (int64_t)nh * o.nl) * o.s_nl;
 #pragma unroll
     for (int i = 0; i < C::TM; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t m = m0 + (wm * C::TM + i) * 16 + 4 * r + lg;
-        if (m < o.M) base[(m / o.ml) * o.s_mh + (m % o.ml) * o.s_ml + noff] = acc[i][j][r];
+        const uint32_t mh = o.s_mh ? (uint32_t)m / (uint32_t)o.ml : 0u;
+        if (m < o.M) base[(int64_t)mh * o.s_mh + (m - (int64_t)mh * o.ml) * o.s_ml + noff] = acc[i][j][r];
       }
   }
 }
@@ -90,12 +125,20 @@ __device__ __forceinline__ void store_tile(const OutMap& o, int64_t z, int64_t m
 // Global -> register -> LDS loader for one operand described by an OpMap.
 //   KC = true : lanes run along k (16 consecutive k of one row per 16 lanes)
 //   KC = false: lanes run along the row index
-template <class C, int R, bool KC>
+//   SCALE     : multiply element (r, kc) by ks[z*s_ksz + kc] (applied when storing to LDS)
+// The slab sequence is walked in order: kb outer, kc in chunks of 16 inner.
+template <class C, int R, bool KC, bool SCALE = false>
 struct Loader {
   static constexpr int E = R * C::BK / C::NT;
-  int64_t off[E];
-  bool ok[E];
+  static_assert(E <= 32, "validity mask holds 32 elements");
+  int64_t rowbase[E];  // offset of (row, kb = 0, kc = 0), rows past the end clamped to the last one
+  unsigned rowok;      // bit q: the row of element q exists
+  double v[E];         // raw loaded values; invalid ones are zeroed when written to LDS
+  double sc[SCALE ? E : 1];
   int64_t kso;
+  int64_t kb;          // slab the next load() fetches: (kb, kc0)
+  int kc0;
+  int kvalid;          // valid k entries of the slab last loaded
 
   __device__ __forceinline__ static int rr(int t, int q) {
     const int e = t + C::NT * q;
@@ -105,27 +148,51 @@ struct Loader {
     const int e = t + C::NT * q;
     return KC ? e % C::BK : e / R;
   }
-  __device__ __forceinline__ void init(const OpMap& o, int64_t r0, int64_t z, int t) {
+  __device__ __forceinline__ void init(const OpMap& o, int64_t r0, int64_t z, int64_t kb0, int t) {
     kso = z * o.s_ksz;
+    kb = kb0;
+    kc0 = 0;
+    kvalid = 0;
+    rowok = 0;
 #pragma unroll
     for (int q = 0; q < E; ++q) {
       const int64_t r = r0 + rr(t, q);
-      ok[q] = r < o.rows;
-      off[q] = ok[q] ? z * o.s_z + (r / o.rl) * o.s_rh + (r % o.rl) * o.s_rlo : 0;
+      const bool ok = r < o.rows;
+      rowok |= (ok ? 1u : 0u) << q;
+      const uint32_t rc = (uint32_t)(ok ? r : o.rows - 1);   // row indices fit 32 bits
+      uint32_t rh = 0, rlo = rc;
+      if (o.s_rh != 0) {
+        rh = rc / (uint32_t)o.rl;
+        rlo = rc - rh * (uint32_t)o.rl;
+      }
+      rowbase[q] = z * o.s_z + (int64_t)rh * o.s_rh + (int64_t)rlo * o.s_rlo;
     }
   }
-  __device__ __forceinline__ void load(const OpMap& o, int64_t kb, int64_t kc0, int t, double (&v)[E]) const {
-    const int64_t kbo = kb * o.s_kb;
+  // issue the loads of the current slab (addresses clamped in range) and advance
+  __device__ __forceinline__ void load(const OpMap& o, int t) {
+    const double* __restrict__ base = o.p + kb * o.s_kb;
+    const int klast = (int)o.kc_n - 1;
 #pragma unroll
     for (int q = 0; q < E; ++q) {
-      const int64_t kc = kc0 + kk(t, q);
-      v[q] = (ok[q] && kc < o.kc_n) ? o.p[off[q] + kbo + kc * o.s_kc] : 0.0;
-      if (o.ks && kc < o.kc_n) v[q] *= o.ks[kso + kc];
+      const int kc = min(kc0 + kk(t, q), klast);
+      const int64_t koff = KC ? (int64_t)kc : (int64_t)(uint32_t)kc * (uint32_t)o.s_kc;
+      v[q] = base[rowbase[q] + koff];
+      if (SCALE) sc[q] = o.ks[kso + kc];
+    }
+    kvalid = (int)o.kc_n - kc0;
+    kc0 += C::BK;
+    if (kc0 >= o.kc_n) {
+      kc0 = 0;
+      ++kb;
     }
   }
-  __device__ __forceinline__ static void store(double* S, int t, const double (&v)[E]) {
+  __device__ __forceinline__ void store(double* S, int t) const {
 #pragma unroll
-    for (int q = 0; q < E; ++q) S[rr(t, q) * C::LD + kk(t, q)] = v[q];
+    for (int q = 0; q < E; ++q) {
+      const bool ok = ((rowok >> q) & 1u) && kk(t, q) < kvalid;
+      const double x = SCALE ? v[q] * sc[q] : v[q];
+      S[rr(t, q) * C::LD + kk(t, q)] = ok ? x : 0.0;
+    }
   }
 };
 
@@ -134,66 +201,45 @@ struct Loader {
 template <class C, bool AK, bool BK>
 __global__ void __launch_bounds__(C::NT) gemm_kernel(OpMap A, OpMap B, OutMap O, int64_t tilesM,
                                                      int64_t tilesN) {
-  __shared__ double smem[2 * (C::LDS_A + C::LDS_B)];
+  __shared__ double smem[2 * C::STAGE];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave % C::WM, wn = wave / C::WM;
-  const int64_t ntile = tilesM * tilesN;
-  const int64_t tile = xcd_remap(blockIdx.x, ntile);
+  const int64_t tile = xcd_remap(blockIdx.x, tilesM * tilesN);
   const int64_t z = blockIdx.z;
   const int64_t m0 = (tile % tilesM) * C::BM, n0 = (tile / tilesM) * C::BN;
 
   Loader<C, C::BM, AK> la;
   Loader<C, C::BN, BK> lb;
-  la.init(A, m0, z, t);
-  lb.init(B, n0, z, t);
-  constexpr int STAGE = C::LDS_A + C::LDS_B;
-#define As(b) (smem + (b) * STAGE)
-#define Bs(b) (smem + (b) * STAGE + C::LDS_A)
-
+  la.init(A, m0, z, 0, t);
+  lb.init(B, n0, z, 0, t);
   d4 acc[C::TM][C::TN];
   zero_acc<C>(acc);
-  const int64_t nkc = (A.kc_n + C::BK - 1) / C::BK;
-  const int64_t nslab = A.kb_n * nkc;
-  double va[Loader<C, C::BM, AK>::E], vb[Loader<C, C::BN, BK>::E];
-  if (nslab > 0) {
-    la.load(A, 0, 0, t, va);
-    lb.load(B, 0, 0, t, vb);
-    la.store(As(0), t, va);
-    lb.store(Bs(0), t, vb);
-  }
-  __syncthreads();
-  int64_t kb = 0, kc0 = 0;
-  for (int64_t s = 0; s < nslab; ++s) {
-    const int cur = s & 1;
-    const bool more = s + 1 < nslab;
-    if (more) {
-      kc0 += C::BK;
-      if (kc0 >= A.kc_n) { kc0 = 0; ++kb; }
-      la.load(A, kb, kc0, t, va);
-      lb.load(B, kb, kc0, t, vb);
-    }
-    mma_slab<C>(As(cur), Bs(cur), acc, wm, wn, lane);
-    if (more) {
-      la.store(As(cur ^ 1), t, va);
-      lb.store(Bs(cur ^ 1), t, vb);
-    }
-    __syncthreads();
-  }
+  const int64_t nslab = A.kb_n * ((A.kc_n + C::BK - 1) / C::BK);
+  pipeline<C>(
+      smem, nslab, acc, wm, wn, lane,
+      [&](int64_t) {
+        la.load(A, t);
+        lb.load(B, t);
+      },
+      [&](int st) {
+        la.store(smem + st * C::STAGE, t);
+        lb.store(smem + st * C::STAGE + C::LDS_A, t);
+      });
   store_tile<C>(O, z, m0, n0, acc, wm, wn, lane);
 }
 
 // ---------------------------------------------------------------------------------------
 // Lower-triangle tile SYRK with the kb range split over workgroups:
-// Kpart[split][z] tile (I, J), I >= J, = sum_{kb in split} sum_kc A(i, kb, kc) A(j, kb, kc).
-template <class C>
+// Kpart[split][z] tile (I, J), I >= J, = sum_{kb in split} sum_kc A(i, kb, kc) Bw(j, kb, kc),
+// where Bw is A times an optional per-kc weight.
+template <class C, bool SCALE>
 __global__ void __launch_bounds__(C::NT) syrk_kernel(OpMap A, OpMap Bw, int64_t n, int64_t nz, int nsplit,
                                                      int64_t npairs, double* Kpart) {
   static_assert(C::BM == C::BN, "square tiles");
-  __shared__ double smem[2 * (C::LDS_A + C::LDS_B)];
+  __shared__ double smem[2 * C::STAGE];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave % C::WM, wn = wave / C::WM;
-  const int64_t nitem = npairs * nsplit;
-  const int64_t item = xcd_remap(blockIdx.x, nitem);
+  const int64_t item = xcd_remap(blockIdx.x, npairs * nsplit);
   const int64_t z = blockIdx.z;
   const int64_t pair = item % npairs;
   const int split = (int)(item / npairs);
@@ -206,44 +252,23 @@ __global__ void __launch_bounds__(C::NT) syrk_kernel(OpMap A, OpMap Bw, int64_t 
   const int64_t kb_lo = A.kb_n * split / nsplit, kb_hi = A.kb_n * (split + 1) / nsplit;
 
   Loader<C, C::BM, true> la;
-  Loader<C, C::BN, true> lb;
-  la.init(A, m0, z, t);
-  lb.init(Bw, n0, z, t);
-  constexpr int STAGE = C::LDS_A + C::LDS_B;
-#define As(b) (smem + (b) * STAGE)
-#define Bs(b) (smem + (b) * STAGE + C::LDS_A)
-
+  Loader<C, C::BN, true, SCALE> lb;
+  la.init(A, m0, z, kb_lo, t);
+  lb.init(Bw, n0, z, kb_lo, t);
   d4 acc[C::TM][C::TN];
   zero_acc<C>(acc);
-  const int64_t nkc = (A.kc_n + C::BK - 1) / C::BK;
-  const int64_t nslab = (kb_hi - kb_lo) * nkc;
-  double va[Loader<C, C::BM, true>::E], vb[Loader<C, C::BN, true>::E];
-  if (nslab > 0) {
-    la.load(A, kb_lo, 0, t, va);
-    lb.load(Bw, kb_lo, 0, t, vb);
-    la.store(As(0), t, va);
-    lb.store(Bs(0), t, vb);
-  }
-  __syncthreads();
-  int64_t kb = kb_lo, kc0 = 0;
-  for (int64_t s = 0; s < nslab; ++s) {
-    const int cur = s & 1;
-    const bool more = s + 1 < nslab;
-    if (more) {
-      kc0 += C::BK;
-      if (kc0 >= A.kc_n) { kc0 = 0; ++kb; }
-      la.load(A, kb, kc0, t, va);
-      lb.load(Bw, kb, kc0, t, vb);
-    }
-    mma_slab<C>(As(cur), Bs(cur), acc, wm, wn, lane);
-    if (more) {
-      la.store(As(cur ^ 1), t, va);
-      lb.store(Bs(cur ^ 1), t, vb);
-    }
-    __syncthreads();
-  }
+  const int64_t nslab = (kb_hi - kb_lo) * ((A.kc_n + C::BK - 1) / C::BK);
+  pipeline<C>(
+      smem, nslab, acc, wm, wn, lane,
+      [&](int64_t) {
+        la.load(A, t);
+        lb.load(Bw, t);
+      },
+      [&](int st) {
+        la.store(smem + st * C::STAGE, t);
+        lb.store(smem + st * C::STAGE + C::LDS_A, t);
+      });
   OutMap o = out_plain(Kpart + ((int64_t)split * nz + z) * n * n, n, n, n);
-  o.s_z = 0;
   store_tile<C>(o, 0, m0, n0, acc, wm, wn, lane);
 }
 
@@ -261,14 +286,15 @@ __global__ void __launch_bounds__(256) syrk_reduce_kernel(const double* __restri
 
 // ---------------------------------------------------------------------------------------
 // Half transform of one packed, symmetric b^P against a dense C.
-// A operand element (m, k) = b^P_{mk}: a tile strictly below the diagonal is read along k
-// (contiguous runs of a packed row), a tile strictly above it along m (contiguous runs of
-// packed row k), a tile on the diagonal element by element through max/min.
+// A operand element (m, k) = b^P_{mk}.  A slab strictly below the diagonal (every k < every
+// m) is read along k: 16-element runs of packed rows.  Any other slab is read along m and
+// addressed through (max, min), which for slabs above the diagonal are runs of packed row k.
+// Packed offsets stay in 32 bits (nao <= 46340).
 template <class C>
 __global__ void __launch_bounds__(C::NT) half_kernel(const double* __restrict__ B, int64_t naux, int nao,
                                                      int64_t npair, OpMap Cm, double* __restrict__ X,
                                                      int64_t ldx, int64_t tilesM, int64_t tilesN) {
-  __shared__ double smem[2 * (C::LDS_A + C::LDS_B)];
+  __shared__ double smem[2 * C::STAGE];
   constexpr int EA = C::BM * C::BK / C::NT;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave % C::WM, wn = wave / C::WM;
@@ -279,63 +305,62 @@ __global__ void __launch_bounds__(C::NT) half_kernel(const double* __restrict__ 
   const double* __restrict__ Bp = B + P * npair;
 
   Loader<C, C::BN, false> lb;
-  lb.init(Cm, n0, 0, t);
-  constexpr int STAGE = C::LDS_A + C::LDS_B;
-#define As(b) (smem + (b) * STAGE)
-#define Bs(b) (smem + (b) * STAGE + C::LDS_A)
-
-  // A tile loader: returns values and their LDS slots for slab k0
-  auto load_a = [&](int k0, double (&v)[EA], int (&slot)[EA]) {
-    const bool below = k0 + C::BK - 1 <= m0;
-    const bool above = k0 >= m0 + C::BM - 1;
+  lb.init(Cm, n0, 0, 0, t);
+  static_assert(EA <= 32, "validity mask holds 32 elements");
+  static_assert(C::NT % C::BK == 0 && C::NT % C::BM == 0, "per-thread row / column of the A loads");
+  // below-diagonal mapping: element q is row m0 + t/16 + q*NT/16, column k0 + t%16
+  // other mapping:          element q is row m0 + t%BM,        column k0 + t/BM + q*NT/BM
+  const unsigned last = (unsigned)nao - 1u;
+  unsigned rowoffB[EA], rowokB = 0;
 #pragma unroll
-    for (int q = 0; q < EA; ++q) {
-      const int e = t + C::NT * q;
-      if (below) {
-        const int r = e / C::BK, k = e % C::BK;
-        const int m = m0 + r, kg = k0 + k;
-        v[q] = m < nao ? Bp[(int64_t)m * (m + 1) / 2 + kg] : 0.0;
-        slot[q] = r * C::LD + k;
-      } else {
-        const int r = e % C::BM, k = e / C::BM;
-        const int m = m0 + r, kg = k0 + k;
-        if (above) {
-          v[q] = kg < nao ? Bp[(int64_t)kg * (kg + 1) / 2 + m] : 0.0;
-        } else {
-          const int hi = m > kg ? m : kg, lo = m > kg ? kg : m;
-          v[q] = (m < nao && kg < nao) ? Bp[(int64_t)hi * (hi + 1) / 2 + lo] : 0.0;
-        }
-        slot[q] = r * C::LD + k;
-      }
-    }
-  };
+  for (int q = 0; q < EA; ++q) {
+    const unsigned m = (unsigned)(m0 + (t + C::NT * q) / C::BK);
+    rowokB |= (m <= last ? 1u : 0u) << q;
+    const unsigned mc = m <= last ? m : last;
+    rowoffB[q] = mc * (mc + 1u) / 2u + (unsigned)(t % C::BK);
+  }
+  const unsigned mA = (unsigned)(m0 + t % C::BM);
+  const unsigned mAc = mA <= last ? mA : last;
+  const unsigned mAoff = mAc * (mAc + 1u) / 2u;
+  double va[EA];
+  unsigned amask = 0;
+  bool below = false;
 
   d4 acc[C::TM][C::TN];
   zero_acc<C>(acc);
   const int nslab = (nao + C::BK - 1) / C::BK;
-  double va[EA], vb[Loader<C, C::BN, false>::E];
-  int sa[EA];
-  load_a(0, va, sa);
-  lb.load(Cm, 0, 0, t, vb);
+  pipeline<C>(
+      smem, nslab, acc, wm, wn, lane,
+      [&](int64_t s) {
+        const unsigned k0 = (unsigned)s * C::BK;
+        below = (int)k0 + C::BK - 1 <= m0;
+        if (below) {
+          amask = rowokB;
 #pragma unroll
-  for (int q = 0; q < EA; ++q) As(0)[sa[q]] = va[q];
-  lb.store(Bs(0), t, vb);
-  __syncthreads();
-  for (int s = 0; s < nslab; ++s) {
-    const int cur = s & 1;
-    const bool more = s + 1 < nslab;
-    if (more) {
-      load_a((s + 1) * C::BK, va, sa);
-      lb.load(Cm, 0, (int64_t)(s + 1) * C::BK, t, vb);
-    }
-    mma_slab<C>(As(cur), Bs(cur), acc, wm, wn, lane);
-    if (more) {
+          for (int q = 0; q < EA; ++q) va[q] = Bp[rowoffB[q] + k0];
+        } else {
+          amask = 0;
 #pragma unroll
-      for (int q = 0; q < EA; ++q) As(cur ^ 1)[sa[q]] = va[q];
-      lb.store(Bs(cur ^ 1), t, vb);
-    }
-    __syncthreads();
-  }
+          for (int q = 0; q < EA; ++q) {
+            const unsigned k = k0 + (unsigned)((t + C::NT * q) / C::BM);
+            amask |= (mA <= last && k <= last ? 1u : 0u) << q;
+            const unsigned kc = k <= last ? k : last;
+            const unsigned idx = mAc >= kc ? mAoff + kc : kc * (kc + 1u) / 2u + mAc;
+            va[q] = Bp[idx];
+          }
+        }
+        lb.load(Cm, t);
+      },
+      [&](int st) {
+        double* As = smem + st * C::STAGE;
+#pragma unroll
+        for (int q = 0; q < EA; ++q) {
+          const int e = t + C::NT * q;
+          const int slot = below ? (e / C::BK) * C::LD + e % C::BK : (e % C::BM) * C::LD + e / C::BM;
+          As[slot] = ((amask >> q) & 1u) ? va[q] : 0.0;
+        }
+        lb.store(smem + st * C::STAGE + C::LDS_A, t);
+      });
   OutMap o = out_plain(X + P * (int64_t)nao * ldx, nao, Cm.rows, ldx);
   store_tile<C>(o, 0, m0, n0, acc, wm, wn, lane);
 }
@@ -357,7 +382,10 @@ __global__ void __launch_bounds__(256) jvec_kernel(const double* __restrict__ X,
     const double cw = wz ? Cz[m * nocc + c] * wz[c] : Cz[m * nocc + c];
     s = fma(cw, Xp[m * ldx + c], s);
     c += 256;
-    while (c >= nocc) { c -= nocc; ++m; }
+    while (c >= nocc) {
+      c -= nocc;
+      ++m;
+    }
   }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
@@ -410,22 +438,46 @@ __global__ void __launch_bounds__(256) fill_zero_kernel(double* p, int64_t n) {
 
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-hipError_t launch_half_transform(const double* B, int64_t naux, int64_t nao, const double* C,
-                                 int64_t ldc, int64_t ncol, double* X, int64_t ldx, hipStream_t s) {
-  typedef CfgBig Cg;
-  // B operand: element (n = column of C, k = AO index) at C + k*ldc + n
-  OpMap cm{C, ncol, ncol > 0 ? ncol : 1, 0, 1, 1, nao, 0, ldc, 0, nullptr, 0};
-  const int64_t tm = cdiv(nao, Cg::BM), tn = cdiv(ncol, Cg::BN);
+template <class Cg>
+static hipError_t half_launch(const double* B, int64_t naux, int64_t nao, const OpMap& cm, double* X, int64_t ldx,
+                              hipStream_t s) {
+  const int64_t tm = cdiv(nao, Cg::BM), tn = cdiv(cm.rows, Cg::BN);
   const int64_t nblk = tm * tn * naux;
   if (nblk == 0) return hipSuccess;
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
-  half_kernel<Cg><<<dim3((unsigned)nblk), dim3(Cg::NT), 0, s>>>(B, naux, (int)nao, nao * (nao + 1) / 2, cm,
-                                                                 X, ldx, tm, tn);
+  half_kernel<Cg><<<dim3((unsigned)nblk), dim3(Cg::NT), 0, s>>>(B, naux, (int)nao, nao * (nao + 1) / 2, cm, X, ldx,
+                                                                 tm, tn);
   return hipGetLastError();
 }
 
+// Column tile of the half transform: the widest of {176, 96, 48} that pads ncol least.
+int half_tile_n(int64_t ncol) {
+  const int cands[3] = {176, 96, 48};
+  int best = cands[0];
+  int64_t best_pad = cdiv(ncol, best) * best;
+  for (int c : cands) {
+    const int64_t pad = cdiv(ncol, c) * c;
+    if (pad < best_pad) {
+      best = c;
+      best_pad = pad;
+    }
+  }
+  return best;
+}
+
+hipError_t launch_half_transform(const double* B, int64_t naux, int64_t nao, const double* C, int64_t ldc,
+                                 int64_t ncol, double* X, int64_t ldx, hipStream_t s) {
+  // B operand: element (n = column of C, k = AO index) at C + k*ldc + n
+  const OpMap cm{C, ncol, ncol > 0 ? ncol : 1, 0, 1, 1, nao, 0, ldc, 0, nullptr, 0};
+  switch (half_tile_n(ncol)) {
+    case 176: return half_launch<CfgH176>(B, naux, nao, cm, X, ldx, s);
+    case 96: return half_launch<CfgH96>(B, naux, nao, cm, X, ldx, s);
+    default: return half_launch<CfgH48>(B, naux, nao, cm, X, ldx, s);
+  }
+}
+
 hipError_t launch_gemm(const OpMap& A, const OpMap& Bm, const OutMap& O, int64_t nz, hipStream_t s) {
-  typedef CfgBig Cg;
+  typedef CfgSq Cg;
   const int64_t tm = cdiv(O.M, Cg::BM), tn = cdiv(O.N, Cg::BN);
   if (tm * tn == 0 || nz == 0) return hipSuccess;
   if (tm * tn > 0x7fffffffLL || nz > 65535) return hipErrorInvalidValue;
@@ -438,10 +490,10 @@ hipError_t launch_gemm(const OpMap& A, const OpMap& Bm, const OutMap& O, int64_t
   return hipGetLastError();
 }
 
-int syrk_tile() { return CfgBig::BM; }
+int syrk_tile() { return CfgSq::BM; }
 
 int syrk_splits(int64_t n, int64_t kb_n, int64_t nz) {
-  const int64_t T = cdiv(n, CfgBig::BM);
+  const int64_t T = cdiv(n, CfgSq::BM);
   const int64_t work = T * (T + 1) / 2 * (nz > 0 ? nz : 1);
   int64_t ns = cdiv(1024, work);
   if (ns > kb_n) ns = kb_n;
@@ -449,36 +501,36 @@ int syrk_splits(int64_t n, int64_t kb_n, int64_t nz) {
   return (int)ns;
 }
 
-hipError_t launch_syrk_partial(const OpMap& A, const OpMap& Bw, int64_t n, int64_t nz, int nsplit,
-                               double* Kpart, hipStream_t s) {
-  typedef CfgBig Cg;
+hipError_t launch_syrk_partial(const OpMap& A, const OpMap& Bw, int64_t n, int64_t nz, int nsplit, double* Kpart,
+                               hipStream_t s) {
+  typedef CfgSq Cg;
   const int64_t T = cdiv(n, Cg::BM);
   const int64_t npairs = T * (T + 1) / 2;
   if (npairs == 0 || nz == 0) return hipSuccess;
   if (nz > 65535) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(npairs * nsplit), 1, (unsigned)nz);
-  syrk_kernel<Cg><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
+  if (Bw.ks) syrk_kernel<Cg, true><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
+  else syrk_kernel<Cg, false><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
   return hipGetLastError();
 }
 
-hipError_t launch_syrk_reduce(const double* Kpart, int nsplit, int64_t n, int64_t nz, double* K,
-                              hipStream_t s) {
+hipError_t launch_syrk_reduce(const double* Kpart, int nsplit, int64_t n, int64_t nz, double* K, hipStream_t s) {
   const int64_t tot = n * n * nz;
   if (tot == 0) return hipSuccess;
   syrk_reduce_kernel<<<(unsigned)cdiv(tot, 256), 256, 0, s>>>(Kpart, nsplit, n, nz, K);
   return hipGetLastError();
 }
 
-hipError_t launch_jvec(const double* X, int64_t naux, int64_t nao, int64_t ldx, const double* C,
-                       const double* w, int64_t nocc, int64_t nz, double* v, hipStream_t s) {
+hipError_t launch_jvec(const double* X, int64_t naux, int64_t nao, int64_t ldx, const double* C, const double* w,
+                       int64_t nocc, int64_t nz, double* v, hipStream_t s) {
   if (naux == 0 || nz == 0) return hipSuccess;
   if (nz > 65535 || naux > 0x7fffffffLL) return hipErrorInvalidValue;
   jvec_kernel<<<dim3((unsigned)naux, (unsigned)nz), 256, 0, s>>>(X, nao, ldx, C, w, nocc, v, naux);
   return hipGetLastError();
 }
 
-hipError_t launch_coulomb(const double* B, int64_t naux, int64_t nao, const double* v, int64_t nz,
-                          double* J, hipStream_t s) {
+hipError_t launch_coulomb(const double* B, int64_t naux, int64_t nao, const double* v, int64_t nz, double* J,
+                          hipStream_t s) {
   const int64_t npair = nao * (nao + 1) / 2;
   for (int64_t z0 = 0; z0 < nz; z0 += kCoulombZ) {
     const int nzc = (int)(nz - z0 < kCoulombZ ? nz - z0 : kCoulombZ);
