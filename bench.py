@@ -112,6 +112,9 @@ def main():
     ap.add_argument("--workload", default="paper", choices=["tiny", "medium", "paper"])
     ap.add_argument("--cpu-rows", type=int, default=240, help="auxiliary rows in the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="copy this many MiB device-to-device once before the steps (a known-size "
+                         "reference for the HBM byte counters of a profiling run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the path would shard "
@@ -143,6 +146,15 @@ def main():
         "eri": torch.empty((nac,) * 4, dtype=torch.float64, device=dev),
         "papa": torch.empty((nmo, nac, nac, nac), dtype=torch.float64, device=dev),
     }
+    if args.calibration_copy_mib > 0:
+        n = args.calibration_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"[bench] calibration copy of {args.calibration_copy_mib} MiB done")
     run = lambda: dfmi.step(B, nao, Cocc, Cact, C, outputs=out, ctx=ctx)
     for i in range(args.warmup):
         run()
