@@ -1,11 +1,15 @@
 #!/usr/bin/env python3
 """Benchmark of the density-fitted contraction step on one MI355X.
 
-One step = one forward pass of the whole hot path through df_step at paper scale
-(N_ao = 1200, N_aux = 4800, N_occ = 300, N_ac = 40, N_mo = 1200, B = 27.7 GB packed FP64):
-the shared half transform X = b^P [C_occ | C_act], the J-vector and J, K, the second
-transform b^P_{pu}, (uv|wx) and (pu|vw).  Inputs are drawn on the GPU and are resident
-in HBM before the timed region starts.
+One step = one pass of the whole hot path at paper scale (N_ao = 1200, N_aux = 4800,
+N_occ = 300, N_ac = 40, N_mo = 1200, B = 27.7 GB packed FP64):
+  forward  (df_step): the shared half transform X = b^P [C_occ | C_act], the J-vector and J,
+           K, the second transform b^P_{pu}, (uv|wx) and (pu|vw), keeping X for the adjoint;
+  adjoint  (df_step_backward): the vector-Jacobian product of (J, K, (uv|wx)) with respect to
+           (C_occ, C_act) for the cotangents of the model energy
+           E = tr(D h) + 1/2 tr(D J) - 1/4 tr(D K) + 1/2 sum (uv|wx) Gamma,
+           i.e. gJ = D/2, gK = -D/4, g_eri = Gamma/2 (the contraction part of dE/dkappa).
+Inputs are drawn on the GPU and are resident in HBM before the timed region starts.
 
 Prints one JSON line with the step throughput (algorithmic TFLOP/s), the roofline figure
 of the dominant kernel (live HIP-event timing on the library's stream) and the FP64 CPU
@@ -32,8 +36,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def step_flops(naux, nao, nocc, nac, nmo):
-    """Algorithmic FP64 FLOPs of one forward step (half, J, K, b_pu, (pu|vw))."""
+def step_flops(naux, nao, nocc, nac, nmo, adjoint=True):
+    """Algorithmic FP64 FLOPs of one step: forward (half, J, K, b_pu, (pu|vw)) and the generic
+    adjoint (J part 4 N_aux npair + 2 N_ao^2 N_occ, K part 4 N_aux N_ao^2 N_occ, eri part
+    2 N_aux N_ac^4 + 2 N_aux N_ao N_ac^2)."""
     npair = nao * (nao + 1) // 2
     f = {
         "half_transform": 2 * naux * nao * nao * (nocc + nac),
@@ -42,6 +48,9 @@ def step_flops(naux, nao, nocc, nac, nmo):
         "mo_transform": 2 * naux * nao * nmo * nac,
         "papa": 2 * naux * nmo * nac ** 3,
     }
+    if adjoint:
+        f["adjoint"] = (4 * naux * npair + 2 * nao * nao * nocc + 4 * naux * nao * nao * nocc
+                        + 2 * naux * nac ** 4 + 2 * naux * nao * nac * nac)
     return f
 
 
@@ -55,9 +64,12 @@ def kernel_table(kt, naux, nao, nocc, nac, nmo, steps):
         "mo_transform": ("mfma", 2 * naux * nao * nmo * nac + 2 * naux * nao * nac * nac),
         "papa": ("mfma", 2 * naux * nmo * nac ** 3),
         "eri": ("mfma", 2 * naux * nac ** 4),
+        "adjoint": ("mfma", 4 * naux * nao * nao * nocc + 2 * nao * nao * nocc + 2 * naux * nac ** 4
+                    + 2 * naux * nao * nac * nac),
         # HBM-bound kernels: bytes read + written
-        "jvec": ("hbm", 8 * (naux * nao * nocc + nao * nocc + naux)),
-        "coulomb": ("hbm", 8 * (naux * npair + naux + 2 * nao * nao)),
+        # forward J-vector reads X_occ, the adjoint's reads B; each Coulomb build streams B
+        "jvec": ("hbm", 8 * (naux * nao * nocc + nao * nocc + naux) + 8 * (naux * npair + npair + naux)),
+        "coulomb": ("hbm", 2 * 8 * (naux * npair + naux + 2 * nao * nao)),
         "k_reduce": ("hbm", None),
         "other": ("hbm", None),
     }
@@ -97,11 +109,11 @@ def cpu_baseline(wl, rows, seed):
     eri, _ = O.active_eri(B, wl.nao, Cact)
     pa = O.papa(B, wl.nao, C, Cact)
     dt = time.perf_counter() - t0
-    fl = sum(step_flops(rows, wl.nao, wl.nocc, wl.nac, wl.nmo).values())
+    fl = sum(step_flops(rows, wl.nao, wl.nocc, wl.nac, wl.nmo, adjoint=False).values())
     assert np.isfinite(J).all() and np.isfinite(K).all() and np.isfinite(pa).all() and np.isfinite(eri).all()
     return {"value": fl / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{rows} of {wl.naux} auxiliary rows at N_ao={wl.nao}, N_occ={wl.nocc}, N_ac={wl.nac} "
-                      f"(forward J, K, v, (uv|wx), (pu|vw)); {dt:.2f} s"}
+                      f"(forward J, K, v, (uv|wx), (pu|vw); rate in algorithmic FP64 FLOP/s); {dt:.2f} s"}
 
 
 def main():
@@ -112,6 +124,7 @@ def main():
     ap.add_argument("--workload", default="paper", choices=["tiny", "medium", "paper"])
     ap.add_argument("--cpu-rows", type=int, default=240, help="auxiliary rows in the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forward-only", action="store_true", help="time df_step alone (no adjoint)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="copy this many MiB device-to-device once before the steps (a known-size "
                          "reference for the HBM byte counters of a profiling run)")
@@ -135,6 +148,12 @@ def main():
     C = torch.from_numpy(synth.orbitals(nao, seed=wl.seed)).to(dev)
     Cocc = C[:, :nocc].contiguous()
     Cact = C[:, nocc:nocc + nac].contiguous()
+    # cotangents of the model energy: gJ = D/2, gK = -D/4, g_eri = Gamma/2
+    D = Cocc @ Cocc.T
+    gJ = (0.5 * D).contiguous()
+    gK = (-0.25 * D).contiguous()
+    geri = (0.5 * torch.from_numpy(synth.two_body_density(nac, seed=wl.seed)).to(dev)).contiguous()
+    del D
     torch.cuda.synchronize()
     log(f"[bench] inputs ready in {time.perf_counter() - t0:.1f} s (B {B.numel() * 8 / 1e9:.2f} GB)")
 
@@ -146,6 +165,9 @@ def main():
         "eri": torch.empty((nac,) * 4, dtype=torch.float64, device=dev),
         "papa": torch.empty((nmo, nac, nac, nac), dtype=torch.float64, device=dev),
     }
+    if not args.forward_only:
+        out["Xocc"] = torch.empty((naux, nao, nocc), dtype=torch.float64, device=dev)
+        out["Xact"] = torch.empty((nao, naux, nac), dtype=torch.float64, device=dev)
     if args.calibration_copy_mib > 0:
         n = args.calibration_copy_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device=dev)
@@ -155,7 +177,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         log(f"[bench] calibration copy of {args.calibration_copy_mib} MiB done")
-    run = lambda: dfmi.step(B, nao, Cocc, Cact, C, outputs=out, ctx=ctx)
+    def run():
+        dfmi.step(B, nao, Cocc, Cact, C, outputs=out, ctx=ctx)
+        if not args.forward_only:
+            dfmi.step_backward(B, nao, Cocc, Cact, gJ, gK, geri, out["Xocc"], out["Xact"], ctx=ctx)
     for i in range(args.warmup):
         run()
         torch.cuda.synchronize()
@@ -173,7 +198,7 @@ def main():
     ctx.set_timing(False)
     log(f"[bench] {args.steps} timed steps in {dt:.3f} s")
 
-    fl = step_flops(naux, nao, nocc, nac, nmo)
+    fl = step_flops(naux, nao, nocc, nac, nmo, adjoint=not args.forward_only)
     w_alg = sum(fl.values())
     ms = dt / args.steps * 1e3
     value = w_alg / (dt / args.steps) / 1e12
@@ -204,8 +229,11 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"DF forward step ({wl.name}): N_ao={nao}, N_aux={naux}, N_occ={nocc}, N_ac={nac}, "
-                        f"N_mo={nmo}; outputs J, K, v, (uv|wx), (pu|vw)",
+            "workload": f"DF step ({wl.name}): N_ao={nao}, N_aux={naux}, N_occ={nocc}, N_ac={nac}, "
+                        f"N_mo={nmo}; forward J, K, v, (uv|wx), (pu|vw)"
+                        + ("" if args.forward_only else " + adjoint of (J, K, (uv|wx)) for the model-energy "
+                           "cotangents"),
+            "precision": "fp64",
             "nao": nao, "naux": naux, "nocc": nocc, "nac": nac, "nmo": nmo,
             "flops_per_step": w_alg,
             "parallelism": "single GPU",

@@ -61,7 +61,8 @@ typedef enum df_op {
   DF_OP_JK = 2,
   DF_OP_ACTIVE_ERI = 3,
   DF_OP_PAPA = 4,
-  DF_OP_STEP = 5
+  DF_OP_STEP = 5,
+  DF_OP_STEP_BACKWARD = 6
 } df_op;
 
 /* Kernel classes reported by df_timing_read. */
@@ -74,12 +75,19 @@ typedef enum df_kernel_kind {
   DF_KERNEL_MO_TRANSFORM = 5,    /* b^P_{pu} = Cp^T X, Eq. (ao2mo_2) */
   DF_KERNEL_PAPA = 6,            /* (pu|vw) / (pu|qv) contraction over P */
   DF_KERNEL_ERI = 7,             /* (uv|wx) contraction over P */
-  DF_KERNEL_OTHER = 8,           /* fills and coefficient gathers */
-  DF_NUM_KERNEL_KINDS = 9
+  DF_KERNEL_OTHER = 8,           /* fills, symmetrisations and coefficient gathers */
+  DF_KERNEL_ADJOINT = 9,         /* the products of df_step_backward */
+  DF_NUM_KERNEL_KINDS = 10
 } df_kernel_kind;
 
-/* Flag bits. */
+/* Flag bits of calls. */
 #define DF_PAPA_FULL 0x1   /* df_papa: return (pu|qv) of Eq. (papa) instead of (pu|vw) */
+
+/* Flag bits of df_dims.flags for df_workspace_size only. */
+#define DF_CALLER_X  0x10  /* DF_OP_STEP / DF_OP_STEP_BACKWARD: Xocc and Xact are passed in */
+#define DF_BWD_GJ    0x20  /* DF_OP_STEP_BACKWARD: gJ is given */
+#define DF_BWD_GK    0x40  /* DF_OP_STEP_BACKWARD: gK is given */
+#define DF_BWD_GERI  0x80  /* DF_OP_STEP_BACKWARD: geri is given */
 
 /* Problem sizes for df_workspace_size; fields an operation does not use are ignored. */
 typedef struct df_dims {
@@ -179,13 +187,37 @@ df_status df_papa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
 /*
  * One forward pass of the whole path from a single half transform X = b^P [Cocc | Cact]:
  * J, K and v of D = Cocc diag(w) Cocc^T (as df_jk with ndm = 1), eri = (uv|wx) and
- * papa = (pu|vw) (as df_active_eri and df_papa).  Any output pointer may be NULL.
- * Workspace: df_workspace_size(DF_OP_STEP, {naux, nao, 1, nocc, nac, np}).
+ * papa = (pu|vw) (as df_active_eri and df_papa).  Any of J, K, v, eri, papa may be NULL.
+ *   Xocc [naux][nao][nocc], Xact [nao][naux][nac]: optional outputs (both or neither; one of
+ *   zero size may be NULL) that
+ *   receive the half-transformed factors b^P Cocc (P-major) and b^P Cact (AO-major), e.g. to be
+ *   handed to df_step_backward; when given they replace the workspace's copies.
+ * Workspace: df_workspace_size(DF_OP_STEP, {naux, nao, 1, nocc, nac, np,
+ *            flags = DF_CALLER_X if Xocc/Xact are given}).
  */
 df_status df_step(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
                   const double* Cocc, int64_t nocc, const double* w,
                   const double* Cact, int64_t nac, const double* Cp, int64_t np,
-                  double* J, double* K, double* v, double* eri, double* papa, int flags);
+                  double* J, double* K, double* v, double* eri, double* papa,
+                  double* Xocc, double* Xact, int flags);
+
+/*
+ * Vector-Jacobian product of df_step's (J, K, eri) as functions of (Cocc, Cact), unit
+ * weights (the adjoint used for the orbital-rotation gradient of the differentiable step):
+ *   dCocc = 2 M Cocc + sum_P b^P S b^P Cocc,   M = sum_P <b^P, gJ> b^P,   S = gK + gK^T
+ *   dCact = sum_P (b^P Cact)(Z_P + Z_P^T),      Z_P[u][v] = sum_wx (geri[uvwx] + geri[wxuv]) b^P_wx
+ *   gJ, gK [nao][nao], geri [nac]^4: cotangents, each may be NULL (= zero)
+ *   Xocc, Xact: the half transforms from df_step (both or neither; one of zero size may be
+ *            NULL); both NULL recomputes them
+ *   dCocc [nao][nocc], dCact [nao][nac]: outputs (overwritten)
+ * Workspace: df_workspace_size(DF_OP_STEP_BACKWARD, {naux, nao, 1, nocc, nac,
+ *            flags = DF_BWD_GJ|DF_BWD_GK|DF_BWD_GERI for the given cotangents, | DF_CALLER_X}).
+ */
+df_status df_step_backward(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
+                           const double* Cocc, int64_t nocc, const double* Cact, int64_t nac,
+                           const double* gJ, const double* gK, const double* geri,
+                           const double* Xocc, const double* Xact,
+                           double* dCocc, double* dCact, int flags);
 
 #ifdef __cplusplus
 }

@@ -90,7 +90,7 @@ struct PapaPlan {
   size_t x, bpu, bvw, bqv;
 };
 struct StepPlan {
-  size_t ccat, x, kpart, vtmp, bpu, buv;
+  size_t ccat, xo, xa, kpart, vtmp, bpu, buv;
   int nsplit;
 };
 
@@ -121,16 +121,48 @@ PapaPlan plan_papa(Plan& pl, int64_t naux, int64_t nao, int64_t nac, int64_t np,
   return p;
 }
 
-StepPlan plan_step(Plan& pl, int64_t naux, int64_t nao, int64_t nocc, int64_t nac, int64_t np) {
+StepPlan plan_step(Plan& pl, int64_t naux, int64_t nao, int64_t nocc, int64_t nac, int64_t np, bool caller_x) {
   StepPlan p{};
   const int64_t ncol = nocc + nac;
   p.ccat = pl.take(nao * ncol);
-  p.x = pl.take(naux * nao * ncol);
+  p.xo = pl.take(caller_x ? 0 : naux * nao * nocc);
+  p.xa = pl.take(caller_x ? 0 : naux * nao * nac);
   p.nsplit = dfk::syrk_splits(nao, naux, 1);
   p.kpart = pl.take((int64_t)p.nsplit * nao * nao);
   p.vtmp = pl.take(naux);
   p.bpu = pl.take(naux * np * nac);
   p.buv = pl.take(naux * nac * nac);
+  return p;
+}
+
+// Workspace of df_step_backward.  flags: DF_BWD_GJ / DF_BWD_GK / DF_BWD_GERI say which cotangents
+// are given, DF_CALLER_X that the forward's half transforms are passed in.
+struct BwdPlan {
+  size_t ccat, xo, xa, g, u, M, S, Y, kpart, Gs, buv, Z, apart;
+  int nsk, nsa;
+};
+
+BwdPlan plan_backward(Plan& pl, int64_t naux, int64_t nao, int64_t nocc, int64_t nac, int flags) {
+  BwdPlan p{};
+  const bool gj = flags & DF_BWD_GJ, gk = flags & DF_BWD_GK, ge = flags & DF_BWD_GERI;
+  const bool cx = flags & DF_CALLER_X;
+  const bool need_xo = gk && nocc > 0 && !cx, need_xa = ge && nac > 0 && !cx;
+  const int64_t npair = nao * (nao + 1) / 2;
+  p.ccat = pl.take(need_xo && need_xa ? nao * (nocc + nac) : 0);
+  p.xo = pl.take(need_xo ? naux * nao * nocc : 0);
+  p.xa = pl.take(need_xa ? naux * nao * nac : 0);
+  p.g = pl.take(gj && nocc > 0 ? npair : 0);
+  p.u = pl.take(gj && nocc > 0 ? naux : 0);
+  p.M = pl.take(gj && nocc > 0 ? nao * nao : 0);
+  p.S = pl.take(gk && nocc > 0 ? nao * nao : 0);
+  p.Y = pl.take(gk && nocc > 0 ? naux * nao * nocc : 0);
+  p.nsk = gk && nocc > 0 ? dfk::half_reduce_splits(nao, nocc, naux) : 1;
+  p.kpart = pl.take(gk && nocc > 0 ? (int64_t)p.nsk * nao * nocc : 0);
+  p.Gs = pl.take(ge && nac > 0 ? nac * nac * nac * nac : 0);
+  p.buv = pl.take(ge && nac > 0 ? naux * nac * nac : 0);
+  p.Z = pl.take(ge && nac > 0 ? naux * nac * nac : 0);
+  p.nsa = ge && nac > 0 ? dfk::gemm_splits(nao, nac, (naux * nac + 15) / 16) : 1;
+  p.apart = pl.take(ge && nac > 0 && p.nsa > 1 ? (int64_t)p.nsa * nao * nac : 0);
   return p;
 }
 
@@ -207,23 +239,64 @@ size_t dbytes(int64_t n) { return (size_t)std::max<int64_t>(n, 0) * sizeof(doubl
 
 // ---- building blocks on the device ----
 
-// X (ldx columns, first ncol used) = b^P C
+// T_P = b^P C (ncol columns of C, row stride ldc), written through `out` with z = P
 df_status run_half(df_ctx* c, const double* B, int64_t naux, int64_t nao, const double* C, int64_t ldc,
-                   int64_t ncol, double* X, int64_t ldx) {
-  DF_LAUNCH(DF_KERNEL_HALF_TRANSFORM, dfk::launch_half_transform(B, naux, nao, C, ldc, ncol, X, ldx, c->stream),
+                   int64_t ncol, const dfk::OutMap& out) {
+  DF_LAUNCH(DF_KERNEL_HALF_TRANSFORM, dfk::launch_half_transform(B, naux, nao, C, ldc, ncol, out, c->stream),
             "half transform launch");
   return DF_OK;
 }
 
-// out[P][p][u] = sum_mu Cl[mu][p] X[P][mu][xoff + u]  (Cl is [nao][nl], X row stride ldx)
-df_status run_mo(df_ctx* c, const double* Cl, int64_t nl, const double* X, int64_t naux, int64_t nao,
-                 int64_t ldx, int64_t xoff, int64_t nr, double* out) {
-  const int kind = DF_KERNEL_MO_TRANSFORM;
+// X P-major [naux][nao][ld] (all ncol columns)
+dfk::OutMap out_pmajor(double* X, int64_t naux, int64_t nao, int64_t ncol, int64_t ld) {
+  (void)naux;
+  dfk::OutMap o = dfk::out_plain(X, nao, ncol, ld);
+  o.s_z = nao * ld;
+  return o;
+}
+
+// columns [0, nocc) to Xo P-major [naux][nao][nocc], columns [nocc, nocc+nac) to Xa AO-major [nao][naux][nac]
+dfk::OutMap out_split(double* Xo, double* Xa, int64_t naux, int64_t nao, int64_t nocc, int64_t nac) {
+  dfk::OutMap o = dfk::out_plain(Xo, nao, nocc + nac, nocc);
+  o.s_z = nao * nocc;
+  o.nsplit = nocc;
+  o.p2 = Xa;
+  o.s2_m = naux * nac;
+  o.s2_z = nac;
+  return o;
+}
+
+// out[P][p][u] = sum_mu Cl[mu][p] Xa[mu][P][u]  (Cl is [nao][nl], Xa AO-major [nao][naux][nr])
+df_status run_mo(df_ctx* c, const double* Cl, int64_t nl, const double* Xa, int64_t naux, int64_t nao, int64_t nr,
+                 double* out) {
   if (nl == 0 || nr == 0) return DF_OK;
-  dfk::OpMap A{Cl, nl, nl, 0, 1, 1, nao, 0, nl, 0, nullptr, 0};
-  dfk::OpMap Bm{X + xoff, naux * nr, nr, nao * ldx, 1, 1, nao, 0, ldx, 0, nullptr, 0};
-  dfk::OutMap O{out, nl, naux * nr, nl, 0, nr, nr, nl * nr, 1, 0};
+  const int kind = DF_KERNEL_MO_TRANSFORM;
+  const dfk::OpMap A = dfk::op_map(Cl, nl, 1, nao, nl);
+  const dfk::OpMap Bm = dfk::op_map(Xa, naux * nr, 1, nao, naux * nr);
+  dfk::OutMap O = dfk::out_plain(out, nl, naux * nr, nr);
+  O.nl = nr;
+  O.s_nh = nl * nr;
   DF_LAUNCH(kind, dfk::launch_gemm(A, Bm, O, 1, c->stream), "second transform launch");
+  return DF_OK;
+}
+
+// Y[P][p][c] = sum_mu C2[mu][p] X[P][mu][c]  (X P-major [naux][nao][ncol]), batched over P
+df_status run_mo_pmajor(df_ctx* c, const double* C2, int64_t n2, const double* X, int64_t naux, int64_t nao,
+                        int64_t ncol, double* Y) {
+  if (n2 == 0 || ncol == 0) return DF_OK;
+  const dfk::OpMap A = dfk::op_map(C2, n2, 1, nao, n2);
+  dfk::OpMap Bm = dfk::op_map(X, ncol, 1, nao, ncol);
+  Bm.s_z = nao * ncol;
+  dfk::OutMap O = dfk::out_plain(Y, n2, ncol, ncol);
+  O.s_z = n2 * ncol;
+  for (int64_t p0 = 0; p0 < naux; p0 += 65535) {
+    const int64_t np_ = std::min<int64_t>(65535, naux - p0);
+    dfk::OpMap Bp = Bm;
+    Bp.p = X + p0 * nao * ncol;
+    dfk::OutMap Op = O;
+    Op.p = Y + p0 * n2 * ncol;
+    DF_LAUNCH(DF_KERNEL_MO_TRANSFORM, dfk::launch_gemm(A, Bp, Op, np_, c->stream), "second transform launch");
+  }
   return DF_OK;
 }
 
@@ -231,8 +304,8 @@ df_status run_mo(df_ctx* c, const double* Cl, int64_t nl, const double* X, int64
 df_status run_pgemm(df_ctx* c, int kind, const double* L, int64_t M, const double* R, int64_t N, int64_t naux,
                     double* out) {
   if (M == 0 || N == 0) return DF_OK;
-  dfk::OpMap A{L, M, M, 0, 1, 1, naux, 0, M, 0, nullptr, 0};
-  dfk::OpMap Bm{R, N, N, 0, 1, 1, naux, 0, N, 0, nullptr, 0};
+  const dfk::OpMap A = dfk::op_map(L, M, 1, naux, M);
+  const dfk::OpMap Bm = dfk::op_map(R, N, 1, naux, N);
   dfk::OutMap O = dfk::out_plain(out, M, N, N);
   DF_LAUNCH(kind, dfk::launch_gemm(A, Bm, O, 1, c->stream), "aux contraction launch");
   return DF_OK;
@@ -241,7 +314,10 @@ df_status run_pgemm(df_ctx* c, int kind, const double* L, int64_t M, const doubl
 // K[z] = sum_P X_z[P] diag(w_z) X_z[P]^T with X_z[P][i][c] = X[P][i][z*nocc + c]  (w may be NULL)
 df_status run_k(df_ctx* c, const double* X, const double* w, int64_t naux, int64_t nao, int64_t ldx,
                 int64_t nocc, int64_t nz, int nsplit, double* kpart, double* K) {
-  dfk::OpMap A{X, nao, nao, 0, ldx, naux, nocc, nao * ldx, 1, nocc, nullptr, 0};
+  dfk::OpMap A = dfk::op_map(X, nao, ldx, nocc, 1);
+  A.kb_n = naux;
+  A.s_kb = nao * ldx;
+  A.s_z = nocc;
   dfk::OpMap Bw = A;
   Bw.ks = w;
   Bw.s_ksz = nocc;
@@ -350,7 +426,12 @@ df_status df_workspace_size(df_op op, const df_dims* d, size_t* bytes) {
     case DF_OP_PAPA:
       plan_papa(pl, d->naux, d->nao, d->nac, d->np, d->nq, (d->flags & DF_PAPA_FULL) != 0);
       break;
-    case DF_OP_STEP: plan_step(pl, d->naux, d->nao, d->nocc, d->nac, d->np); break;
+    case DF_OP_STEP:
+      plan_step(pl, d->naux, d->nao, d->nocc, d->nac, d->np, (d->flags & DF_CALLER_X) != 0);
+      break;
+    case DF_OP_STEP_BACKWARD:
+      plan_backward(pl, d->naux, d->nao, d->nocc, d->nac, d->flags);
+      break;
     default: return DF_ERR_UNSUPPORTED;
   }
   *bytes = pl.total;
@@ -376,8 +457,8 @@ df_status df_half_transform(df_ctx* ctx, const double* B, int64_t naux, int64_t 
                            {Y, dbytes(naux * n2 * ncol), "Y", true}};
   if (!check_overlap(c, rs)) return DF_ERR_ARG;
   if (df_status s = enter(c)) return s;
-  if (df_status s = run_half(c, B, naux, nao, C, ncol, ncol, X, ncol)) return s;
-  if (C2) return run_mo(c, C2, n2, X, naux, nao, ncol, 0, ncol, Y);
+  if (df_status s = run_half(c, B, naux, nao, C, ncol, ncol, out_pmajor(X, naux, nao, ncol, ncol))) return s;
+  if (C2) return run_mo_pmajor(c, C2, n2, X, naux, nao, ncol, Y);
   return DF_OK;
 }
 
@@ -424,7 +505,7 @@ df_status df_jk(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int64_t
              "density factor gather");
     Ccat = cc;
   }
-  if (df_status s = run_half(c, B, naux, nao, Ccat, ncol, ncol, X, ncol)) return s;
+  if (df_status s = run_half(c, B, naux, nao, Ccat, ncol, ncol, out_pmajor(X, naux, nao, ncol, ncol))) return s;
   if (J || v) {
     double* vv = v ? v : (double*)(c->ws + p.vtmp);
     DF_LAUNCH(DF_KERNEL_JVEC, dfk::launch_jvec(X, naux, nao, ncol, Cocc, w, nocc, ndm, vv, c->stream), "J-vector launch");
@@ -461,8 +542,8 @@ df_status df_active_eri(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
   if (df_status s = enter(c)) return s;
   double* X = (double*)(c->ws + p.x);
   double* bu = buv ? buv : (double*)(c->ws + p.buv);
-  if (df_status s = run_half(c, B, naux, nao, Cact, nac, nac, X, nac)) return s;
-  if (df_status s = run_mo(c, Cact, nac, X, naux, nao, nac, 0, nac, bu)) return s;
+  if (df_status s = run_half(c, B, naux, nao, Cact, nac, nac, out_split(nullptr, X, naux, nao, 0, nac))) return s;
+  if (df_status s = run_mo(c, Cact, nac, X, naux, nao, nac, bu)) return s;
   return run_pgemm(c, DF_KERNEL_ERI, bu, nac * nac, bu, nac * nac, naux, eri);
 }
 
@@ -499,21 +580,21 @@ df_status df_papa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const
   if (df_status s = enter(c)) return s;
   double* X = (double*)(c->ws + p.x);
   double* bpu = (double*)(c->ws + p.bpu);
-  if (df_status s = run_half(c, B, naux, nao, Cact, nac, nac, X, nac)) return s;
-  if (df_status s = run_mo(c, Cp, np, X, naux, nao, nac, 0, nac, bpu)) return s;
+  if (df_status s = run_half(c, B, naux, nao, Cact, nac, nac, out_split(nullptr, X, naux, nao, 0, nac))) return s;
+  if (df_status s = run_mo(c, Cp, np, X, naux, nao, nac, bpu)) return s;
   if (full) {
     double* bqv = (double*)(c->ws + p.bqv);
-    if (df_status s = run_mo(c, Cq, nq, X, naux, nao, nac, 0, nac, bqv)) return s;
+    if (df_status s = run_mo(c, Cq, nq, X, naux, nao, nac, bqv)) return s;
     return run_pgemm(c, DF_KERNEL_PAPA, bpu, np * nac, bqv, nq * nac, naux, out);
   }
   double* bvw = (double*)(c->ws + p.bvw);
-  if (df_status s = run_mo(c, Cact, nac, X, naux, nao, nac, 0, nac, bvw)) return s;
+  if (df_status s = run_mo(c, Cact, nac, X, naux, nao, nac, bvw)) return s;
   return run_pgemm(c, DF_KERNEL_PAPA, bpu, np * nac, bvw, nac * nac, naux, out);
 }
 
 df_status df_step(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const double* Cocc, int64_t nocc,
                   const double* w, const double* Cact, int64_t nac, const double* Cp, int64_t np, double* J,
-                  double* K, double* v, double* eri, double* papa, int flags) {
+                  double* K, double* v, double* eri, double* papa, double* Xocc, double* Xact, int flags) {
   df_ctx* c = ctx;
   if (check_ctx(c)) return DF_ERR_ARG;
   if (df_status s = check_core(c, B, naux, nao)) return s;
@@ -522,6 +603,9 @@ df_status df_step(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const
   if (nocc > 0 && !Cocc) return fail(c, DF_ERR_ARG, "Cocc is NULL");
   if (nac > 0 && !Cact) return fail(c, DF_ERR_ARG, "Cact is NULL");
   if (np > 0 && !Cp) return fail(c, DF_ERR_ARG, "Cp is NULL");
+  const bool caller_x = Xocc != nullptr || Xact != nullptr;
+  if (caller_x && ((nocc > 0 && !Xocc) || (nac > 0 && !Xact)))
+    return fail(c, DF_ERR_ARG, "Xocc and Xact must be given together (NULL only for an empty one)");
   const int64_t npair = nao * (nao + 1) / 2;
   std::vector<Range> rs = {{B, dbytes(naux * npair), "B", false},
                            {Cocc, dbytes(nao * nocc), "Cocc", false},
@@ -532,9 +616,11 @@ df_status df_step(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const
                            {K, dbytes(nao * nao), "K", true},
                            {v, dbytes(naux), "v", true},
                            {eri, dbytes(nac * nac * nac * nac), "eri", true},
-                           {papa, dbytes(np * nac * nac * nac), "papa", true}};
+                           {papa, dbytes(np * nac * nac * nac), "papa", true},
+                           {Xocc, dbytes(naux * nao * nocc), "Xocc", true},
+                           {Xact, dbytes(naux * nao * nac), "Xact", true}};
   Plan pl;
-  const StepPlan p = plan_step(pl, naux, nao, nocc, nac, np);
+  const StepPlan p = plan_step(pl, naux, nao, nocc, nac, np, caller_x);
   const int64_t ncol = nocc + nac;
   if (ncol > 0) {
     if (!check_overlap(c, rs)) return DF_ERR_ARG;
@@ -551,35 +637,162 @@ df_status df_step(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const
   if (ncol == 0) return DF_OK;
   double* cc = (double*)(c->ws + p.ccat);
   if (nocc > 0)
-    DF_LAUNCH(DF_KERNEL_OTHER, hipMemcpy2DAsync(cc, ncol * sizeof(double), Cocc, nocc * sizeof(double), nocc * sizeof(double), nao,
-                            hipMemcpyDeviceToDevice, c->stream),
-           "Cocc gather");
+    DF_LAUNCH(DF_KERNEL_OTHER,
+              hipMemcpy2DAsync(cc, ncol * sizeof(double), Cocc, nocc * sizeof(double), nocc * sizeof(double), nao,
+                               hipMemcpyDeviceToDevice, c->stream),
+              "Cocc gather");
   if (nac > 0)
-    DF_LAUNCH(DF_KERNEL_OTHER, hipMemcpy2DAsync(cc + nocc, ncol * sizeof(double), Cact, nac * sizeof(double), nac * sizeof(double), nao,
-                            hipMemcpyDeviceToDevice, c->stream),
-           "Cact gather");
-  double* X = (double*)(c->ws + p.x);
-  if (df_status s = run_half(c, B, naux, nao, cc, ncol, ncol, X, ncol)) return s;
+    DF_LAUNCH(DF_KERNEL_OTHER,
+              hipMemcpy2DAsync(cc + nocc, ncol * sizeof(double), Cact, nac * sizeof(double), nac * sizeof(double),
+                               nao, hipMemcpyDeviceToDevice, c->stream),
+              "Cact gather");
+  double* Xo = caller_x ? Xocc : (double*)(c->ws + p.xo);
+  double* Xa = caller_x ? Xact : (double*)(c->ws + p.xa);
+  if (df_status s = run_half(c, B, naux, nao, cc, ncol, ncol, out_split(Xo, Xa, naux, nao, nocc, nac))) return s;
   if (nocc > 0) {
     if (J || v) {
       double* vv = v ? v : (double*)(c->ws + p.vtmp);
-      DF_LAUNCH(DF_KERNEL_JVEC, dfk::launch_jvec(X, naux, nao, ncol, Cocc, w, nocc, 1, vv, c->stream), "J-vector launch");
+      DF_LAUNCH(DF_KERNEL_JVEC, dfk::launch_jvec(Xo, naux, nao, nocc, Cocc, w, nocc, 1, vv, c->stream),
+                "J-vector launch");
       if (J) DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_coulomb(B, naux, nao, vv, 1, J, c->stream), "Coulomb launch");
     }
     if (K)
-      if (df_status s = run_k(c, X, w, naux, nao, ncol, nocc, 1, p.nsplit, (double*)(c->ws + p.kpart), K))
+      if (df_status s = run_k(c, Xo, w, naux, nao, nocc, nocc, 1, p.nsplit, (double*)(c->ws + p.kpart), K))
         return s;
   }
   if (nac > 0 && (eri || papa)) {
     double* buv = (double*)(c->ws + p.buv);
-    if (df_status s = run_mo(c, Cact, nac, X, naux, nao, ncol, nocc, nac, buv)) return s;
+    if (df_status s = run_mo(c, Cact, nac, Xa, naux, nao, nac, buv)) return s;
     if (eri)
       if (df_status s = run_pgemm(c, DF_KERNEL_ERI, buv, nac * nac, buv, nac * nac, naux, eri)) return s;
     if (papa && np > 0) {
       double* bpu = (double*)(c->ws + p.bpu);
-      if (df_status s = run_mo(c, Cp, np, X, naux, nao, ncol, nocc, nac, bpu)) return s;
+      if (df_status s = run_mo(c, Cp, np, Xa, naux, nao, nac, bpu)) return s;
       if (df_status s = run_pgemm(c, DF_KERNEL_PAPA, bpu, np * nac, buv, nac * nac, naux, papa)) return s;
     }
+  }
+  return DF_OK;
+}
+
+df_status df_step_backward(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const double* Cocc,
+                           int64_t nocc, const double* Cact, int64_t nac, const double* gJ, const double* gK,
+                           const double* geri, const double* Xocc, const double* Xact, double* dCocc,
+                           double* dCact, int flags) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (df_status s = check_core(c, B, naux, nao)) return s;
+  if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_step_backward takes no flags");
+  if (nocc < 0 || nac < 0) return fail(c, DF_ERR_SHAPE, "sizes must be >= 0");
+  if (nocc > 0 && (!Cocc || !dCocc)) return fail(c, DF_ERR_ARG, "Cocc and dCocc are required when nocc > 0");
+  if (nac > 0 && (!Cact || !dCact)) return fail(c, DF_ERR_ARG, "Cact and dCact are required when nac > 0");
+  const bool caller_x = Xocc != nullptr || Xact != nullptr;
+  if (caller_x && ((nocc > 0 && !Xocc) || (nac > 0 && !Xact)))
+    return fail(c, DF_ERR_ARG, "Xocc and Xact must be given together (NULL only for an empty one)");
+  const int pflags = (gJ ? DF_BWD_GJ : 0) | (gK ? DF_BWD_GK : 0) | (geri ? DF_BWD_GERI : 0) | (caller_x ? DF_CALLER_X : 0);
+  const int64_t npair = nao * (nao + 1) / 2;
+  std::vector<Range> rs = {{B, dbytes(naux * npair), "B", false},
+                           {Cocc, dbytes(nao * nocc), "Cocc", false},
+                           {Cact, dbytes(nao * nac), "Cact", false},
+                           {gJ, dbytes(nao * nao), "gJ", false},
+                           {gK, dbytes(nao * nao), "gK", false},
+                           {geri, dbytes(nac * nac * nac * nac), "geri", false},
+                           {Xocc, dbytes(naux * nao * nocc), "Xocc", false},
+                           {Xact, dbytes(naux * nao * nac), "Xact", false},
+                           {dCocc, dbytes(nao * nocc), "dCocc", true},
+                           {dCact, dbytes(nao * nac), "dCact", true}};
+  Plan pl;
+  const BwdPlan p = plan_backward(pl, naux, nao, nocc, nac, pflags);
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (df_status s = need_ws(c, pl.total)) return s;
+  if (pl.total) rs.push_back({c->ws, pl.total, "workspace", true});
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (df_status s = enter(c)) return s;
+  char* ws = c->ws;
+  const bool do_j = gJ && nocc > 0, do_k = gK && nocc > 0, do_e = geri && nac > 0;
+  if (nocc > 0 && !do_j && !do_k)
+    DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(dCocc, nao * nocc, c->stream), "fill");
+  if (nac > 0 && !do_e) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(dCact, nao * nac, c->stream), "fill");
+  // half transforms of the forward, recomputed when not supplied
+  const double* Xo = Xocc;
+  const double* Xa = Xact;
+  if (!caller_x && (do_k || do_e)) {
+    double* xo = do_k ? (double*)(ws + p.xo) : nullptr;
+    double* xa = do_e ? (double*)(ws + p.xa) : nullptr;
+    if (do_k && do_e) {
+      double* cc = (double*)(ws + p.ccat);
+      const int64_t ncol = nocc + nac;
+      DF_LAUNCH(DF_KERNEL_OTHER,
+                hipMemcpy2DAsync(cc, ncol * sizeof(double), Cocc, nocc * sizeof(double), nocc * sizeof(double), nao,
+                                 hipMemcpyDeviceToDevice, c->stream),
+                "Cocc gather");
+      DF_LAUNCH(DF_KERNEL_OTHER,
+                hipMemcpy2DAsync(cc + nocc, ncol * sizeof(double), Cact, nac * sizeof(double), nac * sizeof(double),
+                                 nao, hipMemcpyDeviceToDevice, c->stream),
+                "Cact gather");
+      if (df_status s = run_half(c, B, naux, nao, cc, ncol, ncol, out_split(xo, xa, naux, nao, nocc, nac))) return s;
+    } else if (do_k) {
+      if (df_status s = run_half(c, B, naux, nao, Cocc, nocc, nocc, out_pmajor(xo, naux, nao, nocc, nocc))) return s;
+    } else {
+      if (df_status s = run_half(c, B, naux, nao, Cact, nac, nac, out_split(nullptr, xa, naux, nao, 0, nac))) return s;
+    }
+    Xo = xo;
+    Xa = xa;
+  }
+  if (do_j) {
+    // dCocc = 2 M Cocc,  M = sum_P <b^P, gJ> b^P
+    double* g = (double*)(ws + p.g);
+    double* u = (double*)(ws + p.u);
+    double* M = (double*)(ws + p.M);
+    DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_pair_weights(gJ, nao, g, c->stream), "pair weights");
+    DF_LAUNCH(DF_KERNEL_JVEC, dfk::launch_jvec_packed(B, naux, nao, g, u, c->stream), "J-vector launch");
+    DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_coulomb(B, naux, nao, u, 1, M, c->stream), "Coulomb launch");
+    const dfk::OpMap A = dfk::op_map(M, nao, nao, nao, 1);
+    const dfk::OpMap Bm = dfk::op_map(Cocc, nocc, 1, nao, nocc);
+    dfk::OutMap O = dfk::out_plain(dCocc, nao, nocc, nocc);
+    O.alpha = 2.0;
+    DF_LAUNCH(DF_KERNEL_ADJOINT, dfk::launch_gemm(A, Bm, O, 1, c->stream), "adjoint product");
+  }
+  if (do_k) {
+    // dCocc += sum_P b^P Y_P,  Y_P = S X_P,  S = gK + gK^T
+    double* S = (double*)(ws + p.S);
+    double* Y = (double*)(ws + p.Y);
+    DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_symmetrize(gK, nao, 1, S, c->stream), "symmetrize");
+    const dfk::OpMap A = dfk::op_map(S, nao, nao, nao, 1);
+    dfk::OpMap Bm = dfk::op_map(Xo, naux * nocc, 1, nao, nocc);
+    Bm.rl = nocc;
+    Bm.s_rh = nao * nocc;
+    dfk::OutMap O = dfk::out_plain(Y, nao, naux * nocc, nocc);
+    O.nl = nocc;
+    O.s_nh = nao * nocc;
+    DF_LAUNCH(DF_KERNEL_ADJOINT, dfk::launch_gemm(A, Bm, O, 1, c->stream), "adjoint product");
+    dfk::OpMap Ym = dfk::op_map(Y, nocc, 1, nao, nocc);
+    Ym.kb_n = naux;
+    Ym.s_kb = nao * nocc;
+    dfk::OutMap Od = dfk::out_plain(dCocc, nao, nocc, nocc);
+    Od.accumulate = do_j ? 1 : 0;
+    DF_LAUNCH(DF_KERNEL_ADJOINT,
+              dfk::launch_half_reduce(B, naux, nao, Ym, Od, p.nsk, (double*)(ws + p.kpart), c->stream),
+              "adjoint packed product");
+  }
+  if (do_e) {
+    // dCact = sum_P X^act_P (Z_P + Z_P^T),  Z_P[uv] = sum_wx (geri[uvwx] + geri[wxuv]) b^P_wx
+    const int64_t n2 = nac * nac;
+    double* Gs = (double*)(ws + p.Gs);
+    double* buv = (double*)(ws + p.buv);
+    double* Z = (double*)(ws + p.Z);
+    DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_symmetrize(geri, n2, 1, Gs, c->stream), "symmetrize");
+    if (df_status s = run_mo(c, Cact, nac, Xa, naux, nao, nac, buv)) return s;
+    const dfk::OpMap A = dfk::op_map(buv, naux, n2, n2, 1);
+    const dfk::OpMap Bm = dfk::op_map(Gs, n2, n2, n2, 1);
+    DF_LAUNCH(DF_KERNEL_ADJOINT, dfk::launch_gemm(A, Bm, dfk::out_plain(Z, naux, n2, n2), 1, c->stream),
+              "adjoint product");
+    DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_symmetrize(Z, nac, naux, Z, c->stream), "symmetrize");
+    const dfk::OpMap Ax = dfk::op_map(Xa, nao, naux * nac, naux * nac, 1);
+    const dfk::OpMap Bz = dfk::op_map(Z, nac, 1, naux * nac, nac);
+    DF_LAUNCH(DF_KERNEL_ADJOINT,
+              dfk::launch_gemm_split(Ax, Bz, dfk::out_plain(dCact, nao, nac, nac), p.nsa, (double*)(ws + p.apart),
+                                     c->stream),
+              "adjoint product");
   }
   return DF_OK;
 }

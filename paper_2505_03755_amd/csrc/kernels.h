@@ -5,9 +5,10 @@
 
 namespace dfk {
 
-// Element (r, k) of a matrix operand.  The row index r in [0, rows) splits as
+// Element (r, k) of a matrix operand in batch z.  The row index r in [0, rows) splits as
 // r = rh * rl + rlo; the contraction index k splits as (kb, kc), kb in [0, kb_n),
-// kc in [0, kc_n).  Address = p + rh*s_rh + rlo*s_rlo + kb*s_kb + kc*s_kc (+ z*s_z).
+// kc in [0, kc_n).  Address = p + z*s_z + kb*s_kb + (rh*s_rh + rlo*s_rlo + kc*s_kc).
+// The bracketed part must stay below 2^32 elements (offsets_fit on the host).
 struct OpMap {
   const double* p;
   int64_t rows, rl, s_rh, s_rlo;
@@ -17,42 +18,73 @@ struct OpMap {
   int64_t s_ksz;
 };
 
-// Output element (m, n): p + z*s_z + (m/ml)*s_mh + (m%ml)*s_ml + (n/nl)*s_nh + (n%nl)*s_nl.
+// Output element (m, n) of batch z.  Columns n < nsplit go to
+//   p + z*s_z + (m/ml)*s_mh + (m%ml)*s_ml + (n/nl)*s_nh + (n%nl)*s_nl,
+// columns n >= nsplit to  p2 + z*s2_z + m*s2_m + (n - nsplit).
+// The stored value is alpha * result, added to what is there when `accumulate` is set.
 struct OutMap {
   double* p;
   int64_t M, N;
   int64_t ml, s_mh, s_ml;
   int64_t nl, s_nh, s_nl;
   int64_t s_z;
+  int64_t nsplit;
+  double* p2;
+  int64_t s2_m, s2_z;
+  double alpha;
+  int accumulate;
 };
 
-__host__ __device__ inline OpMap op_rowmajor(const double* p, int64_t rows, int64_t k, int64_t ld_row, int64_t ld_k) {
+__host__ __device__ inline OpMap op_map(const double* p, int64_t rows, int64_t ld_row, int64_t kc_n, int64_t ld_k) {
   // element (r, k) at p + r*ld_row + k*ld_k
-  return OpMap{p, rows, rows > 0 ? rows : 1, 0, ld_row, 1, k, 0, ld_k, 0, nullptr, 0};
+  return OpMap{p, rows, rows > 0 ? rows : 1, 0, ld_row, 1, kc_n, 0, ld_k, 0, nullptr, 0};
 }
 
 __host__ __device__ inline OutMap out_plain(double* p, int64_t M, int64_t N, int64_t ld) {
-  return OutMap{p, M, N, M > 0 ? M : 1, 0, ld, N > 0 ? N : 1, 0, 1, 0};
+  return OutMap{p, M, N, M > 0 ? M : 1, 0, ld, N > 0 ? N : 1, 0, 1, 0, N, nullptr, 0, 0, 1.0, 0};
 }
 
-// X[P][m][c] = sum_k b^P_{mk} C[k][c] for c in [0, ncol); X row stride ldx, slab stride
-// nao*ldx.  P in [p0, p0 + np_).
-hipError_t launch_half_transform(const double* B, int64_t naux, int64_t nao, const double* C,
-                                 int64_t ldc, int64_t ncol, double* X, int64_t ldx,
-                                 hipStream_t s);
+// True when every within-slab element offset of `o` fits 32 bits.
+bool offsets_fit(const OpMap& o);
+
+// Half transform: for each P, T[m][c] = sum_k b^P_{mk} C[k][c], c in [0, ncol), written
+// through `out` with z = P (out.M = nao, out.N = ncol).
+hipError_t launch_half_transform(const double* B, int64_t naux, int64_t nao, const double* C, int64_t ldc,
+                                 int64_t ncol, const OutMap& out, hipStream_t s);
 
 // C(m, n) = sum_k A(m, k) B(n, k) for a batch of nz problems (grid z).
 hipError_t launch_gemm(const OpMap& A, const OpMap& Bm, const OutMap& C, int64_t nz, hipStream_t s);
 
-// Lower-tile SYRK with a split over kb: Kpart[split][z][i][j] = sum_{kb in split, kc} A(i,(kb,kc)) A(j,(kb,kc))
-// for tile(i) >= tile(j).  Returns the number of splits used through *nsplit (planning:
-// syrk_splits()).  Kpart is dense [nsplit][nz][n][n].
+// The same product for one problem with the contraction split over nsplit workgroup sets:
+// partial sums go to part [nsplit][M][N] and a fixed-order reduction writes C.  gemm_splits()
+// is the split count the workspace is planned with (part needs nsplit*M*N doubles if > 1).
+int gemm_splits(int64_t M, int64_t N, int64_t nslab);
+int64_t gemm_slabs(const OpMap& A);
+hipError_t launch_gemm_split(const OpMap& A, const OpMap& Bm, const OutMap& C, int nsplit, double* part,
+                             hipStream_t s);
+
+// C(m, n) = sum_{P < naux} sum_k b^P_{mk} Y(n, (P, k)), Y given as an OpMap whose kb is P and
+// kc the AO index k; split over P ranges with partials [nsplit][nao][N] (half_reduce_splits()).
+int half_reduce_splits(int64_t nao, int64_t N, int64_t naux);
+hipError_t launch_half_reduce(const double* B, int64_t naux, int64_t nao, const OpMap& Y, const OutMap& C,
+                              int nsplit, double* part, hipStream_t s);
+
+// g[pair(i,j)] = G[i][j] + G[j][i] (i > j), G[i][i] (i == j): <b^P, G> = sum_pair b^P[pair] g[pair]
+hipError_t launch_pair_weights(const double* G, int64_t nao, double* g, hipStream_t s);
+// u[P] = sum_pair B[P][pair] g[pair]
+hipError_t launch_jvec_packed(const double* B, int64_t naux, int64_t nao, const double* g, double* u,
+                              hipStream_t s);
+// out[z] = in[z] + in[z]^T for nz square n x n matrices (out may equal in)
+hipError_t launch_symmetrize(const double* in, int64_t n, int64_t nz, double* out, hipStream_t s);
+
+// Lower-tile SYRK with a split over kb: Kpart[split][z][i][j] = sum_{kb in split, kc} A(i,(kb,kc)) Bw(j,(kb,kc))
+// for tile(i) >= tile(j) (Bw = A with an optional per-kc weight).  Kpart is dense [nsplit][nz][n][n];
+// syrk_splits() gives the number of splits the workspace is planned for.
 int syrk_splits(int64_t n, int64_t kb_n, int64_t nz);
 int syrk_tile();
-// Bw is A with an optional contraction-index scale (signed occupation weights).
 hipError_t launch_syrk_partial(const OpMap& A, const OpMap& Bw, int64_t n, int64_t nz, int nsplit,
                                double* Kpart, hipStream_t s);
-// K[z][i][j] = sum_s Kpart[s][z][max-tile element]; both triangles written.
+// K[z][i][j] = sum_s Kpart[s][z][max(i,j)][min(i,j)]; both triangles written.
 hipError_t launch_syrk_reduce(const double* Kpart, int nsplit, int64_t n, int64_t nz, double* K,
                               hipStream_t s);
 
@@ -64,7 +96,7 @@ hipError_t launch_jvec(const double* X, int64_t naux, int64_t nao, int64_t ldx, 
 hipError_t launch_coulomb(const double* B, int64_t naux, int64_t nao, const double* v,
                           int64_t nz, double* J, hipStream_t s);
 
-// Y[r][c] = 0 for a strided 2-D block (used for zero-sized contractions).
+// p[0..n) = 0
 hipError_t launch_fill_zero(double* p, int64_t n, hipStream_t s);
 
 }  // namespace dfk

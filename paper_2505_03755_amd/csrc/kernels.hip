@@ -19,13 +19,19 @@
 
 #include <math.h>
 
+#include <type_traits>
+#include <utility>
+
 namespace dfk {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-template <int WM_, int WN_, int TM_, int TN_>
+// WM x WN waves, each TM x TN MFMA tiles of 16 x 16; IL selects the interleaved schedule
+// (loads and LDS stores spread between the MFMAs) over the bulk one.
+template <int WM_, int WN_, int TM_, int TN_, bool IL_ = false>
 struct Cfg {
   static constexpr int WM = WM_, WN = WN_, TM = TM_, TN = TN_;
+  static constexpr bool IL = IL_;
   static constexpr int NT = 64 * WM * WN;
   static constexpr int BM = 16 * TM * WM, BN = 16 * TN * WN, BK = 16;
   static constexpr int LD = BK + 1;
@@ -33,8 +39,9 @@ struct Cfg {
   static_assert((BM * BK) % NT == 0 && (BN * BK) % NT == 0, "tile must split evenly over threads");
 };
 
-// generic products and the K SYRK: 128 x 128 tiles, 2 x 2 waves of 64 x 64
+// generic products: 128 x 128 tiles, 2 x 2 waves of 64 x 64; the K SYRK the same, interleaved
 typedef Cfg<2, 2, 4, 4> CfgSq;
+typedef Cfg<2, 2, 4, 4, true> CfgSyrk;
 // half transform: 128 rows x {176, 96, 48} columns, 4 waves stacked along the rows
 typedef Cfg<4, 1, 2, 11> CfgH176;
 typedef Cfg<4, 1, 2, 6> CfgH96;
@@ -51,22 +58,21 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t id, int64_t n) {
   return (id % 8) * (full / 8) + id / 8;
 }
 
+// One k-step (4 deep) worth of MFMA operands of one wave.
 template <class C>
-__device__ __forceinline__ void mma_slab(const double* __restrict__ As, const double* __restrict__ Bs,
-                                         d4 (&acc)[C::TM][C::TN], int wm, int wn, int lane) {
+struct Frag {
+  double a[C::TM];
+  double b[C::TN];
+};
+
+template <class C>
+__device__ __forceinline__ void read_frag(const double* __restrict__ As, const double* __restrict__ Bs, int kk,
+                                          Frag<C>& f, int wm, int wn, int lane) {
   const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
-  for (int kk = 0; kk < C::BK; kk += 4) {
-    double a[C::TM], b[C::TN];
+  for (int i = 0; i < C::TM; ++i) f.a[i] = As[((wm * C::TM + i) * 16 + lr) * C::LD + kk + lk];
 #pragma unroll
-    for (int i = 0; i < C::TM; ++i) a[i] = As[((wm * C::TM + i) * 16 + lr) * C::LD + kk + lk];
-#pragma unroll
-    for (int j = 0; j < C::TN; ++j) b[j] = Bs[((wn * C::TN + j) * 16 + lr) * C::LD + kk + lk];
-#pragma unroll
-    for (int i = 0; i < C::TM; ++i)
-#pragma unroll
-      for (int j = 0; j < C::TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-  }
+  for (int j = 0; j < C::TN; ++j) f.b[j] = Bs[((wn * C::TN + j) * 16 + lr) * C::LD + kk + lk];
 }
 
 template <class C>
@@ -77,68 +83,158 @@ __device__ __forceinline__ void zero_acc(d4 (&acc)[C::TM][C::TN]) {
     for (int j = 0; j < C::TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 }
 
-// Two-stage software pipeline over nslab k-slabs.  load(s) fetches slab s into registers,
-// store(stage) writes those registers into LDS stage `stage`.
-template <class C, class FLoad, class FStore>
-__device__ __forceinline__ void pipeline(double* smem, int64_t nslab, d4 (&acc)[C::TM][C::TN], int wm, int wn,
-                                         int lane, FLoad&& load, FStore&& store) {
-  if (nslab > 0) {
-    load(0);
-    store(0);
-  }
+// Compile-time loops.
+template <int... I, class F>
+__device__ __forceinline__ void static_for_impl(std::integer_sequence<int, I...>, F&& f) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(std::make_integer_sequence<int, N>{}, f);
+}
+
+// One slab of the software pipeline.  LDS stage `cur` holds the slab being multiplied and F[0]
+// already holds its first k-step of operands.  While its TM*TN*BK/4 MFMAs issue one by one,
+// the wave reads the operands of the next k-step, issues the global loads of the next slab in
+// the first half, and writes those same registers to the other LDS stage in the second half
+// (a few thousand cycles after the loads went out).  Then one barrier and the first operands
+// of the next slab.  Every slot is generated at compile time, so the body is one basic block;
+// scheduling fences keep the interleave.
+template <class C, class Src>
+__device__ __forceinline__ void slab_step(Src& src, double* smem, int cur, d4 (&acc)[C::TM][C::TN],
+                                          Frag<C> (&F)[2], int wm, int wn, int lane) {
+  const double* As = smem + cur * C::STAGE;
+  const double* Bs = As + C::LDS_A;
+  double* An = smem + (cur ^ 1) * C::STAGE;
+  double* Bn = An + C::LDS_A;
+  constexpr int KS = C::BK / 4;            // k-steps per slab
+  constexpr int PK = C::TM * C::TN;        // MFMAs per k-step
+  constexpr int NM = PK * KS;              // MFMAs per slab
+  constexpr int HALF = NM / 2;
+  constexpr int NL = Src::NL;
+  static_assert(HALF > 0, "at least two MFMAs per slab");
+  src.begin();
+  static_for<NM>([&](auto IDXc) {
+    constexpr int IDX = decltype(IDXc)::value;
+    constexpr int ks = IDX / PK, ij = IDX % PK, i = ij / C::TN, j = ij % C::TN;
+    if constexpr (ij == 0) {
+      if constexpr (ks + 1 < KS) read_frag<C>(As, Bs, (ks + 1) * 4, F[(ks + 1) & 1], wm, wn, lane);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(F[ks & 1].a[i], F[ks & 1].b[j], acc[i][j], 0, 0, 0);
+    if constexpr (IDX < HALF) {
+      constexpr int Q0 = IDX * NL / HALF, Q1 = (IDX + 1) * NL / HALF;
+      static_for<Q1 - Q0>([&](auto R) { src.template load<Q0 + decltype(R)::value>(); });
+    } else {
+      constexpr int Q0 = (IDX - HALF) * NL / HALF, Q1 = (IDX - HALF + 1) * NL / HALF;
+      static_for<Q1 - Q0>([&](auto R) { src.template store<Q0 + decltype(R)::value>(An, Bn); });
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  });
+  src.finish();
   __syncthreads();
-  for (int64_t s = 0; s < nslab; ++s) {
-    const int cur = (int)(s & 1);
-    const bool more = s + 1 < nslab;
-    if (more) load(s + 1);
-    // keep the prefetch ahead of, and its consumers behind, the MFMA block
-    __builtin_amdgcn_sched_barrier(0);
-    mma_slab<C>(smem + cur * C::STAGE, smem + cur * C::STAGE + C::LDS_A, acc, wm, wn, lane);
-    __builtin_amdgcn_sched_barrier(0);
-    if (more) store(cur ^ 1);
-    __syncthreads();
+  read_frag<C>(An, Bn, 0, F[0], wm, wn, lane);
+}
+
+// Bulk schedule of one slab: all global loads of the next slab, then every MFMA of this one,
+// then the LDS stores of the loaded registers into the other stage and one barrier.
+template <class C, class Src>
+__device__ __forceinline__ void slab_step_bulk(Src& src, double* smem, int cur, d4 (&acc)[C::TM][C::TN], int wm,
+                                               int wn, int lane) {
+  const double* As = smem + cur * C::STAGE;
+  const double* Bs = As + C::LDS_A;
+  double* An = smem + (cur ^ 1) * C::STAGE;
+  src.begin();
+  static_for<Src::NL>([&](auto Q) { src.template load<decltype(Q)::value>(); });
+  src.finish();
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int kk = 0; kk < C::BK; kk += 4) {
+    Frag<C> f;
+    read_frag<C>(As, Bs, kk, f, wm, wn, lane);
+#pragma unroll
+    for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+      for (int j = 0; j < C::TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.a[i], f.b[j], acc[i][j], 0, 0, 0);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  static_for<Src::NL>([&](auto Q) { src.template store<decltype(Q)::value>(An, An + C::LDS_A); });
+  __syncthreads();
+}
+
+// Runs nslab slabs through the pipeline (nslab >= 1).  The loads issued during the last slab
+// re-read it (the sources clamp) and land in the stage nobody reads any more.
+template <class C, class Src>
+__device__ __forceinline__ void mainloop(Src& src, double* smem, int64_t nslab, d4 (&acc)[C::TM][C::TN], int wm,
+                                         int wn, int lane) {
+  src.begin();
+  static_for<Src::NL>([&](auto Q) { src.template load<decltype(Q)::value>(); });
+  src.finish();
+  static_for<Src::NL>([&](auto Q) { src.template store<decltype(Q)::value>(smem, smem + C::LDS_A); });
+  __syncthreads();
+  if constexpr (C::IL) {
+    Frag<C> F[2];
+    read_frag<C>(smem, smem + C::LDS_A, 0, F[0], wm, wn, lane);
+    for (int64_t s = 0; s < nslab; ++s) slab_step<C>(src, smem, (int)(s & 1), acc, F, wm, wn, lane);
+  } else {
+    for (int64_t s = 0; s < nslab; ++s) slab_step_bulk<C>(src, smem, (int)(s & 1), acc, wm, wn, lane);
   }
 }
 
-template <class C>
+// Epilogue.  GEN = false stores the accumulators as they are (o.alpha must be 1 and
+// o.accumulate 0); GEN = true applies alpha and accumulate.  Arithmetic on the accumulators
+// here moves them out of the matrix-core registers for the whole main loop (a copy per MFMA
+// operand per slab), so only launches that need it instantiate GEN.
+template <class C, bool GEN>
 __device__ __forceinline__ void store_tile(const OutMap& o, int64_t z, int64_t m0, int64_t n0,
                                            const d4 (&acc)[C::TM][C::TN], int wm, int wn, int lane) {
   const int lr = lane & 15, lg = lane >> 4;
-  double* base = o.p + z * o.s_z;
+  const int64_t zo1 = z * o.s_z, zo2 = z * o.s2_z;
 #pragma unroll
   for (int j = 0; j < C::TN; ++j) {
     const int64_t n = n0 + (wn * C::TN + j) * 16 + lr;
-    if (n >= o.N) continue;
+    const bool nok = n < o.N, first = n < o.nsplit;
     const uint32_t nh = o.s_nh ? (uint32_t)n / (uint32_t)o.nl : 0u;
-    const int64_t noff = (int64_t)nh * o.s_nh + (n - (int64_t)nh * o.nl) * o.s_nl;
+    const int64_t noff1 = (int64_t)nh * o.s_nh + (n - (int64_t)nh * o.nl) * o.s_nl;
+    // integer select: p2 is null when every column goes to p
+    const uintptr_t col = first ? (uintptr_t)o.p + 8u * (uint64_t)(zo1 + noff1)
+                                : (uintptr_t)o.p2 + 8u * (uint64_t)(zo2 + n - o.nsplit);
 #pragma unroll
     for (int i = 0; i < C::TM; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t m = m0 + (wm * C::TM + i) * 16 + 4 * r + lg;
         const uint32_t mh = o.s_mh ? (uint32_t)m / (uint32_t)o.ml : 0u;
-        if (m < o.M) base[(int64_t)mh * o.s_mh + (m - (int64_t)mh * o.ml) * o.s_ml + noff] = acc[i][j][r];
+        const int64_t moff = first ? (int64_t)mh * o.s_mh + (m - (int64_t)mh * o.ml) * o.s_ml : m * o.s2_m;
+        double* const dst = (double*)col + moff;
+        if constexpr (GEN) {
+          const double val = o.alpha * acc[i][j][r];
+          if (nok && m < o.M) *dst = o.accumulate ? *dst + val : val;
+        } else {
+          if (nok && m < o.M) *dst = acc[i][j][r];
+        }
       }
   }
 }
 
-// Global -> register -> LDS loader for one operand described by an OpMap.
+// Operand described by an OpMap, staged through two register sets.  Slabs are walked in order
+// (kb outer, kc in chunks of 16 inner) from slab `first` to `last`; loads past `last` re-read it.
 //   KC = true : lanes run along k (16 consecutive k of one row per 16 lanes)
 //   KC = false: lanes run along the row index
-//   SCALE     : multiply element (r, kc) by ks[z*s_ksz + kc] (applied when storing to LDS)
-// The slab sequence is walked in order: kb outer, kc in chunks of 16 inner.
+//   SCALE     : element (r, kc) times ks[z*s_ksz + kc]
 template <class C, int R, bool KC, bool SCALE = false>
-struct Loader {
+struct Operand {
   static constexpr int E = R * C::BK / C::NT;
   static_assert(E <= 32, "validity mask holds 32 elements");
-  int64_t rowbase[E];  // offset of (row, kb = 0, kc = 0), rows past the end clamped to the last one
-  unsigned rowok;      // bit q: the row of element q exists
-  double v[E];         // raw loaded values; invalid ones are zeroed when written to LDS
+  uint32_t eoff[E];     // offset of element q from the slab base (rows past the end clamped)
+  unsigned rowok;       // bit q: the row of element q exists
+  double v[E];
   double sc[SCALE ? E : 1];
-  int64_t kso;
-  int64_t kb;          // slab the next load() fetches: (kb, kc0)
-  int kc0;
-  int kvalid;          // valid k entries of the slab last loaded
+  int kval;             // valid k entries of the slab held in v
+  const double* base;
+  int64_t zoff, kso;
+  int64_t kb, kb_last;  // cursor: next slab to load is (kb, kc0)
+  int kc0, kc_last;
 
   __device__ __forceinline__ static int rr(int t, int q) {
     const int e = t + C::NT * q;
@@ -148,84 +244,144 @@ struct Loader {
     const int e = t + C::NT * q;
     return KC ? e % C::BK : e / R;
   }
-  __device__ __forceinline__ void init(const OpMap& o, int64_t r0, int64_t z, int64_t kb0, int t) {
+  // rows [r0, r0 + R) of batch z; slabs s_begin .. s_end - 1 in (kb outer, kc chunk inner) order
+  __device__ __forceinline__ void init(const OpMap& o, int64_t r0, int64_t z, int64_t s_begin, int64_t s_end,
+                                       int t) {
+    zoff = z * o.s_z;
     kso = z * o.s_ksz;
-    kb = kb0;
-    kc0 = 0;
-    kvalid = 0;
+    const int64_t nkc = (o.kc_n + C::BK - 1) / C::BK;
+    kb = s_begin / nkc;
+    kc0 = (int)(s_begin % nkc) * C::BK;
+    kb_last = (s_end - 1) / nkc;
+    kc_last = (int)((s_end - 1) % nkc) * C::BK;
     rowok = 0;
 #pragma unroll
     for (int q = 0; q < E; ++q) {
       const int64_t r = r0 + rr(t, q);
       const bool ok = r < o.rows;
       rowok |= (ok ? 1u : 0u) << q;
-      const uint32_t rc = (uint32_t)(ok ? r : o.rows - 1);   // row indices fit 32 bits
+      const uint32_t rc = (uint32_t)(ok ? r : o.rows - 1);
       uint32_t rh = 0, rlo = rc;
       if (o.s_rh != 0) {
         rh = rc / (uint32_t)o.rl;
         rlo = rc - rh * (uint32_t)o.rl;
       }
-      rowbase[q] = z * o.s_z + (int64_t)rh * o.s_rh + (int64_t)rlo * o.s_rlo;
+      eoff[q] = rh * (uint32_t)o.s_rh + rlo * (uint32_t)o.s_rlo + (uint32_t)kk(t, q) * (uint32_t)o.s_kc;
     }
   }
-  // issue the loads of the current slab (addresses clamped in range) and advance
+  __device__ __forceinline__ void begin(const OpMap& o) {
+    base = o.p + zoff + kb * o.s_kb + (int64_t)kc0 * o.s_kc;
+    kval = (int)o.kc_n - kc0;
+  }
+  template <int q>
   __device__ __forceinline__ void load(const OpMap& o, int t) {
-    const double* __restrict__ base = o.p + kb * o.s_kb;
-    const int klast = (int)o.kc_n - 1;
-#pragma unroll
-    for (int q = 0; q < E; ++q) {
-      const int kc = min(kc0 + kk(t, q), klast);
-      const int64_t koff = KC ? (int64_t)kc : (int64_t)(uint32_t)kc * (uint32_t)o.s_kc;
-      v[q] = base[rowbase[q] + koff];
-      if (SCALE) sc[q] = o.ks[kso + kc];
-    }
-    kvalid = (int)o.kc_n - kc0;
-    kc0 += C::BK;
-    if (kc0 >= o.kc_n) {
-      kc0 = 0;
-      ++kb;
-    }
+    // entries past kc_n read the last valid k of the row instead (zeroed in store)
+    const int over = kk(t, q) - (kval - 1);
+    const uint32_t back = over > 0 ? (uint32_t)over * (uint32_t)o.s_kc : 0u;
+    v[q] = base[eoff[q] - back];
+    if constexpr (SCALE) sc[q] = o.ks[kso + kc0 + min(kk(t, q), kval - 1)];
   }
-  __device__ __forceinline__ void store(double* S, int t) const {
-#pragma unroll
-    for (int q = 0; q < E; ++q) {
-      const bool ok = ((rowok >> q) & 1u) && kk(t, q) < kvalid;
-      const double x = SCALE ? v[q] * sc[q] : v[q];
-      S[rr(t, q) * C::LD + kk(t, q)] = ok ? x : 0.0;
+  __device__ __forceinline__ void finish(const OpMap& o) {
+    // advance the cursor, but never past the last slab
+    const bool at_end = kb == kb_last && kc0 == kc_last;
+    int nkc = kc0 + C::BK;
+    int64_t nkb = kb;
+    if (nkc >= o.kc_n) {
+      nkc = 0;
+      ++nkb;
     }
+    kc0 = at_end ? kc0 : nkc;
+    kb = at_end ? kb : nkb;
+  }
+  template <int q>
+  __device__ __forceinline__ void store(double* Sm, int t) const {
+    const bool ok = ((rowok >> q) & 1u) && kk(t, q) < kval;
+    const double x = SCALE ? v[q] * sc[q] : v[q];
+    Sm[rr(t, q) * C::LD + kk(t, q)] = ok ? x : 0.0;
+  }
+};
+
+// Source of a product with both operands from OpMaps (kb range [kb_first, kb_end)).
+template <class C, bool AK, bool BK, bool SCALE>
+struct PairSrc {
+  static constexpr int EA = Operand<C, C::BM, AK>::E;
+  static constexpr int NL = EA + Operand<C, C::BN, BK, SCALE>::E;
+  Operand<C, C::BM, AK> a;
+  Operand<C, C::BN, BK, SCALE> b;
+  const OpMap* A;
+  const OpMap* B;
+  int t;
+  __device__ __forceinline__ void begin() {
+    a.begin(*A);
+    b.begin(*B);
+  }
+  template <int q>
+  __device__ __forceinline__ void load() {
+    if constexpr (q < EA) a.template load<q>(*A, t);
+    else b.template load<q - EA>(*B, t);
+  }
+  __device__ __forceinline__ void finish() {
+    a.finish(*A);
+    b.finish(*B);
+  }
+  template <int q>
+  __device__ __forceinline__ void store(double* As, double* Bs) const {
+    if constexpr (q < EA) a.template store<q>(As, t);
+    else b.template store<q - EA>(Bs, t);
   }
 };
 
 // ---------------------------------------------------------------------------------------
-// Generic tiled product  C(m, n) = sum_k A(m, k) B(n, k)  over a batch (grid z).
-template <class C, bool AK, bool BK>
-__global__ void __launch_bounds__(C::NT) gemm_kernel(OpMap A, OpMap B, OutMap O, int64_t tilesM,
-                                                     int64_t tilesN) {
+// Generic tiled product  C(m, n) = sum_k A(m, k) B(n, k)  over a batch (grid z).  With grid
+// y = nsplit > 1 each workgroup set covers a contiguous range of k slabs and writes its partial
+// sums to part[split][M][N] (nz must be 1 then).
+template <class C, bool AK, bool BK, bool GEN>
+__global__ void __launch_bounds__(C::NT) gemm_kernel(OpMap A, OpMap B, OutMap O, int64_t tilesM, int64_t tilesN,
+                                                     double* part) {
   __shared__ double smem[2 * C::STAGE];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave % C::WM, wn = wave / C::WM;
   const int64_t tile = xcd_remap(blockIdx.x, tilesM * tilesN);
   const int64_t z = blockIdx.z;
   const int64_t m0 = (tile % tilesM) * C::BM, n0 = (tile / tilesM) * C::BN;
+  const int64_t nslab_all = A.kb_n * ((A.kc_n + C::BK - 1) / C::BK);
+  const int nsplit = gridDim.y, split = blockIdx.y;
+  const int64_t s0 = nslab_all * split / nsplit, s1 = nslab_all * (split + 1) / nsplit;
 
-  Loader<C, C::BM, AK> la;
-  Loader<C, C::BN, BK> lb;
-  la.init(A, m0, z, 0, t);
-  lb.init(B, n0, z, 0, t);
   d4 acc[C::TM][C::TN];
   zero_acc<C>(acc);
-  const int64_t nslab = A.kb_n * ((A.kc_n + C::BK - 1) / C::BK);
-  pipeline<C>(
-      smem, nslab, acc, wm, wn, lane,
-      [&](int64_t) {
-        la.load(A, t);
-        lb.load(B, t);
-      },
-      [&](int st) {
-        la.store(smem + st * C::STAGE, t);
-        lb.store(smem + st * C::STAGE + C::LDS_A, t);
-      });
-  store_tile<C>(O, z, m0, n0, acc, wm, wn, lane);
+  if (s1 > s0) {
+    PairSrc<C, AK, BK, false> src;
+    src.A = &A;
+    src.B = &B;
+    src.t = t;
+    src.a.init(A, m0, z, s0, s1, t);
+    src.b.init(B, n0, z, s0, s1, t);
+    mainloop<C>(src, smem, s1 - s0, acc, wm, wn, lane);
+  }
+  if (part) {
+    const OutMap po = out_plain(part + (int64_t)split * O.M * O.N, O.M, O.N, O.N);
+    store_tile<C, false>(po, 0, m0, n0, acc, wm, wn, lane);
+  } else {
+    store_tile<C, GEN>(O, z, m0, n0, acc, wm, wn, lane);
+  }
+}
+
+// C(m, n) = alpha * sum_s part[s][m][n] (+ C), fixed order over s.
+__global__ void __launch_bounds__(256) split_reduce_kernel(const double* __restrict__ part, int nsplit, OutMap O) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t MN = O.M * O.N;
+  if (idx >= MN) return;
+  const int64_t m = idx / O.N, n = idx % O.N;
+  double s = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) s += part[(int64_t)sp * MN + idx];
+  double* dst;
+  if (n < O.nsplit) {
+    dst = O.p + (m / O.ml) * O.s_mh + (m % O.ml) * O.s_ml + (n / O.nl) * O.s_nh + (n % O.nl) * O.s_nl;
+  } else {
+    dst = O.p2 + m * O.s2_m + (n - O.nsplit);
+  }
+  *dst = O.accumulate ? *dst + O.alpha * s : O.alpha * s;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -251,25 +407,21 @@ __global__ void __launch_bounds__(C::NT) syrk_kernel(OpMap A, OpMap Bw, int64_t 
   const int64_t m0 = I * C::BM, n0 = J * C::BN;
   const int64_t kb_lo = A.kb_n * split / nsplit, kb_hi = A.kb_n * (split + 1) / nsplit;
 
-  Loader<C, C::BM, true> la;
-  Loader<C, C::BN, true, SCALE> lb;
-  la.init(A, m0, z, kb_lo, t);
-  lb.init(Bw, n0, z, kb_lo, t);
   d4 acc[C::TM][C::TN];
   zero_acc<C>(acc);
   const int64_t nslab = (kb_hi - kb_lo) * ((A.kc_n + C::BK - 1) / C::BK);
-  pipeline<C>(
-      smem, nslab, acc, wm, wn, lane,
-      [&](int64_t) {
-        la.load(A, t);
-        lb.load(Bw, t);
-      },
-      [&](int st) {
-        la.store(smem + st * C::STAGE, t);
-        lb.store(smem + st * C::STAGE + C::LDS_A, t);
-      });
+  if (nslab > 0) {
+    PairSrc<C, true, true, SCALE> src;
+    src.A = &A;
+    src.B = &Bw;
+    src.t = t;
+    const int64_t nkc = (A.kc_n + C::BK - 1) / C::BK;
+    src.a.init(A, m0, z, kb_lo * nkc, kb_hi * nkc, t);
+    src.b.init(Bw, n0, z, kb_lo * nkc, kb_hi * nkc, t);
+    mainloop<C>(src, smem, nslab, acc, wm, wn, lane);
+  }
   OutMap o = out_plain(Kpart + ((int64_t)split * nz + z) * n * n, n, n, n);
-  store_tile<C>(o, 0, m0, n0, acc, wm, wn, lane);
+  store_tile<C, false>(o, 0, m0, n0, acc, wm, wn, lane);
 }
 
 __global__ void __launch_bounds__(256) syrk_reduce_kernel(const double* __restrict__ Kpart, int nsplit,
@@ -289,80 +441,146 @@ __global__ void __launch_bounds__(256) syrk_reduce_kernel(const double* __restri
 // A operand element (m, k) = b^P_{mk}.  A slab strictly below the diagonal (every k < every
 // m) is read along k: 16-element runs of packed rows.  Any other slab is read along m and
 // addressed through (max, min), which for slabs above the diagonal are runs of packed row k.
-// Packed offsets stay in 32 bits (nao <= 46340).
+// Both address sets are formed and one is selected, so the loads stay branch-free; packed
+// offsets stay in 32 bits (nao <= 46340).
+template <class C>
+struct HalfSrc {
+  static constexpr int EA = C::BM * C::BK / C::NT;
+  static constexpr int NL = EA + Operand<C, C::BN, false>::E;
+  static_assert(EA <= 32, "validity mask holds 32 elements");
+  static_assert(C::NT % C::BK == 0 && C::NT % C::BM == 0, "per-thread row / column of the A loads");
+  Operand<C, C::BN, false> c;
+  const OpMap* Cm;
+  const double* Bbase;  // packed b^P of the current P: Bbase + P*npair
+  const double* Bp;
+  int64_t npair, P, P_last;
+  unsigned last;        // nao - 1
+  int m0, t, nks, ks;   // k slabs per P, current k slab
+  unsigned rowoffB[EA], rowokB, mA, mAc, mAoff;
+  double va[EA];
+  unsigned amask;
+  bool below;
+  unsigned k0;
+
+  // slabs run over P in [P0, P1) (outer) and the k chunks of nao (inner)
+  __device__ __forceinline__ void init(const double* B, int64_t npair_, int64_t P0, int64_t P1, int nao, int m0_,
+                                       int t_) {
+    Bbase = B;
+    npair = npair_;
+    P = P0;
+    P_last = P1 - 1;
+    last = (unsigned)nao - 1u;
+    m0 = m0_;
+    t = t_;
+    nks = (nao + C::BK - 1) / C::BK;
+    ks = 0;
+    rowokB = 0;
+    // below-diagonal mapping: element q is row m0 + t/16 + q*NT/16, column k0 + t%16
+#pragma unroll
+    for (int q = 0; q < EA; ++q) {
+      const unsigned m = (unsigned)(m0 + (t + C::NT * q) / C::BK);
+      rowokB |= (m <= last ? 1u : 0u) << q;
+      const unsigned mc = m <= last ? m : last;
+      rowoffB[q] = mc * (mc + 1u) / 2u + (unsigned)(t % C::BK);
+    }
+    // other mapping: element q is row m0 + t%BM, column k0 + t/BM + q*NT/BM
+    mA = (unsigned)(m0 + t % C::BM);
+    mAc = mA <= last ? mA : last;
+    mAoff = mAc * (mAc + 1u) / 2u;
+  }
+  __device__ __forceinline__ void begin() {
+    Bp = Bbase + P * npair;
+    k0 = (unsigned)ks * C::BK;
+    below = (int)k0 + C::BK - 1 <= m0;
+    amask = below ? rowokB : 0u;
+    c.begin(*Cm);
+  }
+  template <int q>
+  __device__ __forceinline__ void load() {
+    if constexpr (q < EA) {
+      const unsigned k = k0 + (unsigned)((t + C::NT * q) / C::BM);
+      const unsigned kc = k <= last ? k : last;
+      const unsigned io = mAc >= kc ? mAoff + kc : kc * (kc + 1u) / 2u + mAc;
+      const unsigned idx = below ? rowoffB[q] + k0 : io;
+      if (!below) amask |= ((mA <= last && k <= last) ? 1u : 0u) << q;
+      va[q] = Bp[idx];
+    } else {
+      c.template load<q - EA>(*Cm, t);
+    }
+  }
+  __device__ __forceinline__ void finish() {
+    const bool at_end = P == P_last && ks == nks - 1;
+    int nk = ks + 1;
+    int64_t nP = P;
+    if (nk == nks) {
+      nk = 0;
+      ++nP;
+    }
+    ks = at_end ? ks : nk;
+    P = at_end ? P : nP;
+    c.finish(*Cm);
+  }
+  template <int q>
+  __device__ __forceinline__ void store(double* As, double* Bs) const {
+    if constexpr (q < EA) {
+      const int e = t + C::NT * q;
+      const int slot = below ? (e / C::BK) * C::LD + e % C::BK : (e % C::BM) * C::LD + e / C::BM;
+      As[slot] = ((amask >> q) & 1u) ? va[q] : 0.0;
+    } else {
+      c.template store<q - EA>(Bs, t);
+    }
+  }
+};
+
 template <class C>
 __global__ void __launch_bounds__(C::NT) half_kernel(const double* __restrict__ B, int64_t naux, int nao,
-                                                     int64_t npair, OpMap Cm, double* __restrict__ X,
-                                                     int64_t ldx, int64_t tilesM, int64_t tilesN) {
+                                                     int64_t npair, OpMap Cm, OutMap out, int64_t tilesM,
+                                                     int64_t tilesN) {
   __shared__ double smem[2 * C::STAGE];
-  constexpr int EA = C::BM * C::BK / C::NT;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave % C::WM, wn = wave / C::WM;
   const int64_t ntile = tilesM * tilesN;
   const int64_t item = xcd_remap(blockIdx.x, ntile * naux);
   const int64_t P = item / ntile, tile = item % ntile;
   const int m0 = (int)((tile % tilesM) * C::BM), n0 = (int)((tile / tilesM) * C::BN);
-  const double* __restrict__ Bp = B + P * npair;
+  const int nslab = (nao + C::BK - 1) / C::BK;
 
-  Loader<C, C::BN, false> lb;
-  lb.init(Cm, n0, 0, 0, t);
-  static_assert(EA <= 32, "validity mask holds 32 elements");
-  static_assert(C::NT % C::BK == 0 && C::NT % C::BM == 0, "per-thread row / column of the A loads");
-  // below-diagonal mapping: element q is row m0 + t/16 + q*NT/16, column k0 + t%16
-  // other mapping:          element q is row m0 + t%BM,        column k0 + t/BM + q*NT/BM
-  const unsigned last = (unsigned)nao - 1u;
-  unsigned rowoffB[EA], rowokB = 0;
-#pragma unroll
-  for (int q = 0; q < EA; ++q) {
-    const unsigned m = (unsigned)(m0 + (t + C::NT * q) / C::BK);
-    rowokB |= (m <= last ? 1u : 0u) << q;
-    const unsigned mc = m <= last ? m : last;
-    rowoffB[q] = mc * (mc + 1u) / 2u + (unsigned)(t % C::BK);
-  }
-  const unsigned mA = (unsigned)(m0 + t % C::BM);
-  const unsigned mAc = mA <= last ? mA : last;
-  const unsigned mAoff = mAc * (mAc + 1u) / 2u;
-  double va[EA];
-  unsigned amask = 0;
-  bool below = false;
-
+  HalfSrc<C> src;
+  src.Cm = &Cm;
+  src.c.init(Cm, n0, 0, 0, nslab, t);
+  src.init(B, npair, P, P + 1, nao, m0, t);
   d4 acc[C::TM][C::TN];
   zero_acc<C>(acc);
-  const int nslab = (nao + C::BK - 1) / C::BK;
-  pipeline<C>(
-      smem, nslab, acc, wm, wn, lane,
-      [&](int64_t s) {
-        const unsigned k0 = (unsigned)s * C::BK;
-        below = (int)k0 + C::BK - 1 <= m0;
-        if (below) {
-          amask = rowokB;
-#pragma unroll
-          for (int q = 0; q < EA; ++q) va[q] = Bp[rowoffB[q] + k0];
-        } else {
-          amask = 0;
-#pragma unroll
-          for (int q = 0; q < EA; ++q) {
-            const unsigned k = k0 + (unsigned)((t + C::NT * q) / C::BM);
-            amask |= (mA <= last && k <= last ? 1u : 0u) << q;
-            const unsigned kc = k <= last ? k : last;
-            const unsigned idx = mAc >= kc ? mAoff + kc : kc * (kc + 1u) / 2u + mAc;
-            va[q] = Bp[idx];
-          }
-        }
-        lb.load(Cm, t);
-      },
-      [&](int st) {
-        double* As = smem + st * C::STAGE;
-#pragma unroll
-        for (int q = 0; q < EA; ++q) {
-          const int e = t + C::NT * q;
-          const int slot = below ? (e / C::BK) * C::LD + e % C::BK : (e % C::BM) * C::LD + e / C::BM;
-          As[slot] = ((amask >> q) & 1u) ? va[q] : 0.0;
-        }
-        lb.store(smem + st * C::STAGE + C::LDS_A, t);
-      });
-  OutMap o = out_plain(X + P * (int64_t)nao * ldx, nao, Cm.rows, ldx);
-  store_tile<C>(o, 0, m0, n0, acc, wm, wn, lane);
+  mainloop<C>(src, smem, nslab, acc, wm, wn, lane);
+  store_tile<C, false>(out, P, m0, n0, acc, wm, wn, lane);
+}
+
+// part[split] (m, n) = sum_{P in split} sum_k b^P_{mk} Y(n, (P, k)): the packed half-transform
+// product with the right operand changing with P and the P sum split over grid y.
+template <class C>
+__global__ void __launch_bounds__(C::NT) half_reduce_kernel(const double* __restrict__ B, int64_t naux, int nao,
+                                                            int64_t npair, OpMap Y, int64_t N, int64_t tilesM,
+                                                            int64_t tilesN, double* part) {
+  __shared__ double smem[2 * C::STAGE];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = wave % C::WM, wn = wave / C::WM;
+  const int64_t ntile = tilesM * tilesN;
+  const int nsplit = gridDim.y, split = blockIdx.y;
+  const int64_t tile = xcd_remap(blockIdx.x, ntile);
+  const int m0 = (int)((tile % tilesM) * C::BM), n0 = (int)((tile / tilesM) * C::BN);
+  const int64_t P0 = naux * split / nsplit, P1 = naux * (split + 1) / nsplit;
+  const int nks = (nao + C::BK - 1) / C::BK;
+  d4 acc[C::TM][C::TN];
+  zero_acc<C>(acc);
+  if (P1 > P0) {
+    HalfSrc<C> src;
+    src.Cm = &Y;
+    src.c.init(Y, n0, 0, P0 * nks, P1 * nks, t);
+    src.init(B, npair, P0, P1, nao, m0, t);
+    mainloop<C>(src, smem, (P1 - P0) * nks, acc, wm, wn, lane);
+  }
+  const OutMap po = out_plain(part + (int64_t)split * nao * N, nao, N, N);
+  store_tile<C, false>(po, 0, m0, n0, acc, wm, wn, lane);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -428,6 +646,61 @@ __global__ void __launch_bounds__(256) coulomb_kernel(const double* __restrict__
   }
 }
 
+// g[pair(i,j)] = G[i][j] + G[j][i] for i > j, G[i][i] on the diagonal
+__global__ void __launch_bounds__(256) pair_weights_kernel(const double* __restrict__ G, int64_t nao,
+                                                           double* __restrict__ g) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t npair = nao * (nao + 1) / 2;
+  if (p >= npair) return;
+  int64_t i = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+  while (i * (i + 1) / 2 > p) --i;
+  while ((i + 1) * (i + 2) / 2 <= p) ++i;
+  const int64_t j = p - i * (i + 1) / 2;
+  g[p] = i == j ? G[i * nao + i] : G[i * nao + j] + G[j * nao + i];
+}
+
+// u[P] = sum_pair B[P][pair] g[pair]: eight rows of B per workgroup share each read of g; a
+// fixed-order reduction keeps it deterministic.
+constexpr int kJvRows = 8;
+__global__ void __launch_bounds__(256) jvec_packed_kernel(const double* __restrict__ B, int64_t naux, int64_t npair,
+                                                          const double* __restrict__ g, double* __restrict__ u) {
+  __shared__ double red[kJvRows][4];
+  const int64_t P0 = (int64_t)blockIdx.x * kJvRows;
+  double s[kJvRows];
+#pragma unroll
+  for (int r = 0; r < kJvRows; ++r) s[r] = 0.0;
+  for (int64_t p = threadIdx.x; p < npair; p += 256) {
+    const double gp = g[p];
+#pragma unroll
+    for (int r = 0; r < kJvRows; ++r)
+      if (P0 + r < naux) s[r] = fma(B[(P0 + r) * npair + p], gp, s[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < kJvRows; ++r) {
+    double x = s[r];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    if ((threadIdx.x & 63) == 0) red[r][threadIdx.x >> 6] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < kJvRows && P0 + threadIdx.x < naux) {
+    const int r = threadIdx.x;
+    u[P0 + r] = (red[r][0] + red[r][1]) + (red[r][2] + red[r][3]);
+  }
+}
+
+// out[z] = in[z] + in[z]^T (in place allowed: each pair (i, j), i <= j, is handled by one thread)
+__global__ void __launch_bounds__(256) symmetrize_kernel(const double* in, int64_t n, int64_t nz, double* out) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t nn = n * n;
+  if (idx >= nn * nz) return;
+  const int64_t z = idx / nn, rem = idx % nn, i = rem / n, j = rem % n;
+  if (i > j) return;
+  const double* a = in + z * nn;
+  const double s = a[i * n + j] + a[j * n + i];
+  out[z * nn + i * n + j] = s;
+  out[z * nn + j * n + i] = s;
+}
+
 __global__ void __launch_bounds__(256) fill_zero_kernel(double* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) p[i] = 0.0;
@@ -438,14 +711,23 @@ __global__ void __launch_bounds__(256) fill_zero_kernel(double* p, int64_t n) {
 
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+bool offsets_fit(const OpMap& o) {
+  if (o.rows <= 0 || o.kc_n <= 0) return true;
+  const int64_t last = o.rows - 1;
+  const int64_t rh = o.s_rh ? last / o.rl : 0, rlo = o.s_rh ? o.rl - 1 : last;
+  const int64_t kmax = o.kc_n - 1 + 15;   // a slab may address up to 15 entries past the end before clamping
+  const int64_t top = rh * o.s_rh + rlo * o.s_rlo + kmax * o.s_kc;
+  return o.rows < (1LL << 31) && o.rl < (1LL << 31) && top < (1LL << 32);
+}
+
 template <class Cg>
-static hipError_t half_launch(const double* B, int64_t naux, int64_t nao, const OpMap& cm, double* X, int64_t ldx,
+static hipError_t half_launch(const double* B, int64_t naux, int64_t nao, const OpMap& cm, const OutMap& out,
                               hipStream_t s) {
   const int64_t tm = cdiv(nao, Cg::BM), tn = cdiv(cm.rows, Cg::BN);
   const int64_t nblk = tm * tn * naux;
   if (nblk == 0) return hipSuccess;
-  if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
-  half_kernel<Cg><<<dim3((unsigned)nblk), dim3(Cg::NT), 0, s>>>(B, naux, (int)nao, nao * (nao + 1) / 2, cm, X, ldx,
+  if (nblk > 0x7fffffffLL || !offsets_fit(cm) || out.alpha != 1.0 || out.accumulate) return hipErrorInvalidValue;
+  half_kernel<Cg><<<dim3((unsigned)nblk), dim3(Cg::NT), 0, s>>>(B, naux, (int)nao, nao * (nao + 1) / 2, cm, out,
                                                                  tm, tn);
   return hipGetLastError();
 }
@@ -466,34 +748,118 @@ int half_tile_n(int64_t ncol) {
 }
 
 hipError_t launch_half_transform(const double* B, int64_t naux, int64_t nao, const double* C, int64_t ldc,
-                                 int64_t ncol, double* X, int64_t ldx, hipStream_t s) {
+                                 int64_t ncol, const OutMap& out, hipStream_t s) {
   // B operand: element (n = column of C, k = AO index) at C + k*ldc + n
-  const OpMap cm{C, ncol, ncol > 0 ? ncol : 1, 0, 1, 1, nao, 0, ldc, 0, nullptr, 0};
+  const OpMap cm = op_map(C, ncol, 1, nao, ldc);
   switch (half_tile_n(ncol)) {
-    case 176: return half_launch<CfgH176>(B, naux, nao, cm, X, ldx, s);
-    case 96: return half_launch<CfgH96>(B, naux, nao, cm, X, ldx, s);
-    default: return half_launch<CfgH48>(B, naux, nao, cm, X, ldx, s);
+    case 176: return half_launch<CfgH176>(B, naux, nao, cm, out, s);
+    case 96: return half_launch<CfgH96>(B, naux, nao, cm, out, s);
+    default: return half_launch<CfgH48>(B, naux, nao, cm, out, s);
   }
 }
 
-hipError_t launch_gemm(const OpMap& A, const OpMap& Bm, const OutMap& O, int64_t nz, hipStream_t s) {
+static hipError_t gemm_launch(const OpMap& A, const OpMap& Bm, const OutMap& O, int64_t nz, int nsplit,
+                              double* part, hipStream_t s) {
   typedef CfgSq Cg;
   const int64_t tm = cdiv(O.M, Cg::BM), tn = cdiv(O.N, Cg::BN);
   if (tm * tn == 0 || nz == 0) return hipSuccess;
-  if (tm * tn > 0x7fffffffLL || nz > 65535) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)(tm * tn), 1, (unsigned)nz);
+  if (tm * tn > 0x7fffffffLL || nz > 65535 || nsplit < 1 || nsplit > 65535 || !offsets_fit(A) || !offsets_fit(Bm))
+    return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(tm * tn), (unsigned)nsplit, (unsigned)nz);
   const bool ak = A.s_kc == 1, bk = Bm.s_kc == 1;
-  if (ak && bk) gemm_kernel<Cg, true, true><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn);
-  else if (ak) gemm_kernel<Cg, true, false><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn);
-  else if (bk) gemm_kernel<Cg, false, true><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn);
-  else gemm_kernel<Cg, false, false><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn);
+  if (!part && (O.alpha != 1.0 || O.accumulate)) {
+    // small products that scale or accumulate: general epilogue, operand layouts as given
+    if (ak && bk) gemm_kernel<Cg, true, true, true><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn, part);
+    else if (ak) gemm_kernel<Cg, true, false, true><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn, part);
+    else if (bk) gemm_kernel<Cg, false, true, true><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn, part);
+    else gemm_kernel<Cg, false, false, true><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn, part);
+    return hipGetLastError();
+  }
+  if (ak && bk) gemm_kernel<Cg, true, true, false><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn, part);
+  else if (ak) gemm_kernel<Cg, true, false, false><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn, part);
+  else if (bk) gemm_kernel<Cg, false, true, false><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn, part);
+  else gemm_kernel<Cg, false, false, false><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn, part);
   return hipGetLastError();
 }
 
-int syrk_tile() { return CfgSq::BM; }
+hipError_t launch_gemm(const OpMap& A, const OpMap& Bm, const OutMap& O, int64_t nz, hipStream_t s) {
+  return gemm_launch(A, Bm, O, nz, 1, nullptr, s);
+}
+
+int64_t gemm_slabs(const OpMap& A) { return A.kb_n * cdiv(A.kc_n, 16); }
+
+int gemm_splits(int64_t M, int64_t N, int64_t nslab) {
+  const int64_t tiles = cdiv(M, CfgSq::BM) * cdiv(N, CfgSq::BN);
+  if (tiles == 0) return 1;
+  int64_t ns = cdiv(1024, tiles);
+  if (ns > nslab / 4) ns = nslab / 4;   // keep at least four slabs per split
+  if (ns < 1) ns = 1;
+  if (ns > 4096) ns = 4096;
+  return (int)ns;
+}
+
+hipError_t launch_gemm_split(const OpMap& A, const OpMap& Bm, const OutMap& O, int nsplit, double* part,
+                             hipStream_t s) {
+  if (nsplit <= 1) return gemm_launch(A, Bm, O, 1, 1, nullptr, s);
+  hipError_t e = gemm_launch(A, Bm, O, 1, nsplit, part, s);
+  if (e != hipSuccess) return e;
+  const int64_t MN = O.M * O.N;
+  if (MN == 0) return hipSuccess;
+  split_reduce_kernel<<<(unsigned)cdiv(MN, 256), 256, 0, s>>>(part, nsplit, O);
+  return hipGetLastError();
+}
+
+int half_reduce_splits(int64_t nao, int64_t N, int64_t naux) {
+  const int64_t tiles = cdiv(nao, CfgH176::BM) * cdiv(N, CfgH176::BN);
+  int64_t ns = cdiv(1024, tiles > 0 ? tiles : 1);
+  if (ns > naux) ns = naux;
+  if (ns < 1) ns = 1;
+  if (ns > 65535) ns = 65535;
+  return (int)ns;
+}
+
+hipError_t launch_half_reduce(const double* B, int64_t naux, int64_t nao, const OpMap& Y, const OutMap& O,
+                              int nsplit, double* part, hipStream_t s) {
+  typedef CfgH176 Cg;
+  const int64_t tm = cdiv(nao, Cg::BM), tn = cdiv(O.N, Cg::BN);
+  if (tm * tn == 0) return hipSuccess;
+  if (nsplit < 1 || nsplit > 65535 || !offsets_fit(Y)) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(tm * tn), (unsigned)nsplit, 1);
+  half_reduce_kernel<Cg><<<grid, Cg::NT, 0, s>>>(B, naux, (int)nao, nao * (nao + 1) / 2, Y, O.N, tm, tn, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  OutMap Oc = O;
+  Oc.M = nao;
+  const int64_t MN = nao * O.N;
+  split_reduce_kernel<<<(unsigned)cdiv(MN, 256), 256, 0, s>>>(part, nsplit, Oc);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_weights(const double* G, int64_t nao, double* g, hipStream_t s) {
+  const int64_t npair = nao * (nao + 1) / 2;
+  if (npair == 0) return hipSuccess;
+  pair_weights_kernel<<<(unsigned)cdiv(npair, 256), 256, 0, s>>>(G, nao, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_jvec_packed(const double* B, int64_t naux, int64_t nao, const double* g, double* u,
+                              hipStream_t s) {
+  if (naux == 0) return hipSuccess;
+  jvec_packed_kernel<<<(unsigned)cdiv(naux, kJvRows), 256, 0, s>>>(B, naux, nao * (nao + 1) / 2, g, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_symmetrize(const double* in, int64_t n, int64_t nz, double* out, hipStream_t s) {
+  const int64_t tot = n * n * nz;
+  if (tot == 0) return hipSuccess;
+  symmetrize_kernel<<<(unsigned)cdiv(tot, 256), 256, 0, s>>>(in, n, nz, out);
+  return hipGetLastError();
+}
+
+int syrk_tile() { return CfgSyrk::BM; }
 
 int syrk_splits(int64_t n, int64_t kb_n, int64_t nz) {
-  const int64_t T = cdiv(n, CfgSq::BM);
+  const int64_t T = cdiv(n, CfgSyrk::BM);
   const int64_t work = T * (T + 1) / 2 * (nz > 0 ? nz : 1);
   int64_t ns = cdiv(1024, work);
   if (ns > kb_n) ns = kb_n;
@@ -503,11 +869,11 @@ int syrk_splits(int64_t n, int64_t kb_n, int64_t nz) {
 
 hipError_t launch_syrk_partial(const OpMap& A, const OpMap& Bw, int64_t n, int64_t nz, int nsplit, double* Kpart,
                                hipStream_t s) {
-  typedef CfgSq Cg;
+  typedef CfgSyrk Cg;
   const int64_t T = cdiv(n, Cg::BM);
   const int64_t npairs = T * (T + 1) / 2;
   if (npairs == 0 || nz == 0) return hipSuccess;
-  if (nz > 65535) return hipErrorInvalidValue;
+  if (nz > 65535 || !offsets_fit(A)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(npairs * nsplit), 1, (unsigned)nz);
   if (Bw.ks) syrk_kernel<Cg, true><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
   else syrk_kernel<Cg, false><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);

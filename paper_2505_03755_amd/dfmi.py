@@ -27,15 +27,20 @@ DF_OP_JK = 2
 DF_OP_ACTIVE_ERI = 3
 DF_OP_PAPA = 4
 DF_OP_STEP = 5
+DF_OP_STEP_BACKWARD = 6
 
 DF_PAPA_FULL = 0x1
+DF_CALLER_X = 0x10
+DF_BWD_GJ = 0x20
+DF_BWD_GK = 0x40
+DF_BWD_GERI = 0x80
 
 KERNEL_KINDS = ["half_transform", "jvec", "coulomb", "k_syrk", "k_reduce", "mo_transform", "papa", "eri",
-                "other"]
+                "other", "adjoint"]
 
 EXPORTED = ["df_create", "df_destroy", "df_last_error", "df_set_stream", "df_set_workspace",
             "df_set_timing", "df_timing_read", "df_workspace_size", "df_half_transform", "df_jk",
-            "df_active_eri", "df_papa", "df_step"]
+            "df_active_eri", "df_papa", "df_step", "df_step_backward"]
 
 
 class DFError(RuntimeError):
@@ -81,7 +86,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         L.df_jk.argtypes = [vp, dp, i64, i64, i64, dp, i64, dp, dp, dp, dp, i32]
         L.df_active_eri.argtypes = [vp, dp, i64, i64, dp, i64, dp, dp, i32]
         L.df_papa.argtypes = [vp, dp, i64, i64, dp, i64, dp, i64, dp, i64, dp, i32]
-        L.df_step.argtypes = [vp, dp, i64, i64, dp, i64, dp, dp, i64, dp, i64, dp, dp, dp, dp, dp, i32]
+        L.df_step.argtypes = [vp, dp, i64, i64, dp, i64, dp, dp, i64, dp, i64, dp, dp, dp, dp, dp, dp, dp, i32]
+        L.df_step_backward.argtypes = [vp, dp, i64, i64, dp, i64, dp, i64, dp, dp, dp, dp, dp, dp, dp, i32]
         for name in EXPORTED:
             if name != "df_last_error":
                 getattr(L, name).restype = ctypes.c_int
@@ -284,16 +290,19 @@ def papa(B, nao: int, Cp, Cact, Cq=None, ctx: Context | None = None):
     return out
 
 
-def step(B, nao: int, Cocc, Cact, Cp, w=None, outputs=None, ctx: Context | None = None):
-    """J, K, v, (uv|wx) and (pu|vw) from one shared half transform (df_step)."""
+def step(B, nao: int, Cocc, Cact, Cp, w=None, outputs=None, keep_x=False, ctx: Context | None = None):
+    """J, K, v, (uv|wx) and (pu|vw) from one shared half transform (df_step).
+
+    With keep_x the half-transformed factors are returned too, as "Xocc" [naux, nao, nocc]
+    and "Xact" [nao, naux, nac] (what df_step_backward reuses)."""
     import torch
     ctx = ctx or context(B.device)
     for n, t in (("B", B), ("Cocc", Cocc), ("w", w), ("Cact", Cact), ("Cp", Cp)):
         _check_tensor(n, t, ctx.device)
     naux = _naux_of(B, nao)
     nocc, nac, np_ = Cocc.shape[1], Cact.shape[1], Cp.shape[1]
+    dev = ctx.device
     if outputs is None:
-        dev = ctx.device
         outputs = {
             "J": torch.empty((nao, nao), dtype=torch.float64, device=dev),
             "K": torch.empty((nao, nao), dtype=torch.float64, device=dev),
@@ -301,9 +310,94 @@ def step(B, nao: int, Cocc, Cact, Cp, w=None, outputs=None, ctx: Context | None 
             "eri": torch.empty((nac,) * 4, dtype=torch.float64, device=dev),
             "papa": torch.empty((np_, nac, nac, nac), dtype=torch.float64, device=dev),
         }
-    ctx.prepare(DF_OP_STEP, naux=naux, nao=nao, ndm=1, nocc=nocc, nac=nac, np=np_)
+    if keep_x:
+        outputs.setdefault("Xocc", torch.empty((naux, nao, nocc), dtype=torch.float64, device=dev))
+        outputs.setdefault("Xact", torch.empty((nao, naux, nac), dtype=torch.float64, device=dev))
     o = outputs
+    for k in ("J", "K", "v", "eri", "papa", "Xocc", "Xact"):
+        _check_tensor(k, o.get(k), dev)
+    caller_x = o.get("Xocc") is not None
+    ctx.prepare(DF_OP_STEP, naux=naux, nao=nao, ndm=1, nocc=nocc, nac=nac, np=np_,
+                flags=DF_CALLER_X if caller_x else 0)
     ctx.check(ctx._lib.df_step(ctx.handle, _ptr(B), naux, nao, _ptr(Cocc), nocc, _ptr(w), _ptr(Cact), nac,
                                _ptr(Cp), np_, _ptr(o.get("J")), _ptr(o.get("K")), _ptr(o.get("v")),
-                               _ptr(o.get("eri")), _ptr(o.get("papa")), 0))
+                               _ptr(o.get("eri")), _ptr(o.get("papa")), _ptr(o.get("Xocc")), _ptr(o.get("Xact")), 0))
     return outputs
+
+
+def step_backward(B, nao: int, Cocc, Cact, gJ=None, gK=None, geri=None, Xocc=None, Xact=None,
+                  ctx: Context | None = None):
+    """Vector-Jacobian product of (J, K, eri) w.r.t. (Cocc, Cact) (df_step_backward)."""
+    import torch
+    ctx = ctx or context(B.device)
+    for n, t in (("B", B), ("Cocc", Cocc), ("Cact", Cact), ("gJ", gJ), ("gK", gK), ("geri", geri),
+                 ("Xocc", Xocc), ("Xact", Xact)):
+        _check_tensor(n, t, ctx.device)
+    naux = _naux_of(B, nao)
+    nocc, nac = Cocc.shape[1], Cact.shape[1]
+    dCocc = torch.empty_like(Cocc)
+    dCact = torch.empty_like(Cact)
+    flags = ((DF_BWD_GJ if gJ is not None else 0) | (DF_BWD_GK if gK is not None else 0)
+             | (DF_BWD_GERI if geri is not None else 0) | (DF_CALLER_X if Xocc is not None else 0))
+    ctx.prepare(DF_OP_STEP_BACKWARD, naux=naux, nao=nao, ndm=1, nocc=nocc, nac=nac, flags=flags)
+    ctx.check(ctx._lib.df_step_backward(ctx.handle, _ptr(B), naux, nao, _ptr(Cocc), nocc, _ptr(Cact), nac,
+                                        _ptr(gJ), _ptr(gK), _ptr(geri), _ptr(Xocc), _ptr(Xact),
+                                        _ptr(dCocc), _ptr(dCact), 0))
+    return dCocc, dCact
+
+
+def _autograd_function():
+    import torch
+
+    class DFStep(torch.autograd.Function):
+        """(J, K, eri) = DFStep.apply(B, nao, Cocc, Cact, keep_x): differentiable in Cocc and Cact.
+
+        The forward keeps the half-transformed factors for the backward when keep_x is set
+        (13.8 GB + 1.8 GB at paper scale); otherwise the backward recomputes them."""
+
+        @staticmethod
+        def forward(fctx, B, nao, Cocc, Cact, keep_x=True):
+            Cocc = Cocc.contiguous()
+            Cact = Cact.contiguous()
+            Cp = Cact[:, :0]   # no (pu|vw) needed here
+            out = step(B, nao, Cocc, Cact, Cp.contiguous(), keep_x=keep_x)
+            fctx.nao = nao
+            fctx.save_for_backward(B, Cocc, Cact)
+            fctx.xs = (out.get("Xocc"), out.get("Xact"))
+            return out["J"], out["K"], out["eri"]
+
+        @staticmethod
+        def backward(fctx, gJ, gK, geri):
+            B, Cocc, Cact = fctx.saved_tensors
+            c = lambda g: None if g is None else g.contiguous()
+            Xo, Xa = fctx.xs
+            dCocc, dCact = step_backward(B, fctx.nao, Cocc, Cact, c(gJ), c(gK), c(geri), Xo, Xa)
+            fctx.xs = None
+            return None, None, dCocc, dCact, None
+
+    return DFStep
+
+
+_DFStep = None
+
+
+def dfstep_apply(B, nao: int, Cocc, Cact, keep_x=True):
+    """(J, K, eri) with autograd support through the library's hand-written adjoint."""
+    global _DFStep
+    if _DFStep is None:
+        _DFStep = _autograd_function()
+    return _DFStep.apply(B, nao, Cocc, Cact, keep_x)
+
+
+def energy(B, nao: int, C0, kappa, nocc: int, nac: int, h, Gamma, keep_x=True):
+    """E(kappa) = tr(D h) + 1/2 tr(D J) - 1/4 tr(D K) + 1/2 sum (uv|wx) Gamma, C = C0 exp(kappa - kappa^T).
+
+    Differentiable in kappa: torch's matrix exponential supplies dC/dkappa, the library's
+    adjoint supplies the contraction part."""
+    import torch
+    C = C0 @ torch.linalg.matrix_exp(kappa - kappa.T)
+    Cocc = C[:, :nocc]
+    Cact = C[:, nocc:nocc + nac]
+    J, K, eri = dfstep_apply(B, nao, Cocc, Cact, keep_x)
+    D = Cocc @ Cocc.T
+    return (D * h).sum() + 0.5 * (D * J).sum() - 0.25 * (D * K).sum() + 0.5 * (eri * Gamma).sum()

@@ -128,11 +128,39 @@ def test_active_eri_and_papa_argument_errors(L, ctx):
 def test_step_argument_errors(L, ctx):
     B, Co, Ca, Cp = fake(1 << 30), fake(2 << 30), fake(3 << 30), fake(4 << 30)
     J, K = fake(5 << 30), fake(6 << 30)
-    assert L.df_step(ctx, B, 10, 7, None, 3, None, Ca, 2, Cp, 7, J, K, None, None, None, 0) == dfmi.DF_ERR_ARG
-    assert L.df_step(ctx, B, 10, 7, Co, 3, None, None, 2, Cp, 7, J, K, None, None, None, 0) == dfmi.DF_ERR_ARG
-    assert L.df_step(ctx, B, 10, 7, Co, 3, None, Ca, 2, Cp, 7, J, K, None, None, None, 8) == dfmi.DF_ERR_UNSUPPORTED
-    assert L.df_step(ctx, B, 10, 7, Co, 3, None, Ca, 2, Cp, 7, J, J, None, None, None, 0) == dfmi.DF_ERR_ARG
-    assert L.df_step(ctx, B, 10, 7, Co, 3, None, Ca, 2, Cp, 7, J, K, None, None, None, 0) == dfmi.DF_ERR_WORKSPACE
+    X = (None, None)
+    assert L.df_step(ctx, B, 10, 7, None, 3, None, Ca, 2, Cp, 7, J, K, None, None, None, *X, 0) == dfmi.DF_ERR_ARG
+    assert L.df_step(ctx, B, 10, 7, Co, 3, None, None, 2, Cp, 7, J, K, None, None, None, *X, 0) == dfmi.DF_ERR_ARG
+    assert L.df_step(ctx, B, 10, 7, Co, 3, None, Ca, 2, Cp, 7, J, K, None, None, None, *X, 8) == dfmi.DF_ERR_UNSUPPORTED
+    assert L.df_step(ctx, B, 10, 7, Co, 3, None, Ca, 2, Cp, 7, J, J, None, None, None, *X, 0) == dfmi.DF_ERR_ARG
+    assert L.df_step(ctx, B, 10, 7, Co, 3, None, Ca, 2, Cp, 7, J, K, None, None, None, *X, 0) == dfmi.DF_ERR_WORKSPACE
+    # Xocc and Xact come together
+    assert L.df_step(ctx, B, 10, 7, Co, 3, None, Ca, 2, Cp, 7, J, K, None, None, None, fake(7 << 30), None, 0) == dfmi.DF_ERR_ARG
+    # ... except that an empty one may be NULL: validation passes and the missing workspace is reported
+    assert L.df_step(ctx, B, 10, 7, Co, 3, None, Ca, 0, Cp, 7, J, K, None, None, None, fake(7 << 30), None, 0) == dfmi.DF_ERR_WORKSPACE
+    assert L.df_step(ctx, B, 10, 7, Co, 0, None, Ca, 2, Cp, 7, J, K, None, None, None, None, fake(7 << 30), 0) == dfmi.DF_ERR_WORKSPACE
+    # with caller-owned X the workspace shrinks by the two half transforms
+    a = dfmi.workspace_size(dfmi.DF_OP_STEP, naux=10, nao=7, nocc=3, nac=2, np=7)
+    b = dfmi.workspace_size(dfmi.DF_OP_STEP, naux=10, nao=7, nocc=3, nac=2, np=7, flags=dfmi.DF_CALLER_X)
+    assert a - b >= 10 * 7 * 5 * 8
+
+
+def test_step_backward_argument_errors(L, ctx):
+    B, Co, Ca = fake(1 << 30), fake(2 << 30), fake(3 << 30)
+    gJ, gK, dCo, dCa = fake(4 << 30), fake(5 << 30), fake(6 << 30), fake(7 << 30)
+    f = L.df_step_backward
+    assert f(ctx, B, 10, 7, None, 3, Ca, 2, gJ, gK, None, None, None, dCo, dCa, 0) == dfmi.DF_ERR_ARG
+    assert f(ctx, B, 10, 7, Co, 3, Ca, 2, gJ, gK, None, None, None, None, dCa, 0) == dfmi.DF_ERR_ARG
+    assert f(ctx, B, 10, 7, Co, 3, Ca, 2, gJ, gK, None, None, None, dCo, dCa, 1) == dfmi.DF_ERR_UNSUPPORTED
+    assert f(ctx, B, 10, 7, Co, -3, Ca, 2, gJ, gK, None, None, None, dCo, dCa, 0) == dfmi.DF_ERR_SHAPE
+    assert f(ctx, B, 10, 7, Co, 3, Ca, 2, gJ, gK, None, fake(8 << 30), None, dCo, dCa, 0) == dfmi.DF_ERR_ARG
+    assert f(ctx, B, 10, 7, Co, 3, Ca, 0, gJ, gK, None, fake(8 << 30), None, dCo, None, 0) == dfmi.DF_ERR_WORKSPACE
+    assert f(ctx, B, 10, 7, Co, 3, Ca, 2, gJ, gK, None, None, None, dCo, dCo, 0) == dfmi.DF_ERR_ARG   # outputs alias
+    assert f(ctx, B, 10, 7, Co, 3, Ca, 2, gJ, gK, None, None, None, dCo, dCa, 0) == dfmi.DF_ERR_WORKSPACE
+    w_all = dfmi.workspace_size(dfmi.DF_OP_STEP_BACKWARD, naux=10, nao=7, nocc=3, nac=2,
+                                flags=dfmi.DF_BWD_GJ | dfmi.DF_BWD_GK | dfmi.DF_BWD_GERI)
+    w_j = dfmi.workspace_size(dfmi.DF_OP_STEP_BACKWARD, naux=10, nao=7, nocc=3, nac=2, flags=dfmi.DF_BWD_GJ)
+    assert w_all > w_j > 0
 
 
 def test_valid_call_without_device_fails_loudly(L, ctx):
