@@ -54,6 +54,36 @@ def step_flops(naux, nao, nocc, nac, nmo, adjoint=True):
     return f
 
 
+def kernel_source_digest() -> str:
+    """sha256 of the kernel sources: HBM byte counts are valid only for the kernels they came from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_2505_03755_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_per_launch(kernel: str):
+    """Scaled HBM bytes (fetch + write) per launch of `kernel`, from the committed rocprofv3 counter
+    summary, or None when there is none or it was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_paper_hbm_bytes.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel sources sha256") != kernel_source_digest():
+        return None
+    try:
+        return float(fields["traffic bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def kernel_table(kt, naux, nao, nocc, nac, nmo, steps):
     """Per-kernel time per step and its roofline figure."""
     npair = nao * (nao + 1) // 2
@@ -91,9 +121,11 @@ def kernel_table(kt, naux, nao, nocc, nac, nmo, steps):
     return out
 
 
-def cpu_baseline(wl, rows, seed):
-    """The FP64 oracle on `rows` auxiliary rows of the same workload (host cores)."""
+def cpu_baseline(wl, rows, seed, adjoint=True):
+    """The FP64 oracle on `rows` auxiliary rows of the same workload (host cores): the forward
+    outputs and, with `adjoint`, the vector-Jacobian product for the model-energy cotangents."""
     import numpy as np
+    from oracle import df_grad as G
     from oracle import df_oracle as O
     from paper_2505_03755_amd import synth
     try:
@@ -104,16 +136,22 @@ def cpu_baseline(wl, rows, seed):
     B = synth.cholesky_vectors(rows, wl.nao, wl.L, seed=seed)
     C = synth.orbitals(wl.nao, seed=seed)
     Cocc, Cact = C[:, :wl.nocc], C[:, wl.nocc:wl.nocc + wl.nac]
+    D = Cocc @ Cocc.T
+    Gam = synth.two_body_density(wl.nac, seed=seed)
     t0 = time.perf_counter()
     J, K, v = O.jk(B, wl.nao, Cocc)
     eri, _ = O.active_eri(B, wl.nao, Cact)
     pa = O.papa(B, wl.nao, C, Cact)
+    outs = [J, K, eri, pa]
+    if adjoint:
+        outs += list(G.step_vjp(B, wl.nao, Cocc, Cact, 0.5 * D, -0.25 * D, 0.5 * Gam))
     dt = time.perf_counter() - t0
-    fl = sum(step_flops(rows, wl.nao, wl.nocc, wl.nac, wl.nmo, adjoint=False).values())
-    assert np.isfinite(J).all() and np.isfinite(K).all() and np.isfinite(pa).all() and np.isfinite(eri).all()
+    fl = sum(step_flops(rows, wl.nao, wl.nocc, wl.nac, wl.nmo, adjoint=adjoint).values())
+    assert all(np.isfinite(o).all() for o in outs)
+    what = "forward J, K, v, (uv|wx), (pu|vw)" + (" + adjoint" if adjoint else "")
     return {"value": fl / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{rows} of {wl.naux} auxiliary rows at N_ao={wl.nao}, N_occ={wl.nocc}, N_ac={wl.nac} "
-                      f"(forward J, K, v, (uv|wx), (pu|vw); rate in algorithmic FP64 FLOP/s); {dt:.2f} s"}
+                      f"({what}; rate in algorithmic FP64 FLOP/s of that sample); {dt:.2f} s"}
 
 
 def main():
@@ -122,7 +160,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="paper", choices=["tiny", "medium", "paper"])
-    ap.add_argument("--cpu-rows", type=int, default=240, help="auxiliary rows in the CPU oracle sample")
+    ap.add_argument("--cpu-rows", type=int, default=24, help="auxiliary rows in the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forward-only", action="store_true", help="time df_step alone (no adjoint)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
@@ -188,12 +226,17 @@ def main():
 
     ctx.set_timing(True)
     ctx.timing_read()
+    stream = torch.cuda.current_stream(dev)    # the stream the library launches on
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    ev[0].record(stream)
+    for i in range(args.steps):
         run()
+        ev[i + 1].record(stream)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    step_ms = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps))
     kt = ctx.timing_read()
     ctx.set_timing(False)
     log(f"[bench] {args.steps} timed steps in {dt:.3f} s")
@@ -211,7 +254,7 @@ def main():
         "peak": PEAK_FP64_MFMA_TFLOPS,
         "unit": "TFLOP/s",
         "frac": half["tflops"] / PEAK_FP64_MFMA_TFLOPS,
-        "traffic": None,
+        "traffic": traffic_per_launch("half_transform"),
         "algorithmic_per_launch": f"2*N_aux*N_ao^2*(N_occ+N_ac) = {fl['half_transform']:.4e} FLOP",
         "avg_launch_ms": kt["half_transform"][0] / kt["half_transform"][1],
     }
@@ -223,6 +266,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "step_ms_median": step_ms[len(step_ms) // 2],
+        "step_ms_min": step_ms[0],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -245,7 +290,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log(f"[bench] timing the CPU oracle on {args.cpu_rows} auxiliary rows")
-        res["cpu_baseline"] = cpu_baseline(wl, args.cpu_rows, wl.seed)
+        res["cpu_baseline"] = cpu_baseline(wl, args.cpu_rows, wl.seed, adjoint=not args.forward_only)
     print(json.dumps(res), flush=True)
 
 

@@ -39,11 +39,13 @@ struct Cfg {
   static_assert((BM * BK) % NT == 0 && (BN * BK) % NT == 0, "tile must split evenly over threads");
 };
 
-// generic products: 128 x 128 tiles, 2 x 2 waves of 64 x 64; the K SYRK the same, interleaved
-typedef Cfg<2, 2, 4, 4> CfgSq;
+// Every MFMA kernel is sized for two waves per SIMD (at most 256 registers per lane, two
+// workgroups' LDS per CU), so one wave's barrier and LDS latency hide behind the other's MFMAs.
+// generic products and the K SYRK: 128 x 128 tiles, 2 x 2 waves of 64 x 64, interleaved
+typedef Cfg<2, 2, 4, 4, true> CfgSq;
 typedef Cfg<2, 2, 4, 4, true> CfgSyrk;
-// half transform: 128 rows x {176, 96, 48} columns, 4 waves stacked along the rows
-typedef Cfg<4, 1, 2, 11> CfgH176;
+// half transform: {64, 128, 128} rows x {176, 96, 48} columns, 4 waves stacked along the rows
+typedef Cfg<4, 1, 1, 11, true> CfgH176;
 typedef Cfg<4, 1, 2, 6> CfgH96;
 typedef Cfg<4, 1, 2, 3> CfgH48;
 
@@ -336,7 +338,7 @@ struct PairSrc {
 // y = nsplit > 1 each workgroup set covers a contiguous range of k slabs and writes its partial
 // sums to part[split][M][N] (nz must be 1 then).
 template <class C, bool AK, bool BK, bool GEN>
-__global__ void __launch_bounds__(C::NT) gemm_kernel(OpMap A, OpMap B, OutMap O, int64_t tilesM, int64_t tilesN,
+__global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) gemm_kernel(OpMap A, OpMap B, OutMap O, int64_t tilesM, int64_t tilesN,
                                                      double* part) {
   __shared__ double smem[2 * C::STAGE];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -533,7 +535,7 @@ struct HalfSrc {
 };
 
 template <class C>
-__global__ void __launch_bounds__(C::NT) half_kernel(const double* __restrict__ B, int64_t naux, int nao,
+__global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) half_kernel(const double* __restrict__ B, int64_t naux, int nao,
                                                      int64_t npair, OpMap Cm, OutMap out, int64_t tilesM,
                                                      int64_t tilesN) {
   __shared__ double smem[2 * C::STAGE];
@@ -558,7 +560,7 @@ __global__ void __launch_bounds__(C::NT) half_kernel(const double* __restrict__ 
 // part[split] (m, n) = sum_{P in split} sum_k b^P_{mk} Y(n, (P, k)): the packed half-transform
 // product with the right operand changing with P and the P sum split over grid y.
 template <class C>
-__global__ void __launch_bounds__(C::NT) half_reduce_kernel(const double* __restrict__ B, int64_t naux, int nao,
+__global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) half_reduce_kernel(const double* __restrict__ B, int64_t naux, int nao,
                                                             int64_t npair, OpMap Y, int64_t N, int64_t tilesM,
                                                             int64_t tilesN, double* part) {
   __shared__ double smem[2 * C::STAGE];
