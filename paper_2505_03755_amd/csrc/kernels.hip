@@ -543,8 +543,9 @@ __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2)))
   const int wm = wave % C::WM, wn = wave / C::WM;
   const int64_t ntile = tilesM * tilesN;
   const int64_t item = xcd_remap(blockIdx.x, ntile * naux);
+  // row band major: the column tiles of one band of b^P run side by side and share its reads in L2
   const int64_t P = item / ntile, tile = item % ntile;
-  const int m0 = (int)((tile % tilesM) * C::BM), n0 = (int)((tile / tilesM) * C::BN);
+  const int m0 = (int)((tile / tilesN) * C::BM), n0 = (int)((tile % tilesN) * C::BN);
   const int nslab = (nao + C::BK - 1) / C::BK;
 
   HalfSrc<C> src;
@@ -562,14 +563,17 @@ __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2)))
 template <class C>
 __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) half_reduce_kernel(const double* __restrict__ B, int64_t naux, int nao,
                                                             int64_t npair, OpMap Y, int64_t N, int64_t tilesM,
-                                                            int64_t tilesN, double* part) {
+                                                            int64_t tilesN, int nsplit, double* part) {
   __shared__ double smem[2 * C::STAGE];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave % C::WM, wn = wave / C::WM;
   const int64_t ntile = tilesM * tilesN;
-  const int nsplit = gridDim.y, split = blockIdx.y;
-  const int64_t tile = xcd_remap(blockIdx.x, ntile);
-  const int m0 = (int)((tile % tilesM) * C::BM), n0 = (int)((tile / tilesM) * C::BN);
+  // split major, then row band: the tiles of one P range sit on one XCD, and the column tiles
+  // of a band side by side
+  const int64_t item = xcd_remap(blockIdx.x, ntile * nsplit);
+  const int split = (int)(item / ntile);
+  const int64_t tile = item % ntile;
+  const int m0 = (int)((tile / tilesN) * C::BM), n0 = (int)((tile % tilesN) * C::BN);
   const int64_t P0 = naux * split / nsplit, P1 = naux * (split + 1) / nsplit;
   const int nks = (nao + C::BK - 1) / C::BK;
   d4 acc[C::TM][C::TN];
@@ -790,14 +794,36 @@ hipError_t launch_gemm(const OpMap& A, const OpMap& Bm, const OutMap& O, int64_t
 
 int64_t gemm_slabs(const OpMap& A) { return A.kb_n * cdiv(A.kc_n, 16); }
 
+// Workgroups resident at once for the MFMA kernels on MI355X: 256 CUs x 2 (each kernel is sized
+// for two workgroups per CU).  A launch of W equal workgroups takes ceil(W / kResident) rounds.
+static constexpr int64_t kResident = 512;
+
+// Split count s in [1, max_split] for a launch of tiles * s equal workgroups: the one that fills
+// its last round best, among counts that fill at least one round (when any does), the smaller
+// on ties (less partial-sum traffic).
+static int balanced_splits(int64_t tiles, int64_t max_split) {
+  if (tiles <= 0) return 1;
+  if (max_split < 1) max_split = 1;
+  if (max_split > 4096) max_split = 4096;
+  const int64_t s_fill = cdiv(kResident, tiles);
+  int64_t lo = s_fill <= max_split ? s_fill : max_split, hi = 4 * lo < max_split ? 4 * lo : max_split;
+  if (hi < lo) hi = lo;
+  int best = (int)lo;
+  double best_eff = -1.0;
+  for (int64_t sp = lo; sp <= hi; ++sp) {
+    const int64_t w = tiles * sp;
+    const double eff = (double)w / (double)(cdiv(w, kResident) * kResident);
+    if (eff > best_eff + 1e-9) {
+      best_eff = eff;
+      best = (int)sp;
+    }
+  }
+  return best;
+}
+
 int gemm_splits(int64_t M, int64_t N, int64_t nslab) {
-  const int64_t tiles = cdiv(M, CfgSq::BM) * cdiv(N, CfgSq::BN);
-  if (tiles == 0) return 1;
-  int64_t ns = cdiv(1024, tiles);
-  if (ns > nslab / 4) ns = nslab / 4;   // keep at least four slabs per split
-  if (ns < 1) ns = 1;
-  if (ns > 4096) ns = 4096;
-  return (int)ns;
+  // at least four slabs per split
+  return balanced_splits(cdiv(M, CfgSq::BM) * cdiv(N, CfgSq::BN), nslab / 4);
 }
 
 hipError_t launch_gemm_split(const OpMap& A, const OpMap& Bm, const OutMap& O, int nsplit, double* part,
@@ -812,12 +838,7 @@ hipError_t launch_gemm_split(const OpMap& A, const OpMap& Bm, const OutMap& O, i
 }
 
 int half_reduce_splits(int64_t nao, int64_t N, int64_t naux) {
-  const int64_t tiles = cdiv(nao, CfgH176::BM) * cdiv(N, CfgH176::BN);
-  int64_t ns = cdiv(1024, tiles > 0 ? tiles : 1);
-  if (ns > naux) ns = naux;
-  if (ns < 1) ns = 1;
-  if (ns > 65535) ns = 65535;
-  return (int)ns;
+  return balanced_splits(cdiv(nao, CfgH176::BM) * cdiv(N, CfgH176::BN), naux);
 }
 
 hipError_t launch_half_reduce(const double* B, int64_t naux, int64_t nao, const OpMap& Y, const OutMap& O,
@@ -826,8 +847,10 @@ hipError_t launch_half_reduce(const double* B, int64_t naux, int64_t nao, const 
   const int64_t tm = cdiv(nao, Cg::BM), tn = cdiv(O.N, Cg::BN);
   if (tm * tn == 0) return hipSuccess;
   if (nsplit < 1 || nsplit > 65535 || !offsets_fit(Y)) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)(tm * tn), (unsigned)nsplit, 1);
-  half_reduce_kernel<Cg><<<grid, Cg::NT, 0, s>>>(B, naux, (int)nao, nao * (nao + 1) / 2, Y, O.N, tm, tn, part);
+  const int64_t nblk = tm * tn * nsplit;
+  if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+  half_reduce_kernel<Cg><<<dim3((unsigned)nblk), Cg::NT, 0, s>>>(B, naux, (int)nao, nao * (nao + 1) / 2, Y, O.N, tm,
+                                                                tn, nsplit, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   OutMap Oc = O;
@@ -862,11 +885,7 @@ int syrk_tile() { return CfgSyrk::BM; }
 
 int syrk_splits(int64_t n, int64_t kb_n, int64_t nz) {
   const int64_t T = cdiv(n, CfgSyrk::BM);
-  const int64_t work = T * (T + 1) / 2 * (nz > 0 ? nz : 1);
-  int64_t ns = cdiv(1024, work);
-  if (ns > kb_n) ns = kb_n;
-  if (ns < 1) ns = 1;
-  return (int)ns;
+  return balanced_splits(T * (T + 1) / 2 * (nz > 0 ? nz : 1), kb_n);
 }
 
 hipError_t launch_syrk_partial(const OpMap& A, const OpMap& Bw, int64_t n, int64_t nz, int nsplit, double* Kpart,
