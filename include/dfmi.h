@@ -140,7 +140,7 @@ df_status df_workspace_size(df_op op, const df_dims* dims, size_t* bytes);
  *   C  [nao][ncol]        coefficients (input), ncol >= 1
  *   X  [naux][nao][ncol]  output; the untransformed AO index comes first, as in b^P_{e2 p1}
  *   C2 [nao][n2], Y [naux][n2][ncol]  both NULL (n2 = 0) or both given
- * Workspace: none.
+ * Workspace: df_workspace_size(DF_OP_HALF_TRANSFORM, {naux, nao, ncol}) (a zero-padded copy of C).
  */
 df_status df_half_transform(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
                             const double* C, int64_t ncol, double* X,

@@ -83,21 +83,25 @@ struct JkPlan {
   size_t ccat, x, kpart, vtmp;
   int nsplit;
 };
+struct HalfPlan {
+  size_t cpad;
+};
 struct ActPlan {
-  size_t x, buv;
+  size_t cpad, x, buv;
 };
 struct PapaPlan {
-  size_t x, bpu, bvw, bqv;
+  size_t cpad, x, bpu, bvw, bqv;
 };
 struct StepPlan {
   size_t ccat, xo, xa, kpart, vtmp, bpu, buv;
   int nsplit;
 };
 
+// ccat / cpad: the dense operand of the half transform, [kpad16(nao)][ncol] with zero pad rows.
 JkPlan plan_jk(Plan& pl, int64_t naux, int64_t nao, int64_t ndm, int64_t nocc) {
   JkPlan p{};
   const int64_t ncol = ndm * nocc;
-  p.ccat = pl.take(ndm > 1 ? nao * ncol : 0);
+  p.ccat = pl.take(dfk::kpad16(nao) * ncol);
   p.x = pl.take(naux * nao * ncol);
   p.nsplit = dfk::syrk_splits(nao, naux, ndm);
   p.kpart = pl.take((int64_t)p.nsplit * ndm * nao * nao);
@@ -105,8 +109,15 @@ JkPlan plan_jk(Plan& pl, int64_t naux, int64_t nao, int64_t ndm, int64_t nocc) {
   return p;
 }
 
+HalfPlan plan_half(Plan& pl, int64_t nao, int64_t ncol) {
+  HalfPlan p{};
+  p.cpad = pl.take(dfk::kpad16(nao) * ncol);
+  return p;
+}
+
 ActPlan plan_act(Plan& pl, int64_t naux, int64_t nao, int64_t nac) {
   ActPlan p{};
+  p.cpad = pl.take(dfk::kpad16(nao) * nac);
   p.x = pl.take(naux * nao * nac);
   p.buv = pl.take(naux * nac * nac);
   return p;
@@ -114,6 +125,7 @@ ActPlan plan_act(Plan& pl, int64_t naux, int64_t nao, int64_t nac) {
 
 PapaPlan plan_papa(Plan& pl, int64_t naux, int64_t nao, int64_t nac, int64_t np, int64_t nq, bool full) {
   PapaPlan p{};
+  p.cpad = pl.take(dfk::kpad16(nao) * nac);
   p.x = pl.take(naux * nao * nac);
   p.bpu = pl.take(naux * np * nac);
   p.bvw = pl.take(full ? 0 : naux * nac * nac);
@@ -124,7 +136,7 @@ PapaPlan plan_papa(Plan& pl, int64_t naux, int64_t nao, int64_t nac, int64_t np,
 StepPlan plan_step(Plan& pl, int64_t naux, int64_t nao, int64_t nocc, int64_t nac, int64_t np, bool caller_x) {
   StepPlan p{};
   const int64_t ncol = nocc + nac;
-  p.ccat = pl.take(nao * ncol);
+  p.ccat = pl.take(dfk::kpad16(nao) * ncol);
   p.xo = pl.take(caller_x ? 0 : naux * nao * nocc);
   p.xa = pl.take(caller_x ? 0 : naux * nao * nac);
   p.nsplit = dfk::syrk_splits(nao, naux, 1);
@@ -148,14 +160,14 @@ BwdPlan plan_backward(Plan& pl, int64_t naux, int64_t nao, int64_t nocc, int64_t
   const bool cx = flags & DF_CALLER_X;
   const bool need_xo = gk && nocc > 0 && !cx, need_xa = ge && nac > 0 && !cx;
   const int64_t npair = nao * (nao + 1) / 2;
-  p.ccat = pl.take(need_xo && need_xa ? nao * (nocc + nac) : 0);
+  p.ccat = pl.take(dfk::kpad16(nao) * ((need_xo ? nocc : 0) + (need_xa ? nac : 0)));
   p.xo = pl.take(need_xo ? naux * nao * nocc : 0);
   p.xa = pl.take(need_xa ? naux * nao * nac : 0);
   p.g = pl.take(gj && nocc > 0 ? npair : 0);
   p.u = pl.take(gj && nocc > 0 ? naux : 0);
   p.M = pl.take(gj && nocc > 0 ? nao * nao : 0);
   p.S = pl.take(gk && nocc > 0 ? nao * nao : 0);
-  p.Y = pl.take(gk && nocc > 0 ? naux * nao * nocc : 0);
+  p.Y = pl.take(gk && nocc > 0 ? naux * dfk::kpad16(nao) * nocc : 0);   // [P][kpad16(nao)][nocc]
   p.nsk = gk && nocc > 0 ? dfk::half_reduce_splits(nao, nocc, naux) : 1;
   p.kpart = pl.take(gk && nocc > 0 ? (int64_t)p.nsk * nao * nocc : 0);
   p.Gs = pl.take(ge && nac > 0 ? nac * nac * nac * nac : 0);
@@ -240,9 +252,33 @@ size_t dbytes(int64_t n) { return (size_t)std::max<int64_t>(n, 0) * sizeof(doubl
 // ---- building blocks on the device ----
 
 // T_P = b^P C (ncol columns of C, row stride ldc), written through `out` with z = P
-df_status run_half(df_ctx* c, const double* B, int64_t naux, int64_t nao, const double* C, int64_t ldc,
-                   int64_t ncol, const dfk::OutMap& out) {
-  DF_LAUNCH(DF_KERNEL_HALF_TRANSFORM, dfk::launch_half_transform(B, naux, nao, C, ldc, ncol, out, c->stream),
+// A block of columns of the dense half-transform operand: src [nao][ncols] (row stride ld) goes to
+// columns [col0, col0 + ncols).
+struct ColBlock {
+  const double* src;
+  int64_t ld, ncols, col0;
+};
+
+// cpad [kpad16(nao)][ncol] = the blocks side by side, rows nao.. zero.
+df_status pad_operand(df_ctx* c, double* cpad, int64_t nao, int64_t ncol, const ColBlock* blocks, int nb) {
+  for (int i = 0; i < nb; ++i) {
+    const ColBlock& b = blocks[i];
+    if (b.ncols == 0) continue;
+    DF_LAUNCH(DF_KERNEL_OTHER,
+              hipMemcpy2DAsync(cpad + b.col0, ncol * sizeof(double), b.src, b.ld * sizeof(double),
+                               b.ncols * sizeof(double), nao, hipMemcpyDeviceToDevice, c->stream),
+              "operand gather");
+  }
+  const int64_t kp = dfk::kpad16(nao);
+  if (kp > nao)
+    DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(cpad + nao * ncol, (kp - nao) * ncol, c->stream), "fill");
+  return DF_OK;
+}
+
+// half transform against a padded operand from pad_operand
+df_status run_half(df_ctx* c, const double* B, int64_t naux, int64_t nao, const double* cpad, int64_t ncol,
+                   const dfk::OutMap& out) {
+  DF_LAUNCH(DF_KERNEL_HALF_TRANSFORM, dfk::launch_half_transform(B, naux, nao, cpad, ncol, ncol, out, c->stream),
             "half transform launch");
   return DF_OK;
 }
@@ -420,7 +456,7 @@ df_status df_workspace_size(df_op op, const df_dims* d, size_t* bytes) {
     return DF_ERR_SHAPE;
   Plan pl;
   switch (op) {
-    case DF_OP_HALF_TRANSFORM: break;
+    case DF_OP_HALF_TRANSFORM: plan_half(pl, d->nao, d->ncol); break;
     case DF_OP_JK: plan_jk(pl, d->naux, d->nao, std::max<int64_t>(d->ndm, 1), d->nocc); break;
     case DF_OP_ACTIVE_ERI: plan_act(pl, d->naux, d->nao, d->nac); break;
     case DF_OP_PAPA:
@@ -455,9 +491,17 @@ df_status df_half_transform(df_ctx* ctx, const double* B, int64_t naux, int64_t 
                            {X, dbytes(naux * nao * ncol), "X", true},
                            {C2, dbytes(nao * n2), "C2", false},
                            {Y, dbytes(naux * n2 * ncol), "Y", true}};
+  Plan pl;
+  const HalfPlan p = plan_half(pl, nao, ncol);
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (df_status s = need_ws(c, pl.total)) return s;
+  rs.push_back({c->ws, pl.total, "workspace", true});
   if (!check_overlap(c, rs)) return DF_ERR_ARG;
   if (df_status s = enter(c)) return s;
-  if (df_status s = run_half(c, B, naux, nao, C, ncol, ncol, out_pmajor(X, naux, nao, ncol, ncol))) return s;
+  double* cpad = (double*)(c->ws + p.cpad);
+  const ColBlock blk{C, ncol, ncol, 0};
+  if (df_status s = pad_operand(c, cpad, nao, ncol, &blk, 1)) return s;
+  if (df_status s = run_half(c, B, naux, nao, cpad, ncol, out_pmajor(X, naux, nao, ncol, ncol))) return s;
   if (C2) return run_mo_pmajor(c, C2, n2, X, naux, nao, ncol, Y);
   return DF_OK;
 }
@@ -496,16 +540,11 @@ df_status df_jk(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int64_t
   if (!J && !K && !v) return DF_OK;
   const int64_t ncol = ndm * nocc;
   double* X = (double*)(c->ws + p.x);
-  const double* Ccat = Cocc;
-  if (ndm > 1) {
-    double* cc = (double*)(c->ws + p.ccat);
-    for (int64_t z = 0; z < ndm; ++z)
-      DF_LAUNCH(DF_KERNEL_OTHER, hipMemcpy2DAsync(cc + z * nocc, ncol * sizeof(double), Cocc + z * nao * nocc, nocc * sizeof(double),
-                              nocc * sizeof(double), nao, hipMemcpyDeviceToDevice, c->stream),
-             "density factor gather");
-    Ccat = cc;
-  }
-  if (df_status s = run_half(c, B, naux, nao, Ccat, ncol, ncol, out_pmajor(X, naux, nao, ncol, ncol))) return s;
+  double* cc = (double*)(c->ws + p.ccat);
+  std::vector<ColBlock> blks((size_t)ndm);
+  for (int64_t z = 0; z < ndm; ++z) blks[(size_t)z] = ColBlock{Cocc + z * nao * nocc, nocc, nocc, z * nocc};
+  if (df_status s = pad_operand(c, cc, nao, ncol, blks.data(), (int)ndm)) return s;
+  if (df_status s = run_half(c, B, naux, nao, cc, ncol, out_pmajor(X, naux, nao, ncol, ncol))) return s;
   if (J || v) {
     double* vv = v ? v : (double*)(c->ws + p.vtmp);
     DF_LAUNCH(DF_KERNEL_JVEC, dfk::launch_jvec(X, naux, nao, ncol, Cocc, w, nocc, ndm, vv, c->stream), "J-vector launch");
@@ -542,7 +581,10 @@ df_status df_active_eri(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
   if (df_status s = enter(c)) return s;
   double* X = (double*)(c->ws + p.x);
   double* bu = buv ? buv : (double*)(c->ws + p.buv);
-  if (df_status s = run_half(c, B, naux, nao, Cact, nac, nac, out_split(nullptr, X, naux, nao, 0, nac))) return s;
+  double* cpad = (double*)(c->ws + p.cpad);
+  const ColBlock blk{Cact, nac, nac, 0};
+  if (df_status s = pad_operand(c, cpad, nao, nac, &blk, 1)) return s;
+  if (df_status s = run_half(c, B, naux, nao, cpad, nac, out_split(nullptr, X, naux, nao, 0, nac))) return s;
   if (df_status s = run_mo(c, Cact, nac, X, naux, nao, nac, bu)) return s;
   return run_pgemm(c, DF_KERNEL_ERI, bu, nac * nac, bu, nac * nac, naux, eri);
 }
@@ -580,7 +622,10 @@ df_status df_papa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const
   if (df_status s = enter(c)) return s;
   double* X = (double*)(c->ws + p.x);
   double* bpu = (double*)(c->ws + p.bpu);
-  if (df_status s = run_half(c, B, naux, nao, Cact, nac, nac, out_split(nullptr, X, naux, nao, 0, nac))) return s;
+  double* cpad = (double*)(c->ws + p.cpad);
+  const ColBlock blk{Cact, nac, nac, 0};
+  if (df_status s = pad_operand(c, cpad, nao, nac, &blk, 1)) return s;
+  if (df_status s = run_half(c, B, naux, nao, cpad, nac, out_split(nullptr, X, naux, nao, 0, nac))) return s;
   if (df_status s = run_mo(c, Cp, np, X, naux, nao, nac, bpu)) return s;
   if (full) {
     double* bqv = (double*)(c->ws + p.bqv);
@@ -636,19 +681,11 @@ df_status df_step(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const
   }
   if (ncol == 0) return DF_OK;
   double* cc = (double*)(c->ws + p.ccat);
-  if (nocc > 0)
-    DF_LAUNCH(DF_KERNEL_OTHER,
-              hipMemcpy2DAsync(cc, ncol * sizeof(double), Cocc, nocc * sizeof(double), nocc * sizeof(double), nao,
-                               hipMemcpyDeviceToDevice, c->stream),
-              "Cocc gather");
-  if (nac > 0)
-    DF_LAUNCH(DF_KERNEL_OTHER,
-              hipMemcpy2DAsync(cc + nocc, ncol * sizeof(double), Cact, nac * sizeof(double), nac * sizeof(double),
-                               nao, hipMemcpyDeviceToDevice, c->stream),
-              "Cact gather");
+  const ColBlock blks[2] = {{Cocc, nocc, nocc, 0}, {Cact, nac, nac, nocc}};
+  if (df_status s = pad_operand(c, cc, nao, ncol, blks, 2)) return s;
   double* Xo = caller_x ? Xocc : (double*)(c->ws + p.xo);
   double* Xa = caller_x ? Xact : (double*)(c->ws + p.xa);
-  if (df_status s = run_half(c, B, naux, nao, cc, ncol, ncol, out_split(Xo, Xa, naux, nao, nocc, nac))) return s;
+  if (df_status s = run_half(c, B, naux, nao, cc, ncol, out_split(Xo, Xa, naux, nao, nocc, nac))) return s;
   if (nocc > 0) {
     if (J || v) {
       double* vv = v ? v : (double*)(c->ws + p.vtmp);
@@ -718,23 +755,11 @@ df_status df_step_backward(df_ctx* ctx, const double* B, int64_t naux, int64_t n
   if (!caller_x && (do_k || do_e)) {
     double* xo = do_k ? (double*)(ws + p.xo) : nullptr;
     double* xa = do_e ? (double*)(ws + p.xa) : nullptr;
-    if (do_k && do_e) {
-      double* cc = (double*)(ws + p.ccat);
-      const int64_t ncol = nocc + nac;
-      DF_LAUNCH(DF_KERNEL_OTHER,
-                hipMemcpy2DAsync(cc, ncol * sizeof(double), Cocc, nocc * sizeof(double), nocc * sizeof(double), nao,
-                                 hipMemcpyDeviceToDevice, c->stream),
-                "Cocc gather");
-      DF_LAUNCH(DF_KERNEL_OTHER,
-                hipMemcpy2DAsync(cc + nocc, ncol * sizeof(double), Cact, nac * sizeof(double), nac * sizeof(double),
-                                 nao, hipMemcpyDeviceToDevice, c->stream),
-                "Cact gather");
-      if (df_status s = run_half(c, B, naux, nao, cc, ncol, ncol, out_split(xo, xa, naux, nao, nocc, nac))) return s;
-    } else if (do_k) {
-      if (df_status s = run_half(c, B, naux, nao, Cocc, nocc, nocc, out_pmajor(xo, naux, nao, nocc, nocc))) return s;
-    } else {
-      if (df_status s = run_half(c, B, naux, nao, Cact, nac, nac, out_split(nullptr, xa, naux, nao, 0, nac))) return s;
-    }
+    double* cc = (double*)(ws + p.ccat);
+    const int64_t no = do_k ? nocc : 0, na = do_e ? nac : 0;
+    const ColBlock blks[2] = {{Cocc, nocc, no, 0}, {Cact, nac, na, no}};
+    if (df_status s = pad_operand(c, cc, nao, no + na, blks, 2)) return s;
+    if (df_status s = run_half(c, B, naux, nao, cc, no + na, out_split(xo, xa, naux, nao, no, na))) return s;
     Xo = xo;
     Xa = xa;
   }
@@ -761,13 +786,18 @@ df_status df_step_backward(df_ctx* ctx, const double* B, int64_t naux, int64_t n
     dfk::OpMap Bm = dfk::op_map(Xo, naux * nocc, 1, nao, nocc);
     Bm.rl = nocc;
     Bm.s_rh = nao * nocc;
+    // Y [P][kpad16(nao)][nocc]: the packed product reads whole 16-row slabs of each Y_P
+    const int64_t kp = dfk::kpad16(nao);
     dfk::OutMap O = dfk::out_plain(Y, nao, naux * nocc, nocc);
     O.nl = nocc;
-    O.s_nh = nao * nocc;
+    O.s_nh = kp * nocc;
     DF_LAUNCH(DF_KERNEL_ADJOINT, dfk::launch_gemm(A, Bm, O, 1, c->stream), "adjoint product");
+    if (kp > nao)
+      DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero_strided(Y + nao * nocc, naux, kp * nocc, (kp - nao) * nocc, c->stream),
+                "fill");
     dfk::OpMap Ym = dfk::op_map(Y, nocc, 1, nao, nocc);
     Ym.kb_n = naux;
-    Ym.s_kb = nao * nocc;
+    Ym.s_kb = kp * nocc;
     dfk::OutMap Od = dfk::out_plain(dCocc, nao, nocc, nocc);
     Od.accumulate = do_j ? 1 : 0;
     DF_LAUNCH(DF_KERNEL_ADJOINT,

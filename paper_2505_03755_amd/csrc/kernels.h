@@ -47,8 +47,12 @@ __host__ __device__ inline OutMap out_plain(double* p, int64_t M, int64_t N, int
 // True when every within-slab element offset of `o` fits 32 bits.
 bool offsets_fit(const OpMap& o);
 
+// n rounded up to a multiple of the 16-deep contraction slab.
+inline int64_t kpad16(int64_t n) { return (n + 15) / 16 * 16; }
+
 // Half transform: for each P, T[m][c] = sum_k b^P_{mk} C[k][c], c in [0, ncol), written
-// through `out` with z = P (out.M = nao, out.N = ncol).
+// through `out` with z = P (out.M = nao, out.N = ncol, alpha 1, no accumulate).  C has
+// kpad16(nao) rows (row stride ldc), rows nao.. zero.
 hipError_t launch_half_transform(const double* B, int64_t naux, int64_t nao, const double* C, int64_t ldc,
                                  int64_t ncol, const OutMap& out, hipStream_t s);
 
@@ -64,7 +68,8 @@ hipError_t launch_gemm_split(const OpMap& A, const OpMap& Bm, const OutMap& C, i
                              hipStream_t s);
 
 // C(m, n) = sum_{P < naux} sum_k b^P_{mk} Y(n, (P, k)), Y given as an OpMap whose kb is P and
-// kc the AO index k; split over P ranges with partials [nsplit][nao][N] (half_reduce_splits()).
+// kc the AO index k (kc_n = nao); for every P the entries k in [nao, kpad16(nao)) must exist
+// and be zero.  Split over P ranges with partials [nsplit][nao][N] (half_reduce_splits()).
 int half_reduce_splits(int64_t nao, int64_t N, int64_t naux);
 hipError_t launch_half_reduce(const double* B, int64_t naux, int64_t nao, const OpMap& Y, const OutMap& C,
                               int nsplit, double* part, hipStream_t s);
@@ -98,5 +103,7 @@ hipError_t launch_coulomb(const double* B, int64_t naux, int64_t nao, const doub
 
 // p[0..n) = 0
 hipError_t launch_fill_zero(double* p, int64_t n, hipStream_t s);
+// p[z*s_z + i] = 0 for z < nz, i < n
+hipError_t launch_fill_zero_strided(double* p, int64_t nz, int64_t s_z, int64_t n, hipStream_t s);
 
 }  // namespace dfk

@@ -95,16 +95,26 @@ __device__ __forceinline__ void static_for(F&& f) {
   static_for_impl(std::make_integer_sequence<int, N>{}, f);
 }
 
-// One slab of the software pipeline.  LDS stage `cur` holds the slab being multiplied and F[0]
-// already holds its first k-step of operands.  While its TM*TN*BK/4 MFMAs issue one by one,
-// the wave reads the operands of the next k-step, issues the global loads of the next slab in
-// the first half, and writes those same registers to the other LDS stage in the second half
-// (a few thousand cycles after the loads went out).  Then one barrier and the first operands
-// of the next slab.  Every slot is generated at compile time, so the body is one basic block;
-// scheduling fences keep the interleave.
+// Sources.  A source feeds both operand tiles of a product slab by slab:
+//   begin()          set up the next slab (uniform values only)
+//   load<q>()        issue global load q (of NL) of the slab
+//   finish()         advance to the following slab (clamped at the last one)
+//   store<q>(A, B)   write loaded element q to the LDS tiles A, B
+// Rows and columns past the end of a matrix are read at clamped (valid) addresses and never
+// zeroed: they only reach output rows and columns that are not stored.  Only contraction
+// indices past the end (a partial last slab) must contribute zero.
+
+// One slab of the software pipeline (interleaved schedule).  LDS stage `cur` holds the slab being
+// multiplied and F[0] already holds its first k-step of operands.  While its TM*TN*BK/4 MFMAs
+// issue one by one, the wave reads the operands of the next k-step, issues the global loads of
+// the next slab in the first half and writes those registers to the other LDS stage in the
+// second half.  Then one barrier and the first operands of the next slab.  Every slot is
+// generated at compile time, so the body is one basic block; scheduling fences keep the
+// interleave.  (One body per kernel: alternative slab bodies in one loop overflow the 256
+// registers a lane has at two waves per SIMD.)
 template <class C, class Src>
-__device__ __forceinline__ void slab_step(Src& src, double* smem, int cur, d4 (&acc)[C::TM][C::TN],
-                                          Frag<C> (&F)[2], int wm, int wn, int lane) {
+__device__ __forceinline__ void slab_step(Src& src, double* smem, int cur, d4 (&acc)[C::TM][C::TN], Frag<C> (&F)[2],
+                                          int wm, int wn, int lane) {
   const double* As = smem + cur * C::STAGE;
   const double* Bs = As + C::LDS_A;
   double* An = smem + (cur ^ 1) * C::STAGE;
@@ -219,21 +229,25 @@ __device__ __forceinline__ void store_tile(const OutMap& o, int64_t z, int64_t m
   }
 }
 
-// Operand described by an OpMap, staged through two register sets.  Slabs are walked in order
-// (kb outer, kc in chunks of 16 inner) from slab `first` to `last`; loads past `last` re-read it.
+// Operand described by an OpMap, staged through registers.  Slabs are walked in order (kb outer,
+// kc in chunks of 16 inner) from slab `s_begin` to `s_end - 1`; the cursor stops at the last one.
 //   KC = true : lanes run along k (16 consecutive k of one row per 16 lanes)
 //   KC = false: lanes run along the row index
 //   SCALE     : element (r, kc) times ks[z*s_ksz + kc]
-template <class C, int R, bool KC, bool SCALE = false>
+//   CLAMP     : kc_n need not be a multiple of 16: in a partial slab k is clamped to the last
+//               entry and entries past kc_n are zeroed.  Without CLAMP, every slab is read whole,
+//               so kc_n must be a multiple of 16 or the rows padded with zeros up to one.
+// Element q of a thread sits at base + eoff[q] with base uniform per slab, so without CLAMP a
+// slab costs no per-element arithmetic.
+template <class C, int R, bool KC, bool SCALE = false, bool CLAMP = true>
 struct Operand {
   static constexpr int E = R * C::BK / C::NT;
-  static_assert(E <= 32, "validity mask holds 32 elements");
-  uint32_t eoff[E];     // offset of element q from the slab base (rows past the end clamped)
-  unsigned rowok;       // bit q: the row of element q exists
+  uint32_t eoff[E];     // offset of element q from the slab base (row clamped to the last one)
   double v[E];
   double sc[SCALE ? E : 1];
-  int kval;             // valid k entries of the slab held in v
+  int kval;             // valid k entries of the slab set up by begin()
   const double* base;
+  const double* ksb;
   int64_t zoff, kso;
   int64_t kb, kb_last;  // cursor: next slab to load is (kb, kc0)
   int kc0, kc_last;
@@ -246,7 +260,7 @@ struct Operand {
     const int e = t + C::NT * q;
     return KC ? e % C::BK : e / R;
   }
-  // rows [r0, r0 + R) of batch z; slabs s_begin .. s_end - 1 in (kb outer, kc chunk inner) order
+  // rows [r0, r0 + R) of batch z
   __device__ __forceinline__ void init(const OpMap& o, int64_t r0, int64_t z, int64_t s_begin, int64_t s_end,
                                        int t) {
     zoff = z * o.s_z;
@@ -256,13 +270,10 @@ struct Operand {
     kc0 = (int)(s_begin % nkc) * C::BK;
     kb_last = (s_end - 1) / nkc;
     kc_last = (int)((s_end - 1) % nkc) * C::BK;
-    rowok = 0;
 #pragma unroll
     for (int q = 0; q < E; ++q) {
       const int64_t r = r0 + rr(t, q);
-      const bool ok = r < o.rows;
-      rowok |= (ok ? 1u : 0u) << q;
-      const uint32_t rc = (uint32_t)(ok ? r : o.rows - 1);
+      const uint32_t rc = (uint32_t)(r < o.rows ? r : o.rows - 1);
       uint32_t rh = 0, rlo = rc;
       if (o.s_rh != 0) {
         rh = rc / (uint32_t)o.rl;
@@ -274,14 +285,20 @@ struct Operand {
   __device__ __forceinline__ void begin(const OpMap& o) {
     base = o.p + zoff + kb * o.s_kb + (int64_t)kc0 * o.s_kc;
     kval = (int)o.kc_n - kc0;
+    if constexpr (SCALE) ksb = o.ks + kso + kc0;
   }
   template <int q>
   __device__ __forceinline__ void load(const OpMap& o, int t) {
-    // entries past kc_n read the last valid k of the row instead (zeroed in store)
-    const int over = kk(t, q) - (kval - 1);
-    const uint32_t back = over > 0 ? (uint32_t)over * (uint32_t)o.s_kc : 0u;
-    v[q] = base[eoff[q] - back];
-    if constexpr (SCALE) sc[q] = o.ks[kso + kc0 + min(kk(t, q), kval - 1)];
+    if constexpr (!CLAMP) {
+      v[q] = base[eoff[q]];
+      if constexpr (SCALE) sc[q] = ksb[kk(t, q)];
+    } else {
+      // entries past kc_n read the last valid k of the row instead (zeroed in store)
+      const int over = kk(t, q) - (kval - 1);
+      const uint32_t back = over > 0 ? (uint32_t)over * (uint32_t)o.s_kc : 0u;
+      v[q] = base[eoff[q] - back];
+      if constexpr (SCALE) sc[q] = ksb[min(kk(t, q), kval - 1)];
+    }
   }
   __device__ __forceinline__ void finish(const OpMap& o) {
     // advance the cursor, but never past the last slab
@@ -297,19 +314,20 @@ struct Operand {
   }
   template <int q>
   __device__ __forceinline__ void store(double* Sm, int t) const {
-    const bool ok = ((rowok >> q) & 1u) && kk(t, q) < kval;
     const double x = SCALE ? v[q] * sc[q] : v[q];
-    Sm[rr(t, q) * C::LD + kk(t, q)] = ok ? x : 0.0;
+    const int slot = rr(t, q) * C::LD + kk(t, q);
+    if constexpr (!CLAMP) Sm[slot] = x;
+    else Sm[slot] = kk(t, q) < kval ? x : 0.0;
   }
 };
 
-// Source of a product with both operands from OpMaps (kb range [kb_first, kb_end)).
-template <class C, bool AK, bool BK, bool SCALE>
+// Source of a product with both operands from OpMaps over the same slab sequence.
+template <class C, bool AK, bool BK, bool SCALE, bool CLAMP>
 struct PairSrc {
-  static constexpr int EA = Operand<C, C::BM, AK>::E;
-  static constexpr int NL = EA + Operand<C, C::BN, BK, SCALE>::E;
-  Operand<C, C::BM, AK> a;
-  Operand<C, C::BN, BK, SCALE> b;
+  static constexpr int EA = Operand<C, C::BM, AK, false, CLAMP>::E;
+  static constexpr int NL = EA + Operand<C, C::BN, BK, SCALE, CLAMP>::E;
+  Operand<C, C::BM, AK, false, CLAMP> a;
+  Operand<C, C::BN, BK, SCALE, CLAMP> b;
   const OpMap* A;
   const OpMap* B;
   int t;
@@ -337,7 +355,7 @@ struct PairSrc {
 // Generic tiled product  C(m, n) = sum_k A(m, k) B(n, k)  over a batch (grid z).  With grid
 // y = nsplit > 1 each workgroup set covers a contiguous range of k slabs and writes its partial
 // sums to part[split][M][N] (nz must be 1 then).
-template <class C, bool AK, bool BK, bool GEN>
+template <class C, bool AK, bool BK, bool GEN, bool CLAMP>
 __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) gemm_kernel(OpMap A, OpMap B, OutMap O, int64_t tilesM, int64_t tilesN,
                                                      double* part) {
   __shared__ double smem[2 * C::STAGE];
@@ -353,7 +371,7 @@ __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2)))
   d4 acc[C::TM][C::TN];
   zero_acc<C>(acc);
   if (s1 > s0) {
-    PairSrc<C, AK, BK, false> src;
+    PairSrc<C, AK, BK, false, CLAMP> src;
     src.A = &A;
     src.B = &B;
     src.t = t;
@@ -390,7 +408,7 @@ __global__ void __launch_bounds__(256) split_reduce_kernel(const double* __restr
 // Lower-triangle tile SYRK with the kb range split over workgroups:
 // Kpart[split][z] tile (I, J), I >= J, = sum_{kb in split} sum_kc A(i, kb, kc) Bw(j, kb, kc),
 // where Bw is A times an optional per-kc weight.
-template <class C, bool SCALE>
+template <class C, bool SCALE, bool CLAMP>
 __global__ void __launch_bounds__(C::NT) syrk_kernel(OpMap A, OpMap Bw, int64_t n, int64_t nz, int nsplit,
                                                      int64_t npairs, double* Kpart) {
   static_assert(C::BM == C::BN, "square tiles");
@@ -413,7 +431,7 @@ __global__ void __launch_bounds__(C::NT) syrk_kernel(OpMap A, OpMap Bw, int64_t 
   zero_acc<C>(acc);
   const int64_t nslab = (kb_hi - kb_lo) * ((A.kc_n + C::BK - 1) / C::BK);
   if (nslab > 0) {
-    PairSrc<C, true, true, SCALE> src;
+    PairSrc<C, true, true, SCALE, CLAMP> src;
     src.A = &A;
     src.B = &Bw;
     src.t = t;
@@ -440,29 +458,32 @@ __global__ void __launch_bounds__(256) syrk_reduce_kernel(const double* __restri
 
 // ---------------------------------------------------------------------------------------
 // Half transform of one packed, symmetric b^P against a dense C.
-// A operand element (m, k) = b^P_{mk}.  A slab strictly below the diagonal (every k < every
-// m) is read along k: 16-element runs of packed rows.  Any other slab is read along m and
-// addressed through (max, min), which for slabs above the diagonal are runs of packed row k.
-// Both address sets are formed and one is selected, so the loads stay branch-free; packed
-// offsets stay in 32 bits (nao <= 46340).
+// A operand element (m, k) = b^P_{mk}, packed at T(max(m, k)) + min(m, k), T(i) = i(i+1)/2.
+// A slab wholly below the diagonal of its row band (k0 + 15 <= m0: every k <= every m) is read
+// along k, as 16-element runs of packed rows m: T(m) + k0 + (t % 16), a uniform base plus a
+// per-thread constant.  Any other slab is read along m through (max, min); there k is uniform
+// per wave and element, so T(k) is scalar work.  Both addresses are formed and a uniform select
+// picks one.  The dense operand (C, or Y in the P-summed form) is read without clamping: its k
+// extent must be padded with zero rows to a multiple of 16, which also cancels the clamped
+// duplicates of b^P read for k past the end.  Packed offsets stay in 32 bits (nao <= 46340).
 template <class C>
 struct HalfSrc {
   static constexpr int EA = C::BM * C::BK / C::NT;
-  static constexpr int NL = EA + Operand<C, C::BN, false>::E;
-  static_assert(EA <= 32, "validity mask holds 32 elements");
+  static constexpr int NL = EA + Operand<C, C::BN, false, false, false>::E;
   static_assert(C::NT % C::BK == 0 && C::NT % C::BM == 0, "per-thread row / column of the A loads");
-  Operand<C, C::BN, false> c;
+  static_assert(C::BM % 64 == 0, "t / BM is the same for all lanes of a wave");
+  Operand<C, C::BN, false, false, false> c;
   const OpMap* Cm;
   const double* Bbase;  // packed b^P of the current P: Bbase + P*npair
   const double* Bp;
   int64_t npair, P, P_last;
   unsigned last;        // nao - 1
   int m0, t, nks, ks;   // k slabs per P, current k slab
-  unsigned rowoffB[EA], rowokB, mA, mAc, mAoff;
-  double va[EA];
-  unsigned amask;
+  unsigned k0, kw;      // slab start; wave-uniform k offset t / BM of the along-m mapping
   bool below;
-  unsigned k0;
+  uint32_t offB[EA];    // along-k mapping: T(m) + t % 16 for row m = m0 + e / 16 (clamped)
+  uint32_t mAc, mAoff;  // along-m mapping: row m0 + t % BM (clamped) and T of it
+  double va[EA];
 
   // slabs run over P in [P0, P1) (outer) and the k chunks of nao (inner)
   __device__ __forceinline__ void init(const double* B, int64_t npair_, int64_t P0, int64_t P1, int nao, int m0_,
@@ -476,36 +497,31 @@ struct HalfSrc {
     t = t_;
     nks = (nao + C::BK - 1) / C::BK;
     ks = 0;
-    rowokB = 0;
-    // below-diagonal mapping: element q is row m0 + t/16 + q*NT/16, column k0 + t%16
 #pragma unroll
     for (int q = 0; q < EA; ++q) {
       const unsigned m = (unsigned)(m0 + (t + C::NT * q) / C::BK);
-      rowokB |= (m <= last ? 1u : 0u) << q;
       const unsigned mc = m <= last ? m : last;
-      rowoffB[q] = mc * (mc + 1u) / 2u + (unsigned)(t % C::BK);
+      offB[q] = mc * (mc + 1u) / 2u + (unsigned)(t % C::BK);
     }
-    // other mapping: element q is row m0 + t%BM, column k0 + t/BM + q*NT/BM
-    mA = (unsigned)(m0 + t % C::BM);
+    const unsigned mA = (unsigned)(m0 + t % C::BM);
     mAc = mA <= last ? mA : last;
     mAoff = mAc * (mAc + 1u) / 2u;
+    kw = (unsigned)__builtin_amdgcn_readfirstlane(t / C::BM);
   }
   __device__ __forceinline__ void begin() {
     Bp = Bbase + P * npair;
     k0 = (unsigned)ks * C::BK;
     below = (int)k0 + C::BK - 1 <= m0;
-    amask = below ? rowokB : 0u;
     c.begin(*Cm);
   }
   template <int q>
   __device__ __forceinline__ void load() {
     if constexpr (q < EA) {
-      const unsigned k = k0 + (unsigned)((t + C::NT * q) / C::BM);
-      const unsigned kc = k <= last ? k : last;
-      const unsigned io = mAc >= kc ? mAoff + kc : kc * (kc + 1u) / 2u + mAc;
-      const unsigned idx = below ? rowoffB[q] + k0 : io;
-      if (!below) amask |= ((mA <= last && k <= last) ? 1u : 0u) << q;
-      va[q] = Bp[idx];
+      const unsigned kr = k0 + kw + (unsigned)(q * (C::NT / C::BM));   // uniform
+      const unsigned kc = kr <= last ? kr : last;
+      const unsigned Tk = kc * (kc + 1u) / 2u;
+      const unsigned other = mAc >= kc ? mAoff + kc : Tk + mAc;
+      va[q] = Bp[below ? offB[q] + k0 : other];
     } else {
       c.template load<q - EA>(*Cm, t);
     }
@@ -526,8 +542,7 @@ struct HalfSrc {
   __device__ __forceinline__ void store(double* As, double* Bs) const {
     if constexpr (q < EA) {
       const int e = t + C::NT * q;
-      const int slot = below ? (e / C::BK) * C::LD + e % C::BK : (e % C::BM) * C::LD + e / C::BM;
-      As[slot] = ((amask >> q) & 1u) ? va[q] : 0.0;
+      As[below ? (e / C::BK) * C::LD + e % C::BK : (e % C::BM) * C::LD + e / C::BM] = va[q];
     } else {
       c.template store<q - EA>(Bs, t);
     }
@@ -712,6 +727,11 @@ __global__ void __launch_bounds__(256) fill_zero_kernel(double* p, int64_t n) {
   if (i < n) p[i] = 0.0;
 }
 
+__global__ void __launch_bounds__(256) fill_zero_strided_kernel(double* p, int64_t nz, int64_t s_z, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n * nz) p[(i / n) * s_z + i % n] = 0.0;
+}
+
 // ---------------------------------------------------------------------------------------
 // Launchers
 
@@ -764,27 +784,31 @@ hipError_t launch_half_transform(const double* B, int64_t naux, int64_t nao, con
   }
 }
 
+template <bool GEN, bool CLAMP>
+static void gemm_go(const OpMap& A, const OpMap& Bm, const OutMap& O, dim3 grid, int64_t tm, int64_t tn, double* part,
+                    hipStream_t s) {
+  typedef CfgSq Cg;
+  const bool ak = A.s_kc == 1, bk = Bm.s_kc == 1;
+  if (ak && bk) gemm_kernel<Cg, true, true, GEN, CLAMP><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn, part);
+  else if (ak) gemm_kernel<Cg, true, false, GEN, CLAMP><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn, part);
+  else if (bk) gemm_kernel<Cg, false, true, GEN, CLAMP><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn, part);
+  else gemm_kernel<Cg, false, false, GEN, CLAMP><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn, part);
+}
+
 static hipError_t gemm_launch(const OpMap& A, const OpMap& Bm, const OutMap& O, int64_t nz, int nsplit,
                               double* part, hipStream_t s) {
   typedef CfgSq Cg;
   const int64_t tm = cdiv(O.M, Cg::BM), tn = cdiv(O.N, Cg::BN);
   if (tm * tn == 0 || nz == 0) return hipSuccess;
-  if (tm * tn > 0x7fffffffLL || nz > 65535 || nsplit < 1 || nsplit > 65535 || !offsets_fit(A) || !offsets_fit(Bm))
+  if (tm * tn > 0x7fffffffLL || nz > 65535 || nsplit < 1 || nsplit > 65535 || !offsets_fit(A) || !offsets_fit(Bm) ||
+      A.kc_n != Bm.kc_n || A.kb_n != Bm.kb_n)
     return hipErrorInvalidValue;
   const dim3 grid((unsigned)(tm * tn), (unsigned)nsplit, (unsigned)nz);
-  const bool ak = A.s_kc == 1, bk = Bm.s_kc == 1;
-  if (!part && (O.alpha != 1.0 || O.accumulate)) {
-    // small products that scale or accumulate: general epilogue, operand layouts as given
-    if (ak && bk) gemm_kernel<Cg, true, true, true><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn, part);
-    else if (ak) gemm_kernel<Cg, true, false, true><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn, part);
-    else if (bk) gemm_kernel<Cg, false, true, true><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn, part);
-    else gemm_kernel<Cg, false, false, true><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn, part);
-    return hipGetLastError();
-  }
-  if (ak && bk) gemm_kernel<Cg, true, true, false><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn, part);
-  else if (ak) gemm_kernel<Cg, true, false, false><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn, part);
-  else if (bk) gemm_kernel<Cg, false, true, false><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn, part);
-  else gemm_kernel<Cg, false, false, false><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn, part);
+  // whole slabs (no clamping) when the contraction chunks are multiples of 16
+  const bool clamp = A.kc_n % 16 != 0;
+  if (!part && (O.alpha != 1.0 || O.accumulate)) gemm_go<true, true>(A, Bm, O, grid, tm, tn, part, s);
+  else if (clamp) gemm_go<false, true>(A, Bm, O, grid, tm, tn, part, s);
+  else gemm_go<false, false>(A, Bm, O, grid, tm, tn, part, s);
   return hipGetLastError();
 }
 
@@ -896,8 +920,11 @@ hipError_t launch_syrk_partial(const OpMap& A, const OpMap& Bw, int64_t n, int64
   if (npairs == 0 || nz == 0) return hipSuccess;
   if (nz > 65535 || !offsets_fit(A)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(npairs * nsplit), 1, (unsigned)nz);
-  if (Bw.ks) syrk_kernel<Cg, true><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
-  else syrk_kernel<Cg, false><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
+  const bool clamp = A.kc_n % 16 != 0;
+  if (Bw.ks && clamp) syrk_kernel<Cg, true, true><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
+  else if (Bw.ks) syrk_kernel<Cg, true, false><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
+  else if (clamp) syrk_kernel<Cg, false, true><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
+  else syrk_kernel<Cg, false, false><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
   return hipGetLastError();
 }
 
@@ -932,6 +959,13 @@ hipError_t launch_coulomb(const double* B, int64_t naux, int64_t nao, const doub
 hipError_t launch_fill_zero(double* p, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   fill_zero_kernel<<<(unsigned)cdiv(n, 256), 256, 0, s>>>(p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero_strided(double* p, int64_t nz, int64_t s_z, int64_t n, hipStream_t s) {
+  const int64_t tot = n * nz;
+  if (tot <= 0) return hipSuccess;
+  fill_zero_strided_kernel<<<(unsigned)cdiv(tot, 256), 256, 0, s>>>(p, nz, s_z, n);
   return hipGetLastError();
 }
 

@@ -52,7 +52,7 @@ def test_create_rejects_bad_arguments(L):
 
 def test_workspace_size(L):
     n = dfmi.workspace_size(dfmi.DF_OP_HALF_TRANSFORM, naux=10, nao=7, ncol=3)
-    assert n == 0
+    assert n >= 16 * 3 * 8          # C padded to 16 rows
     jk = dfmi.workspace_size(dfmi.DF_OP_JK, naux=10, nao=7, ndm=1, nocc=3)
     assert jk >= 10 * 7 * 3 * 8
     step = dfmi.workspace_size(dfmi.DF_OP_STEP, naux=10, nao=7, nocc=3, nac=2, np=7)
@@ -169,6 +169,11 @@ def test_valid_call_without_device_fails_loudly(L, ctx):
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     B, C, X = fake(1 << 30), fake(2 << 30), fake(3 << 30)
+    # without a workspace the call stops at the argument checks
+    assert L.df_half_transform(ctx, B, 4, 3, C, 2, X, None, 0, None, 0) == dfmi.DF_ERR_WORKSPACE
+    n = dfmi.workspace_size(dfmi.DF_OP_HALF_TRANSFORM, naux=4, nao=3, ncol=2)
+    assert L.df_set_workspace(ctx, fake(4 << 30), n) == dfmi.DF_OK   # recorded only, never touched here
     st = L.df_half_transform(ctx, B, 4, 3, C, 2, X, None, 0, None, 0)
     assert st == dfmi.DF_ERR_HIP
     assert b"hipSetDevice" in L.df_last_error(ctx)
+    assert L.df_set_workspace(ctx, None, 0) == dfmi.DF_OK
