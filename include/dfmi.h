@@ -62,7 +62,9 @@ typedef enum df_op {
   DF_OP_ACTIVE_ERI = 3,
   DF_OP_PAPA = 4,
   DF_OP_STEP = 5,
-  DF_OP_STEP_BACKWARD = 6
+  DF_OP_STEP_BACKWARD = 6,
+  DF_OP_SPLIT_MATMUL = 7,
+  DF_OP_STEP_SPLIT = 8
 } df_op;
 
 /* Kernel classes reported by df_timing_read. */
@@ -77,7 +79,8 @@ typedef enum df_kernel_kind {
   DF_KERNEL_ERI = 7,             /* (uv|wx) contraction over P */
   DF_KERNEL_OTHER = 8,           /* fills, symmetrisations and coefficient gathers */
   DF_KERNEL_ADJOINT = 9,         /* the products of df_step_backward */
-  DF_NUM_KERNEL_KINDS = 10
+  DF_KERNEL_SPLIT = 10,          /* splitting FP64 operands into int8 slices */
+  DF_NUM_KERNEL_KINDS = 11
 } df_kernel_kind;
 
 /* Flag bits of calls. */
@@ -100,6 +103,8 @@ typedef struct df_dims {
   int64_t ncol;   /* columns of C in df_half_transform */
   int64_t n2;     /* columns of C2 in df_half_transform (0 if no second transform) */
   int flags;
+  int nslice;     /* int8 slices per operand (DF_OP_SPLIT_MATMUL, DF_OP_STEP_SPLIT) */
+  int64_t m, n, k;  /* product sizes of DF_OP_SPLIT_MATMUL */
 } df_dims;
 
 /* Create a context on HIP device `device` that enqueues onto `stream`
@@ -218,6 +223,47 @@ df_status df_step_backward(df_ctx* ctx, const double* B, int64_t naux, int64_t n
                            const double* gJ, const double* gK, const double* geri,
                            const double* Xocc, const double* Xact,
                            double* dCocc, double* dCact, int flags);
+
+/*
+ * Split precision on the int8 matrix cores.  An FP64 row x is cut into nslice int8 slices,
+ *   x[k] ~= 2^e sum_{s < nslice} a_s[k] 2^-(6 + 7 s),   a_s in [-64, 64],  max|x| < 2^e,
+ * exactly up to a residual below 2^(e - 7 nslice); a product keeps the slice pairs with
+ * s + t < nslice, summed exactly in int32 and then in FP64.  For two rows of length K the
+ * error is below K (nslice + 4) 2^(e_a + e_b - 7 nslice) plus FP64 rounding; nslice = 7 gives
+ * FP64-level results.  nslice must be in [4, 8].  This is the mixed-precision direction the
+ * paper lists as future work (Sec. Conclusions), applied to Eqs. (ao2mo_1), (K_2), (ao2mo_2)
+ * and (papa).
+ */
+
+/*
+ * C[m][n] = sum_k A[m][k] B[n][k] by the split method.
+ *   A [M][lda], B [N][ldb] (lda, ldb >= K), C [M][ldc] (ldc >= N), row major, FP64, device.
+ * Workspace: df_workspace_size(DF_OP_SPLIT_MATMUL, {m = M, n = N, k = K, nslice}).
+ */
+df_status df_split_matmul(df_ctx* ctx, const double* A, int64_t lda, int64_t M, const double* B, int64_t ldb,
+                          int64_t N, int64_t K, int nslice, double* C, int64_t ldc, int flags);
+
+/*
+ * One-time split of the Cholesky vectors for df_step_split: the rows (P, mu) of the unpacked
+ * b^P (Eq. cholesky) as int8 planes.
+ *   Bs [nslice][naux * nao][kpad64(nao)] int8 (kpad64(n) = n rounded up to a multiple of 64),
+ *   Be [naux * nao] int32 exponents; both caller-owned device buffers, overwritten.
+ *   naux * nao < 2^31.  No workspace.
+ */
+df_status df_split_cholesky(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int nslice, int8_t* Bs,
+                            int* Be, int flags);
+
+/*
+ * df_step in split precision (unit weights): the half transform (against Bs, Be from
+ * df_split_cholesky with the same nslice), K, the second transforms, (uv|wx) and (pu|vw) are
+ * split products; the J-vector v and J (from the packed B) are FP64.  Outputs as in df_step;
+ * any of J, K, v, eri, papa may be NULL.
+ * Workspace: df_workspace_size(DF_OP_STEP_SPLIT, {naux, nao, 1, nocc, nac, np, nslice}).
+ */
+df_status df_step_split(df_ctx* ctx, const double* B, const int8_t* Bs, const int* Be, int nslice, int64_t naux,
+                        int64_t nao, const double* Cocc, int64_t nocc, const double* Cact, int64_t nac,
+                        const double* Cp, int64_t np, double* J, double* K, double* v, double* eri, double* papa,
+                        int flags);
 
 #ifdef __cplusplus
 }

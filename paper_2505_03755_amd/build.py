@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdfmi.so")
-SOURCES = [os.path.join(HERE, "csrc", "kernels.hip"), os.path.join(HERE, "csrc", "api.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", n) for n in ("kernels.hip", "split.hip", "api.cpp")]
 ARCH = "gfx950"
 
 

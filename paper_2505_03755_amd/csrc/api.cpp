@@ -178,6 +178,74 @@ BwdPlan plan_backward(Plan& pl, int64_t naux, int64_t nao, int64_t nocc, int64_t
   return p;
 }
 
+// ---- split precision ----
+// Planes of an operand with `rows` rows and contraction length K: [nslice][rows][kpad64(K)] int8
+// and [rows] int32 exponents.
+struct SplitBuf {
+  size_t planes, ex;
+};
+SplitBuf take_split(Plan& pl, int64_t rows, int64_t K, int nslice) {
+  SplitBuf b{};
+  const int64_t bytes = (int64_t)nslice * rows * dfk::kpad64(K);
+  b.planes = pl.take((bytes + 7) / 8);
+  b.ex = pl.take((rows * 4 + 7) / 8);
+  return b;
+}
+
+// Split count for a slice product of `tiles` 64 x 64 tiles and nks 64-deep steps: about two
+// workgroups per CU (one resident per CU), at least 32 steps per split.
+int slice_splits(int64_t tiles, int64_t nks) {
+  int64_t ns = tiles > 0 ? (512 + tiles - 1) / tiles : 1;
+  if (ns > nks / 32) ns = nks / 32;
+  if (ns < 1) ns = 1;
+  if (ns > 4096) ns = 4096;
+  return (int)ns;
+}
+
+struct SplitMmPlan {
+  SplitBuf a, b;
+  size_t part;
+  int nsplit;
+};
+SplitMmPlan plan_split_mm(Plan& pl, int64_t M, int64_t N, int64_t K, int nslice) {
+  SplitMmPlan p{};
+  p.a = take_split(pl, M, K, nslice);
+  p.b = take_split(pl, N, K, nslice);
+  const int64_t T = dfk::slice_gemm_tile();
+  p.nsplit = slice_splits(((M + T - 1) / T) * ((N + T - 1) / T), dfk::kpad64(K) / 64);
+  p.part = pl.take(p.nsplit > 1 ? (int64_t)p.nsplit * M * N : 0);
+  return p;
+}
+
+// Workspace of df_step_split (forward in split precision; B comes pre-split).
+struct StepSplitPlan {
+  size_t ccat, xo, xa, bpu, buv, kpart, vtmp;
+  SplitBuf cs, xos, xas, cps, cas, bpus, buvs;
+  int nsk;
+};
+StepSplitPlan plan_step_split(Plan& pl, int64_t naux, int64_t nao, int64_t nocc, int64_t nac, int64_t np,
+                              int nslice) {
+  StepSplitPlan p{};
+  const int64_t ncol = nocc + nac, T = dfk::slice_gemm_tile();
+  p.ccat = pl.take(nao * ncol);
+  p.xo = pl.take(naux * nao * nocc);     // P-major [naux][nao][nocc]
+  p.xa = pl.take(naux * nao * nac);      // P-major [naux][nao][nac]
+  p.bpu = pl.take(naux * np * nac);
+  p.buv = pl.take(naux * nac * nac);
+  p.cs = take_split(pl, ncol, nao, nslice);
+  p.xos = take_split(pl, nocc > 0 ? nao : 0, naux * nocc, nslice);
+  const int64_t tk = (nao + T - 1) / T;
+  p.nsk = slice_splits(tk * (tk + 1) / 2, dfk::kpad64(naux * nocc) / 64);
+  p.kpart = pl.take(nocc > 0 ? (int64_t)p.nsk * nao * nao : 0);
+  p.vtmp = pl.take(naux);
+  p.xas = take_split(pl, naux * nac, nao, nslice);
+  p.cps = take_split(pl, nac > 0 ? np : 0, nao, nslice);
+  p.cas = take_split(pl, nac, nao, nslice);
+  p.bpus = take_split(pl, np * nac, naux, nslice);
+  p.buvs = take_split(pl, nac * nac, naux, nslice);
+  return p;
+}
+
 df_status check_ctx(df_ctx* c) {
   if (!c) return DF_ERR_ARG;
   c->err.clear();
@@ -272,6 +340,19 @@ df_status pad_operand(df_ctx* c, double* cpad, int64_t nao, int64_t ncol, const 
   const int64_t kp = dfk::kpad16(nao);
   if (kp > nao)
     DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(cpad + nao * ncol, (kp - nao) * ncol, c->stream), "fill");
+  return DF_OK;
+}
+
+// cc [nao][ncol] = the blocks side by side (no padding)
+df_status pad_operand_plain(df_ctx* c, double* cc, int64_t nao, int64_t ncol, const ColBlock* blocks, int nb) {
+  for (int i = 0; i < nb; ++i) {
+    const ColBlock& b = blocks[i];
+    if (b.ncols == 0) continue;
+    DF_LAUNCH(DF_KERNEL_OTHER,
+              hipMemcpy2DAsync(cc + b.col0, ncol * sizeof(double), b.src, b.ld * sizeof(double),
+                               b.ncols * sizeof(double), nao, hipMemcpyDeviceToDevice, c->stream),
+              "operand gather");
+  }
   return DF_OK;
 }
 
@@ -451,6 +532,13 @@ df_status df_set_workspace(df_ctx* ctx, void* ptr, size_t bytes) {
 df_status df_workspace_size(df_op op, const df_dims* d, size_t* bytes) {
   if (!d || !bytes) return DF_ERR_ARG;
   *bytes = 0;
+  if (op == DF_OP_SPLIT_MATMUL) {
+    if (d->m < 0 || d->n < 0 || d->k < 1 || d->nslice < 4 || d->nslice > 8) return DF_ERR_SHAPE;
+    Plan pm;
+    plan_split_mm(pm, d->m, d->n, d->k, d->nslice);
+    *bytes = pm.total;
+    return DF_OK;
+  }
   if (d->naux < 1 || d->nao < 1 || d->nao > kMaxNao) return DF_ERR_SHAPE;
   if (d->ndm < 0 || d->nocc < 0 || d->nac < 0 || d->np < 0 || d->nq < 0 || d->ncol < 0 || d->n2 < 0)
     return DF_ERR_SHAPE;
@@ -467,6 +555,10 @@ df_status df_workspace_size(df_op op, const df_dims* d, size_t* bytes) {
       break;
     case DF_OP_STEP_BACKWARD:
       plan_backward(pl, d->naux, d->nao, d->nocc, d->nac, d->flags);
+      break;
+    case DF_OP_STEP_SPLIT:
+      if (d->nslice < 4 || d->nslice > 8) return DF_ERR_SHAPE;
+      plan_step_split(pl, d->naux, d->nao, d->nocc, d->nac, d->np, d->nslice);
       break;
     default: return DF_ERR_UNSUPPORTED;
   }
@@ -823,6 +915,203 @@ df_status df_step_backward(df_ctx* ctx, const double* B, int64_t naux, int64_t n
               dfk::launch_gemm_split(Ax, Bz, dfk::out_plain(dCact, nao, nac, nac), p.nsa, (double*)(ws + p.apart),
                                      c->stream),
               "adjoint product");
+  }
+  return DF_OK;
+}
+
+df_status df_split_matmul(df_ctx* ctx, const double* A, int64_t lda, int64_t M, const double* Bm, int64_t ldb,
+                          int64_t N, int64_t K, int nslice, double* C, int64_t ldc, int flags) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_split_matmul takes no flags");
+  if (nslice < 4 || nslice > 8) return fail(c, DF_ERR_SHAPE, "nslice must be in [4, 8]");
+  if (M < 0 || N < 0 || K < 1) return fail(c, DF_ERR_SHAPE, "M, N must be >= 0 and K >= 1");
+  if (M > 0 && (!A || lda < K)) return fail(c, DF_ERR_ARG, "A is NULL or lda < K");
+  if (N > 0 && (!Bm || ldb < K)) return fail(c, DF_ERR_ARG, "B is NULL or ldb < K");
+  if (M > 0 && N > 0 && (!C || ldc < N)) return fail(c, DF_ERR_ARG, "C is NULL or ldc < N");
+  if (M > 0x7fffffffLL || N > 0x7fffffffLL) return fail(c, DF_ERR_SHAPE, "M and N must be below 2^31");
+  std::vector<Range> rs = {{A, dbytes(M > 0 ? (M - 1) * lda + K : 0), "A", false},
+                           {Bm, dbytes(N > 0 ? (N - 1) * ldb + K : 0), "B", false},
+                           {C, dbytes(M > 0 && N > 0 ? (M - 1) * ldc + N : 0), "C", true}};
+  Plan pl;
+  const SplitMmPlan p = plan_split_mm(pl, M, N, K, nslice);
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (M == 0 || N == 0) return DF_OK;
+  if (df_status s = need_ws(c, pl.total)) return s;
+  rs.push_back({c->ws, pl.total, "workspace", true});
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (df_status s = enter(c)) return s;
+  int8_t* ap = (int8_t*)(c->ws + p.a.planes);
+  int8_t* bp = (int8_t*)(c->ws + p.b.planes);
+  int* ea = (int*)(c->ws + p.a.ex);
+  int* eb = (int*)(c->ws + p.b.ex);
+  DF_LAUNCH(DF_KERNEL_SPLIT, dfk::launch_split_rows(dfk::op_map(A, M, lda, K, 1), K, nslice, ap, ea, c->stream),
+            "split launch");
+  DF_LAUNCH(DF_KERNEL_SPLIT, dfk::launch_split_rows(dfk::op_map(Bm, N, ldb, K, 1), K, nslice, bp, eb, c->stream),
+            "split launch");
+  const dfk::OutMap O = dfk::out_plain(C, M, N, ldc);
+  double* part = p.nsplit > 1 ? (double*)(c->ws + p.part) : nullptr;
+  DF_LAUNCH(DF_KERNEL_OTHER,
+            dfk::launch_slice_gemm(ap, ea, M, bp, eb, N, dfk::kpad64(K), nslice, O, false, p.nsplit, part, c->stream),
+            "slice product launch");
+  if (part) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_split_reduce(part, p.nsplit, O, c->stream), "split reduce");
+  return DF_OK;
+}
+
+df_status df_split_cholesky(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int nslice, int8_t* Bs,
+                            int* Be, int flags) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (df_status s = check_core(c, B, naux, nao)) return s;
+  if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_split_cholesky takes no flags");
+  if (nslice < 4 || nslice > 8) return fail(c, DF_ERR_SHAPE, "nslice must be in [4, 8]");
+  if (!Bs || !Be) return fail(c, DF_ERR_ARG, "Bs and Be are required");
+  if (naux * nao > 0x7fffffffLL) return fail(c, DF_ERR_SHAPE, "naux * nao must be below 2^31");
+  const int64_t npair = nao * (nao + 1) / 2;
+  std::vector<Range> rs = {{B, dbytes(naux * npair), "B", false},
+                           {Bs, (size_t)nslice * naux * nao * dfk::kpad64(nao), "Bs", true},
+                           {Be, (size_t)naux * nao * 4, "Be", true}};
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (df_status s = enter(c)) return s;
+  DF_LAUNCH(DF_KERNEL_SPLIT, dfk::launch_split_packed(B, naux, nao, nslice, Bs, Be, c->stream), "split launch");
+  return DF_OK;
+}
+
+df_status df_step_split(df_ctx* ctx, const double* B, const int8_t* Bs, const int* Be, int nslice, int64_t naux,
+                        int64_t nao, const double* Cocc, int64_t nocc, const double* Cact, int64_t nac,
+                        const double* Cp, int64_t np, double* J, double* K, double* v, double* eri, double* papa,
+                        int flags) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (df_status s = check_core(c, B, naux, nao)) return s;
+  if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_step_split takes no flags");
+  if (nslice < 4 || nslice > 8) return fail(c, DF_ERR_SHAPE, "nslice must be in [4, 8]");
+  if (!Bs || !Be) return fail(c, DF_ERR_ARG, "Bs and Be (from df_split_cholesky) are required");
+  if (nocc < 0 || nac < 0 || np < 0) return fail(c, DF_ERR_SHAPE, "sizes must be >= 0");
+  if (nocc > 0 && !Cocc) return fail(c, DF_ERR_ARG, "Cocc is NULL");
+  if (nac > 0 && !Cact) return fail(c, DF_ERR_ARG, "Cact is NULL");
+  if (np > 0 && !Cp) return fail(c, DF_ERR_ARG, "Cp is NULL");
+  if (naux * nao > 0x7fffffffLL || naux * nac > 0x7fffffffLL || np * nac > 0x7fffffffLL)
+    return fail(c, DF_ERR_SHAPE, "problem too large for the split path");
+  const int64_t npair = nao * (nao + 1) / 2;
+  const int64_t ncol = nocc + nac;
+  std::vector<Range> rs = {{B, dbytes(naux * npair), "B", false},
+                           {Bs, (size_t)nslice * naux * nao * dfk::kpad64(nao), "Bs", false},
+                           {Be, (size_t)naux * nao * 4, "Be", false},
+                           {Cocc, dbytes(nao * nocc), "Cocc", false},
+                           {Cact, dbytes(nao * nac), "Cact", false},
+                           {Cp, dbytes(nao * np), "Cp", false},
+                           {J, dbytes(nao * nao), "J", true},
+                           {K, dbytes(nao * nao), "K", true},
+                           {v, dbytes(naux), "v", true},
+                           {eri, dbytes(nac * nac * nac * nac), "eri", true},
+                           {papa, dbytes(np * nac * nac * nac), "papa", true}};
+  Plan pl;
+  const StepSplitPlan p = plan_step_split(pl, naux, nao, nocc, nac, np, nslice);
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (df_status s = need_ws(c, pl.total)) return s;
+  rs.push_back({c->ws, pl.total, "workspace", true});
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (df_status s = enter(c)) return s;
+  char* ws = c->ws;
+  if (nocc == 0) {
+    if (J) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(J, nao * nao, c->stream), "fill");
+    if (K) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(K, nao * nao, c->stream), "fill");
+    if (v) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(v, naux, c->stream), "fill");
+  }
+  if (ncol == 0) return DF_OK;
+  const int64_t kpo = dfk::kpad64(nao);
+  // a2: X[(P, m)][c] = sum_k b^P_{mk} [Cocc | Cact][k][c], against the pre-split rows of b^P
+  double* cc = (double*)(ws + p.ccat);
+  const ColBlock blks[2] = {{Cocc, nocc, nocc, 0}, {Cact, nac, nac, nocc}};
+  if (df_status s = pad_operand_plain(c, cc, nao, ncol, blks, 2)) return s;
+  int8_t* cs = (int8_t*)(ws + p.cs.planes);
+  int* ce = (int*)(ws + p.cs.ex);
+  DF_LAUNCH(DF_KERNEL_SPLIT, dfk::launch_split_rows(dfk::op_map(cc, ncol, 1, nao, ncol), nao, nslice, cs, ce, c->stream),
+            "split launch");
+  double* Xo = (double*)(ws + p.xo);
+  double* Xa = (double*)(ws + p.xa);
+  dfk::OutMap OX = dfk::out_plain(Xo, naux * nao, ncol, nocc);
+  OX.nsplit = nocc;
+  OX.p2 = Xa;
+  OX.s2_m = nac;
+  DF_LAUNCH(DF_KERNEL_HALF_TRANSFORM,
+            dfk::launch_slice_gemm(Bs, Be, naux * nao, cs, ce, ncol, kpo, nslice, OX, false, 1, nullptr, c->stream),
+            "slice product launch");
+  if (nocc > 0) {
+    // a3, a4 in FP64
+    if (J || v) {
+      double* vv = v ? v : (double*)(ws + p.vtmp);
+      DF_LAUNCH(DF_KERNEL_JVEC, dfk::launch_jvec(Xo, naux, nao, nocc, Cocc, nullptr, nocc, 1, vv, c->stream),
+                "J-vector launch");
+      if (J) DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_coulomb(B, naux, nao, vv, 1, J, c->stream), "Coulomb launch");
+    }
+    // a5: K = sum_{P, c} X[P][i][c] X[P][j][c] from the split rows i of X_occ
+    if (K) {
+      dfk::OpMap ox = dfk::op_map(Xo, nao, nocc, nocc, 1);
+      ox.kb_n = naux;
+      ox.s_kb = nao * nocc;
+      int8_t* xs = (int8_t*)(ws + p.xos.planes);
+      int* xe = (int*)(ws + p.xos.ex);
+      DF_LAUNCH(DF_KERNEL_SPLIT, dfk::launch_split_rows(ox, naux * nocc, nslice, xs, xe, c->stream), "split launch");
+      double* kpart = (double*)(ws + p.kpart);
+      const dfk::OutMap OK = dfk::out_plain(kpart, nao, nao, nao);
+      DF_LAUNCH(DF_KERNEL_K_SYRK,
+                dfk::launch_slice_gemm(xs, xe, nao, xs, xe, nao, dfk::kpad64(naux * nocc), nslice, OK, true, p.nsk,
+                                       p.nsk > 1 ? kpart : nullptr, c->stream),
+                "slice product launch");
+      DF_LAUNCH(DF_KERNEL_K_REDUCE, dfk::launch_syrk_reduce(kpart, p.nsk, nao, 1, K, c->stream), "K reduce launch");
+    }
+  }
+  if (nac > 0 && (eri || papa)) {
+    // a6: b^P_{pu} = sum_mu Cp[mu][p] X[P][mu][u]; split rows (P, u) of X_act and rows p of Cp
+    dfk::OpMap oxa = dfk::op_map(Xa, naux * nac, 1, nao, nac);
+    oxa.rl = nac;
+    oxa.s_rh = nao * nac;
+    int8_t* xas = (int8_t*)(ws + p.xas.planes);
+    int* xae = (int*)(ws + p.xas.ex);
+    DF_LAUNCH(DF_KERNEL_SPLIT, dfk::launch_split_rows(oxa, nao, nslice, xas, xae, c->stream), "split launch");
+    auto second = [&](const double* Cl, int64_t nl, const SplitBuf& sb, double* out) -> df_status {
+      int8_t* ls = (int8_t*)(ws + sb.planes);
+      int* le = (int*)(ws + sb.ex);
+      DF_LAUNCH(DF_KERNEL_SPLIT, dfk::launch_split_rows(dfk::op_map(Cl, nl, 1, nao, nl), nao, nslice, ls, le, c->stream),
+                "split launch");
+      dfk::OutMap O = dfk::out_plain(out, nl, naux * nac, nac);
+      O.nl = nac;
+      O.s_nh = nl * nac;
+      DF_LAUNCH(DF_KERNEL_MO_TRANSFORM,
+                dfk::launch_slice_gemm(ls, le, nl, xas, xae, naux * nac, kpo, nslice, O, false, 1, nullptr, c->stream),
+                "slice product launch");
+      return DF_OK;
+    };
+    double* buv = (double*)(ws + p.buv);
+    if (df_status s = second(Cact, nac, p.cas, buv)) return s;
+    const int64_t n2 = nac * nac;
+    int8_t* bvs = (int8_t*)(ws + p.buvs.planes);
+    int* bve = (int*)(ws + p.buvs.ex);
+    DF_LAUNCH(DF_KERNEL_SPLIT, dfk::launch_split_rows(dfk::op_map(buv, n2, 1, naux, n2), naux, nslice, bvs, bve, c->stream),
+              "split launch");
+    const int64_t kpa = dfk::kpad64(naux);
+    // a8: (uv|wx) = sum_P b^P_uv b^P_wx
+    if (eri)
+      DF_LAUNCH(DF_KERNEL_ERI,
+                dfk::launch_slice_gemm(bvs, bve, n2, bvs, bve, n2, kpa, nslice, dfk::out_plain(eri, n2, n2, n2), false,
+                                       1, nullptr, c->stream),
+                "slice product launch");
+    // a7: (pu|vw) = sum_P b^P_pu b^P_vw
+    if (papa && np > 0) {
+      double* bpu = (double*)(ws + p.bpu);
+      if (df_status s = second(Cp, np, p.cps, bpu)) return s;
+      int8_t* bps = (int8_t*)(ws + p.bpus.planes);
+      int* bpe = (int*)(ws + p.bpus.ex);
+      DF_LAUNCH(DF_KERNEL_SPLIT,
+                dfk::launch_split_rows(dfk::op_map(bpu, np * nac, 1, naux, np * nac), naux, nslice, bps, bpe, c->stream),
+                "split launch");
+      DF_LAUNCH(DF_KERNEL_PAPA,
+                dfk::launch_slice_gemm(bps, bpe, np * nac, bvs, bve, n2, kpa, nslice, dfk::out_plain(papa, np * nac, n2, n2),
+                                       false, 1, nullptr, c->stream),
+                "slice product launch");
+    }
   }
   return DF_OK;
 }

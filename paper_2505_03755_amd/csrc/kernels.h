@@ -67,6 +67,9 @@ int64_t gemm_slabs(const OpMap& A);
 hipError_t launch_gemm_split(const OpMap& A, const OpMap& Bm, const OutMap& C, int nsplit, double* part,
                              hipStream_t s);
 
+// C = alpha * sum_s part[s] (+ C), fixed order over s; part is [nsplit][O.M][O.N].
+hipError_t launch_split_reduce(const double* part, int nsplit, const OutMap& O, hipStream_t s);
+
 // C(m, n) = sum_{P < naux} sum_k b^P_{mk} Y(n, (P, k)), Y given as an OpMap whose kb is P and
 // kc the AO index k (kc_n = nao); for every P the entries k in [nao, kpad16(nao)) must exist
 // and be zero.  Split over P ranges with partials [nsplit][nao][N] (half_reduce_splits()).
@@ -105,5 +108,23 @@ hipError_t launch_coulomb(const double* B, int64_t naux, int64_t nao, const doub
 hipError_t launch_fill_zero(double* p, int64_t n, hipStream_t s);
 // p[z*s_z + i] = 0 for z < nz, i < n
 hipError_t launch_fill_zero_strided(double* p, int64_t nz, int64_t s_z, int64_t n, hipStream_t s);
+
+// ---- split precision (split.hip) ----
+// n rounded up to a multiple of the 64-deep int8 contraction step.
+int64_t kpad64(int64_t n);
+// Splits each row r < o.rows of the operand (k over kb_n * kc_n = K) into nslice int8 planes
+// [nslice][rows][kpad64(K)] (zeros past K) and its exponent ex[r].  nslice in [4, 8].
+hipError_t launch_split_rows(const OpMap& o, int64_t K, int nslice, int8_t* planes, int* ex, hipStream_t s);
+// The same for the rows (P, m) of the unpacked b^P (rows naux*nao, K = nao).
+hipError_t launch_split_packed(const double* B, int64_t naux, int64_t nao, int nslice, int8_t* planes, int* ex,
+                               hipStream_t s);
+// C(m, n) = sum_k A(m, k) B(n, k) from the split planes of A [nslice][M][kp] and B [nslice][N][kp]
+// (kp a multiple of 64), written through O (alpha / accumulate honoured) or, with nsplit > 1, as
+// partial sums part[split][M][N] over k ranges.  With tri (M == N) only the 64 x 64 tiles on and
+// below the diagonal are formed.
+hipError_t launch_slice_gemm(const int8_t* A, const int* ea, int64_t M, const int8_t* B, const int* eb, int64_t N,
+                             int64_t kp, int nslice, const OutMap& O, bool tri, int nsplit, double* part,
+                             hipStream_t s);
+int slice_gemm_tile();
 
 }  // namespace dfk

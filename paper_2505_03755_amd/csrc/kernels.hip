@@ -850,6 +850,13 @@ int gemm_splits(int64_t M, int64_t N, int64_t nslab) {
   return balanced_splits(cdiv(M, CfgSq::BM) * cdiv(N, CfgSq::BN), nslab / 4);
 }
 
+hipError_t launch_split_reduce(const double* part, int nsplit, const OutMap& O, hipStream_t s) {
+  const int64_t MN = O.M * O.N;
+  if (MN == 0) return hipSuccess;
+  split_reduce_kernel<<<(unsigned)cdiv(MN, 256), 256, 0, s>>>(part, nsplit, O);
+  return hipGetLastError();
+}
+
 hipError_t launch_gemm_split(const OpMap& A, const OpMap& Bm, const OutMap& O, int nsplit, double* part,
                              hipStream_t s) {
   if (nsplit <= 1) return gemm_launch(A, Bm, O, 1, 1, nullptr, s);

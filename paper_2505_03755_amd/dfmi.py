@@ -28,6 +28,8 @@ DF_OP_ACTIVE_ERI = 3
 DF_OP_PAPA = 4
 DF_OP_STEP = 5
 DF_OP_STEP_BACKWARD = 6
+DF_OP_SPLIT_MATMUL = 7
+DF_OP_STEP_SPLIT = 8
 
 DF_PAPA_FULL = 0x1
 DF_CALLER_X = 0x10
@@ -36,11 +38,12 @@ DF_BWD_GK = 0x40
 DF_BWD_GERI = 0x80
 
 KERNEL_KINDS = ["half_transform", "jvec", "coulomb", "k_syrk", "k_reduce", "mo_transform", "papa", "eri",
-                "other", "adjoint"]
+                "other", "adjoint", "split"]
 
 EXPORTED = ["df_create", "df_destroy", "df_last_error", "df_set_stream", "df_set_workspace",
             "df_set_timing", "df_timing_read", "df_workspace_size", "df_half_transform", "df_jk",
-            "df_active_eri", "df_papa", "df_step", "df_step_backward"]
+            "df_active_eri", "df_papa", "df_step", "df_step_backward", "df_split_matmul",
+            "df_split_cholesky", "df_step_split"]
 
 
 class DFError(RuntimeError):
@@ -53,7 +56,8 @@ class Dims(ctypes.Structure):
     _fields_ = [("naux", ctypes.c_int64), ("nao", ctypes.c_int64), ("ndm", ctypes.c_int64),
                 ("nocc", ctypes.c_int64), ("nac", ctypes.c_int64), ("np", ctypes.c_int64),
                 ("nq", ctypes.c_int64), ("ncol", ctypes.c_int64), ("n2", ctypes.c_int64),
-                ("flags", ctypes.c_int)]
+                ("flags", ctypes.c_int), ("nslice", ctypes.c_int),
+                ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64)]
 
 
 _lib = None
@@ -88,6 +92,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         L.df_papa.argtypes = [vp, dp, i64, i64, dp, i64, dp, i64, dp, i64, dp, i32]
         L.df_step.argtypes = [vp, dp, i64, i64, dp, i64, dp, dp, i64, dp, i64, dp, dp, dp, dp, dp, dp, dp, i32]
         L.df_step_backward.argtypes = [vp, dp, i64, i64, dp, i64, dp, i64, dp, dp, dp, dp, dp, dp, dp, i32]
+        L.df_split_matmul.argtypes = [vp, dp, i64, i64, dp, i64, i64, i64, i32, dp, i64, i32]
+        L.df_split_cholesky.argtypes = [vp, dp, i64, i64, i32, vp, vp, i32]
+        L.df_step_split.argtypes = [vp, dp, vp, vp, i32, i64, i64, dp, i64, dp, i64, dp, i64,
+                                    dp, dp, dp, dp, dp, i32]
         for name in EXPORTED:
             if name != "df_last_error":
                 getattr(L, name).restype = ctypes.c_int
@@ -146,11 +154,16 @@ class Context:
         if st != DF_OK:
             raise DFError(st, self._lib.df_last_error(self._h).decode())
 
-    def prepare(self, op: int, **dims):
-        """Bind the current torch stream and a workspace big enough for `op`."""
+    def bind_stream(self):
+        """Make the library launch on torch's current stream of this device."""
         import torch
         stream = torch.cuda.current_stream(self.device)
         self.check(self._lib.df_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)))
+
+    def prepare(self, op: int, **dims):
+        """Bind the current torch stream and a workspace big enough for `op`."""
+        import torch
+        self.bind_stream()
         need = workspace_size(op, **dims)
         if need and (self._ws is None or self._ws.numel() < need):
             self._ws = None
@@ -344,6 +357,75 @@ def step_backward(B, nao: int, Cocc, Cact, gJ=None, gK=None, geri=None, Xocc=Non
                                         _ptr(gJ), _ptr(gK), _ptr(geri), _ptr(Xocc), _ptr(Xact),
                                         _ptr(dCocc), _ptr(dCact), 0))
     return dCocc, dCact
+
+
+def dev_of(ctx):
+    return ctx.device
+
+
+def kpad64(n: int) -> int:
+    return (n + 63) // 64 * 64
+
+
+def split_matmul(A, B, nslice: int = 7, ctx: Context | None = None):
+    """C = A B^T by the int8 slice method (df_split_matmul); A [M, K], B [N, K] FP64 on the GPU."""
+    import torch
+    ctx = ctx or context(A.device)
+    for n, t in (("A", A), ("B", B)):
+        _check_tensor(n, t, ctx.device)
+    M, K = A.shape
+    N = B.shape[0]
+    if B.shape[1] != K:
+        raise ValueError("A and B need the same number of columns")
+    C = torch.empty((M, N), dtype=torch.float64, device=ctx.device)
+    ctx.prepare(DF_OP_SPLIT_MATMUL, m=M, n=N, k=K, nslice=nslice)
+    ctx.check(ctx._lib.df_split_matmul(ctx.handle, _ptr(A), K, M, _ptr(B), K, N, K, nslice, _ptr(C), N, 0))
+    return C
+
+
+def split_cholesky(B, nao: int, nslice: int = 7, ctx: Context | None = None):
+    """int8 planes [nslice, naux*nao, kpad64(nao)] and exponents [naux*nao] of the unpacked b^P rows."""
+    import torch
+    ctx = ctx or context(B.device)
+    _check_tensor("B", B, ctx.device)
+    naux = _naux_of(B, nao)
+    Bs = torch.empty((nslice, naux * nao, kpad64(nao)), dtype=torch.int8, device=ctx.device)
+    Be = torch.empty((naux * nao,), dtype=torch.int32, device=ctx.device)
+    ctx.bind_stream()
+    ctx.check(ctx._lib.df_split_cholesky(ctx.handle, _ptr(B), naux, nao, nslice, _ptr(Bs), _ptr(Be), 0))
+    return Bs, Be
+
+
+def step_split(B, Bs, Be, nao: int, Cocc, Cact, Cp, outputs=None, ctx: Context | None = None):
+    """df_step in split precision (df_step_split); nslice is taken from Bs."""
+    import torch
+    ctx = ctx or context(B.device)
+    for n, t in (("B", B), ("Cocc", Cocc), ("Cact", Cact), ("Cp", Cp)):
+        _check_tensor(n, t, ctx.device)
+    naux = _naux_of(B, nao)
+    nslice = Bs.shape[0]
+    if (Bs.dtype != torch.int8 or Be.dtype != torch.int32 or tuple(Bs.shape) != (nslice, naux * nao, kpad64(nao))
+            or tuple(Be.shape) != (naux * nao,) or Bs.device != dev_of(ctx) or Be.device != dev_of(ctx)
+            or not Bs.is_contiguous() or not Be.is_contiguous()):
+        raise ValueError("Bs, Be must come from split_cholesky(B, nao) on the same device")
+    nocc, nac, np_ = Cocc.shape[1], Cact.shape[1], Cp.shape[1]
+    dev = ctx.device
+    if outputs is None:
+        outputs = {
+            "J": torch.empty((nao, nao), dtype=torch.float64, device=dev),
+            "K": torch.empty((nao, nao), dtype=torch.float64, device=dev),
+            "v": torch.empty((naux,), dtype=torch.float64, device=dev),
+            "eri": torch.empty((nac,) * 4, dtype=torch.float64, device=dev),
+            "papa": torch.empty((np_, nac, nac, nac), dtype=torch.float64, device=dev),
+        }
+    o = outputs
+    for k in ("J", "K", "v", "eri", "papa"):
+        _check_tensor(k, o.get(k), dev)
+    ctx.prepare(DF_OP_STEP_SPLIT, naux=naux, nao=nao, ndm=1, nocc=nocc, nac=nac, np=np_, nslice=nslice)
+    ctx.check(ctx._lib.df_step_split(ctx.handle, _ptr(B), _ptr(Bs), _ptr(Be), nslice, naux, nao, _ptr(Cocc), nocc,
+                                     _ptr(Cact), nac, _ptr(Cp), np_, _ptr(o.get("J")), _ptr(o.get("K")),
+                                     _ptr(o.get("v")), _ptr(o.get("eri")), _ptr(o.get("papa")), 0))
+    return outputs
 
 
 def _autograd_function():

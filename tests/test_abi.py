@@ -177,3 +177,34 @@ def test_valid_call_without_device_fails_loudly(L, ctx):
     assert st == dfmi.DF_ERR_HIP
     assert b"hipSetDevice" in L.df_last_error(ctx)
     assert L.df_set_workspace(ctx, None, 0) == dfmi.DF_OK
+
+
+def test_split_argument_errors(L, ctx):
+    A, B, C = fake(1 << 30), fake(2 << 30), fake(3 << 30)
+    f = L.df_split_matmul
+    assert f(ctx, A, 8, 4, B, 8, 5, 8, 3, C, 5, 0) == dfmi.DF_ERR_SHAPE          # nslice < 4
+    assert f(ctx, A, 8, 4, B, 8, 5, 8, 9, C, 5, 0) == dfmi.DF_ERR_SHAPE          # nslice > 8
+    assert f(ctx, A, 7, 4, B, 8, 5, 8, 7, C, 5, 0) == dfmi.DF_ERR_ARG            # lda < K
+    assert f(ctx, A, 8, 4, B, 8, 5, 8, 7, C, 4, 0) == dfmi.DF_ERR_ARG            # ldc < N
+    assert f(ctx, A, 8, 4, B, 8, 5, 8, 7, C, 5, 1) == dfmi.DF_ERR_UNSUPPORTED
+    assert f(ctx, A, 8, 4, B, 8, 5, 8, 7, C, 5, 0) == dfmi.DF_ERR_WORKSPACE
+    assert f(ctx, A, 8, 0, B, 8, 5, 8, 7, C, 5, 0) == dfmi.DF_OK                 # empty product
+    Bs, Be = fake(4 << 30), fake(5 << 30)
+    assert L.df_split_cholesky(ctx, B, 10, 7, 7, None, Be, 0) == dfmi.DF_ERR_ARG
+    assert L.df_split_cholesky(ctx, B, 10, 7, 2, Bs, Be, 0) == dfmi.DF_ERR_SHAPE
+    s = L.df_step_split
+    Co, Ca, Cp, J, K = fake(6 << 30), fake(7 << 30), fake(8 << 30), fake(9 << 30), fake(10 << 30)
+    assert s(ctx, B, None, Be, 7, 10, 7, Co, 3, Ca, 2, Cp, 7, J, K, None, None, None, 0) == dfmi.DF_ERR_ARG
+    assert s(ctx, B, Bs, Be, 7, 10, 7, None, 3, Ca, 2, Cp, 7, J, K, None, None, None, 0) == dfmi.DF_ERR_ARG
+    assert s(ctx, B, Bs, Be, 3, 10, 7, Co, 3, Ca, 2, Cp, 7, J, K, None, None, None, 0) == dfmi.DF_ERR_SHAPE
+    assert s(ctx, B, Bs, Be, 7, 10, 7, Co, 3, Ca, 2, Cp, 7, J, K, None, None, None, 0) == dfmi.DF_ERR_WORKSPACE
+
+
+def test_split_workspace_sizes():
+    w = dfmi.workspace_size(dfmi.DF_OP_SPLIT_MATMUL, m=100, n=50, k=70, nslice=7)
+    assert w >= 7 * (100 + 50) * 128 + 4 * 150         # planes padded to 128 columns + exponents
+    s5 = dfmi.workspace_size(dfmi.DF_OP_STEP_SPLIT, naux=20, nao=9, nocc=4, nac=2, np=9, nslice=5)
+    s7 = dfmi.workspace_size(dfmi.DF_OP_STEP_SPLIT, naux=20, nao=9, nocc=4, nac=2, np=9, nslice=7)
+    assert s7 > s5 > 0
+    with pytest.raises(dfmi.DFError):
+        dfmi.workspace_size(dfmi.DF_OP_STEP_SPLIT, naux=20, nao=9, nocc=4, nac=2, np=9, nslice=9)
