@@ -193,9 +193,14 @@ SplitBuf take_split(Plan& pl, int64_t rows, int64_t K, int nslice) {
 }
 
 // Split count for a slice product of `tiles` 64 x 64 tiles and nks 64-deep steps: about two
-// workgroups per CU (one resident per CU), at least 32 steps per split.
+// workgroups per CU (one resident per CU), at least 32 steps per split.  Long contractions
+// are cut further, to at most kSliceSteps steps per split, so that the operand rows of the
+// splits in flight stay within the 256 MB last-level cache.
+constexpr int64_t kSliceSteps = 256;
 int slice_splits(int64_t tiles, int64_t nks) {
   int64_t ns = tiles > 0 ? (512 + tiles - 1) / tiles : 1;
+  const int64_t ns_cache = (nks + kSliceSteps - 1) / kSliceSteps;
+  if (ns < ns_cache) ns = ns_cache;
   if (ns > nks / 32) ns = nks / 32;
   if (ns < 1) ns = 1;
   if (ns > 4096) ns = 4096;

@@ -70,40 +70,77 @@ __device__ __forceinline__ double block_max(double v) {
 }
 
 // Rows of a dense operand given as an OpMap; the contraction index k = kb * kc_n + kc runs over
-// K = kb_n * kc_n.  Thread t visits k = t, t + 256, ...; (kb, kc) are stepped, not divided.
-template <int S>
-__global__ void __launch_bounds__(256) split_rows_kernel(OpMap o, int64_t K, int64_t kp, int8_t* planes, int* ex) {
-  const int64_t r = blockIdx.x;
-  const int t = threadIdx.x;
+// K = kb_n * kc_n.  Work is cut into chunks of kSplitChunk k per workgroup (grid x = chunk,
+// y = row): one pass takes the chunk maxima into the row exponent with an integer atomic max
+// (exponents order like the magnitudes), a second writes the slices, four k per thread as one
+// 32-bit word per plane.
+constexpr int kSplitChunk = 1024;
+constexpr int kNoExponent = -1000;   // rows that are all zero keep this (their slices are 0)
+
+__device__ __forceinline__ const double* opmap_row(const OpMap& o, int64_t r) {
   const int64_t rh = o.s_rh ? r / o.rl : 0, rlo = o.s_rh ? r % o.rl : r;
-  const double* row = o.p + rh * o.s_rh + rlo * o.s_rlo;
-  const int64_t step_kb = 256 / o.kc_n, step_kc = 256 % o.kc_n;
-  double m = 0.0;
-  {
-    int64_t kb = t / o.kc_n, kc = t % o.kc_n;
-    for (int64_t k = t; k < K; k += 256) {
-      m = fmax(m, fabs(row[kb * o.s_kb + kc * o.s_kc]));
-      kb += step_kb;
-      kc += step_kc;
-      if (kc >= o.kc_n) {
-        kc -= o.kc_n;
-        ++kb;
-      }
-    }
-  }
-  const int e = row_exponent(block_max(m));
-  if (t == 0) ex[r] = e;
-  const int64_t plane = o.rows * kp;
-  int64_t kb = t / o.kc_n, kc = t % o.kc_n;
-  for (int64_t k = t; k < kp; k += 256) {
-    const double x = k < K ? row[kb * o.s_kb + kc * o.s_kc] : 0.0;
-    write_slices<S>(x, e, planes, plane, r * kp + k);
-    kb += step_kb;
-    kc += step_kc;
-    if (kc >= o.kc_n) {
-      kc -= o.kc_n;
+  return o.p + rh * o.s_rh + rlo * o.s_rlo;
+}
+
+// Walks k = (kb, kc) of one row in steps of `step` without dividing per element.
+struct KWalk {
+  int64_t kb, kc, db, dc, kc_n;
+  __device__ __forceinline__ KWalk(const OpMap& o, int64_t k, int64_t step)
+      : kb(k / o.kc_n), kc(k % o.kc_n), db(step / o.kc_n), dc(step % o.kc_n), kc_n(o.kc_n) {}
+  __device__ __forceinline__ int64_t off(const OpMap& o) const { return kb * o.s_kb + kc * o.s_kc; }
+  __device__ __forceinline__ void next() {
+    kb += db;
+    kc += dc;
+    if (kc >= kc_n) {
+      kc -= kc_n;
       ++kb;
     }
+  }
+};
+
+__global__ void __launch_bounds__(256) fill_int_kernel(int* p, int64_t n, int v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void __launch_bounds__(256) split_max_kernel(OpMap o, int64_t K, int64_t r0, int* ex) {
+  const int64_t r = r0 + blockIdx.y, k0 = (int64_t)blockIdx.x * kSplitChunk;
+  const double* row = opmap_row(o, r);
+  double m = 0.0;
+  KWalk w(o, k0 + threadIdx.x, 256);
+  for (int64_t k = k0 + threadIdx.x; k < K && k < k0 + kSplitChunk; k += 256) {
+    m = fmax(m, fabs(row[w.off(o)]));
+    w.next();
+  }
+  m = block_max(m);
+  if (threadIdx.x == 0 && m > 0.0) atomicMax(ex + r, row_exponent(m));
+}
+
+template <int S>
+__global__ void __launch_bounds__(256) split_slice_kernel(OpMap o, int64_t K, int64_t kp, int64_t r0, int8_t* planes,
+                                                          const int* ex) {
+  const int64_t r = r0 + blockIdx.y, k = (int64_t)blockIdx.x * kSplitChunk + 4 * threadIdx.x;
+  if (k >= kp) return;
+  const double* row = opmap_row(o, r);
+  const int e = ex[r];
+  const int64_t plane = o.rows * kp;
+  double x[4];
+  KWalk w(o, k < K ? k : 0, 1);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    x[q] = k + q < K ? ldexp(row[w.off(o)], kSplitBits0 - e) : 0.0;
+    w.next();
+  }
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    uint32_t w = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double a = rint(x[q]);
+      w |= ((uint32_t)(int)a & 0xffu) << (8 * q);
+      x[q] = (x[q] - a) * (double)(1 << kSplitBits);
+    }
+    *(uint32_t*)(planes + s * plane + r * kp + k) = w;
   }
 }
 
@@ -128,11 +165,13 @@ __global__ void __launch_bounds__(256) split_packed_kernel(const double* __restr
 }
 
 // ---------------------------------------------------------------------------------------
-// Slice product.  Workgroup tile 64 x 64 (2 x 2 waves of 32 x 32), k steps of 64 bytes, one LDS
-// stage refilled from registers between two barriers; the global loads of the next step are in
-// flight while the current one is multiplied.  With `tri`, only tiles I >= J of a square output
-// are formed (the lower half of a symmetric product).
+// Slice product.  Workgroup tile 64 x 64 over 8 waves (2 x 4) of 32 x 16 (two MFMA tiles), k steps
+// of 64 bytes through one LDS stage refilled from registers between two barriers; the global
+// loads of the next step are in flight while the current one is multiplied.  About 200
+// registers per lane: two waves per SIMD, accumulators in VGPRs.  With `tri`, only tiles
+// I >= J of a square output are formed (the lower half of a symmetric product).
 constexpr int kTM = 64, kKB = 64, kRow = 80;   // LDS row pitch 80 bytes: conflict-free operand reads
+constexpr int kFlushSteps = 512;               // 32768 k per int32 accumulation
 
 template <int S>
 struct I8Tile {
@@ -140,14 +179,14 @@ struct I8Tile {
 };
 
 template <int S, bool GEN>
-__global__ void __launch_bounds__(256) slice_gemm_kernel(const int8_t* __restrict__ Ap, const int* __restrict__ ea,
+__global__ void __launch_bounds__(512) slice_gemm_kernel(const int8_t* __restrict__ Ap, const int* __restrict__ ea,
                                                          int64_t M, const int8_t* __restrict__ Bp,
                                                          const int* __restrict__ eb, int64_t N, int64_t kp,
                                                          OutMap O, int64_t tilesM, int64_t tilesN, int tri,
                                                          int64_t ntri, double* part) {
   __shared__ __attribute__((aligned(16))) int8_t lds[I8Tile<S>::LDS];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
+  const int wm = wave & 1, wn = wave >> 1;      // rows 32 wm.., columns 16 wn..
   const int nsplit = gridDim.y, split = blockIdx.y;
   int64_t I, J;
   if (tri) {
@@ -157,124 +196,110 @@ __global__ void __launch_bounds__(256) slice_gemm_kernel(const int8_t* __restric
     while ((I + 1) * (I + 2) / 2 <= pr) ++I;
     J = pr - I * (I + 1) / 2;
   } else {
+    // column tiles of one row block side by side (on one XCD): the row block is read once
     const int64_t tile = xcd_remap_i8(blockIdx.x, tilesM * tilesN);
-    I = tile % tilesM;
-    J = tile / tilesM;
+    I = tile / tilesN;
+    J = tile % tilesN;
   }
   const int64_t m0 = I * kTM, n0 = J * kTM;
   const int64_t nks = kp / kKB;
   const int64_t ks0 = nks * split / nsplit, ks1 = nks * (split + 1) / nsplit;
 
-  // global -> register staging: thread t loads 16 bytes of row t / 4, chunk t % 4, every slice
-  const int lr = t >> 2, lc = (t & 3) * 16;
-  const int64_t ra = m0 + lr < M ? m0 + lr : M - 1, rb = n0 + lr < N ? n0 + lr : N - 1;
-  const int64_t planeA = M * kp, planeB = N * kp;
-  const int8_t* ga = Ap + ra * kp + lc;
-  const int8_t* gb = Bp + rb * kp + lc;
-  v4i sa[S], sb[S];
-  auto gload = [&](int64_t ks) {
+  // global -> register staging: threads 0..255 load A, 256..511 load B: 16 bytes of row
+  // (t % 256) / 4, chunk t % 4, of every slice
+  const int side = t >> 8, lr = (t & 255) >> 2, lc = (t & 3) * 16;
+  const int64_t rows = side ? N : M, r0 = side ? n0 : m0;
+  const int64_t rr = r0 + lr < rows ? r0 + lr : rows - 1;
+  const int64_t plane = rows * kp;
+  const int8_t* g = (side ? Bp : Ap) + rr * kp + lc;
+  int8_t* lw = lds + (side * S * kTM + lr) * kRow + lc;
+  // two register stages: the loads of step k + 2 go out while step k + 1 is still in flight
+  v4i st[2][S];
+  auto gload = [&](int b, int64_t ks) {
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      sa[s] = *(const v4i*)(ga + s * planeA + ks * kKB);
-      sb[s] = *(const v4i*)(gb + s * planeB + ks * kKB);
-    }
+    for (int s = 0; s < S; ++s) st[b][s] = *(const v4i*)(g + s * plane + ks * kKB);
   };
-  auto lstore = [&]() {
+  auto lstore = [&](int b) {
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      *(v4i*)(lds + (s * kTM + lr) * kRow + lc) = sa[s];
-      *(v4i*)(lds + ((S + s) * kTM + lr) * kRow + lc) = sb[s];
-    }
+    for (int s = 0; s < S; ++s) *(v4i*)(lw + s * kTM * kRow) = st[b][s];
   };
 
-  v4i acc[S][2][2];
-  double F[2][2][4];
-#pragma unroll
-  for (int d = 0; d < S; ++d)
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) acc[d][i][j] = v4i{0, 0, 0, 0};
+  v4i acc[S][2];
+  double F[2][4];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) F[i][j][r] = 0.0;
+    for (int r = 0; r < 4; ++r) F[i][r] = 0.0;
 
-  auto flush = [&]() {
+  // operand fragment reads: row / column (lane % 16) of a 16-row tile, bytes 16 (lane / 16)
+  const int fr = lane & 15, fk = (lane >> 4) * 16;
+  const int8_t* la = lds + (wm * 32 + fr) * kRow + fk;
+  const int8_t* lb = lds + (S * kTM + wn * 16 + fr) * kRow + fk;
+  // one k step: registers of stage b to LDS, refill stage b with step ks + 2, multiply
+  auto step = [&](int b, int64_t ks) {
+    __syncthreads();   // the previous step's reads of LDS are done
+    lstore(b);
+    __syncthreads();
+    if (ks + 2 < ks1) gload(b, ks + 2);
+    v4i fb[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) fb[s] = *(const v4i*)(lb + s * kTM * kRow);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      v4i fa[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) fa[s] = *(const v4i*)(la + (s * kTM + i * 16) * kRow);
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int u = 0; u + s < S; ++u)
+          acc[s + u][i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[s], fb[u], acc[s + u][i], 0, 0, 0);
+    }
+  };
+  if (ks1 > ks0) gload(0, ks0);
+  if (ks1 > ks0 + 1) gload(1, ks0 + 1);
+  for (int64_t kc = ks0; kc < ks1; kc += kFlushSteps) {   // chunks start at even offsets from ks0
+    const int64_t kend = kc + kFlushSteps < ks1 ? kc + kFlushSteps : ks1;
+#pragma unroll
+    for (int d = 0; d < S; ++d)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) acc[d][i] = v4i{0, 0, 0, 0};
+    for (int64_t ks = kc; ks < kend; ks += 2) {
+      step(0, ks);
+      if (ks + 1 < kend) step(1, ks + 1);
+    }
+    // int32 sums of this chunk into FP64
 #pragma unroll
     for (int d = 0; d < S; ++d)
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) F[i][j][r] += ldexp((double)acc[d][i][j][r], -kSplitBits * d);
-          acc[d][i][j] = v4i{0, 0, 0, 0};
-        }
-  };
-
-  // operand fragment reads: row / column (lane % 16) of the wave's 16-row tile, bytes 16 (lane / 16)
-  const int fr = lane & 15, fk = (lane >> 4) * 16;
-  int64_t since_flush = 0;
-  if (ks1 > ks0) gload(ks0);
-  for (int64_t ks = ks0; ks < ks1; ++ks) {
-    __syncthreads();   // the previous step's reads of LDS are done
-    lstore();
-    __syncthreads();
-    if (ks + 1 < ks1) gload(ks + 1);
-    v4i fa[S][2];
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-#pragma unroll
-      for (int i = 0; i < 2; ++i) fa[s][i] = *(const v4i*)(lds + (s * kTM + wm * 32 + i * 16 + fr) * kRow + fk);
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      v4i fb[S];
-#pragma unroll
-      for (int s = 0; s < S; ++s) fb[s] = *(const v4i*)(lds + ((S + s) * kTM + wn * 32 + j * 16 + fr) * kRow + fk);
-#pragma unroll
-      for (int s = 0; s < S; ++s)
-#pragma unroll
-        for (int u = 0; u + s < S; ++u)
-#pragma unroll
-          for (int i = 0; i < 2; ++i)
-            acc[s + u][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[s][i], fb[u], acc[s + u][i][j], 0, 0, 0);
-    }
-    if (++since_flush == 512) {   // 32768 k: int32 stays exact
-      flush();
-      since_flush = 0;
-    }
+        for (int r = 0; r < 4; ++r) F[i][r] += ldexp((double)acc[d][i][r], -kSplitBits * d);
   }
-  flush();
 
   // epilogue: value = 2^(ea + eb - 12) F
-  const int64_t rowbase = m0 + wm * 32, colbase = n0 + wn * 32;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t m = rowbase + i * 16 + (lane >> 4) * 4 + r;
-        const int64_t n = colbase + j * 16 + (lane & 15);
-        if (m >= M || n >= N) continue;
-        const double val = ldexp(F[i][j][r], ea[m] + eb[n] - 2 * kSplitBits0);
-        if (part) {
-          part[((int64_t)split * M + m) * N + n] = val;
+    for (int r = 0; r < 4; ++r) {
+      const int64_t m = m0 + wm * 32 + i * 16 + (lane >> 4) * 4 + r;
+      const int64_t n = n0 + wn * 16 + (lane & 15);
+      if (m >= M || n >= N) continue;
+      const double val = ldexp(F[i][r], ea[m] + eb[n] - 2 * kSplitBits0);
+      if (part) {
+        part[((int64_t)split * M + m) * N + n] = val;
+      } else {
+        double* dst;
+        if (n < O.nsplit) {
+          const int64_t nh = O.s_nh ? n / O.nl : 0, mh = O.s_mh ? m / O.ml : 0;
+          dst = O.p + (mh * O.s_mh + (m - mh * O.ml) * O.s_ml) + (nh * O.s_nh + (n - nh * O.nl) * O.s_nl);
         } else {
-          double* dst;
-          if (n < O.nsplit) {
-            const int64_t nh = O.s_nh ? n / O.nl : 0, mh = O.s_mh ? m / O.ml : 0;
-            dst = O.p + (mh * O.s_mh + (m - mh * O.ml) * O.s_ml) + (nh * O.s_nh + (n - nh * O.nl) * O.s_nl);
-          } else {
-            dst = O.p2 + m * O.s2_m + (n - O.nsplit);
-          }
-          if (GEN) *dst = O.accumulate ? *dst + O.alpha * val : O.alpha * val;
-          else *dst = val;
+          dst = O.p2 + m * O.s2_m + (n - O.nsplit);
         }
+        if (GEN) *dst = O.accumulate ? *dst + O.alpha * val : O.alpha * val;
+        else *dst = val;
       }
+    }
 }
 
 }  // namespace
@@ -283,13 +308,24 @@ int64_t kpad64(int64_t n) { return (n + 63) / 64 * 64; }
 
 template <int S>
 static hipError_t split_rows_s(const OpMap& o, int64_t K, int8_t* planes, int* ex, hipStream_t s) {
-  split_rows_kernel<S><<<(unsigned)o.rows, 256, 0, s>>>(o, K, kpad64(K), planes, ex);
+  const int64_t kp = kpad64(K);
+  fill_int_kernel<<<(unsigned)((o.rows + 255) / 256), 256, 0, s>>>(ex, o.rows, kNoExponent);
+  for (int64_t r0 = 0; r0 < o.rows; r0 += 65535) {   // grid y carries the row
+    const unsigned nr = (unsigned)(o.rows - r0 < 65535 ? o.rows - r0 : 65535);
+    split_max_kernel<<<dim3((unsigned)((K + kSplitChunk - 1) / kSplitChunk), nr), 256, 0, s>>>(o, K, r0, ex);
+  }
+  for (int64_t r0 = 0; r0 < o.rows; r0 += 65535) {
+    const unsigned nr = (unsigned)(o.rows - r0 < 65535 ? o.rows - r0 : 65535);
+    split_slice_kernel<S><<<dim3((unsigned)((kp + kSplitChunk - 1) / kSplitChunk), nr), 256, 0, s>>>(o, K, kp, r0,
+                                                                                                      planes, ex);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_split_rows(const OpMap& o, int64_t K, int nslice, int8_t* planes, int* ex, hipStream_t s) {
   if (o.rows <= 0) return hipSuccess;
-  if (o.rows > 0x7fffffffLL || K <= 0) return hipErrorInvalidValue;
+  if (o.rows > 0x7fffffffLL || K <= 0 || (kpad64(K) + kSplitChunk - 1) / kSplitChunk > 0x7fffffffLL)
+    return hipErrorInvalidValue;
   switch (nslice) {
     case 4: return split_rows_s<4>(o, K, planes, ex, s);
     case 5: return split_rows_s<5>(o, K, planes, ex, s);
@@ -330,8 +366,8 @@ static void slice_gemm_s(const int8_t* A, const int* ea, int64_t M, const int8_t
   const int64_t ntri = tm * (tm + 1) / 2;
   const dim3 grid((unsigned)(tri ? ntri : tm * tn), (unsigned)nsplit, 1);
   const bool gen = !part && (O.alpha != 1.0 || O.accumulate);
-  if (gen) slice_gemm_kernel<S, true><<<grid, 256, 0, s>>>(A, ea, M, B, eb, N, kp, O, tm, tn, tri, ntri, part);
-  else slice_gemm_kernel<S, false><<<grid, 256, 0, s>>>(A, ea, M, B, eb, N, kp, O, tm, tn, tri, ntri, part);
+  if (gen) slice_gemm_kernel<S, true><<<grid, 512, 0, s>>>(A, ea, M, B, eb, N, kp, O, tm, tn, tri, ntri, part);
+  else slice_gemm_kernel<S, false><<<grid, 512, 0, s>>>(A, ea, M, B, eb, N, kp, O, tm, tn, tri, ntri, part);
 }
 
 hipError_t launch_slice_gemm(const int8_t* A, const int* ea, int64_t M, const int8_t* B, const int* eb, int64_t N,
