@@ -154,6 +154,47 @@ def cpu_baseline(wl, rows, seed, adjoint=True):
                       f"({what}; rate in algorithmic FP64 FLOP/s of that sample); {dt:.2f} s"}
 
 
+def split_comparison(B, nao, Cocc, Cact, C, nslice, reps, ctx):
+    """Forward step in FP64 (df_step) and in split precision (df_step_split, nslice int8 slices),
+    timed alone with HIP events on the library's stream, and the model energy from both."""
+    import math
+    import torch
+    from paper_2505_03755_amd import dfmi, synth
+    dev = B.device
+    nac = Cact.shape[1]
+    Bs, Be = dfmi.split_cholesky(B, nao, nslice=nslice, ctx=ctx)     # once per B, not timed
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn):
+        out = fn(None)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record(stream)
+        for i in range(reps):
+            fn(out)
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        ms = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(reps))
+        return out, ms[len(ms) // 2]
+
+    ref, ms64 = timed(lambda o: dfmi.step(B, nao, Cocc, Cact, C, outputs=o, ctx=ctx))
+    spl, mss = timed(lambda o: dfmi.step_split(B, Bs, Be, nao, Cocc, Cact, C, outputs=o, ctx=ctx))
+    del Bs, Be
+    h = torch.from_numpy(synth.symmetric_matrix(nao)).to(dev)
+    Gam = torch.from_numpy(synth.two_body_density(nac)).to(dev)
+    D = Cocc @ Cocc.T
+
+    def energy(o):
+        return math.fsum([(D * h).sum().item(), 0.5 * (D * o["J"]).sum().item(),
+                          -0.25 * (D * o["K"]).sum().item(), 0.5 * (o["eri"] * Gam).sum().item()])
+
+    e64, es = energy(ref), energy(spl)
+    rel = {k: ((spl[k] - ref[k]).norm() / ref[k].norm()).item() for k in ("J", "K", "v", "eri", "papa")}
+    return {"nslice": nslice, "forward_ms_fp64": ms64, "forward_ms_split": mss, "speedup": ms64 / mss,
+            "E_fp64": e64, "dE_split_minus_fp64": es - e64, "dE_bar": 1e-8, "meets_bar": abs(es - e64) <= 1e-8,
+            "rel_diff": rel}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +204,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=24, help="auxiliary rows in the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forward-only", action="store_true", help="time df_step alone (no adjoint)")
+    ap.add_argument("--no-split", action="store_true", help="skip the split-precision comparison")
+    ap.add_argument("--split-slices", type=int, default=7)
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="copy this many MiB device-to-device once before the steps (a known-size "
                          "reference for the HBM byte counters of a profiling run)")
@@ -286,6 +329,12 @@ def main():
         "roofline": roof,
         "kernels": kernels,
     }
+    if not args.no_split:
+        log(f"[bench] split precision ({args.split_slices} slices) against FP64, forward step")
+        for k in ("Xocc", "Xact"):
+            out.pop(k, None)
+        torch.cuda.empty_cache()
+        res["split_precision"] = split_comparison(B, nao, Cocc, Cact, C, args.split_slices, 5, ctx)
     del B
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
