@@ -225,6 +225,36 @@ df_status df_step_backward(df_ctx* ctx, const double* B, int64_t naux, int64_t n
                            double* dCocc, double* dCact, int flags);
 
 /*
+ * Batched fragment subproblems (the embedding-space problems of the fragment CASSCFs, Sec.
+ * "Calculation of effective potentials"): problem i has its own packed B, N_ao, N_aux and ndm
+ * densities D_k = C_k C_k^T (unit weights), and asks for
+ *   J[k], K[k] as in df_jk, (uv|wx) as in df_active_eri, and the full (pu|qv) of Eq. (papa)
+ *   with p, q over the columns of Cp (as df_papa with DF_PAPA_FULL and Cq = Cp).
+ * The half transforms of all problems ([C_1 .. C_ndm | Cact] against b^P) run as one grouped
+ * launch, and so do the K tiles; problems are ordered largest first inside each launch.
+ * Any output may be NULL.  Inputs and outputs of all problems must not overlap each other.
+ */
+typedef struct df_problem {
+  const double* B;      /* [naux][npair] packed Cholesky vectors */
+  int64_t naux, nao;
+  int64_t ndm;          /* densities (>= 1) */
+  const double* Cocc;   /* [ndm][nao][nocc] */
+  int64_t nocc;
+  const double* Cact;   /* [nao][nac] */
+  int64_t nac;
+  const double* Cp;     /* [nao][np] */
+  int64_t np;
+  double* J;            /* [ndm][nao][nao] */
+  double* K;            /* [ndm][nao][nao] */
+  double* eri;          /* [nac][nac][nac][nac] */
+  double* papa;         /* [np][nac][np][nac] */
+} df_problem;
+
+/* Workspace bytes for df_batched_step on these problems. */
+df_status df_batched_workspace_size(const df_problem* probs, int nprob, size_t* bytes);
+df_status df_batched_step(df_ctx* ctx, const df_problem* probs, int nprob, int flags);
+
+/*
  * Split precision on the int8 matrix cores.  An FP64 row x is cut into nslice int8 slices,
  *   x[k] ~= 2^e sum_{s < nslice} a_s[k] 2^-(6 + 7 s),   a_s in [-64, 64],  max|x| < 2^e,
  * exactly up to a residual below 2^(e - 7 nslice); a product keeps the slice pairs with

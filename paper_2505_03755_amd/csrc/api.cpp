@@ -251,6 +251,33 @@ StepSplitPlan plan_step_split(Plan& pl, int64_t naux, int64_t nao, int64_t nocc,
   return p;
 }
 
+// ---- batched problems ----
+struct BatchedPiece {
+  size_t cpad, x, v, kpart, buv, bpu;
+  int nsplit;
+};
+int64_t batched_ncol(const df_problem& q) { return q.ndm * q.nocc + q.nac; }
+// half-transform work of a problem, for the largest-first order
+int64_t batched_work(const df_problem& q) { return q.naux * q.nao * q.nao * batched_ncol(q); }
+
+std::vector<BatchedPiece> plan_batched(Plan& pl, const df_problem* probs, int n) {
+  std::vector<BatchedPiece> v((size_t)n);
+  for (int i = 0; i < n; ++i) {
+    const df_problem& q = probs[i];
+    BatchedPiece& b = v[(size_t)i];
+    const int64_t ncol = batched_ncol(q);
+    const bool need_x = ncol > 0 && (q.J || q.K || q.eri || q.papa);
+    b.cpad = pl.take(need_x ? dfk::kpad16(q.nao) * ncol : 0);
+    b.x = pl.take(need_x ? q.naux * q.nao * ncol : 0);
+    b.v = pl.take(q.J && q.nocc > 0 ? q.ndm * q.naux : 0);
+    b.nsplit = dfk::syrk_splits(q.nao, q.naux, q.ndm);
+    b.kpart = pl.take(q.K && q.nocc > 0 ? (int64_t)b.nsplit * q.ndm * q.nao * q.nao : 0);
+    b.buv = pl.take(q.eri && q.nac > 0 ? q.naux * q.nac * q.nac : 0);
+    b.bpu = pl.take(q.papa && q.nac > 0 && q.np > 0 ? q.naux * q.np * q.nac : 0);
+  }
+  return v;
+}
+
 df_status check_ctx(df_ctx* c) {
   if (!c) return DF_ERR_ARG;
   c->err.clear();
@@ -417,6 +444,26 @@ df_status run_mo_pmajor(df_ctx* c, const double* C2, int64_t n2, const double* X
     Bp.p = X + p0 * nao * ncol;
     dfk::OutMap Op = O;
     Op.p = Y + p0 * n2 * ncol;
+    DF_LAUNCH(DF_KERNEL_MO_TRANSFORM, dfk::launch_gemm(A, Bp, Op, np_, c->stream), "second transform launch");
+  }
+  return DF_OK;
+}
+
+// Y[P][p][u] = sum_mu C2[mu][p] X[P][mu][off + u], u < nu  (X P-major with row stride ldx), batched over P
+df_status run_mo_cols(df_ctx* c, const double* C2, int64_t n2, const double* X, int64_t naux, int64_t nao, int64_t ldx,
+                      int64_t off, int64_t nu, double* Y) {
+  if (n2 == 0 || nu == 0) return DF_OK;
+  const dfk::OpMap A = dfk::op_map(C2, n2, 1, nao, n2);
+  dfk::OpMap Bm = dfk::op_map(X + off, nu, 1, nao, ldx);
+  Bm.s_z = nao * ldx;
+  dfk::OutMap O = dfk::out_plain(Y, n2, nu, nu);
+  O.s_z = n2 * nu;
+  for (int64_t p0 = 0; p0 < naux; p0 += 65535) {
+    const int64_t np_ = std::min<int64_t>(65535, naux - p0);
+    dfk::OpMap Bp = Bm;
+    Bp.p = X + off + p0 * nao * ldx;
+    dfk::OutMap Op = O;
+    Op.p = Y + p0 * n2 * nu;
     DF_LAUNCH(DF_KERNEL_MO_TRANSFORM, dfk::launch_gemm(A, Bp, Op, np_, c->stream), "second transform launch");
   }
   return DF_OK;
@@ -1116,6 +1163,128 @@ df_status df_step_split(df_ctx* ctx, const double* B, const int8_t* Bs, const in
                 dfk::launch_slice_gemm(bps, bpe, np * nac, bvs, bve, n2, kpa, nslice, dfk::out_plain(papa, np * nac, n2, n2),
                                        false, 1, nullptr, c->stream),
                 "slice product launch");
+    }
+  }
+  return DF_OK;
+}
+
+df_status df_batched_workspace_size(const df_problem* probs, int nprob, size_t* bytes) {
+  if (!bytes || nprob < 0 || (nprob > 0 && !probs)) return DF_ERR_ARG;
+  *bytes = 0;
+  for (int i = 0; i < nprob; ++i) {
+    const df_problem& q = probs[i];
+    if (q.naux < 1 || q.nao < 1 || q.nao > kMaxNao || q.ndm < 1 || q.nocc < 0 || q.nac < 0 || q.np < 0)
+      return DF_ERR_SHAPE;
+  }
+  Plan pl;
+  plan_batched(pl, probs, nprob);
+  *bytes = pl.total;
+  return DF_OK;
+}
+
+df_status df_batched_step(df_ctx* ctx, const df_problem* probs, int nprob, int flags) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_batched_step takes no flags");
+  if (nprob < 0 || (nprob > 0 && !probs)) return fail(c, DF_ERR_ARG, "probs is NULL");
+  std::vector<Range> rs;
+  for (int i = 0; i < nprob; ++i) {
+    const df_problem& q = probs[i];
+    const std::string tag = "problem " + std::to_string(i) + " ";
+    if (df_status s = check_core(c, q.B, q.naux, q.nao)) return s;
+    if (q.ndm < 1 || q.nocc < 0 || q.nac < 0 || q.np < 0) return fail(c, DF_ERR_SHAPE, tag + "has a bad size");
+    if (q.nocc > 0 && (q.J || q.K) && !q.Cocc) return fail(c, DF_ERR_ARG, tag + "Cocc is NULL");
+    if (q.nac > 0 && (q.eri || q.papa) && !q.Cact) return fail(c, DF_ERR_ARG, tag + "Cact is NULL");
+    if (q.np > 0 && q.papa && !q.Cp) return fail(c, DF_ERR_ARG, tag + "Cp is NULL");
+    const int64_t npair = q.nao * (q.nao + 1) / 2;
+    rs.push_back({q.B, dbytes(q.naux * npair), "B", false});
+    rs.push_back({q.Cocc, dbytes(q.ndm * q.nao * q.nocc), "Cocc", false});
+    rs.push_back({q.Cact, dbytes(q.nao * q.nac), "Cact", false});
+    rs.push_back({q.Cp, dbytes(q.nao * q.np), "Cp", false});
+    rs.push_back({q.J, dbytes(q.ndm * q.nao * q.nao), "J", true});
+    rs.push_back({q.K, dbytes(q.ndm * q.nao * q.nao), "K", true});
+    rs.push_back({q.eri, dbytes(q.nac * q.nac * q.nac * q.nac), "eri", true});
+    rs.push_back({q.papa, dbytes(q.np * q.nac * q.np * q.nac), "papa", true});
+  }
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  Plan pl;
+  const std::vector<BatchedPiece> pc = plan_batched(pl, probs, nprob);
+  if (df_status s = need_ws(c, pl.total)) return s;
+  if (pl.total) rs.push_back({c->ws, pl.total, "workspace", true});
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (nprob == 0) return DF_OK;
+  if (df_status s = enter(c)) return s;
+  char* ws = c->ws;
+  // largest first
+  std::vector<int> order((size_t)nprob);
+  for (int i = 0; i < nprob; ++i) order[(size_t)i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return batched_work(probs[a]) > batched_work(probs[b]); });
+  // zero outputs of problems without occupied columns
+  for (int i : order) {
+    const df_problem& q = probs[i];
+    if (q.nocc == 0) {
+      if (q.J) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(q.J, q.ndm * q.nao * q.nao, c->stream), "fill");
+      if (q.K) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(q.K, q.ndm * q.nao * q.nao, c->stream), "fill");
+    }
+  }
+  // padded operands [C_1 .. C_ndm | Cact], then the grouped half transforms
+  std::vector<dfk::GroupHalf> gh;
+  std::vector<dfk::GroupSyrk> gs;
+  for (int i : order) {
+    const df_problem& q = probs[i];
+    const BatchedPiece& b = pc[(size_t)i];
+    const int64_t ncol = batched_ncol(q);
+    if (ncol == 0 || !(q.J || q.K || q.eri || q.papa)) continue;
+    double* cp = (double*)(ws + b.cpad);
+    std::vector<ColBlock> blks;
+    for (int64_t z = 0; z < q.ndm; ++z) blks.push_back({q.Cocc + z * q.nao * q.nocc, q.nocc, q.nocc, z * q.nocc});
+    blks.push_back({q.Cact, q.nac, q.nac, q.ndm * q.nocc});
+    if (df_status s = pad_operand(c, cp, q.nao, ncol, blks.data(), (int)blks.size())) return s;
+    double* X = (double*)(ws + b.x);
+    gh.push_back({q.B, q.naux, q.nao, cp, ncol, ncol, out_pmajor(X, q.naux, q.nao, ncol, ncol)});
+    if (q.K && q.nocc > 0) {
+      dfk::OpMap A = dfk::op_map(X, q.nao, ncol, q.nocc, 1);
+      A.kb_n = q.naux;
+      A.s_kb = q.nao * ncol;
+      A.s_z = q.nocc;
+      gs.push_back({A, q.nao, q.ndm, b.nsplit, (double*)(ws + b.kpart)});
+    }
+  }
+  for (size_t g0 = 0; g0 < gh.size(); g0 += 8) {
+    const int n = (int)std::min<size_t>(8, gh.size() - g0);
+    DF_LAUNCH(DF_KERNEL_HALF_TRANSFORM, dfk::launch_half_group(gh.data() + g0, n, c->stream), "grouped half transform");
+  }
+  for (size_t g0 = 0; g0 < gs.size(); g0 += 8) {
+    const int n = (int)std::min<size_t>(8, gs.size() - g0);
+    DF_LAUNCH(DF_KERNEL_K_SYRK, dfk::launch_syrk_group(gs.data() + g0, n, c->stream), "grouped K tiles");
+  }
+  // per problem: K reduction, J-vectors and J, active-space blocks
+  for (int i : order) {
+    const df_problem& q = probs[i];
+    const BatchedPiece& b = pc[(size_t)i];
+    const int64_t ncol = batched_ncol(q);
+    if (ncol == 0 || !(q.J || q.K || q.eri || q.papa)) continue;
+    const double* X = (const double*)(ws + b.x);
+    if (q.K && q.nocc > 0)
+      DF_LAUNCH(DF_KERNEL_K_REDUCE, dfk::launch_syrk_reduce((double*)(ws + b.kpart), b.nsplit, q.nao, q.ndm, q.K, c->stream),
+                "K reduce launch");
+    if (q.J && q.nocc > 0) {
+      double* v = (double*)(ws + b.v);
+      DF_LAUNCH(DF_KERNEL_JVEC, dfk::launch_jvec(X, q.naux, q.nao, ncol, q.Cocc, nullptr, q.nocc, q.ndm, v, c->stream),
+                "J-vector launch");
+      DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_coulomb(q.B, q.naux, q.nao, v, q.ndm, q.J, c->stream), "Coulomb launch");
+    }
+    const int64_t off = q.ndm * q.nocc;
+    if (q.eri && q.nac > 0) {
+      double* buv = (double*)(ws + b.buv);
+      if (df_status s = run_mo_cols(c, q.Cact, q.nac, X, q.naux, q.nao, ncol, off, q.nac, buv)) return s;
+      if (df_status s = run_pgemm(c, DF_KERNEL_ERI, buv, q.nac * q.nac, buv, q.nac * q.nac, q.naux, q.eri)) return s;
+    }
+    if (q.papa && q.nac > 0 && q.np > 0) {
+      double* bpu = (double*)(ws + b.bpu);
+      if (df_status s = run_mo_cols(c, q.Cp, q.np, X, q.naux, q.nao, ncol, off, q.nac, bpu)) return s;
+      if (df_status s = run_pgemm(c, DF_KERNEL_PAPA, bpu, q.np * q.nac, bpu, q.np * q.nac, q.naux, q.papa)) return s;
     }
   }
   return DF_OK;

@@ -109,6 +109,25 @@ hipError_t launch_fill_zero(double* p, int64_t n, hipStream_t s);
 // p[z*s_z + i] = 0 for z < nz, i < n
 hipError_t launch_fill_zero_strided(double* p, int64_t nz, int64_t s_z, int64_t n, hipStream_t s);
 
+// ---- grouped launches over several problems (at most 8 per launch, largest first) ----
+// Half transform of problem p: as launch_half_transform with (B, naux, nao, C, ldc, ncol, out).
+struct GroupHalf {
+  const double* B;
+  int64_t naux, nao;
+  const double* C;   // kpad16(nao) rows, zero past nao
+  int64_t ldc, ncol;
+  OutMap out;
+};
+hipError_t launch_half_group(const GroupHalf* probs, int n, hipStream_t s);
+// Lower-tile SYRK partials of problem p: as launch_syrk_partial with (A, A, n, nz, nsplit, Kpart).
+struct GroupSyrk {
+  OpMap A;
+  int64_t n, nz;
+  int nsplit;
+  double* Kpart;
+};
+hipError_t launch_syrk_group(const GroupSyrk* probs, int n, hipStream_t s);
+
 // ---- split precision (split.hip) ----
 // n rounded up to a multiple of the 64-deep int8 contraction step.
 int64_t kpad64(int64_t n);

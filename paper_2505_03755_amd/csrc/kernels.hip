@@ -41,6 +41,9 @@ struct Cfg {
 
 // Every MFMA kernel is sized for two waves per SIMD (at most 256 registers per lane, two
 // workgroups' LDS per CU), so one wave's barrier and LDS latency hide behind the other's MFMAs.
+// problems per grouped launch (their descriptors travel in the kernel arguments)
+constexpr int kMaxGroup = 8;
+
 // generic products and the K SYRK: 128 x 128 tiles, 2 x 2 waves of 64 x 64, interleaved
 typedef Cfg<2, 2, 4, 4, true> CfgSq;
 typedef Cfg<2, 2, 4, 4, true> CfgSyrk;
@@ -408,15 +411,13 @@ __global__ void __launch_bounds__(256) split_reduce_kernel(const double* __restr
 // Lower-triangle tile SYRK with the kb range split over workgroups:
 // Kpart[split][z] tile (I, J), I >= J, = sum_{kb in split} sum_kc A(i, kb, kc) Bw(j, kb, kc),
 // where Bw is A times an optional per-kc weight.
+// One (tile pair, split) item of density z.
 template <class C, bool SCALE, bool CLAMP>
-__global__ void __launch_bounds__(C::NT) syrk_kernel(OpMap A, OpMap Bw, int64_t n, int64_t nz, int nsplit,
-                                                     int64_t npairs, double* Kpart) {
+__device__ __forceinline__ void syrk_tile(const OpMap& A, const OpMap& Bw, int64_t n, int64_t nz, int nsplit,
+                                          int64_t npairs, double* Kpart, int64_t item, int64_t z, double* smem) {
   static_assert(C::BM == C::BN, "square tiles");
-  __shared__ double smem[2 * C::STAGE];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave % C::WM, wn = wave / C::WM;
-  const int64_t item = xcd_remap(blockIdx.x, npairs * nsplit);
-  const int64_t z = blockIdx.z;
   const int64_t pair = item % npairs;
   const int split = (int)(item / npairs);
   // triangular decode: pair = I(I+1)/2 + J, 0 <= J <= I
@@ -442,6 +443,39 @@ __global__ void __launch_bounds__(C::NT) syrk_kernel(OpMap A, OpMap Bw, int64_t 
   }
   OutMap o = out_plain(Kpart + ((int64_t)split * nz + z) * n * n, n, n, n);
   store_tile<C, false>(o, 0, m0, n0, acc, wm, wn, lane);
+}
+
+template <class C, bool SCALE, bool CLAMP>
+__global__ void __launch_bounds__(C::NT) syrk_kernel(OpMap A, OpMap Bw, int64_t n, int64_t nz, int nsplit,
+                                                     int64_t npairs, double* Kpart) {
+  __shared__ double smem[2 * C::STAGE];
+  syrk_tile<C, SCALE, CLAMP>(A, Bw, n, nz, nsplit, npairs, Kpart, xcd_remap(blockIdx.x, npairs * nsplit), blockIdx.z,
+                             smem);
+}
+
+// Grouped K SYRK: problem p owns items [start[p], start[p + 1]) = (density z, split, tile pair),
+// z outermost; unit weights.
+struct SyrkDesc {
+  OpMap A;
+  int64_t n, nz, npairs;
+  double* Kpart;
+  int nsplit;
+};
+struct SyrkGroup {
+  int n;
+  int64_t start[kMaxGroup + 1];
+  SyrkDesc d[kMaxGroup];
+};
+
+template <class C, bool CLAMP>
+__global__ void __launch_bounds__(C::NT) syrk_group_kernel(SyrkGroup g) {
+  __shared__ double smem[2 * C::STAGE];
+  const int64_t bid = xcd_remap(blockIdx.x, g.start[g.n]);
+  int p = 0;
+  while (p + 1 < g.n && bid >= g.start[p + 1]) ++p;
+  const SyrkDesc& d = g.d[p];
+  const int64_t item = bid - g.start[p], per_z = d.npairs * d.nsplit;
+  syrk_tile<C, false, CLAMP>(d.A, d.A, d.n, d.nz, d.nsplit, d.npairs, d.Kpart, item % per_z, item / per_z, smem);
 }
 
 __global__ void __launch_bounds__(256) syrk_reduce_kernel(const double* __restrict__ Kpart, int nsplit,
@@ -549,15 +583,14 @@ struct HalfSrc {
   }
 };
 
+// One output tile (item = P * tiles + tile) of the half transform.
 template <class C>
-__global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) half_kernel(const double* __restrict__ B, int64_t naux, int nao,
-                                                     int64_t npair, OpMap Cm, OutMap out, int64_t tilesM,
-                                                     int64_t tilesN) {
-  __shared__ double smem[2 * C::STAGE];
+__device__ __forceinline__ void half_tile(const double* __restrict__ B, int nao, int64_t npair, const OpMap& Cm,
+                                          const OutMap& out, int64_t tilesM, int64_t tilesN, int64_t item,
+                                          double* smem) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave % C::WM, wn = wave / C::WM;
   const int64_t ntile = tilesM * tilesN;
-  const int64_t item = xcd_remap(blockIdx.x, ntile * naux);
   // row band major: the column tiles of one band of b^P run side by side and share its reads in L2
   const int64_t P = item / ntile, tile = item % ntile;
   const int m0 = (int)((tile / tilesN) * C::BM), n0 = (int)((tile % tilesN) * C::BN);
@@ -571,6 +604,40 @@ __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2)))
   zero_acc<C>(acc);
   mainloop<C>(src, smem, nslab, acc, wm, wn, lane);
   store_tile<C, false>(out, P, m0, n0, acc, wm, wn, lane);
+}
+
+template <class C>
+__global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) half_kernel(const double* __restrict__ B, int64_t naux, int nao,
+                                                     int64_t npair, OpMap Cm, OutMap out, int64_t tilesM,
+                                                     int64_t tilesN) {
+  __shared__ double smem[2 * C::STAGE];
+  half_tile<C>(B, nao, npair, Cm, out, tilesM, tilesN, xcd_remap(blockIdx.x, tilesM * tilesN * naux), smem);
+}
+
+// Grouped half transform over several problems in one launch.  Work items of problem p are
+// [start[p], start[p + 1]); problems are listed largest first, so the big ones start first and
+// the small ones fill in behind them.
+struct HalfDesc {
+  const double* B;
+  int64_t npair, tilesM, tilesN;
+  OpMap Cm;
+  OutMap out;
+  int nao;
+};
+struct HalfGroup {
+  int n;
+  int64_t start[kMaxGroup + 1];
+  HalfDesc d[kMaxGroup];
+};
+
+template <class C>
+__global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) half_group_kernel(HalfGroup g) {
+  __shared__ double smem[2 * C::STAGE];
+  const int64_t bid = xcd_remap(blockIdx.x, g.start[g.n]);
+  int p = 0;
+  while (p + 1 < g.n && bid >= g.start[p + 1]) ++p;
+  const HalfDesc& d = g.d[p];
+  half_tile<C>(d.B, d.nao, d.npair, d.Cm, d.out, d.tilesM, d.tilesN, bid - g.start[p], smem);
 }
 
 // part[split] (m, n) = sum_{P in split} sum_k b^P_{mk} Y(n, (P, k)): the packed half-transform
@@ -932,6 +999,60 @@ hipError_t launch_syrk_partial(const OpMap& A, const OpMap& Bw, int64_t n, int64
   else if (Bw.ks) syrk_kernel<Cg, true, false><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
   else if (clamp) syrk_kernel<Cg, false, true><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
   else syrk_kernel<Cg, false, false><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
+  return hipGetLastError();
+}
+
+// ---- grouped launches ----
+hipError_t launch_half_group(const GroupHalf* probs, int n, hipStream_t s) {
+  if (n < 1 || n > kMaxGroup) return hipErrorInvalidValue;
+  typedef CfgH176 Cg;
+  HalfGroup g{};
+  g.n = n;
+  g.start[0] = 0;
+  for (int p = 0; p < n; ++p) {
+    const GroupHalf& q = probs[p];
+    HalfDesc& d = g.d[p];
+    d.B = q.B;
+    d.nao = (int)q.nao;
+    d.npair = q.nao * (q.nao + 1) / 2;
+    d.Cm = op_map(q.C, q.ncol, 1, q.nao, q.ldc);
+    d.out = q.out;
+    d.tilesM = cdiv(q.nao, Cg::BM);
+    d.tilesN = cdiv(q.ncol, Cg::BN);
+    if (!offsets_fit(d.Cm) || q.out.alpha != 1.0 || q.out.accumulate) return hipErrorInvalidValue;
+    g.start[p + 1] = g.start[p] + d.tilesM * d.tilesN * q.naux;
+  }
+  if (g.start[n] == 0) return hipSuccess;
+  if (g.start[n] > 0x7fffffffLL) return hipErrorInvalidValue;
+  half_group_kernel<Cg><<<(unsigned)g.start[n], Cg::NT, 0, s>>>(g);
+  return hipGetLastError();
+}
+
+hipError_t launch_syrk_group(const GroupSyrk* probs, int n, hipStream_t s) {
+  if (n < 1 || n > kMaxGroup) return hipErrorInvalidValue;
+  typedef CfgSyrk Cg;
+  SyrkGroup g{};
+  g.n = n;
+  g.start[0] = 0;
+  bool clamp = false;
+  for (int p = 0; p < n; ++p) {
+    const GroupSyrk& q = probs[p];
+    SyrkDesc& d = g.d[p];
+    d.A = q.A;
+    d.n = q.n;
+    d.nz = q.nz;
+    const int64_t T = cdiv(q.n, Cg::BM);
+    d.npairs = T * (T + 1) / 2;
+    d.nsplit = q.nsplit;
+    d.Kpart = q.Kpart;
+    if (!offsets_fit(q.A) || q.nsplit < 1) return hipErrorInvalidValue;
+    clamp = clamp || q.A.kc_n % 16 != 0;
+    g.start[p + 1] = g.start[p] + d.npairs * d.nsplit * q.nz;
+  }
+  if (g.start[n] == 0) return hipSuccess;
+  if (g.start[n] > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (clamp) syrk_group_kernel<Cg, true><<<(unsigned)g.start[n], Cg::NT, 0, s>>>(g);
+  else syrk_group_kernel<Cg, false><<<(unsigned)g.start[n], Cg::NT, 0, s>>>(g);
   return hipGetLastError();
 }
 

@@ -43,7 +43,7 @@ KERNEL_KINDS = ["half_transform", "jvec", "coulomb", "k_syrk", "k_reduce", "mo_t
 EXPORTED = ["df_create", "df_destroy", "df_last_error", "df_set_stream", "df_set_workspace",
             "df_set_timing", "df_timing_read", "df_workspace_size", "df_half_transform", "df_jk",
             "df_active_eri", "df_papa", "df_step", "df_step_backward", "df_split_matmul",
-            "df_split_cholesky", "df_step_split"]
+            "df_split_cholesky", "df_step_split", "df_batched_workspace_size", "df_batched_step"]
 
 
 class DFError(RuntimeError):
@@ -92,6 +92,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         L.df_papa.argtypes = [vp, dp, i64, i64, dp, i64, dp, i64, dp, i64, dp, i32]
         L.df_step.argtypes = [vp, dp, i64, i64, dp, i64, dp, dp, i64, dp, i64, dp, dp, dp, dp, dp, dp, dp, i32]
         L.df_step_backward.argtypes = [vp, dp, i64, i64, dp, i64, dp, i64, dp, dp, dp, dp, dp, dp, dp, i32]
+        L.df_batched_workspace_size.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_size_t)]
+        L.df_batched_step.argtypes = [vp, vp, i32, i32]
         L.df_split_matmul.argtypes = [vp, dp, i64, i64, dp, i64, i64, i64, i32, dp, i64, i32]
         L.df_split_cholesky.argtypes = [vp, dp, i64, i64, i32, vp, vp, i32]
         L.df_step_split.argtypes = [vp, dp, vp, vp, i32, i64, i64, dp, i64, dp, i64, dp, i64,
@@ -357,6 +359,51 @@ def step_backward(B, nao: int, Cocc, Cact, gJ=None, gK=None, geri=None, Xocc=Non
                                         _ptr(gJ), _ptr(gK), _ptr(geri), _ptr(Xocc), _ptr(Xact),
                                         _ptr(dCocc), _ptr(dCact), 0))
     return dCocc, dCact
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("B", ctypes.c_void_p), ("naux", ctypes.c_int64), ("nao", ctypes.c_int64),
+                ("ndm", ctypes.c_int64), ("Cocc", ctypes.c_void_p), ("nocc", ctypes.c_int64),
+                ("Cact", ctypes.c_void_p), ("nac", ctypes.c_int64), ("Cp", ctypes.c_void_p),
+                ("np", ctypes.c_int64), ("J", ctypes.c_void_p), ("K", ctypes.c_void_p),
+                ("eri", ctypes.c_void_p), ("papa", ctypes.c_void_p)]
+
+
+def batched_step(problems, ctx: Context | None = None):
+    """df_batched_step over a list of dicts {B, nao, Cocc [ndm, nao, nocc], Cact, Cp}; returns one
+    dict of outputs per problem: J, K [ndm, nao, nao], eri [nac]^4, papa (pu|qv) [np, nac, np, nac]."""
+    import torch
+    if not problems:
+        return []
+    dev = problems[0]["B"].device
+    ctx = ctx or context(dev)
+    arr = (Problem * len(problems))()
+    outs = []
+    for i, pr in enumerate(problems):
+        B, nao, Co, Ca, Cp = pr["B"], pr["nao"], pr["Cocc"], pr["Cact"], pr["Cp"]
+        for n, t in (("B", B), ("Cocc", Co), ("Cact", Ca), ("Cp", Cp)):
+            _check_tensor(n, t, ctx.device)
+        naux = _naux_of(B, nao)
+        ndm, nocc = Co.shape[0], Co.shape[2]
+        nac, np_ = Ca.shape[1], Cp.shape[1]
+        o = {"J": torch.empty((ndm, nao, nao), dtype=torch.float64, device=dev),
+             "K": torch.empty((ndm, nao, nao), dtype=torch.float64, device=dev),
+             "eri": torch.empty((nac,) * 4, dtype=torch.float64, device=dev),
+             "papa": torch.empty((np_, nac, np_, nac), dtype=torch.float64, device=dev)}
+        outs.append(o)
+        arr[i] = Problem(_ptr(B), naux, nao, ndm, _ptr(Co), nocc, _ptr(Ca), nac, _ptr(Cp), np_,
+                         _ptr(o["J"]), _ptr(o["K"]), _ptr(o["eri"]), _ptr(o["papa"]))
+    L = ctx._lib
+    need = ctypes.c_size_t(0)
+    ctx.check(L.df_batched_workspace_size(arr, len(problems), ctypes.byref(need)))
+    ctx.bind_stream()
+    if need.value and (ctx._ws is None or ctx._ws.numel() < need.value):
+        ctx._ws = None
+        ctx._ws = torch.empty(need.value, dtype=torch.uint8, device=ctx.device)
+    if ctx._ws is not None:
+        ctx.check(L.df_set_workspace(ctx._h, ctypes.c_void_p(ctx._ws.data_ptr()), ctx._ws.numel()))
+    ctx.check(L.df_batched_step(ctx.handle, arr, len(problems), 0))
+    return outs
 
 
 def dev_of(ctx):

@@ -141,3 +141,37 @@ WORKLOADS = {
     "medium": Workload("medium", nao=600, naux=2400, nocc=150, nac=20, L=40.0),
     "paper": Workload("paper", nao=1200, naux=4800, nocc=300, nac=40, L=40.0),
 }
+
+
+@dataclass(frozen=True)
+class Fragment:
+    """One embedding-space subproblem of the batched fragment workload."""
+    index: int
+    nemb: int
+    nac: int
+    ndm: int = 64
+    L: float = 20.0
+
+    @property
+    def naux(self) -> int:
+        return 4 * self.nemb
+
+    @property
+    def nocc(self) -> int:
+        return self.nemb // 4
+
+
+# Eight uneven fragment subproblems (N_emb 80 .. 400, N_aux = 4 N_emb, 4-8 active orbitals,
+# 64 densities of N_emb / 4 occupied columns each), the shapes of the fragment CASSCFs.
+FRAGMENTS = tuple(Fragment(i, n, a) for i, (n, a) in enumerate(
+    [(80, 4), (120, 4), (160, 6), (200, 6), (240, 6), (280, 8), (340, 8), (400, 8)]))
+
+
+def fragment_problem(f: Fragment, seed: int = 0, ndm: int | None = None):
+    """Host inputs of fragment f: packed B [naux, npair], ndm density factors [ndm, nemb, nocc] and
+    orbitals C [nemb, nemb]; the active block is C[:, nocc:nocc + nac], the p space all of C."""
+    ndm = f.ndm if ndm is None else ndm
+    B = cholesky_vectors(f.naux, f.nemb, f.L, seed=seed * 101 + f.index)
+    Cd = fragment_densities(f.nemb, f.nocc, ndm, f.index, seed=seed)
+    C = orbitals(f.nemb, seed=seed * 101 + f.index)
+    return B, Cd, C

@@ -208,3 +208,22 @@ def test_split_workspace_sizes():
     assert s7 > s5 > 0
     with pytest.raises(dfmi.DFError):
         dfmi.workspace_size(dfmi.DF_OP_STEP_SPLIT, naux=20, nao=9, nocc=4, nac=2, np=9, nslice=9)
+
+
+def test_batched_argument_errors(L, ctx):
+    P = dfmi.Problem
+    arr = (P * 2)()
+    arr[0] = P(1 << 30, 10, 7, 2, 2 << 30, 3, 3 << 30, 2, 4 << 30, 7, 5 << 30, 6 << 30, None, None)
+    arr[1] = P(7 << 30, 12, 5, 1, 8 << 30, 2, None, 0, None, 0, 9 << 30, None, None, None)
+    n = ctypes.c_size_t(0)
+    assert L.df_batched_workspace_size(arr, 2, ctypes.byref(n)) == dfmi.DF_OK and n.value > 0
+    assert L.df_batched_step(ctx, arr, 2, 1) == dfmi.DF_ERR_UNSUPPORTED
+    assert L.df_batched_step(ctx, None, 2, 0) == dfmi.DF_ERR_ARG
+    assert L.df_batched_step(ctx, arr, 2, 0) == dfmi.DF_ERR_WORKSPACE
+    assert L.df_batched_step(ctx, arr, 0, 0) == dfmi.DF_OK
+    arr[1].J = 5 << 30                        # problem 1's J overlaps problem 0's J
+    assert L.df_batched_step(ctx, arr, 2, 0) == dfmi.DF_ERR_ARG
+    arr[1].J = 9 << 30
+    arr[1].ndm = 0
+    assert L.df_batched_step(ctx, arr, 2, 0) == dfmi.DF_ERR_SHAPE
+    assert L.df_batched_workspace_size(arr, 2, ctypes.byref(n)) == dfmi.DF_ERR_SHAPE

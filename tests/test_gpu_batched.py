@@ -1,0 +1,112 @@
+"""GPU parity of the batched fragment subproblems (df_batched_step).
+
+Each problem's outputs are checked against the FP64 oracle (normwise 1e-10) and against the
+unbatched library calls on the same inputs (df_jk, df_active_eri, df_papa with DF_PAPA_FULL),
+which may tile differently: 1e-12.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import df_oracle as O
+from paper_2505_03755_amd import dfmi, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+def rel(a, b):
+    a = a.detach().cpu().numpy() if isinstance(a, torch.Tensor) else np.asarray(a)
+    b = b.detach().cpu().numpy() if isinstance(b, torch.Tensor) else np.asarray(b)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a)
+
+
+def make(nemb, naux, nocc, nac, ndm, seed):
+    B = synth.cholesky_vectors(naux, nemb, 10.0, seed=seed)
+    Cd = synth.fragment_densities(nemb, nocc, ndm, seed, seed=seed) if nocc else np.zeros((ndm, nemb, 0))
+    C = synth.orbitals(nemb, seed=seed)
+    return {"B": B, "nao": nemb, "Cocc": Cd, "Cact": C[:, nocc:nocc + nac], "Cp": C}
+
+
+def to_dev(p):
+    return {"B": dev(p["B"]), "nao": p["nao"], "Cocc": dev(p["Cocc"]), "Cact": dev(p["Cact"]), "Cp": dev(p["Cp"])}
+
+
+# (nemb, naux, nocc, nac, ndm): uneven sizes straddling the tiles, a problem without occupied
+# columns and one without active orbitals
+RAGGED = [(33, 40, 7, 3, 3), (130, 90, 20, 5, 2), (17, 70, 4, 2, 5), (64, 64, 0, 4, 2), (70, 30, 9, 0, 3)]
+
+
+def check_problem(p, out, tol_oracle=1e-10):
+    B, nao = p["B"], p["nao"]
+    ndm, nocc = p["Cocc"].shape[0], p["Cocc"].shape[2]
+    nac = p["Cact"].shape[1]
+    for z in range(ndm):
+        if nocc:
+            J, K, _ = O.jk(B, nao, p["Cocc"][z])
+            assert rel(out["J"][z], J) <= tol_oracle
+            assert rel(out["K"][z], K) <= tol_oracle
+            assert torch.equal(out["K"][z], out["K"][z].T)
+        else:
+            assert not out["J"][z].any() and not out["K"][z].any()
+    if nac:
+        eri, _ = O.active_eri(B, nao, p["Cact"])
+        assert rel(out["eri"], eri) <= tol_oracle
+        pf = O.papa_full(B, nao, p["Cp"], p["Cact"], p["Cp"])
+        assert rel(out["papa"], pf) <= tol_oracle
+
+
+def test_batched_ragged_against_oracle():
+    probs = [make(*shape, seed=i + 1) for i, shape in enumerate(RAGGED)]
+    outs = dfmi.batched_step([to_dev(p) for p in probs])
+    torch.cuda.synchronize()
+    for p, o in zip(probs, outs):
+        check_problem(p, o)
+
+
+def test_batched_equals_unbatched_calls():
+    probs = [make(*shape, seed=i + 11) for i, shape in enumerate(RAGGED)]
+    dps = [to_dev(p) for p in probs]
+    outs = dfmi.batched_step(dps)
+    for dp, o in zip(dps, outs):
+        ndm, nocc, nac = dp["Cocc"].shape[0], dp["Cocc"].shape[2], dp["Cact"].shape[1]
+        if nocc:
+            J, K, _ = dfmi.jk(dp["B"], dp["nao"], dp["Cocc"])
+            assert rel(o["J"], J) <= 1e-12 and rel(o["K"], K) <= 1e-12
+        if nac:
+            eri = dfmi.active_eri(dp["B"], dp["nao"], dp["Cact"])
+            eri = eri[0] if isinstance(eri, tuple) else eri
+            assert rel(o["eri"], eri) <= 1e-12
+            pf = dfmi.papa(dp["B"], dp["nao"], dp["Cp"], dp["Cact"], Cq=dp["Cp"])
+            assert rel(o["papa"], pf) <= 1e-12
+    torch.cuda.synchronize()
+
+
+def test_batched_more_than_one_group():
+    """Nine problems: two grouped launches per phase."""
+    shapes = [(20 + 7 * i, 30 + 5 * i, 3 + i % 3, 2 + i % 2, 2) for i in range(9)]
+    probs = [make(*s, seed=100 + i) for i, s in enumerate(shapes)]
+    outs = dfmi.batched_step([to_dev(p) for p in probs])
+    torch.cuda.synchronize()
+    for p, o in zip(probs, outs):
+        check_problem(p, o)
+
+
+def test_fragment_workload_reduced_densities():
+    """The eight fragment shapes (N_emb 80..400, N_aux = 4 N_emb) with 4 densities each."""
+    probs = []
+    for f in synth.FRAGMENTS:
+        B, Cd, C = synth.fragment_problem(f, ndm=4)
+        probs.append({"B": B, "nao": f.nemb, "Cocc": Cd, "Cact": C[:, f.nocc:f.nocc + f.nac], "Cp": C})
+    outs = dfmi.batched_step([to_dev(p) for p in probs])
+    torch.cuda.synchronize()
+    for p, o in zip(probs[:4], outs[:4]):          # the oracle on the four smaller ones
+        check_problem(p, o)
+    for p, o in zip(probs[4:], outs[4:]):          # sampled densities on the larger ones
+        J, K, _ = O.jk(p["B"], p["nao"], p["Cocc"][3])
+        assert rel(o["J"][3], J) <= 1e-10 and rel(o["K"][3], K) <= 1e-10
