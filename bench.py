@@ -195,6 +195,60 @@ def split_comparison(B, nao, Cocc, Cact, C, nslice, reps, ctx):
             "rel_diff": rel}
 
 
+def fragment_flops(f, ndm):
+    """Algorithmic FLOPs of one fragment subproblem: half transform, J, K, b_pu and the full
+    (pu|qv), and (uv|wx)."""
+    n, naux, nocc, nac = f.nemb, f.naux, f.nocc, f.nac
+    npair = n * (n + 1) // 2
+    return (2 * naux * n * n * (ndm * nocc + nac) + ndm * (2 * naux * n * nocc + 2 * naux * npair)
+            + ndm * naux * nocc * n * (n + 1) + 2 * naux * n * n * nac + 2 * naux * (n * nac) ** 2
+            + 2 * naux * n * nac * nac + 2 * naux * nac ** 4)
+
+
+def batched_fragments(ndm, reps, ctx):
+    """The eight fragment subproblems with ndm densities each: df_batched_step (grouped launches)
+    against the same work issued problem by problem (df_jk, df_active_eri, df_papa FULL)."""
+    import numpy as np
+    import torch
+    from paper_2505_03755_amd import dfmi, synth
+    dev = torch.device("cuda", 0)
+    probs = []
+    for f in synth.FRAGMENTS:
+        B, Cd, C = synth.fragment_problem(f, ndm=ndm)
+        probs.append({"B": torch.from_numpy(B).to(dev), "nao": f.nemb, "Cocc": torch.from_numpy(Cd).to(dev),
+                      "Cact": torch.from_numpy(np.ascontiguousarray(C[:, f.nocc:f.nocc + f.nac])).to(dev),
+                      "Cp": torch.from_numpy(C).to(dev)})
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record(stream)
+        for i in range(reps):
+            fn()
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        ms = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(reps))
+        return ms[len(ms) // 2]
+
+    def unbatched():
+        for p in probs:
+            dfmi.jk(p["B"], p["nao"], p["Cocc"], want_v=False, ctx=ctx)
+            dfmi.active_eri(p["B"], p["nao"], p["Cact"], ctx=ctx)
+            dfmi.papa(p["B"], p["nao"], p["Cp"], p["Cact"], Cq=p["Cp"], ctx=ctx)
+
+    ms_b = timed(lambda: dfmi.batched_step(probs, ctx=ctx))
+    ms_u = timed(unbatched)
+    fl = sum(fragment_flops(f, ndm) for f in synth.FRAGMENTS)
+    del probs
+    torch.cuda.empty_cache()
+    return {"workload": "8 fragment subproblems, N_emb 80..400, N_aux = 4 N_emb, N_occ = N_emb/4, "
+                        f"N_ac 4..8, {ndm} densities each; J, K, (uv|wx), full (pu|qv)",
+            "flops": fl, "ms_batched": ms_b, "tflops_batched": fl / ms_b / 1e9,
+            "ms_unbatched": ms_u, "tflops_unbatched": fl / ms_u / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -205,6 +259,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forward-only", action="store_true", help="time df_step alone (no adjoint)")
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision comparison")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched fragment workload")
+    ap.add_argument("--fragment-densities", type=int, default=64)
     ap.add_argument("--split-slices", type=int, default=7)
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="copy this many MiB device-to-device once before the steps (a known-size "
@@ -336,7 +392,11 @@ def main():
         torch.cuda.empty_cache()
         res["split_precision"] = split_comparison(B, nao, Cocc, Cact, C, args.split_slices, 5, ctx)
     del B
+    out.clear()
     torch.cuda.empty_cache()
+    if not args.no_batched:
+        log(f"[bench] batched fragment subproblems, {args.fragment_densities} densities each")
+        res["batched_fragments"] = batched_fragments(args.fragment_densities, 3, ctx)
     if not args.no_cpu_baseline:
         log(f"[bench] timing the CPU oracle on {args.cpu_rows} auxiliary rows")
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_rows, wl.seed, adjoint=not args.forward_only)

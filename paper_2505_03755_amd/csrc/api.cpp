@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -253,24 +254,53 @@ StepSplitPlan plan_step_split(Plan& pl, int64_t naux, int64_t nao, int64_t nocc,
 
 // ---- batched problems ----
 struct BatchedPiece {
-  size_t cpad, x, v, kpart, buv, bpu;
+  size_t cpad, xo, xa, v, jp, kpart, buv, bpu;
   int nsplit;
 };
 int64_t batched_ncol(const df_problem& q) { return q.ndm * q.nocc + q.nac; }
 // half-transform work of a problem, for the largest-first order
 int64_t batched_work(const df_problem& q) { return q.naux * q.nao * q.nao * batched_ncol(q); }
 
+// Split counts of the grouped K launch: every (density, split, tile pair) item gets about the
+// same number of 16-deep slabs, about four rounds of resident workgroups in all, so that the
+// long contractions of the big problems do not run alone at the end.
+std::vector<int> batched_k_splits(const df_problem* probs, int n) {
+  const int64_t T = dfk::syrk_tile();
+  double total = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const df_problem& q = probs[i];
+    if (!q.K || q.nocc <= 0) continue;
+    const int64_t t = (q.nao + T - 1) / T;
+    total += (double)(t * (t + 1) / 2) * q.ndm * q.naux * ((q.nocc + 15) / 16);
+  }
+  const double target = std::max(64.0, total / (4.0 * 512.0));   // slabs per item
+  std::vector<int> ns((size_t)n, 1);
+  for (int i = 0; i < n; ++i) {
+    const df_problem& q = probs[i];
+    if (!q.K || q.nocc <= 0) continue;
+    const double slabs = (double)q.naux * ((q.nocc + 15) / 16);
+    ns[(size_t)i] = (int)std::min<double>((double)q.naux, std::max(1.0, std::ceil(slabs / target)));
+  }
+  return ns;
+}
+
+// J of many densities as one product: Jp[z][pair] = sum_P v[z][P] b^P[pair] (then unpacked)
+bool batched_j_gemm(const df_problem& q) { return q.ndm > 4; }
+
 std::vector<BatchedPiece> plan_batched(Plan& pl, const df_problem* probs, int n) {
   std::vector<BatchedPiece> v((size_t)n);
+  const std::vector<int> ks = batched_k_splits(probs, n);
   for (int i = 0; i < n; ++i) {
     const df_problem& q = probs[i];
     BatchedPiece& b = v[(size_t)i];
     const int64_t ncol = batched_ncol(q);
     const bool need_x = ncol > 0 && (q.J || q.K || q.eri || q.papa);
     b.cpad = pl.take(need_x ? dfk::kpad16(q.nao) * ncol : 0);
-    b.x = pl.take(need_x ? q.naux * q.nao * ncol : 0);
+    b.xo = pl.take(need_x ? q.naux * q.nao * q.ndm * q.nocc : 0);   // P-major [naux][nao][ndm*nocc]
+    b.xa = pl.take(need_x ? q.naux * q.nao * q.nac : 0);            // AO-major [nao][naux][nac]
     b.v = pl.take(q.J && q.nocc > 0 ? q.ndm * q.naux : 0);
-    b.nsplit = dfk::syrk_splits(q.nao, q.naux, q.ndm);
+    b.jp = pl.take(q.J && q.nocc > 0 && batched_j_gemm(q) ? q.ndm * q.nao * (q.nao + 1) / 2 : 0);
+    b.nsplit = ks[(size_t)i];
     b.kpart = pl.take(q.K && q.nocc > 0 ? (int64_t)b.nsplit * q.ndm * q.nao * q.nao : 0);
     b.buv = pl.take(q.eri && q.nac > 0 ? q.naux * q.nac * q.nac : 0);
     b.bpu = pl.take(q.papa && q.nac > 0 && q.np > 0 ? q.naux * q.np * q.nac : 0);
@@ -444,26 +474,6 @@ df_status run_mo_pmajor(df_ctx* c, const double* C2, int64_t n2, const double* X
     Bp.p = X + p0 * nao * ncol;
     dfk::OutMap Op = O;
     Op.p = Y + p0 * n2 * ncol;
-    DF_LAUNCH(DF_KERNEL_MO_TRANSFORM, dfk::launch_gemm(A, Bp, Op, np_, c->stream), "second transform launch");
-  }
-  return DF_OK;
-}
-
-// Y[P][p][u] = sum_mu C2[mu][p] X[P][mu][off + u], u < nu  (X P-major with row stride ldx), batched over P
-df_status run_mo_cols(df_ctx* c, const double* C2, int64_t n2, const double* X, int64_t naux, int64_t nao, int64_t ldx,
-                      int64_t off, int64_t nu, double* Y) {
-  if (n2 == 0 || nu == 0) return DF_OK;
-  const dfk::OpMap A = dfk::op_map(C2, n2, 1, nao, n2);
-  dfk::OpMap Bm = dfk::op_map(X + off, nu, 1, nao, ldx);
-  Bm.s_z = nao * ldx;
-  dfk::OutMap O = dfk::out_plain(Y, n2, nu, nu);
-  O.s_z = n2 * nu;
-  for (int64_t p0 = 0; p0 < naux; p0 += 65535) {
-    const int64_t np_ = std::min<int64_t>(65535, naux - p0);
-    dfk::OpMap Bp = Bm;
-    Bp.p = X + off + p0 * nao * ldx;
-    dfk::OutMap Op = O;
-    Op.p = Y + p0 * n2 * nu;
     DF_LAUNCH(DF_KERNEL_MO_TRANSFORM, dfk::launch_gemm(A, Bp, Op, np_, c->stream), "second transform launch");
   }
   return DF_OK;
@@ -1241,12 +1251,14 @@ df_status df_batched_step(df_ctx* ctx, const df_problem* probs, int nprob, int f
     for (int64_t z = 0; z < q.ndm; ++z) blks.push_back({q.Cocc + z * q.nao * q.nocc, q.nocc, q.nocc, z * q.nocc});
     blks.push_back({q.Cact, q.nac, q.nac, q.ndm * q.nocc});
     if (df_status s = pad_operand(c, cp, q.nao, ncol, blks.data(), (int)blks.size())) return s;
-    double* X = (double*)(ws + b.x);
-    gh.push_back({q.B, q.naux, q.nao, cp, ncol, ncol, out_pmajor(X, q.naux, q.nao, ncol, ncol)});
+    double* Xo = (double*)(ws + b.xo);
+    double* Xa = (double*)(ws + b.xa);
+    const int64_t no = q.ndm * q.nocc;
+    gh.push_back({q.B, q.naux, q.nao, cp, ncol, ncol, out_split(Xo, Xa, q.naux, q.nao, no, q.nac)});
     if (q.K && q.nocc > 0) {
-      dfk::OpMap A = dfk::op_map(X, q.nao, ncol, q.nocc, 1);
+      dfk::OpMap A = dfk::op_map(Xo, q.nao, no, q.nocc, 1);
       A.kb_n = q.naux;
-      A.s_kb = q.nao * ncol;
+      A.s_kb = q.nao * no;
       A.s_z = q.nocc;
       gs.push_back({A, q.nao, q.ndm, b.nsplit, (double*)(ws + b.kpart)});
     }
@@ -1265,25 +1277,36 @@ df_status df_batched_step(df_ctx* ctx, const df_problem* probs, int nprob, int f
     const BatchedPiece& b = pc[(size_t)i];
     const int64_t ncol = batched_ncol(q);
     if (ncol == 0 || !(q.J || q.K || q.eri || q.papa)) continue;
-    const double* X = (const double*)(ws + b.x);
+    const double* Xo = (const double*)(ws + b.xo);
+    const double* Xa = (const double*)(ws + b.xa);
+    const int64_t no = q.ndm * q.nocc;
     if (q.K && q.nocc > 0)
       DF_LAUNCH(DF_KERNEL_K_REDUCE, dfk::launch_syrk_reduce((double*)(ws + b.kpart), b.nsplit, q.nao, q.ndm, q.K, c->stream),
                 "K reduce launch");
     if (q.J && q.nocc > 0) {
       double* v = (double*)(ws + b.v);
-      DF_LAUNCH(DF_KERNEL_JVEC, dfk::launch_jvec(X, q.naux, q.nao, ncol, q.Cocc, nullptr, q.nocc, q.ndm, v, c->stream),
+      DF_LAUNCH(DF_KERNEL_JVEC, dfk::launch_jvec(Xo, q.naux, q.nao, no, q.Cocc, nullptr, q.nocc, q.ndm, v, c->stream),
                 "J-vector launch");
-      DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_coulomb(q.B, q.naux, q.nao, v, q.ndm, q.J, c->stream), "Coulomb launch");
+      if (batched_j_gemm(q)) {
+        const int64_t npair = q.nao * (q.nao + 1) / 2;
+        double* jp = (double*)(ws + b.jp);
+        const dfk::OpMap A = dfk::op_map(v, q.ndm, q.naux, q.naux, 1);
+        const dfk::OpMap Bm = dfk::op_map(q.B, npair, 1, q.naux, npair);
+        DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_gemm(A, Bm, dfk::out_plain(jp, q.ndm, npair, npair), 1, c->stream),
+                  "Coulomb product launch");
+        DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_unpack_sym(jp, q.ndm, q.nao, q.J, c->stream), "unpack launch");
+      } else {
+        DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_coulomb(q.B, q.naux, q.nao, v, q.ndm, q.J, c->stream), "Coulomb launch");
+      }
     }
-    const int64_t off = q.ndm * q.nocc;
     if (q.eri && q.nac > 0) {
       double* buv = (double*)(ws + b.buv);
-      if (df_status s = run_mo_cols(c, q.Cact, q.nac, X, q.naux, q.nao, ncol, off, q.nac, buv)) return s;
+      if (df_status s = run_mo(c, q.Cact, q.nac, Xa, q.naux, q.nao, q.nac, buv)) return s;
       if (df_status s = run_pgemm(c, DF_KERNEL_ERI, buv, q.nac * q.nac, buv, q.nac * q.nac, q.naux, q.eri)) return s;
     }
     if (q.papa && q.nac > 0 && q.np > 0) {
       double* bpu = (double*)(ws + b.bpu);
-      if (df_status s = run_mo_cols(c, q.Cp, q.np, X, q.naux, q.nao, ncol, off, q.nac, bpu)) return s;
+      if (df_status s = run_mo(c, q.Cp, q.np, Xa, q.naux, q.nao, q.nac, bpu)) return s;
       if (df_status s = run_pgemm(c, DF_KERNEL_PAPA, bpu, q.np * q.nac, bpu, q.np * q.nac, q.naux, q.papa)) return s;
     }
   }

@@ -789,6 +789,20 @@ __global__ void __launch_bounds__(256) symmetrize_kernel(const double* in, int64
   out[z * nn + j * n + i] = s;
 }
 
+__global__ void __launch_bounds__(256) unpack_sym_kernel(const double* __restrict__ Jp, int64_t nz, int64_t nao,
+                                                         int64_t npair, double* __restrict__ J) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= nz * npair) return;
+  const int64_t z = idx / npair, p = idx % npair;
+  int64_t i = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+  while (i * (i + 1) / 2 > p) --i;
+  while ((i + 1) * (i + 2) / 2 <= p) ++i;
+  const int64_t j = p - i * (i + 1) / 2;
+  const double x = Jp[idx];
+  J[z * nao * nao + i * nao + j] = x;
+  J[z * nao * nao + j * nao + i] = x;
+}
+
 __global__ void __launch_bounds__(256) fill_zero_kernel(double* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) p[i] = 0.0;
@@ -1087,6 +1101,13 @@ hipError_t launch_coulomb(const double* B, int64_t naux, int64_t nao, const doub
 hipError_t launch_fill_zero(double* p, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   fill_zero_kernel<<<(unsigned)cdiv(n, 256), 256, 0, s>>>(p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_sym(const double* Jp, int64_t nz, int64_t nao, double* J, hipStream_t s) {
+  const int64_t npair = nao * (nao + 1) / 2, tot = nz * npair;
+  if (tot <= 0) return hipSuccess;
+  unpack_sym_kernel<<<(unsigned)cdiv(tot, 256), 256, 0, s>>>(Jp, nz, nao, npair, J);
   return hipGetLastError();
 }
 
