@@ -151,7 +151,7 @@ StepPlan plan_step(Plan& pl, int64_t naux, int64_t nao, int64_t nocc, int64_t na
 // Workspace of df_step_backward.  flags: DF_BWD_GJ / DF_BWD_GK / DF_BWD_GERI say which cotangents
 // are given, DF_CALLER_X that the forward's half transforms are passed in.
 struct BwdPlan {
-  size_t ccat, xo, xa, g, u, M, S, Y, kpart, Gs, buv, Z, apart;
+  size_t ccat, xo, xa, g, u, upart, M, S, Y, kpart, Gs, buv, Z, apart;
   int nsk, nsa;
 };
 
@@ -166,6 +166,7 @@ BwdPlan plan_backward(Plan& pl, int64_t naux, int64_t nao, int64_t nocc, int64_t
   p.xa = pl.take(need_xa ? naux * nao * nac : 0);
   p.g = pl.take(gj && nocc > 0 ? npair : 0);
   p.u = pl.take(gj && nocc > 0 ? naux : 0);
+  p.upart = pl.take(gj && nocc > 0 ? (int64_t)dfk::jvec_packed_chunks() * naux : 0);
   p.M = pl.take(gj && nocc > 0 ? nao * nao : 0);
   p.S = pl.take(gk && nocc > 0 ? nao * nao : 0);
   p.Y = pl.take(gk && nocc > 0 ? naux * dfk::kpad16(nao) * nocc : 0);   // [P][kpad16(nao)][nocc]
@@ -262,10 +263,13 @@ int64_t batched_ncol(const df_problem& q) { return q.ndm * q.nocc + q.nac; }
 int64_t batched_work(const df_problem& q) { return q.naux * q.nao * q.nao * batched_ncol(q); }
 
 // Split counts of the grouped K launch: every (density, split, tile pair) item gets about the
-// same number of 16-deep slabs, about four rounds of resident workgroups in all, so that the
-// long contractions of the big problems do not run alone at the end.
+// same number of 16-deep slabs, about sixteen rounds of resident workgroups in all, so that
+// the long contractions of the big problems do not run alone at the end.
 std::vector<int> batched_k_splits(const df_problem* probs, int n) {
-  const int64_t T = dfk::syrk_tile();
+  int64_t nmax = 0;
+  for (int i = 0; i < n; ++i)
+    if (probs[i].K && probs[i].nocc > 0) nmax = std::max(nmax, probs[i].nao);
+  const int64_t T = dfk::syrk_tile_for(nmax);
   double total = 0.0;
   for (int i = 0; i < n; ++i) {
     const df_problem& q = probs[i];
@@ -273,7 +277,7 @@ std::vector<int> batched_k_splits(const df_problem* probs, int n) {
     const int64_t t = (q.nao + T - 1) / T;
     total += (double)(t * (t + 1) / 2) * q.ndm * q.naux * ((q.nocc + 15) / 16);
   }
-  const double target = std::max(64.0, total / (4.0 * 512.0));   // slabs per item
+  const double target = std::max(64.0, total / (16.0 * 512.0));   // slabs per item
   std::vector<int> ns((size_t)n, 1);
   for (int i = 0; i < n; ++i) {
     const df_problem& q = probs[i];
@@ -923,7 +927,8 @@ df_status df_step_backward(df_ctx* ctx, const double* B, int64_t naux, int64_t n
     double* u = (double*)(ws + p.u);
     double* M = (double*)(ws + p.M);
     DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_pair_weights(gJ, nao, g, c->stream), "pair weights");
-    DF_LAUNCH(DF_KERNEL_JVEC, dfk::launch_jvec_packed(B, naux, nao, g, u, c->stream), "J-vector launch");
+    DF_LAUNCH(DF_KERNEL_JVEC, dfk::launch_jvec_packed(B, naux, nao, g, (double*)(ws + p.upart), u, c->stream),
+              "J-vector launch");
     DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_coulomb(B, naux, nao, u, 1, M, c->stream), "Coulomb launch");
     const dfk::OpMap A = dfk::op_map(M, nao, nao, nao, 1);
     const dfk::OpMap Bm = dfk::op_map(Cocc, nocc, 1, nao, nocc);

@@ -80,7 +80,9 @@ hipError_t launch_half_reduce(const double* B, int64_t naux, int64_t nao, const 
 // g[pair(i,j)] = G[i][j] + G[j][i] (i > j), G[i][i] (i == j): <b^P, G> = sum_pair b^P[pair] g[pair]
 hipError_t launch_pair_weights(const double* G, int64_t nao, double* g, hipStream_t s);
 // u[P] = sum_pair B[P][pair] g[pair]
-hipError_t launch_jvec_packed(const double* B, int64_t naux, int64_t nao, const double* g, double* u,
+// (partial sums over jvec_packed_chunks() chunks of the pairs go to part [chunks][naux] first)
+int jvec_packed_chunks();
+hipError_t launch_jvec_packed(const double* B, int64_t naux, int64_t nao, const double* g, double* part, double* u,
                               hipStream_t s);
 // out[z] = in[z] + in[z]^T for nz square n x n matrices (out may equal in)
 hipError_t launch_symmetrize(const double* in, int64_t n, int64_t nz, double* out, hipStream_t s);
@@ -89,7 +91,9 @@ hipError_t launch_symmetrize(const double* in, int64_t n, int64_t nz, double* ou
 // for tile(i) >= tile(j) (Bw = A with an optional per-kc weight).  Kpart is dense [nsplit][nz][n][n];
 // syrk_splits() gives the number of splits the workspace is planned for.
 int syrk_splits(int64_t n, int64_t kb_n, int64_t nz);
-int syrk_tile();
+// SYRK tile edge for an n x n result (64 up to n = 640, else 128); a group uses the edge of its
+// largest member.
+int syrk_tile_for(int64_t n);
 hipError_t launch_syrk_partial(const OpMap& A, const OpMap& Bw, int64_t n, int64_t nz, int nsplit,
                                double* Kpart, hipStream_t s);
 // K[z][i][j] = sum_s Kpart[s][z][max(i,j)][min(i,j)]; both triangles written.

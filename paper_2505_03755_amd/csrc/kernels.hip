@@ -47,8 +47,11 @@ constexpr int kMaxGroup = 8;
 // generic products and the K SYRK: 128 x 128 tiles, 2 x 2 waves of 64 x 64, interleaved
 typedef Cfg<2, 2, 4, 4, true> CfgSq;
 typedef Cfg<2, 2, 4, 4, true> CfgSyrk;
+// small matrices (fragment sizes): 64 x 64 SYRK tiles pad the triangle less
+typedef Cfg<2, 2, 2, 2, true> CfgSyrk64;
 // half transform: {64, 128, 128} rows x {176, 96, 48} columns, 4 waves stacked along the rows
 typedef Cfg<4, 1, 1, 11, true> CfgH176;
+typedef Cfg<4, 1, 1, 10, true> CfgH160;   // the P-summed packed product: 300 columns in 2 x 160
 typedef Cfg<4, 1, 2, 6> CfgH96;
 typedef Cfg<4, 1, 2, 3> CfgH48;
 
@@ -750,14 +753,20 @@ __global__ void __launch_bounds__(256) pair_weights_kernel(const double* __restr
 // u[P] = sum_pair B[P][pair] g[pair]: eight rows of B per workgroup share each read of g; a
 // fixed-order reduction keeps it deterministic.
 constexpr int kJvRows = 8;
+// Partial sums part[c][P] = sum_{pair in chunk c} B[P][pair] g[pair] for kJvRows rows per
+// workgroup (grid x) and kJvChunks chunks of the pairs (grid y): enough workgroups to keep HBM
+// busy; the chunks are summed in a fixed order afterwards.
+constexpr int kJvChunks = 8;
 __global__ void __launch_bounds__(256) jvec_packed_kernel(const double* __restrict__ B, int64_t naux, int64_t npair,
-                                                          const double* __restrict__ g, double* __restrict__ u) {
+                                                          const double* __restrict__ g, double* __restrict__ part) {
   __shared__ double red[kJvRows][4];
   const int64_t P0 = (int64_t)blockIdx.x * kJvRows;
+  const int64_t c = blockIdx.y, chunk = (npair + kJvChunks - 1) / kJvChunks;
+  const int64_t p0 = c * chunk, p1 = p0 + chunk < npair ? p0 + chunk : npair;
   double s[kJvRows];
 #pragma unroll
   for (int r = 0; r < kJvRows; ++r) s[r] = 0.0;
-  for (int64_t p = threadIdx.x; p < npair; p += 256) {
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += 256) {
     const double gp = g[p];
 #pragma unroll
     for (int r = 0; r < kJvRows; ++r)
@@ -772,8 +781,17 @@ __global__ void __launch_bounds__(256) jvec_packed_kernel(const double* __restri
   __syncthreads();
   if (threadIdx.x < kJvRows && P0 + threadIdx.x < naux) {
     const int r = threadIdx.x;
-    u[P0 + r] = (red[r][0] + red[r][1]) + (red[r][2] + red[r][3]);
+    part[c * naux + P0 + r] = (red[r][0] + red[r][1]) + (red[r][2] + red[r][3]);
   }
+}
+
+__global__ void __launch_bounds__(256) jvec_chunks_kernel(const double* __restrict__ part, int64_t naux,
+                                                          double* __restrict__ u) {
+  const int64_t P = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (P >= naux) return;
+  double s = 0.0;
+  for (int c = 0; c < kJvChunks; ++c) s += part[c * naux + P];
+  u[P] = s;
 }
 
 // out[z] = in[z] + in[z]^T (in place allowed: each pair (i, j), i <= j, is handled by one thread)
@@ -949,21 +967,30 @@ hipError_t launch_gemm_split(const OpMap& A, const OpMap& Bm, const OutMap& O, i
   return hipGetLastError();
 }
 
+// Column tile of the P-summed packed product: 176 or 160, whichever pads N less (176 on ties).
+static int half_reduce_tile_n(int64_t N) { return cdiv(N, 160) * 160 < cdiv(N, 176) * 176 ? 160 : 176; }
+
 int half_reduce_splits(int64_t nao, int64_t N, int64_t naux) {
-  return balanced_splits(cdiv(nao, CfgH176::BM) * cdiv(N, CfgH176::BN), naux);
+  return balanced_splits(cdiv(nao, CfgH176::BM) * cdiv(N, half_reduce_tile_n(N)), naux);
 }
 
-hipError_t launch_half_reduce(const double* B, int64_t naux, int64_t nao, const OpMap& Y, const OutMap& O,
-                              int nsplit, double* part, hipStream_t s) {
-  typedef CfgH176 Cg;
+template <class Cg>
+static hipError_t half_reduce_go(const double* B, int64_t naux, int64_t nao, const OpMap& Y, const OutMap& O,
+                                 int nsplit, double* part, hipStream_t s) {
   const int64_t tm = cdiv(nao, Cg::BM), tn = cdiv(O.N, Cg::BN);
-  if (tm * tn == 0) return hipSuccess;
-  if (nsplit < 1 || nsplit > 65535 || !offsets_fit(Y)) return hipErrorInvalidValue;
   const int64_t nblk = tm * tn * nsplit;
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
   half_reduce_kernel<Cg><<<dim3((unsigned)nblk), Cg::NT, 0, s>>>(B, naux, (int)nao, nao * (nao + 1) / 2, Y, O.N, tm,
                                                                 tn, nsplit, part);
-  hipError_t e = hipGetLastError();
+  return hipGetLastError();
+}
+
+hipError_t launch_half_reduce(const double* B, int64_t naux, int64_t nao, const OpMap& Y, const OutMap& O,
+                              int nsplit, double* part, hipStream_t s) {
+  if (nao <= 0 || O.N <= 0) return hipSuccess;
+  if (nsplit < 1 || nsplit > 65535 || !offsets_fit(Y)) return hipErrorInvalidValue;
+  hipError_t e = half_reduce_tile_n(O.N) == 160 ? half_reduce_go<CfgH160>(B, naux, nao, Y, O, nsplit, part, s)
+                                                 : half_reduce_go<CfgH176>(B, naux, nao, Y, O, nsplit, part, s);
   if (e != hipSuccess) return e;
   OutMap Oc = O;
   Oc.M = nao;
@@ -979,10 +1006,16 @@ hipError_t launch_pair_weights(const double* G, int64_t nao, double* g, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_jvec_packed(const double* B, int64_t naux, int64_t nao, const double* g, double* u,
+int jvec_packed_chunks() { return kJvChunks; }
+
+hipError_t launch_jvec_packed(const double* B, int64_t naux, int64_t nao, const double* g, double* part, double* u,
                               hipStream_t s) {
   if (naux == 0) return hipSuccess;
-  jvec_packed_kernel<<<(unsigned)cdiv(naux, kJvRows), 256, 0, s>>>(B, naux, nao * (nao + 1) / 2, g, u);
+  jvec_packed_kernel<<<dim3((unsigned)cdiv(naux, kJvRows), kJvChunks), 256, 0, s>>>(B, naux, nao * (nao + 1) / 2, g,
+                                                                                    part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  jvec_chunks_kernel<<<(unsigned)cdiv(naux, 256), 256, 0, s>>>(part, naux, u);
   return hipGetLastError();
 }
 
@@ -993,16 +1026,18 @@ hipError_t launch_symmetrize(const double* in, int64_t n, int64_t nz, double* ou
   return hipGetLastError();
 }
 
-int syrk_tile() { return CfgSyrk::BM; }
+
+
+int syrk_tile_for(int64_t n) { return n <= 640 ? CfgSyrk64::BM : CfgSyrk::BM; }
 
 int syrk_splits(int64_t n, int64_t kb_n, int64_t nz) {
-  const int64_t T = cdiv(n, CfgSyrk::BM);
+  const int64_t T = cdiv(n, syrk_tile_for(n));
   return balanced_splits(T * (T + 1) / 2 * (nz > 0 ? nz : 1), kb_n);
 }
 
-hipError_t launch_syrk_partial(const OpMap& A, const OpMap& Bw, int64_t n, int64_t nz, int nsplit, double* Kpart,
-                               hipStream_t s) {
-  typedef CfgSyrk Cg;
+template <class Cg>
+static hipError_t syrk_go(const OpMap& A, const OpMap& Bw, int64_t n, int64_t nz, int nsplit, double* Kpart,
+                          hipStream_t s) {
   const int64_t T = cdiv(n, Cg::BM);
   const int64_t npairs = T * (T + 1) / 2;
   if (npairs == 0 || nz == 0) return hipSuccess;
@@ -1014,6 +1049,12 @@ hipError_t launch_syrk_partial(const OpMap& A, const OpMap& Bw, int64_t n, int64
   else if (clamp) syrk_kernel<Cg, false, true><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
   else syrk_kernel<Cg, false, false><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
   return hipGetLastError();
+}
+
+hipError_t launch_syrk_partial(const OpMap& A, const OpMap& Bw, int64_t n, int64_t nz, int nsplit, double* Kpart,
+                               hipStream_t s) {
+  return syrk_tile_for(n) == CfgSyrk64::BM ? syrk_go<CfgSyrk64>(A, Bw, n, nz, nsplit, Kpart, s)
+                                           : syrk_go<CfgSyrk>(A, Bw, n, nz, nsplit, Kpart, s);
 }
 
 // ---- grouped launches ----
@@ -1042,9 +1083,8 @@ hipError_t launch_half_group(const GroupHalf* probs, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_syrk_group(const GroupSyrk* probs, int n, hipStream_t s) {
-  if (n < 1 || n > kMaxGroup) return hipErrorInvalidValue;
-  typedef CfgSyrk Cg;
+template <class Cg>
+static hipError_t syrk_group_go(const GroupSyrk* probs, int n, hipStream_t s) {
   SyrkGroup g{};
   g.n = n;
   g.start[0] = 0;
@@ -1068,6 +1108,18 @@ hipError_t launch_syrk_group(const GroupSyrk* probs, int n, hipStream_t s) {
   if (clamp) syrk_group_kernel<Cg, true><<<(unsigned)g.start[n], Cg::NT, 0, s>>>(g);
   else syrk_group_kernel<Cg, false><<<(unsigned)g.start[n], Cg::NT, 0, s>>>(g);
   return hipGetLastError();
+}
+
+int syrk_group_tile(const GroupSyrk* probs, int n) {
+  int64_t nmax = 0;
+  for (int p = 0; p < n; ++p) nmax = probs[p].n > nmax ? probs[p].n : nmax;
+  return syrk_tile_for(nmax);
+}
+
+hipError_t launch_syrk_group(const GroupSyrk* probs, int n, hipStream_t s) {
+  if (n < 1 || n > kMaxGroup) return hipErrorInvalidValue;
+  return syrk_group_tile(probs, n) == CfgSyrk64::BM ? syrk_group_go<CfgSyrk64>(probs, n, s)
+                                                   : syrk_group_go<CfgSyrk>(probs, n, s);
 }
 
 hipError_t launch_syrk_reduce(const double* Kpart, int nsplit, int64_t n, int64_t nz, double* K, hipStream_t s) {
