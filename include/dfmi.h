@@ -276,9 +276,13 @@ df_status df_split_matmul(df_ctx* ctx, const double* A, int64_t lda, int64_t M, 
 /*
  * One-time split of the Cholesky vectors for df_step_split: the rows (P, mu) of the unpacked
  * b^P (Eq. cholesky) as int8 planes.
- *   Bs [nslice][naux * nao][kpad64(nao)] int8 (kpad64(n) = n rounded up to a multiple of 64),
- *   Be [naux * nao] int32 exponents; both caller-owned device buffers, overwritten.
- *   naux * nao < 2^31.  No workspace.
+ *   Bs: nslice * R * kpad64(nao) int8 (R = naux * nao rounded up to a multiple of 32, kpad64(n) =
+ *   n rounded up to a multiple of 64) in 1 KB blocks of 32 rows x 32 k: block (s, g, b) of slice
+ *   s, row group g, k block b at byte ((s * R / 32 + g) * kpad64(nao) / 32 + b) * 1024, its
+ *   16-byte slot rr + 32 c holding k = 32 b + 16 c + [0, 16) of row 32 g + rr; zeros past the
+ *   last row and past nao.  Row r = P * nao + mu is b^P_{mu, k} over k.
+ *   Be [naux * nao] int32 exponents; both caller-owned device buffers, overwritten; Bs 16-byte
+ *   aligned (DF_ERR_ARG otherwise).  naux * nao <= 2^31 - 32.  No workspace.
  */
 df_status df_split_cholesky(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int nslice, int8_t* Bs,
                             int* Be, int flags);

@@ -181,31 +181,32 @@ BwdPlan plan_backward(Plan& pl, int64_t naux, int64_t nao, int64_t nocc, int64_t
 }
 
 // ---- split precision ----
-// Planes of an operand with `rows` rows and contraction length K: [nslice][rows][kpad64(K)] int8
-// and [rows] int32 exponents.
+// Planes of an operand with `rows` rows and contraction length K (split_plane_bytes: 1 KB blocks
+// of 32 rows x 32 k) and [rows] int32 exponents.
 struct SplitBuf {
   size_t planes, ex;
 };
 SplitBuf take_split(Plan& pl, int64_t rows, int64_t K, int nslice) {
   SplitBuf b{};
-  const int64_t bytes = (int64_t)nslice * rows * dfk::kpad64(K);
+  const int64_t bytes = dfk::split_plane_bytes(rows, K, nslice);
   b.planes = pl.take((bytes + 7) / 8);
   b.ex = pl.take((rows * 4 + 7) / 8);
   return b;
 }
 
-// Split count for a slice product of `tiles` 64 x 64 tiles and nks 64-deep steps: about two
-// workgroups per CU (one resident per CU), at least 32 steps per split.  Long contractions
-// are cut further, to at most kSliceSteps steps per split, so that the operand rows of the
-// splits in flight stay within the 256 MB last-level cache.
-constexpr int64_t kSliceSteps = 256;
+// Split count for a slice product of `tiles` workgroup tiles and nks 32-deep steps: at least
+// one workgroup per CU (one is resident per CU), at least 32 steps per split.  Long
+// contractions are cut further, to at most kSliceSteps steps per split, so that the operand rows
+// of the splits in flight stay within the 256 MB last-level cache; that is also below the
+// longest split the int32 sums allow.
+constexpr int64_t kSliceSteps = 512;
+static_assert(kSliceSteps <= 1024, "a split longer than the exact int32 range");
 int slice_splits(int64_t tiles, int64_t nks) {
-  int64_t ns = tiles > 0 ? (512 + tiles - 1) / tiles : 1;
+  int64_t ns = tiles > 0 ? (256 + tiles - 1) / tiles : 1;
   const int64_t ns_cache = (nks + kSliceSteps - 1) / kSliceSteps;
-  if (ns < ns_cache) ns = ns_cache;
   if (ns > nks / 32) ns = nks / 32;
+  if (ns < ns_cache) ns = ns_cache;
   if (ns < 1) ns = 1;
-  if (ns > 4096) ns = 4096;
   return (int)ns;
 }
 
@@ -218,8 +219,7 @@ SplitMmPlan plan_split_mm(Plan& pl, int64_t M, int64_t N, int64_t K, int nslice)
   SplitMmPlan p{};
   p.a = take_split(pl, M, K, nslice);
   p.b = take_split(pl, N, K, nslice);
-  const int64_t T = dfk::slice_gemm_tile();
-  p.nsplit = slice_splits(((M + T - 1) / T) * ((N + T - 1) / T), dfk::kpad64(K) / 64);
+  p.nsplit = slice_splits(dfk::slice_gemm_tiles(M, N, false), dfk::slice_gemm_steps(dfk::kpad64(K)));
   p.part = pl.take(p.nsplit > 1 ? (int64_t)p.nsplit * M * N : 0);
   return p;
 }
@@ -233,7 +233,7 @@ struct StepSplitPlan {
 StepSplitPlan plan_step_split(Plan& pl, int64_t naux, int64_t nao, int64_t nocc, int64_t nac, int64_t np,
                               int nslice) {
   StepSplitPlan p{};
-  const int64_t ncol = nocc + nac, T = dfk::slice_gemm_tile();
+  const int64_t ncol = nocc + nac;
   p.ccat = pl.take(nao * ncol);
   p.xo = pl.take(naux * nao * nocc);     // P-major [naux][nao][nocc]
   p.xa = pl.take(naux * nao * nac);      // P-major [naux][nao][nac]
@@ -241,8 +241,7 @@ StepSplitPlan plan_step_split(Plan& pl, int64_t naux, int64_t nao, int64_t nocc,
   p.buv = pl.take(naux * nac * nac);
   p.cs = take_split(pl, ncol, nao, nslice);
   p.xos = take_split(pl, nocc > 0 ? nao : 0, naux * nocc, nslice);
-  const int64_t tk = (nao + T - 1) / T;
-  p.nsk = slice_splits(tk * (tk + 1) / 2, dfk::kpad64(naux * nocc) / 64);
+  p.nsk = slice_splits(dfk::slice_gemm_tiles(nao, nao, true), dfk::slice_gemm_steps(dfk::kpad64(naux * nocc)));
   p.kpart = pl.take(nocc > 0 ? (int64_t)p.nsk * nao * nao : 0);
   p.vtmp = pl.take(naux);
   p.xas = take_split(pl, naux * nac, nao, nslice);
@@ -996,7 +995,8 @@ df_status df_split_matmul(df_ctx* ctx, const double* A, int64_t lda, int64_t M, 
   if (M > 0 && (!A || lda < K)) return fail(c, DF_ERR_ARG, "A is NULL or lda < K");
   if (N > 0 && (!Bm || ldb < K)) return fail(c, DF_ERR_ARG, "B is NULL or ldb < K");
   if (M > 0 && N > 0 && (!C || ldc < N)) return fail(c, DF_ERR_ARG, "C is NULL or ldc < N");
-  if (M > 0x7fffffffLL || N > 0x7fffffffLL) return fail(c, DF_ERR_SHAPE, "M and N must be below 2^31");
+  if (dfk::rpad32(M) > 0x7fffffffLL || dfk::rpad32(N) > 0x7fffffffLL || K > (1LL << 30))
+    return fail(c, DF_ERR_SHAPE, "M and N must be below 2^31 - 32 and K at most 2^30");
   std::vector<Range> rs = {{A, dbytes(M > 0 ? (M - 1) * lda + K : 0), "A", false},
                            {Bm, dbytes(N > 0 ? (N - 1) * ldb + K : 0), "B", false},
                            {C, dbytes(M > 0 && N > 0 ? (M - 1) * ldc + N : 0), "C", true}};
@@ -1033,10 +1033,11 @@ df_status df_split_cholesky(df_ctx* ctx, const double* B, int64_t naux, int64_t 
   if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_split_cholesky takes no flags");
   if (nslice < 4 || nslice > 8) return fail(c, DF_ERR_SHAPE, "nslice must be in [4, 8]");
   if (!Bs || !Be) return fail(c, DF_ERR_ARG, "Bs and Be are required");
-  if (naux * nao > 0x7fffffffLL) return fail(c, DF_ERR_SHAPE, "naux * nao must be below 2^31");
+  if ((uintptr_t)Bs % 16 != 0) return fail(c, DF_ERR_ARG, "Bs must be 16-byte aligned");
+  if (dfk::rpad32(naux * nao) > 0x7fffffffLL) return fail(c, DF_ERR_SHAPE, "naux * nao must be below 2^31 - 32");
   const int64_t npair = nao * (nao + 1) / 2;
   std::vector<Range> rs = {{B, dbytes(naux * npair), "B", false},
-                           {Bs, (size_t)nslice * naux * nao * dfk::kpad64(nao), "Bs", true},
+                           {Bs, (size_t)dfk::split_plane_bytes(naux * nao, nao, nslice), "Bs", true},
                            {Be, (size_t)naux * nao * 4, "Be", true}};
   if (!check_overlap(c, rs)) return DF_ERR_ARG;
   if (df_status s = enter(c)) return s;
@@ -1054,16 +1055,18 @@ df_status df_step_split(df_ctx* ctx, const double* B, const int8_t* Bs, const in
   if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_step_split takes no flags");
   if (nslice < 4 || nslice > 8) return fail(c, DF_ERR_SHAPE, "nslice must be in [4, 8]");
   if (!Bs || !Be) return fail(c, DF_ERR_ARG, "Bs and Be (from df_split_cholesky) are required");
+  if ((uintptr_t)Bs % 16 != 0) return fail(c, DF_ERR_ARG, "Bs must be 16-byte aligned");
   if (nocc < 0 || nac < 0 || np < 0) return fail(c, DF_ERR_SHAPE, "sizes must be >= 0");
   if (nocc > 0 && !Cocc) return fail(c, DF_ERR_ARG, "Cocc is NULL");
   if (nac > 0 && !Cact) return fail(c, DF_ERR_ARG, "Cact is NULL");
   if (np > 0 && !Cp) return fail(c, DF_ERR_ARG, "Cp is NULL");
-  if (naux * nao > 0x7fffffffLL || naux * nac > 0x7fffffffLL || np * nac > 0x7fffffffLL)
+  if (dfk::rpad32(naux * nao) > 0x7fffffffLL || dfk::rpad32(naux * nac) > 0x7fffffffLL ||
+      dfk::rpad32(np * nac) > 0x7fffffffLL || naux * nocc > (1LL << 30))
     return fail(c, DF_ERR_SHAPE, "problem too large for the split path");
   const int64_t npair = nao * (nao + 1) / 2;
   const int64_t ncol = nocc + nac;
   std::vector<Range> rs = {{B, dbytes(naux * npair), "B", false},
-                           {Bs, (size_t)nslice * naux * nao * dfk::kpad64(nao), "Bs", false},
+                           {Bs, (size_t)dfk::split_plane_bytes(naux * nao, nao, nslice), "Bs", false},
                            {Be, (size_t)naux * nao * 4, "Be", false},
                            {Cocc, dbytes(nao * nocc), "Cocc", false},
                            {Cact, dbytes(nao * nac), "Cact", false},

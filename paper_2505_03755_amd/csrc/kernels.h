@@ -135,21 +135,31 @@ struct GroupSyrk {
 hipError_t launch_syrk_group(const GroupSyrk* probs, int n, hipStream_t s);
 
 // ---- split precision (split.hip) ----
-// n rounded up to a multiple of the 64-deep int8 contraction step.
+// n rounded up to a multiple of 64 (contraction length of the planes) and of 32 (their rows).
 int64_t kpad64(int64_t n);
+int64_t rpad32(int64_t n);
+// Bytes of the planes of an operand: nslice * rpad32(rows) * kpad64(K), in 1 KB blocks of 32 rows
+// x 32 k; block (s, g, b) at ((s * G + g) * KB + b) KB (G = rpad32(rows) / 32, KB = kpad64(K) / 32),
+// slot l = rr + 32 c (16 bytes) of it holding k = 32 b + 16 c + [0, 16) of row 32 g + rr.
+int64_t split_plane_bytes(int64_t rows, int64_t K, int nslice);
 // Splits each row r < o.rows of the operand (k over kb_n * kc_n = K) into nslice int8 planes
-// [nslice][rows][kpad64(K)] (zeros past K) and its exponent ex[r].  nslice in [4, 8].
+// (zeros past K and past o.rows) and its exponent ex[r].  nslice in [4, 8].
 hipError_t launch_split_rows(const OpMap& o, int64_t K, int nslice, int8_t* planes, int* ex, hipStream_t s);
 // The same for the rows (P, m) of the unpacked b^P (rows naux*nao, K = nao).
 hipError_t launch_split_packed(const double* B, int64_t naux, int64_t nao, int nslice, int8_t* planes, int* ex,
                                hipStream_t s);
-// C(m, n) = sum_k A(m, k) B(n, k) from the split planes of A [nslice][M][kp] and B [nslice][N][kp]
-// (kp a multiple of 64), written through O (alpha / accumulate honoured) or, with nsplit > 1, as
-// partial sums part[split][M][N] over k ranges.  With tri (M == N) only the 64 x 64 tiles on and
-// below the diagonal are formed.
+// C(m, n) = sum_k A(m, k) B(n, k) from the split planes of A (M rows) and B (N rows) with
+// kp = kpad64(K), written through O (alpha / accumulate honoured) or, with nsplit > 1, as partial
+// sums part[split][M][N] over k ranges.  Every split must be at most slice_gemm_max_steps() steps
+// of 32 k long (the int32 sums are exact up to there).  With tri (M == N) tiles wholly above the
+// diagonal are skipped; the tiles on it are written whole.
 hipError_t launch_slice_gemm(const int8_t* A, const int* ea, int64_t M, const int8_t* B, const int* eb, int64_t N,
                              int64_t kp, int nslice, const OutMap& O, bool tri, int nsplit, double* part,
                              hipStream_t s);
-int slice_gemm_tile();
+// Workgroup tiles of a slice product that do work, 32-deep steps of a contraction of kp, and
+// the longest split in steps.
+int64_t slice_gemm_tiles(int64_t M, int64_t N, bool tri);
+int64_t slice_gemm_steps(int64_t kp);
+int64_t slice_gemm_max_steps();
 
 }  // namespace dfk

@@ -12,10 +12,11 @@
 // per d), after which the int32 sums are flushed into FP64 as F += 2^(-7 d) I_d.  The result is
 // 2^(e_a + e_b - 12) F.
 //
-// Planes are [S][rows][kp] int8 with kp a multiple of 64 and zeros past K; exponents [rows] int32.
+// Planes are int8 in 1 KB blocks of 32 rows x 32 k (layout below); exponents [rows] int32.
 //
-// Operand layout of v_mfma_i32_16x16x64_i8 (checked on gfx950): A[i][k] in lane i + 16 (k / 16),
-// byte k % 16 (B likewise with its column j); D[i][j] in lane j + 16 (i / 4), element i % 4.
+// Operand layout of v_mfma_i32_32x32x32_i8 (checked on gfx950): A[i][k] in lane i + 32 (k / 16),
+// byte k % 16 (B likewise with its column j); D[i][j] in lane j + 32 ((i / 4) % 2), element
+// 4 (i / 8) + i % 4.  global_load_lds with 16 bytes puts lane l's data at the LDS address + 16 l.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -25,10 +26,19 @@
 namespace dfk {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
 
 namespace {
 
 constexpr int kSplitBits0 = 6, kSplitBits = 7;
+
+// s_waitcnt immediate that waits until at most N vector-memory operations are outstanding
+// (vmcnt in bits 3:0 and 15:14; expcnt and lgkmcnt at their maxima, i.e. not waited on)
+template <int N>
+struct kVmcnt {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  static constexpr int imm = (N & 15) | (((N >> 4) & 3) << 14) | (7 << 4) | (15 << 8);
+};
 
 // Block index -> work item with runs of consecutive items on one XCD (the dispatcher deals
 // consecutive workgroups to the 8 XCDs in turn).
@@ -44,18 +54,6 @@ __device__ __forceinline__ int row_exponent(double m) {
   return e;
 }
 
-// slices of x * 2^-e (|.| < 1), written to planes[s * plane + off]
-template <int S>
-__device__ __forceinline__ void write_slices(double x, int e, int8_t* planes, int64_t plane, int64_t off) {
-  double r = ldexp(x, kSplitBits0 - e);
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const double a = rint(r);
-    planes[s * plane + off] = (int8_t)(int)a;
-    r = (r - a) * (double)(1 << kSplitBits);
-  }
-}
-
 // max |.| over one row, by one 256-thread workgroup
 __device__ __forceinline__ double block_max(double v) {
   __shared__ double red[4];
@@ -69,11 +67,20 @@ __device__ __forceinline__ double block_max(double v) {
   return v;
 }
 
+// Plane layout.  The planes of an operand with `rows` rows and contraction length K hold
+// rpad32(rows) rows (zeros past `rows`) and kp = kpad64(K) k (zeros past K), cut into 1 KB blocks
+// of 32 rows x 32 k: block (s, g, b) of slice s, row group g, k block b starts at byte
+// ((s * G + g) * KB + b) * 1024 (G = rpad32(rows) / 32, KB = kp / 32), and its 16-byte slot
+// l = rr + 32 c holds the 16 k = 32 b + 16 c + [0, 16) of row 32 g + rr -- the operand fragment
+// of matrix-core lane l.  A block is one contiguous 1 KB load and one conflict-free LDS read.
+__device__ __forceinline__ int64_t block_offset(int s, int64_t g, int64_t b, int64_t G, int64_t KB) {
+  return (((int64_t)s * G + g) * KB + b) * 1024;
+}
+
 // Rows of a dense operand given as an OpMap; the contraction index k = kb * kc_n + kc runs over
-// K = kb_n * kc_n.  Work is cut into chunks of kSplitChunk k per workgroup (grid x = chunk,
-// y = row): one pass takes the chunk maxima into the row exponent with an integer atomic max
-// (exponents order like the magnitudes), a second writes the slices, four k per thread as one
-// 32-bit word per plane.
+// K = kb_n * kc_n.  The exponent pass cuts each row into chunks of kSplitChunk k per workgroup
+// (grid x = chunk, y = row) and takes the chunk maxima into the row exponent with an integer
+// atomic max (exponents order like the magnitudes).
 constexpr int kSplitChunk = 1024;
 constexpr int kNoExponent = -1000;   // rows that are all zero keep this (their slices are 0)
 
@@ -116,42 +123,69 @@ __global__ void __launch_bounds__(256) split_max_kernel(OpMap o, int64_t K, int6
   if (threadIdx.x == 0 && m > 0.0) atomicMax(ex + r, row_exponent(m));
 }
 
+// 16 scaled values of one slot -> its 16 bytes in each of the S planes
 template <int S>
-__global__ void __launch_bounds__(256) split_slice_kernel(OpMap o, int64_t K, int64_t kp, int64_t r0, int8_t* planes,
-                                                          const int* ex) {
-  const int64_t r = r0 + blockIdx.y, k = (int64_t)blockIdx.x * kSplitChunk + 4 * threadIdx.x;
-  if (k >= kp) return;
-  const double* row = opmap_row(o, r);
-  const int e = ex[r];
-  const int64_t plane = o.rows * kp;
-  double x[4];
-  KWalk w(o, k < K ? k : 0, 1);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    x[q] = k + q < K ? ldexp(row[w.off(o)], kSplitBits0 - e) : 0.0;
-    w.next();
-  }
+__device__ __forceinline__ void write_slot(double (&x)[16], int8_t* planes, int64_t G, int64_t KB, int64_t g,
+                                           int64_t b, int slot) {
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    uint32_t w = 0;
+    v4i w = {0, 0, 0, 0};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 16; ++q) {
       const double a = rint(x[q]);
-      w |= ((uint32_t)(int)a & 0xffu) << (8 * q);
+      w[q >> 2] |= (int)(((uint32_t)(int)a & 0xffu) << (8 * (q & 3)));
       x[q] = (x[q] - a) * (double)(1 << kSplitBits);
     }
-    *(uint32_t*)(planes + s * plane + r * kp + k) = w;
+    *(v4i*)(planes + block_offset(s, g, b, G, KB) + slot * 16) = w;
   }
 }
 
-// Row (P, m) of the unpacked b^P: element k = b^P_{mk}, packed at T(max) + min.
+// One workgroup per (row group g = blockIdx.x, 128 k); thread t fills slot (rr = t % 32,
+// 16 k at 16 (t / 32)) of its block in every plane; rows past o.rows are zero.
+template <int S>
+__global__ void __launch_bounds__(256) split_slice_kernel(OpMap o, int64_t K, int64_t kp, int64_t y0, int8_t* planes,
+                                                          const int* ex) {
+  const int t = threadIdx.x, rr = t & 31;
+  const int64_t g = blockIdx.x, kq = (y0 + blockIdx.y) * 8 + (t >> 5);   // 16-k chunk
+  if (16 * kq >= kp) return;
+  const int64_t r = 32 * g + rr, k = 16 * kq;
+  double x[16];
+  if (r < o.rows) {
+    const double* row = opmap_row(o, r);
+    const int e = ex[r];
+    KWalk w(o, k < K ? k : 0, 1);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      x[q] = k + q < K ? ldexp(row[w.off(o)], kSplitBits0 - e) : 0.0;
+      w.next();
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) x[q] = 0.0;
+  }
+  write_slot<S>(x, planes, (o.rows + 31) / 32, kp / 32, g, kq >> 1, rr + 32 * (int)(kq & 1));
+}
+
+// Row r = (P, m) of the unpacked b^P (element k = b^P_{mk}, packed at T(max) + min), one
+// workgroup per row of rpad32(naux * nao); rows past naux * nao are zero.
 template <int S>
 __global__ void __launch_bounds__(256) split_packed_kernel(const double* __restrict__ B, int64_t nao, int64_t npair,
                                                            int64_t kp, int8_t* planes, int* ex, int64_t rows) {
   const int64_t r = blockIdx.x;
+  const int t = threadIdx.x;
+  const int64_t G = (rows + 31) / 32, KB = kp / 32, g = r / 32;
+  const int rr = (int)(r % 32);
+  if (r >= rows) {
+    double z[16];
+    for (int64_t kq = t; kq < kp / 16; kq += 256) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) z[q] = 0.0;
+      write_slot<S>(z, planes, G, KB, g, kq >> 1, rr + 32 * (int)(kq & 1));
+    }
+    return;
+  }
   const int64_t P = r / nao, m = r % nao;
   const double* Bp = B + P * npair;
-  const int t = threadIdx.x;
   auto elem = [&](int64_t k) {
     const int64_t hi = m > k ? m : k, lo = m > k ? k : m;
     return Bp[hi * (hi + 1) / 2 + lo];
@@ -160,151 +194,150 @@ __global__ void __launch_bounds__(256) split_packed_kernel(const double* __restr
   for (int64_t k = t; k < nao; k += 256) mx = fmax(mx, fabs(elem(k)));
   const int e = row_exponent(block_max(mx));
   if (t == 0) ex[r] = e;
-  const int64_t plane = rows * kp;
-  for (int64_t k = t; k < kp; k += 256) write_slices<S>(k < nao ? elem(k) : 0.0, e, planes, plane, r * kp + k);
+  double x[16];
+  for (int64_t kq = t; kq < kp / 16; kq += 256) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) x[q] = 16 * kq + q < nao ? ldexp(elem(16 * kq + q), kSplitBits0 - e) : 0.0;
+    write_slot<S>(x, planes, G, KB, g, kq >> 1, rr + 32 * (int)(kq & 1));
+  }
 }
 
 // ---------------------------------------------------------------------------------------
-// Slice product.  Workgroup tile 64 x 64 over 8 waves (2 x 4) of 32 x 16 (two MFMA tiles), k steps
-// of 64 bytes through one LDS stage refilled from registers between two barriers; the global
-// loads of the next step are in flight while the current one is multiplied.  About 200
-// registers per lane: two waves per SIMD, accumulators in VGPRs.  With `tri`, only tiles
-// I >= J of a square output are formed (the lower half of a symmetric product).
-constexpr int kTM = 64, kKB = 64, kRow = 80;   // LDS row pitch 80 bytes: conflict-free operand reads
-constexpr int kFlushSteps = 512;               // 32768 k per int32 accumulation
+// Slice product.  Workgroup tile 128 x 64 over 8 waves (4 x 2) of 32 x 32, one
+// v_mfma_i32_32x32x32_i8 per slice pair and 32-deep k step.  Each k step moves S (4 + 2) blocks
+// of 1 KB from HBM / L2 straight into LDS (global_load_lds, no staging registers), three LDS
+// stages deep; a wave reads its S + S operand fragments as one 16-byte LDS read per lane each.
+// One int32 accumulator per slice diagonal d = s + t (exact over kMaxSteps steps = 32768 k, so
+// every split is at most that long and no FP64 sums are kept in the loop).  About 200 registers
+// per lane: two waves per SIMD.  With `tri` (M == N), tiles wholly above the diagonal exit.
+constexpr int kGM = 128, kGN = 64, kKS = 32, kStages = 3;
+constexpr int kMaxSteps = 1024;
 
 template <int S>
-struct I8Tile {
-  static constexpr int LDS = 2 * S * kTM * kRow;   // A then B, slices outer
+struct SliceTile {
+  static constexpr int GA = kGM / 32, GB = kGN / 32;
+  static constexpr int NBLK = S * (GA + GB);        // blocks per k step
+  static constexpr int STAGE = NBLK * 1024;
+  static constexpr int LPW = (NBLK + 7) / 8;        // direct loads per wave and step (at most)
+  static constexpr int LPW_MIN = NBLK / 8;          // ... and at least
 };
 
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
 template <int S, bool GEN>
-__global__ void __launch_bounds__(512) slice_gemm_kernel(const int8_t* __restrict__ Ap, const int* __restrict__ ea,
-                                                         int64_t M, const int8_t* __restrict__ Bp,
-                                                         const int* __restrict__ eb, int64_t N, int64_t kp,
-                                                         OutMap O, int64_t tilesM, int64_t tilesN, int tri,
-                                                         int64_t ntri, double* part) {
-  __shared__ __attribute__((aligned(16))) int8_t lds[I8Tile<S>::LDS];
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wm = wave & 1, wn = wave >> 1;      // rows 32 wm.., columns 16 wn..
+__global__ void __launch_bounds__(512, 1) slice_gemm_kernel(const int8_t* __restrict__ Ap, const int* __restrict__ ea,
+                                                            int64_t M, const int8_t* __restrict__ Bp,
+                                                            const int* __restrict__ eb, int64_t N, int64_t KB,
+                                                            OutMap O, int64_t tilesM, int64_t tilesN, int tri,
+                                                            double* part) {
+  typedef SliceTile<S> T;
+  __shared__ __attribute__((aligned(1024))) int8_t lds[kStages * T::STAGE];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wm = wave & 3, wn = wave >> 2;
   const int nsplit = gridDim.y, split = blockIdx.y;
-  int64_t I, J;
-  if (tri) {
-    const int64_t pr = xcd_remap_i8(blockIdx.x, ntri);
-    I = (int64_t)((sqrt(8.0 * (double)pr + 1.0) - 1.0) * 0.5);
-    while (I * (I + 1) / 2 > pr) --I;
-    while ((I + 1) * (I + 2) / 2 <= pr) ++I;
-    J = pr - I * (I + 1) / 2;
-  } else {
-    // column tiles of one row block side by side (on one XCD): the row block is read once
-    const int64_t tile = xcd_remap_i8(blockIdx.x, tilesM * tilesN);
-    I = tile / tilesN;
-    J = tile % tilesN;
+  const int64_t tile = xcd_remap_i8(blockIdx.x, tilesM * tilesN);
+  const int64_t I = tile / tilesN, J = tile % tilesN;   // column tiles of one row band side by side
+  if (tri && J * kGN > I * kGM + kGM - 1) return;       // no element on or below the diagonal
+  const int64_t GAn = (M + 31) / 32, GBn = (N + 31) / 32;
+  const int64_t ks0 = KB * split / nsplit, ks1 = KB * (split + 1) / nsplit;
+
+  // this wave's direct loads: blocks j = wave + 8 i of the step (A blocks s * GA + g first)
+  const int8_t* gp[T::LPW];
+  int loff[T::LPW];
+#pragma unroll
+  for (int i = 0; i < T::LPW; ++i) {
+    int j = wave + 8 * i;
+    if (j >= T::NBLK) j = T::NBLK - 1;   // unused slot (never issued)
+    loff[i] = j * 1024;
+    if (j < S * T::GA) {
+      const int s = j / T::GA;
+      int64_t g = I * T::GA + j % T::GA;
+      if (g >= GAn) g = GAn - 1;         // past the last row group: its outputs are not stored
+      gp[i] = Ap + block_offset(s, g, 0, GAn, KB) + 16 * lane;
+    } else {
+      const int s = (j - S * T::GA) / T::GB;
+      int64_t g = J * T::GB + (j - S * T::GA) % T::GB;
+      if (g >= GBn) g = GBn - 1;
+      gp[i] = Bp + block_offset(s, g, 0, GBn, KB) + 16 * lane;
+    }
   }
-  const int64_t m0 = I * kTM, n0 = J * kTM;
-  const int64_t nks = kp / kKB;
-  const int64_t ks0 = nks * split / nsplit, ks1 = nks * (split + 1) / nsplit;
-
-  // global -> register staging: threads 0..255 load A, 256..511 load B: 16 bytes of row
-  // (t % 256) / 4, chunk t % 4, of every slice
-  const int side = t >> 8, lr = (t & 255) >> 2, lc = (t & 3) * 16;
-  const int64_t rows = side ? N : M, r0 = side ? n0 : m0;
-  const int64_t rr = r0 + lr < rows ? r0 + lr : rows - 1;
-  const int64_t plane = rows * kp;
-  const int8_t* g = (side ? Bp : Ap) + rr * kp + lc;
-  int8_t* lw = lds + (side * S * kTM + lr) * kRow + lc;
-  // two register stages: the loads of step k + 2 go out while step k + 1 is still in flight
-  v4i st[2][S];
-  auto gload = [&](int b, int64_t ks) {
+  auto issue = [&](int st, int64_t ks) {
 #pragma unroll
-    for (int s = 0; s < S; ++s) st[b][s] = *(const v4i*)(g + s * plane + ks * kKB);
-  };
-  auto lstore = [&](int b) {
-#pragma unroll
-    for (int s = 0; s < S; ++s) *(v4i*)(lw + s * kTM * kRow) = st[b][s];
+    for (int i = 0; i < T::LPW; ++i)
+      if (i < T::LPW_MIN || wave + 8 * i < T::NBLK)
+        __builtin_amdgcn_global_load_lds((const void*)(gp[i] + ks * 1024), (lds_ptr_t)(lds + st * T::STAGE + loff[i]),
+                                         16, 0, 0);
   };
 
-  v4i acc[S][2];
-  double F[2][4];
+  v16i acc[S];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int d = 0; d < S; ++d)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) F[i][r] = 0.0;
+    for (int e = 0; e < 16; ++e) acc[d][e] = 0;
 
-  // operand fragment reads: row / column (lane % 16) of a 16-row tile, bytes 16 (lane / 16)
-  const int fr = lane & 15, fk = (lane >> 4) * 16;
-  const int8_t* la = lds + (wm * 32 + fr) * kRow + fk;
-  const int8_t* lb = lds + (S * kTM + wn * 16 + fr) * kRow + fk;
-  // one k step: registers of stage b to LDS, refill stage b with step ks + 2, multiply
-  auto step = [&](int b, int64_t ks) {
-    __syncthreads();   // the previous step's reads of LDS are done
-    lstore(b);
-    __syncthreads();
-    if (ks + 2 < ks1) gload(b, ks + 2);
-    v4i fb[S];
+  const int8_t* fa0 = lds + wm * 1024 + 16 * lane;
+  const int8_t* fb0 = lds + (S * T::GA + wn) * 1024 + 16 * lane;
 #pragma unroll
-    for (int s = 0; s < S; ++s) fb[s] = *(const v4i*)(lb + s * kTM * kRow);
+  for (int p = 0; p < kStages - 1; ++p)
+    if (ks0 + p < ks1) issue(p, ks0 + p);
+  int st = 0;
+  for (int64_t ks = ks0; ks < ks1; ++ks) {
+    // this wave's loads of step ks have landed once at most the next step's are outstanding
+    if (ks + 1 < ks1) __builtin_amdgcn_s_waitcnt(kVmcnt<T::LPW_MIN>::imm);
+    else __builtin_amdgcn_s_waitcnt(kVmcnt<0>::imm);
+    // every wave's loads of step ks are in LDS, and its reads of step ks - 1 (into the stage the
+    // next issue overwrites) are done.  A plain barrier: a workgroup fence would also wait for
+    // the loads of step ks + 1.
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    if (ks + kStages - 1 < ks1) issue(st == 0 ? kStages - 1 : st - 1, ks + kStages - 1);
+    v4i fa[S], fb[S];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      v4i fa[S];
-#pragma unroll
-      for (int s = 0; s < S; ++s) fa[s] = *(const v4i*)(la + (s * kTM + i * 16) * kRow);
-#pragma unroll
-      for (int s = 0; s < S; ++s)
-#pragma unroll
-        for (int u = 0; u + s < S; ++u)
-          acc[s + u][i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[s], fb[u], acc[s + u][i], 0, 0, 0);
+    for (int s = 0; s < S; ++s) {
+      fa[s] = *(const v4i*)(fa0 + st * T::STAGE + s * T::GA * 1024);
+      fb[s] = *(const v4i*)(fb0 + st * T::STAGE + s * T::GB * 1024);
     }
-  };
-  if (ks1 > ks0) gload(0, ks0);
-  if (ks1 > ks0 + 1) gload(1, ks0 + 1);
-  for (int64_t kc = ks0; kc < ks1; kc += kFlushSteps) {   // chunks start at even offsets from ks0
-    const int64_t kend = kc + kFlushSteps < ks1 ? kc + kFlushSteps : ks1;
 #pragma unroll
-    for (int d = 0; d < S; ++d)
+    for (int s = 0; s < S; ++s)
 #pragma unroll
-      for (int i = 0; i < 2; ++i) acc[d][i] = v4i{0, 0, 0, 0};
-    for (int64_t ks = kc; ks < kend; ks += 2) {
-      step(0, ks);
-      if (ks + 1 < kend) step(1, ks + 1);
-    }
-    // int32 sums of this chunk into FP64
-#pragma unroll
-    for (int d = 0; d < S; ++d)
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) F[i][r] += ldexp((double)acc[d][i][r], -kSplitBits * d);
+      for (int u = 0; u + s < S; ++u) acc[s + u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[s], fb[u], acc[s + u], 0, 0, 0);
+    st = st == kStages - 1 ? 0 : st + 1;
   }
 
-  // epilogue: value = 2^(ea + eb - 12) F
+  // epilogue: value = 2^(ea + eb - 12) sum_d 2^(-7 d) I_d.  D[i][j] of the 32 x 32 tile is in
+  // lane j + 32 ((i / 4) % 2), element 4 (i / 8) + i % 4.
+  const int64_t m0 = I * kGM + 32 * wm, n = J * kGN + 32 * wn + (lane & 31);
+  if (n >= N) return;
+  const int ebn = eb[n];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int e = 0; e < 16; ++e) {
+    const int64_t m = m0 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+    if (m >= M) continue;
+    double F = 0.0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t m = m0 + wm * 32 + i * 16 + (lane >> 4) * 4 + r;
-      const int64_t n = n0 + wn * 16 + (lane & 15);
-      if (m >= M || n >= N) continue;
-      const double val = ldexp(F[i][r], ea[m] + eb[n] - 2 * kSplitBits0);
-      if (part) {
-        part[((int64_t)split * M + m) * N + n] = val;
+    for (int d = S - 1; d >= 0; --d) F += ldexp((double)acc[d][e], -kSplitBits * d);
+    const double val = ldexp(F, ea[m] + ebn - 2 * kSplitBits0);
+    if (part) {
+      part[((int64_t)split * M + m) * N + n] = val;
+    } else {
+      double* dst;
+      if (n < O.nsplit) {
+        const int64_t nh = O.s_nh ? n / O.nl : 0, mh = O.s_mh ? m / O.ml : 0;
+        dst = O.p + (mh * O.s_mh + (m - mh * O.ml) * O.s_ml) + (nh * O.s_nh + (n - nh * O.nl) * O.s_nl);
       } else {
-        double* dst;
-        if (n < O.nsplit) {
-          const int64_t nh = O.s_nh ? n / O.nl : 0, mh = O.s_mh ? m / O.ml : 0;
-          dst = O.p + (mh * O.s_mh + (m - mh * O.ml) * O.s_ml) + (nh * O.s_nh + (n - nh * O.nl) * O.s_nl);
-        } else {
-          dst = O.p2 + m * O.s2_m + (n - O.nsplit);
-        }
-        if (GEN) *dst = O.accumulate ? *dst + O.alpha * val : O.alpha * val;
-        else *dst = val;
+        dst = O.p2 + m * O.s2_m + (n - O.nsplit);
       }
+      if (GEN) *dst = O.accumulate ? *dst + O.alpha * val : O.alpha * val;
+      else *dst = val;
     }
+  }
 }
 
 }  // namespace
 
 int64_t kpad64(int64_t n) { return (n + 63) / 64 * 64; }
+int64_t rpad32(int64_t n) { return (n + 31) / 32 * 32; }
+int64_t split_plane_bytes(int64_t rows, int64_t K, int nslice) { return (int64_t)nslice * rpad32(rows) * kpad64(K); }
 
 template <int S>
 static hipError_t split_rows_s(const OpMap& o, int64_t K, int8_t* planes, int* ex, hipStream_t s) {
@@ -314,17 +347,17 @@ static hipError_t split_rows_s(const OpMap& o, int64_t K, int8_t* planes, int* e
     const unsigned nr = (unsigned)(o.rows - r0 < 65535 ? o.rows - r0 : 65535);
     split_max_kernel<<<dim3((unsigned)((K + kSplitChunk - 1) / kSplitChunk), nr), 256, 0, s>>>(o, K, r0, ex);
   }
-  for (int64_t r0 = 0; r0 < o.rows; r0 += 65535) {
-    const unsigned nr = (unsigned)(o.rows - r0 < 65535 ? o.rows - r0 : 65535);
-    split_slice_kernel<S><<<dim3((unsigned)((kp + kSplitChunk - 1) / kSplitChunk), nr), 256, 0, s>>>(o, K, kp, r0,
-                                                                                                      planes, ex);
+  const int64_t ny = (kp + 127) / 128;   // grid y carries 128 k
+  for (int64_t y0 = 0; y0 < ny; y0 += 65535) {
+    const unsigned n = (unsigned)(ny - y0 < 65535 ? ny - y0 : 65535);
+    split_slice_kernel<S><<<dim3((unsigned)(rpad32(o.rows) / 32), n), 256, 0, s>>>(o, K, kp, y0, planes, ex);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_split_rows(const OpMap& o, int64_t K, int nslice, int8_t* planes, int* ex, hipStream_t s) {
   if (o.rows <= 0) return hipSuccess;
-  if (o.rows > 0x7fffffffLL || K <= 0 || (kpad64(K) + kSplitChunk - 1) / kSplitChunk > 0x7fffffffLL)
+  if (rpad32(o.rows) > 0x7fffffffLL || K <= 0 || (K + kSplitChunk - 1) / kSplitChunk > 0x7fffffffLL)
     return hipErrorInvalidValue;
   switch (nslice) {
     case 4: return split_rows_s<4>(o, K, planes, ex, s);
@@ -340,7 +373,8 @@ template <int S>
 static hipError_t split_packed_s(const double* B, int64_t naux, int64_t nao, int8_t* planes, int* ex,
                                  hipStream_t s) {
   const int64_t rows = naux * nao;
-  split_packed_kernel<S><<<(unsigned)rows, 256, 0, s>>>(B, nao, nao * (nao + 1) / 2, kpad64(nao), planes, ex, rows);
+  split_packed_kernel<S><<<(unsigned)rpad32(rows), 256, 0, s>>>(B, nao, nao * (nao + 1) / 2, kpad64(nao), planes, ex,
+                                                                rows);
   return hipGetLastError();
 }
 
@@ -348,7 +382,7 @@ hipError_t launch_split_packed(const double* B, int64_t naux, int64_t nao, int n
                                hipStream_t s) {
   const int64_t rows = naux * nao;
   if (rows <= 0) return hipSuccess;
-  if (rows > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (rpad32(rows) > 0x7fffffffLL) return hipErrorInvalidValue;
   switch (nslice) {
     case 4: return split_packed_s<4>(B, naux, nao, planes, ex, s);
     case 5: return split_packed_s<5>(B, naux, nao, planes, ex, s);
@@ -359,15 +393,30 @@ hipError_t launch_split_packed(const double* B, int64_t naux, int64_t nao, int n
   }
 }
 
+static int64_t slice_tiles_m(int64_t M) { return (M + kGM - 1) / kGM; }
+static int64_t slice_tiles_n(int64_t N) { return (N + kGN - 1) / kGN; }
+
+int64_t slice_gemm_tiles(int64_t M, int64_t N, bool tri) {
+  const int64_t tm = slice_tiles_m(M), tn = slice_tiles_n(N);
+  if (!tri) return tm * tn;
+  int64_t c = 0;
+  for (int64_t I = 0; I < tm; ++I) {
+    const int64_t jmax = (I * kGM + kGM - 1) / kGN + 1;
+    c += jmax < tn ? jmax : tn;
+  }
+  return c;
+}
+int64_t slice_gemm_steps(int64_t kp) { return kp / kKS; }
+int64_t slice_gemm_max_steps() { return kMaxSteps; }
+
 template <int S>
 static void slice_gemm_s(const int8_t* A, const int* ea, int64_t M, const int8_t* B, const int* eb, int64_t N,
                          int64_t kp, const OutMap& O, bool tri, int nsplit, double* part, hipStream_t s) {
-  const int64_t tm = (M + kTM - 1) / kTM, tn = (N + kTM - 1) / kTM;
-  const int64_t ntri = tm * (tm + 1) / 2;
-  const dim3 grid((unsigned)(tri ? ntri : tm * tn), (unsigned)nsplit, 1);
+  const int64_t tm = slice_tiles_m(M), tn = slice_tiles_n(N);
+  const dim3 grid((unsigned)(tm * tn), (unsigned)nsplit, 1);
   const bool gen = !part && (O.alpha != 1.0 || O.accumulate);
-  if (gen) slice_gemm_kernel<S, true><<<grid, 512, 0, s>>>(A, ea, M, B, eb, N, kp, O, tm, tn, tri, ntri, part);
-  else slice_gemm_kernel<S, false><<<grid, 512, 0, s>>>(A, ea, M, B, eb, N, kp, O, tm, tn, tri, ntri, part);
+  if (gen) slice_gemm_kernel<S, true><<<grid, 512, 0, s>>>(A, ea, M, B, eb, N, kp / kKS, O, tm, tn, tri, part);
+  else slice_gemm_kernel<S, false><<<grid, 512, 0, s>>>(A, ea, M, B, eb, N, kp / kKS, O, tm, tn, tri, part);
 }
 
 hipError_t launch_slice_gemm(const int8_t* A, const int* ea, int64_t M, const int8_t* B, const int* eb, int64_t N,
@@ -376,8 +425,9 @@ hipError_t launch_slice_gemm(const int8_t* A, const int* ea, int64_t M, const in
   if (M <= 0 || N <= 0) return hipSuccess;
   if (kp % 64 != 0 || kp <= 0 || nsplit < 1 || nsplit > 65535 || (tri && M != N) || (nsplit > 1 && !part))
     return hipErrorInvalidValue;
-  const int64_t tm = (M + kTM - 1) / kTM, tn = (N + kTM - 1) / kTM;
-  if ((tri ? tm * (tm + 1) / 2 : tm * tn) > 0x7fffffffLL) return hipErrorInvalidValue;
+  // every split at most kMaxSteps steps long: the int32 diagonal sums stay exact
+  if ((kp / kKS + nsplit - 1) / nsplit > kMaxSteps) return hipErrorInvalidValue;
+  if (slice_tiles_m(M) * slice_tiles_n(N) > 0x7fffffffLL) return hipErrorInvalidValue;
   switch (nslice) {
     case 4: slice_gemm_s<4>(A, ea, M, B, eb, N, kp, O, tri, nsplit, part, s); break;
     case 5: slice_gemm_s<5>(A, ea, M, B, eb, N, kp, O, tri, nsplit, part, s); break;
@@ -388,7 +438,5 @@ hipError_t launch_slice_gemm(const int8_t* A, const int* ea, int64_t M, const in
   }
   return hipGetLastError();
 }
-
-int slice_gemm_tile() { return kTM; }
 
 }  // namespace dfk

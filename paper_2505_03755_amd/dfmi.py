@@ -414,6 +414,17 @@ def kpad64(n: int) -> int:
     return (n + 63) // 64 * 64
 
 
+def rpad32(n: int) -> int:
+    return (n + 31) // 32 * 32
+
+
+def split_plane_shape(rows: int, K: int, nslice: int):
+    """Shape of the int8 planes of `rows` rows of length K: [nslice][row group][k block][1024],
+    1 KB blocks of 32 rows x 32 k whose 16-byte slot rr + 32 c holds k = 32 b + 16 c + [0, 16) of
+    row 32 g + rr (zeros past `rows` and past K)."""
+    return (nslice, rpad32(rows) // 32, kpad64(K) // 32, 1024)
+
+
 def split_matmul(A, B, nslice: int = 7, ctx: Context | None = None):
     """C = A B^T by the int8 slice method (df_split_matmul); A [M, K], B [N, K] FP64 on the GPU."""
     import torch
@@ -431,12 +442,13 @@ def split_matmul(A, B, nslice: int = 7, ctx: Context | None = None):
 
 
 def split_cholesky(B, nao: int, nslice: int = 7, ctx: Context | None = None):
-    """int8 planes [nslice, naux*nao, kpad64(nao)] and exponents [naux*nao] of the unpacked b^P rows."""
+    """int8 planes (split_plane_shape(naux*nao, nao, nslice)) and exponents [naux*nao] of the
+    unpacked b^P rows."""
     import torch
     ctx = ctx or context(B.device)
     _check_tensor("B", B, ctx.device)
     naux = _naux_of(B, nao)
-    Bs = torch.empty((nslice, naux * nao, kpad64(nao)), dtype=torch.int8, device=ctx.device)
+    Bs = torch.empty(split_plane_shape(naux * nao, nao, nslice), dtype=torch.int8, device=ctx.device)
     Be = torch.empty((naux * nao,), dtype=torch.int32, device=ctx.device)
     ctx.bind_stream()
     ctx.check(ctx._lib.df_split_cholesky(ctx.handle, _ptr(B), naux, nao, nslice, _ptr(Bs), _ptr(Be), 0))
@@ -451,7 +463,7 @@ def step_split(B, Bs, Be, nao: int, Cocc, Cact, Cp, outputs=None, ctx: Context |
         _check_tensor(n, t, ctx.device)
     naux = _naux_of(B, nao)
     nslice = Bs.shape[0]
-    if (Bs.dtype != torch.int8 or Be.dtype != torch.int32 or tuple(Bs.shape) != (nslice, naux * nao, kpad64(nao))
+    if (Bs.dtype != torch.int8 or Be.dtype != torch.int32 or tuple(Bs.shape) != split_plane_shape(naux * nao, nao, nslice)
             or tuple(Be.shape) != (naux * nao,) or Bs.device != dev_of(ctx) or Be.device != dev_of(ctx)
             or not Bs.is_contiguous() or not Be.is_contiguous()):
         raise ValueError("Bs, Be must come from split_cholesky(B, nao) on the same device")

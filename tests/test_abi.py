@@ -192,17 +192,21 @@ def test_split_argument_errors(L, ctx):
     Bs, Be = fake(4 << 30), fake(5 << 30)
     assert L.df_split_cholesky(ctx, B, 10, 7, 7, None, Be, 0) == dfmi.DF_ERR_ARG
     assert L.df_split_cholesky(ctx, B, 10, 7, 2, Bs, Be, 0) == dfmi.DF_ERR_SHAPE
+    assert L.df_split_cholesky(ctx, B, 10, 7, 7, fake((4 << 30) + 8), Be, 0) == dfmi.DF_ERR_ARG   # Bs unaligned
     s = L.df_step_split
     Co, Ca, Cp, J, K = fake(6 << 30), fake(7 << 30), fake(8 << 30), fake(9 << 30), fake(10 << 30)
     assert s(ctx, B, None, Be, 7, 10, 7, Co, 3, Ca, 2, Cp, 7, J, K, None, None, None, 0) == dfmi.DF_ERR_ARG
     assert s(ctx, B, Bs, Be, 7, 10, 7, None, 3, Ca, 2, Cp, 7, J, K, None, None, None, 0) == dfmi.DF_ERR_ARG
     assert s(ctx, B, Bs, Be, 3, 10, 7, Co, 3, Ca, 2, Cp, 7, J, K, None, None, None, 0) == dfmi.DF_ERR_SHAPE
+    Bu = fake((4 << 30) + 8)
+    assert s(ctx, B, Bu, Be, 7, 10, 7, Co, 3, Ca, 2, Cp, 7, J, K, None, None, None, 0) == dfmi.DF_ERR_ARG
     assert s(ctx, B, Bs, Be, 7, 10, 7, Co, 3, Ca, 2, Cp, 7, J, K, None, None, None, 0) == dfmi.DF_ERR_WORKSPACE
 
 
 def test_split_workspace_sizes():
     w = dfmi.workspace_size(dfmi.DF_OP_SPLIT_MATMUL, m=100, n=50, k=70, nslice=7)
-    assert w >= 7 * (100 + 50) * 128 + 4 * 150         # planes padded to 128 columns + exponents
+    assert w >= 7 * (128 + 64) * 128 + 4 * 150         # planes: rows to 32, columns to 64; exponents
+    assert dfmi.split_plane_shape(100, 70, 7) == (7, 4, 4, 1024)
     s5 = dfmi.workspace_size(dfmi.DF_OP_STEP_SPLIT, naux=20, nao=9, nocc=4, nac=2, np=9, nslice=5)
     s7 = dfmi.workspace_size(dfmi.DF_OP_STEP_SPLIT, naux=20, nao=9, nocc=4, nac=2, np=9, nslice=7)
     assert s7 > s5 > 0

@@ -75,13 +75,17 @@ def test_split_cholesky_reconstructs_rows(S, nao, naux):
     Bp = synth.cholesky_vectors(naux, nao, 8.0, seed=nao)
     Bs, Be = dfmi.split_cholesky(dev(Bp), nao, nslice=S)
     torch.cuda.synchronize()
-    planes = Bs.cpu().numpy().astype(np.float64)        # [S][naux*nao][kp]
+    blocks = Bs.cpu().numpy().astype(np.float64)         # [S][row group][k block][1024]
+    G, KB = blocks.shape[1], blocks.shape[2]
+    assert blocks.shape == (S, (naux * nao + 31) // 32, (nao + 63) // 64 * 2, 1024)
+    # slot rr + 32 c of block (s, g, b) holds k = 32 b + 16 c + [0, 16) of row 32 g + rr
+    planes = blocks.reshape(S, G, KB, 2, 32, 16).transpose(0, 1, 4, 2, 3, 5).reshape(S, 32 * G, 32 * KB)
     ex = Be.cpu().numpy().astype(np.float64)
     assert np.abs(planes).max() <= 64
     full = O.unpack(Bp, nao).reshape(naux * nao, nao)     # rows (P, mu)
     assert np.array_equal(ex, row_exp(full))
-    kp = planes.shape[2]
-    assert kp % 64 == 0 and kp >= nao and not planes[:, :, nao:].any()
+    assert not planes[:, :, nao:].any() and not planes[:, naux * nao:, :].any()
+    planes = planes[:, :naux * nao, :]
     rec = sum(planes[s, :, :nao] * np.exp2(-6 - 7 * s) for s in range(S)) * np.exp2(ex)[:, None]
     assert np.all(np.abs(rec - full) <= np.exp2(ex - 7 * S)[:, None])
 
