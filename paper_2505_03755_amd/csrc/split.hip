@@ -81,7 +81,7 @@ __device__ __forceinline__ int64_t block_offset(int s, int64_t g, int64_t b, int
 // K = kb_n * kc_n.  The exponent pass cuts each row into chunks of kSplitChunk k per workgroup
 // (grid x = chunk, y = row) and takes the chunk maxima into the row exponent with an integer
 // atomic max (exponents order like the magnitudes).
-constexpr int kSplitChunk = 1024;
+constexpr int kSplitChunk = 4096;
 constexpr int kNoExponent = -1000;   // rows that are all zero keep this (their slices are 0)
 
 __device__ __forceinline__ const double* opmap_row(const OpMap& o, int64_t r) {
@@ -121,6 +121,33 @@ __global__ void __launch_bounds__(256) split_max_kernel(OpMap o, int64_t K, int6
   }
   m = block_max(m);
   if (threadIdx.x == 0 && m > 0.0) atomicMax(ex + r, row_exponent(m));
+}
+
+// The same for operands whose rows are adjacent in memory (row stride 1, contraction index far
+// apart): 32 rows x kSplitChunkR k per workgroup with the lanes along the rows, so that every
+// load reads 32 consecutive rows.
+constexpr int kSplitChunkR = 256;
+__global__ void __launch_bounds__(256) split_max_rows_kernel(OpMap o, int64_t K, int64_t y0, int* ex) {
+  const int t = threadIdx.x, rr = t & 31, kk = t >> 5;
+  const int64_t r = 32 * (int64_t)blockIdx.x + rr, k0 = (y0 + blockIdx.y) * kSplitChunkR;
+  double m = 0.0;
+  if (r < o.rows) {
+    const double* row = opmap_row(o, r);
+    KWalk w(o, k0 + kk, 8);
+    for (int64_t k = k0 + kk; k < K && k < k0 + kSplitChunkR; k += 8) {
+      m = fmax(m, fabs(row[w.off(o)]));
+      w.next();
+    }
+  }
+  // the 8 threads of a row: lanes rr and rr + 32 of each of the 4 waves
+  m = fmax(m, __shfl_xor(m, 32));
+  __shared__ double red[4][32];
+  if ((t & 63) < 32) red[t >> 6][rr] = m;
+  __syncthreads();
+  if (t < 32) {
+    m = fmax(fmax(red[0][t], red[1][t]), fmax(red[2][t], red[3][t]));
+    if (r < o.rows && m > 0.0) atomicMax(ex + r, row_exponent(m));
+  }
 }
 
 // 16 scaled values of one slot -> its 16 bytes in each of the S planes
@@ -164,6 +191,36 @@ __global__ void __launch_bounds__(256) split_slice_kernel(OpMap o, int64_t K, in
     for (int q = 0; q < 16; ++q) x[q] = 0.0;
   }
   write_slot<S>(x, planes, (o.rows + 31) / 32, kp / 32, g, kq >> 1, rr + 32 * (int)(kq & 1));
+}
+
+// The same for operands whose contraction index is contiguous (s_kc = 1): the 32 rows x 128 k of
+// the workgroup are first read along k into LDS (coalesced), then cut slot by slot.
+template <int S>
+__global__ void __launch_bounds__(256) split_slice_kmajor_kernel(OpMap o, int64_t K, int64_t kp, int64_t y0,
+                                                                 int8_t* planes, const int* ex) {
+  __shared__ double tile[32][129];
+  const int t = threadIdx.x;
+  const int64_t g = blockIdx.x, k0 = (y0 + blockIdx.y) * 128;
+  {
+    // element (32 g + (t >> 7) + 2 j, k0 + (t & 127)): one column k per thread
+    const int64_t k = k0 + (t & 127);
+    const int64_t koff = k < K ? (k / o.kc_n) * o.s_kb + (k % o.kc_n) * o.s_kc : 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int rr = (t >> 7) + 2 * j;
+      const int64_t r = 32 * g + rr;
+      tile[rr][t & 127] = r < o.rows && k < K ? opmap_row(o, r)[koff] : 0.0;
+    }
+  }
+  __syncthreads();
+  const int rr = t & 31, kq = t >> 5;
+  const int64_t r = 32 * g + rr, kq16 = k0 / 16 + kq;
+  if (16 * kq16 >= kp) return;
+  const int e = r < o.rows ? ex[r] : 0;
+  double x[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) x[q] = ldexp(tile[rr][16 * kq + q], kSplitBits0 - e);
+  write_slot<S>(x, planes, (o.rows + 31) / 32, kp / 32, g, kq16 >> 1, rr + 32 * (int)(kq16 & 1));
 }
 
 // Row r = (P, m) of the unpacked b^P (element k = b^P_{mk}, packed at T(max) + min), one
@@ -276,6 +333,8 @@ __global__ void __launch_bounds__(512, 1) slice_gemm_kernel(const int8_t* __rest
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc[d][e] = 0;
 
+  // a wave whose 32 rows or 32 columns all lie past the end only takes part in loads and barriers
+  const bool live = I * kGM + 32 * wm < M && J * kGN + 32 * wn < N;
   const int8_t* fa0 = lds + wm * 1024 + 16 * lane;
   const int8_t* fb0 = lds + (S * T::GA + wn) * 1024 + 16 * lane;
 #pragma unroll
@@ -291,6 +350,10 @@ __global__ void __launch_bounds__(512, 1) slice_gemm_kernel(const int8_t* __rest
     // the loads of step ks + 1.
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
     if (ks + kStages - 1 < ks1) issue(st == 0 ? kStages - 1 : st - 1, ks + kStages - 1);
+    if (!live) {
+      st = st == kStages - 1 ? 0 : st + 1;
+      continue;
+    }
     v4i fa[S], fb[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -342,15 +405,27 @@ int64_t split_plane_bytes(int64_t rows, int64_t K, int nslice) { return (int64_t
 template <int S>
 static hipError_t split_rows_s(const OpMap& o, int64_t K, int8_t* planes, int* ex, hipStream_t s) {
   const int64_t kp = kpad64(K);
+  const unsigned ng = (unsigned)(rpad32(o.rows) / 32);
+  // rows adjacent in memory with the contraction index elsewhere: lanes along the rows
+  const bool rows_adjacent = o.s_rlo == 1 && o.s_kc != 1;
   fill_int_kernel<<<(unsigned)((o.rows + 255) / 256), 256, 0, s>>>(ex, o.rows, kNoExponent);
-  for (int64_t r0 = 0; r0 < o.rows; r0 += 65535) {   // grid y carries the row
-    const unsigned nr = (unsigned)(o.rows - r0 < 65535 ? o.rows - r0 : 65535);
-    split_max_kernel<<<dim3((unsigned)((K + kSplitChunk - 1) / kSplitChunk), nr), 256, 0, s>>>(o, K, r0, ex);
+  if (rows_adjacent) {
+    const int64_t ny = (K + kSplitChunkR - 1) / kSplitChunkR;
+    for (int64_t y0 = 0; y0 < ny; y0 += 65535) {
+      const unsigned n = (unsigned)(ny - y0 < 65535 ? ny - y0 : 65535);
+      split_max_rows_kernel<<<dim3(ng, n), 256, 0, s>>>(o, K, y0, ex);
+    }
+  } else {
+    for (int64_t r0 = 0; r0 < o.rows; r0 += 65535) {   // grid y carries the row
+      const unsigned nr = (unsigned)(o.rows - r0 < 65535 ? o.rows - r0 : 65535);
+      split_max_kernel<<<dim3((unsigned)((K + kSplitChunk - 1) / kSplitChunk), nr), 256, 0, s>>>(o, K, r0, ex);
+    }
   }
   const int64_t ny = (kp + 127) / 128;   // grid y carries 128 k
   for (int64_t y0 = 0; y0 < ny; y0 += 65535) {
     const unsigned n = (unsigned)(ny - y0 < 65535 ? ny - y0 : 65535);
-    split_slice_kernel<S><<<dim3((unsigned)(rpad32(o.rows) / 32), n), 256, 0, s>>>(o, K, kp, y0, planes, ex);
+    if (o.s_kc == 1) split_slice_kmajor_kernel<S><<<dim3(ng, n), 256, 0, s>>>(o, K, kp, y0, planes, ex);
+    else split_slice_kernel<S><<<dim3(ng, n), 256, 0, s>>>(o, K, kp, y0, planes, ex);
   }
   return hipGetLastError();
 }
