@@ -50,6 +50,18 @@ def test_split_matmul_within_bound(S, M, N, K):
     assert np.all(err <= bound(A, B, S)), (np.max(err / bound(A, B, S)))
 
 
+@pytest.mark.parametrize("S", [5, 7])
+def test_split_matmul_split_over_k(S):
+    """K = 40000: the product runs as several k splits (each at most 32768 k) and a fixed-order sum."""
+    rng = np.random.default_rng(41)
+    M, N, K = 70, 50, 40000
+    A = rng.standard_normal((M, K)) * np.exp2(rng.integers(-10, 10, (M, 1)))
+    B = rng.standard_normal((N, K))
+    C = dfmi.split_matmul(dev(A), dev(B), nslice=S).cpu().numpy()
+    err = np.abs(C - A @ B.T)
+    assert np.all(err <= bound(A, B, S)), (np.max(err / bound(A, B, S)))
+
+
 def test_split_matmul_not_fp64_at_few_slices():
     """With 4 slices the method error dominates FP64 rounding: the int8 path really is in use."""
     rng = np.random.default_rng(5)
@@ -105,7 +117,7 @@ def split_problem(nao, naux, nocc, nac, S, seed=0, L=10.0):
 
 
 @pytest.mark.parametrize("nao,naux,nocc,nac", [(120, 480, 30, 8), (33, 17, 5, 3), (130, 9, 17, 5), (7, 70, 0, 3),
-                                               (9, 20, 4, 0)])
+                                               (9, 20, 4, 0), (40, 1100, 16, 3)])
 def test_step_split_matches_oracle(nao, naux, nocc, nac):
     Bp, C, gB, Bs, Be = split_problem(nao, naux, nocc, nac, 7, seed=nao + naux)
     Co, Ca = C[:, :nocc], C[:, nocc:nocc + nac]
