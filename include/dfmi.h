@@ -255,6 +255,31 @@ df_status df_batched_workspace_size(const df_problem* probs, int nprob, size_t* 
 df_status df_batched_step(df_ctx* ctx, const df_problem* probs, int nprob, int flags);
 
 /*
+ * Autotuning of df_batched_step's grouped launches (tile shapes chosen by measurement rather
+ * than by a fixed rule).  With enable != 0, the first df_batched_step on a problem group whose
+ * shape the context has not seen runs every candidate of each phase twice on the call's own
+ * buffers, timed with events on the context's stream.  The phases are the half-transform
+ * column tile (176, 96, 48) and the K tile (64, 128) with its split target (16, 4, 64 rounds of
+ * resident workgroups).  The call keeps the fastest of each phase in the context's table, keyed
+ * by every problem's (naux, nao, ndm, nocc, nac, np) and its requested outputs, then computes
+ * its outputs with them.
+ *   - Such a call waits for the GPU.  It is never made while the stream is being captured;
+ *     under capture the defaults (or a stored choice) are used.
+ *   - Later calls with the same shape use the stored choice, whether tuning is on or off.
+ *   - Results do not depend on the choice beyond FP64 rounding order.
+ *   - df_batched_workspace_size covers every candidate.
+ * df_batched_tuning reports the configuration df_batched_step would use for a group: the
+ * stored one (*tuned = 1) or the defaults (*tuned = 0).  df_batched_set_tuning stores a choice
+ * for a group's shape (each value from the candidate lists above, else DF_ERR_ARG), e.g. to
+ * replay a measured configuration.  None of these calls allocates device memory.
+ */
+df_status df_set_autotune(df_ctx* ctx, int enable);
+df_status df_batched_tuning(df_ctx* ctx, const df_problem* probs, int nprob, int* half_tile_n, int* k_tile,
+                            int* k_rounds, int* tuned);
+df_status df_batched_set_tuning(df_ctx* ctx, const df_problem* probs, int nprob, int half_tile_n, int k_tile,
+                                int k_rounds);
+
+/*
  * Split precision on the int8 matrix cores.  An FP64 row x is cut into nslice int8 slices,
  *   x[k] ~= 2^e sum_{s < nslice} a_s[k] 2^-(6 + 7 s),   a_s in [-64, 64],  max|x| < 2^e,
  * exactly up to a residual below 2^(e - 7 nslice); a product keeps the slice pairs with

@@ -7,8 +7,15 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <map>
 #include <string>
 #include <vector>
+
+// Configuration of the grouped launches of df_batched_step: column tile of the half transform,
+// K tile and the number of rounds of resident workgroups the K split counts aim at.
+struct BatchedTune {
+  int half_n, k_tile, k_rounds;
+};
 
 struct df_ctx {
   int device = 0;
@@ -25,6 +32,9 @@ struct df_ctx {
   std::vector<hipEvent_t> ev_pool;
   std::vector<Timed> pending;
   hipEvent_t cur_a = nullptr;
+  // autotuning of df_batched_step (df_set_autotune): configuration per problem-group shape
+  bool autotune = false;
+  std::map<std::string, BatchedTune> tune;
 };
 
 namespace {
@@ -264,11 +274,22 @@ int64_t batched_work(const df_problem& q) { return q.naux * q.nao * q.nao * batc
 // Split counts of the grouped K launch: every (density, split, tile pair) item gets about the
 // same number of 16-deep slabs, about sixteen rounds of resident workgroups in all, so that
 // the long contractions of the big problems do not run alone at the end.
-std::vector<int> batched_k_splits(const df_problem* probs, int n) {
+// Candidate configurations the autotuner times (the first of each is the default).
+constexpr int kHalfTiles[] = {176, 96, 48};
+constexpr int kKTiles[] = {64, 128};
+constexpr int kKRounds[] = {16, 4, 64};
+
+int batched_default_k_tile(const df_problem* probs, int n) {
   int64_t nmax = 0;
   for (int i = 0; i < n; ++i)
     if (probs[i].K && probs[i].nocc > 0) nmax = std::max(nmax, probs[i].nao);
-  const int64_t T = dfk::syrk_tile_for(nmax);
+  return dfk::syrk_tile_for(nmax);
+}
+
+// Split counts of the grouped K launch for K tile T: every (density, split, tile pair) item gets
+// about the same number of 16-deep slabs, about `rounds` rounds of resident workgroups in all, so
+// that the long contractions of the big problems do not run alone at the end.
+std::vector<int> batched_k_splits(const df_problem* probs, int n, int T, int rounds) {
   double total = 0.0;
   for (int i = 0; i < n; ++i) {
     const df_problem& q = probs[i];
@@ -276,7 +297,7 @@ std::vector<int> batched_k_splits(const df_problem* probs, int n) {
     const int64_t t = (q.nao + T - 1) / T;
     total += (double)(t * (t + 1) / 2) * q.ndm * q.naux * ((q.nocc + 15) / 16);
   }
-  const double target = std::max(64.0, total / (16.0 * 512.0));   // slabs per item
+  const double target = std::max(64.0, total / (rounds * 512.0));   // slabs per item
   std::vector<int> ns((size_t)n, 1);
   for (int i = 0; i < n; ++i) {
     const df_problem& q = probs[i];
@@ -287,12 +308,41 @@ std::vector<int> batched_k_splits(const df_problem* probs, int n) {
   return ns;
 }
 
+// The most splits any candidate configuration asks for (the workspace holds that many partials).
+std::vector<int> batched_k_splits_max(const df_problem* probs, int n) {
+  std::vector<int> m((size_t)n, 1);
+  for (int T : kKTiles)
+    for (int r : kKRounds) {
+      const std::vector<int> ns = batched_k_splits(probs, n, T, r);
+      for (int i = 0; i < n; ++i) m[(size_t)i] = std::max(m[(size_t)i], ns[(size_t)i]);
+    }
+  return m;
+}
+
+BatchedTune batched_default_tune(const df_problem* probs, int n) {
+  return BatchedTune{kHalfTiles[0], batched_default_k_tile(probs, n), kKRounds[0]};
+}
+
+// The shape of a problem group: what the work and hence the best configuration depend on.
+std::string batched_key(const df_problem* probs, int n) {
+  std::string k;
+  for (int i = 0; i < n; ++i) {
+    const df_problem& q = probs[i];
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%lld,%lld,%lld,%lld,%lld,%lld,%d%d%d%d;", (long long)q.naux, (long long)q.nao,
+                  (long long)q.ndm, (long long)q.nocc, (long long)q.nac, (long long)q.np, q.J != nullptr,
+                  q.K != nullptr, q.eri != nullptr, q.papa != nullptr);
+    k += buf;
+  }
+  return k;
+}
+
 // J of many densities as one product: Jp[z][pair] = sum_P v[z][P] b^P[pair] (then unpacked)
 bool batched_j_gemm(const df_problem& q) { return q.ndm > 4; }
 
 std::vector<BatchedPiece> plan_batched(Plan& pl, const df_problem* probs, int n) {
   std::vector<BatchedPiece> v((size_t)n);
-  const std::vector<int> ks = batched_k_splits(probs, n);
+  const std::vector<int> ks = batched_k_splits_max(probs, n);
   for (int i = 0; i < n; ++i) {
     const df_problem& q = probs[i];
     BatchedPiece& b = v[(size_t)i];
@@ -1186,6 +1236,40 @@ df_status df_step_split(df_ctx* ctx, const double* B, const int8_t* Bs, const in
   return DF_OK;
 }
 
+df_status df_set_autotune(df_ctx* ctx, int enable) {
+  if (!ctx) return DF_ERR_ARG;
+  ctx->autotune = enable != 0;
+  return DF_OK;
+}
+
+df_status df_batched_tuning(df_ctx* ctx, const df_problem* probs, int nprob, int* half_tile_n, int* k_tile,
+                            int* k_rounds, int* tuned) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (nprob < 0 || (nprob > 0 && !probs)) return fail(c, DF_ERR_ARG, "probs is NULL");
+  if (!half_tile_n || !k_tile || !k_rounds || !tuned) return fail(c, DF_ERR_ARG, "output pointers are NULL");
+  BatchedTune tu = batched_default_tune(probs, nprob);
+  const auto it = c->tune.find(batched_key(probs, nprob));
+  *tuned = it != c->tune.end();
+  if (*tuned) tu = it->second;
+  *half_tile_n = tu.half_n;
+  *k_tile = tu.k_tile;
+  *k_rounds = tu.k_rounds;
+  return DF_OK;
+}
+
+df_status df_batched_set_tuning(df_ctx* ctx, const df_problem* probs, int nprob, int half_tile_n, int k_tile,
+                                int k_rounds) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (nprob < 0 || (nprob > 0 && !probs)) return fail(c, DF_ERR_ARG, "probs is NULL");
+  auto in = [](int v, const int* set, int n) { return std::find(set, set + n, v) != set + n; };
+  if (!in(half_tile_n, kHalfTiles, 3) || !in(k_tile, kKTiles, 2) || !in(k_rounds, kKRounds, 3))
+    return fail(c, DF_ERR_ARG, "not a candidate configuration");
+  c->tune[batched_key(probs, nprob)] = BatchedTune{half_tile_n, k_tile, k_rounds};
+  return DF_OK;
+}
+
 df_status df_batched_workspace_size(const df_problem* probs, int nprob, size_t* bytes) {
   if (!bytes || nprob < 0 || (nprob > 0 && !probs)) return DF_ERR_ARG;
   *bytes = 0;
@@ -1246,9 +1330,8 @@ df_status df_batched_step(df_ctx* ctx, const df_problem* probs, int nprob, int f
       if (q.K) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(q.K, q.ndm * q.nao * q.nao, c->stream), "fill");
     }
   }
-  // padded operands [C_1 .. C_ndm | Cact], then the grouped half transforms
+  // padded operands [C_1 .. C_ndm | Cact] and the descriptors of the grouped half transforms
   std::vector<dfk::GroupHalf> gh;
-  std::vector<dfk::GroupSyrk> gs;
   for (int i : order) {
     const df_problem& q = probs[i];
     const BatchedPiece& b = pc[(size_t)i];
@@ -1261,25 +1344,109 @@ df_status df_batched_step(df_ctx* ctx, const df_problem* probs, int nprob, int f
     if (df_status s = pad_operand(c, cp, q.nao, ncol, blks.data(), (int)blks.size())) return s;
     double* Xo = (double*)(ws + b.xo);
     double* Xa = (double*)(ws + b.xa);
-    const int64_t no = q.ndm * q.nocc;
-    gh.push_back({q.B, q.naux, q.nao, cp, ncol, ncol, out_split(Xo, Xa, q.naux, q.nao, no, q.nac)});
-    if (q.K && q.nocc > 0) {
-      dfk::OpMap A = dfk::op_map(Xo, q.nao, no, q.nocc, 1);
+    gh.push_back({q.B, q.naux, q.nao, cp, ncol, ncol, out_split(Xo, Xa, q.naux, q.nao, q.ndm * q.nocc, q.nac)});
+  }
+  auto run_half = [&](int tile_n) -> df_status {
+    for (size_t g0 = 0; g0 < gh.size(); g0 += dfk::kMaxGroup) {
+      const int n = (int)std::min<size_t>(dfk::kMaxGroup, gh.size() - g0);
+      DF_LAUNCH(DF_KERNEL_HALF_TRANSFORM, dfk::launch_half_group(gh.data() + g0, n, tile_n, c->stream),
+                "grouped half transform");
+    }
+    return DF_OK;
+  };
+  // grouped K tiles with the split counts of (tile, rounds), then the fixed-order reductions
+  auto run_k = [&](int tile, int rounds) -> df_status {
+    const std::vector<int> ns = batched_k_splits(probs, nprob, tile, rounds);
+    std::vector<dfk::GroupSyrk> gs;
+    for (int i : order) {
+      const df_problem& q = probs[i];
+      if (!q.K || q.nocc <= 0) continue;
+      const int64_t no = q.ndm * q.nocc;
+      dfk::OpMap A = dfk::op_map((const double*)(ws + pc[(size_t)i].xo), q.nao, no, q.nocc, 1);
       A.kb_n = q.naux;
       A.s_kb = q.nao * no;
       A.s_z = q.nocc;
-      gs.push_back({A, q.nao, q.ndm, b.nsplit, (double*)(ws + b.kpart)});
+      gs.push_back({A, q.nao, q.ndm, ns[(size_t)i], (double*)(ws + pc[(size_t)i].kpart)});
+    }
+    for (size_t g0 = 0; g0 < gs.size(); g0 += dfk::kMaxGroup) {
+      const int n = (int)std::min<size_t>(dfk::kMaxGroup, gs.size() - g0);
+      DF_LAUNCH(DF_KERNEL_K_SYRK, dfk::launch_syrk_group(gs.data() + g0, n, tile, c->stream), "grouped K tiles");
+    }
+    for (int i : order) {
+      const df_problem& q = probs[i];
+      if (!q.K || q.nocc <= 0) continue;
+      DF_LAUNCH(DF_KERNEL_K_REDUCE,
+                dfk::launch_syrk_reduce((double*)(ws + pc[(size_t)i].kpart), ns[(size_t)i], q.nao, q.ndm, q.K,
+                                        c->stream),
+                "K reduce launch");
+    }
+    return DF_OK;
+  };
+  BatchedTune tu = batched_default_tune(probs, nprob);
+  const std::string key = batched_key(probs, nprob);
+  const auto known = c->tune.find(key);
+  if (known != c->tune.end()) {
+    tu = known->second;
+  } else if (c->autotune) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    DF_HIP(hipStreamIsCapturing(c->stream, &cs), "hipStreamIsCapturing");
+    if (cs == hipStreamCaptureStatusNone) {
+      // time every candidate of each phase twice on these buffers (the best of the two counts);
+      // the half transform runs first, so that the K candidates read its X
+      hipEvent_t ea = nullptr, eb = nullptr;
+      if (df_status s = take_event(c, &ea)) return s;
+      if (df_status s = take_event(c, &eb)) {
+        c->ev_pool.push_back(ea);
+        return s;
+      }
+      const bool timing = c->timing;
+      c->timing = false;
+      auto best_of = [&](const auto& run, float* ms) -> df_status {
+        *ms = 3.0e38f;
+        for (int rep = 0; rep < 2; ++rep) {
+          DF_HIP(hipEventRecord(ea, c->stream), "hipEventRecord");
+          if (df_status s = run()) return s;
+          DF_HIP(hipEventRecord(eb, c->stream), "hipEventRecord");
+          DF_HIP(hipEventSynchronize(eb), "hipEventSynchronize");
+          float el = 0.0f;
+          DF_HIP(hipEventElapsedTime(&el, ea, eb), "hipEventElapsedTime");
+          *ms = std::min(*ms, el);
+        }
+        return DF_OK;
+      };
+      auto tune_all = [&]() -> df_status {
+        float best = 3.0e38f, ms = 0.0f;
+        for (int tn : kHalfTiles) {
+          if (df_status s = best_of([&] { return run_half(tn); }, &ms)) return s;
+          if (ms < best) {
+            best = ms;
+            tu.half_n = tn;
+          }
+        }
+        if (df_status s = run_half(tu.half_n)) return s;
+        best = 3.0e38f;
+        for (int kt : kKTiles)
+          for (int kr : kKRounds) {
+            if (df_status s = best_of([&] { return run_k(kt, kr); }, &ms)) return s;
+            if (ms < best) {
+              best = ms;
+              tu.k_tile = kt;
+              tu.k_rounds = kr;
+            }
+          }
+        return DF_OK;
+      };
+      const df_status ts = tune_all();
+      c->timing = timing;
+      c->ev_pool.push_back(ea);
+      c->ev_pool.push_back(eb);
+      if (ts != DF_OK) return ts;
+      c->tune[key] = tu;
     }
   }
-  for (size_t g0 = 0; g0 < gh.size(); g0 += 8) {
-    const int n = (int)std::min<size_t>(8, gh.size() - g0);
-    DF_LAUNCH(DF_KERNEL_HALF_TRANSFORM, dfk::launch_half_group(gh.data() + g0, n, c->stream), "grouped half transform");
-  }
-  for (size_t g0 = 0; g0 < gs.size(); g0 += 8) {
-    const int n = (int)std::min<size_t>(8, gs.size() - g0);
-    DF_LAUNCH(DF_KERNEL_K_SYRK, dfk::launch_syrk_group(gs.data() + g0, n, c->stream), "grouped K tiles");
-  }
-  // per problem: K reduction, J-vectors and J, active-space blocks
+  if (df_status s = run_half(tu.half_n)) return s;
+  if (df_status s = run_k(tu.k_tile, tu.k_rounds)) return s;
+  // per problem: J-vectors and J, active-space blocks
   for (int i : order) {
     const df_problem& q = probs[i];
     const BatchedPiece& b = pc[(size_t)i];
@@ -1288,9 +1455,6 @@ df_status df_batched_step(df_ctx* ctx, const df_problem* probs, int nprob, int f
     const double* Xo = (const double*)(ws + b.xo);
     const double* Xa = (const double*)(ws + b.xa);
     const int64_t no = q.ndm * q.nocc;
-    if (q.K && q.nocc > 0)
-      DF_LAUNCH(DF_KERNEL_K_REDUCE, dfk::launch_syrk_reduce((double*)(ws + b.kpart), b.nsplit, q.nao, q.ndm, q.K, c->stream),
-                "K reduce launch");
     if (q.J && q.nocc > 0) {
       double* v = (double*)(ws + b.v);
       DF_LAUNCH(DF_KERNEL_JVEC, dfk::launch_jvec(Xo, q.naux, q.nao, no, q.Cocc, nullptr, q.nocc, q.ndm, v, c->stream),

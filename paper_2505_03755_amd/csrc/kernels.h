@@ -116,6 +116,8 @@ hipError_t launch_unpack_sym(const double* Jp, int64_t nz, int64_t nao, double* 
 hipError_t launch_fill_zero_strided(double* p, int64_t nz, int64_t s_z, int64_t n, hipStream_t s);
 
 // ---- grouped launches over several problems (at most 8 per launch, largest first) ----
+// problems per grouped launch (their descriptors travel in the kernel arguments)
+constexpr int kMaxGroup = 8;
 // Half transform of problem p: as launch_half_transform with (B, naux, nao, C, ldc, ncol, out).
 struct GroupHalf {
   const double* B;
@@ -124,7 +126,8 @@ struct GroupHalf {
   int64_t ldc, ncol;
   OutMap out;
 };
-hipError_t launch_half_group(const GroupHalf* probs, int n, hipStream_t s);
+// tile_n: column tile of the launch, 176, 96 or 48 (0 = 176).
+hipError_t launch_half_group(const GroupHalf* probs, int n, int tile_n, hipStream_t s);
 // Lower-tile SYRK partials of problem p: as launch_syrk_partial with (A, A, n, nz, nsplit, Kpart).
 struct GroupSyrk {
   OpMap A;
@@ -132,7 +135,9 @@ struct GroupSyrk {
   int nsplit;
   double* Kpart;
 };
-hipError_t launch_syrk_group(const GroupSyrk* probs, int n, hipStream_t s);
+// tile: 64 or 128 (0 = syrk_group_tile()).
+hipError_t launch_syrk_group(const GroupSyrk* probs, int n, int tile, hipStream_t s);
+int syrk_group_tile(const GroupSyrk* probs, int n);
 
 // ---- split precision (split.hip) ----
 // n rounded up to a multiple of 64 (contraction length of the planes) and of 32 (their rows).

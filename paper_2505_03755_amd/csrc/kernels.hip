@@ -41,9 +41,6 @@ struct Cfg {
 
 // Every MFMA kernel is sized for two waves per SIMD (at most 256 registers per lane, two
 // workgroups' LDS per CU), so one wave's barrier and LDS latency hide behind the other's MFMAs.
-// problems per grouped launch (their descriptors travel in the kernel arguments)
-constexpr int kMaxGroup = 8;
-
 // generic products and the K SYRK: 128 x 128 tiles, 2 x 2 waves of 64 x 64, interleaved
 typedef Cfg<2, 2, 4, 4, true> CfgSq;
 typedef Cfg<2, 2, 4, 4, true> CfgSyrk;
@@ -1058,9 +1055,8 @@ hipError_t launch_syrk_partial(const OpMap& A, const OpMap& Bw, int64_t n, int64
 }
 
 // ---- grouped launches ----
-hipError_t launch_half_group(const GroupHalf* probs, int n, hipStream_t s) {
-  if (n < 1 || n > kMaxGroup) return hipErrorInvalidValue;
-  typedef CfgH176 Cg;
+template <class Cg>
+static hipError_t half_group_go(const GroupHalf* probs, int n, hipStream_t s) {
   HalfGroup g{};
   g.n = n;
   g.start[0] = 0;
@@ -1081,6 +1077,17 @@ hipError_t launch_half_group(const GroupHalf* probs, int n, hipStream_t s) {
   if (g.start[n] > 0x7fffffffLL) return hipErrorInvalidValue;
   half_group_kernel<Cg><<<(unsigned)g.start[n], Cg::NT, 0, s>>>(g);
   return hipGetLastError();
+}
+
+hipError_t launch_half_group(const GroupHalf* probs, int n, int tile_n, hipStream_t s) {
+  if (n < 1 || n > kMaxGroup) return hipErrorInvalidValue;
+  switch (tile_n) {
+    case 0:
+    case 176: return half_group_go<CfgH176>(probs, n, s);
+    case 96: return half_group_go<CfgH96>(probs, n, s);
+    case 48: return half_group_go<CfgH48>(probs, n, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <class Cg>
@@ -1116,10 +1123,12 @@ int syrk_group_tile(const GroupSyrk* probs, int n) {
   return syrk_tile_for(nmax);
 }
 
-hipError_t launch_syrk_group(const GroupSyrk* probs, int n, hipStream_t s) {
+hipError_t launch_syrk_group(const GroupSyrk* probs, int n, int tile, hipStream_t s) {
   if (n < 1 || n > kMaxGroup) return hipErrorInvalidValue;
-  return syrk_group_tile(probs, n) == CfgSyrk64::BM ? syrk_group_go<CfgSyrk64>(probs, n, s)
-                                                   : syrk_group_go<CfgSyrk>(probs, n, s);
+  if (tile == 0) tile = syrk_group_tile(probs, n);
+  if (tile == CfgSyrk64::BM) return syrk_group_go<CfgSyrk64>(probs, n, s);
+  if (tile == CfgSyrk::BM) return syrk_group_go<CfgSyrk>(probs, n, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_syrk_reduce(const double* Kpart, int nsplit, int64_t n, int64_t nz, double* K, hipStream_t s) {

@@ -43,7 +43,8 @@ KERNEL_KINDS = ["half_transform", "jvec", "coulomb", "k_syrk", "k_reduce", "mo_t
 EXPORTED = ["df_create", "df_destroy", "df_last_error", "df_set_stream", "df_set_workspace",
             "df_set_timing", "df_timing_read", "df_workspace_size", "df_half_transform", "df_jk",
             "df_active_eri", "df_papa", "df_step", "df_step_backward", "df_split_matmul",
-            "df_split_cholesky", "df_step_split", "df_batched_workspace_size", "df_batched_step"]
+            "df_split_cholesky", "df_step_split", "df_batched_workspace_size", "df_batched_step",
+            "df_set_autotune", "df_batched_tuning", "df_batched_set_tuning"]
 
 
 class DFError(RuntimeError):
@@ -94,6 +95,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         L.df_step_backward.argtypes = [vp, dp, i64, i64, dp, i64, dp, i64, dp, dp, dp, dp, dp, dp, dp, i32]
         L.df_batched_workspace_size.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_size_t)]
         L.df_batched_step.argtypes = [vp, vp, i32, i32]
+        L.df_set_autotune.argtypes = [vp, i32]
+        pi = ctypes.POINTER(ctypes.c_int)
+        L.df_batched_tuning.argtypes = [vp, vp, i32, pi, pi, pi, pi]
+        L.df_batched_set_tuning.argtypes = [vp, vp, i32, i32, i32, i32]
         L.df_split_matmul.argtypes = [vp, dp, i64, i64, dp, i64, i64, i64, i32, dp, i64, i32]
         L.df_split_cholesky.argtypes = [vp, dp, i64, i64, i32, vp, vp, i32]
         L.df_step_split.argtypes = [vp, dp, vp, vp, i32, i64, i64, dp, i64, dp, i64, dp, i64,
@@ -173,6 +178,10 @@ class Context:
         if self._ws is not None:
             self.check(self._lib.df_set_workspace(self._h, ctypes.c_void_p(self._ws.data_ptr()),
                                                   self._ws.numel()))
+
+    def set_autotune(self, on: bool):
+        """Tune df_batched_step's tiles on the first call of each new problem-group shape."""
+        self.check(self._lib.df_set_autotune(self._h, 1 if on else 0))
 
     def set_timing(self, on: bool):
         self.check(self._lib.df_set_timing(self._h, 1 if on else 0))
@@ -404,6 +413,36 @@ def batched_step(problems, ctx: Context | None = None):
         ctx.check(L.df_set_workspace(ctx._h, ctypes.c_void_p(ctx._ws.data_ptr()), ctx._ws.numel()))
     ctx.check(L.df_batched_step(ctx.handle, arr, len(problems), 0))
     return outs
+
+
+def _shape_array(problems):
+    """df_problem array carrying the sizes of `problems` and placeholder (never dereferenced)
+    output pointers: what the tuning calls read is the sizes and which outputs are requested."""
+    arr = (Problem * len(problems))()
+    one = 1
+    for i, pr in enumerate(problems):
+        nao = pr["nao"]
+        naux = _naux_of(pr["B"], nao)
+        Co, Ca, Cp = pr["Cocc"], pr["Cact"], pr["Cp"]
+        arr[i] = Problem(one, naux, nao, Co.shape[0], one, Co.shape[2], one, Ca.shape[1], one, Cp.shape[1],
+                         one, one, one, one)
+    return arr
+
+
+def batched_tuning(problems, ctx: Context | None = None) -> dict:
+    """Configuration df_batched_step uses for this group's shape (df_batched_tuning)."""
+    ctx = ctx or context(problems[0]["B"].device)
+    arr = _shape_array(problems)
+    v = [ctypes.c_int(0) for _ in range(4)]
+    ctx.check(ctx._lib.df_batched_tuning(ctx.handle, arr, len(problems), *[ctypes.byref(x) for x in v]))
+    return {"half_tile_n": v[0].value, "k_tile": v[1].value, "k_rounds": v[2].value, "tuned": bool(v[3].value)}
+
+
+def batched_set_tuning(problems, half_tile_n: int, k_tile: int, k_rounds: int, ctx: Context | None = None):
+    """Store a configuration for this group's shape (df_batched_set_tuning)."""
+    ctx = ctx or context(problems[0]["B"].device)
+    arr = _shape_array(problems)
+    ctx.check(ctx._lib.df_batched_set_tuning(ctx.handle, arr, len(problems), half_tile_n, k_tile, k_rounds))
 
 
 def dev_of(ctx):

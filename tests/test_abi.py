@@ -231,3 +231,30 @@ def test_batched_argument_errors(L, ctx):
     arr[1].ndm = 0
     assert L.df_batched_step(ctx, arr, 2, 0) == dfmi.DF_ERR_SHAPE
     assert L.df_batched_workspace_size(arr, 2, ctypes.byref(n)) == dfmi.DF_ERR_SHAPE
+
+
+def test_batched_tuning_table(L, ctx):
+    """The autotuning table: defaults, a stored choice per group shape, candidate checks."""
+    P = dfmi.Problem
+    arr = (P * 2)()
+    arr[0] = P(1 << 30, 10, 7, 2, 2 << 30, 3, 3 << 30, 2, 4 << 30, 7, 5 << 30, 6 << 30, None, None)
+    arr[1] = P(7 << 30, 12, 5, 1, 8 << 30, 2, None, 0, None, 0, 9 << 30, None, None, None)
+    v = [ctypes.c_int(-1) for _ in range(4)]
+    refs = [ctypes.byref(x) for x in v]
+
+    def read():
+        assert L.df_batched_tuning(ctx, arr, 2, *refs) == dfmi.DF_OK
+        return tuple(x.value for x in v)
+
+    assert read() == (176, 64, 16, 0)                      # defaults (N_ao <= 640: 64-wide K tiles)
+    assert L.df_batched_set_tuning(ctx, arr, 2, 96, 128, 4) == dfmi.DF_OK
+    assert read() == (96, 128, 4, 1)
+    arr[0].ndm = 3                                        # another shape: defaults again
+    assert read() == (176, 64, 16, 0)
+    arr[0].ndm = 2
+    assert read() == (96, 128, 4, 1)
+    for bad in ((100, 128, 4), (96, 32, 4), (96, 128, 5)):
+        assert L.df_batched_set_tuning(ctx, arr, 2, *bad) == dfmi.DF_ERR_ARG
+    assert L.df_batched_tuning(ctx, arr, 2, None, refs[1], refs[2], refs[3]) == dfmi.DF_ERR_ARG
+    assert L.df_set_autotune(None, 1) == dfmi.DF_ERR_ARG
+    assert L.df_set_autotune(ctx, 1) == dfmi.DF_OK and L.df_set_autotune(ctx, 0) == dfmi.DF_OK

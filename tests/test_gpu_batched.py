@@ -110,3 +110,75 @@ def test_fragment_workload_reduced_densities():
     for p, o in zip(probs[4:], outs[4:]):          # sampled densities on the larger ones
         J, K, _ = O.jk(p["B"], p["nao"], p["Cocc"][3])
         assert rel(o["J"][3], J) <= 1e-10 and rel(o["K"][3], K) <= 1e-10
+
+
+def oracle_outputs(p):
+    B, nao = p["B"], p["nao"]
+    ndm, nocc = p["Cocc"].shape[0], p["Cocc"].shape[2]
+    nac = p["Cact"].shape[1]
+    out = {}
+    if nocc:
+        jk = [O.jk(B, nao, p["Cocc"][z]) for z in range(ndm)]
+        out["J"], out["K"] = [j[0] for j in jk], [j[1] for j in jk]
+    if nac:
+        out["eri"] = O.active_eri(B, nao, p["Cact"])[0]
+        out["papa"] = O.papa_full(B, nao, p["Cp"], p["Cact"], p["Cp"])
+    return out
+
+
+def close_to_oracle(o, ref, tol=1e-10):
+    for z in range(len(ref.get("J", []))):
+        assert rel(o["J"][z], ref["J"][z]) <= tol and rel(o["K"][z], ref["K"][z]) <= tol
+        assert torch.equal(o["K"][z], o["K"][z].T)
+    if "eri" in ref:
+        assert rel(o["eri"], ref["eri"]) <= tol and rel(o["papa"], ref["papa"]) <= tol
+
+
+def test_batched_every_candidate_configuration():
+    """Every configuration the autotuner can choose gives the oracle's results."""
+    probs = [make(*shape, seed=i + 31) for i, shape in enumerate(RAGGED)]
+    refs = [oracle_outputs(p) for p in probs]
+    dps = [to_dev(p) for p in probs]
+    ctx = dfmi.context(dps[0]["B"].device)
+    try:
+        for half_n in (176, 96, 48):
+            for k_tile in (64, 128):
+                for k_rounds in (16, 4, 64):
+                    dfmi.batched_set_tuning(dps, half_n, k_tile, k_rounds, ctx=ctx)
+                    assert dfmi.batched_tuning(dps, ctx=ctx) == {"half_tile_n": half_n, "k_tile": k_tile,
+                                                                 "k_rounds": k_rounds, "tuned": True}
+                    outs = dfmi.batched_step(dps, ctx=ctx)
+                    torch.cuda.synchronize()
+                    for o, r in zip(outs, refs):
+                        close_to_oracle(o, r)
+    finally:
+        dfmi.batched_set_tuning(dps, 176, 64, 16, ctx=ctx)
+
+
+def test_batched_autotune_fragment_workload():
+    """Autotuning on the eight fragment shapes (4 densities): the first call measures and stores a
+    candidate configuration, and its outputs and those of the next call match the oracle."""
+    probs = []
+    for f in synth.FRAGMENTS:
+        B, Cd, C = synth.fragment_problem(f, ndm=4)
+        probs.append({"B": B, "nao": f.nemb, "Cocc": Cd, "Cact": C[:, f.nocc:f.nocc + f.nac], "Cp": C})
+    dps = [to_dev(p) for p in probs]
+    ctx = dfmi.context(dps[0]["B"].device)
+    assert not dfmi.batched_tuning(dps, ctx=ctx)["tuned"]
+    ctx.set_autotune(True)
+    try:
+        first = dfmi.batched_step(dps, ctx=ctx)
+    finally:
+        ctx.set_autotune(False)
+    t = dfmi.batched_tuning(dps, ctx=ctx)
+    assert t["tuned"] and t["half_tile_n"] in (176, 96, 48) and t["k_tile"] in (64, 128)
+    assert t["k_rounds"] in (16, 4, 64)
+    second = dfmi.batched_step(dps, ctx=ctx)
+    torch.cuda.synchronize()
+    for a, b in zip(first, second):
+        for k in a:
+            assert torch.equal(a[k], b[k])
+    for p, o in zip(probs[:3], first[:3]):
+        close_to_oracle(o, oracle_outputs(p))
+    J, K, _ = O.jk(probs[7]["B"], probs[7]["nao"], probs[7]["Cocc"][2])
+    assert rel(first[7]["J"][2], J) <= 1e-10 and rel(first[7]["K"][2], K) <= 1e-10
