@@ -207,7 +207,8 @@ def fragment_flops(f, ndm):
 
 def batched_fragments(ndm, reps, ctx):
     """The eight fragment subproblems with ndm densities each: df_batched_step (grouped launches)
-    against the same work issued problem by problem (df_jk, df_active_eri, df_papa FULL)."""
+    with its default tiles, autotuned, and the tuned call replayed from a HIP graph, against the
+    same work issued problem by problem (df_jk, df_active_eri, df_papa FULL)."""
     import numpy as np
     import torch
     from paper_2505_03755_amd import dfmi, synth
@@ -238,7 +239,28 @@ def batched_fragments(ndm, reps, ctx):
             dfmi.active_eri(p["B"], p["nao"], p["Cact"], ctx=ctx)
             dfmi.papa(p["B"], p["nao"], p["Cp"], p["Cact"], Cq=p["Cp"], ctx=ctx)
 
+    ms_default = timed(lambda: dfmi.batched_step(probs, ctx=ctx))
+    # the autotuner measures its candidates on the first call of this group shape
+    ctx.set_autotune(True)
+    t0 = time.perf_counter()
+    dfmi.batched_step(probs, ctx=ctx)
+    torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t0
+    ctx.set_autotune(False)
+    tuning = dfmi.batched_tuning(probs, ctx=ctx)
     ms_b = timed(lambda: dfmi.batched_step(probs, ctx=ctx))
+    # the tuned call captured once into a HIP graph and replayed
+    side = torch.cuda.Stream(dev)
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        dfmi.batched_step(probs, ctx=ctx)
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        dfmi.batched_step(probs, ctx=ctx)
+    ms_g = timed(graph.replay)
+    del graph
     ms_u = timed(unbatched)
     fl = sum(fragment_flops(f, ndm) for f in synth.FRAGMENTS)
     del probs
@@ -246,6 +268,8 @@ def batched_fragments(ndm, reps, ctx):
     return {"workload": "8 fragment subproblems, N_emb 80..400, N_aux = 4 N_emb, N_occ = N_emb/4, "
                         f"N_ac 4..8, {ndm} densities each; J, K, (uv|wx), full (pu|qv)",
             "flops": fl, "ms_batched": ms_b, "tflops_batched": fl / ms_b / 1e9,
+            "tuning": {k: tuning[k] for k in ("half_tile_n", "k_tile", "k_rounds")}, "tuning_call_s": tune_s,
+            "ms_batched_default_tiles": ms_default, "ms_graph_replay": ms_g,
             "ms_unbatched": ms_u, "tflops_unbatched": fl / ms_u / 1e9}
 
 

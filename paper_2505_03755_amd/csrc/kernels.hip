@@ -3,8 +3,11 @@
 // Every dense contraction runs on the FP64 matrix cores (v_mfma_f64_16x16x4_f64,
 // 64 cycles per issue per SIMD; one wave per SIMD can keep the unit busy).  Operand
 // tiles go global -> registers -> LDS in a [row][k] layout with a row stride of 17
-// doubles: the "k fastest" and "row fastest" global-load mappings both write, and the
-// MFMA operand reads read, 32 lanes per LDS cycle without bank conflicts.
+// doubles.  The LDS serves 32 lanes of 8-byte accesses per cycle over 64 banks.  With this
+// stride the "row fastest" stores are conflict-free; the "k fastest" stores and the MFMA
+// operand reads have one colliding pair per 32 lanes.  An 18-double stride makes the reads
+// conflict-free and the stores worse; the kernels run equally fast with either, because
+// the conflicts hide behind the MFMAs.
 //
 // Main loop: two LDS stages; the global loads of slab s+1 are issued before the MFMAs
 // of slab s and written to the other stage after them, one barrier per slab.  Loads
