@@ -156,7 +156,9 @@ def cpu_baseline(wl, rows, seed, adjoint=True):
 
 def split_comparison(B, nao, Cocc, Cact, C, nslice, reps, ctx):
     """Forward step in FP64 (df_step) and in split precision (df_step_split, nslice int8 slices),
-    timed alone with HIP events on the library's stream, and the model energy from both."""
+    timed alone with HIP events on the library's stream, and the model energy from both; then the
+    adjoint for the model-energy cotangents in FP64 (df_step_backward) and in split precision
+    (df_step_backward_split), timed the same way, with the difference of the gradients."""
     import math
     import torch
     from paper_2505_03755_amd import dfmi, synth
@@ -179,7 +181,6 @@ def split_comparison(B, nao, Cocc, Cact, C, nslice, reps, ctx):
 
     ref, ms64 = timed(lambda o: dfmi.step(B, nao, Cocc, Cact, C, outputs=o, ctx=ctx))
     spl, mss = timed(lambda o: dfmi.step_split(B, Bs, Be, nao, Cocc, Cact, C, outputs=o, ctx=ctx))
-    del Bs, Be
     h = torch.from_numpy(synth.symmetric_matrix(nao)).to(dev)
     Gam = torch.from_numpy(synth.two_body_density(nac)).to(dev)
     D = Cocc @ Cocc.T
@@ -190,9 +191,26 @@ def split_comparison(B, nao, Cocc, Cact, C, nslice, reps, ctx):
 
     e64, es = energy(ref), energy(spl)
     rel = {k: ((spl[k] - ref[k]).norm() / ref[k].norm()).item() for k in ("J", "K", "v", "eri", "papa")}
+    del ref, spl
+    # the adjoint for the model-energy cotangents (gJ = D/2, gK = -D/4, geri = Gamma/2), each
+    # path on the factors its own forward kept
+    gJ, gK, ge = (0.5 * D).contiguous(), (-0.25 * D).contiguous(), (0.5 * Gam).contiguous()
+    xs = dfmi.step_split(B, Bs, Be, nao, Cocc, Cact, C, keep_x=True, ctx=ctx)
+    del Bs, Be
+    Bt, Bte = dfmi.split_cholesky_t(B, nao, nslice=nslice, ctx=ctx)   # once per B, not timed
+    x64 = dfmi.step(B, nao, Cocc, Cact, C, keep_x=True, ctx=ctx)
+    g64, bms64 = timed(lambda o: dfmi.step_backward(B, nao, Cocc, Cact, gJ, gK, ge, x64["Xocc"], x64["Xact"],
+                                                    ctx=ctx))
+    gs, bmss = timed(lambda o: dfmi.step_backward_split(B, Bt, Bte, nao, Cocc, Cact, gJ, gK, ge, xs["Xocc"],
+                                                        xs["Xact"], ctx=ctx))
+    grel = {name: ((a - b).norm() / b.norm()).item() for name, a, b in (("dCocc", gs[0], g64[0]),
+                                                                       ("dCact", gs[1], g64[1]))}
+    del xs, x64, Bt, Bte, g64, gs
+    torch.cuda.empty_cache()
     return {"nslice": nslice, "forward_ms_fp64": ms64, "forward_ms_split": mss, "speedup": ms64 / mss,
             "E_fp64": e64, "dE_split_minus_fp64": es - e64, "dE_bar": 1e-8, "meets_bar": abs(es - e64) <= 1e-8,
-            "rel_diff": rel}
+            "rel_diff": rel, "adjoint_ms_fp64": bms64, "adjoint_ms_split": bmss,
+            "adjoint_speedup": bms64 / bmss, "gradient_rel_diff": grel}
 
 
 def fragment_flops(f, ndm):
@@ -410,7 +428,7 @@ def main():
         "kernels": kernels,
     }
     if not args.no_split:
-        log(f"[bench] split precision ({args.split_slices} slices) against FP64, forward step")
+        log(f"[bench] split precision ({args.split_slices} slices) against FP64, forward and adjoint")
         for k in ("Xocc", "Xact"):
             out.pop(k, None)
         torch.cuda.empty_cache()

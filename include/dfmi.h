@@ -64,7 +64,8 @@ typedef enum df_op {
   DF_OP_STEP = 5,
   DF_OP_STEP_BACKWARD = 6,
   DF_OP_SPLIT_MATMUL = 7,
-  DF_OP_STEP_SPLIT = 8
+  DF_OP_STEP_SPLIT = 8,
+  DF_OP_STEP_BACKWARD_SPLIT = 9
 } df_op;
 
 /* Kernel classes reported by df_timing_read. */
@@ -87,10 +88,10 @@ typedef enum df_kernel_kind {
 #define DF_PAPA_FULL 0x1   /* df_papa: return (pu|qv) of Eq. (papa) instead of (pu|vw) */
 
 /* Flag bits of df_dims.flags for df_workspace_size only. */
-#define DF_CALLER_X  0x10  /* DF_OP_STEP / DF_OP_STEP_BACKWARD: Xocc and Xact are passed in */
-#define DF_BWD_GJ    0x20  /* DF_OP_STEP_BACKWARD: gJ is given */
-#define DF_BWD_GK    0x40  /* DF_OP_STEP_BACKWARD: gK is given */
-#define DF_BWD_GERI  0x80  /* DF_OP_STEP_BACKWARD: geri is given */
+#define DF_CALLER_X  0x10  /* DF_OP_STEP / DF_OP_STEP_BACKWARD / DF_OP_STEP_SPLIT: Xocc, Xact passed in */
+#define DF_BWD_GJ    0x20  /* DF_OP_STEP_BACKWARD(_SPLIT): gJ is given */
+#define DF_BWD_GK    0x40  /* DF_OP_STEP_BACKWARD(_SPLIT): gK is given */
+#define DF_BWD_GERI  0x80  /* DF_OP_STEP_BACKWARD(_SPLIT): geri is given */
 
 /* Problem sizes for df_workspace_size; fields an operation does not use are ignored. */
 typedef struct df_dims {
@@ -103,7 +104,7 @@ typedef struct df_dims {
   int64_t ncol;   /* columns of C in df_half_transform */
   int64_t n2;     /* columns of C2 in df_half_transform (0 if no second transform) */
   int flags;
-  int nslice;     /* int8 slices per operand (DF_OP_SPLIT_MATMUL, DF_OP_STEP_SPLIT) */
+  int nslice;     /* int8 slices per operand (split-precision ops) */
   int64_t m, n, k;  /* product sizes of DF_OP_SPLIT_MATMUL */
 } df_dims;
 
@@ -313,16 +314,43 @@ df_status df_split_cholesky(df_ctx* ctx, const double* B, int64_t naux, int64_t 
                             int* Be, int flags);
 
 /*
+ * The same split for products that contract over (P, nu): the rows mu of the DF tensor over
+ * k = P * nao + nu (element b^P_{mu nu}), for df_step_backward_split.
+ *   Bt: nslice * rpad32(nao) * kpad64(naux * nao) int8 in the block layout of Bs (rows mu),
+ *   Bte [nao] int32 exponents (of max over P and nu of |b^P_{mu nu}|); caller-owned device
+ *   buffers, overwritten; Bt 16-byte aligned.  naux * nao <= 2^30.  No workspace.
+ */
+df_status df_split_cholesky_t(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int nslice, int8_t* Bt,
+                              int* Bte, int flags);
+
+/*
  * df_step in split precision (unit weights): the half transform (against Bs, Be from
  * df_split_cholesky with the same nslice), K, the second transforms, (uv|wx) and (pu|vw) are
  * split products; the J-vector v and J (from the packed B) are FP64.  Outputs as in df_step;
- * any of J, K, v, eri, papa may be NULL.
- * Workspace: df_workspace_size(DF_OP_STEP_SPLIT, {naux, nao, 1, nocc, nac, np, nslice}).
+ * any of J, K, v, eri, papa may be NULL.  Xocc [naux][nao][nocc] and Xact [nao][naux][nac]
+ * (the layouts of df_step), both or neither, receive the half-transformed factors for
+ * df_step_backward_split (NULL only for an empty one).
+ * Workspace: df_workspace_size(DF_OP_STEP_SPLIT, {naux, nao, 1, nocc, nac, np, nslice,
+ *            flags = DF_CALLER_X if Xocc/Xact are given}).
  */
 df_status df_step_split(df_ctx* ctx, const double* B, const int8_t* Bs, const int* Be, int nslice, int64_t naux,
                         int64_t nao, const double* Cocc, int64_t nocc, const double* Cact, int64_t nac,
                         const double* Cp, int64_t np, double* J, double* K, double* v, double* eri, double* papa,
-                        int flags);
+                        double* Xocc, double* Xact, int flags);
+
+/*
+ * df_step_backward in split precision: the exchange part, Y_P = S X_P and sum_P b^P Y_P with
+ * S = gK + gK^T, as slice products against Bt, Bte (df_split_cholesky_t, same nslice).  The
+ * Coulomb part (2 M Cocc) and the active-space part stay FP64, as in df_step_backward.
+ * Xocc is required with gK and Xact with geri; there is no recomputation here.  Arguments,
+ * outputs and cotangent rules are otherwise as in df_step_backward; nao <= 32768.
+ * Workspace: df_workspace_size(DF_OP_STEP_BACKWARD_SPLIT, {naux, nao, 1, nocc, nac, nslice,
+ *            flags = DF_BWD_GJ | DF_BWD_GK | DF_BWD_GERI for the given cotangents}).
+ */
+df_status df_step_backward_split(df_ctx* ctx, const double* B, const int8_t* Bt, const int* Bte, int nslice,
+                                 int64_t naux, int64_t nao, const double* Cocc, int64_t nocc, const double* Cact,
+                                 int64_t nac, const double* gJ, const double* gK, const double* geri,
+                                 const double* Xocc, const double* Xact, double* dCocc, double* dCact, int flags);
 
 #ifdef __cplusplus
 }

@@ -241,12 +241,12 @@ struct StepSplitPlan {
   int nsk;
 };
 StepSplitPlan plan_step_split(Plan& pl, int64_t naux, int64_t nao, int64_t nocc, int64_t nac, int64_t np,
-                              int nslice) {
+                              int nslice, bool caller_x) {
   StepSplitPlan p{};
   const int64_t ncol = nocc + nac;
   p.ccat = pl.take(nao * ncol);
-  p.xo = pl.take(naux * nao * nocc);     // P-major [naux][nao][nocc]
-  p.xa = pl.take(naux * nao * nac);      // P-major [naux][nao][nac]
+  p.xo = pl.take(caller_x ? 0 : naux * nao * nocc);   // P-major [naux][nao][nocc]
+  p.xa = pl.take(caller_x ? 0 : naux * nao * nac);    // AO-major [nao][naux][nac]
   p.bpu = pl.take(naux * np * nac);
   p.buv = pl.take(naux * nac * nac);
   p.cs = take_split(pl, ncol, nao, nslice);
@@ -259,6 +259,31 @@ StepSplitPlan plan_step_split(Plan& pl, int64_t naux, int64_t nao, int64_t nocc,
   p.cas = take_split(pl, nac, nao, nslice);
   p.bpus = take_split(pl, np * nac, naux, nslice);
   p.buvs = take_split(pl, nac * nac, naux, nslice);
+  return p;
+}
+
+// Workspace of df_step_backward_split: the Coulomb and active parts as in df_step_backward
+// (FP64), the exchange part as slice products.
+struct BwdSplitPlan {
+  BwdPlan f;
+  size_t S, Y, part;
+  SplitBuf ss, xs, ys;
+  int nsk;
+};
+BwdSplitPlan plan_backward_split(Plan& pl, int64_t naux, int64_t nao, int64_t nocc, int64_t nac, int flags,
+                                 int nslice) {
+  BwdSplitPlan p{};
+  p.f = plan_backward(pl, naux, nao, nocc, nac, (flags & ~DF_BWD_GK) | DF_CALLER_X);
+  p.nsk = 1;
+  if ((flags & DF_BWD_GK) && nocc > 0) {
+    p.S = pl.take(nao * nao);
+    p.Y = pl.take(naux * nao * nocc);   // P-major [naux][nao][nocc]
+    p.ss = take_split(pl, nao, nao, nslice);
+    p.xs = take_split(pl, naux * nocc, nao, nslice);
+    p.ys = take_split(pl, nocc, naux * nao, nslice);
+    p.nsk = slice_splits(dfk::slice_gemm_tiles(nao, nocc, false), dfk::slice_gemm_steps(dfk::kpad64(naux * nao)));
+    p.part = pl.take(p.nsk > 1 ? (int64_t)p.nsk * nao * nocc : 0);
+  }
   return p;
 }
 
@@ -673,7 +698,11 @@ df_status df_workspace_size(df_op op, const df_dims* d, size_t* bytes) {
       break;
     case DF_OP_STEP_SPLIT:
       if (d->nslice < 4 || d->nslice > 8) return DF_ERR_SHAPE;
-      plan_step_split(pl, d->naux, d->nao, d->nocc, d->nac, d->np, d->nslice);
+      plan_step_split(pl, d->naux, d->nao, d->nocc, d->nac, d->np, d->nslice, (d->flags & DF_CALLER_X) != 0);
+      break;
+    case DF_OP_STEP_BACKWARD_SPLIT:
+      if (d->nslice < 4 || d->nslice > 8) return DF_ERR_SHAPE;
+      plan_backward_split(pl, d->naux, d->nao, d->nocc, d->nac, d->flags, d->nslice);
       break;
     default: return DF_ERR_UNSUPPORTED;
   }
@@ -918,6 +947,48 @@ df_status df_step(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const
   return DF_OK;
 }
 
+// dCocc = 2 M Cocc,  M = sum_P <b^P, gJ> b^P  (the Coulomb part of the adjoint, FP64)
+static df_status bwd_coulomb(df_ctx* c, char* ws, const BwdPlan& p, const double* B, int64_t naux, int64_t nao,
+                             const double* gJ, const double* Cocc, int64_t nocc, double* dCocc) {
+  double* g = (double*)(ws + p.g);
+  double* u = (double*)(ws + p.u);
+  double* M = (double*)(ws + p.M);
+  DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_pair_weights(gJ, nao, g, c->stream), "pair weights");
+  DF_LAUNCH(DF_KERNEL_JVEC, dfk::launch_jvec_packed(B, naux, nao, g, (double*)(ws + p.upart), u, c->stream),
+            "J-vector launch");
+  DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_coulomb(B, naux, nao, u, 1, M, c->stream), "Coulomb launch");
+  const dfk::OpMap A = dfk::op_map(M, nao, nao, nao, 1);
+  const dfk::OpMap Bm = dfk::op_map(Cocc, nocc, 1, nao, nocc);
+  dfk::OutMap O = dfk::out_plain(dCocc, nao, nocc, nocc);
+  O.alpha = 2.0;
+  DF_LAUNCH(DF_KERNEL_ADJOINT, dfk::launch_gemm(A, Bm, O, 1, c->stream), "adjoint product");
+  return DF_OK;
+}
+
+// dCact = sum_P X^act_P (Z_P + Z_P^T),  Z_P[uv] = sum_wx (geri[uvwx] + geri[wxuv]) b^P_wx
+// (the active-space part of the adjoint, FP64; Xa AO-major [nao][naux][nac])
+static df_status bwd_active(df_ctx* c, char* ws, const BwdPlan& p, int64_t naux, int64_t nao, const double* Cact,
+                            int64_t nac, const double* geri, const double* Xa, double* dCact) {
+  const int64_t n2 = nac * nac;
+  double* Gs = (double*)(ws + p.Gs);
+  double* buv = (double*)(ws + p.buv);
+  double* Z = (double*)(ws + p.Z);
+  DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_symmetrize(geri, n2, 1, Gs, c->stream), "symmetrize");
+  if (df_status s = run_mo(c, Cact, nac, Xa, naux, nao, nac, buv)) return s;
+  const dfk::OpMap A = dfk::op_map(buv, naux, n2, n2, 1);
+  const dfk::OpMap Bm = dfk::op_map(Gs, n2, n2, n2, 1);
+  DF_LAUNCH(DF_KERNEL_ADJOINT, dfk::launch_gemm(A, Bm, dfk::out_plain(Z, naux, n2, n2), 1, c->stream),
+            "adjoint product");
+  DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_symmetrize(Z, nac, naux, Z, c->stream), "symmetrize");
+  const dfk::OpMap Ax = dfk::op_map(Xa, nao, naux * nac, naux * nac, 1);
+  const dfk::OpMap Bz = dfk::op_map(Z, nac, 1, naux * nac, nac);
+  DF_LAUNCH(DF_KERNEL_ADJOINT,
+            dfk::launch_gemm_split(Ax, Bz, dfk::out_plain(dCact, nao, nac, nac), p.nsa, (double*)(ws + p.apart),
+                                   c->stream),
+            "adjoint product");
+  return DF_OK;
+}
+
 df_status df_step_backward(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const double* Cocc,
                            int64_t nocc, const double* Cact, int64_t nac, const double* gJ, const double* gK,
                            const double* geri, const double* Xocc, const double* Xact, double* dCocc,
@@ -970,21 +1041,8 @@ df_status df_step_backward(df_ctx* ctx, const double* B, int64_t naux, int64_t n
     Xo = xo;
     Xa = xa;
   }
-  if (do_j) {
-    // dCocc = 2 M Cocc,  M = sum_P <b^P, gJ> b^P
-    double* g = (double*)(ws + p.g);
-    double* u = (double*)(ws + p.u);
-    double* M = (double*)(ws + p.M);
-    DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_pair_weights(gJ, nao, g, c->stream), "pair weights");
-    DF_LAUNCH(DF_KERNEL_JVEC, dfk::launch_jvec_packed(B, naux, nao, g, (double*)(ws + p.upart), u, c->stream),
-              "J-vector launch");
-    DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_coulomb(B, naux, nao, u, 1, M, c->stream), "Coulomb launch");
-    const dfk::OpMap A = dfk::op_map(M, nao, nao, nao, 1);
-    const dfk::OpMap Bm = dfk::op_map(Cocc, nocc, 1, nao, nocc);
-    dfk::OutMap O = dfk::out_plain(dCocc, nao, nocc, nocc);
-    O.alpha = 2.0;
-    DF_LAUNCH(DF_KERNEL_ADJOINT, dfk::launch_gemm(A, Bm, O, 1, c->stream), "adjoint product");
-  }
+  if (do_j)
+    if (df_status s = bwd_coulomb(c, ws, p, B, naux, nao, gJ, Cocc, nocc, dCocc)) return s;
   if (do_k) {
     // dCocc += sum_P b^P Y_P,  Y_P = S X_P,  S = gK + gK^T
     double* S = (double*)(ws + p.S);
@@ -1012,26 +1070,8 @@ df_status df_step_backward(df_ctx* ctx, const double* B, int64_t naux, int64_t n
               dfk::launch_half_reduce(B, naux, nao, Ym, Od, p.nsk, (double*)(ws + p.kpart), c->stream),
               "adjoint packed product");
   }
-  if (do_e) {
-    // dCact = sum_P X^act_P (Z_P + Z_P^T),  Z_P[uv] = sum_wx (geri[uvwx] + geri[wxuv]) b^P_wx
-    const int64_t n2 = nac * nac;
-    double* Gs = (double*)(ws + p.Gs);
-    double* buv = (double*)(ws + p.buv);
-    double* Z = (double*)(ws + p.Z);
-    DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_symmetrize(geri, n2, 1, Gs, c->stream), "symmetrize");
-    if (df_status s = run_mo(c, Cact, nac, Xa, naux, nao, nac, buv)) return s;
-    const dfk::OpMap A = dfk::op_map(buv, naux, n2, n2, 1);
-    const dfk::OpMap Bm = dfk::op_map(Gs, n2, n2, n2, 1);
-    DF_LAUNCH(DF_KERNEL_ADJOINT, dfk::launch_gemm(A, Bm, dfk::out_plain(Z, naux, n2, n2), 1, c->stream),
-              "adjoint product");
-    DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_symmetrize(Z, nac, naux, Z, c->stream), "symmetrize");
-    const dfk::OpMap Ax = dfk::op_map(Xa, nao, naux * nac, naux * nac, 1);
-    const dfk::OpMap Bz = dfk::op_map(Z, nac, 1, naux * nac, nac);
-    DF_LAUNCH(DF_KERNEL_ADJOINT,
-              dfk::launch_gemm_split(Ax, Bz, dfk::out_plain(dCact, nao, nac, nac), p.nsa, (double*)(ws + p.apart),
-                                     c->stream),
-              "adjoint product");
-  }
+  if (do_e)
+    if (df_status s = bwd_active(c, ws, p, naux, nao, Cact, nac, geri, Xa, dCact)) return s;
   return DF_OK;
 }
 
@@ -1098,11 +1138,14 @@ df_status df_split_cholesky(df_ctx* ctx, const double* B, int64_t naux, int64_t 
 df_status df_step_split(df_ctx* ctx, const double* B, const int8_t* Bs, const int* Be, int nslice, int64_t naux,
                         int64_t nao, const double* Cocc, int64_t nocc, const double* Cact, int64_t nac,
                         const double* Cp, int64_t np, double* J, double* K, double* v, double* eri, double* papa,
-                        int flags) {
+                        double* Xocc, double* Xact, int flags) {
   df_ctx* c = ctx;
   if (check_ctx(c)) return DF_ERR_ARG;
   if (df_status s = check_core(c, B, naux, nao)) return s;
   if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_step_split takes no flags");
+  const bool caller_x = Xocc != nullptr || Xact != nullptr;
+  if (caller_x && ((nocc > 0 && !Xocc) || (nac > 0 && !Xact)))
+    return fail(c, DF_ERR_ARG, "Xocc and Xact must be given together (NULL only for an empty one)");
   if (nslice < 4 || nslice > 8) return fail(c, DF_ERR_SHAPE, "nslice must be in [4, 8]");
   if (!Bs || !Be) return fail(c, DF_ERR_ARG, "Bs and Be (from df_split_cholesky) are required");
   if ((uintptr_t)Bs % 16 != 0) return fail(c, DF_ERR_ARG, "Bs must be 16-byte aligned");
@@ -1125,9 +1168,11 @@ df_status df_step_split(df_ctx* ctx, const double* B, const int8_t* Bs, const in
                            {K, dbytes(nao * nao), "K", true},
                            {v, dbytes(naux), "v", true},
                            {eri, dbytes(nac * nac * nac * nac), "eri", true},
-                           {papa, dbytes(np * nac * nac * nac), "papa", true}};
+                           {papa, dbytes(np * nac * nac * nac), "papa", true},
+                           {Xocc, dbytes(naux * nao * nocc), "Xocc", true},
+                           {Xact, dbytes(naux * nao * nac), "Xact", true}};
   Plan pl;
-  const StepSplitPlan p = plan_step_split(pl, naux, nao, nocc, nac, np, nslice);
+  const StepSplitPlan p = plan_step_split(pl, naux, nao, nocc, nac, np, nslice, caller_x);
   if (!check_overlap(c, rs)) return DF_ERR_ARG;
   if (df_status s = need_ws(c, pl.total)) return s;
   rs.push_back({c->ws, pl.total, "workspace", true});
@@ -1141,20 +1186,23 @@ df_status df_step_split(df_ctx* ctx, const double* B, const int8_t* Bs, const in
   }
   if (ncol == 0) return DF_OK;
   const int64_t kpo = dfk::kpad64(nao);
-  // a2: X[(P, m)][c] = sum_k b^P_{mk} [Cocc | Cact][k][c], against the pre-split rows of b^P
+  // a2: X[(P, m)][c] = sum_k b^P_{mk} [Cact | Cocc][k][c], against the pre-split rows of b^P;
+  // X_act goes out AO-major [m][P][u], X_occ P-major [P][m][i] (the layouts of df_step)
   double* cc = (double*)(ws + p.ccat);
-  const ColBlock blks[2] = {{Cocc, nocc, nocc, 0}, {Cact, nac, nac, nocc}};
+  const ColBlock blks[2] = {{Cact, nac, nac, 0}, {Cocc, nocc, nocc, nac}};
   if (df_status s = pad_operand_plain(c, cc, nao, ncol, blks, 2)) return s;
   int8_t* cs = (int8_t*)(ws + p.cs.planes);
   int* ce = (int*)(ws + p.cs.ex);
   DF_LAUNCH(DF_KERNEL_SPLIT, dfk::launch_split_rows(dfk::op_map(cc, ncol, 1, nao, ncol), nao, nslice, cs, ce, c->stream),
             "split launch");
-  double* Xo = (double*)(ws + p.xo);
-  double* Xa = (double*)(ws + p.xa);
-  dfk::OutMap OX = dfk::out_plain(Xo, naux * nao, ncol, nocc);
-  OX.nsplit = nocc;
-  OX.p2 = Xa;
-  OX.s2_m = nac;
+  double* Xo = caller_x ? Xocc : (double*)(ws + p.xo);
+  double* Xa = caller_x ? Xact : (double*)(ws + p.xa);
+  dfk::OutMap OX = dfk::out_plain(Xa, naux * nao, ncol, naux * nac);
+  OX.ml = nao;       // m = (P, mu): P * nac + mu * naux * nac
+  OX.s_mh = nac;
+  OX.nsplit = nac;
+  OX.p2 = Xo;
+  OX.s2_m = nocc;
   DF_LAUNCH(DF_KERNEL_HALF_TRANSFORM,
             dfk::launch_slice_gemm(Bs, Be, naux * nao, cs, ce, ncol, kpo, nslice, OX, false, 1, nullptr, c->stream),
             "slice product launch");
@@ -1184,10 +1232,8 @@ df_status df_step_split(df_ctx* ctx, const double* B, const int8_t* Bs, const in
     }
   }
   if (nac > 0 && (eri || papa)) {
-    // a6: b^P_{pu} = sum_mu Cp[mu][p] X[P][mu][u]; split rows (P, u) of X_act and rows p of Cp
-    dfk::OpMap oxa = dfk::op_map(Xa, naux * nac, 1, nao, nac);
-    oxa.rl = nac;
-    oxa.s_rh = nao * nac;
+    // a6: b^P_{pu} = sum_mu Cp[mu][p] X[mu][P][u]; split rows (P, u) of X_act and rows p of Cp
+    const dfk::OpMap oxa = dfk::op_map(Xa, naux * nac, 1, nao, naux * nac);
     int8_t* xas = (int8_t*)(ws + p.xas.planes);
     int* xae = (int*)(ws + p.xas.ex);
     DF_LAUNCH(DF_KERNEL_SPLIT, dfk::launch_split_rows(oxa, nao, nslice, xas, xae, c->stream), "split launch");
@@ -1267,6 +1313,114 @@ df_status df_batched_set_tuning(df_ctx* ctx, const df_problem* probs, int nprob,
   if (!in(half_tile_n, kHalfTiles, 3) || !in(k_tile, kKTiles, 2) || !in(k_rounds, kKRounds, 3))
     return fail(c, DF_ERR_ARG, "not a candidate configuration");
   c->tune[batched_key(probs, nprob)] = BatchedTune{half_tile_n, k_tile, k_rounds};
+  return DF_OK;
+}
+
+df_status df_split_cholesky_t(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int nslice, int8_t* Bt,
+                              int* Bte, int flags) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (df_status s = check_core(c, B, naux, nao)) return s;
+  if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_split_cholesky_t takes no flags");
+  if (nslice < 4 || nslice > 8) return fail(c, DF_ERR_SHAPE, "nslice must be in [4, 8]");
+  if (!Bt || !Bte) return fail(c, DF_ERR_ARG, "Bt and Bte are required");
+  if ((uintptr_t)Bt % 16 != 0) return fail(c, DF_ERR_ARG, "Bt must be 16-byte aligned");
+  if (naux * nao > (1LL << 30)) return fail(c, DF_ERR_SHAPE, "naux * nao must be at most 2^30");
+  const int64_t npair = nao * (nao + 1) / 2;
+  std::vector<Range> rs = {{B, dbytes(naux * npair), "B", false},
+                           {Bt, (size_t)dfk::split_plane_bytes(nao, naux * nao, nslice), "Bt", true},
+                           {Bte, (size_t)nao * 4, "Bte", true}};
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (df_status s = enter(c)) return s;
+  DF_LAUNCH(DF_KERNEL_SPLIT, dfk::launch_split_packed_t(B, naux, nao, nslice, Bt, Bte, c->stream), "split launch");
+  return DF_OK;
+}
+
+df_status df_step_backward_split(df_ctx* ctx, const double* B, const int8_t* Bt, const int* Bte, int nslice,
+                                 int64_t naux, int64_t nao, const double* Cocc, int64_t nocc, const double* Cact,
+                                 int64_t nac, const double* gJ, const double* gK, const double* geri,
+                                 const double* Xocc, const double* Xact, double* dCocc, double* dCact, int flags) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (df_status s = check_core(c, B, naux, nao)) return s;
+  if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_step_backward_split takes no flags");
+  if (nslice < 4 || nslice > 8) return fail(c, DF_ERR_SHAPE, "nslice must be in [4, 8]");
+  if (nocc < 0 || nac < 0) return fail(c, DF_ERR_SHAPE, "sizes must be >= 0");
+  if (nocc > 0 && (!Cocc || !dCocc)) return fail(c, DF_ERR_ARG, "Cocc and dCocc are required when nocc > 0");
+  if (nac > 0 && (!Cact || !dCact)) return fail(c, DF_ERR_ARG, "Cact and dCact are required when nac > 0");
+  const bool do_j = gJ && nocc > 0, do_k = gK && nocc > 0, do_e = geri && nac > 0;
+  if (do_k && (!Xocc || !Bt || !Bte)) return fail(c, DF_ERR_ARG, "gK needs Xocc and Bt, Bte (df_split_cholesky_t)");
+  if (do_e && !Xact) return fail(c, DF_ERR_ARG, "geri needs Xact");
+  if (Bt && (uintptr_t)Bt % 16 != 0) return fail(c, DF_ERR_ARG, "Bt must be 16-byte aligned");
+  if (nao > 32768 || naux * nao > (1LL << 30) || dfk::rpad32(naux * nocc) > 0x7fffffffLL)
+    return fail(c, DF_ERR_SHAPE, "problem too large for the split path");
+  const int pflags = (gJ ? DF_BWD_GJ : 0) | (gK ? DF_BWD_GK : 0) | (geri ? DF_BWD_GERI : 0);
+  const int64_t npair = nao * (nao + 1) / 2;
+  std::vector<Range> rs = {{B, dbytes(naux * npair), "B", false},
+                           {Bt, (size_t)dfk::split_plane_bytes(nao, naux * nao, nslice), "Bt", false},
+                           {Bte, (size_t)nao * 4, "Bte", false},
+                           {Cocc, dbytes(nao * nocc), "Cocc", false},
+                           {Cact, dbytes(nao * nac), "Cact", false},
+                           {gJ, dbytes(nao * nao), "gJ", false},
+                           {gK, dbytes(nao * nao), "gK", false},
+                           {geri, dbytes(nac * nac * nac * nac), "geri", false},
+                           {Xocc, dbytes(naux * nao * nocc), "Xocc", false},
+                           {Xact, dbytes(naux * nao * nac), "Xact", false},
+                           {dCocc, dbytes(nao * nocc), "dCocc", true},
+                           {dCact, dbytes(nao * nac), "dCact", true}};
+  Plan pl;
+  const BwdSplitPlan p = plan_backward_split(pl, naux, nao, nocc, nac, pflags, nslice);
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (df_status s = need_ws(c, pl.total)) return s;
+  if (pl.total) rs.push_back({c->ws, pl.total, "workspace", true});
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (df_status s = enter(c)) return s;
+  char* ws = c->ws;
+  if (nocc > 0 && !do_j && !do_k) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(dCocc, nao * nocc, c->stream), "fill");
+  if (nac > 0 && !do_e) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(dCact, nao * nac, c->stream), "fill");
+  if (do_j)
+    if (df_status s = bwd_coulomb(c, ws, p.f, B, naux, nao, gJ, Cocc, nocc, dCocc)) return s;
+  if (do_k) {
+    // dCocc += sum_P b^P Y_P,  Y_P = S X_P,  S = gK + gK^T, both products from int8 slices
+    double* S = (double*)(ws + p.S);
+    double* Y = (double*)(ws + p.Y);
+    DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_symmetrize(gK, nao, 1, S, c->stream), "symmetrize");
+    const int64_t kpo = dfk::kpad64(nao), kpb = dfk::kpad64(naux * nao);
+    int8_t* ss = (int8_t*)(ws + p.ss.planes);
+    int* se = (int*)(ws + p.ss.ex);
+    int8_t* xs = (int8_t*)(ws + p.xs.planes);
+    int* xe = (int*)(ws + p.xs.ex);
+    int8_t* ys = (int8_t*)(ws + p.ys.planes);
+    int* ye = (int*)(ws + p.ys.ex);
+    // rows mu of S over nu; rows (P, i) of X over nu
+    DF_LAUNCH(DF_KERNEL_SPLIT, dfk::launch_split_rows(dfk::op_map(S, nao, nao, nao, 1), nao, nslice, ss, se, c->stream),
+              "split launch");
+    dfk::OpMap ox = dfk::op_map(Xocc, naux * nocc, 1, nao, nocc);
+    ox.rl = nocc;
+    ox.s_rh = nao * nocc;
+    DF_LAUNCH(DF_KERNEL_SPLIT, dfk::launch_split_rows(ox, nao, nslice, xs, xe, c->stream), "split launch");
+    // Y[P][mu][i] = sum_nu S[mu][nu] X[P][nu][i]
+    dfk::OutMap OY = dfk::out_plain(Y, nao, naux * nocc, nocc);
+    OY.nl = nocc;
+    OY.s_nh = nao * nocc;
+    DF_LAUNCH(DF_KERNEL_ADJOINT,
+              dfk::launch_slice_gemm(ss, se, nao, xs, xe, naux * nocc, kpo, nslice, OY, false, 1, nullptr, c->stream),
+              "slice product launch");
+    // rows i of Y over (P, nu); then dCocc[mu][i] += sum_{P, nu} b^P_{mu nu} Y[P][nu][i]
+    dfk::OpMap oy = dfk::op_map(Y, nocc, 1, nao, nocc);
+    oy.kb_n = naux;
+    oy.s_kb = nao * nocc;
+    DF_LAUNCH(DF_KERNEL_SPLIT, dfk::launch_split_rows(oy, naux * nao, nslice, ys, ye, c->stream), "split launch");
+    dfk::OutMap Od = dfk::out_plain(dCocc, nao, nocc, nocc);
+    Od.accumulate = do_j ? 1 : 0;
+    double* part = p.nsk > 1 ? (double*)(ws + p.part) : nullptr;
+    DF_LAUNCH(DF_KERNEL_ADJOINT,
+              dfk::launch_slice_gemm(Bt, Bte, nao, ys, ye, nocc, kpb, nslice, Od, false, p.nsk, part, c->stream),
+              "slice product launch");
+    if (part) DF_LAUNCH(DF_KERNEL_ADJOINT, dfk::launch_split_reduce(part, p.nsk, Od, c->stream), "split reduce");
+  }
+  if (do_e)
+    if (df_status s = bwd_active(c, ws, p.f, naux, nao, Cact, nac, geri, Xact, dCact)) return s;
   return DF_OK;
 }
 

@@ -153,6 +153,10 @@ hipError_t launch_split_rows(const OpMap& o, int64_t K, int nslice, int8_t* plan
 // The same for the rows (P, m) of the unpacked b^P (rows naux*nao, K = nao).
 hipError_t launch_split_packed(const double* B, int64_t naux, int64_t nao, int nslice, int8_t* planes, int* ex,
                                hipStream_t s);
+// The same for the rows mu of the DF tensor over k = (P, nu), k = P nao + nu (rows nao,
+// K = naux * nao): the exponent of row mu is the largest over P.
+hipError_t launch_split_packed_t(const double* B, int64_t naux, int64_t nao, int nslice, int8_t* planes, int* ex,
+                                 hipStream_t s);
 // C(m, n) = sum_k A(m, k) B(n, k) from the split planes of A (M rows) and B (N rows) with
 // kp = kpad64(K), written through O (alpha / accumulate honoured) or, with nsplit > 1, as partial
 // sums part[split][M][N] over k ranges.  Every split must be at most slice_gemm_max_steps() steps

@@ -259,6 +259,57 @@ __global__ void __launch_bounds__(256) split_packed_kernel(const double* __restr
   }
 }
 
+// Rows mu of the DF tensor over k = (P, nu), k = P nao + nu (element b^P_{mu nu}): the operand
+// of products that contract over (P, nu).  Exponent of row mu: the largest row exponent over
+// P, taken per (P, mu) row with one workgroup each and merged by integer atomic max.
+__global__ void __launch_bounds__(256) split_packed_t_max_kernel(const double* __restrict__ B, int64_t nao,
+                                                                 int64_t npair, int* ex) {
+  const int64_t r = blockIdx.x, P = r / nao, m = r % nao;
+  const double* Bp = B + P * npair;
+  double mx = 0.0;
+  for (int64_t k = threadIdx.x; k < nao; k += 256) {
+    const int64_t hi = m > k ? m : k, lo = m > k ? k : m;
+    mx = fmax(mx, fabs(Bp[hi * (hi + 1) / 2 + lo]));
+  }
+  mx = block_max(mx);
+  if (threadIdx.x == 0 && mx > 0.0) atomicMax(ex + m, row_exponent(mx));
+}
+
+// One workgroup per (row group g = blockIdx.x, 128 k); thread t fills slot (rr = t % 32, 16 k at
+// 16 (t / 32)) of its block in every plane.  Lanes run along mu: for mu <= nu the 32 elements
+// of a load are one run of packed row nu.
+template <int S>
+__global__ void __launch_bounds__(256) split_packed_t_kernel(const double* __restrict__ B, int64_t naux,
+                                                             int64_t nao, int64_t npair, int64_t kp, int64_t y0,
+                                                             int8_t* planes, const int* ex) {
+  const int t = threadIdx.x, rr = t & 31;
+  const int64_t g = blockIdx.x, kq = (y0 + blockIdx.y) * 8 + (t >> 5);
+  if (16 * kq >= kp) return;
+  const int64_t m = 32 * g + rr, K = naux * nao;
+  double x[16];
+  if (m < nao) {
+    const int e = ex[m];
+    int64_t k = 16 * kq, P = k / nao, nu = k % nao;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      double v = 0.0;
+      if (k + q < K) {
+        const int64_t hi = m > nu ? m : nu, lo = m > nu ? nu : m;
+        v = B[P * npair + hi * (hi + 1) / 2 + lo];
+      }
+      x[q] = ldexp(v, kSplitBits0 - e);
+      if (++nu == nao) {
+        nu = 0;
+        ++P;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) x[q] = 0.0;
+  }
+  write_slot<S>(x, planes, (nao + 31) / 32, kp / 32, g, kq >> 1, rr + 32 * (int)(kq & 1));
+}
+
 // ---------------------------------------------------------------------------------------
 // Slice product.  Workgroup tile 128 x 64 over 8 waves (4 x 2) of 32 x 32, one
 // v_mfma_i32_32x32x32_i8 per slice pair and 32-deep k step.  Each k step moves S (4 + 2) blocks
@@ -464,6 +515,35 @@ hipError_t launch_split_packed(const double* B, int64_t naux, int64_t nao, int n
     case 6: return split_packed_s<6>(B, naux, nao, planes, ex, s);
     case 7: return split_packed_s<7>(B, naux, nao, planes, ex, s);
     case 8: return split_packed_s<8>(B, naux, nao, planes, ex, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int S>
+static hipError_t split_packed_t_s(const double* B, int64_t naux, int64_t nao, int8_t* planes, int* ex,
+                                   hipStream_t s) {
+  const int64_t npair = nao * (nao + 1) / 2, kp = kpad64(naux * nao);
+  fill_int_kernel<<<(unsigned)((nao + 255) / 256), 256, 0, s>>>(ex, nao, kNoExponent);
+  split_packed_t_max_kernel<<<(unsigned)(naux * nao), 256, 0, s>>>(B, nao, npair, ex);
+  const int64_t ny = (kp + 127) / 128;
+  for (int64_t y0 = 0; y0 < ny; y0 += 65535) {
+    const unsigned n = (unsigned)(ny - y0 < 65535 ? ny - y0 : 65535);
+    split_packed_t_kernel<S><<<dim3((unsigned)(rpad32(nao) / 32), n), 256, 0, s>>>(B, naux, nao, npair, kp, y0,
+                                                                                   planes, ex);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_split_packed_t(const double* B, int64_t naux, int64_t nao, int nslice, int8_t* planes, int* ex,
+                                 hipStream_t s) {
+  if (naux <= 0 || nao <= 0) return hipSuccess;
+  if (naux * nao > 0x7fffffffLL) return hipErrorInvalidValue;
+  switch (nslice) {
+    case 4: return split_packed_t_s<4>(B, naux, nao, planes, ex, s);
+    case 5: return split_packed_t_s<5>(B, naux, nao, planes, ex, s);
+    case 6: return split_packed_t_s<6>(B, naux, nao, planes, ex, s);
+    case 7: return split_packed_t_s<7>(B, naux, nao, planes, ex, s);
+    case 8: return split_packed_t_s<8>(B, naux, nao, planes, ex, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -30,6 +30,7 @@ DF_OP_STEP = 5
 DF_OP_STEP_BACKWARD = 6
 DF_OP_SPLIT_MATMUL = 7
 DF_OP_STEP_SPLIT = 8
+DF_OP_STEP_BACKWARD_SPLIT = 9
 
 DF_PAPA_FULL = 0x1
 DF_CALLER_X = 0x10
@@ -44,7 +45,8 @@ EXPORTED = ["df_create", "df_destroy", "df_last_error", "df_set_stream", "df_set
             "df_set_timing", "df_timing_read", "df_workspace_size", "df_half_transform", "df_jk",
             "df_active_eri", "df_papa", "df_step", "df_step_backward", "df_split_matmul",
             "df_split_cholesky", "df_step_split", "df_batched_workspace_size", "df_batched_step",
-            "df_set_autotune", "df_batched_tuning", "df_batched_set_tuning"]
+            "df_set_autotune", "df_batched_tuning", "df_batched_set_tuning", "df_split_cholesky_t",
+            "df_step_backward_split"]
 
 
 class DFError(RuntimeError):
@@ -102,7 +104,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         L.df_split_matmul.argtypes = [vp, dp, i64, i64, dp, i64, i64, i64, i32, dp, i64, i32]
         L.df_split_cholesky.argtypes = [vp, dp, i64, i64, i32, vp, vp, i32]
         L.df_step_split.argtypes = [vp, dp, vp, vp, i32, i64, i64, dp, i64, dp, i64, dp, i64,
-                                    dp, dp, dp, dp, dp, i32]
+                                    dp, dp, dp, dp, dp, dp, dp, i32]
+        L.df_split_cholesky_t.argtypes = [vp, dp, i64, i64, i32, vp, vp, i32]
+        L.df_step_backward_split.argtypes = [vp, dp, vp, vp, i32, i64, i64, dp, i64, dp, i64, dp, dp, dp, dp, dp,
+                                             dp, dp, i32]
         for name in EXPORTED:
             if name != "df_last_error":
                 getattr(L, name).restype = ctypes.c_int
@@ -494,8 +499,10 @@ def split_cholesky(B, nao: int, nslice: int = 7, ctx: Context | None = None):
     return Bs, Be
 
 
-def step_split(B, Bs, Be, nao: int, Cocc, Cact, Cp, outputs=None, ctx: Context | None = None):
-    """df_step in split precision (df_step_split); nslice is taken from Bs."""
+def step_split(B, Bs, Be, nao: int, Cocc, Cact, Cp, outputs=None, keep_x=False, ctx: Context | None = None):
+    """df_step in split precision (df_step_split); nslice is taken from Bs.  With keep_x the
+    half-transformed factors are returned too, as "Xocc" [naux, nao, nocc] and "Xact"
+    [nao, naux, nac] (what df_step_backward_split takes)."""
     import torch
     ctx = ctx or context(B.device)
     for n, t in (("B", B), ("Cocc", Cocc), ("Cact", Cact), ("Cp", Cp)):
@@ -516,14 +523,60 @@ def step_split(B, Bs, Be, nao: int, Cocc, Cact, Cp, outputs=None, ctx: Context |
             "eri": torch.empty((nac,) * 4, dtype=torch.float64, device=dev),
             "papa": torch.empty((np_, nac, nac, nac), dtype=torch.float64, device=dev),
         }
+    if keep_x:
+        outputs.setdefault("Xocc", torch.empty((naux, nao, nocc), dtype=torch.float64, device=dev))
+        outputs.setdefault("Xact", torch.empty((nao, naux, nac), dtype=torch.float64, device=dev))
     o = outputs
-    for k in ("J", "K", "v", "eri", "papa"):
+    for k in ("J", "K", "v", "eri", "papa", "Xocc", "Xact"):
         _check_tensor(k, o.get(k), dev)
-    ctx.prepare(DF_OP_STEP_SPLIT, naux=naux, nao=nao, ndm=1, nocc=nocc, nac=nac, np=np_, nslice=nslice)
+    caller_x = o.get("Xocc") is not None
+    ctx.prepare(DF_OP_STEP_SPLIT, naux=naux, nao=nao, ndm=1, nocc=nocc, nac=nac, np=np_, nslice=nslice,
+                flags=DF_CALLER_X if caller_x else 0)
     ctx.check(ctx._lib.df_step_split(ctx.handle, _ptr(B), _ptr(Bs), _ptr(Be), nslice, naux, nao, _ptr(Cocc), nocc,
                                      _ptr(Cact), nac, _ptr(Cp), np_, _ptr(o.get("J")), _ptr(o.get("K")),
-                                     _ptr(o.get("v")), _ptr(o.get("eri")), _ptr(o.get("papa")), 0))
+                                     _ptr(o.get("v")), _ptr(o.get("eri")), _ptr(o.get("papa")),
+                                     _ptr(o.get("Xocc")), _ptr(o.get("Xact")), 0))
     return outputs
+
+
+def split_cholesky_t(B, nao: int, nslice: int = 7, ctx: Context | None = None):
+    """int8 planes (split_plane_shape(nao, naux*nao, nslice)) and exponents [nao] of the rows mu of
+    the DF tensor over k = P*nao + nu (df_split_cholesky_t)."""
+    import torch
+    ctx = ctx or context(B.device)
+    _check_tensor("B", B, ctx.device)
+    naux = _naux_of(B, nao)
+    Bt = torch.empty(split_plane_shape(nao, naux * nao, nslice), dtype=torch.int8, device=ctx.device)
+    Bte = torch.empty((nao,), dtype=torch.int32, device=ctx.device)
+    ctx.bind_stream()
+    ctx.check(ctx._lib.df_split_cholesky_t(ctx.handle, _ptr(B), naux, nao, nslice, _ptr(Bt), _ptr(Bte), 0))
+    return Bt, Bte
+
+
+def step_backward_split(B, Bt, Bte, nao: int, Cocc, Cact, gJ=None, gK=None, geri=None, Xocc=None, Xact=None,
+                        ctx: Context | None = None):
+    """step_backward with the exchange part as slice products (df_step_backward_split); nslice is
+    taken from Bt.  Xocc and Xact come from step_split(..., keep_x=True) or step(..., keep_x=True)."""
+    import torch
+    ctx = ctx or context(B.device)
+    for n, t in (("B", B), ("Cocc", Cocc), ("Cact", Cact), ("gJ", gJ), ("gK", gK), ("geri", geri),
+                 ("Xocc", Xocc), ("Xact", Xact)):
+        _check_tensor(n, t, ctx.device)
+    naux = _naux_of(B, nao)
+    nslice = Bt.shape[0]
+    if (Bt.dtype != torch.int8 or Bte.dtype != torch.int32 or tuple(Bt.shape) != split_plane_shape(nao, naux * nao, nslice)
+            or tuple(Bte.shape) != (nao,) or not Bt.is_contiguous() or not Bte.is_contiguous()):
+        raise ValueError("Bt, Bte must come from split_cholesky_t(B, nao)")
+    nocc, nac = Cocc.shape[1], Cact.shape[1]
+    dCocc = torch.empty_like(Cocc)
+    dCact = torch.empty_like(Cact)
+    flags = ((DF_BWD_GJ if gJ is not None else 0) | (DF_BWD_GK if gK is not None else 0)
+             | (DF_BWD_GERI if geri is not None else 0))
+    ctx.prepare(DF_OP_STEP_BACKWARD_SPLIT, naux=naux, nao=nao, ndm=1, nocc=nocc, nac=nac, nslice=nslice, flags=flags)
+    ctx.check(ctx._lib.df_step_backward_split(ctx.handle, _ptr(B), _ptr(Bt), _ptr(Bte), nslice, naux, nao,
+                                              _ptr(Cocc), nocc, _ptr(Cact), nac, _ptr(gJ), _ptr(gK), _ptr(geri),
+                                              _ptr(Xocc), _ptr(Xact), _ptr(dCocc), _ptr(dCact), 0))
+    return dCocc, dCact
 
 
 def _autograd_function():

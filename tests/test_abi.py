@@ -195,12 +195,46 @@ def test_split_argument_errors(L, ctx):
     assert L.df_split_cholesky(ctx, B, 10, 7, 7, fake((4 << 30) + 8), Be, 0) == dfmi.DF_ERR_ARG   # Bs unaligned
     s = L.df_step_split
     Co, Ca, Cp, J, K = fake(6 << 30), fake(7 << 30), fake(8 << 30), fake(9 << 30), fake(10 << 30)
-    assert s(ctx, B, None, Be, 7, 10, 7, Co, 3, Ca, 2, Cp, 7, J, K, None, None, None, 0) == dfmi.DF_ERR_ARG
-    assert s(ctx, B, Bs, Be, 7, 10, 7, None, 3, Ca, 2, Cp, 7, J, K, None, None, None, 0) == dfmi.DF_ERR_ARG
-    assert s(ctx, B, Bs, Be, 3, 10, 7, Co, 3, Ca, 2, Cp, 7, J, K, None, None, None, 0) == dfmi.DF_ERR_SHAPE
+    assert s(ctx, B, None, Be, 7, 10, 7, Co, 3, Ca, 2, Cp, 7, J, K, None, None, None, None, None, 0) == dfmi.DF_ERR_ARG
+    assert s(ctx, B, Bs, Be, 7, 10, 7, None, 3, Ca, 2, Cp, 7, J, K, None, None, None, None, None, 0) == dfmi.DF_ERR_ARG
+    assert s(ctx, B, Bs, Be, 3, 10, 7, Co, 3, Ca, 2, Cp, 7, J, K, None, None, None, None, None, 0) == dfmi.DF_ERR_SHAPE
     Bu = fake((4 << 30) + 8)
-    assert s(ctx, B, Bu, Be, 7, 10, 7, Co, 3, Ca, 2, Cp, 7, J, K, None, None, None, 0) == dfmi.DF_ERR_ARG
-    assert s(ctx, B, Bs, Be, 7, 10, 7, Co, 3, Ca, 2, Cp, 7, J, K, None, None, None, 0) == dfmi.DF_ERR_WORKSPACE
+    assert s(ctx, B, Bu, Be, 7, 10, 7, Co, 3, Ca, 2, Cp, 7, J, K, None, None, None, None, None, 0) == dfmi.DF_ERR_ARG
+    assert s(ctx, B, Bs, Be, 7, 10, 7, Co, 3, Ca, 2, Cp, 7, J, K, None, None, None, None, None, 0) == dfmi.DF_ERR_WORKSPACE
+
+
+def test_split_adjoint_argument_errors(L, ctx):
+    B, Bt, Bte = fake(1 << 30), fake(2 << 30), fake(3 << 30)
+    Co, Ca, gK, Xo, Xa, dCo, dCa = (fake(k << 30) for k in range(4, 11))
+    t = L.df_split_cholesky_t
+    assert t(ctx, B, 10, 7, 7, None, Bte, 0) == dfmi.DF_ERR_ARG
+    assert t(ctx, B, 10, 7, 3, Bt, Bte, 0) == dfmi.DF_ERR_SHAPE
+    assert t(ctx, B, 10, 7, 7, fake((2 << 30) + 8), Bte, 0) == dfmi.DF_ERR_ARG      # Bt unaligned
+    assert t(ctx, B, 10, 7, 7, Bt, Bte, 1) == dfmi.DF_ERR_UNSUPPORTED
+    b = L.df_step_backward_split
+    args = [ctx, B, Bt, Bte, 7, 10, 7, Co, 3, Ca, 2, None, gK, None, Xo, Xa, dCo, dCa, 0]
+    assert b(*args) == dfmi.DF_ERR_WORKSPACE
+    for i, code in ((2, dfmi.DF_ERR_ARG),        # gK without Bt
+                    (14, dfmi.DF_ERR_ARG),       # gK without Xocc
+                    (16, dfmi.DF_ERR_ARG)):      # nocc > 0 without dCocc
+        bad = list(args)
+        bad[i] = None
+        assert b(*bad) == code
+    bad = list(args)
+    bad[4] = 9
+    assert b(*bad) == dfmi.DF_ERR_SHAPE
+    bad = list(args)
+    bad[13] = fake(11 << 30)                      # geri without Xact
+    bad[15] = None
+    assert b(*bad) == dfmi.DF_ERR_ARG
+    # Xocc and Xact of df_step_split go together
+    s = L.df_step_split
+    Bs, Be, Cp, J, K = fake(12 << 30), fake(13 << 30), fake(14 << 30), fake(15 << 30), fake(16 << 30)
+    assert s(ctx, B, Bs, Be, 7, 10, 7, Co, 3, Ca, 2, Cp, 7, J, K, None, None, None, Xo, None, 0) == dfmi.DF_ERR_ARG
+    w = dfmi.workspace_size(dfmi.DF_OP_STEP_BACKWARD_SPLIT, naux=20, nao=9, nocc=4, nac=2, nslice=7,
+                            flags=dfmi.DF_BWD_GK)
+    assert w >= 7 * 32 * 192 + 7 * 96 * 64      # planes of Y (rows i over (P, nu)) and of X
+    assert dfmi.workspace_size(dfmi.DF_OP_STEP_BACKWARD_SPLIT, naux=20, nao=9, nocc=4, nac=2, nslice=7) < w
 
 
 def test_split_workspace_sizes():

@@ -154,3 +154,77 @@ def test_split_energy_error_medium(S, bar):
     E = math.fsum(terms)
     E_ref = G.energy(Bp, wl.nao, C, wl.nocc, wl.nac, h, Gam)
     assert abs(E - E_ref) <= bar, (E - E_ref, E_ref)
+
+
+def unblock(blocks):
+    """[S][row group][k block][1024] -> [S][32 G][32 KB]: slot rr + 32 c of block (s, g, b) holds
+    k = 32 b + 16 c + [0, 16) of row 32 g + rr."""
+    S, G, KB = blocks.shape[:3]
+    return blocks.reshape(S, G, KB, 2, 32, 16).transpose(0, 1, 4, 2, 3, 5).reshape(S, 32 * G, 32 * KB)
+
+
+@pytest.mark.parametrize("nao,naux", [(1, 2), (33, 17), (70, 9)])
+def test_split_cholesky_t_reconstructs_rows(nao, naux):
+    """Rows mu of the DF tensor over k = (P, nu): b^P_{mu nu} within 2^(e - 7 S) of the slices."""
+    S = 7
+    Bp = synth.cholesky_vectors(naux, nao, 8.0, seed=nao + 1)
+    Bt, Bte = dfmi.split_cholesky_t(dev(Bp), nao, nslice=S)
+    torch.cuda.synchronize()
+    planes = unblock(Bt.cpu().numpy().astype(np.float64))
+    assert planes.shape == (S, (nao + 31) // 32 * 32, (naux * nao + 63) // 64 * 64)
+    assert np.abs(planes).max() <= 64
+    rows = O.unpack(Bp, nao).transpose(1, 0, 2).reshape(nao, naux * nao)   # [mu][(P, nu)]
+    ex = Bte.cpu().numpy().astype(np.float64)
+    assert np.array_equal(ex, row_exp(rows))
+    assert not planes[:, nao:, :].any() and not planes[:, :, naux * nao:].any()
+    planes = planes[:, :nao, :naux * nao]
+    rec = sum(planes[s] * np.exp2(-6 - 7 * s) for s in range(S)) * np.exp2(ex)[:, None]
+    assert np.all(np.abs(rec - rows) <= np.exp2(ex - 7 * S)[:, None])
+
+
+ADJ_SHAPES = [(120, 480, 30, 8), (33, 17, 5, 3), (130, 9, 17, 5), (40, 1100, 16, 3), (9, 20, 4, 0), (7, 70, 0, 3)]
+
+
+@pytest.mark.parametrize("nao,naux,nocc,nac", ADJ_SHAPES)
+def test_step_backward_split_matches_oracle(nao, naux, nocc, nac):
+    """Split forward (keeping X) then the split adjoint, against the oracle's VJP; and against the
+    FP64 adjoint on the same saved factors.  (40, 1100, 16, 3) contracts over 44000 (P, nu): the
+    last product runs as two k splits."""
+    Bp, C, gB, Bs, Be = split_problem(nao, naux, nocc, nac, 7, seed=nao + 2 * naux)
+    Bt, Bte = dfmi.split_cholesky_t(gB, nao, nslice=7)
+    Co, Ca = C[:, :nocc].copy(), C[:, nocc:nocc + nac].copy()
+    out = dfmi.step_split(gB, Bs, Be, nao, dev(Co), dev(Ca), dev(C), keep_x=True)
+    torch.cuda.synchronize()
+    if nocc:
+        close(out["Xocc"], O.half_transform(Bp, nao, Co), 1e-11)
+    if nac:
+        close(out["Xact"], O.half_transform(Bp, nao, Ca).transpose(1, 0, 2), 1e-11)
+    rng = np.random.default_rng(nao)
+    gJ, gK = rng.standard_normal((nao, nao)), rng.standard_normal((nao, nao))
+    ge = rng.standard_normal((nac,) * 4)
+    ref_o, ref_a = G.step_vjp(Bp, nao, Co, Ca, gJ, gK, ge)
+    args = (dev(Co), dev(Ca), dev(gJ), dev(gK), dev(ge), out["Xocc"], out["Xact"])
+    dCo, dCa = dfmi.step_backward_split(gB, Bt, Bte, nao, *args)
+    f_o, f_a = dfmi.step_backward(gB, nao, *args)
+    torch.cuda.synchronize()
+    if nocc:
+        close(dCo, ref_o, 1e-11)
+        close(dCo, f_o.cpu().numpy(), 1e-11)
+    if nac:
+        close(dCa, ref_a, 1e-11)
+        close(dCa, f_a.cpu().numpy(), 1e-11)
+
+
+def test_step_backward_split_exchange_medium():
+    """Medium workload: with gK = D/2 the exchange part of the adjoint is K C_occ (oracle K)."""
+    wl = synth.WORKLOADS["medium"]
+    Bp, C, gB, Bs, Be = split_problem(wl.nao, wl.naux, wl.nocc, wl.nac, 7, seed=0, L=wl.L)
+    Bt, Bte = dfmi.split_cholesky_t(gB, wl.nao, nslice=7)
+    Co, Ca = C[:, :wl.nocc].copy(), C[:, wl.nocc:wl.nocc + wl.nac].copy()
+    out = dfmi.step_split(gB, Bs, Be, wl.nao, dev(Co), dev(Ca), dev(C), keep_x=True)
+    D = Co @ Co.T
+    dCo, _ = dfmi.step_backward_split(gB, Bt, Bte, wl.nao, dev(Co), dev(Ca), None, dev(0.5 * D), None,
+                                      out["Xocc"], out["Xact"])
+    torch.cuda.synchronize()
+    K = O.exchange(Bp, wl.nao, Co)
+    close(dCo, K @ Co, 1e-11)
