@@ -46,6 +46,9 @@ struct Cfg {
 // workgroups' LDS per CU), so one wave's barrier and LDS latency hide behind the other's MFMAs.
 // generic products and the K SYRK: 128 x 128 tiles, 2 x 2 waves of 64 x 64, interleaved
 typedef Cfg<2, 2, 4, 4, true> CfgSq;
+// tall products (M >= 256): 256 x 128 tiles, 4 x 2 waves of 64 x 64, one workgroup per CU; the
+// same per-wave work with a quarter fewer loads per MFMA
+typedef Cfg<4, 2, 4, 4, true> CfgTall;
 typedef Cfg<2, 2, 4, 4, true> CfgSyrk;
 // small matrices (fragment sizes): 64 x 64 SYRK tiles pad the triangle less
 typedef Cfg<2, 2, 2, 2, true> CfgSyrk64;
@@ -883,10 +886,14 @@ hipError_t launch_half_transform(const double* B, int64_t naux, int64_t nao, con
   }
 }
 
-template <bool GEN, bool CLAMP>
+// The 256-row tile when it pads the rows no more than the 128-row one.
+static bool gemm_tall(int64_t M) {
+  return M >= 256 && cdiv(M, CfgTall::BM) * CfgTall::BM <= cdiv(M, CfgSq::BM) * CfgSq::BM;
+}
+
+template <class Cg, bool GEN, bool CLAMP>
 static void gemm_go(const OpMap& A, const OpMap& Bm, const OutMap& O, dim3 grid, int64_t tm, int64_t tn, double* part,
                     hipStream_t s) {
-  typedef CfgSq Cg;
   const bool ak = A.s_kc == 1, bk = Bm.s_kc == 1;
   if (ak && bk) gemm_kernel<Cg, true, true, GEN, CLAMP><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn, part);
   else if (ak) gemm_kernel<Cg, true, false, GEN, CLAMP><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn, part);
@@ -894,9 +901,9 @@ static void gemm_go(const OpMap& A, const OpMap& Bm, const OutMap& O, dim3 grid,
   else gemm_kernel<Cg, false, false, GEN, CLAMP><<<grid, Cg::NT, 0, s>>>(A, Bm, O, tm, tn, part);
 }
 
-static hipError_t gemm_launch(const OpMap& A, const OpMap& Bm, const OutMap& O, int64_t nz, int nsplit,
-                              double* part, hipStream_t s) {
-  typedef CfgSq Cg;
+template <class Cg>
+static hipError_t gemm_launch_cfg(const OpMap& A, const OpMap& Bm, const OutMap& O, int64_t nz, int nsplit,
+                                  double* part, hipStream_t s) {
   const int64_t tm = cdiv(O.M, Cg::BM), tn = cdiv(O.N, Cg::BN);
   if (tm * tn == 0 || nz == 0) return hipSuccess;
   if (tm * tn > 0x7fffffffLL || nz > 65535 || nsplit < 1 || nsplit > 65535 || !offsets_fit(A) || !offsets_fit(Bm) ||
@@ -905,10 +912,16 @@ static hipError_t gemm_launch(const OpMap& A, const OpMap& Bm, const OutMap& O, 
   const dim3 grid((unsigned)(tm * tn), (unsigned)nsplit, (unsigned)nz);
   // whole slabs (no clamping) when the contraction chunks are multiples of 16
   const bool clamp = A.kc_n % 16 != 0;
-  if (!part && (O.alpha != 1.0 || O.accumulate)) gemm_go<true, true>(A, Bm, O, grid, tm, tn, part, s);
-  else if (clamp) gemm_go<false, true>(A, Bm, O, grid, tm, tn, part, s);
-  else gemm_go<false, false>(A, Bm, O, grid, tm, tn, part, s);
+  if (!part && (O.alpha != 1.0 || O.accumulate)) gemm_go<Cg, true, true>(A, Bm, O, grid, tm, tn, part, s);
+  else if (clamp) gemm_go<Cg, false, true>(A, Bm, O, grid, tm, tn, part, s);
+  else gemm_go<Cg, false, false>(A, Bm, O, grid, tm, tn, part, s);
   return hipGetLastError();
+}
+
+static hipError_t gemm_launch(const OpMap& A, const OpMap& Bm, const OutMap& O, int64_t nz, int nsplit,
+                              double* part, hipStream_t s) {
+  return gemm_tall(O.M) ? gemm_launch_cfg<CfgTall>(A, Bm, O, nz, nsplit, part, s)
+                        : gemm_launch_cfg<CfgSq>(A, Bm, O, nz, nsplit, part, s);
 }
 
 hipError_t launch_gemm(const OpMap& A, const OpMap& Bm, const OutMap& O, int64_t nz, hipStream_t s) {
@@ -945,7 +958,8 @@ static int balanced_splits(int64_t tiles, int64_t max_split) {
 }
 
 int gemm_splits(int64_t M, int64_t N, int64_t nslab) {
-  // at least four slabs per split
+  // at least four slabs per split; a tall tile takes the room of two resident workgroups
+  if (gemm_tall(M)) return balanced_splits(2 * cdiv(M, CfgTall::BM) * cdiv(N, CfgTall::BN), nslab / 4);
   return balanced_splits(cdiv(M, CfgSq::BM) * cdiv(N, CfgSq::BN), nslab / 4);
 }
 
