@@ -45,6 +45,25 @@ SHAPES = [(120, 480, 30, 8), (33, 17, 5, 3), (130, 9, 17, 5), (2, 3, 1, 1), (257
           (6, 4, 5, 0), (6, 4, 0, 3)]
 
 
+def test_vjp_tall_tiles():
+    """N_ao = 500 pads to 512 rows in both tile heights, so Y_P = S X_P and the second transforms
+    take the 256 x 128 tiles (ragged in every dimension)."""
+    nao, naux, nocc, nac = 500, 30, 21, 6
+    B, Co, Ca = problem(nao, naux, nocc, nac, seed=5)
+    rng = np.random.default_rng(11)
+    gJ, gK = rng.standard_normal((nao, nao)), rng.standard_normal((nao, nao))
+    ge = rng.standard_normal((nac,) * 4)
+    ref_o, ref_a = G.step_vjp(B, nao, Co, Ca, gJ, gK, ge)
+    gB, gCo, gCa = dev(B), dev(Co), dev(Ca)
+    C = synth.orbitals(nao, seed=5)                       # all 500 orbitals as p: b_pu has 500 rows
+    out = dfmi.step(gB, nao, gCo, gCa, dev(C), keep_x=True)
+    dCo, dCa = dfmi.step_backward(gB, nao, gCo, gCa, dev(gJ), dev(gK), dev(ge), out["Xocc"], out["Xact"])
+    torch.cuda.synchronize()
+    close(dCo, ref_o, what="dCocc")
+    close(dCa, ref_a, what="dCact")
+    close(out["papa"], O.papa(B, nao, C, Ca), what="(pu|vw) with 500 orbitals p")
+
+
 @pytest.mark.parametrize("nao,naux,nocc,nac", SHAPES)
 @pytest.mark.parametrize("which", ["J", "K", "eri", "all"])
 @pytest.mark.parametrize("keep_x", [False, True])
