@@ -470,17 +470,21 @@ struct SyrkDesc {
 struct SyrkGroup {
   int n;
   int64_t start[kMaxGroup + 1];
+  int64_t xs[9];   // items of XCD x: [xs[x], xs[x + 1])
   SyrkDesc d[kMaxGroup];
 };
 
+// With the per-XCD chunks of half_group_kernel.
 template <class C, bool CLAMP>
 __global__ void __launch_bounds__(C::NT) syrk_group_kernel(SyrkGroup g) {
   __shared__ double smem[2 * C::STAGE];
-  const int64_t bid = xcd_remap(blockIdx.x, g.start[g.n]);
+  const int x = blockIdx.x % 8;
+  const int64_t it = g.xs[x] + blockIdx.x / 8;
+  if (it >= g.xs[x + 1]) return;
   int p = 0;
-  while (p + 1 < g.n && bid >= g.start[p + 1]) ++p;
+  while (p + 1 < g.n && it >= g.start[p + 1]) ++p;
   const SyrkDesc& d = g.d[p];
-  const int64_t item = bid - g.start[p], per_z = d.npairs * d.nsplit;
+  const int64_t item = it - g.start[p], per_z = d.npairs * d.nsplit;
   syrk_tile<C, false, CLAMP>(d.A, d.A, d.n, d.nz, d.nsplit, d.npairs, d.Kpart, item % per_z, item / per_z, smem);
 }
 
@@ -633,17 +637,26 @@ struct HalfDesc {
 struct HalfGroup {
   int n;
   int64_t start[kMaxGroup + 1];
+  int64_t xs[9];   // items of XCD x: [xs[x], xs[x + 1])
   HalfDesc d[kMaxGroup];
 };
 
+// Grouped launches: the item list is cut into 8 contiguous chunks of about equal cost, one per
+// XCD.  The dispatcher deals workgroups to the 8 XCDs in turn, so workgroup b runs on XCD b % 8
+// and takes item b / 8 of that XCD's chunk (workgroups past the end of their chunk exit):
+// consecutive items run side by side on one XCD and share its L2, and every XCD gets the same
+// work although the items of different problems differ in cost.  (A persistent grid striding
+// through the chunks balanced uneven items worse than the dispatcher does.)
 template <class C>
 __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) half_group_kernel(HalfGroup g) {
   __shared__ double smem[2 * C::STAGE];
-  const int64_t bid = xcd_remap(blockIdx.x, g.start[g.n]);
+  const int x = blockIdx.x % 8;
+  const int64_t item = g.xs[x] + blockIdx.x / 8;
+  if (item >= g.xs[x + 1]) return;
   int p = 0;
-  while (p + 1 < g.n && bid >= g.start[p + 1]) ++p;
+  while (p + 1 < g.n && item >= g.start[p + 1]) ++p;
   const HalfDesc& d = g.d[p];
-  half_tile<C>(d.B, d.nao, d.npair, d.Cm, d.out, d.tilesM, d.tilesN, bid - g.start[p], smem);
+  half_tile<C>(d.B, d.nao, d.npair, d.Cm, d.out, d.tilesM, d.tilesN, item - g.start[p], smem);
 }
 
 // part[split] (m, n) = sum_{P in split} sum_k b^P_{mk} Y(n, (P, k)): the packed half-transform
@@ -1072,6 +1085,33 @@ hipError_t launch_syrk_partial(const OpMap& A, const OpMap& Bw, int64_t n, int64
 }
 
 // ---- grouped launches ----
+// Cuts items [0, start[n]) into 8 contiguous chunks of about equal cost (each item of problem p
+// costs cost[p]) and returns the length of the longest (the grid is 8 times that).
+static int64_t xcd_chunks(const int64_t* start, const double* cost, int n, int64_t* xs) {
+  double total = 0.0;
+  for (int p = 0; p < n; ++p) total += (double)(start[p + 1] - start[p]) * cost[p];
+  xs[0] = 0;
+  int p = 0;
+  double before = 0.0;   // cost of the items of problems before p
+  for (int x = 1; x < 8; ++x) {
+    const double target = total * x / 8.0;
+    while (p < n && before + (double)(start[p + 1] - start[p]) * cost[p] <= target) {
+      before += (double)(start[p + 1] - start[p]) * cost[p];
+      ++p;
+    }
+    int64_t i = start[n];
+    if (p < n) {
+      i = start[p] + (int64_t)((target - before) / cost[p] + 0.5);
+      if (i > start[p + 1]) i = start[p + 1];
+    }
+    xs[x] = i < xs[x - 1] ? xs[x - 1] : i;
+  }
+  xs[8] = start[n];
+  int64_t longest = 1;
+  for (int x = 0; x < 8; ++x) longest = xs[x + 1] - xs[x] > longest ? xs[x + 1] - xs[x] : longest;
+  return longest;
+}
+
 template <class Cg>
 static hipError_t half_group_go(const GroupHalf* probs, int n, hipStream_t s) {
   HalfGroup g{};
@@ -1092,7 +1132,11 @@ static hipError_t half_group_go(const GroupHalf* probs, int n, hipStream_t s) {
   }
   if (g.start[n] == 0) return hipSuccess;
   if (g.start[n] > 0x7fffffffLL) return hipErrorInvalidValue;
-  half_group_kernel<Cg><<<(unsigned)g.start[n], Cg::NT, 0, s>>>(g);
+  double cost[kMaxGroup];   // slabs per item, plus about two for the prologue and the epilogue
+  for (int p = 0; p < n; ++p) cost[p] = (double)cdiv(g.d[p].nao, Cg::BK) + 2.0;
+  const int64_t per = xcd_chunks(g.start, cost, n, g.xs);
+  if (8 * per > 0x7fffffffLL) return hipErrorInvalidValue;
+  half_group_kernel<Cg><<<(unsigned)(8 * per), Cg::NT, 0, s>>>(g);
   return hipGetLastError();
 }
 
@@ -1129,8 +1173,13 @@ static hipError_t syrk_group_go(const GroupSyrk* probs, int n, hipStream_t s) {
   }
   if (g.start[n] == 0) return hipSuccess;
   if (g.start[n] > 0x7fffffffLL) return hipErrorInvalidValue;
-  if (clamp) syrk_group_kernel<Cg, true><<<(unsigned)g.start[n], Cg::NT, 0, s>>>(g);
-  else syrk_group_kernel<Cg, false><<<(unsigned)g.start[n], Cg::NT, 0, s>>>(g);
+  double cost[kMaxGroup];   // slabs of one split, plus about two for the prologue and the epilogue
+  for (int p = 0; p < n; ++p)
+    cost[p] = (double)cdiv(g.d[p].A.kb_n, g.d[p].nsplit) * (double)cdiv(g.d[p].A.kc_n, Cg::BK) + 2.0;
+  const int64_t per = xcd_chunks(g.start, cost, n, g.xs);
+  if (8 * per > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (clamp) syrk_group_kernel<Cg, true><<<(unsigned)(8 * per), Cg::NT, 0, s>>>(g);
+  else syrk_group_kernel<Cg, false><<<(unsigned)(8 * per), Cg::NT, 0, s>>>(g);
   return hipGetLastError();
 }
 
