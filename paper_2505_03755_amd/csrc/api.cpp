@@ -289,8 +289,8 @@ BwdSplitPlan plan_backward_split(Plan& pl, int64_t naux, int64_t nao, int64_t no
 
 // ---- batched problems ----
 struct BatchedPiece {
-  size_t cpad, xo, xa, v, jp, kpart, buv, bpu;
-  int nsplit;
+  size_t cpad, xo, xa, v, jp, kpart, buv, bpu, dfull, dw, vpart;
+  int nsplit, vsplit;
 };
 int64_t batched_ncol(const df_problem& q) { return q.ndm * q.nocc + q.nac; }
 // half-transform work of a problem, for the largest-first order
@@ -365,6 +365,10 @@ std::string batched_key(const df_problem* probs, int n) {
 // J of many densities as one product: Jp[z][pair] = sum_P v[z][P] b^P[pair] (then unpacked)
 bool batched_j_gemm(const df_problem& q) { return q.ndm > 4; }
 
+// The J-vectors from packed B and the packed densities (v = Dw B^T) instead of from X_occ, when
+// X_occ (naux nao ndm nocc) is the larger of the two to read (B: naux npair).
+bool batched_jvec_from_b(const df_problem& q) { return q.J && q.nocc > 0 && 2 * q.ndm * q.nocc > q.nao + 1; }
+
 std::vector<BatchedPiece> plan_batched(Plan& pl, const df_problem* probs, int n) {
   std::vector<BatchedPiece> v((size_t)n);
   const std::vector<int> ks = batched_k_splits_max(probs, n);
@@ -377,6 +381,11 @@ std::vector<BatchedPiece> plan_batched(Plan& pl, const df_problem* probs, int n)
     b.xo = pl.take(need_x ? q.naux * q.nao * q.ndm * q.nocc : 0);   // P-major [naux][nao][ndm*nocc]
     b.xa = pl.take(need_x ? q.naux * q.nao * q.nac : 0);            // AO-major [nao][naux][nac]
     b.v = pl.take(q.J && q.nocc > 0 ? q.ndm * q.naux : 0);
+    const int64_t npair = q.nao * (q.nao + 1) / 2;
+    b.dfull = pl.take(batched_jvec_from_b(q) ? q.ndm * q.nao * q.nao : 0);
+    b.dw = pl.take(batched_jvec_from_b(q) ? q.ndm * npair : 0);
+    b.vsplit = batched_jvec_from_b(q) ? dfk::gemm_splits(q.ndm, q.naux, (npair + 15) / 16) : 1;
+    b.vpart = pl.take(b.vsplit > 1 ? (int64_t)b.vsplit * q.ndm * q.naux : 0);
     b.jp = pl.take(q.J && q.nocc > 0 && batched_j_gemm(q) ? q.ndm * q.nao * (q.nao + 1) / 2 : 0);
     b.nsplit = ks[(size_t)i];
     b.kpart = pl.take(q.K && q.nocc > 0 ? (int64_t)b.nsplit * q.ndm * q.nao * q.nao : 0);
@@ -1448,7 +1457,8 @@ df_status df_batched_step(df_ctx* ctx, const df_problem* probs, int nprob, int f
     const df_problem& q = probs[i];
     const std::string tag = "problem " + std::to_string(i) + " ";
     if (df_status s = check_core(c, q.B, q.naux, q.nao)) return s;
-    if (q.ndm < 1 || q.nocc < 0 || q.nac < 0 || q.np < 0) return fail(c, DF_ERR_SHAPE, tag + "has a bad size");
+    if (q.ndm < 1 || q.ndm > 65535 || q.nocc < 0 || q.nac < 0 || q.np < 0)
+      return fail(c, DF_ERR_SHAPE, tag + "has a bad size");
     if (q.nocc > 0 && (q.J || q.K) && !q.Cocc) return fail(c, DF_ERR_ARG, tag + "Cocc is NULL");
     if (q.nac > 0 && (q.eri || q.papa) && !q.Cact) return fail(c, DF_ERR_ARG, tag + "Cact is NULL");
     if (q.np > 0 && q.papa && !q.Cp) return fail(c, DF_ERR_ARG, tag + "Cp is NULL");
@@ -1611,8 +1621,24 @@ df_status df_batched_step(df_ctx* ctx, const df_problem* probs, int nprob, int f
     const int64_t no = q.ndm * q.nocc;
     if (q.J && q.nocc > 0) {
       double* v = (double*)(ws + b.v);
-      DF_LAUNCH(DF_KERNEL_JVEC, dfk::launch_jvec(Xo, q.naux, q.nao, no, q.Cocc, nullptr, q.nocc, q.ndm, v, c->stream),
-                "J-vector launch");
+      if (batched_jvec_from_b(q)) {
+        // v[z][P] = sum_pair Dw[z][pair] b^P[pair]
+        const int64_t npair = q.nao * (q.nao + 1) / 2;
+        double* dw = (double*)(ws + b.dw);
+        DF_LAUNCH(DF_KERNEL_JVEC,
+                  dfk::launch_dens_pairs(q.Cocc, q.nao, q.nocc, q.ndm, (double*)(ws + b.dfull), dw, c->stream),
+                  "density launch");
+        const dfk::OpMap A = dfk::op_map(dw, q.ndm, npair, npair, 1);
+        const dfk::OpMap Bm = dfk::op_map(q.B, q.naux, npair, npair, 1);
+        DF_LAUNCH(DF_KERNEL_JVEC,
+                  dfk::launch_gemm_split(A, Bm, dfk::out_plain(v, q.ndm, q.naux, q.naux), b.vsplit,
+                                         (double*)(ws + b.vpart), c->stream),
+                  "J-vector product launch");
+      } else {
+        DF_LAUNCH(DF_KERNEL_JVEC,
+                  dfk::launch_jvec(Xo, q.naux, q.nao, no, q.Cocc, nullptr, q.nocc, q.ndm, v, c->stream),
+                  "J-vector launch");
+      }
       if (batched_j_gemm(q)) {
         const int64_t npair = q.nao * (q.nao + 1) / 2;
         double* jp = (double*)(ws + b.jp);

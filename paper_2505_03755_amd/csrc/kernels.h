@@ -79,6 +79,11 @@ hipError_t launch_half_reduce(const double* B, int64_t naux, int64_t nao, const 
 
 // g[pair(i,j)] = G[i][j] + G[j][i] (i > j), G[i][i] (i == j): <b^P, G> = sum_pair b^P[pair] g[pair]
 hipError_t launch_pair_weights(const double* G, int64_t nao, double* g, hipStream_t s);
+// Dw [ndm][npair] = the packed densities C_z C_z^T of C [ndm][nao][nocc], off-diagonal pairs
+// weighted 2 (so that v[z][P] = sum_pair b^P[pair] Dw[z][pair]); D [ndm][nao][nao] is scratch
+// for the full products.  ndm <= 65535.
+hipError_t launch_dens_pairs(const double* C, int64_t nao, int64_t nocc, int64_t ndm, double* D, double* Dw,
+                             hipStream_t s);
 // u[P] = sum_pair B[P][pair] g[pair]
 // (partial sums over jvec_packed_chunks() chunks of the pairs go to part [chunks][naux] first)
 int jvec_packed_chunks();

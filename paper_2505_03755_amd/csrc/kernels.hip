@@ -759,6 +759,8 @@ __global__ void __launch_bounds__(256) pair_weights_kernel(const double* __restr
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t npair = nao * (nao + 1) / 2;
   if (p >= npair) return;
+  G += (int64_t)blockIdx.y * nao * nao;   // matrix blockIdx.y of a batch
+  g += (int64_t)blockIdx.y * npair;
   int64_t i = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
   while (i * (i + 1) / 2 > p) --i;
   while ((i + 1) * (i + 2) / 2 <= p) ++i;
@@ -1030,6 +1032,22 @@ hipError_t launch_pair_weights(const double* G, int64_t nao, double* g, hipStrea
   const int64_t npair = nao * (nao + 1) / 2;
   if (npair == 0) return hipSuccess;
   pair_weights_kernel<<<(unsigned)cdiv(npair, 256), 256, 0, s>>>(G, nao, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_dens_pairs(const double* C, int64_t nao, int64_t nocc, int64_t ndm, double* D, double* Dw,
+                             hipStream_t s) {
+  const int64_t npair = nao * (nao + 1) / 2;
+  if (npair == 0 || ndm == 0) return hipSuccess;
+  if (ndm > 65535) return hipErrorInvalidValue;
+  // D_z = C_z C_z^T on the matrix cores, then packed with the pair weights
+  OpMap Cz = op_map(C, nao, nocc, nocc, 1);
+  Cz.s_z = nao * nocc;
+  OutMap O = out_plain(D, nao, nao, nao);
+  O.s_z = nao * nao;
+  hipError_t e = launch_gemm(Cz, Cz, O, ndm, s);
+  if (e != hipSuccess) return e;
+  pair_weights_kernel<<<dim3((unsigned)cdiv(npair, 256), (unsigned)ndm), 256, 0, s>>>(D, nao, Dw);
   return hipGetLastError();
 }
 
