@@ -223,10 +223,11 @@ def fragment_flops(f, ndm):
             + 2 * naux * n * nac * nac + 2 * naux * nac ** 4)
 
 
-def batched_fragments(ndm, reps, ctx):
+def batched_fragments(ndm, reps, ctx, nslice=7):
     """The eight fragment subproblems with ndm densities each: df_batched_step (grouped launches)
     with its default tiles, autotuned, and the tuned call replayed from a HIP graph, against the
-    same work issued problem by problem (df_jk, df_active_eri, df_papa FULL)."""
+    same work issued problem by problem (df_jk, df_active_eri, df_papa FULL); then the batch in
+    split precision (df_batched_step_split, nslice slices) with its largest difference to FP64."""
     import numpy as np
     import torch
     from paper_2505_03755_amd import dfmi, synth
@@ -280,6 +281,15 @@ def batched_fragments(ndm, reps, ctx):
     ms_g = timed(graph.replay)
     del graph
     ms_u = timed(unbatched)
+    # split precision: each fragment's B split once (not timed), then df_batched_step_split
+    ref = dfmi.batched_step(probs, ctx=ctx)
+    for p in probs:
+        p["Bs"], p["Be"] = dfmi.split_cholesky(p["B"], p["nao"], nslice=nslice, ctx=ctx)
+    ms_s = timed(lambda: dfmi.batched_step_split(probs, nslice=nslice, ctx=ctx))
+    spl = dfmi.batched_step_split(probs, nslice=nslice, ctx=ctx)
+    torch.cuda.synchronize()
+    srel = {k: max(((o[k] - r[k]).norm() / r[k].norm()).item() for o, r in zip(spl, ref)) for k in ("J", "K", "eri", "papa")}
+    del ref, spl
     fl = sum(fragment_flops(f, ndm) for f in synth.FRAGMENTS)
     del probs
     torch.cuda.empty_cache()
@@ -288,7 +298,9 @@ def batched_fragments(ndm, reps, ctx):
             "flops": fl, "ms_batched": ms_b, "tflops_batched": fl / ms_b / 1e9,
             "tuning": {k: tuning[k] for k in ("half_tile_n", "k_tile", "k_rounds")}, "tuning_call_s": tune_s,
             "ms_batched_default_tiles": ms_default, "ms_graph_replay": ms_g,
-            "ms_unbatched": ms_u, "tflops_unbatched": fl / ms_u / 1e9}
+            "ms_unbatched": ms_u, "tflops_unbatched": fl / ms_u / 1e9,
+            "split": {"nslice": nslice, "ms_batched": ms_s, "speedup_vs_fp64": ms_b / ms_s,
+                      "max_rel_diff_vs_fp64": srel}}
 
 
 def main():
@@ -438,7 +450,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_batched:
         log(f"[bench] batched fragment subproblems, {args.fragment_densities} densities each")
-        res["batched_fragments"] = batched_fragments(args.fragment_densities, 3, ctx)
+        res["batched_fragments"] = batched_fragments(args.fragment_densities, 3, ctx, args.split_slices)
     if not args.no_cpu_baseline:
         log(f"[bench] timing the CPU oracle on {args.cpu_rows} auxiliary rows")
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_rows, wl.seed, adjoint=not args.forward_only)

@@ -281,6 +281,20 @@ df_status df_batched_set_tuning(df_ctx* ctx, const df_problem* probs, int nprob,
                                 int k_rounds);
 
 /*
+ * df_batched_step in split precision: the same outputs of the same problems, with the half
+ * transform, every density's K, the second transforms, (uv|wx) and the full (pu|qv) as int8
+ * slice products (nslice slices, as in df_step_split); J and the J-vectors stay FP64.
+ *   - Bs[i], Be[i] are problem i's planes and exponents from df_split_cholesky with the same
+ *     nslice.
+ *   - Problems run one after another in the given order and share one workspace region,
+ *     df_batched_split_workspace_size(probs, nprob, nslice) bytes (the largest problem's need).
+ *   - The K products of all densities of a problem run as one launch.
+ */
+df_status df_batched_split_workspace_size(const df_problem* probs, int nprob, int nslice, size_t* bytes);
+df_status df_batched_step_split(df_ctx* ctx, const df_problem* probs, const int8_t* const* Bs, const int* const* Be,
+                                int nprob, int nslice, int flags);
+
+/*
  * Split precision on the int8 matrix cores.  An FP64 row x is cut into nslice int8 slices,
  *   x[k] ~= 2^e sum_{s < nslice} a_s[k] 2^-(6 + 7 s),   a_s in [-64, 64],  max|x| < 2^e,
  * exactly up to a residual below 2^(e - 7 nslice); a product keeps the slice pairs with

@@ -395,6 +395,47 @@ std::vector<BatchedPiece> plan_batched(Plan& pl, const df_problem* probs, int n)
   return v;
 }
 
+// Workspace of one problem of df_batched_step_split (problems run one after another and share
+// one region, sized for the largest).
+struct SplitPiece {
+  size_t cc, xo, xa, v, jp, dfull, dw, vpart, kpart, buv, bpu;
+  SplitBuf cs, xos, xas, cas, cps, buvs, bpus;
+  int64_t xplane;   // bytes of the planes of one density's X_occ
+  int vsplit, nsk;
+};
+SplitPiece plan_split_piece(Plan& pl, const df_problem& q, int nslice) {
+  SplitPiece b{};
+  const int64_t ncol = batched_ncol(q), no = q.ndm * q.nocc, npair = q.nao * (q.nao + 1) / 2;
+  const bool need_x = ncol > 0 && (q.J || q.K || q.eri || q.papa);
+  const bool dj = q.J && q.nocc > 0, dk = q.K && q.nocc > 0;
+  const bool de = q.eri && q.nac > 0, dp = q.papa && q.nac > 0 && q.np > 0;
+  b.cc = pl.take(need_x ? q.nao * ncol : 0);
+  b.cs = take_split(pl, need_x ? ncol : 0, q.nao, nslice);
+  b.xo = pl.take(need_x ? q.naux * q.nao * no : 0);          // P-major [naux][nao][ndm*nocc]
+  b.xa = pl.take(need_x ? q.naux * q.nao * q.nac : 0);      // AO-major [nao][naux][nac]
+  b.v = pl.take(dj ? q.ndm * q.naux : 0);
+  b.jp = pl.take(dj && batched_j_gemm(q) ? q.ndm * npair : 0);
+  b.dfull = pl.take(batched_jvec_from_b(q) ? q.ndm * q.nao * q.nao : 0);
+  b.dw = pl.take(batched_jvec_from_b(q) ? q.ndm * npair : 0);
+  b.vsplit = batched_jvec_from_b(q) ? dfk::gemm_splits(q.ndm, q.naux, (npair + 15) / 16) : 1;
+  b.vpart = pl.take(b.vsplit > 1 ? (int64_t)b.vsplit * q.ndm * q.naux : 0);
+  b.xplane = dk ? dfk::split_plane_bytes(q.nao, q.naux * q.nocc, nslice) : 0;
+  b.xos.planes = pl.take((q.ndm * b.xplane + 7) / 8);
+  b.xos.ex = pl.take(dk ? (q.ndm * q.nao * 4 + 7) / 8 : 0);
+  b.nsk = dk ? slice_splits(dfk::slice_gemm_tiles(q.nao, q.nao, true) * q.ndm,
+                            dfk::slice_gemm_steps(dfk::kpad64(q.naux * q.nocc)))
+             : 1;
+  b.kpart = pl.take(dk ? (int64_t)b.nsk * q.ndm * q.nao * q.nao : 0);
+  b.xas = take_split(pl, de || dp ? q.naux * q.nac : 0, q.nao, nslice);
+  b.cas = take_split(pl, de ? q.nac : 0, q.nao, nslice);
+  b.buv = pl.take(de ? q.naux * q.nac * q.nac : 0);
+  b.buvs = take_split(pl, de ? q.nac * q.nac : 0, q.naux, nslice);
+  b.cps = take_split(pl, dp ? q.np : 0, q.nao, nslice);
+  b.bpu = pl.take(dp ? q.naux * q.np * q.nac : 0);
+  b.bpus = take_split(pl, dp ? q.np * q.nac : 0, q.naux, nslice);
+  return b;
+}
+
 df_status check_ctx(df_ctx* c) {
   if (!c) return DF_ERR_ARG;
   c->err.clear();
@@ -1447,6 +1488,36 @@ df_status df_batched_workspace_size(const df_problem* probs, int nprob, size_t* 
   return DF_OK;
 }
 
+// J (FP64) of problem q from its J-vectors: V B^T over the packed pairs for many densities, else
+// the Coulomb kernel.  v comes from X_occ (Xo) or, when that is the larger read, from packed B.
+static df_status batched_coulomb(df_ctx* c, const df_problem& q, const double* Xo, double* v, double* jp,
+                                 double* dfull, double* dw, int vsplit, double* vpart) {
+  const int64_t npair = q.nao * (q.nao + 1) / 2;
+  if (batched_jvec_from_b(q)) {
+    DF_LAUNCH(DF_KERNEL_JVEC, dfk::launch_dens_pairs(q.Cocc, q.nao, q.nocc, q.ndm, dfull, dw, c->stream),
+              "density launch");
+    const dfk::OpMap A = dfk::op_map(dw, q.ndm, npair, npair, 1);
+    const dfk::OpMap Bm = dfk::op_map(q.B, q.naux, npair, npair, 1);
+    DF_LAUNCH(DF_KERNEL_JVEC,
+              dfk::launch_gemm_split(A, Bm, dfk::out_plain(v, q.ndm, q.naux, q.naux), vsplit, vpart, c->stream),
+              "J-vector product launch");
+  } else {
+    DF_LAUNCH(DF_KERNEL_JVEC,
+              dfk::launch_jvec(Xo, q.naux, q.nao, q.ndm * q.nocc, q.Cocc, nullptr, q.nocc, q.ndm, v, c->stream),
+              "J-vector launch");
+  }
+  if (batched_j_gemm(q)) {
+    const dfk::OpMap A = dfk::op_map(v, q.ndm, q.naux, q.naux, 1);
+    const dfk::OpMap Bm = dfk::op_map(q.B, npair, 1, q.naux, npair);
+    DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_gemm(A, Bm, dfk::out_plain(jp, q.ndm, npair, npair), 1, c->stream),
+              "Coulomb product launch");
+    DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_unpack_sym(jp, q.ndm, q.nao, q.J, c->stream), "unpack launch");
+  } else {
+    DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_coulomb(q.B, q.naux, q.nao, v, q.ndm, q.J, c->stream), "Coulomb launch");
+  }
+  return DF_OK;
+}
+
 df_status df_batched_step(df_ctx* ctx, const df_problem* probs, int nprob, int flags) {
   df_ctx* c = ctx;
   if (check_ctx(c)) return DF_ERR_ARG;
@@ -1618,39 +1689,10 @@ df_status df_batched_step(df_ctx* ctx, const df_problem* probs, int nprob, int f
     if (ncol == 0 || !(q.J || q.K || q.eri || q.papa)) continue;
     const double* Xo = (const double*)(ws + b.xo);
     const double* Xa = (const double*)(ws + b.xa);
-    const int64_t no = q.ndm * q.nocc;
-    if (q.J && q.nocc > 0) {
-      double* v = (double*)(ws + b.v);
-      if (batched_jvec_from_b(q)) {
-        // v[z][P] = sum_pair Dw[z][pair] b^P[pair]
-        const int64_t npair = q.nao * (q.nao + 1) / 2;
-        double* dw = (double*)(ws + b.dw);
-        DF_LAUNCH(DF_KERNEL_JVEC,
-                  dfk::launch_dens_pairs(q.Cocc, q.nao, q.nocc, q.ndm, (double*)(ws + b.dfull), dw, c->stream),
-                  "density launch");
-        const dfk::OpMap A = dfk::op_map(dw, q.ndm, npair, npair, 1);
-        const dfk::OpMap Bm = dfk::op_map(q.B, q.naux, npair, npair, 1);
-        DF_LAUNCH(DF_KERNEL_JVEC,
-                  dfk::launch_gemm_split(A, Bm, dfk::out_plain(v, q.ndm, q.naux, q.naux), b.vsplit,
-                                         (double*)(ws + b.vpart), c->stream),
-                  "J-vector product launch");
-      } else {
-        DF_LAUNCH(DF_KERNEL_JVEC,
-                  dfk::launch_jvec(Xo, q.naux, q.nao, no, q.Cocc, nullptr, q.nocc, q.ndm, v, c->stream),
-                  "J-vector launch");
-      }
-      if (batched_j_gemm(q)) {
-        const int64_t npair = q.nao * (q.nao + 1) / 2;
-        double* jp = (double*)(ws + b.jp);
-        const dfk::OpMap A = dfk::op_map(v, q.ndm, q.naux, q.naux, 1);
-        const dfk::OpMap Bm = dfk::op_map(q.B, npair, 1, q.naux, npair);
-        DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_gemm(A, Bm, dfk::out_plain(jp, q.ndm, npair, npair), 1, c->stream),
-                  "Coulomb product launch");
-        DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_unpack_sym(jp, q.ndm, q.nao, q.J, c->stream), "unpack launch");
-      } else {
-        DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_coulomb(q.B, q.naux, q.nao, v, q.ndm, q.J, c->stream), "Coulomb launch");
-      }
-    }
+    if (q.J && q.nocc > 0)
+      if (df_status s = batched_coulomb(c, q, Xo, (double*)(ws + b.v), (double*)(ws + b.jp), (double*)(ws + b.dfull),
+                                        (double*)(ws + b.dw), b.vsplit, (double*)(ws + b.vpart)))
+        return s;
     if (q.eri && q.nac > 0) {
       double* buv = (double*)(ws + b.buv);
       if (df_status s = run_mo(c, q.Cact, q.nac, Xa, q.naux, q.nao, q.nac, buv)) return s;
@@ -1662,6 +1704,177 @@ df_status df_batched_step(df_ctx* ctx, const df_problem* probs, int nprob, int f
       if (df_status s = run_pgemm(c, DF_KERNEL_PAPA, bpu, q.np * q.nac, bpu, q.np * q.nac, q.naux, q.papa)) return s;
     }
   }
+  return DF_OK;
+}
+
+// One problem of df_batched_step_split, its workspace at ws.
+static df_status split_problem_run(df_ctx* c, char* ws, const df_problem& q, const int8_t* Bs, const int* Be,
+                                   int nslice) {
+  Plan pl;
+  const SplitPiece b = plan_split_piece(pl, q, nslice);
+  const int64_t ncol = batched_ncol(q), no = q.ndm * q.nocc, nao = q.nao, naux = q.naux, nac = q.nac;
+  if (q.nocc == 0) {
+    if (q.J) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(q.J, q.ndm * nao * nao, c->stream), "fill");
+    if (q.K) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(q.K, q.ndm * nao * nao, c->stream), "fill");
+  }
+  if (ncol == 0 || !(q.J || q.K || q.eri || q.papa)) return DF_OK;
+  auto planes = [&](const SplitBuf& sb) { return (int8_t*)(ws + sb.planes); };
+  auto exps = [&](const SplitBuf& sb) { return (int*)(ws + sb.ex); };
+  const int64_t kpo = dfk::kpad64(nao);
+  // half transform against the split b^P: [Cact | C_1 .. C_ndm] -> X_act AO-major, X_occ P-major
+  double* cc = (double*)(ws + b.cc);
+  std::vector<ColBlock> blks = {{q.Cact, nac, nac, 0}};
+  for (int64_t z = 0; z < q.ndm; ++z) blks.push_back({q.Cocc + z * nao * q.nocc, q.nocc, q.nocc, nac + z * q.nocc});
+  if (df_status s = pad_operand_plain(c, cc, nao, ncol, blks.data(), (int)blks.size())) return s;
+  DF_LAUNCH(DF_KERNEL_SPLIT,
+            dfk::launch_split_rows(dfk::op_map(cc, ncol, 1, nao, ncol), nao, nslice, planes(b.cs), exps(b.cs), c->stream),
+            "split launch");
+  double* Xo = (double*)(ws + b.xo);
+  double* Xa = (double*)(ws + b.xa);
+  dfk::OutMap OX = dfk::out_plain(Xa, naux * nao, ncol, naux * nac);
+  OX.ml = nao;
+  OX.s_mh = nac;
+  OX.nsplit = nac;
+  OX.p2 = Xo;
+  OX.s2_m = no;
+  DF_LAUNCH(DF_KERNEL_HALF_TRANSFORM,
+            dfk::launch_slice_gemm(Bs, Be, naux * nao, planes(b.cs), exps(b.cs), ncol, kpo, nslice, OX, false, 1,
+                                   nullptr, c->stream),
+            "slice product launch");
+  if (q.J && q.nocc > 0)
+    if (df_status s = batched_coulomb(c, q, Xo, (double*)(ws + b.v), (double*)(ws + b.jp), (double*)(ws + b.dfull),
+                                      (double*)(ws + b.dw), b.vsplit, (double*)(ws + b.vpart)))
+      return s;
+  if (q.K && q.nocc > 0) {
+    // rows m of each density's X_occ over (P, i), then K_z = sum_{P, i} X[P][m][z i] X[P][n][z i]
+    // for all densities in one batched launch, lower tiles, reduced and mirrored
+    int8_t* xs = planes(b.xos);
+    int* xe = exps(b.xos);
+    for (int64_t z = 0; z < q.ndm; ++z) {
+      dfk::OpMap ox = dfk::op_map(Xo + z * q.nocc, nao, no, q.nocc, 1);
+      ox.kb_n = naux;
+      ox.s_kb = nao * no;
+      DF_LAUNCH(DF_KERNEL_SPLIT,
+                dfk::launch_split_rows(ox, naux * q.nocc, nslice, xs + z * b.xplane, xe + z * nao, c->stream),
+                "split launch");
+    }
+    double* kpart = (double*)(ws + b.kpart);
+    const dfk::SliceBatch zs{b.xplane, nao, b.xplane, nao};
+    DF_LAUNCH(DF_KERNEL_K_SYRK,
+              dfk::launch_slice_gemm_batched(xs, xe, nao, xs, xe, nao, dfk::kpad64(naux * q.nocc), nslice,
+                                             dfk::out_plain(kpart, nao, nao, nao), true, b.nsk, kpart, q.ndm, zs,
+                                             c->stream),
+              "slice product launch");
+    DF_LAUNCH(DF_KERNEL_K_REDUCE, dfk::launch_syrk_reduce(kpart, b.nsk, nao, q.ndm, q.K, c->stream),
+              "K reduce launch");
+  }
+  const bool de = q.eri && nac > 0, dp = q.papa && nac > 0 && q.np > 0;
+  if (de || dp) {
+    // rows (P, u) of X_act over m; b^P_{lu} = sum_m Cl[m][l] X[m][P][u] for l in Cact, Cp
+    const dfk::OpMap oxa = dfk::op_map(Xa, naux * nac, 1, nao, naux * nac);
+    DF_LAUNCH(DF_KERNEL_SPLIT, dfk::launch_split_rows(oxa, nao, nslice, planes(b.xas), exps(b.xas), c->stream),
+              "split launch");
+    auto second = [&](const double* Cl, int64_t nl, const SplitBuf& sb, double* out) -> df_status {
+      DF_LAUNCH(DF_KERNEL_SPLIT,
+                dfk::launch_split_rows(dfk::op_map(Cl, nl, 1, nao, nl), nao, nslice, planes(sb), exps(sb), c->stream),
+                "split launch");
+      dfk::OutMap O = dfk::out_plain(out, nl, naux * nac, nac);
+      O.nl = nac;
+      O.s_nh = nl * nac;
+      DF_LAUNCH(DF_KERNEL_MO_TRANSFORM,
+                dfk::launch_slice_gemm(planes(sb), exps(sb), nl, planes(b.xas), exps(b.xas), naux * nac, kpo, nslice,
+                                       O, false, 1, nullptr, c->stream),
+                "slice product launch");
+      return DF_OK;
+    };
+    // sum over P of products of rows (l, u) of b^P_lu, split along P
+    auto pproduct = [&](int kind, double* bl, int64_t rows, const SplitBuf& sb, double* out) -> df_status {
+      DF_LAUNCH(DF_KERNEL_SPLIT,
+                dfk::launch_split_rows(dfk::op_map(bl, rows, 1, naux, rows), naux, nslice, planes(sb), exps(sb),
+                                       c->stream),
+                "split launch");
+      DF_LAUNCH(kind,
+                dfk::launch_slice_gemm(planes(sb), exps(sb), rows, planes(sb), exps(sb), rows, dfk::kpad64(naux), nslice,
+                                       dfk::out_plain(out, rows, rows, rows), false, 1, nullptr, c->stream),
+                "slice product launch");
+      return DF_OK;
+    };
+    if (de) {
+      double* buv = (double*)(ws + b.buv);
+      if (df_status s = second(q.Cact, nac, b.cas, buv)) return s;
+      if (df_status s = pproduct(DF_KERNEL_ERI, buv, nac * nac, b.buvs, q.eri)) return s;
+    }
+    if (dp) {
+      double* bpu = (double*)(ws + b.bpu);
+      if (df_status s = second(q.Cp, q.np, b.cps, bpu)) return s;
+      if (df_status s = pproduct(DF_KERNEL_PAPA, bpu, q.np * nac, b.bpus, q.papa)) return s;
+    }
+  }
+  return DF_OK;
+}
+
+df_status df_batched_split_workspace_size(const df_problem* probs, int nprob, int nslice, size_t* bytes) {
+  if (!bytes || nprob < 0 || (nprob > 0 && !probs)) return DF_ERR_ARG;
+  *bytes = 0;
+  if (nslice < 4 || nslice > 8) return DF_ERR_SHAPE;
+  for (int i = 0; i < nprob; ++i) {
+    const df_problem& q = probs[i];
+    if (q.naux < 1 || q.nao < 1 || q.nao > kMaxNao || q.ndm < 1 || q.ndm > 65535 || q.nocc < 0 || q.nac < 0 ||
+        q.np < 0)
+      return DF_ERR_SHAPE;
+    Plan pl;
+    plan_split_piece(pl, q, nslice);
+    *bytes = std::max(*bytes, pl.total);
+  }
+  return DF_OK;
+}
+
+df_status df_batched_step_split(df_ctx* ctx, const df_problem* probs, const int8_t* const* Bs, const int* const* Be,
+                                int nprob, int nslice, int flags) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_batched_step_split takes no flags");
+  if (nslice < 4 || nslice > 8) return fail(c, DF_ERR_SHAPE, "nslice must be in [4, 8]");
+  if (nprob < 0 || (nprob > 0 && (!probs || !Bs || !Be))) return fail(c, DF_ERR_ARG, "probs, Bs or Be is NULL");
+  std::vector<Range> rs;
+  size_t need = 0;
+  for (int i = 0; i < nprob; ++i) {
+    const df_problem& q = probs[i];
+    const std::string tag = "problem " + std::to_string(i) + " ";
+    if (df_status s = check_core(c, q.B, q.naux, q.nao)) return s;
+    if (q.ndm < 1 || q.ndm > 65535 || q.nocc < 0 || q.nac < 0 || q.np < 0)
+      return fail(c, DF_ERR_SHAPE, tag + "has a bad size");
+    if (dfk::rpad32(q.naux * q.nao) > 0x7fffffffLL || dfk::rpad32(q.naux * q.nac) > 0x7fffffffLL ||
+        dfk::rpad32(q.np * q.nac) > 0x7fffffffLL || q.naux * q.nocc > (1LL << 30))
+      return fail(c, DF_ERR_SHAPE, tag + "is too large for the split path");
+    if (q.nocc > 0 && (q.J || q.K) && !q.Cocc) return fail(c, DF_ERR_ARG, tag + "Cocc is NULL");
+    if (q.nac > 0 && (q.eri || q.papa) && !q.Cact) return fail(c, DF_ERR_ARG, tag + "Cact is NULL");
+    if (q.np > 0 && q.papa && !q.Cp) return fail(c, DF_ERR_ARG, tag + "Cp is NULL");
+    if (!Bs[i] || !Be[i]) return fail(c, DF_ERR_ARG, tag + "Bs or Be is NULL");
+    if ((uintptr_t)Bs[i] % 16 != 0) return fail(c, DF_ERR_ARG, tag + "Bs must be 16-byte aligned");
+    const int64_t npair = q.nao * (q.nao + 1) / 2;
+    rs.push_back({q.B, dbytes(q.naux * npair), "B", false});
+    rs.push_back({Bs[i], (size_t)dfk::split_plane_bytes(q.naux * q.nao, q.nao, nslice), "Bs", false});
+    rs.push_back({Be[i], (size_t)q.naux * q.nao * 4, "Be", false});
+    rs.push_back({q.Cocc, dbytes(q.ndm * q.nao * q.nocc), "Cocc", false});
+    rs.push_back({q.Cact, dbytes(q.nao * q.nac), "Cact", false});
+    rs.push_back({q.Cp, dbytes(q.nao * q.np), "Cp", false});
+    rs.push_back({q.J, dbytes(q.ndm * q.nao * q.nao), "J", true});
+    rs.push_back({q.K, dbytes(q.ndm * q.nao * q.nao), "K", true});
+    rs.push_back({q.eri, dbytes(q.nac * q.nac * q.nac * q.nac), "eri", true});
+    rs.push_back({q.papa, dbytes(q.np * q.nac * q.np * q.nac), "papa", true});
+    Plan pl;
+    plan_split_piece(pl, q, nslice);
+    need = std::max(need, pl.total);
+  }
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (df_status s = need_ws(c, need)) return s;
+  if (need) rs.push_back({c->ws, need, "workspace", true});
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (nprob == 0) return DF_OK;
+  if (df_status s = enter(c)) return s;
+  for (int i = 0; i < nprob; ++i)
+    if (df_status s = split_problem_run(c, c->ws, probs[i], Bs[i], Be[i], nslice)) return s;
   return DF_OK;
 }
 

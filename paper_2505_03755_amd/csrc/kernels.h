@@ -170,6 +170,15 @@ hipError_t launch_split_packed_t(const double* B, int64_t naux, int64_t nao, int
 hipError_t launch_slice_gemm(const int8_t* A, const int* ea, int64_t M, const int8_t* B, const int* eb, int64_t N,
                              int64_t kp, int nslice, const OutMap& O, bool tri, int nsplit, double* part,
                              hipStream_t s);
+// A batch of nz slice products of equal shape: product z reads A + z a, ea + z ea, B + z b,
+// eb + z eb (bytes of planes, entries of exponents) and writes O at z O.s_z (z O.s2_z for the
+// columns past O.nsplit) or partials part[split][z][M][N].
+struct SliceBatch {
+  int64_t a, ea, b, eb;
+};
+hipError_t launch_slice_gemm_batched(const int8_t* A, const int* ea, int64_t M, const int8_t* B, const int* eb,
+                                     int64_t N, int64_t kp, int nslice, const OutMap& O, bool tri, int nsplit,
+                                     double* part, int64_t nz, const SliceBatch& zs, hipStream_t s);
 // Workgroup tiles of a slice product that do work, 32-deep steps of a contraction of kp, and
 // the longest split in steps.
 int64_t slice_gemm_tiles(int64_t M, int64_t N, bool tri);

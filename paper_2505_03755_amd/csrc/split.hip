@@ -337,9 +337,15 @@ __global__ void __launch_bounds__(512, 1) slice_gemm_kernel(const int8_t* __rest
                                                             int64_t M, const int8_t* __restrict__ Bp,
                                                             const int* __restrict__ eb, int64_t N, int64_t KB,
                                                             OutMap O, int64_t tilesM, int64_t tilesN, int tri,
-                                                            double* part) {
+                                                            double* part, SliceBatch zs) {
   typedef SliceTile<S> T;
   __shared__ __attribute__((aligned(1024))) int8_t lds[kStages * T::STAGE];
+  // product z of a batch (grid z): its operands and outputs at the batch strides
+  const int64_t z = blockIdx.z, nz = gridDim.z;
+  Ap += z * zs.a;
+  ea += z * zs.ea;
+  Bp += z * zs.b;
+  eb += z * zs.eb;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave & 3, wn = wave >> 2;
@@ -432,14 +438,14 @@ __global__ void __launch_bounds__(512, 1) slice_gemm_kernel(const int8_t* __rest
     for (int d = S - 1; d >= 0; --d) F += ldexp((double)acc[d][e], -kSplitBits * d);
     const double val = ldexp(F, ea[m] + ebn - 2 * kSplitBits0);
     if (part) {
-      part[((int64_t)split * M + m) * N + n] = val;
+      part[(((int64_t)split * nz + z) * M + m) * N + n] = val;
     } else {
       double* dst;
       if (n < O.nsplit) {
         const int64_t nh = O.s_nh ? n / O.nl : 0, mh = O.s_mh ? m / O.ml : 0;
-        dst = O.p + (mh * O.s_mh + (m - mh * O.ml) * O.s_ml) + (nh * O.s_nh + (n - nh * O.nl) * O.s_nl);
+        dst = O.p + z * O.s_z + (mh * O.s_mh + (m - mh * O.ml) * O.s_ml) + (nh * O.s_nh + (n - nh * O.nl) * O.s_nl);
       } else {
-        dst = O.p2 + m * O.s2_m + (n - O.nsplit);
+        dst = O.p2 + z * O.s2_z + m * O.s2_m + (n - O.nsplit);
       }
       if (GEN) *dst = O.accumulate ? *dst + O.alpha * val : O.alpha * val;
       else *dst = val;
@@ -566,29 +572,37 @@ int64_t slice_gemm_max_steps() { return kMaxSteps; }
 
 template <int S>
 static void slice_gemm_s(const int8_t* A, const int* ea, int64_t M, const int8_t* B, const int* eb, int64_t N,
-                         int64_t kp, const OutMap& O, bool tri, int nsplit, double* part, hipStream_t s) {
+                         int64_t kp, const OutMap& O, bool tri, int nsplit, double* part, int64_t nz,
+                         const SliceBatch& zs, hipStream_t s) {
   const int64_t tm = slice_tiles_m(M), tn = slice_tiles_n(N);
-  const dim3 grid((unsigned)(tm * tn), (unsigned)nsplit, 1);
+  const dim3 grid((unsigned)(tm * tn), (unsigned)nsplit, (unsigned)nz);
   const bool gen = !part && (O.alpha != 1.0 || O.accumulate);
-  if (gen) slice_gemm_kernel<S, true><<<grid, 512, 0, s>>>(A, ea, M, B, eb, N, kp / kKS, O, tm, tn, tri, part);
-  else slice_gemm_kernel<S, false><<<grid, 512, 0, s>>>(A, ea, M, B, eb, N, kp / kKS, O, tm, tn, tri, part);
+  if (gen) slice_gemm_kernel<S, true><<<grid, 512, 0, s>>>(A, ea, M, B, eb, N, kp / kKS, O, tm, tn, tri, part, zs);
+  else slice_gemm_kernel<S, false><<<grid, 512, 0, s>>>(A, ea, M, B, eb, N, kp / kKS, O, tm, tn, tri, part, zs);
 }
 
 hipError_t launch_slice_gemm(const int8_t* A, const int* ea, int64_t M, const int8_t* B, const int* eb, int64_t N,
                              int64_t kp, int nslice, const OutMap& O, bool tri, int nsplit, double* part,
                              hipStream_t s) {
-  if (M <= 0 || N <= 0) return hipSuccess;
-  if (kp % 64 != 0 || kp <= 0 || nsplit < 1 || nsplit > 65535 || (tri && M != N) || (nsplit > 1 && !part))
+  return launch_slice_gemm_batched(A, ea, M, B, eb, N, kp, nslice, O, tri, nsplit, part, 1, SliceBatch{}, s);
+}
+
+hipError_t launch_slice_gemm_batched(const int8_t* A, const int* ea, int64_t M, const int8_t* B, const int* eb,
+                                     int64_t N, int64_t kp, int nslice, const OutMap& O, bool tri, int nsplit,
+                                     double* part, int64_t nz, const SliceBatch& zs, hipStream_t s) {
+  if (M <= 0 || N <= 0 || nz == 0) return hipSuccess;
+  if (kp % 64 != 0 || kp <= 0 || nsplit < 1 || nsplit > 65535 || (tri && M != N) || (nsplit > 1 && !part) ||
+      nz < 0 || nz > 65535)
     return hipErrorInvalidValue;
   // every split at most kMaxSteps steps long: the int32 diagonal sums stay exact
   if ((kp / kKS + nsplit - 1) / nsplit > kMaxSteps) return hipErrorInvalidValue;
   if (slice_tiles_m(M) * slice_tiles_n(N) > 0x7fffffffLL) return hipErrorInvalidValue;
   switch (nslice) {
-    case 4: slice_gemm_s<4>(A, ea, M, B, eb, N, kp, O, tri, nsplit, part, s); break;
-    case 5: slice_gemm_s<5>(A, ea, M, B, eb, N, kp, O, tri, nsplit, part, s); break;
-    case 6: slice_gemm_s<6>(A, ea, M, B, eb, N, kp, O, tri, nsplit, part, s); break;
-    case 7: slice_gemm_s<7>(A, ea, M, B, eb, N, kp, O, tri, nsplit, part, s); break;
-    case 8: slice_gemm_s<8>(A, ea, M, B, eb, N, kp, O, tri, nsplit, part, s); break;
+    case 4: slice_gemm_s<4>(A, ea, M, B, eb, N, kp, O, tri, nsplit, part, nz, zs, s); break;
+    case 5: slice_gemm_s<5>(A, ea, M, B, eb, N, kp, O, tri, nsplit, part, nz, zs, s); break;
+    case 6: slice_gemm_s<6>(A, ea, M, B, eb, N, kp, O, tri, nsplit, part, nz, zs, s); break;
+    case 7: slice_gemm_s<7>(A, ea, M, B, eb, N, kp, O, tri, nsplit, part, nz, zs, s); break;
+    case 8: slice_gemm_s<8>(A, ea, M, B, eb, N, kp, O, tri, nsplit, part, nz, zs, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -46,7 +46,7 @@ EXPORTED = ["df_create", "df_destroy", "df_last_error", "df_set_stream", "df_set
             "df_active_eri", "df_papa", "df_step", "df_step_backward", "df_split_matmul",
             "df_split_cholesky", "df_step_split", "df_batched_workspace_size", "df_batched_step",
             "df_set_autotune", "df_batched_tuning", "df_batched_set_tuning", "df_split_cholesky_t",
-            "df_step_backward_split"]
+            "df_step_backward_split", "df_batched_split_workspace_size", "df_batched_step_split"]
 
 
 class DFError(RuntimeError):
@@ -101,6 +101,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         pi = ctypes.POINTER(ctypes.c_int)
         L.df_batched_tuning.argtypes = [vp, vp, i32, pi, pi, pi, pi]
         L.df_batched_set_tuning.argtypes = [vp, vp, i32, i32, i32, i32]
+        L.df_batched_split_workspace_size.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
+        L.df_batched_step_split.argtypes = [vp, vp, vp, vp, i32, i32, i32]
         L.df_split_matmul.argtypes = [vp, dp, i64, i64, dp, i64, i64, i64, i32, dp, i64, i32]
         L.df_split_cholesky.argtypes = [vp, dp, i64, i64, i32, vp, vp, i32]
         L.df_step_split.argtypes = [vp, dp, vp, vp, i32, i64, i64, dp, i64, dp, i64, dp, i64,
@@ -417,6 +419,51 @@ def batched_step(problems, ctx: Context | None = None):
     if ctx._ws is not None:
         ctx.check(L.df_set_workspace(ctx._h, ctypes.c_void_p(ctx._ws.data_ptr()), ctx._ws.numel()))
     ctx.check(L.df_batched_step(ctx.handle, arr, len(problems), 0))
+    return outs
+
+
+def batched_step_split(problems, nslice: int = 7, ctx: Context | None = None):
+    """df_batched_step_split: as batched_step, in split precision; each problem dict also carries
+    "Bs", "Be" from split_cholesky(B, nao, nslice)."""
+    import torch
+    if not problems:
+        return []
+    dev = problems[0]["B"].device
+    ctx = ctx or context(dev)
+    arr = (Problem * len(problems))()
+    bs = (ctypes.c_void_p * len(problems))()
+    be = (ctypes.c_void_p * len(problems))()
+    outs = []
+    for i, pr in enumerate(problems):
+        B, nao, Co, Ca, Cp = pr["B"], pr["nao"], pr["Cocc"], pr["Cact"], pr["Cp"]
+        for n, t in (("B", B), ("Cocc", Co), ("Cact", Ca), ("Cp", Cp)):
+            _check_tensor(n, t, ctx.device)
+        naux = _naux_of(B, nao)
+        Bs, Be = pr["Bs"], pr["Be"]
+        if (Bs.dtype != torch.int8 or Be.dtype != torch.int32
+                or tuple(Bs.shape) != split_plane_shape(naux * nao, nao, nslice) or tuple(Be.shape) != (naux * nao,)
+                or not Bs.is_contiguous() or not Be.is_contiguous()):
+            raise ValueError(f"problem {i}: Bs, Be must come from split_cholesky(B, nao, {nslice})")
+        ndm, nocc = Co.shape[0], Co.shape[2]
+        nac, np_ = Ca.shape[1], Cp.shape[1]
+        o = {"J": torch.empty((ndm, nao, nao), dtype=torch.float64, device=dev),
+             "K": torch.empty((ndm, nao, nao), dtype=torch.float64, device=dev),
+             "eri": torch.empty((nac,) * 4, dtype=torch.float64, device=dev),
+             "papa": torch.empty((np_, nac, np_, nac), dtype=torch.float64, device=dev)}
+        outs.append(o)
+        arr[i] = Problem(_ptr(B), naux, nao, ndm, _ptr(Co), nocc, _ptr(Ca), nac, _ptr(Cp), np_,
+                         _ptr(o["J"]), _ptr(o["K"]), _ptr(o["eri"]), _ptr(o["papa"]))
+        bs[i], be[i] = Bs.data_ptr(), Be.data_ptr()
+    L = ctx._lib
+    need = ctypes.c_size_t(0)
+    ctx.check(L.df_batched_split_workspace_size(arr, len(problems), nslice, ctypes.byref(need)))
+    ctx.bind_stream()
+    if need.value and (ctx._ws is None or ctx._ws.numel() < need.value):
+        ctx._ws = None
+        ctx._ws = torch.empty(need.value, dtype=torch.uint8, device=ctx.device)
+    if ctx._ws is not None:
+        ctx.check(L.df_set_workspace(ctx._h, ctypes.c_void_p(ctx._ws.data_ptr()), ctx._ws.numel()))
+    ctx.check(L.df_batched_step_split(ctx.handle, arr, bs, be, len(problems), nslice, 0))
     return outs
 
 

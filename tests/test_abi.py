@@ -292,3 +292,24 @@ def test_batched_tuning_table(L, ctx):
     assert L.df_batched_tuning(ctx, arr, 2, None, refs[1], refs[2], refs[3]) == dfmi.DF_ERR_ARG
     assert L.df_set_autotune(None, 1) == dfmi.DF_ERR_ARG
     assert L.df_set_autotune(ctx, 1) == dfmi.DF_OK and L.df_set_autotune(ctx, 0) == dfmi.DF_OK
+
+
+def test_batched_split_argument_errors(L, ctx):
+    P = dfmi.Problem
+    arr = (P * 2)()
+    arr[0] = P(1 << 30, 10, 7, 2, 2 << 30, 3, 3 << 30, 2, 4 << 30, 7, 5 << 30, 6 << 30, None, None)
+    arr[1] = P(7 << 30, 12, 5, 1, 8 << 30, 2, None, 0, None, 0, 9 << 30, None, None, None)
+    bs = (ctypes.c_void_p * 2)(1 << 34, 2 << 34)
+    be = (ctypes.c_void_p * 2)(3 << 34, 4 << 34)
+    n = ctypes.c_size_t(0)
+    assert L.df_batched_split_workspace_size(arr, 2, 7, ctypes.byref(n)) == dfmi.DF_OK and n.value > 0
+    assert L.df_batched_split_workspace_size(arr, 2, 3, ctypes.byref(n)) == dfmi.DF_ERR_SHAPE
+    assert L.df_batched_step_split(ctx, arr, bs, be, 2, 7, 1) == dfmi.DF_ERR_UNSUPPORTED
+    assert L.df_batched_step_split(ctx, arr, None, be, 2, 7, 0) == dfmi.DF_ERR_ARG
+    assert L.df_batched_step_split(ctx, arr, bs, be, 2, 9, 0) == dfmi.DF_ERR_SHAPE
+    assert L.df_batched_step_split(ctx, arr, bs, be, 2, 7, 0) == dfmi.DF_ERR_WORKSPACE
+    assert L.df_batched_step_split(ctx, arr, bs, be, 0, 7, 0) == dfmi.DF_OK
+    bad = (ctypes.c_void_p * 2)((1 << 34) + 8, 2 << 34)                         # Bs not 16-byte aligned
+    assert L.df_batched_step_split(ctx, arr, bad, be, 2, 7, 0) == dfmi.DF_ERR_ARG
+    bad = (ctypes.c_void_p * 2)(1 << 34, None)
+    assert L.df_batched_step_split(ctx, arr, bad, be, 2, 7, 0) == dfmi.DF_ERR_ARG

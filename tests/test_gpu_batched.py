@@ -182,3 +182,38 @@ def test_batched_autotune_fragment_workload():
         close_to_oracle(o, oracle_outputs(p))
     J, K, _ = O.jk(probs[7]["B"], probs[7]["nao"], probs[7]["Cocc"][2])
     assert rel(first[7]["J"][2], J) <= 1e-10 and rel(first[7]["K"][2], K) <= 1e-10
+
+
+def with_split(dps, S=7):
+    for dp in dps:
+        dp["Bs"], dp["Be"] = dfmi.split_cholesky(dp["B"], dp["nao"], nslice=S)
+    return dps
+
+
+def test_batched_split_ragged_against_oracle():
+    """Split precision (7 slices) against the oracle and against the FP64 batch."""
+    probs = [make(*shape, seed=i + 51) for i, shape in enumerate(RAGGED)]
+    dps = with_split([to_dev(p) for p in probs])
+    outs = dfmi.batched_step_split(dps)
+    ref = dfmi.batched_step(dps)
+    torch.cuda.synchronize()
+    for p, o, r in zip(probs, outs, ref):
+        check_problem(p, o, tol_oracle=1e-11)
+        for k in o:
+            assert rel(o[k], r[k]) <= 1e-11, k
+
+
+def test_batched_split_fragment_workload_reduced_densities():
+    """The eight fragment shapes with 4 densities each: oracle on the smaller ones, a sampled
+    density of the larger ones."""
+    probs = []
+    for f in synth.FRAGMENTS:
+        B, Cd, C = synth.fragment_problem(f, ndm=4)
+        probs.append({"B": B, "nao": f.nemb, "Cocc": Cd, "Cact": C[:, f.nocc:f.nocc + f.nac], "Cp": C})
+    outs = dfmi.batched_step_split(with_split([to_dev(p) for p in probs]))
+    torch.cuda.synchronize()
+    for p, o in zip(probs[:3], outs[:3]):
+        check_problem(p, o, tol_oracle=1e-11)
+    for p, o in zip(probs[6:], outs[6:]):
+        J, K, _ = O.jk(p["B"], p["nao"], p["Cocc"][1])
+        assert rel(o["J"][1], J) <= 1e-11 and rel(o["K"][1], K) <= 1e-11
