@@ -227,7 +227,8 @@ def batched_fragments(ndm, reps, ctx, nslice=7):
     """The eight fragment subproblems with ndm densities each: df_batched_step (grouped launches)
     with its default tiles, autotuned, and the tuned call replayed from a HIP graph, against the
     same work issued problem by problem (df_jk, df_active_eri, df_papa FULL); then the batch in
-    split precision (df_batched_step_split, nslice slices) with its largest difference to FP64."""
+    split precision (df_batched_step_split, nslice slices; K from slices, and K kept in FP64) with
+    its largest difference to FP64."""
     import numpy as np
     import torch
     from paper_2505_03755_amd import dfmi, synth
@@ -285,11 +286,17 @@ def batched_fragments(ndm, reps, ctx, nslice=7):
     ref = dfmi.batched_step(probs, ctx=ctx)
     for p in probs:
         p["Bs"], p["Be"] = dfmi.split_cholesky(p["B"], p["nao"], nslice=nslice, ctx=ctx)
-    ms_s = timed(lambda: dfmi.batched_step_split(probs, nslice=nslice, ctx=ctx))
-    spl = dfmi.batched_step_split(probs, nslice=nslice, ctx=ctx)
-    torch.cuda.synchronize()
-    srel = {k: max(((o[k] - r[k]).norm() / r[k].norm()).item() for o, r in zip(spl, ref)) for k in ("J", "K", "eri", "papa")}
-    del ref, spl
+    split = {"nslice": nslice}
+    for name, kf in (("", False), ("k_fp64_", True)):
+        ms_s = timed(lambda: dfmi.batched_step_split(probs, nslice=nslice, k_fp64=kf, ctx=ctx))
+        spl = dfmi.batched_step_split(probs, nslice=nslice, k_fp64=kf, ctx=ctx)
+        torch.cuda.synchronize()
+        split[name + "ms_batched"] = ms_s
+        split[name + "speedup_vs_fp64"] = ms_b / ms_s
+        split[name + "max_rel_diff_vs_fp64"] = {
+            k: max(((o[k] - r[k]).norm() / r[k].norm()).item() for o, r in zip(spl, ref)) for k in ("J", "K", "eri", "papa")}
+        del spl
+    del ref
     fl = sum(fragment_flops(f, ndm) for f in synth.FRAGMENTS)
     del probs
     torch.cuda.empty_cache()
@@ -299,8 +306,7 @@ def batched_fragments(ndm, reps, ctx, nslice=7):
             "tuning": {k: tuning[k] for k in ("half_tile_n", "k_tile", "k_rounds")}, "tuning_call_s": tune_s,
             "ms_batched_default_tiles": ms_default, "ms_graph_replay": ms_g,
             "ms_unbatched": ms_u, "tflops_unbatched": fl / ms_u / 1e9,
-            "split": {"nslice": nslice, "ms_batched": ms_s, "speedup_vs_fp64": ms_b / ms_s,
-                      "max_rel_diff_vs_fp64": srel}}
+            "split": split}
 
 
 def main():

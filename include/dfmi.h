@@ -92,6 +92,7 @@ typedef enum df_kernel_kind {
 #define DF_BWD_GJ    0x20  /* DF_OP_STEP_BACKWARD(_SPLIT): gJ is given */
 #define DF_BWD_GK    0x40  /* DF_OP_STEP_BACKWARD(_SPLIT): gK is given */
 #define DF_BWD_GERI  0x80  /* DF_OP_STEP_BACKWARD(_SPLIT): geri is given */
+#define DF_SPLIT_K_FP64 0x100  /* df_batched_step_split: K in FP64 from the split-precision X_occ */
 
 /* Problem sizes for df_workspace_size; fields an operation does not use are ignored. */
 typedef struct df_dims {
@@ -289,8 +290,11 @@ df_status df_batched_set_tuning(df_ctx* ctx, const df_problem* probs, int nprob,
  *   - Problems run one after another in the given order and share one workspace region,
  *     df_batched_split_workspace_size(probs, nprob, nslice) bytes (the largest problem's need).
  *   - The K products of all densities of a problem run as one launch.
+ *   - flags = DF_SPLIT_K_FP64 computes K in FP64 from X_occ (the exchange product of
+ *     df_batched_step) instead of splitting every density's X_occ, which for many densities
+ *     costs more than the int8 product saves.  The workspace query takes the same flags.
  */
-df_status df_batched_split_workspace_size(const df_problem* probs, int nprob, int nslice, size_t* bytes);
+df_status df_batched_split_workspace_size(const df_problem* probs, int nprob, int nslice, int flags, size_t* bytes);
 df_status df_batched_step_split(df_ctx* ctx, const df_problem* probs, const int8_t* const* Bs, const int* const* Be,
                                 int nprob, int nslice, int flags);
 

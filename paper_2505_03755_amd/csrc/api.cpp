@@ -403,7 +403,7 @@ struct SplitPiece {
   int64_t xplane;   // bytes of the planes of one density's X_occ
   int vsplit, nsk;
 };
-SplitPiece plan_split_piece(Plan& pl, const df_problem& q, int nslice) {
+SplitPiece plan_split_piece(Plan& pl, const df_problem& q, int nslice, bool k_fp64) {
   SplitPiece b{};
   const int64_t ncol = batched_ncol(q), no = q.ndm * q.nocc, npair = q.nao * (q.nao + 1) / 2;
   const bool need_x = ncol > 0 && (q.J || q.K || q.eri || q.papa);
@@ -419,12 +419,14 @@ SplitPiece plan_split_piece(Plan& pl, const df_problem& q, int nslice) {
   b.dw = pl.take(batched_jvec_from_b(q) ? q.ndm * npair : 0);
   b.vsplit = batched_jvec_from_b(q) ? dfk::gemm_splits(q.ndm, q.naux, (npair + 15) / 16) : 1;
   b.vpart = pl.take(b.vsplit > 1 ? (int64_t)b.vsplit * q.ndm * q.naux : 0);
-  b.xplane = dk ? dfk::split_plane_bytes(q.nao, q.naux * q.nocc, nslice) : 0;
+  const bool dks = dk && !k_fp64;   // K from int8 slices of every density's X_occ
+  b.xplane = dks ? dfk::split_plane_bytes(q.nao, q.naux * q.nocc, nslice) : 0;
   b.xos.planes = pl.take((q.ndm * b.xplane + 7) / 8);
-  b.xos.ex = pl.take(dk ? (q.ndm * q.nao * 4 + 7) / 8 : 0);
-  b.nsk = dk ? slice_splits(dfk::slice_gemm_tiles(q.nao, q.nao, true) * q.ndm,
-                            dfk::slice_gemm_steps(dfk::kpad64(q.naux * q.nocc)))
-             : 1;
+  b.xos.ex = pl.take(dks ? (q.ndm * q.nao * 4 + 7) / 8 : 0);
+  b.nsk = !dk ? 1
+          : dks ? slice_splits(dfk::slice_gemm_tiles(q.nao, q.nao, true) * q.ndm,
+                               dfk::slice_gemm_steps(dfk::kpad64(q.naux * q.nocc)))
+                : dfk::syrk_splits(q.nao, q.naux, q.ndm);
   b.kpart = pl.take(dk ? (int64_t)b.nsk * q.ndm * q.nao * q.nao : 0);
   b.xas = take_split(pl, de || dp ? q.naux * q.nac : 0, q.nao, nslice);
   b.cas = take_split(pl, de ? q.nac : 0, q.nao, nslice);
@@ -1709,9 +1711,9 @@ df_status df_batched_step(df_ctx* ctx, const df_problem* probs, int nprob, int f
 
 // One problem of df_batched_step_split, its workspace at ws.
 static df_status split_problem_run(df_ctx* c, char* ws, const df_problem& q, const int8_t* Bs, const int* Be,
-                                   int nslice) {
+                                   int nslice, bool k_fp64) {
   Plan pl;
-  const SplitPiece b = plan_split_piece(pl, q, nslice);
+  const SplitPiece b = plan_split_piece(pl, q, nslice, k_fp64);
   const int64_t ncol = batched_ncol(q), no = q.ndm * q.nocc, nao = q.nao, naux = q.naux, nac = q.nac;
   if (q.nocc == 0) {
     if (q.J) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(q.J, q.ndm * nao * nao, c->stream), "fill");
@@ -1745,7 +1747,17 @@ static df_status split_problem_run(df_ctx* c, char* ws, const df_problem& q, con
     if (df_status s = batched_coulomb(c, q, Xo, (double*)(ws + b.v), (double*)(ws + b.jp), (double*)(ws + b.dfull),
                                       (double*)(ws + b.dw), b.vsplit, (double*)(ws + b.vpart)))
       return s;
-  if (q.K && q.nocc > 0) {
+  if (q.K && q.nocc > 0 && k_fp64) {
+    // K_z = sum_{P, i} X[P][m][z i] X[P][n][z i] in FP64, lower tiles, reduced and mirrored
+    dfk::OpMap A = dfk::op_map(Xo, nao, no, q.nocc, 1);
+    A.kb_n = naux;
+    A.s_kb = nao * no;
+    A.s_z = q.nocc;
+    double* kpart = (double*)(ws + b.kpart);
+    DF_LAUNCH(DF_KERNEL_K_SYRK, dfk::launch_syrk_partial(A, A, nao, q.ndm, b.nsk, kpart, c->stream), "K tiles launch");
+    DF_LAUNCH(DF_KERNEL_K_REDUCE, dfk::launch_syrk_reduce(kpart, b.nsk, nao, q.ndm, q.K, c->stream),
+              "K reduce launch");
+  } else if (q.K && q.nocc > 0) {
     // rows m of each density's X_occ over (P, i), then K_z = sum_{P, i} X[P][m][z i] X[P][n][z i]
     // for all densities in one batched launch, lower tiles, reduced and mirrored
     int8_t* xs = planes(b.xos);
@@ -1813,9 +1825,10 @@ static df_status split_problem_run(df_ctx* c, char* ws, const df_problem& q, con
   return DF_OK;
 }
 
-df_status df_batched_split_workspace_size(const df_problem* probs, int nprob, int nslice, size_t* bytes) {
+df_status df_batched_split_workspace_size(const df_problem* probs, int nprob, int nslice, int flags, size_t* bytes) {
   if (!bytes || nprob < 0 || (nprob > 0 && !probs)) return DF_ERR_ARG;
   *bytes = 0;
+  if (flags & ~DF_SPLIT_K_FP64) return DF_ERR_UNSUPPORTED;
   if (nslice < 4 || nslice > 8) return DF_ERR_SHAPE;
   for (int i = 0; i < nprob; ++i) {
     const df_problem& q = probs[i];
@@ -1823,7 +1836,7 @@ df_status df_batched_split_workspace_size(const df_problem* probs, int nprob, in
         q.np < 0)
       return DF_ERR_SHAPE;
     Plan pl;
-    plan_split_piece(pl, q, nslice);
+    plan_split_piece(pl, q, nslice, (flags & DF_SPLIT_K_FP64) != 0);
     *bytes = std::max(*bytes, pl.total);
   }
   return DF_OK;
@@ -1833,7 +1846,8 @@ df_status df_batched_step_split(df_ctx* ctx, const df_problem* probs, const int8
                                 int nprob, int nslice, int flags) {
   df_ctx* c = ctx;
   if (check_ctx(c)) return DF_ERR_ARG;
-  if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_batched_step_split takes no flags");
+  if (flags & ~DF_SPLIT_K_FP64) return fail(c, DF_ERR_UNSUPPORTED, "df_batched_step_split: unknown flags");
+  const bool k_fp64 = (flags & DF_SPLIT_K_FP64) != 0;
   if (nslice < 4 || nslice > 8) return fail(c, DF_ERR_SHAPE, "nslice must be in [4, 8]");
   if (nprob < 0 || (nprob > 0 && (!probs || !Bs || !Be))) return fail(c, DF_ERR_ARG, "probs, Bs or Be is NULL");
   std::vector<Range> rs;
@@ -1864,7 +1878,7 @@ df_status df_batched_step_split(df_ctx* ctx, const df_problem* probs, const int8
     rs.push_back({q.eri, dbytes(q.nac * q.nac * q.nac * q.nac), "eri", true});
     rs.push_back({q.papa, dbytes(q.np * q.nac * q.np * q.nac), "papa", true});
     Plan pl;
-    plan_split_piece(pl, q, nslice);
+    plan_split_piece(pl, q, nslice, k_fp64);
     need = std::max(need, pl.total);
   }
   if (!check_overlap(c, rs)) return DF_ERR_ARG;
@@ -1874,7 +1888,7 @@ df_status df_batched_step_split(df_ctx* ctx, const df_problem* probs, const int8
   if (nprob == 0) return DF_OK;
   if (df_status s = enter(c)) return s;
   for (int i = 0; i < nprob; ++i)
-    if (df_status s = split_problem_run(c, c->ws, probs[i], Bs[i], Be[i], nslice)) return s;
+    if (df_status s = split_problem_run(c, c->ws, probs[i], Bs[i], Be[i], nslice, k_fp64)) return s;
   return DF_OK;
 }
 

@@ -37,6 +37,7 @@ DF_CALLER_X = 0x10
 DF_BWD_GJ = 0x20
 DF_BWD_GK = 0x40
 DF_BWD_GERI = 0x80
+DF_SPLIT_K_FP64 = 0x100
 
 KERNEL_KINDS = ["half_transform", "jvec", "coulomb", "k_syrk", "k_reduce", "mo_transform", "papa", "eri",
                 "other", "adjoint", "split"]
@@ -101,7 +102,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         pi = ctypes.POINTER(ctypes.c_int)
         L.df_batched_tuning.argtypes = [vp, vp, i32, pi, pi, pi, pi]
         L.df_batched_set_tuning.argtypes = [vp, vp, i32, i32, i32, i32]
-        L.df_batched_split_workspace_size.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
+        L.df_batched_split_workspace_size.argtypes = [vp, i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
         L.df_batched_step_split.argtypes = [vp, vp, vp, vp, i32, i32, i32]
         L.df_split_matmul.argtypes = [vp, dp, i64, i64, dp, i64, i64, i64, i32, dp, i64, i32]
         L.df_split_cholesky.argtypes = [vp, dp, i64, i64, i32, vp, vp, i32]
@@ -422,9 +423,10 @@ def batched_step(problems, ctx: Context | None = None):
     return outs
 
 
-def batched_step_split(problems, nslice: int = 7, ctx: Context | None = None):
+def batched_step_split(problems, nslice: int = 7, k_fp64: bool = False, ctx: Context | None = None):
     """df_batched_step_split: as batched_step, in split precision; each problem dict also carries
-    "Bs", "Be" from split_cholesky(B, nao, nslice)."""
+    "Bs", "Be" from split_cholesky(B, nao, nslice).  k_fp64 computes K in FP64 from the
+    split-precision X_occ (DF_SPLIT_K_FP64)."""
     import torch
     if not problems:
         return []
@@ -456,14 +458,15 @@ def batched_step_split(problems, nslice: int = 7, ctx: Context | None = None):
         bs[i], be[i] = Bs.data_ptr(), Be.data_ptr()
     L = ctx._lib
     need = ctypes.c_size_t(0)
-    ctx.check(L.df_batched_split_workspace_size(arr, len(problems), nslice, ctypes.byref(need)))
+    flags = DF_SPLIT_K_FP64 if k_fp64 else 0
+    ctx.check(L.df_batched_split_workspace_size(arr, len(problems), nslice, flags, ctypes.byref(need)))
     ctx.bind_stream()
     if need.value and (ctx._ws is None or ctx._ws.numel() < need.value):
         ctx._ws = None
         ctx._ws = torch.empty(need.value, dtype=torch.uint8, device=ctx.device)
     if ctx._ws is not None:
         ctx.check(L.df_set_workspace(ctx._h, ctypes.c_void_p(ctx._ws.data_ptr()), ctx._ws.numel()))
-    ctx.check(L.df_batched_step_split(ctx.handle, arr, bs, be, len(problems), nslice, 0))
+    ctx.check(L.df_batched_step_split(ctx.handle, arr, bs, be, len(problems), nslice, flags))
     return outs
 
 

@@ -302,8 +302,13 @@ def test_batched_split_argument_errors(L, ctx):
     bs = (ctypes.c_void_p * 2)(1 << 34, 2 << 34)
     be = (ctypes.c_void_p * 2)(3 << 34, 4 << 34)
     n = ctypes.c_size_t(0)
-    assert L.df_batched_split_workspace_size(arr, 2, 7, ctypes.byref(n)) == dfmi.DF_OK and n.value > 0
-    assert L.df_batched_split_workspace_size(arr, 2, 3, ctypes.byref(n)) == dfmi.DF_ERR_SHAPE
+    assert L.df_batched_split_workspace_size(arr, 2, 7, 0, ctypes.byref(n)) == dfmi.DF_OK and n.value > 0
+    w_split = n.value
+    assert L.df_batched_split_workspace_size(arr, 2, 3, 0, ctypes.byref(n)) == dfmi.DF_ERR_SHAPE
+    assert L.df_batched_split_workspace_size(arr, 2, 7, 1, ctypes.byref(n)) == dfmi.DF_ERR_UNSUPPORTED
+    m = ctypes.c_size_t(0)
+    assert L.df_batched_split_workspace_size(arr, 2, 7, dfmi.DF_SPLIT_K_FP64, ctypes.byref(m)) == dfmi.DF_OK
+    assert 0 < m.value < w_split                   # no int8 copy of X_occ
     assert L.df_batched_step_split(ctx, arr, bs, be, 2, 7, 1) == dfmi.DF_ERR_UNSUPPORTED
     assert L.df_batched_step_split(ctx, arr, None, be, 2, 7, 0) == dfmi.DF_ERR_ARG
     assert L.df_batched_step_split(ctx, arr, bs, be, 2, 9, 0) == dfmi.DF_ERR_SHAPE

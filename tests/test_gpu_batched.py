@@ -190,11 +190,13 @@ def with_split(dps, S=7):
     return dps
 
 
-def test_batched_split_ragged_against_oracle():
-    """Split precision (7 slices) against the oracle and against the FP64 batch."""
+@pytest.mark.parametrize("k_fp64", [False, True])
+def test_batched_split_ragged_against_oracle(k_fp64):
+    """Split precision (7 slices) against the oracle and against the FP64 batch; K from int8 slices
+    or, with k_fp64, in FP64 from the split-precision X_occ."""
     probs = [make(*shape, seed=i + 51) for i, shape in enumerate(RAGGED)]
     dps = with_split([to_dev(p) for p in probs])
-    outs = dfmi.batched_step_split(dps)
+    outs = dfmi.batched_step_split(dps, k_fp64=k_fp64)
     ref = dfmi.batched_step(dps)
     torch.cuda.synchronize()
     for p, o, r in zip(probs, outs, ref):
