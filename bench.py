@@ -213,6 +213,44 @@ def split_comparison(B, nao, Cocc, Cact, C, nslice, reps, ctx):
             "adjoint_speedup": bms64 / bmss, "gradient_rel_diff": grel}
 
 
+def ppaa_block(B, nao, Cact, C, reps, ctx):
+    """(pq|uv) of Eq. (ppaa) with p, q over all MOs (df_ppaa, through the AO basis), timed alone
+    with HIP events on the library's stream, then once more with per-kernel timing."""
+    import torch
+    from paper_2505_03755_amd import dfmi
+    naux = B.shape[0]
+    nac, nmo = Cact.shape[1], C.shape[1]
+    npair, nuv = nao * (nao + 1) // 2, nac * (nac + 1) // 2
+    stream = torch.cuda.current_stream(B.device)
+    out = dfmi.ppaa(B, nao, C, Cact, ctx=ctx)
+    del out
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(stream)
+    for i in range(reps):
+        out = dfmi.ppaa(B, nao, C, Cact, ctx=ctx)
+        del out
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    ms = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(reps))[reps // 2]
+    ctx.set_timing(True)
+    ctx.timing_read()
+    out = dfmi.ppaa(B, nao, C, Cact, ctx=ctx)
+    kt = ctx.timing_read()
+    ctx.set_timing(False)
+    del out
+    torch.cuda.empty_cache()
+    # the AO route's work: W_uv over the packed pairs, then C^T W_uv C
+    fl_w = 2 * naux * npair * nuv
+    fl_t = 2 * nuv * nao * nmo * (nao + nmo)
+    fl_mo = 2 * naux * nao * nmo * (nao + nmo) + 2 * naux * nmo * nmo * nuv
+    names = {"papa": "w_product", "half_transform": "half_transform", "mo_transform": "second_transform"}
+    return {"shape": f"N_ao={nao}, N_aux={naux}, N_mo={nmo}, N_ac={nac}; out [{nuv}][{nmo}][{nmo}]",
+            "ms": ms, "flops": fl_w + fl_t, "tflops": (fl_w + fl_t) / ms / 1e9,
+            "flops_mo_route": fl_mo,
+            "kernels_ms": {names.get(k, k): v[0] for k, v in kt.items() if v[1] > 0}}
+
+
 def fragment_flops(f, ndm):
     """Algorithmic FLOPs of one fragment subproblem: half transform, J, K, b_pu and the full
     (pu|qv), and (uv|wx)."""
@@ -320,6 +358,7 @@ def main():
     ap.add_argument("--forward-only", action="store_true", help="time df_step alone (no adjoint)")
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched fragment workload")
+    ap.add_argument("--no-ppaa", action="store_true", help="skip the (pq|uv) block")
     ap.add_argument("--fragment-densities", type=int, default=64)
     ap.add_argument("--split-slices", type=int, default=7)
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
@@ -451,6 +490,12 @@ def main():
             out.pop(k, None)
         torch.cuda.empty_cache()
         res["split_precision"] = split_comparison(B, nao, Cocc, Cact, C, args.split_slices, 5, ctx)
+    if not args.no_ppaa:
+        log("[bench] (pq|uv) over all MOs")
+        for k in ("Xocc", "Xact"):
+            out.pop(k, None)
+        torch.cuda.empty_cache()
+        res["ppaa"] = ppaa_block(B, nao, Cact, C, 3, ctx)
     del B
     out.clear()
     torch.cuda.empty_cache()

@@ -11,6 +11,7 @@
  *   df_active_eri       (uv|wx), the active-space ERIs of the recombination step (Eq. flas)
  *   df_papa             (pu|vw), the g^{p a}_{a a} pattern of the orbital gradient (Eq. MO_conv);
  *                       with DF_PAPA_FULL the (pu|qv) block of Eq. (papa)
+ *   df_ppaa             (pq|uv) of Eq. (ppaa), through the AO basis
  *   df_step             all of the above from one shared half transform
  *
  * Conventions shared by every call
@@ -65,7 +66,8 @@ typedef enum df_op {
   DF_OP_STEP_BACKWARD = 6,
   DF_OP_SPLIT_MATMUL = 7,
   DF_OP_STEP_SPLIT = 8,
-  DF_OP_STEP_BACKWARD_SPLIT = 9
+  DF_OP_STEP_BACKWARD_SPLIT = 9,
+  DF_OP_PPAA = 10
 } df_op;
 
 /* Kernel classes reported by df_timing_read. */
@@ -101,7 +103,7 @@ typedef struct df_dims {
   int64_t nocc;   /* columns of each density factor */
   int64_t nac;    /* active orbitals */
   int64_t np;     /* columns of Cp (MO space p) */
-  int64_t nq;     /* columns of Cq (DF_PAPA_FULL only) */
+  int64_t nq;     /* columns of Cq (DF_PAPA_FULL, DF_OP_PPAA) */
   int64_t ncol;   /* columns of C in df_half_transform */
   int64_t n2;     /* columns of C2 in df_half_transform (0 if no second transform) */
   int flags;
@@ -190,6 +192,25 @@ df_status df_active_eri(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
 df_status df_papa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
                   const double* Cp, int64_t np, const double* Cact, int64_t nac,
                   const double* Cq, int64_t nq, double* out, int flags);
+
+/*
+ * ppaa block of Eq. (ppaa):  (pq|uv) = sum_P b^P_pq b^P_uv  with  b^P_pq = (Cp^T b^P Cq)_{pq},
+ * b^P_uv = (Cact^T b^P Cact)_{uv}.
+ *   out[pair(u,v)][p][q] = (pq|uv),  pair(u,v) = u(u+1)/2 + v for u >= v (the (uv) index packed
+ *   like B, since (pq|uv) = (pq|vu));  out is [nac(nac+1)/2][np][nq]
+ *   Cp [nao][np], Cq [nao][nq], Cact [nao][nac] (inputs).  Cq = NULL (with nq = 0) means Cq = Cp.
+ * Evaluated through the AO basis: W_uv = sum_P b^P_uv b^P over the packed pairs (one product with
+ * B per chunk of uv pairs), then out[uv] = Cp^T W_uv Cq, so b^P_pq is never formed.  That costs
+ * 2 N_aux npair N_uv + 2 N_uv N_ao nq (N_ao + np) FLOP against 2 N_aux N_ao nq (N_ao + np) +
+ * 2 N_aux np nq N_uv for the MO route (N_uv = nac(nac+1)/2), far less when N_uv < N_aux.
+ * The uv pairs run in chunks that keep the per-chunk buffers near 2 GiB (B is read once per chunk).
+ * Errors: DF_ERR_ARG for a missing Cp/Cact/out (when the output is not empty), nq != 0 without
+ * Cq, or overlapping buffers; DF_ERR_SHAPE for negative sizes; DF_ERR_UNSUPPORTED for flags != 0.
+ * Workspace: df_workspace_size(DF_OP_PPAA, {naux, nao, nac, np, nq}) (nq = 0: nq = np).
+ */
+df_status df_ppaa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
+                  const double* Cp, int64_t np, const double* Cq, int64_t nq,
+                  const double* Cact, int64_t nac, double* out, int flags);
 
 /*
  * One forward pass of the whole path from a single half transform X = b^P [Cocc | Cact]:

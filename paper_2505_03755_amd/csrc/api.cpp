@@ -144,6 +144,28 @@ PapaPlan plan_papa(Plan& pl, int64_t naux, int64_t nao, int64_t nac, int64_t np,
   return p;
 }
 
+// Workspace of df_ppaa.  The uv pairs run in chunks of `chunk`: W_uv [chunk][npair] and
+// T_uv = W_uv Cq [chunk][nao][nq] are the per-chunk buffers, bounded by kPpaaChunkBytes.
+constexpr int64_t kPpaaChunkBytes = int64_t(2) << 30;
+struct PpaaPlan {
+  size_t cpa, cpq, x, buv, vp, w, t;
+  int64_t chunk;
+};
+PpaaPlan plan_ppaa(Plan& pl, int64_t naux, int64_t nao, int64_t nac, int64_t nq) {
+  PpaaPlan p{};
+  const int64_t npair = nao * (nao + 1) / 2, nuv = nac * (nac + 1) / 2;
+  const int64_t per = (npair + nao * nq) * (int64_t)sizeof(double);
+  p.chunk = std::max<int64_t>(1, std::min<int64_t>(nuv, kPpaaChunkBytes / std::max<int64_t>(per, 1)));
+  p.cpa = pl.take(dfk::kpad16(nao) * nac);
+  p.cpq = pl.take(dfk::kpad16(nao) * nq);
+  p.x = pl.take(naux * nao * nac);
+  p.buv = pl.take(naux * nac * nac);
+  p.vp = pl.take(naux * nuv);
+  p.w = pl.take(p.chunk * npair);
+  p.t = pl.take(p.chunk * nao * nq);
+  return p;
+}
+
 StepPlan plan_step(Plan& pl, int64_t naux, int64_t nao, int64_t nocc, int64_t nac, int64_t np, bool caller_x) {
   StepPlan p{};
   const int64_t ncol = nocc + nac;
@@ -742,6 +764,9 @@ df_status df_workspace_size(df_op op, const df_dims* d, size_t* bytes) {
     case DF_OP_PAPA:
       plan_papa(pl, d->naux, d->nao, d->nac, d->np, d->nq, (d->flags & DF_PAPA_FULL) != 0);
       break;
+    case DF_OP_PPAA:
+      plan_ppaa(pl, d->naux, d->nao, d->nac, d->nq > 0 ? d->nq : d->np);
+      break;
     case DF_OP_STEP:
       plan_step(pl, d->naux, d->nao, d->nocc, d->nac, d->np, (d->flags & DF_CALLER_X) != 0);
       break;
@@ -923,6 +948,72 @@ df_status df_papa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const
   double* bvw = (double*)(c->ws + p.bvw);
   if (df_status s = run_mo(c, Cact, nac, X, naux, nao, nac, bvw)) return s;
   return run_pgemm(c, DF_KERNEL_PAPA, bpu, np * nac, bvw, nac * nac, naux, out);
+}
+
+df_status df_ppaa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const double* Cp, int64_t np,
+                  const double* Cq, int64_t nq, const double* Cact, int64_t nac, double* out, int flags) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (df_status s = check_core(c, B, naux, nao)) return s;
+  if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_ppaa takes no flags");
+  if (np < 0 || nac < 0 || nq < 0) return fail(c, DF_ERR_SHAPE, "sizes must be >= 0");
+  if (!Cq) {
+    if (nq != 0) return fail(c, DF_ERR_ARG, "nq must be 0 when Cq is NULL (Cq = Cp)");
+    Cq = Cp;
+    nq = np;
+  }
+  const int64_t nuv = nac * (nac + 1) / 2, nout = nuv * np * nq;
+  if (nout > 0 && (!Cp || !Cact || !out)) return fail(c, DF_ERR_ARG, "Cp, Cact and out are required");
+  const int64_t npair = nao * (nao + 1) / 2;
+  std::vector<Range> rs = {{B, dbytes(naux * npair), "B", false},
+                           {Cp, dbytes(nao * np), "Cp", false},
+                           {Cq == Cp ? nullptr : Cq, dbytes(nao * nq), "Cq", false},
+                           {Cact, dbytes(nao * nac), "Cact", false},
+                           {out, dbytes(nout), "out", true}};
+  Plan pl;
+  const PpaaPlan p = plan_ppaa(pl, naux, nao, nac, nq);
+  if (nout > 0) {
+    if (!check_overlap(c, rs)) return DF_ERR_ARG;
+    if (df_status s = need_ws(c, pl.total)) return s;
+    rs.push_back({c->ws, pl.total, "workspace", true});
+  }
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (nout == 0) return DF_OK;
+  if (df_status s = enter(c)) return s;
+  char* ws = c->ws;
+  double* X = (double*)(ws + p.x);
+  double* buv = (double*)(ws + p.buv);
+  double* vp = (double*)(ws + p.vp);
+  double* W = (double*)(ws + p.w);
+  double* T = (double*)(ws + p.t);
+  double* cpa = (double*)(ws + p.cpa);
+  double* cpq = (double*)(ws + p.cpq);
+  // b^P_uv for every P, its lower triangle packed: vp [naux][nuv]
+  const ColBlock ba{Cact, nac, nac, 0};
+  if (df_status s = pad_operand(c, cpa, nao, nac, &ba, 1)) return s;
+  if (df_status s = run_half(c, B, naux, nao, cpa, nac, out_split(nullptr, X, naux, nao, 0, nac))) return s;
+  if (df_status s = run_mo(c, Cact, nac, X, naux, nao, nac, buv)) return s;
+  DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_pack_lower(buv, naux, nac, vp, c->stream), "pack launch");
+  const ColBlock bq{Cq, nq, nq, 0};
+  if (df_status s = pad_operand(c, cpq, nao, nq, &bq, 1)) return s;
+  // P ranges whose packed rows stay inside 31-bit offsets
+  const int64_t pb = std::max<int64_t>(1, ((int64_t(1) << 31) - 1) / npair);
+  for (int64_t u0 = 0; u0 < nuv; u0 += p.chunk) {
+    const int64_t zc = std::min<int64_t>(p.chunk, nuv - u0);
+    // W_uv = sum_P b^P_uv b^P over the packed pairs
+    for (int64_t p0 = 0; p0 < naux; p0 += pb) {
+      const int64_t pn = std::min<int64_t>(pb, naux - p0);
+      const dfk::OpMap A = dfk::op_map(vp + p0 * nuv + u0, zc, 1, pn, nuv);
+      const dfk::OpMap Bm = dfk::op_map(B + p0 * npair, npair, 1, pn, npair);
+      dfk::OutMap O = dfk::out_plain(W, zc, npair, npair);
+      O.accumulate = p0 > 0;
+      DF_LAUNCH(DF_KERNEL_PAPA, dfk::launch_gemm(A, Bm, O, 1, c->stream), "W product launch");
+    }
+    // T_uv = W_uv Cq (W_uv read packed), then out[uv] = Cp^T T_uv
+    if (df_status s = run_half(c, W, zc, nao, cpq, nq, out_pmajor(T, zc, nao, nq, nq))) return s;
+    if (df_status s = run_mo_pmajor(c, Cp, np, T, zc, nao, nq, out + u0 * np * nq)) return s;
+  }
+  return DF_OK;
 }
 
 df_status df_step(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const double* Cocc, int64_t nocc,

@@ -117,6 +117,8 @@ hipError_t launch_coulomb(const double* B, int64_t naux, int64_t nao, const doub
 hipError_t launch_fill_zero(double* p, int64_t n, hipStream_t s);
 // J[z][i][j] = J[z][j][i] = Jp[z][pair(i, j)] for nz packed symmetric matrices
 hipError_t launch_unpack_sym(const double* Jp, int64_t nz, int64_t nao, double* J, hipStream_t s);
+// Ap[z][pair(i, j)] = A[z][i][j] for i >= j: the lower triangles of nz n x n matrices, packed
+hipError_t launch_pack_lower(const double* A, int64_t nz, int64_t n, double* Ap, hipStream_t s);
 // p[z*s_z + i] = 0 for z < nz, i < n
 hipError_t launch_fill_zero_strided(double* p, int64_t nz, int64_t s_z, int64_t n, hipStream_t s);
 

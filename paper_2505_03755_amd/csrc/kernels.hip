@@ -839,6 +839,18 @@ __global__ void __launch_bounds__(256) unpack_sym_kernel(const double* __restric
   J[z * nao * nao + j * nao + i] = x;
 }
 
+__global__ void __launch_bounds__(256) pack_lower_kernel(const double* __restrict__ A, int64_t nz, int64_t n,
+                                                         int64_t npair, double* __restrict__ Ap) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= nz * npair) return;
+  const int64_t z = idx / npair, p = idx % npair;
+  int64_t i = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+  while (i * (i + 1) / 2 > p) --i;
+  while ((i + 1) * (i + 2) / 2 <= p) ++i;
+  const int64_t j = p - i * (i + 1) / 2;
+  Ap[idx] = A[z * n * n + i * n + j];
+}
+
 __global__ void __launch_bounds__(256) fill_zero_kernel(double* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) p[i] = 0.0;
@@ -1253,6 +1265,13 @@ hipError_t launch_unpack_sym(const double* Jp, int64_t nz, int64_t nao, double* 
   const int64_t npair = nao * (nao + 1) / 2, tot = nz * npair;
   if (tot <= 0) return hipSuccess;
   unpack_sym_kernel<<<(unsigned)cdiv(tot, 256), 256, 0, s>>>(Jp, nz, nao, npair, J);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_lower(const double* A, int64_t nz, int64_t n, double* Ap, hipStream_t s) {
+  const int64_t npair = n * (n + 1) / 2, tot = nz * npair;
+  if (tot <= 0) return hipSuccess;
+  pack_lower_kernel<<<(unsigned)cdiv(tot, 256), 256, 0, s>>>(A, nz, n, npair, Ap);
   return hipGetLastError();
 }
 

@@ -31,6 +31,7 @@ DF_OP_STEP_BACKWARD = 6
 DF_OP_SPLIT_MATMUL = 7
 DF_OP_STEP_SPLIT = 8
 DF_OP_STEP_BACKWARD_SPLIT = 9
+DF_OP_PPAA = 10
 
 DF_PAPA_FULL = 0x1
 DF_CALLER_X = 0x10
@@ -47,7 +48,8 @@ EXPORTED = ["df_create", "df_destroy", "df_last_error", "df_set_stream", "df_set
             "df_active_eri", "df_papa", "df_step", "df_step_backward", "df_split_matmul",
             "df_split_cholesky", "df_step_split", "df_batched_workspace_size", "df_batched_step",
             "df_set_autotune", "df_batched_tuning", "df_batched_set_tuning", "df_split_cholesky_t",
-            "df_step_backward_split", "df_batched_split_workspace_size", "df_batched_step_split"]
+            "df_step_backward_split", "df_batched_split_workspace_size", "df_batched_step_split",
+            "df_ppaa"]
 
 
 class DFError(RuntimeError):
@@ -94,6 +96,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         L.df_jk.argtypes = [vp, dp, i64, i64, i64, dp, i64, dp, dp, dp, dp, i32]
         L.df_active_eri.argtypes = [vp, dp, i64, i64, dp, i64, dp, dp, i32]
         L.df_papa.argtypes = [vp, dp, i64, i64, dp, i64, dp, i64, dp, i64, dp, i32]
+        L.df_ppaa.argtypes = [vp, dp, i64, i64, dp, i64, dp, i64, dp, i64, dp, i32]
         L.df_step.argtypes = [vp, dp, i64, i64, dp, i64, dp, dp, i64, dp, i64, dp, dp, dp, dp, dp, dp, dp, i32]
         L.df_step_backward.argtypes = [vp, dp, i64, i64, dp, i64, dp, i64, dp, dp, dp, dp, dp, dp, dp, i32]
         L.df_batched_workspace_size.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_size_t)]
@@ -319,6 +322,24 @@ def papa(B, nao: int, Cp, Cact, Cq=None, ctx: Context | None = None):
     ctx.prepare(DF_OP_PAPA, naux=naux, nao=nao, nac=nac, np=np_, nq=nq, flags=flags)
     ctx.check(ctx._lib.df_papa(ctx.handle, _ptr(B), naux, nao, _ptr(Cp), np_, _ptr(Cact), nac, _ptr(Cq), nq,
                                _ptr(out), flags))
+    return out
+
+
+def ppaa(B, nao: int, Cp, Cact, Cq=None, ctx: Context | None = None):
+    """(pq|uv) of Eq. (ppaa) as [nac(nac+1)/2][np][nq], the (uv) index packed (u >= v); Cq
+    defaults to Cp."""
+    import torch
+    ctx = ctx or context(B.device)
+    for n, t in (("B", B), ("Cp", Cp), ("Cact", Cact), ("Cq", Cq)):
+        _check_tensor(n, t, ctx.device)
+    naux = _naux_of(B, nao)
+    np_, nac = Cp.shape[1], Cact.shape[1]
+    nq = Cq.shape[1] if Cq is not None else 0
+    out = torch.empty((nac * (nac + 1) // 2, np_, nq if Cq is not None else np_), dtype=torch.float64,
+                      device=ctx.device)
+    ctx.prepare(DF_OP_PPAA, naux=naux, nao=nao, nac=nac, np=np_, nq=nq)
+    ctx.check(ctx._lib.df_ppaa(ctx.handle, _ptr(B), naux, nao, _ptr(Cp), np_, _ptr(Cq), nq, _ptr(Cact), nac,
+                               _ptr(out), 0))
     return out
 
 

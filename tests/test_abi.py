@@ -125,6 +125,21 @@ def test_active_eri_and_papa_argument_errors(L, ctx):
     assert L.df_papa(ctx, B, 10, 7, Cp, 0, Ca, 2, None, 0, O, 0) == dfmi.DF_OK      # empty output
 
 
+def test_ppaa_argument_errors(L, ctx):
+    B, Cp, Cq, Ca, O = fake(1 << 30), fake(2 << 30), fake(3 << 30), fake(4 << 30), fake(5 << 30)
+    assert L.df_ppaa(ctx, B, 10, 7, Cp, 7, Cq, 5, None, 2, O, 0) == dfmi.DF_ERR_ARG       # no Cact
+    assert L.df_ppaa(ctx, B, 10, 7, Cp, 7, None, 5, Ca, 2, O, 0) == dfmi.DF_ERR_ARG       # nq without Cq
+    assert L.df_ppaa(ctx, B, 10, 7, Cp, -1, None, 0, Ca, 2, O, 0) == dfmi.DF_ERR_SHAPE
+    assert L.df_ppaa(ctx, B, 10, 7, Cp, 7, None, 0, Ca, 2, O, 1) == dfmi.DF_ERR_UNSUPPORTED
+    assert L.df_ppaa(ctx, B, 10, 7, Cp, 7, None, 0, Ca, 2, B, 0) == dfmi.DF_ERR_ARG       # out overlaps B
+    assert L.df_ppaa(ctx, B, 10, 7, Cp, 7, None, 0, Ca, 2, O, 0) == dfmi.DF_ERR_WORKSPACE
+    assert L.df_ppaa(ctx, B, 10, 7, Cp, 7, None, 0, None, 0, None, 0) == dfmi.DF_OK      # nac = 0: empty
+    # workspace: the packed b_uv, and W_uv [nuv][npair] plus W_uv Cq [nuv][nao][nq] for one chunk
+    n = dfmi.workspace_size(dfmi.DF_OP_PPAA, naux=10, nao=7, nac=2, np=7)
+    assert n >= (10 * 3 + 3 * 28 + 3 * 7 * 7) * 8
+    assert dfmi.workspace_size(dfmi.DF_OP_PPAA, naux=10, nao=7, nac=2, np=7, nq=3) < n
+
+
 def test_step_argument_errors(L, ctx):
     B, Co, Ca, Cp = fake(1 << 30), fake(2 << 30), fake(3 << 30), fake(4 << 30)
     J, K = fake(5 << 30), fake(6 << 30)

@@ -130,3 +130,27 @@ def test_adjoint_consistent_with_forward(run):
     lhs = Cact.T @ host["dCact"]
     rhs = 2.0 * np.einsum("uvwx,yvwx->uy", host["eri"], Gam)
     assert rel(lhs, rhs) <= TOL
+
+
+def test_ppaa_sampled_rows_at_paper_scale(run):
+    """(pq|uv) at N_ao 1200, N_aux 4800, N_ac 40 with p, q over all 1200 MOs: the uv pairs run in
+    several chunks and the packed-pair product in two P ranges.  Sampled (p, q) rows against
+    the oracle's sum over P, streamed in P blocks."""
+    wl, B, C, Gam, out, host = run
+    Cact = C[:, wl.nocc:wl.nocc + wl.nac]
+    dev = B.device
+    g = dfmi.ppaa(B, wl.nao, torch.from_numpy(C).to(dev), torch.from_numpy(np.ascontiguousarray(Cact)).to(dev))
+    torch.cuda.synchronize()
+    pr, qr = [0, 299, 300, 339, 340, 1199], [1, 320, 777, 1198]
+    gs = g[:, pr][:, :, qr].cpu().numpy()
+    del g
+    torch.cuda.empty_cache()
+    # one unpack of each P block serves both factors: b^P for [C_p | C_act] x [C_q | C_act]
+    nr, ns = len(pr), len(qr)
+    Cl, Cr = np.hstack([C[:, pr], Cact]), np.hstack([C[:, qr], Cact])
+    ref = np.zeros((nr, ns, wl.nac, wl.nac))
+    for p0 in range(0, wl.naux, 480):
+        m = O.mo_vectors(B[p0:p0 + 480].cpu().numpy(), wl.nao, Cl, Cr)
+        ref += np.tensordot(m[:, :nr, :ns], m[:, nr:, ns:], axes=(0, 0))
+    u, v = np.tril_indices(wl.nac)
+    assert rel(gs, ref[:, :, u, v].transpose(2, 0, 1)) <= TOL
