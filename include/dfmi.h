@@ -251,10 +251,12 @@ df_status df_step_backward(df_ctx* ctx, const double* B, int64_t naux, int64_t n
  * Batched fragment subproblems (the embedding-space problems of the fragment CASSCFs, Sec.
  * "Calculation of effective potentials"): problem i has its own packed B, N_ao, N_aux and ndm
  * densities D_k = C_k C_k^T (unit weights), and asks for
- *   J[k], K[k] as in df_jk, (uv|wx) as in df_active_eri, and the full (pu|qv) of Eq. (papa)
- *   with p, q over the columns of Cp (as df_papa with DF_PAPA_FULL and Cq = Cp).
+ *   J[k], K[k] as in df_jk, (uv|wx) as in df_active_eri, the full (pu|qv) of Eq. (papa)
+ *   with p, q over the columns of Cp (as df_papa with DF_PAPA_FULL and Cq = Cp), and (pq|uv)
+ *   of Eq. (ppaa) over the same p, q (as df_ppaa with Cq = Cp).
  * The half transforms of all problems ([C_1 .. C_ndm | Cact] against b^P) run as one grouped
  * launch, and so do the K tiles; problems are ordered largest first inside each launch.
+ * (pq|uv) runs last, problem after problem, through one workspace region sized for the largest.
  * Any output may be NULL.  Inputs and outputs of all problems must not overlap each other.
  */
 typedef struct df_problem {
@@ -271,6 +273,7 @@ typedef struct df_problem {
   double* K;            /* [ndm][nao][nao] */
   double* eri;          /* [nac][nac][nac][nac] */
   double* papa;         /* [np][nac][np][nac] */
+  double* ppaa;         /* [nac(nac+1)/2][np][np], the (uv) index packed as in df_ppaa */
 } df_problem;
 
 /* Workspace bytes for df_batched_step on these problems. */
@@ -314,6 +317,7 @@ df_status df_batched_set_tuning(df_ctx* ctx, const df_problem* probs, int nprob,
  *   - flags = DF_SPLIT_K_FP64 computes K in FP64 from X_occ (the exchange product of
  *     df_batched_step) instead of splitting every density's X_occ, which for many densities
  *     costs more than the int8 product saves.  The workspace query takes the same flags.
+ *   - (pq|uv) is computed in FP64, as in df_batched_step, after the problem's other outputs.
  */
 df_status df_batched_split_workspace_size(const df_problem* probs, int nprob, int nslice, int flags, size_t* bytes);
 df_status df_batched_step_split(df_ctx* ctx, const df_problem* probs, const int8_t* const* Bs, const int* const* Be,

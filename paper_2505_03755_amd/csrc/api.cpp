@@ -166,6 +166,20 @@ PpaaPlan plan_ppaa(Plan& pl, int64_t naux, int64_t nao, int64_t nac, int64_t nq)
   return p;
 }
 
+// (pq|uv) of a batched problem: requested and not empty
+bool wants_ppaa(const df_problem& q) { return q.ppaa && q.nac > 0 && q.np > 0; }
+// One workspace region serves the (pq|uv) of every problem of a batch in turn: the largest.
+size_t batched_ppaa_bytes(const df_problem* probs, int n) {
+  size_t m = 0;
+  for (int i = 0; i < n; ++i)
+    if (wants_ppaa(probs[i])) {
+      Plan pp;
+      plan_ppaa(pp, probs[i].naux, probs[i].nao, probs[i].nac, probs[i].np);
+      m = std::max(m, pp.total);
+    }
+  return m;
+}
+
 StepPlan plan_step(Plan& pl, int64_t naux, int64_t nao, int64_t nocc, int64_t nac, int64_t np, bool caller_x) {
   StepPlan p{};
   const int64_t ncol = nocc + nac;
@@ -950,37 +964,11 @@ df_status df_papa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const
   return run_pgemm(c, DF_KERNEL_PAPA, bpu, np * nac, bvw, nac * nac, naux, out);
 }
 
-df_status df_ppaa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const double* Cp, int64_t np,
-                  const double* Cq, int64_t nq, const double* Cact, int64_t nac, double* out, int flags) {
-  df_ctx* c = ctx;
-  if (check_ctx(c)) return DF_ERR_ARG;
-  if (df_status s = check_core(c, B, naux, nao)) return s;
-  if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_ppaa takes no flags");
-  if (np < 0 || nac < 0 || nq < 0) return fail(c, DF_ERR_SHAPE, "sizes must be >= 0");
-  if (!Cq) {
-    if (nq != 0) return fail(c, DF_ERR_ARG, "nq must be 0 when Cq is NULL (Cq = Cp)");
-    Cq = Cp;
-    nq = np;
-  }
-  const int64_t nuv = nac * (nac + 1) / 2, nout = nuv * np * nq;
-  if (nout > 0 && (!Cp || !Cact || !out)) return fail(c, DF_ERR_ARG, "Cp, Cact and out are required");
-  const int64_t npair = nao * (nao + 1) / 2;
-  std::vector<Range> rs = {{B, dbytes(naux * npair), "B", false},
-                           {Cp, dbytes(nao * np), "Cp", false},
-                           {Cq == Cp ? nullptr : Cq, dbytes(nao * nq), "Cq", false},
-                           {Cact, dbytes(nao * nac), "Cact", false},
-                           {out, dbytes(nout), "out", true}};
-  Plan pl;
-  const PpaaPlan p = plan_ppaa(pl, naux, nao, nac, nq);
-  if (nout > 0) {
-    if (!check_overlap(c, rs)) return DF_ERR_ARG;
-    if (df_status s = need_ws(c, pl.total)) return s;
-    rs.push_back({c->ws, pl.total, "workspace", true});
-  }
-  if (!check_overlap(c, rs)) return DF_ERR_ARG;
-  if (nout == 0) return DF_OK;
-  if (df_status s = enter(c)) return s;
-  char* ws = c->ws;
+// (pq|uv) into out [nuv][np][nq] with the workspace pieces of p at ws (see plan_ppaa)
+static df_status ppaa_run(df_ctx* c, char* ws, const PpaaPlan& p, const double* B, int64_t naux, int64_t nao,
+                          const double* Cp, int64_t np, const double* Cq, int64_t nq, const double* Cact,
+                          int64_t nac, double* out) {
+  const int64_t npair = nao * (nao + 1) / 2, nuv = nac * (nac + 1) / 2;
   double* X = (double*)(ws + p.x);
   double* buv = (double*)(ws + p.buv);
   double* vp = (double*)(ws + p.vp);
@@ -1014,6 +1002,39 @@ df_status df_ppaa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const
     if (df_status s = run_mo_pmajor(c, Cp, np, T, zc, nao, nq, out + u0 * np * nq)) return s;
   }
   return DF_OK;
+}
+
+df_status df_ppaa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const double* Cp, int64_t np,
+                  const double* Cq, int64_t nq, const double* Cact, int64_t nac, double* out, int flags) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (df_status s = check_core(c, B, naux, nao)) return s;
+  if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_ppaa takes no flags");
+  if (np < 0 || nac < 0 || nq < 0) return fail(c, DF_ERR_SHAPE, "sizes must be >= 0");
+  if (!Cq) {
+    if (nq != 0) return fail(c, DF_ERR_ARG, "nq must be 0 when Cq is NULL (Cq = Cp)");
+    Cq = Cp;
+    nq = np;
+  }
+  const int64_t nuv = nac * (nac + 1) / 2, nout = nuv * np * nq;
+  if (nout > 0 && (!Cp || !Cact || !out)) return fail(c, DF_ERR_ARG, "Cp, Cact and out are required");
+  const int64_t npair = nao * (nao + 1) / 2;
+  std::vector<Range> rs = {{B, dbytes(naux * npair), "B", false},
+                           {Cp, dbytes(nao * np), "Cp", false},
+                           {Cq == Cp ? nullptr : Cq, dbytes(nao * nq), "Cq", false},
+                           {Cact, dbytes(nao * nac), "Cact", false},
+                           {out, dbytes(nout), "out", true}};
+  Plan pl;
+  const PpaaPlan p = plan_ppaa(pl, naux, nao, nac, nq);
+  if (nout > 0) {
+    if (!check_overlap(c, rs)) return DF_ERR_ARG;
+    if (df_status s = need_ws(c, pl.total)) return s;
+    rs.push_back({c->ws, pl.total, "workspace", true});
+  }
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (nout == 0) return DF_OK;
+  if (df_status s = enter(c)) return s;
+  return ppaa_run(c, c->ws, p, B, naux, nao, Cp, np, Cq, nq, Cact, nac, out);
 }
 
 df_status df_step(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const double* Cocc, int64_t nocc,
@@ -1577,7 +1598,7 @@ df_status df_batched_workspace_size(const df_problem* probs, int nprob, size_t* 
   }
   Plan pl;
   plan_batched(pl, probs, nprob);
-  *bytes = pl.total;
+  *bytes = pl.total + batched_ppaa_bytes(probs, nprob);
   return DF_OK;
 }
 
@@ -1626,8 +1647,10 @@ df_status df_batched_step(df_ctx* ctx, const df_problem* probs, int nprob, int f
     if (q.nocc > 0 && (q.J || q.K) && !q.Cocc) return fail(c, DF_ERR_ARG, tag + "Cocc is NULL");
     if (q.nac > 0 && (q.eri || q.papa) && !q.Cact) return fail(c, DF_ERR_ARG, tag + "Cact is NULL");
     if (q.np > 0 && q.papa && !q.Cp) return fail(c, DF_ERR_ARG, tag + "Cp is NULL");
+    if (wants_ppaa(q) && (!q.Cact || !q.Cp)) return fail(c, DF_ERR_ARG, tag + "ppaa needs Cact and Cp");
     const int64_t npair = q.nao * (q.nao + 1) / 2;
     rs.push_back({q.B, dbytes(q.naux * npair), "B", false});
+    rs.push_back({q.ppaa, dbytes(q.nac * (q.nac + 1) / 2 * q.np * q.np), "ppaa", true});
     rs.push_back({q.Cocc, dbytes(q.ndm * q.nao * q.nocc), "Cocc", false});
     rs.push_back({q.Cact, dbytes(q.nao * q.nac), "Cact", false});
     rs.push_back({q.Cp, dbytes(q.nao * q.np), "Cp", false});
@@ -1639,6 +1662,8 @@ df_status df_batched_step(df_ctx* ctx, const df_problem* probs, int nprob, int f
   if (!check_overlap(c, rs)) return DF_ERR_ARG;
   Plan pl;
   const std::vector<BatchedPiece> pc = plan_batched(pl, probs, nprob);
+  const size_t ppaa_off = pl.total;
+  pl.total += batched_ppaa_bytes(probs, nprob);
   if (df_status s = need_ws(c, pl.total)) return s;
   if (pl.total) rs.push_back({c->ws, pl.total, "workspace", true});
   if (!check_overlap(c, rs)) return DF_ERR_ARG;
@@ -1797,6 +1822,16 @@ df_status df_batched_step(df_ctx* ctx, const df_problem* probs, int nprob, int f
       if (df_status s = run_pgemm(c, DF_KERNEL_PAPA, bpu, q.np * q.nac, bpu, q.np * q.nac, q.naux, q.papa)) return s;
     }
   }
+  // (pq|uv) through the AO basis, problem after problem in one region
+  for (int i : order) {
+    const df_problem& q = probs[i];
+    if (!wants_ppaa(q)) continue;
+    Plan pp;
+    const PpaaPlan p = plan_ppaa(pp, q.naux, q.nao, q.nac, q.np);
+    if (df_status s = ppaa_run(c, ws + ppaa_off, p, q.B, q.naux, q.nao, q.Cp, q.np, q.Cp, q.np, q.Cact, q.nac,
+                               q.ppaa))
+      return s;
+  }
   return DF_OK;
 }
 
@@ -1930,6 +1965,7 @@ df_status df_batched_split_workspace_size(const df_problem* probs, int nprob, in
     plan_split_piece(pl, q, nslice, (flags & DF_SPLIT_K_FP64) != 0);
     *bytes = std::max(*bytes, pl.total);
   }
+  *bytes = std::max(*bytes, batched_ppaa_bytes(probs, nprob));
   return DF_OK;
 }
 
@@ -1955,6 +1991,7 @@ df_status df_batched_step_split(df_ctx* ctx, const df_problem* probs, const int8
     if (q.nocc > 0 && (q.J || q.K) && !q.Cocc) return fail(c, DF_ERR_ARG, tag + "Cocc is NULL");
     if (q.nac > 0 && (q.eri || q.papa) && !q.Cact) return fail(c, DF_ERR_ARG, tag + "Cact is NULL");
     if (q.np > 0 && q.papa && !q.Cp) return fail(c, DF_ERR_ARG, tag + "Cp is NULL");
+    if (wants_ppaa(q) && (!q.Cact || !q.Cp)) return fail(c, DF_ERR_ARG, tag + "ppaa needs Cact and Cp");
     if (!Bs[i] || !Be[i]) return fail(c, DF_ERR_ARG, tag + "Bs or Be is NULL");
     if ((uintptr_t)Bs[i] % 16 != 0) return fail(c, DF_ERR_ARG, tag + "Bs must be 16-byte aligned");
     const int64_t npair = q.nao * (q.nao + 1) / 2;
@@ -1968,18 +2005,29 @@ df_status df_batched_step_split(df_ctx* ctx, const df_problem* probs, const int8
     rs.push_back({q.K, dbytes(q.ndm * q.nao * q.nao), "K", true});
     rs.push_back({q.eri, dbytes(q.nac * q.nac * q.nac * q.nac), "eri", true});
     rs.push_back({q.papa, dbytes(q.np * q.nac * q.np * q.nac), "papa", true});
+    rs.push_back({q.ppaa, dbytes(q.nac * (q.nac + 1) / 2 * q.np * q.np), "ppaa", true});
     Plan pl;
     plan_split_piece(pl, q, nslice, k_fp64);
     need = std::max(need, pl.total);
   }
+  need = std::max(need, batched_ppaa_bytes(probs, nprob));
   if (!check_overlap(c, rs)) return DF_ERR_ARG;
   if (df_status s = need_ws(c, need)) return s;
   if (need) rs.push_back({c->ws, need, "workspace", true});
   if (!check_overlap(c, rs)) return DF_ERR_ARG;
   if (nprob == 0) return DF_OK;
   if (df_status s = enter(c)) return s;
-  for (int i = 0; i < nprob; ++i)
-    if (df_status s = split_problem_run(c, c->ws, probs[i], Bs[i], Be[i], nslice, k_fp64)) return s;
+  for (int i = 0; i < nprob; ++i) {
+    const df_problem& q = probs[i];
+    if (df_status s = split_problem_run(c, c->ws, q, Bs[i], Be[i], nslice, k_fp64)) return s;
+    if (wants_ppaa(q)) {
+      // (pq|uv) in FP64 through the AO basis, in the same region
+      Plan pp;
+      const PpaaPlan p = plan_ppaa(pp, q.naux, q.nao, q.nac, q.np);
+      if (df_status s = ppaa_run(c, c->ws, p, q.B, q.naux, q.nao, q.Cp, q.np, q.Cp, q.np, q.Cact, q.nac, q.ppaa))
+        return s;
+    }
+  }
   return DF_OK;
 }
 

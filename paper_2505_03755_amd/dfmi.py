@@ -404,12 +404,13 @@ class Problem(ctypes.Structure):
                 ("ndm", ctypes.c_int64), ("Cocc", ctypes.c_void_p), ("nocc", ctypes.c_int64),
                 ("Cact", ctypes.c_void_p), ("nac", ctypes.c_int64), ("Cp", ctypes.c_void_p),
                 ("np", ctypes.c_int64), ("J", ctypes.c_void_p), ("K", ctypes.c_void_p),
-                ("eri", ctypes.c_void_p), ("papa", ctypes.c_void_p)]
+                ("eri", ctypes.c_void_p), ("papa", ctypes.c_void_p), ("ppaa", ctypes.c_void_p)]
 
 
-def batched_step(problems, ctx: Context | None = None):
+def batched_step(problems, ppaa: bool = False, ctx: Context | None = None):
     """df_batched_step over a list of dicts {B, nao, Cocc [ndm, nao, nocc], Cact, Cp}; returns one
-    dict of outputs per problem: J, K [ndm, nao, nao], eri [nac]^4, papa (pu|qv) [np, nac, np, nac]."""
+    dict of outputs per problem: J, K [ndm, nao, nao], eri [nac]^4, papa (pu|qv) [np, nac, np, nac],
+    and with ppaa also (pq|uv) [nac(nac+1)/2, np, np]."""
     import torch
     if not problems:
         return []
@@ -428,9 +429,11 @@ def batched_step(problems, ctx: Context | None = None):
              "K": torch.empty((ndm, nao, nao), dtype=torch.float64, device=dev),
              "eri": torch.empty((nac,) * 4, dtype=torch.float64, device=dev),
              "papa": torch.empty((np_, nac, np_, nac), dtype=torch.float64, device=dev)}
+        if ppaa:
+            o["ppaa"] = torch.empty((nac * (nac + 1) // 2, np_, np_), dtype=torch.float64, device=dev)
         outs.append(o)
         arr[i] = Problem(_ptr(B), naux, nao, ndm, _ptr(Co), nocc, _ptr(Ca), nac, _ptr(Cp), np_,
-                         _ptr(o["J"]), _ptr(o["K"]), _ptr(o["eri"]), _ptr(o["papa"]))
+                         _ptr(o["J"]), _ptr(o["K"]), _ptr(o["eri"]), _ptr(o["papa"]), _ptr(o.get("ppaa")))
     L = ctx._lib
     need = ctypes.c_size_t(0)
     ctx.check(L.df_batched_workspace_size(arr, len(problems), ctypes.byref(need)))
@@ -444,10 +447,11 @@ def batched_step(problems, ctx: Context | None = None):
     return outs
 
 
-def batched_step_split(problems, nslice: int = 7, k_fp64: bool = False, ctx: Context | None = None):
+def batched_step_split(problems, nslice: int = 7, k_fp64: bool = False, ppaa: bool = False,
+                       ctx: Context | None = None):
     """df_batched_step_split: as batched_step, in split precision; each problem dict also carries
     "Bs", "Be" from split_cholesky(B, nao, nslice).  k_fp64 computes K in FP64 from the
-    split-precision X_occ (DF_SPLIT_K_FP64)."""
+    split-precision X_occ (DF_SPLIT_K_FP64); (pq|uv) (with ppaa) is FP64."""
     import torch
     if not problems:
         return []
@@ -473,9 +477,11 @@ def batched_step_split(problems, nslice: int = 7, k_fp64: bool = False, ctx: Con
              "K": torch.empty((ndm, nao, nao), dtype=torch.float64, device=dev),
              "eri": torch.empty((nac,) * 4, dtype=torch.float64, device=dev),
              "papa": torch.empty((np_, nac, np_, nac), dtype=torch.float64, device=dev)}
+        if ppaa:
+            o["ppaa"] = torch.empty((nac * (nac + 1) // 2, np_, np_), dtype=torch.float64, device=dev)
         outs.append(o)
         arr[i] = Problem(_ptr(B), naux, nao, ndm, _ptr(Co), nocc, _ptr(Ca), nac, _ptr(Cp), np_,
-                         _ptr(o["J"]), _ptr(o["K"]), _ptr(o["eri"]), _ptr(o["papa"]))
+                         _ptr(o["J"]), _ptr(o["K"]), _ptr(o["eri"]), _ptr(o["papa"]), _ptr(o.get("ppaa")))
         bs[i], be[i] = Bs.data_ptr(), Be.data_ptr()
     L = ctx._lib
     need = ctypes.c_size_t(0)

@@ -280,6 +280,18 @@ def test_batched_argument_errors(L, ctx):
     arr[1].ndm = 0
     assert L.df_batched_step(ctx, arr, 2, 0) == dfmi.DF_ERR_SHAPE
     assert L.df_batched_workspace_size(arr, 2, ctypes.byref(n)) == dfmi.DF_ERR_SHAPE
+    arr[1].ndm = 1
+    # (pq|uv): one more region, the size of problem 0's df_ppaa workspace
+    assert L.df_batched_workspace_size(arr, 2, ctypes.byref(n)) == dfmi.DF_OK
+    base = n.value
+    arr[0].ppaa = 10 << 30
+    assert L.df_batched_workspace_size(arr, 2, ctypes.byref(n)) == dfmi.DF_OK
+    assert n.value - base == dfmi.workspace_size(dfmi.DF_OP_PPAA, naux=10, nao=7, nac=2, np=7)
+    arr[0].Cp = None
+    assert L.df_batched_step(ctx, arr, 2, 0) == dfmi.DF_ERR_ARG     # ppaa needs Cp
+    arr[0].Cp = 4 << 30
+    arr[0].ppaa = 5 << 30                     # overlaps problem 0's J
+    assert L.df_batched_step(ctx, arr, 2, 0) == dfmi.DF_ERR_ARG
 
 
 def test_batched_tuning_table(L, ctx):

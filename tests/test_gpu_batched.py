@@ -42,6 +42,12 @@ def to_dev(p):
 RAGGED = [(33, 40, 7, 3, 3), (130, 90, 20, 5, 2), (17, 70, 4, 2, 5), (64, 64, 0, 4, 2), (70, 30, 9, 0, 3)]
 
 
+def packed_uv(ref):
+    """oracle (pq|uv) [p][q][u][v] -> [pair(u, v)][p][q], u >= v"""
+    u, v = np.tril_indices(ref.shape[2])
+    return np.ascontiguousarray(ref[:, :, u, v].transpose(2, 0, 1))
+
+
 def check_problem(p, out, tol_oracle=1e-10):
     B, nao = p["B"], p["nao"]
     ndm, nocc = p["Cocc"].shape[0], p["Cocc"].shape[2]
@@ -59,6 +65,8 @@ def check_problem(p, out, tol_oracle=1e-10):
         assert rel(out["eri"], eri) <= tol_oracle
         pf = O.papa_full(B, nao, p["Cp"], p["Cact"], p["Cp"])
         assert rel(out["papa"], pf) <= tol_oracle
+        if "ppaa" in out:
+            assert rel(out["ppaa"], packed_uv(O.ppaa(B, nao, p["Cp"], p["Cp"], p["Cact"]))) <= 1e-10
 
 
 def test_batched_ragged_against_oracle():
@@ -67,6 +75,18 @@ def test_batched_ragged_against_oracle():
     torch.cuda.synchronize()
     for p, o in zip(probs, outs):
         check_problem(p, o)
+
+
+def test_batched_ppaa_against_oracle_and_single_call():
+    """(pq|uv) requested in the batch: against the oracle, and bit for bit against df_ppaa (the
+    same route on the same shapes)."""
+    probs = [make(*shape, seed=i + 31) for i, shape in enumerate(RAGGED)]
+    dps = [to_dev(p) for p in probs]
+    outs = dfmi.batched_step(dps, ppaa=True)
+    torch.cuda.synchronize()
+    for p, dp, o in zip(probs, dps, outs):
+        check_problem(p, o)
+        assert torch.equal(o["ppaa"], dfmi.ppaa(dp["B"], dp["nao"], dp["Cp"], dp["Cact"]))
 
 
 def test_batched_equals_unbatched_calls():
@@ -196,8 +216,8 @@ def test_batched_split_ragged_against_oracle(k_fp64):
     or, with k_fp64, in FP64 from the split-precision X_occ."""
     probs = [make(*shape, seed=i + 51) for i, shape in enumerate(RAGGED)]
     dps = with_split([to_dev(p) for p in probs])
-    outs = dfmi.batched_step_split(dps, k_fp64=k_fp64)
-    ref = dfmi.batched_step(dps)
+    outs = dfmi.batched_step_split(dps, k_fp64=k_fp64, ppaa=k_fp64)
+    ref = dfmi.batched_step(dps, ppaa=k_fp64)
     torch.cuda.synchronize()
     for p, o, r in zip(probs, outs, ref):
         check_problem(p, o, tol_oracle=1e-11)
@@ -219,3 +239,19 @@ def test_batched_split_fragment_workload_reduced_densities():
     for p, o in zip(probs[6:], outs[6:]):
         J, K, _ = O.jk(p["B"], p["nao"], p["Cocc"][1])
         assert rel(o["J"][1], J) <= 1e-11 and rel(o["K"][1], K) <= 1e-11
+
+
+def test_fragment_shapes_with_ppaa():
+    """The eight fragment shapes (one density each) with (pq|uv): the oracle on the three
+    smallest, df_ppaa of the same problem on the rest (bitwise)."""
+    probs = []
+    for f in synth.FRAGMENTS:
+        B, Cd, C = synth.fragment_problem(f, ndm=1)
+        probs.append({"B": B, "nao": f.nemb, "Cocc": Cd, "Cact": C[:, f.nocc:f.nocc + f.nac], "Cp": C})
+    dps = [to_dev(p) for p in probs]
+    outs = dfmi.batched_step(dps, ppaa=True)
+    torch.cuda.synchronize()
+    for p, o in zip(probs[:3], outs[:3]):
+        assert rel(o["ppaa"], packed_uv(O.ppaa(p["B"], p["nao"], p["Cp"], p["Cp"], p["Cact"]))) <= 1e-10
+    for dp, o in zip(dps[3:], outs[3:]):
+        assert torch.equal(o["ppaa"], dfmi.ppaa(dp["B"], dp["nao"], dp["Cp"], dp["Cact"]))
