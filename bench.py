@@ -320,6 +320,8 @@ def batched_fragments(ndm, reps, ctx, nslice=7):
     ms_g = timed(graph.replay)
     del graph
     ms_u = timed(unbatched)
+    # the same batch with (pq|uv) of every fragment added (p, q over all its MOs)
+    ms_pp = timed(lambda: dfmi.batched_step(probs, ppaa=True, ctx=ctx))
     # split precision: each fragment's B split once (not timed), then df_batched_step_split
     ref = dfmi.batched_step(probs, ctx=ctx)
     for p in probs:
@@ -344,6 +346,7 @@ def batched_fragments(ndm, reps, ctx, nslice=7):
             "tuning": {k: tuning[k] for k in ("half_tile_n", "k_tile", "k_rounds")}, "tuning_call_s": tune_s,
             "ms_batched_default_tiles": ms_default, "ms_graph_replay": ms_g,
             "ms_unbatched": ms_u, "tflops_unbatched": fl / ms_u / 1e9,
+            "ms_batched_with_ppaa": ms_pp,
             "split": split}
 
 
