@@ -251,6 +251,38 @@ def ppaa_block(B, nao, Cact, C, reps, ctx):
             "kernels_ms": {names.get(k, k): v[0] for k, v in kt.items() if v[1] > 0}}
 
 
+def build_block(naux, nao, reps, ctx):
+    """df_build_cholesky at N_aux x N_ao: the metric factored and B = L^-1 E formed (E drawn on the
+    GPU, the metric on the host, neither timed), timed with HIP events on the library's stream."""
+    import torch
+    from paper_2505_03755_amd import dfmi, synth
+    dev = torch.device("cuda", 0)
+    metric = torch.from_numpy(synth.coulomb_metric(naux, 1e6, seed=11)).to(dev)
+    E = synth.device_cholesky_vectors(naux, nao, 40.0, seed=12, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    L, B, info = dfmi.build_cholesky(metric, E, nao, ctx=ctx)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(stream)
+    for i in range(reps):
+        dfmi.build_cholesky(metric, E, nao, check=False, ctx=ctx)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    ms = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(reps))[reps // 2]
+    ctx.set_timing(True)
+    ctx.timing_read()
+    dfmi.build_cholesky(metric, E, nao, check=False, ctx=ctx)
+    kt = ctx.timing_read()
+    ctx.set_timing(False)
+    ok = int(info.item()) == 0
+    del L, B, E, metric, info
+    torch.cuda.empty_cache()
+    npair = nao * (nao + 1) // 2
+    fl = naux ** 3 / 3 + naux * naux * npair
+    return {"shape": f"N_aux={naux}, N_ao={nao}; metric condition 1e6", "ms": ms, "flops": fl,
+            "tflops": fl / ms / 1e9, "info_ok": ok,
+            "kernels_ms": {k: v[0] for k, v in kt.items() if v[1] > 0}}
+
+
 def fragment_flops(f, ndm):
     """Algorithmic FLOPs of one fragment subproblem: half transform, J, K, b_pu and the full
     (pu|qv), and (uv|wx)."""
@@ -362,6 +394,7 @@ def main():
     ap.add_argument("--no-split", action="store_true", help="skip the split-precision comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched fragment workload")
     ap.add_argument("--no-ppaa", action="store_true", help="skip the (pq|uv) block")
+    ap.add_argument("--no-build", action="store_true", help="skip forming B from the metric")
     ap.add_argument("--fragment-densities", type=int, default=64)
     ap.add_argument("--split-slices", type=int, default=7)
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
@@ -502,6 +535,9 @@ def main():
     del B
     out.clear()
     torch.cuda.empty_cache()
+    if not args.no_build:
+        log("[bench] B from the metric and the three-centre integrals")
+        res["build_cholesky"] = build_block(naux, nao, 3, ctx)
     if not args.no_batched:
         log(f"[bench] batched fragment subproblems, {args.fragment_densities} densities each")
         res["batched_fragments"] = batched_fragments(args.fragment_densities, 3, ctx, args.split_slices)

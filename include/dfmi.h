@@ -12,6 +12,8 @@
  *   df_papa             (pu|vw), the g^{p a}_{a a} pattern of the orbital gradient (Eq. MO_conv);
  *                       with DF_PAPA_FULL the (pu|qv) block of Eq. (papa)
  *   df_ppaa             (pq|uv) of Eq. (ppaa), through the AO basis
+ *   df_build_cholesky   b^P itself from the three-centre integrals and the metric, Eq. (cholesky)
+ *   df_embed_cholesky   b^P in another orbital basis (fragment embedding orbitals)
  *   df_step             all of the above from one shared half transform
  *
  * Conventions shared by every call
@@ -67,7 +69,9 @@ typedef enum df_op {
   DF_OP_SPLIT_MATMUL = 7,
   DF_OP_STEP_SPLIT = 8,
   DF_OP_STEP_BACKWARD_SPLIT = 9,
-  DF_OP_PPAA = 10
+  DF_OP_PPAA = 10,
+  DF_OP_BUILD_CHOLESKY = 11,
+  DF_OP_EMBED_CHOLESKY = 12
 } df_op;
 
 /* Kernel classes reported by df_timing_read. */
@@ -83,7 +87,8 @@ typedef enum df_kernel_kind {
   DF_KERNEL_OTHER = 8,           /* fills, symmetrisations and coefficient gathers */
   DF_KERNEL_ADJOINT = 9,         /* the products of df_step_backward */
   DF_KERNEL_SPLIT = 10,          /* splitting FP64 operands into int8 slices */
-  DF_NUM_KERNEL_KINDS = 11
+  DF_KERNEL_BUILD = 11,          /* metric Cholesky and forward substitution of df_build_cholesky */
+  DF_NUM_KERNEL_KINDS = 12
 } df_kernel_kind;
 
 /* Flag bits of calls. */
@@ -104,7 +109,7 @@ typedef struct df_dims {
   int64_t nac;    /* active orbitals */
   int64_t np;     /* columns of Cp (MO space p) */
   int64_t nq;     /* columns of Cq (DF_PAPA_FULL, DF_OP_PPAA) */
-  int64_t ncol;   /* columns of C in df_half_transform */
+  int64_t ncol;   /* columns of C in df_half_transform; nemb for DF_OP_EMBED_CHOLESKY */
   int64_t n2;     /* columns of C2 in df_half_transform (0 if no second transform) */
   int flags;
   int nslice;     /* int8 slices per operand (split-precision ops) */
@@ -211,6 +216,44 @@ df_status df_papa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
 df_status df_ppaa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
                   const double* Cp, int64_t np, const double* Cq, int64_t nq,
                   const double* Cact, int64_t nac, double* out, int flags);
+
+/*
+ * Cholesky vectors from the three-centre integrals, Eq. (cholesky):
+ *   (mu nu|lam sig) ~ (mu nu|P) (P|Q)^-1 (Q|lam sig) = sum_P b^P_{mu nu} b^P_{lam sig}
+ * with (P|Q) = L L^T and B = L^-1 E, E[Q][pair] = (Q|mu nu) packed like B.
+ *   metric [naux][naux]: (P|Q), symmetric positive definite; its lower triangle is read.
+ *   eri3 [naux][npair]: (Q|mu nu).
+ *   L [naux][naux] (output): the Cholesky factor, lower triangular, upper part zeroed.
+ *       L may be `metric` itself (factored in place).
+ *   B [naux][npair] (output): the Cholesky vectors.  B may be `eri3` itself (in place).
+ *   info: one device int, written 0 on success, else P + 1 for the first auxiliary index P
+ *       whose pivot is not positive (the metric is not positive definite to working
+ *       precision); L and B are then undefined.  It is written on the stream, so read it after
+ *       the stream has drained.
+ * The factorisation runs in 128-wide block columns, left-looking: each diagonal block takes the
+ * earlier columns' update as a product, is factored and inverted by one workgroup, and the panel
+ * below is multiplied by the inverted block.  The substitution runs in block rows,
+ * B_k = L_kk^-1 (E_k - L_{k,<k} B_{<k}), the update as one product over all earlier rows.
+ * Requires 128 * npair < 2^32 and naux^2 < 2^32 (DF_ERR_SHAPE otherwise).
+ * Errors: DF_ERR_ARG for NULL pointers or overlapping buffers other than the two in-place
+ * pairs; DF_ERR_SHAPE for sizes; DF_ERR_UNSUPPORTED for flags != 0.
+ * Workspace: df_workspace_size(DF_OP_BUILD_CHOLESKY, {naux, nao}).
+ */
+df_status df_build_cholesky(df_ctx* ctx, const double* metric, const double* eri3, int64_t naux, int64_t nao,
+                            double* L, double* B, int* info, int flags);
+
+/*
+ * Cholesky vectors in another orbital basis, e.g. a fragment's embedding orbitals (effective
+ * potentials are built the same way in the AO and in the embedding basis, Sec. "Calculation of
+ * effective potentials"):
+ *   Be[P][pair(e, f)] = (M^T b^P M)_{ef},  M [nao][nemb] (input),  Be [naux][nemb(nemb+1)/2]
+ * packed like B.  P runs in chunks that keep b^P M and M^T b^P M near 1 GiB.
+ * Errors: DF_ERR_ARG for missing M/Be (nemb > 0) or overlaps; DF_ERR_SHAPE for sizes;
+ * DF_ERR_UNSUPPORTED for flags != 0.
+ * Workspace: df_workspace_size(DF_OP_EMBED_CHOLESKY, {naux, nao, ncol = nemb}).
+ */
+df_status df_embed_cholesky(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const double* M, int64_t nemb,
+                            double* Be, int flags);
 
 /*
  * One forward pass of the whole path from a single half transform X = b^P [Cocc | Cact]:

@@ -166,6 +166,38 @@ PpaaPlan plan_ppaa(Plan& pl, int64_t naux, int64_t nao, int64_t nac, int64_t nq)
   return p;
 }
 
+// Workspace of df_build_cholesky: the inverted diagonal blocks of L, a panel of the factorisation
+// and one block row of the substitution.
+struct BuildPlan {
+  size_t linv, panel, t;
+  int64_t nblk;
+};
+BuildPlan plan_build(Plan& pl, int64_t naux, int64_t nao) {
+  BuildPlan p{};
+  const int64_t nb = dfk::kCholNB, npair = nao * (nao + 1) / 2;
+  p.nblk = (naux + nb - 1) / nb;
+  p.linv = pl.take(p.nblk * nb * nb);
+  p.panel = pl.take(naux * nb);
+  p.t = pl.take(nb * npair);
+  return p;
+}
+
+// Workspace of df_embed_cholesky: b^P M and M^T b^P M for a chunk of P (near 1 GiB).
+constexpr int64_t kEmbedChunkBytes = int64_t(1) << 30;
+struct EmbedPlan {
+  size_t mpad, x, y;
+  int64_t chunk;
+};
+EmbedPlan plan_embed(Plan& pl, int64_t naux, int64_t nao, int64_t nemb) {
+  EmbedPlan p{};
+  const int64_t per = (nao + nemb) * nemb * (int64_t)sizeof(double);
+  p.chunk = std::max<int64_t>(1, std::min<int64_t>(naux, kEmbedChunkBytes / std::max<int64_t>(per, 1)));
+  p.mpad = pl.take(dfk::kpad16(nao) * nemb);
+  p.x = pl.take(p.chunk * nao * nemb);
+  p.y = pl.take(p.chunk * nemb * nemb);
+  return p;
+}
+
 // (pq|uv) of a batched problem: requested and not empty
 bool wants_ppaa(const df_problem& q) { return q.ppaa && q.nac > 0 && q.np > 0; }
 // One workspace region serves the (pq|uv) of every problem of a batch in turn: the largest.
@@ -778,6 +810,8 @@ df_status df_workspace_size(df_op op, const df_dims* d, size_t* bytes) {
     case DF_OP_PAPA:
       plan_papa(pl, d->naux, d->nao, d->nac, d->np, d->nq, (d->flags & DF_PAPA_FULL) != 0);
       break;
+    case DF_OP_BUILD_CHOLESKY: plan_build(pl, d->naux, d->nao); break;
+    case DF_OP_EMBED_CHOLESKY: plan_embed(pl, d->naux, d->nao, d->ncol); break;
     case DF_OP_PPAA:
       plan_ppaa(pl, d->naux, d->nao, d->nac, d->nq > 0 ? d->nq : d->np);
       break;
@@ -1035,6 +1069,137 @@ df_status df_ppaa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const
   if (nout == 0) return DF_OK;
   if (df_status s = enter(c)) return s;
   return ppaa_run(c, c->ws, p, B, naux, nao, Cp, np, Cq, nq, Cact, nac, out);
+}
+
+df_status df_build_cholesky(df_ctx* ctx, const double* metric, const double* eri3, int64_t naux, int64_t nao,
+                            double* L, double* B, int* info, int flags) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_build_cholesky takes no flags");
+  if (!metric || !eri3 || !L || !B || !info) return fail(c, DF_ERR_ARG, "metric, eri3, L, B and info are required");
+  if (naux < 1 || nao < 1) return fail(c, DF_ERR_SHAPE, "naux and nao must be >= 1");
+  const int64_t nb = dfk::kCholNB, npair = nao * (nao + 1) / 2;
+  // a block row of the substitution is addressed with 32-bit offsets
+  if (nb * npair >= (int64_t(1) << 32) || naux * naux >= (int64_t(1) << 32))
+    return fail(c, DF_ERR_SHAPE, "nao or naux too large for df_build_cholesky");
+  // L may be the metric itself and B the integrals themselves (in place); nothing else may overlap
+  std::vector<Range> rs = {{metric == L ? nullptr : metric, dbytes(naux * naux), "metric", false},
+                           {eri3 == B ? nullptr : eri3, dbytes(naux * npair), "eri3", false},
+                           {L, dbytes(naux * naux), "L", true},
+                           {B, dbytes(naux * npair), "B", true},
+                           {info, sizeof(int), "info", true}};
+  Plan pl;
+  const BuildPlan p = plan_build(pl, naux, nao);
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (df_status s = need_ws(c, pl.total)) return s;
+  rs.push_back({c->ws, pl.total, "workspace", true});
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (df_status s = enter(c)) return s;
+  double* linv = (double*)(c->ws + p.linv);
+  double* panel = (double*)(c->ws + p.panel);
+  double* T = (double*)(c->ws + p.t);
+  const int64_t n = naux;
+  if (L != metric)
+    DF_LAUNCH(DF_KERNEL_OTHER, hipMemcpyAsync(L, metric, dbytes(n * n), hipMemcpyDeviceToDevice, c->stream),
+              "metric copy");
+  // left-looking blocked Cholesky: block column k takes the earlier columns' updates, its
+  // diagonal block is factored (and inverted) in one workgroup, the panel below is solved
+  // against the inverted block
+  for (int64_t k = 0; k < p.nblk; ++k) {
+    const int64_t k0 = k * nb, kb = std::min(nb, n - k0), r0 = k0 + kb, m = n - r0;
+    if (k0 > 0) {
+      const dfk::OpMap A = dfk::op_map(L + k0 * n, kb, n, k0, 1);
+      dfk::OutMap O = dfk::out_plain(L + k0 * n + k0, kb, kb, n);
+      O.alpha = -1.0;
+      O.accumulate = 1;
+      DF_LAUNCH(DF_KERNEL_BUILD, dfk::launch_gemm(A, A, O, 1, c->stream), "diagonal update launch");
+    }
+    DF_LAUNCH(DF_KERNEL_BUILD,
+              dfk::launch_chol_block(L + k0 * n + k0, n, (int)kb, linv + k * nb * nb, info, k0, k == 0, c->stream),
+              "diagonal block launch");
+    if (m == 0) continue;
+    if (k0 > 0) {
+      const dfk::OpMap A = dfk::op_map(L + r0 * n, m, n, k0, 1);
+      const dfk::OpMap Bm = dfk::op_map(L + k0 * n, kb, n, k0, 1);
+      dfk::OutMap O = dfk::out_plain(L + r0 * n + k0, m, kb, n);
+      O.alpha = -1.0;
+      O.accumulate = 1;
+      DF_LAUNCH(DF_KERNEL_BUILD, dfk::launch_gemm(A, Bm, O, 1, c->stream), "panel update launch");
+    }
+    // L_{>k,k} = A_{>k,k} L_kk^-T, through the panel buffer (the product reads the block it replaces)
+    const dfk::OpMap A = dfk::op_map(L + r0 * n + k0, m, n, kb, 1);
+    const dfk::OpMap Bm = dfk::op_map(linv + k * nb * nb, kb, nb, kb, 1);
+    DF_LAUNCH(DF_KERNEL_BUILD, dfk::launch_gemm(A, Bm, dfk::out_plain(panel, m, kb, nb), 1, c->stream),
+              "panel solve launch");
+    DF_LAUNCH(DF_KERNEL_OTHER,
+              hipMemcpy2DAsync(L + r0 * n + k0, n * sizeof(double), panel, nb * sizeof(double), kb * sizeof(double),
+                               m, hipMemcpyDeviceToDevice, c->stream),
+              "panel copy");
+  }
+  DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_zero_upper(L, n, c->stream), "zero launch");
+  // forward substitution by block rows: B_k = L_kk^-1 (E_k - L_{k,<k} B_{<k})
+  for (int64_t k = 0; k < p.nblk; ++k) {
+    const int64_t k0 = k * nb, kb = std::min(nb, n - k0);
+    DF_LAUNCH(DF_KERNEL_OTHER,
+              hipMemcpyAsync(T, eri3 + k0 * npair, dbytes(kb * npair), hipMemcpyDeviceToDevice, c->stream),
+              "block row copy");
+    if (k0 > 0) {
+      // the contraction over the k earlier (full) blocks, one 64-bit-strided slab per block
+      dfk::OpMap A = dfk::op_map(L + k0 * n, kb, n, nb, 1);
+      A.kb_n = k;
+      A.s_kb = nb;
+      dfk::OpMap Bm = dfk::op_map(B, npair, 1, nb, npair);
+      Bm.kb_n = k;
+      Bm.s_kb = nb * npair;
+      dfk::OutMap O = dfk::out_plain(T, kb, npair, npair);
+      O.alpha = -1.0;
+      O.accumulate = 1;
+      DF_LAUNCH(DF_KERNEL_BUILD, dfk::launch_gemm(A, Bm, O, 1, c->stream), "substitution update launch");
+    }
+    const dfk::OpMap A = dfk::op_map(linv + k * nb * nb, kb, nb, kb, 1);
+    const dfk::OpMap Bm = dfk::op_map(T, npair, 1, kb, npair);
+    DF_LAUNCH(DF_KERNEL_BUILD,
+              dfk::launch_gemm(A, Bm, dfk::out_plain(B + k0 * npair, kb, npair, npair), 1, c->stream),
+              "block solve launch");
+  }
+  return DF_OK;
+}
+
+df_status df_embed_cholesky(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const double* M, int64_t nemb,
+                            double* Be, int flags) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (df_status s = check_core(c, B, naux, nao)) return s;
+  if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_embed_cholesky takes no flags");
+  if (nemb < 0 || nemb > kMaxNao) return fail(c, DF_ERR_SHAPE, "nemb must be in [0, 46340]");
+  if (nemb > 0 && (!M || !Be)) return fail(c, DF_ERR_ARG, "M and Be are required");
+  const int64_t npair = nao * (nao + 1) / 2, npe = nemb * (nemb + 1) / 2;
+  std::vector<Range> rs = {{B, dbytes(naux * npair), "B", false},
+                           {M, dbytes(nao * nemb), "M", false},
+                           {Be, dbytes(naux * npe), "Be", true}};
+  Plan pl;
+  const EmbedPlan p = plan_embed(pl, naux, nao, nemb);
+  if (nemb > 0) {
+    if (!check_overlap(c, rs)) return DF_ERR_ARG;
+    if (df_status s = need_ws(c, pl.total)) return s;
+    rs.push_back({c->ws, pl.total, "workspace", true});
+  }
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (nemb == 0) return DF_OK;
+  if (df_status s = enter(c)) return s;
+  double* mpad = (double*)(c->ws + p.mpad);
+  double* X = (double*)(c->ws + p.x);
+  double* Y = (double*)(c->ws + p.y);
+  const ColBlock blk{M, nemb, nemb, 0};
+  if (df_status s = pad_operand(c, mpad, nao, nemb, &blk, 1)) return s;
+  for (int64_t p0 = 0; p0 < naux; p0 += p.chunk) {
+    const int64_t pc = std::min(p.chunk, naux - p0);
+    if (df_status s = run_half(c, B + p0 * npair, pc, nao, mpad, nemb, out_pmajor(X, pc, nao, nemb, nemb)))
+      return s;
+    if (df_status s = run_mo_pmajor(c, M, nemb, X, pc, nao, nemb, Y)) return s;
+    DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_pack_lower(Y, pc, nemb, Be + p0 * npe, c->stream), "pack launch");
+  }
+  return DF_OK;
 }
 
 df_status df_step(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const double* Cocc, int64_t nocc,

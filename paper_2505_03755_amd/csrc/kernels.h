@@ -117,6 +117,16 @@ hipError_t launch_coulomb(const double* B, int64_t naux, int64_t nao, const doub
 hipError_t launch_fill_zero(double* p, int64_t n, hipStream_t s);
 // J[z][i][j] = J[z][j][i] = Jp[z][pair(i, j)] for nz packed symmetric matrices
 hipError_t launch_unpack_sym(const double* Jp, int64_t nz, int64_t nao, double* J, hipStream_t s);
+// Diagonal-block edge of the blocked metric Cholesky.
+constexpr int kCholNB = 128;
+// Factor the kb x kb block at A (row stride lda; kb <= kCholNB) in place: lower triangle = its
+// Cholesky factor, strictly upper part zeroed; Linv [kCholNB][kCholNB] = the factor's inverse
+// (lower).  info: 0 written when `first`, then k0 + j + 1 for a pivot j that is not positive
+// unless an earlier one is recorded.  One workgroup.
+hipError_t launch_chol_block(double* A, int64_t lda, int kb, double* Linv, int* info, int64_t k0, bool first,
+                             hipStream_t s);
+// A[i][j] = 0 for j > i (n x n, row major)
+hipError_t launch_zero_upper(double* A, int64_t n, hipStream_t s);
 // Ap[z][pair(i, j)] = A[z][i][j] for i >= j: the lower triangles of nz n x n matrices, packed
 hipError_t launch_pack_lower(const double* A, int64_t nz, int64_t n, double* Ap, hipStream_t s);
 // p[z*s_z + i] = 0 for z < nz, i < n

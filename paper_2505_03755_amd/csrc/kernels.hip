@@ -851,6 +851,77 @@ __global__ void __launch_bounds__(256) pack_lower_kernel(const double* __restric
   Ap[idx] = A[z * n * n + i * n + j];
 }
 
+// Cholesky factor of one kb x kb diagonal block (kb <= kCholNB) of the metric, in LDS, and the
+// inverse of that factor.  A (row stride lda) holds the block with the earlier blocks' updates
+// already subtracted; its lower triangle is read.  Right-looking elimination: column j is scaled
+// by 1 / sqrt(pivot), then the trailing lower triangle takes the rank-1 update.  The inverse is
+// then found one column per thread by forward substitution: thread c keeps column c of L^-1 in
+// row c of the LDS array (the upper triangle, which the factor does not use), and reads the
+// factor from the strictly lower triangle and the diagonal from dg.  Outputs: the factor back to
+// A (lower, the block's strictly upper part zeroed) and L^-1 to Linv [kCholNB][kCholNB] (lower,
+// upper zeroed).  info: the first block (first != 0) writes 0; a block that meets a pivot that
+// is not positive writes k0 + j + 1 unless info already holds an earlier one.  After such a
+// pivot the block goes on with pivot 1 so that every wave finishes.
+__global__ void __launch_bounds__(256) chol_block_kernel(double* __restrict__ A, int64_t lda, int kb,
+                                                         double* __restrict__ Linv, int* info, int64_t k0,
+                                                         int first) {
+  __shared__ double S[kCholNB][kCholNB + 1];
+  __shared__ double dg[kCholNB];
+  __shared__ int bad;
+  const int t = threadIdx.x;
+  for (int idx = t; idx < kb * kb; idx += 256) {
+    const int i = idx / kb, j = idx % kb;
+    S[i][j] = j <= i ? A[i * lda + j] : 0.0;
+  }
+  if (t == 0) bad = -1;
+  __syncthreads();
+  for (int j = 0; j < kb; ++j) {
+    const double d = S[j][j];
+    const double sd = d > 0.0 ? sqrt(d) : 1.0;
+    const double r = 1.0 / sd;
+    __syncthreads();
+    if (t == 0) {
+      if (!(d > 0.0) && bad < 0) bad = j;
+      dg[j] = sd;
+    }
+    for (int i = j + 1 + t; i < kb; i += 256) S[i][j] *= r;
+    __syncthreads();
+    const int m = kb - j - 1;
+    for (int idx = t; idx < m * m; idx += 256) {
+      const int i = j + 1 + idx / m, c = j + 1 + idx % m;
+      if (c <= i) S[i][c] -= S[i][j] * S[c][j];
+    }
+    __syncthreads();
+  }
+  if (t < kb) {
+    const int c = t;
+    S[c][c] = 1.0 / dg[c];
+    for (int i = c + 1; i < kb; ++i) {
+      double acc = 0.0;
+      for (int j = c; j < i; ++j) acc += S[i][j] * S[c][j];
+      S[c][i] = -acc / dg[i];
+    }
+  }
+  __syncthreads();
+  for (int idx = t; idx < kb * kb; idx += 256) {
+    const int i = idx / kb, j = idx % kb;
+    A[i * lda + j] = j < i ? S[i][j] : (j == i ? dg[i] : 0.0);
+    Linv[i * kCholNB + j] = j <= i ? S[j][i] : 0.0;
+  }
+  if (t == 0) {
+    int cur = first ? 0 : *info;
+    if (cur == 0 && bad >= 0) cur = (int)(k0 + bad + 1);
+    *info = cur;
+  }
+}
+
+// A[i][j] = 0 for j > i, n x n
+__global__ void __launch_bounds__(256) zero_upper_kernel(double* A, int64_t n) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= n * n) return;
+  if (idx % n > idx / n) A[idx] = 0.0;
+}
+
 __global__ void __launch_bounds__(256) fill_zero_kernel(double* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) p[i] = 0.0;
@@ -1265,6 +1336,19 @@ hipError_t launch_unpack_sym(const double* Jp, int64_t nz, int64_t nao, double* 
   const int64_t npair = nao * (nao + 1) / 2, tot = nz * npair;
   if (tot <= 0) return hipSuccess;
   unpack_sym_kernel<<<(unsigned)cdiv(tot, 256), 256, 0, s>>>(Jp, nz, nao, npair, J);
+  return hipGetLastError();
+}
+
+hipError_t launch_chol_block(double* A, int64_t lda, int kb, double* Linv, int* info, int64_t k0, bool first,
+                             hipStream_t s) {
+  if (kb < 1 || kb > kCholNB) return hipErrorInvalidValue;
+  chol_block_kernel<<<1, 256, 0, s>>>(A, lda, kb, Linv, info, k0, first ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_upper(double* A, int64_t n, hipStream_t s) {
+  if (n <= 1) return hipSuccess;
+  zero_upper_kernel<<<(unsigned)cdiv(n * n, 256), 256, 0, s>>>(A, n);
   return hipGetLastError();
 }
 

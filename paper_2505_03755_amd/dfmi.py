@@ -32,6 +32,8 @@ DF_OP_SPLIT_MATMUL = 7
 DF_OP_STEP_SPLIT = 8
 DF_OP_STEP_BACKWARD_SPLIT = 9
 DF_OP_PPAA = 10
+DF_OP_BUILD_CHOLESKY = 11
+DF_OP_EMBED_CHOLESKY = 12
 
 DF_PAPA_FULL = 0x1
 DF_CALLER_X = 0x10
@@ -41,7 +43,7 @@ DF_BWD_GERI = 0x80
 DF_SPLIT_K_FP64 = 0x100
 
 KERNEL_KINDS = ["half_transform", "jvec", "coulomb", "k_syrk", "k_reduce", "mo_transform", "papa", "eri",
-                "other", "adjoint", "split"]
+                "other", "adjoint", "split", "build"]
 
 EXPORTED = ["df_create", "df_destroy", "df_last_error", "df_set_stream", "df_set_workspace",
             "df_set_timing", "df_timing_read", "df_workspace_size", "df_half_transform", "df_jk",
@@ -49,7 +51,7 @@ EXPORTED = ["df_create", "df_destroy", "df_last_error", "df_set_stream", "df_set
             "df_split_cholesky", "df_step_split", "df_batched_workspace_size", "df_batched_step",
             "df_set_autotune", "df_batched_tuning", "df_batched_set_tuning", "df_split_cholesky_t",
             "df_step_backward_split", "df_batched_split_workspace_size", "df_batched_step_split",
-            "df_ppaa"]
+            "df_ppaa", "df_build_cholesky", "df_embed_cholesky"]
 
 
 class DFError(RuntimeError):
@@ -97,6 +99,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         L.df_active_eri.argtypes = [vp, dp, i64, i64, dp, i64, dp, dp, i32]
         L.df_papa.argtypes = [vp, dp, i64, i64, dp, i64, dp, i64, dp, i64, dp, i32]
         L.df_ppaa.argtypes = [vp, dp, i64, i64, dp, i64, dp, i64, dp, i64, dp, i32]
+        L.df_build_cholesky.argtypes = [vp, dp, dp, i64, i64, dp, dp, vp, i32]
+        L.df_embed_cholesky.argtypes = [vp, dp, i64, i64, dp, i64, dp, i32]
         L.df_step.argtypes = [vp, dp, i64, i64, dp, i64, dp, dp, i64, dp, i64, dp, dp, dp, dp, dp, dp, dp, i32]
         L.df_step_backward.argtypes = [vp, dp, i64, i64, dp, i64, dp, i64, dp, dp, dp, dp, dp, dp, dp, i32]
         L.df_batched_workspace_size.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_size_t)]
@@ -341,6 +345,46 @@ def ppaa(B, nao: int, Cp, Cact, Cq=None, ctx: Context | None = None):
     ctx.check(ctx._lib.df_ppaa(ctx.handle, _ptr(B), naux, nao, _ptr(Cp), np_, _ptr(Cq), nq, _ptr(Cact), nac,
                                _ptr(out), 0))
     return out
+
+
+def build_cholesky(metric, eri3, nao: int, in_place: bool = False, check: bool = True,
+                   ctx: Context | None = None):
+    """df_build_cholesky: (L, B, info) with (P|Q) = L L^T and B = L^-1 (Q|mu nu), Eq. (cholesky).
+    in_place factors `metric` and overwrites `eri3` (returned as L and B).  info is a device int32
+    (0, or P + 1 of the first pivot that is not positive); with check it is read (waiting for the
+    stream) and a metric that is not positive definite raises."""
+    import torch
+    ctx = ctx or context(metric.device)
+    _check_tensor("metric", metric, ctx.device, (2,))
+    _check_tensor("eri3", eri3, ctx.device, (2,))
+    naux = metric.shape[0]
+    if tuple(metric.shape) != (naux, naux) or tuple(eri3.shape) != (naux, _npair(nao)):
+        raise ValueError("metric must be [naux, naux] and eri3 [naux, nao(nao+1)/2]")
+    Lt = metric if in_place else torch.empty_like(metric)
+    Bt = eri3 if in_place else torch.empty_like(eri3)
+    info = torch.empty(1, dtype=torch.int32, device=ctx.device)
+    ctx.prepare(DF_OP_BUILD_CHOLESKY, naux=naux, nao=nao)
+    ctx.check(ctx._lib.df_build_cholesky(ctx.handle, _ptr(metric), _ptr(eri3), naux, nao, _ptr(Lt), _ptr(Bt),
+                                         ctypes.c_void_p(info.data_ptr()), 0))
+    if check:
+        bad = int(info.item())
+        if bad:
+            raise ValueError(f"the metric is not positive definite (pivot of auxiliary index {bad - 1})")
+    return Lt, Bt, info
+
+
+def embed_cholesky(B, nao: int, M, ctx: Context | None = None):
+    """df_embed_cholesky: packed b^P in the basis of the columns of M [nao, nemb]."""
+    import torch
+    ctx = ctx or context(B.device)
+    for n, t in (("B", B), ("M", M)):
+        _check_tensor(n, t, ctx.device)
+    naux = _naux_of(B, nao)
+    nemb = M.shape[1]
+    Be = torch.empty((naux, _npair(nemb)), dtype=torch.float64, device=ctx.device)
+    ctx.prepare(DF_OP_EMBED_CHOLESKY, naux=naux, nao=nao, ncol=nemb)
+    ctx.check(ctx._lib.df_embed_cholesky(ctx.handle, _ptr(B), naux, nao, _ptr(M), nemb, _ptr(Be), 0))
+    return Be
 
 
 def step(B, nao: int, Cocc, Cact, Cp, w=None, outputs=None, keep_x=False, ctx: Context | None = None):

@@ -33,7 +33,7 @@ from dataclasses import dataclass
 import numpy as np
 
 __all__ = ["Workload", "WORKLOADS", "npair", "cholesky_vectors", "orbitals",
-           "symmetric_matrix", "two_body_density", "kappa", "fragment_densities",
+           "symmetric_matrix", "two_body_density", "kappa", "fragment_densities", "coulomb_metric",
            "device_cholesky_vectors", "directions"]
 
 
@@ -95,6 +95,14 @@ def fragment_densities(nemb: int, nocc: int, ndm: int, frag: int, seed: int = 0)
         s[s == 0] = 1.0
         out[k] = Q * s
     return out
+
+
+def coulomb_metric(naux: int, cond: float = 1e6, seed: int = 0) -> np.ndarray:
+    """Symmetric positive definite N_aux x N_aux stand-in for the metric (P|Q): a seeded random
+    orthogonal basis with eigenvalues spread geometrically from 1 down to 1/cond."""
+    Q = np.linalg.qr(_rng(seed, 7).standard_normal((naux, naux)))[0]
+    A = (Q * np.geomspace(1.0, 1.0 / cond, naux)) @ Q.T
+    return (A + A.T) * 0.5
 
 
 def directions(n_dir: int, shape, seed: int = 0) -> np.ndarray:

@@ -140,6 +140,26 @@ def test_ppaa_argument_errors(L, ctx):
     assert dfmi.workspace_size(dfmi.DF_OP_PPAA, naux=10, nao=7, nac=2, np=7, nq=3) < n
 
 
+def test_build_and_embed_argument_errors(L, ctx):
+    M, E, Lo, B, info = fake(1 << 30), fake(2 << 30), fake(3 << 30), fake(4 << 30), fake(5 << 30)
+    assert L.df_build_cholesky(ctx, M, E, 300, 20, Lo, B, None, 0) == dfmi.DF_ERR_ARG      # no info
+    assert L.df_build_cholesky(ctx, M, E, 0, 20, Lo, B, info, 0) == dfmi.DF_ERR_SHAPE
+    assert L.df_build_cholesky(ctx, M, E, 300, 20, Lo, B, info, 1) == dfmi.DF_ERR_UNSUPPORTED
+    assert L.df_build_cholesky(ctx, M, E, 300, 20, E, B, info, 0) == dfmi.DF_ERR_ARG       # L overlaps eri3
+    assert L.df_build_cholesky(ctx, M, E, 300, 9000, Lo, B, info, 0) == dfmi.DF_ERR_SHAPE  # 128 npair >= 2^32
+    assert L.df_build_cholesky(ctx, M, E, 300, 20, Lo, B, info, 0) == dfmi.DF_ERR_WORKSPACE
+    assert L.df_build_cholesky(ctx, M, E, 300, 20, M, E, info, 0) == dfmi.DF_ERR_WORKSPACE  # in place is allowed
+    n = dfmi.workspace_size(dfmi.DF_OP_BUILD_CHOLESKY, naux=300, nao=20)
+    assert n >= (3 * 128 * 128 + 300 * 128 + 128 * 210) * 8
+    assert L.df_embed_cholesky(ctx, B, 30, 20, None, 5, E, 0) == dfmi.DF_ERR_ARG
+    assert L.df_embed_cholesky(ctx, B, 30, 20, M, -1, E, 0) == dfmi.DF_ERR_SHAPE
+    assert L.df_embed_cholesky(ctx, B, 30, 20, M, 5, E, 2) == dfmi.DF_ERR_UNSUPPORTED
+    assert L.df_embed_cholesky(ctx, B, 30, 20, M, 5, B, 0) == dfmi.DF_ERR_ARG              # Be overlaps B
+    assert L.df_embed_cholesky(ctx, B, 30, 20, M, 5, E, 0) == dfmi.DF_ERR_WORKSPACE
+    assert L.df_embed_cholesky(ctx, B, 30, 20, None, 0, None, 0) == dfmi.DF_OK
+    assert dfmi.workspace_size(dfmi.DF_OP_EMBED_CHOLESKY, naux=30, nao=20, ncol=5) >= 30 * 25 * 5 * 8
+
+
 def test_step_argument_errors(L, ctx):
     B, Co, Ca, Cp = fake(1 << 30), fake(2 << 30), fake(3 << 30), fake(4 << 30)
     J, K = fake(5 << 30), fake(6 << 30)
