@@ -1,4 +1,5 @@
-"""Graph capture and replay of library calls (df_batched_step, df_step, df_step_split).
+"""Graph capture and replay of library calls (df_batched_step, df_step, df_step_split, df_ppaa,
+df_build_cholesky).
 
 A call launches everything on the context's stream. Inside a call there is no allocation, no
 memset and no host synchronisation, so a call can be captured into a HIP graph and replayed.
@@ -114,3 +115,38 @@ def test_step_split_graph_replay():
         g.replay()
         torch.cuda.synchronize()
         same(out, ref)
+
+
+def test_ppaa_graph_replay():
+    nao, naux, nac = 60, 130, 5
+    t = [dev(a) for a in step_inputs(nao, naux, 10, nac, 7)]
+    g, out = capture(lambda: dfmi.ppaa(t[0], nao, t[3], t[2]))
+    for rep in range(3):
+        for x, a in zip(t, step_inputs(nao, naux, 10, nac, 30 + rep)):
+            x.copy_(dev(a))
+        ref = dfmi.ppaa(t[0], nao, t[3], t[2])
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        same(out, ref)
+
+
+def build_inputs(naux, nao, seed):
+    return dev(synth.coulomb_metric(naux, 1e4, seed=seed)), dev(synth.cholesky_vectors(naux, nao, 10.0, seed=seed))
+
+
+def test_build_cholesky_graph_replay():
+    """Forming B (out of place; the copies and the info write are part of the graph)."""
+    naux, nao = 300, 20
+    metric, E = build_inputs(naux, nao, 2)
+    g, out = capture(lambda: dfmi.build_cholesky(metric, E, nao, check=False))
+    for rep in range(3):
+        m2, e2 = build_inputs(naux, nao, 40 + rep)
+        metric.copy_(m2)
+        E.copy_(e2)
+        ref = dfmi.build_cholesky(metric, E, nao, check=False)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        same(out, ref)
+        assert int(out[2].item()) == 0
