@@ -230,9 +230,10 @@ df_status df_ppaa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
  *       whose pivot is not positive (the metric is not positive definite to working
  *       precision); L and B are then undefined.  It is written on the stream, so read it after
  *       the stream has drained.
- * The factorisation runs in 128-wide block columns, left-looking: each diagonal block takes the
- * earlier columns' update as a product, is factored and inverted by one workgroup, and the panel
- * below is multiplied by the inverted block.  The substitution runs in block rows,
+ * The factorisation runs in 128-wide block columns, right-looking: each diagonal block is
+ * factored and inverted by one workgroup, the panel below is multiplied by the inverted block,
+ * and the trailing matrix takes the panel's update as one product.  The metric's strictly upper
+ * part, when factored in place, is overwritten (zeroed at the end).  The substitution runs in block rows,
  * B_k = L_kk^-1 (E_k - L_{k,<k} B_{<k}), the update as one product over all earlier rows.
  * Requires 128 * npair < 2^32 and naux^2 < 2^32 (DF_ERR_SHAPE otherwise).
  * Errors: DF_ERR_ARG for NULL pointers or overlapping buffers other than the two in-place

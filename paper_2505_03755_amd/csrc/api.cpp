@@ -1102,30 +1102,16 @@ df_status df_build_cholesky(df_ctx* ctx, const double* metric, const double* eri
   if (L != metric)
     DF_LAUNCH(DF_KERNEL_OTHER, hipMemcpyAsync(L, metric, dbytes(n * n), hipMemcpyDeviceToDevice, c->stream),
               "metric copy");
-  // left-looking blocked Cholesky: block column k takes the earlier columns' updates, its
-  // diagonal block is factored (and inverted) in one workgroup, the panel below is solved
-  // against the inverted block
+  // right-looking blocked Cholesky: the diagonal block of column k (all earlier updates applied)
+  // is factored and inverted in one workgroup, the panel below is multiplied by the inverted
+  // block, and the trailing matrix takes the panel's update as one product over the whole square
+  // (its upper half is never read and is zeroed at the end)
   for (int64_t k = 0; k < p.nblk; ++k) {
     const int64_t k0 = k * nb, kb = std::min(nb, n - k0), r0 = k0 + kb, m = n - r0;
-    if (k0 > 0) {
-      const dfk::OpMap A = dfk::op_map(L + k0 * n, kb, n, k0, 1);
-      dfk::OutMap O = dfk::out_plain(L + k0 * n + k0, kb, kb, n);
-      O.alpha = -1.0;
-      O.accumulate = 1;
-      DF_LAUNCH(DF_KERNEL_BUILD, dfk::launch_gemm(A, A, O, 1, c->stream), "diagonal update launch");
-    }
     DF_LAUNCH(DF_KERNEL_BUILD,
               dfk::launch_chol_block(L + k0 * n + k0, n, (int)kb, linv + k * nb * nb, info, k0, k == 0, c->stream),
               "diagonal block launch");
     if (m == 0) continue;
-    if (k0 > 0) {
-      const dfk::OpMap A = dfk::op_map(L + r0 * n, m, n, k0, 1);
-      const dfk::OpMap Bm = dfk::op_map(L + k0 * n, kb, n, k0, 1);
-      dfk::OutMap O = dfk::out_plain(L + r0 * n + k0, m, kb, n);
-      O.alpha = -1.0;
-      O.accumulate = 1;
-      DF_LAUNCH(DF_KERNEL_BUILD, dfk::launch_gemm(A, Bm, O, 1, c->stream), "panel update launch");
-    }
     // L_{>k,k} = A_{>k,k} L_kk^-T, through the panel buffer (the product reads the block it replaces)
     const dfk::OpMap A = dfk::op_map(L + r0 * n + k0, m, n, kb, 1);
     const dfk::OpMap Bm = dfk::op_map(linv + k * nb * nb, kb, nb, kb, 1);
@@ -1135,6 +1121,11 @@ df_status df_build_cholesky(df_ctx* ctx, const double* metric, const double* eri
               hipMemcpy2DAsync(L + r0 * n + k0, n * sizeof(double), panel, nb * sizeof(double), kb * sizeof(double),
                                m, hipMemcpyDeviceToDevice, c->stream),
               "panel copy");
+    // A_{>k,>k} -= L_{>k,k} L_{>k,k}^T
+    dfk::OutMap O = dfk::out_plain(L + r0 * n + r0, m, m, n);
+    O.alpha = -1.0;
+    O.accumulate = 1;
+    DF_LAUNCH(DF_KERNEL_BUILD, dfk::launch_gemm(A, A, O, 1, c->stream), "trailing update launch");
   }
   DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_zero_upper(L, n, c->stream), "zero launch");
   // forward substitution by block rows: B_k = L_kk^-1 (E_k - L_{k,<k} B_{<k})
