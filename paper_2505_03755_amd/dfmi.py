@@ -79,7 +79,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         if _lib is not None:
             return _lib
         if not os.path.exists(path):
-            raise ImportError(f"{path} is not built (run __graft_entry__.build())")
+            raise ImportError(f"{path} is not built (run python -m paper_2505_03755_amd.build)")
         # torch brings its own HIP runtime (same soname as ROCm's).  Loading it first makes
         # libdfmi bind to that one runtime instead of pulling a second copy into the process.
         import torch  # noqa: F401
