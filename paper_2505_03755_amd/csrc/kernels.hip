@@ -886,10 +886,11 @@ __global__ void __launch_bounds__(256) chol_block_kernel(double* __restrict__ A,
     }
     for (int i = j + 1 + t; i < kb; i += 256) S[i][j] *= r;
     __syncthreads();
-    const int m = kb - j - 1;
-    for (int idx = t; idx < m * m; idx += 256) {
-      const int i = j + 1 + idx / m, c = j + 1 + idx % m;
-      if (c <= i) S[i][c] -= S[i][j] * S[c][j];
+    // trailing lower triangle: lane t % 64 takes columns c = j + 1 + (t % 64) + 64 q, the four
+    // wave-groups t / 64 take every fourth row i >= c
+    for (int c = j + 1 + (t & 63); c < kb; c += 64) {
+      const double lc = S[c][j];
+      for (int i = c + (t >> 6); i < kb; i += 4) S[i][c] -= S[i][j] * lc;
     }
     __syncthreads();
   }
