@@ -29,7 +29,7 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("naux,nao,cond", [(300, 20, 1e4), (128, 9, 1e6), (129, 13, 1e2), (57, 30, 1e6),
-                                           (1, 4, 1.0), (520, 33, 1e6)])
+                                           (1, 4, 1.0), (520, 33, 1e6), (200, 1, 1e3), (256, 2, 1e5)])
 def test_build_against_oracle(naux, nao, cond):
     metric = synth.coulomb_metric(naux, cond, seed=naux)
     E = synth.cholesky_vectors(naux, nao, 10.0, seed=naux + 1)
@@ -86,6 +86,15 @@ def test_embed_against_oracle(naux, nao, nemb):
     Be = dfmi.embed_cholesky(dev(B), nao, dev(M))
     torch.cuda.synchronize()
     assert rel(Be, OB.embed(B, nao, M)) <= TOL
+
+
+def test_embed_identity_is_exact():
+    """M = I: every product is by 1 or 0, so the embedded vectors are B bit for bit."""
+    naux, nao = 70, 37
+    B = dev(synth.cholesky_vectors(naux, nao, 10.0, seed=3))
+    Be = dfmi.embed_cholesky(B, nao, dev(np.eye(nao)))
+    torch.cuda.synchronize()
+    assert torch.equal(Be, B)
 
 
 def test_embed_in_chunks_sampled_rows():
