@@ -42,3 +42,12 @@ def test_fragment_densities_orthonormal():
     Cs = synth.fragment_densities(20, 5, 3, frag=2)
     for C in Cs:
         np.testing.assert_allclose(C.T @ C, np.eye(5), atol=1e-13)
+
+
+def test_coulomb_metric_is_spd_with_the_requested_condition():
+    M = synth.coulomb_metric(50, 1e5, seed=3)
+    assert np.array_equal(M, M.T)
+    w = np.linalg.eigvalsh(M)
+    assert w[0] > 0
+    assert np.isclose(w[-1] / w[0], 1e5, rtol=1e-6)
+    assert np.array_equal(M, synth.coulomb_metric(50, 1e5, seed=3))
