@@ -31,7 +31,15 @@
  *  - Calls are asynchronous on the context's stream: they return once the work is
  *    enqueued, and every buffer must stay valid until the stream has drained.
  *    Two calls that share one context (and hence one workspace) must not overlap.
- *  - Outputs are overwritten.  Inputs, outputs and the workspace must not overlap.
+ *  - Outputs are overwritten, or, with DF_ACCUMULATE on the calls that take it, added to
+ *    (out += result): the sums over P of Eqs. (J_2)-(K_2) and of the ERI blocks can then be
+ *    accumulated over blocks of auxiliary rows, as the paper does with its N_blk blocks (Sec.
+ *    "Analysis of computational bottlenecks").  Inputs, outputs and the workspace must not
+ *    overlap.
+ *  - With DF_PREC_SPLIT the bulk products of df_half_transform, df_jk, df_active_eri and df_papa
+ *    run in split precision on the int8 matrix cores (see df_split_matmul below) against int8
+ *    planes of B registered once per context with df_register_split; df_set_split_slices sets
+ *    the slice count.  J-vectors and J stay FP64.
  *  - All arguments are checked before anything is enqueued; on an error return no
  *    output and no workspace byte has been touched, and df_last_error() describes it.
  *  - nocc = 0 or nac = 0 are valid and give zero-sized or zero-valued outputs;
@@ -93,6 +101,8 @@ typedef enum df_kernel_kind {
 
 /* Flag bits of calls. */
 #define DF_PAPA_FULL 0x1   /* df_papa: return (pu|qv) of Eq. (papa) instead of (pu|vw) */
+#define DF_ACCUMULATE 0x2  /* df_half_transform, df_jk, df_active_eri, df_papa: outputs += results */
+#define DF_PREC_SPLIT 0x4  /* the same four calls: bulk products in split precision (int8 slices) */
 
 /* Flag bits of df_dims.flags for df_workspace_size only. */
 #define DF_CALLER_X  0x10  /* DF_OP_STEP / DF_OP_STEP_BACKWARD / DF_OP_STEP_SPLIT: Xocc, Xact passed in */
@@ -100,6 +110,7 @@ typedef enum df_kernel_kind {
 #define DF_BWD_GK    0x40  /* DF_OP_STEP_BACKWARD(_SPLIT): gK is given */
 #define DF_BWD_GERI  0x80  /* DF_OP_STEP_BACKWARD(_SPLIT): geri is given */
 #define DF_SPLIT_K_FP64 0x100  /* df_batched_step_split: K in FP64 from the split-precision X_occ */
+#define DF_WEIGHTED  0x200  /* DF_OP_JK with DF_PREC_SPLIT: weights w are given (their K operand is split too) */
 
 /* Problem sizes for df_workspace_size; fields an operation does not use are ignored. */
 typedef struct df_dims {
@@ -143,8 +154,43 @@ df_status df_set_workspace(df_ctx* ctx, void* ptr, size_t bytes);
 df_status df_set_timing(df_ctx* ctx, int enable);
 df_status df_timing_read(df_ctx* ctx, double* ms, int64_t* launches, int n);
 
-/* Bytes of workspace that operation `op` needs for the sizes in *dims. */
+/* Bytes of workspace that operation `op` needs for the sizes in *dims, with no scratch limit.
+ * dims->flags carries the call's flags (DF_PAPA_FULL, DF_ACCUMULATE, DF_PREC_SPLIT with
+ * dims->nslice slices) and the DF_CALLER_X / DF_BWD_* bits below. */
 df_status df_workspace_size(df_op op, const df_dims* dims, size_t* bytes);
+
+/* The same for calls made on `ctx`: its scratch limit (df_set_scratch_limit) applies to
+ * DF_OP_STEP_BACKWARD, and with DF_PREC_SPLIT a dims->nslice of 0 stands for the context's slice
+ * count.  DF_ERR_WORKSPACE when the scratch limit is below the smallest workspace the operation
+ * can run in (one auxiliary row per chunk). */
+df_status df_workspace_query(df_ctx* ctx, df_op op, const df_dims* dims, size_t* bytes);
+
+/* Bound on the workspace of df_step_backward, in bytes (0: no bound, the default).  With a bound
+ * the adjoint runs over the auxiliary index in chunks of rows: per chunk it forms (or, when the
+ * caller passes them, reads) the half transforms of those rows and the products that need them,
+ * and it accumulates the chunk's part of dCocc and dCact in a fixed order.  So the
+ * half-transformed tensor is recomputed chunk by chunk rather than stored whole when it does not
+ * fit (Sec. "Analysis of computational bottlenecks": blocking along P bounds the peak memory).
+ * The chunk is the most rows whose workspace stays within the bound; df_backward_chunk reports
+ * it.  Results agree with the unbounded call up to FP64 rounding order. */
+df_status df_set_scratch_limit(df_ctx* ctx, size_t bytes);
+
+/* Rows of the auxiliary index per chunk that df_step_backward on `ctx` uses for these sizes
+ * (dims as for DF_OP_STEP_BACKWARD); *rows = naux without a bound.  DF_ERR_WORKSPACE as in
+ * df_workspace_query. */
+df_status df_backward_chunk(df_ctx* ctx, const df_dims* dims, int64_t* rows);
+
+/* Slice count of DF_PREC_SPLIT calls on this context (in [4, 8], default 7). */
+df_status df_set_split_slices(df_ctx* ctx, int nslice);
+
+/* Registers the int8 planes Bs and exponents Be that df_split_cholesky made from B (with
+ * `nslice` slices) for DF_PREC_SPLIT calls on this context.  A call with DF_PREC_SPLIT uses the
+ * registration whose B pointer, naux and nao equal its own and whose nslice is the context's
+ * slice count; without one it fails with DF_ERR_ARG.  Registering the same (B, naux, nao,
+ * nslice) again replaces the planes; Bs = NULL removes that registration.  The buffers stay
+ * caller-owned and must stay valid while registered.  At most 16 registrations. */
+df_status df_register_split(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const int8_t* Bs,
+                            const int* Be, int nslice);
 
 /*
  * Half transform, Eq. (ao2mo_1):       X[P][mu][c] = sum_nu b^P_{mu nu} C[nu][c]
@@ -154,7 +200,10 @@ df_status df_workspace_size(df_op op, const df_dims* dims, size_t* bytes);
  *   C  [nao][ncol]        coefficients (input), ncol >= 1
  *   X  [naux][nao][ncol]  output; the untransformed AO index comes first, as in b^P_{e2 p1}
  *   C2 [nao][n2], Y [naux][n2][ncol]  both NULL (n2 = 0) or both given
- * Workspace: df_workspace_size(DF_OP_HALF_TRANSFORM, {naux, nao, ncol}) (a zero-padded copy of C).
+ * flags: DF_ACCUMULATE (X += b^P C, Y += C2^T (b^P C)), DF_PREC_SPLIT (both products from int8
+ *   slices: rows (P, mu) of b^P against rows c of C; rows p of C2 against rows (P, c) of X).
+ * Workspace: df_workspace_size(DF_OP_HALF_TRANSFORM, {naux, nao, ncol, n2, flags, nslice})
+ * (a zero-padded copy of C; with both flags set and C2, also the new X before it is added).
  */
 df_status df_half_transform(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
                             const double* C, int64_t ncol, double* X,
@@ -170,7 +219,9 @@ df_status df_half_transform(df_ctx* ctx, const double* B, int64_t naux, int64_t 
  *   w    [ndm][nocc]       signed occupation weights, or NULL for all ones
  *   J, K [ndm][nao][nao]   outputs (symmetric, both triangles written); either may be NULL
  *   v    [ndm][naux]       output, or NULL
- * Workspace: df_workspace_size(DF_OP_JK, {naux, nao, ndm, nocc}).
+ * flags: DF_ACCUMULATE (J, K, v += the results); DF_PREC_SPLIT (X_k = b^P C_k and every K_k from
+ *   int8 slices; v and J in FP64 from that X).
+ * Workspace: df_workspace_size(DF_OP_JK, {naux, nao, ndm, nocc, flags, nslice}).
  */
 df_status df_jk(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int64_t ndm,
                 const double* Cocc, int64_t nocc, const double* w,
@@ -180,7 +231,9 @@ df_status df_jk(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int64_t
  * Active-space ERIs:  b_uv[P][u][v] = (Cact^T b^P Cact)_{uv},
  *                     eri[u][v][w][x] = sum_P b_uv[P][u][v] b_uv[P][w][x]
  *   Cact [nao][nac] (input); eri [nac]^4 (output); buv [naux][nac][nac] (output or NULL)
- * Workspace: df_workspace_size(DF_OP_ACTIVE_ERI, {naux, nao, nac}).
+ * flags: DF_ACCUMULATE (eri, buv += the results); DF_PREC_SPLIT (b^P Cact, b_uv and eri from int8
+ *   slices).
+ * Workspace: df_workspace_size(DF_OP_ACTIVE_ERI, {naux, nao, nac, flags, nslice}).
  */
 df_status df_active_eri(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
                         const double* Cact, int64_t nac, double* eri, double* buv, int flags);
@@ -192,7 +245,9 @@ df_status df_active_eri(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
  *   DF_PAPA_FULL:  out[p][u][q][v] = (pu|qv) = sum_P b_pu[P][p][u] b_qv[P][q][v]   (Eq. papa)
  *                  with b_qv[P] = Cq^T b^P Cact;  out is [np][nac][nq][nac]
  *   Cp [nao][np], Cact [nao][nac], Cq [nao][nq] (inputs)
- * Workspace: df_workspace_size(DF_OP_PAPA, {naux, nao, nac, np, nq, flags}).
+ * flags: DF_PAPA_FULL (above), DF_ACCUMULATE (out += the result), DF_PREC_SPLIT (b^P Cact, the
+ *   second transforms and the contraction over P from int8 slices).
+ * Workspace: df_workspace_size(DF_OP_PAPA, {naux, nao, nac, np, nq, flags, nslice}).
  */
 df_status df_papa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
                   const double* Cp, int64_t np, const double* Cact, int64_t nac,
@@ -282,7 +337,9 @@ df_status df_step(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
  *   Xocc, Xact: the half transforms from df_step (both or neither; one of zero size may be
  *            NULL); both NULL recomputes them
  *   dCocc [nao][nocc], dCact [nao][nac]: outputs (overwritten)
- * Workspace: df_workspace_size(DF_OP_STEP_BACKWARD, {naux, nao, 1, nocc, nac,
+ * With a scratch limit on the context (df_set_scratch_limit) the auxiliary rows run in chunks,
+ * each chunk's half transforms recomputed (or read from Xocc, Xact) into bounded workspace.
+ * Workspace: df_workspace_query(ctx, DF_OP_STEP_BACKWARD, {naux, nao, 1, nocc, nac,
  *            flags = DF_BWD_GJ|DF_BWD_GK|DF_BWD_GERI for the given cotangents, | DF_CALLER_X}).
  */
 df_status df_step_backward(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,

@@ -35,6 +35,18 @@ struct df_ctx {
   // autotuning of df_batched_step (df_set_autotune): configuration per problem-group shape
   bool autotune = false;
   std::map<std::string, BatchedTune> tune;
+  // split precision of the DF_PREC_SPLIT calls: slice count and the registered planes of B
+  struct SplitReg {
+    const double* B;
+    int64_t naux, nao;
+    const int8_t* Bs;
+    const int* Be;
+    int nslice;
+  };
+  int nslice = 7;
+  std::vector<SplitReg> splits;
+  // bound on the workspace of df_step_backward (0: none)
+  size_t scratch_limit = 0;
 };
 
 namespace {
@@ -90,59 +102,10 @@ struct Plan {
 };
 
 // Offsets of the workspace pieces of each operation.
-struct JkPlan {
-  size_t ccat, x, kpart, vtmp;
-  int nsplit;
-};
-struct HalfPlan {
-  size_t cpad;
-};
-struct ActPlan {
-  size_t cpad, x, buv;
-};
-struct PapaPlan {
-  size_t cpad, x, bpu, bvw, bqv;
-};
 struct StepPlan {
   size_t ccat, xo, xa, kpart, vtmp, bpu, buv;
   int nsplit;
 };
-
-// ccat / cpad: the dense operand of the half transform, [kpad16(nao)][ncol] with zero pad rows.
-JkPlan plan_jk(Plan& pl, int64_t naux, int64_t nao, int64_t ndm, int64_t nocc) {
-  JkPlan p{};
-  const int64_t ncol = ndm * nocc;
-  p.ccat = pl.take(dfk::kpad16(nao) * ncol);
-  p.x = pl.take(naux * nao * ncol);
-  p.nsplit = dfk::syrk_splits(nao, naux, ndm);
-  p.kpart = pl.take((int64_t)p.nsplit * ndm * nao * nao);
-  p.vtmp = pl.take(ndm * naux);
-  return p;
-}
-
-HalfPlan plan_half(Plan& pl, int64_t nao, int64_t ncol) {
-  HalfPlan p{};
-  p.cpad = pl.take(dfk::kpad16(nao) * ncol);
-  return p;
-}
-
-ActPlan plan_act(Plan& pl, int64_t naux, int64_t nao, int64_t nac) {
-  ActPlan p{};
-  p.cpad = pl.take(dfk::kpad16(nao) * nac);
-  p.x = pl.take(naux * nao * nac);
-  p.buv = pl.take(naux * nac * nac);
-  return p;
-}
-
-PapaPlan plan_papa(Plan& pl, int64_t naux, int64_t nao, int64_t nac, int64_t np, int64_t nq, bool full) {
-  PapaPlan p{};
-  p.cpad = pl.take(dfk::kpad16(nao) * nac);
-  p.x = pl.take(naux * nao * nac);
-  p.bpu = pl.take(naux * np * nac);
-  p.bvw = pl.take(full ? 0 : naux * nac * nac);
-  p.bqv = pl.take(full ? naux * nq * nac : 0);
-  return p;
-}
 
 // Workspace of df_ppaa.  The uv pairs run in chunks of `chunk`: W_uv [chunk][npair] and
 // T_uv = W_uv Cq [chunk][nao][nq] are the per-chunk buffers, bounded by kPpaaChunkBytes.
@@ -226,36 +189,59 @@ StepPlan plan_step(Plan& pl, int64_t naux, int64_t nao, int64_t nocc, int64_t na
   return p;
 }
 
-// Workspace of df_step_backward.  flags: DF_BWD_GJ / DF_BWD_GK / DF_BWD_GERI say which cotangents
-// are given, DF_CALLER_X that the forward's half transforms are passed in.
+// Workspace of df_step_backward for chunks of `chunk` auxiliary rows.  flags: DF_BWD_GJ /
+// DF_BWD_GK / DF_BWD_GERI say which cotangents are given, DF_CALLER_X that the forward's half
+// transforms are passed in.  Per chunk: X_occ and X_act of its rows (when recomputed), Y_P = S X_P
+// [P][kpad16(nao)][nocc], b_uv and Z; the split partials are sized for the most splits any chunk
+// can take, so the total grows with the chunk.
 struct BwdPlan {
   size_t ccat, xo, xa, g, u, upart, M, S, Y, kpart, Gs, buv, Z, apart;
-  int nsk, nsa;
+  int64_t chunk;
 };
 
-BwdPlan plan_backward(Plan& pl, int64_t naux, int64_t nao, int64_t nocc, int64_t nac, int flags) {
+BwdPlan plan_backward(Plan& pl, int64_t naux, int64_t nao, int64_t nocc, int64_t nac, int flags, int64_t chunk) {
   BwdPlan p{};
   const bool gj = flags & DF_BWD_GJ, gk = flags & DF_BWD_GK, ge = flags & DF_BWD_GERI;
   const bool cx = flags & DF_CALLER_X;
-  const bool need_xo = gk && nocc > 0 && !cx, need_xa = ge && nac > 0 && !cx;
-  const int64_t npair = nao * (nao + 1) / 2;
+  const bool do_k = gk && nocc > 0, do_e = ge && nac > 0;
+  const bool need_xo = do_k && !cx, need_xa = do_e && !cx;
+  const int64_t npair = nao * (nao + 1) / 2, ch = chunk;
+  p.chunk = chunk;
   p.ccat = pl.take(dfk::kpad16(nao) * ((need_xo ? nocc : 0) + (need_xa ? nac : 0)));
-  p.xo = pl.take(need_xo ? naux * nao * nocc : 0);
-  p.xa = pl.take(need_xa ? naux * nao * nac : 0);
+  p.xo = pl.take(need_xo ? ch * nao * nocc : 0);
+  p.xa = pl.take(need_xa ? ch * nao * nac : 0);
   p.g = pl.take(gj && nocc > 0 ? npair : 0);
   p.u = pl.take(gj && nocc > 0 ? naux : 0);
   p.upart = pl.take(gj && nocc > 0 ? (int64_t)dfk::jvec_packed_chunks() * naux : 0);
   p.M = pl.take(gj && nocc > 0 ? nao * nao : 0);
-  p.S = pl.take(gk && nocc > 0 ? nao * nao : 0);
-  p.Y = pl.take(gk && nocc > 0 ? naux * dfk::kpad16(nao) * nocc : 0);   // [P][kpad16(nao)][nocc]
-  p.nsk = gk && nocc > 0 ? dfk::half_reduce_splits(nao, nocc, naux) : 1;
-  p.kpart = pl.take(gk && nocc > 0 ? (int64_t)p.nsk * nao * nocc : 0);
-  p.Gs = pl.take(ge && nac > 0 ? nac * nac * nac * nac : 0);
-  p.buv = pl.take(ge && nac > 0 ? naux * nac * nac : 0);
-  p.Z = pl.take(ge && nac > 0 ? naux * nac * nac : 0);
-  p.nsa = ge && nac > 0 ? dfk::gemm_splits(nao, nac, (naux * nac + 15) / 16) : 1;
-  p.apart = pl.take(ge && nac > 0 && p.nsa > 1 ? (int64_t)p.nsa * nao * nac : 0);
+  p.S = pl.take(do_k ? nao * nao : 0);
+  p.Y = pl.take(do_k ? ch * dfk::kpad16(nao) * nocc : 0);
+  p.kpart = pl.take(do_k ? (int64_t)dfk::half_reduce_splits_bound(nao, nocc, ch) * nao * nocc : 0);
+  p.Gs = pl.take(do_e ? nac * nac * nac * nac : 0);
+  p.buv = pl.take(do_e ? ch * nac * nac : 0);
+  p.Z = pl.take(do_e ? ch * nac * nac : 0);
+  p.apart = pl.take(do_e ? (int64_t)dfk::gemm_splits_bound(nao, nac, (ch * nac + 15) / 16) * nao * nac : 0);
   return p;
+}
+
+// Auxiliary rows per chunk of df_step_backward under a workspace bound: all of them without a
+// bound, else the most whose workspace fits (the workspace grows with the chunk); 0 when not even
+// one row fits.
+int64_t backward_rows(int64_t naux, int64_t nao, int64_t nocc, int64_t nac, int flags, size_t limit) {
+  if (limit == 0) return naux;
+  auto need = [&](int64_t ch) {
+    Plan pl;
+    plan_backward(pl, naux, nao, nocc, nac, flags, ch);
+    return pl.total;
+  };
+  if (need(1) > limit) return 0;
+  int64_t lo = 1, hi = naux;   // need(lo) <= limit
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    if (need(mid) <= limit) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
 
 // ---- split precision ----
@@ -286,6 +272,115 @@ int slice_splits(int64_t tiles, int64_t nks) {
   if (ns < ns_cache) ns = ns_cache;
   if (ns < 1) ns = 1;
   return (int)ns;
+}
+
+// ---- plans of the four calls that take DF_ACCUMULATE and DF_PREC_SPLIT ----
+// Split-precision limits of these calls: every contraction (over nao, naux, or naux * nocc in
+// K's splits) fits the int32-exact split length, and the plane rows stay below 2^31.
+bool split_sizes_ok(int64_t naux, int64_t nao, int64_t rows) {
+  return nao <= 32768 && naux <= 32768 && dfk::rpad32(naux * nao) <= 0x7fffffffLL && dfk::rpad32(rows) <= 0x7fffffffLL;
+}
+
+// df_half_transform.  FP64: the zero-padded C.  Split: planes of the rows c of C and, with C2, of
+// the rows p of C2 and the rows (P, c) of X.  With DF_ACCUMULATE and C2, X of this call is
+// formed in `xnew` (Y needs it alone) and then added to X.
+struct HalfPlan {
+  size_t cpad, xnew;
+  SplitBuf cs, xs, c2s;
+};
+HalfPlan plan_half(Plan& pl, int64_t naux, int64_t nao, int64_t ncol, int64_t n2, int flags, int nslice) {
+  HalfPlan p{};
+  const bool acc = flags & DF_ACCUMULATE, sp = flags & DF_PREC_SPLIT;
+  p.cpad = pl.take(sp ? 0 : dfk::kpad16(nao) * ncol);
+  p.xnew = pl.take(acc && n2 > 0 ? naux * nao * ncol : 0);
+  if (sp) {
+    p.cs = take_split(pl, ncol, nao, nslice);
+    p.xs = take_split(pl, n2 > 0 ? naux * ncol : 0, nao, nslice);
+    p.c2s = take_split(pl, n2, nao, nslice);
+  }
+  return p;
+}
+
+// df_jk.  X = b^P [C_1 .. C_ndm] P-major [naux][nao][ndm*nocc]; v of this call in vtmp.  FP64: the
+// padded operand, the K split partials.  Split: planes of the rows (z, c) of the factors, planes of
+// every density's X_occ (rows m over (P, c)) and, with weights, of X diag(w) (xw) as the second
+// operand of each K product.
+struct JkPlan {
+  size_t ccat, x, kpart, vtmp, xw;
+  SplitBuf cs, xos, xws;
+  int64_t xplane;   // bytes of the planes of one density's X_occ
+  int nsplit;
+};
+JkPlan plan_jk(Plan& pl, int64_t naux, int64_t nao, int64_t ndm, int64_t nocc, bool weighted, int flags, int nslice) {
+  JkPlan p{};
+  const bool sp = flags & DF_PREC_SPLIT;
+  const int64_t ncol = ndm * nocc;
+  p.ccat = pl.take(sp ? 0 : dfk::kpad16(nao) * ncol);
+  p.x = pl.take(naux * nao * ncol);
+  p.vtmp = pl.take(ndm * naux);
+  if (!sp) {
+    p.nsplit = dfk::syrk_splits(nao, naux, ndm);
+  } else {
+    p.cs = take_split(pl, ncol, nao, nslice);
+    p.xplane = nocc > 0 ? dfk::split_plane_bytes(nao, naux * nocc, nslice) : 0;
+    p.xos.planes = pl.take((ndm * p.xplane + 7) / 8);
+    p.xos.ex = pl.take((ndm * nao * 4 + 7) / 8);
+    p.xw = pl.take(weighted ? naux * nao * ncol : 0);
+    p.xws.planes = pl.take(weighted ? (ndm * p.xplane + 7) / 8 : 0);
+    p.xws.ex = pl.take(weighted ? (ndm * nao * 4 + 7) / 8 : 0);
+    p.nsplit = nocc > 0 ? slice_splits(dfk::slice_gemm_tiles(nao, nao, true) * ndm,
+                                       dfk::slice_gemm_steps(dfk::kpad64(naux * nocc)))
+                        : 1;
+  }
+  p.kpart = pl.take((int64_t)p.nsplit * ndm * nao * nao);
+  return p;
+}
+
+// df_active_eri: X_act AO-major [nao][naux][nac], b_uv of this call.  Split: planes of the rows u
+// of Cact, of the rows (P, u) of X_act and of the rows uv of b_uv over P.
+struct ActPlan {
+  size_t cpad, x, buv;
+  SplitBuf cas, xas, buvs;
+};
+ActPlan plan_act(Plan& pl, int64_t naux, int64_t nao, int64_t nac, int flags, int nslice) {
+  ActPlan p{};
+  const bool sp = flags & DF_PREC_SPLIT;
+  p.cpad = pl.take(sp ? 0 : dfk::kpad16(nao) * nac);
+  p.x = pl.take(naux * nao * nac);
+  p.buv = pl.take(naux * nac * nac);
+  if (sp) {
+    p.cas = take_split(pl, nac, nao, nslice);
+    p.xas = take_split(pl, naux * nac, nao, nslice);
+    p.buvs = take_split(pl, nac * nac, naux, nslice);
+  }
+  return p;
+}
+
+// df_papa: X_act AO-major, b_pu and b_vw (default) or b_qv (DF_PAPA_FULL).  Split: planes of the
+// rows of Cact, Cp (and Cq), of the rows (P, u) of X_act and of the rows of b_pu and b_vw / b_qv
+// over P.
+struct PapaPlan {
+  size_t cpad, x, bpu, bvw, bqv;
+  SplitBuf cas, cps, cqs, xas, bpus, bvws, bqvs;
+};
+PapaPlan plan_papa(Plan& pl, int64_t naux, int64_t nao, int64_t nac, int64_t np, int64_t nq, int flags, int nslice) {
+  PapaPlan p{};
+  const bool full = flags & DF_PAPA_FULL, sp = flags & DF_PREC_SPLIT;
+  p.cpad = pl.take(sp ? 0 : dfk::kpad16(nao) * nac);
+  p.x = pl.take(naux * nao * nac);
+  p.bpu = pl.take(naux * np * nac);
+  p.bvw = pl.take(full ? 0 : naux * nac * nac);
+  p.bqv = pl.take(full ? naux * nq * nac : 0);
+  if (sp) {
+    p.xas = take_split(pl, naux * nac, nao, nslice);
+    p.cps = take_split(pl, np, nao, nslice);
+    p.bpus = take_split(pl, np * nac, naux, nslice);
+    p.cas = take_split(pl, nac, nao, nslice);
+    p.bvws = take_split(pl, full ? 0 : nac * nac, naux, nslice);
+    p.cqs = take_split(pl, full ? nq : 0, nao, nslice);
+    p.bqvs = take_split(pl, full ? nq * nac : 0, naux, nslice);
+  }
+  return p;
 }
 
 struct SplitMmPlan {
@@ -341,7 +436,7 @@ struct BwdSplitPlan {
 BwdSplitPlan plan_backward_split(Plan& pl, int64_t naux, int64_t nao, int64_t nocc, int64_t nac, int flags,
                                  int nslice) {
   BwdSplitPlan p{};
-  p.f = plan_backward(pl, naux, nao, nocc, nac, (flags & ~DF_BWD_GK) | DF_CALLER_X);
+  p.f = plan_backward(pl, naux, nao, nocc, nac, (flags & ~DF_BWD_GK) | DF_CALLER_X, naux);
   p.nsk = 1;
   if ((flags & DF_BWD_GK) && nocc > 0) {
     p.S = pl.take(nao * nao);
@@ -643,13 +738,14 @@ dfk::OutMap out_split(double* Xo, double* Xa, int64_t naux, int64_t nao, int64_t
   return o;
 }
 
-// out[P][p][u] = sum_mu Cl[mu][p] Xa[mu][P][u]  (Cl is [nao][nl], Xa AO-major [nao][naux][nr])
-df_status run_mo(df_ctx* c, const double* Cl, int64_t nl, const double* Xa, int64_t naux, int64_t nao, int64_t nr,
-                 double* out) {
+// out[P][p][u] = sum_mu Cl[mu][p] Xa[mu][P][u]  (Cl is [nao][nl], Xa AO-major: rows mu of stride ld,
+// columns (P, u) for P < naux)
+df_status run_mo_ld(df_ctx* c, const double* Cl, int64_t nl, const double* Xa, int64_t ld, int64_t naux, int64_t nao,
+                    int64_t nr, double* out) {
   if (nl == 0 || nr == 0) return DF_OK;
   const int kind = DF_KERNEL_MO_TRANSFORM;
   const dfk::OpMap A = dfk::op_map(Cl, nl, 1, nao, nl);
-  const dfk::OpMap Bm = dfk::op_map(Xa, naux * nr, 1, nao, naux * nr);
+  const dfk::OpMap Bm = dfk::op_map(Xa, naux * nr, 1, nao, ld);
   dfk::OutMap O = dfk::out_plain(out, nl, naux * nr, nr);
   O.nl = nr;
   O.s_nh = nl * nr;
@@ -657,15 +753,22 @@ df_status run_mo(df_ctx* c, const double* Cl, int64_t nl, const double* Xa, int6
   return DF_OK;
 }
 
-// Y[P][p][c] = sum_mu C2[mu][p] X[P][mu][c]  (X P-major [naux][nao][ncol]), batched over P
+// run_mo_ld for Xa AO-major [nao][naux][nr]
+df_status run_mo(df_ctx* c, const double* Cl, int64_t nl, const double* Xa, int64_t naux, int64_t nao, int64_t nr,
+                 double* out) {
+  return run_mo_ld(c, Cl, nl, Xa, naux * nr, naux, nao, nr, out);
+}
+
+// Y[P][p][c] (+)= sum_mu C2[mu][p] X[P][mu][c]  (X P-major [naux][nao][ncol]), batched over P
 df_status run_mo_pmajor(df_ctx* c, const double* C2, int64_t n2, const double* X, int64_t naux, int64_t nao,
-                        int64_t ncol, double* Y) {
+                        int64_t ncol, double* Y, int accumulate = 0) {
   if (n2 == 0 || ncol == 0) return DF_OK;
   const dfk::OpMap A = dfk::op_map(C2, n2, 1, nao, n2);
   dfk::OpMap Bm = dfk::op_map(X, ncol, 1, nao, ncol);
   Bm.s_z = nao * ncol;
   dfk::OutMap O = dfk::out_plain(Y, n2, ncol, ncol);
   O.s_z = n2 * ncol;
+  O.accumulate = accumulate;
   for (int64_t p0 = 0; p0 < naux; p0 += 65535) {
     const int64_t np_ = std::min<int64_t>(65535, naux - p0);
     dfk::OpMap Bp = Bm;
@@ -677,20 +780,21 @@ df_status run_mo_pmajor(df_ctx* c, const double* C2, int64_t n2, const double* X
   return DF_OK;
 }
 
-// out[m][n] = sum_P L[P][m] R[P][n]
+// out[m][n] (+)= sum_P L[P][m] R[P][n]
 df_status run_pgemm(df_ctx* c, int kind, const double* L, int64_t M, const double* R, int64_t N, int64_t naux,
-                    double* out) {
+                    double* out, int accumulate = 0) {
   if (M == 0 || N == 0) return DF_OK;
   const dfk::OpMap A = dfk::op_map(L, M, 1, naux, M);
   const dfk::OpMap Bm = dfk::op_map(R, N, 1, naux, N);
   dfk::OutMap O = dfk::out_plain(out, M, N, N);
+  O.accumulate = accumulate;
   DF_LAUNCH(kind, dfk::launch_gemm(A, Bm, O, 1, c->stream), "aux contraction launch");
   return DF_OK;
 }
 
-// K[z] = sum_P X_z[P] diag(w_z) X_z[P]^T with X_z[P][i][c] = X[P][i][z*nocc + c]  (w may be NULL)
+// K[z] (+)= sum_P X_z[P] diag(w_z) X_z[P]^T with X_z[P][i][c] = X[P][i][z*nocc + c]  (w may be NULL)
 df_status run_k(df_ctx* c, const double* X, const double* w, int64_t naux, int64_t nao, int64_t ldx,
-                int64_t nocc, int64_t nz, int nsplit, double* kpart, double* K) {
+                int64_t nocc, int64_t nz, int nsplit, double* kpart, double* K, int accumulate = 0) {
   dfk::OpMap A = dfk::op_map(X, nao, ldx, nocc, 1);
   A.kb_n = naux;
   A.s_kb = nao * ldx;
@@ -699,7 +803,63 @@ df_status run_k(df_ctx* c, const double* X, const double* w, int64_t naux, int64
   Bw.ks = w;
   Bw.s_ksz = nocc;
   DF_LAUNCH(DF_KERNEL_K_SYRK, dfk::launch_syrk_partial(A, Bw, nao, nz, nsplit, kpart, c->stream), "K tiles launch");
-  DF_LAUNCH(DF_KERNEL_K_REDUCE, dfk::launch_syrk_reduce(kpart, nsplit, nao, nz, K, c->stream), "K reduce launch");
+  DF_LAUNCH(DF_KERNEL_K_REDUCE, dfk::launch_syrk_reduce(kpart, nsplit, nao, nz, K, c->stream, accumulate),
+            "K reduce launch");
+  return DF_OK;
+}
+
+// ---- split-precision building blocks ----
+// Planes and exponents of a split operand in the workspace.
+struct SplitOp {
+  int8_t* planes;
+  int* ex;
+};
+SplitOp split_in(char* ws, const SplitBuf& b) { return SplitOp{(int8_t*)(ws + b.planes), (int*)(ws + b.ex)}; }
+
+// the rows of operand o (contraction length K) cut into int8 planes
+df_status split_of(df_ctx* c, const dfk::OpMap& o, int64_t K, int nslice, SplitOp d) {
+  DF_LAUNCH(DF_KERNEL_SPLIT, dfk::launch_split_rows(o, K, nslice, d.planes, d.ex, c->stream), "split launch");
+  return DF_OK;
+}
+
+// O(m, n) = sum_k a(m, k) b(n, k) from the planes of the M rows of a and the N rows of b (K <= 32768)
+df_status slice_product(df_ctx* c, int kind, SplitOp a, int64_t M, SplitOp b, int64_t N, int64_t K, int nslice,
+                        const dfk::OutMap& O) {
+  DF_LAUNCH(kind,
+            dfk::launch_slice_gemm(a.planes, a.ex, M, b.planes, b.ex, N, dfk::kpad64(K), nslice, O, false, 1, nullptr,
+                                   c->stream),
+            "slice product launch");
+  return DF_OK;
+}
+
+// Rows (P, mu) of b^P times C over nu (Eq. ao2mo_1) from the registered planes of B and the planes
+// of the ncol rows of C, written through OX (rows P * nao + mu, columns c).
+df_status split_half(df_ctx* c, const df_ctx::SplitReg& r, SplitOp cs, int64_t ncol, const dfk::OutMap& OX) {
+  DF_LAUNCH(DF_KERNEL_HALF_TRANSFORM,
+            dfk::launch_slice_gemm(r.Bs, r.Be, r.naux * r.nao, cs.planes, cs.ex, ncol, dfk::kpad64(r.nao), r.nslice, OX,
+                                   false, 1, nullptr, c->stream),
+            "slice product launch");
+  return DF_OK;
+}
+
+// The registered split of B for the context's slice count, or NULL.
+const df_ctx::SplitReg* find_split(const df_ctx* c, const double* B, int64_t naux, int64_t nao) {
+  for (const auto& r : c->splits)
+    if (r.B == B && r.naux == naux && r.nao == nao && r.nslice == c->nslice) return &r;
+  return nullptr;
+}
+
+// The split of B a DF_PREC_SPLIT call uses, with its planes appended to the call's input ranges.
+df_status split_for_call(df_ctx* c, const double* B, int64_t naux, int64_t nao, int64_t rows,
+                         const df_ctx::SplitReg** reg, std::vector<Range>& rs) {
+  *reg = find_split(c, B, naux, nao);
+  if (!*reg)
+    return fail(c, DF_ERR_ARG, "DF_PREC_SPLIT: no split of B with " + std::to_string(c->nslice) +
+                                   " slices is registered on this context (df_register_split)");
+  if (!split_sizes_ok(naux, nao, rows))
+    return fail(c, DF_ERR_SHAPE, "problem too large for the split path (nao, naux <= 32768, rows < 2^31)");
+  rs.push_back({(*reg)->Bs, (size_t)dfk::split_plane_bytes(naux * nao, nao, (*reg)->nslice), "Bs", false});
+  rs.push_back({(*reg)->Be, (size_t)naux * nao * 4, "Be", false});
   return DF_OK;
 }
 
@@ -789,8 +949,12 @@ df_status df_set_workspace(df_ctx* ctx, void* ptr, size_t bytes) {
   return DF_OK;
 }
 
-df_status df_workspace_size(df_op op, const df_dims* d, size_t* bytes) {
-  if (!d || !bytes) return DF_ERR_ARG;
+}  // extern "C"
+
+namespace {
+
+// Workspace bytes of `op` for the sizes in *d; `limit` bounds DF_OP_STEP_BACKWARD (0: none).
+df_status workspace_bytes(df_op op, const df_dims* d, size_t limit, size_t* bytes) {
   *bytes = 0;
   if (op == DF_OP_SPLIT_MATMUL) {
     if (d->m < 0 || d->n < 0 || d->k < 1 || d->nslice < 4 || d->nslice > 8) return DF_ERR_SHAPE;
@@ -802,14 +966,18 @@ df_status df_workspace_size(df_op op, const df_dims* d, size_t* bytes) {
   if (d->naux < 1 || d->nao < 1 || d->nao > kMaxNao) return DF_ERR_SHAPE;
   if (d->ndm < 0 || d->nocc < 0 || d->nac < 0 || d->np < 0 || d->nq < 0 || d->ncol < 0 || d->n2 < 0)
     return DF_ERR_SHAPE;
+  const bool split_flag = (d->flags & DF_PREC_SPLIT) != 0;
+  if ((split_flag || op == DF_OP_STEP_SPLIT || op == DF_OP_STEP_BACKWARD_SPLIT) && (d->nslice < 4 || d->nslice > 8))
+    return DF_ERR_SHAPE;
   Plan pl;
   switch (op) {
-    case DF_OP_HALF_TRANSFORM: plan_half(pl, d->nao, d->ncol); break;
-    case DF_OP_JK: plan_jk(pl, d->naux, d->nao, std::max<int64_t>(d->ndm, 1), d->nocc); break;
-    case DF_OP_ACTIVE_ERI: plan_act(pl, d->naux, d->nao, d->nac); break;
-    case DF_OP_PAPA:
-      plan_papa(pl, d->naux, d->nao, d->nac, d->np, d->nq, (d->flags & DF_PAPA_FULL) != 0);
+    case DF_OP_HALF_TRANSFORM: plan_half(pl, d->naux, d->nao, d->ncol, d->n2, d->flags, d->nslice); break;
+    case DF_OP_JK:
+      plan_jk(pl, d->naux, d->nao, std::max<int64_t>(d->ndm, 1), d->nocc, (d->flags & DF_WEIGHTED) != 0, d->flags,
+              d->nslice);
       break;
+    case DF_OP_ACTIVE_ERI: plan_act(pl, d->naux, d->nao, d->nac, d->flags, d->nslice); break;
+    case DF_OP_PAPA: plan_papa(pl, d->naux, d->nao, d->nac, d->np, d->nq, d->flags, d->nslice); break;
     case DF_OP_BUILD_CHOLESKY: plan_build(pl, d->naux, d->nao); break;
     case DF_OP_EMBED_CHOLESKY: plan_embed(pl, d->naux, d->nao, d->ncol); break;
     case DF_OP_PPAA:
@@ -818,15 +986,16 @@ df_status df_workspace_size(df_op op, const df_dims* d, size_t* bytes) {
     case DF_OP_STEP:
       plan_step(pl, d->naux, d->nao, d->nocc, d->nac, d->np, (d->flags & DF_CALLER_X) != 0);
       break;
-    case DF_OP_STEP_BACKWARD:
-      plan_backward(pl, d->naux, d->nao, d->nocc, d->nac, d->flags);
+    case DF_OP_STEP_BACKWARD: {
+      const int64_t rows = backward_rows(d->naux, d->nao, d->nocc, d->nac, d->flags, limit);
+      if (rows == 0) return DF_ERR_WORKSPACE;
+      plan_backward(pl, d->naux, d->nao, d->nocc, d->nac, d->flags, rows);
       break;
+    }
     case DF_OP_STEP_SPLIT:
-      if (d->nslice < 4 || d->nslice > 8) return DF_ERR_SHAPE;
       plan_step_split(pl, d->naux, d->nao, d->nocc, d->nac, d->np, d->nslice, (d->flags & DF_CALLER_X) != 0);
       break;
     case DF_OP_STEP_BACKWARD_SPLIT:
-      if (d->nslice < 4 || d->nslice > 8) return DF_ERR_SHAPE;
       plan_backward_split(pl, d->naux, d->nao, d->nocc, d->nac, d->flags, d->nslice);
       break;
     default: return DF_ERR_UNSUPPORTED;
@@ -835,35 +1004,145 @@ df_status df_workspace_size(df_op op, const df_dims* d, size_t* bytes) {
   return DF_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+df_status df_workspace_size(df_op op, const df_dims* d, size_t* bytes) {
+  if (!d || !bytes) return DF_ERR_ARG;
+  return workspace_bytes(op, d, 0, bytes);
+}
+
+df_status df_workspace_query(df_ctx* ctx, df_op op, const df_dims* d, size_t* bytes) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (!d || !bytes) return fail(c, DF_ERR_ARG, "dims and bytes are required");
+  df_dims e = *d;
+  if ((e.flags & DF_PREC_SPLIT) && e.nslice == 0) e.nslice = c->nslice;
+  const df_status st = workspace_bytes(op, &e, c->scratch_limit, bytes);
+  if (st == DF_ERR_WORKSPACE)
+    return fail(c, st, "the scratch limit of " + std::to_string(c->scratch_limit) +
+                           " bytes is below the workspace of one auxiliary row per chunk");
+  if (st != DF_OK) return fail(c, st, "df_workspace_query: bad sizes or operation");
+  return DF_OK;
+}
+
+df_status df_set_scratch_limit(df_ctx* ctx, size_t bytes) {
+  if (!ctx) return DF_ERR_ARG;
+  ctx->scratch_limit = bytes;
+  return DF_OK;
+}
+
+df_status df_backward_chunk(df_ctx* ctx, const df_dims* d, int64_t* rows) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (!d || !rows) return fail(c, DF_ERR_ARG, "dims and rows are required");
+  if (d->naux < 1 || d->nao < 1 || d->nao > kMaxNao || d->nocc < 0 || d->nac < 0)
+    return fail(c, DF_ERR_SHAPE, "bad sizes");
+  *rows = backward_rows(d->naux, d->nao, d->nocc, d->nac, d->flags, c->scratch_limit);
+  if (*rows == 0) return fail(c, DF_ERR_WORKSPACE, "the scratch limit is below the workspace of one auxiliary row");
+  return DF_OK;
+}
+
+df_status df_set_split_slices(df_ctx* ctx, int nslice) {
+  if (!ctx) return DF_ERR_ARG;
+  if (nslice < 4 || nslice > 8) return fail(ctx, DF_ERR_SHAPE, "nslice must be in [4, 8]");
+  ctx->nslice = nslice;
+  return DF_OK;
+}
+
+df_status df_register_split(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const int8_t* Bs, const int* Be,
+                            int nslice) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (!B) return fail(c, DF_ERR_ARG, "B is NULL");
+  if (naux < 1 || nao < 1 || nao > kMaxNao) return fail(c, DF_ERR_SHAPE, "bad naux or nao");
+  if (nslice < 4 || nslice > 8) return fail(c, DF_ERR_SHAPE, "nslice must be in [4, 8]");
+  if (dfk::rpad32(naux * nao) > 0x7fffffffLL) return fail(c, DF_ERR_SHAPE, "naux * nao must be below 2^31 - 32");
+  auto& v = c->splits;
+  auto it = std::find_if(v.begin(), v.end(), [&](const df_ctx::SplitReg& r) {
+    return r.B == B && r.naux == naux && r.nao == nao && r.nslice == nslice;
+  });
+  if (!Bs) {
+    if (it != v.end()) v.erase(it);
+    return DF_OK;
+  }
+  if (!Be) return fail(c, DF_ERR_ARG, "Be is NULL");
+  if ((uintptr_t)Bs % 16 != 0) return fail(c, DF_ERR_ARG, "Bs must be 16-byte aligned");
+  const df_ctx::SplitReg r{B, naux, nao, Bs, Be, nslice};
+  if (it != v.end()) {
+    *it = r;
+    return DF_OK;
+  }
+  if (v.size() >= 16) return fail(c, DF_ERR_ARG, "at most 16 splits can be registered");
+  v.push_back(r);
+  return DF_OK;
+}
+
 df_status df_half_transform(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const double* C,
                             int64_t ncol, double* X, const double* C2, int64_t n2, double* Y, int flags) {
   df_ctx* c = ctx;
   if (check_ctx(c)) return DF_ERR_ARG;
   if (df_status s = check_core(c, B, naux, nao)) return s;
-  if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_half_transform takes no flags");
+  if (flags & ~(DF_ACCUMULATE | DF_PREC_SPLIT)) return fail(c, DF_ERR_UNSUPPORTED, "df_half_transform: unknown flags");
   if (!C || !X) return fail(c, DF_ERR_ARG, "C and X are required");
   if (ncol < 1) return fail(c, DF_ERR_SHAPE, "ncol must be >= 1");
   if ((C2 == nullptr) != (Y == nullptr)) return fail(c, DF_ERR_ARG, "C2 and Y must be given together");
   if (C2 && n2 < 1) return fail(c, DF_ERR_SHAPE, "n2 must be >= 1 when C2 is given");
   if (!C2 && n2 != 0) return fail(c, DF_ERR_SHAPE, "n2 must be 0 without C2");
+  const bool acc = flags & DF_ACCUMULATE, sp = flags & DF_PREC_SPLIT;
   const int64_t npair = nao * (nao + 1) / 2;
   std::vector<Range> rs = {{B, dbytes(naux * npair), "B", false},
                            {C, dbytes(nao * ncol), "C", false},
                            {X, dbytes(naux * nao * ncol), "X", true},
                            {C2, dbytes(nao * n2), "C2", false},
                            {Y, dbytes(naux * n2 * ncol), "Y", true}};
+  const df_ctx::SplitReg* reg = nullptr;
+  if (sp)
+    if (df_status s = split_for_call(c, B, naux, nao, naux * std::max<int64_t>(ncol, n2), &reg, rs)) return s;
   Plan pl;
-  const HalfPlan p = plan_half(pl, nao, ncol);
+  const HalfPlan p = plan_half(pl, naux, nao, ncol, n2, flags, c->nslice);
   if (!check_overlap(c, rs)) return DF_ERR_ARG;
   if (df_status s = need_ws(c, pl.total)) return s;
   rs.push_back({c->ws, pl.total, "workspace", true});
   if (!check_overlap(c, rs)) return DF_ERR_ARG;
   if (df_status s = enter(c)) return s;
-  double* cpad = (double*)(c->ws + p.cpad);
-  const ColBlock blk{C, ncol, ncol, 0};
-  if (df_status s = pad_operand(c, cpad, nao, ncol, &blk, 1)) return s;
-  if (df_status s = run_half(c, B, naux, nao, cpad, ncol, out_pmajor(X, naux, nao, ncol, ncol))) return s;
-  if (C2) return run_mo_pmajor(c, C2, n2, X, naux, nao, ncol, Y);
+  char* ws = c->ws;
+  // this call's X: into X itself, or, when it must be added to X and also feed Y, into xnew first
+  double* Xd = acc && C2 ? (double*)(ws + p.xnew) : X;
+  const int xacc = acc && !C2;
+  if (!sp) {
+    double* cpad = (double*)(ws + p.cpad);
+    const ColBlock blk{C, ncol, ncol, 0};
+    if (df_status s = pad_operand(c, cpad, nao, ncol, &blk, 1)) return s;
+    dfk::OutMap OX = out_pmajor(Xd, naux, nao, ncol, ncol);
+    OX.accumulate = xacc;
+    if (df_status s = run_half(c, B, naux, nao, cpad, ncol, OX)) return s;
+    if (C2)
+      if (df_status s = run_mo_pmajor(c, C2, n2, Xd, naux, nao, ncol, Y, acc)) return s;
+  } else {
+    // rows (P, mu) of b^P against the rows c of C, both over nu
+    const SplitOp cs = split_in(ws, p.cs);
+    if (df_status s = split_of(c, dfk::op_map(C, ncol, 1, nao, ncol), nao, c->nslice, cs)) return s;
+    dfk::OutMap OX = dfk::out_plain(Xd, naux * nao, ncol, ncol);
+    OX.accumulate = xacc;
+    if (df_status s = split_half(c, *reg, cs, ncol, OX)) return s;
+    if (C2) {
+      // Y[P][p][c] = sum_mu C2[mu][p] X[P][mu][c]: rows p of C2 against rows (P, c) of X, over mu
+      dfk::OpMap ox = dfk::op_map(Xd, naux * ncol, 1, nao, ncol);
+      ox.rl = ncol;
+      ox.s_rh = nao * ncol;
+      const SplitOp xs = split_in(ws, p.xs), c2s = split_in(ws, p.c2s);
+      if (df_status s = split_of(c, ox, nao, c->nslice, xs)) return s;
+      if (df_status s = split_of(c, dfk::op_map(C2, n2, 1, nao, n2), nao, c->nslice, c2s)) return s;
+      dfk::OutMap O = dfk::out_plain(Y, n2, naux * ncol, ncol);
+      O.nl = ncol;
+      O.s_nh = n2 * ncol;
+      O.accumulate = acc;
+      if (df_status s = slice_product(c, DF_KERNEL_MO_TRANSFORM, c2s, n2, xs, naux * ncol, nao, c->nslice, O)) return s;
+    }
+  }
+  if (acc && C2) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_add(Xd, naux * nao * ncol, X, c->stream), "add launch");
   return DF_OK;
 }
 
@@ -872,25 +1151,33 @@ df_status df_jk(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int64_t
   df_ctx* c = ctx;
   if (check_ctx(c)) return DF_ERR_ARG;
   if (df_status s = check_core(c, B, naux, nao)) return s;
-  if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_jk takes no flags");
+  if (flags & ~(DF_ACCUMULATE | DF_PREC_SPLIT)) return fail(c, DF_ERR_UNSUPPORTED, "df_jk: unknown flags");
   if (ndm < 1 || ndm > 65535) return fail(c, DF_ERR_SHAPE, "ndm must be in [1, 65535]");
   if (nocc < 0) return fail(c, DF_ERR_SHAPE, "nocc must be >= 0");
   if (nocc > 0 && !Cocc) return fail(c, DF_ERR_ARG, "Cocc is NULL");
-  const int64_t npair = nao * (nao + 1) / 2;
+  const bool acc = flags & DF_ACCUMULATE, sp = flags & DF_PREC_SPLIT;
+  const int64_t npair = nao * (nao + 1) / 2, ncol = ndm * nocc;
   std::vector<Range> rs = {{B, dbytes(naux * npair), "B", false},
                            {Cocc, dbytes(ndm * nao * nocc), "Cocc", false},
                            {w, dbytes(ndm * nocc), "w", false},
                            {J, dbytes(ndm * nao * nao), "J", true},
                            {K, dbytes(ndm * nao * nao), "K", true},
                            {v, dbytes(ndm * naux), "v", true}};
+  const bool work = nocc > 0 && (J || K || v);
+  const df_ctx::SplitReg* reg = nullptr;
+  if (sp && work) {
+    if (df_status s = split_for_call(c, B, naux, nao, std::max(ncol, nao), &reg, rs)) return s;
+    if (naux * nocc > (int64_t(1) << 30)) return fail(c, DF_ERR_SHAPE, "naux * nocc too large for the split path");
+  }
   Plan pl;
-  const JkPlan p = plan_jk(pl, naux, nao, ndm, nocc);
-  if (nocc > 0 && (J || K || v)) {
+  const JkPlan p = plan_jk(pl, naux, nao, ndm, nocc, w != nullptr, flags, c->nslice);
+  if (work) {
     if (!check_overlap(c, rs)) return DF_ERR_ARG;
     if (df_status s = need_ws(c, pl.total)) return s;
     rs.push_back({c->ws, pl.total, "workspace", true});
   }
   if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (nocc == 0 && acc) return DF_OK;   // nothing to add
   if (df_status s = enter(c)) return s;
   if (nocc == 0) {
     if (J) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(J, ndm * nao * nao, c->stream), "fill");
@@ -898,23 +1185,95 @@ df_status df_jk(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int64_t
     if (v) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(v, ndm * naux, c->stream), "fill");
     return DF_OK;
   }
-  if (!J && !K && !v) return DF_OK;
-  const int64_t ncol = ndm * nocc;
-  double* X = (double*)(c->ws + p.x);
-  double* cc = (double*)(c->ws + p.ccat);
-  std::vector<ColBlock> blks((size_t)ndm);
-  for (int64_t z = 0; z < ndm; ++z) blks[(size_t)z] = ColBlock{Cocc + z * nao * nocc, nocc, nocc, z * nocc};
-  if (df_status s = pad_operand(c, cc, nao, ncol, blks.data(), (int)ndm)) return s;
-  if (df_status s = run_half(c, B, naux, nao, cc, ncol, out_pmajor(X, naux, nao, ncol, ncol))) return s;
-  if (J || v) {
-    double* vv = v ? v : (double*)(c->ws + p.vtmp);
-    DF_LAUNCH(DF_KERNEL_JVEC, dfk::launch_jvec(X, naux, nao, ncol, Cocc, w, nocc, ndm, vv, c->stream), "J-vector launch");
-    if (J) DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_coulomb(B, naux, nao, vv, ndm, J, c->stream), "Coulomb launch");
+  if (!work) return DF_OK;
+  char* ws = c->ws;
+  double* X = (double*)(ws + p.x);
+  if (!sp) {
+    double* cc = (double*)(ws + p.ccat);
+    std::vector<ColBlock> blks((size_t)ndm);
+    for (int64_t z = 0; z < ndm; ++z) blks[(size_t)z] = ColBlock{Cocc + z * nao * nocc, nocc, nocc, z * nocc};
+    if (df_status s = pad_operand(c, cc, nao, ncol, blks.data(), (int)ndm)) return s;
+    if (df_status s = run_half(c, B, naux, nao, cc, ncol, out_pmajor(X, naux, nao, ncol, ncol))) return s;
+  } else {
+    // the rows (z, c) of the factors over mu, then X[P][mu][(z, c)] from the planes of b^P
+    dfk::OpMap oc = dfk::op_map(Cocc, ncol, 1, nao, nocc);
+    oc.rl = nocc;
+    oc.s_rh = nao * nocc;
+    const SplitOp cs = split_in(ws, p.cs);
+    if (df_status s = split_of(c, oc, nao, c->nslice, cs)) return s;
+    if (df_status s = split_half(c, *reg, cs, ncol, dfk::out_plain(X, naux * nao, ncol, ncol))) return s;
   }
-  if (K)
-    if (df_status s = run_k(c, X, w, naux, nao, ncol, nocc, ndm, p.nsplit, (double*)(c->ws + p.kpart), K))
-      return s;
+  if (J || v) {
+    // v of this call (into v itself unless it is to be added to v)
+    double* vv = v && !acc ? v : (double*)(ws + p.vtmp);
+    DF_LAUNCH(DF_KERNEL_JVEC, dfk::launch_jvec(X, naux, nao, ncol, Cocc, w, nocc, ndm, vv, c->stream), "J-vector launch");
+    if (J)
+      DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_coulomb(B, naux, nao, vv, ndm, J, c->stream, acc), "Coulomb launch");
+    if (v && acc) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_add(vv, ndm * naux, v, c->stream), "add launch");
+  }
+  if (K) {
+    double* kpart = (double*)(ws + p.kpart);
+    if (!sp) {
+      if (df_status s = run_k(c, X, w, naux, nao, ncol, nocc, ndm, p.nsplit, kpart, K, acc)) return s;
+    } else {
+      // K_z = sum_{P, c} X[P][m][(z, c)] w_zc X[P][n][(z, c)]: the rows m of each density's X_occ
+      // over (P, c), against those of X diag(w) when there are weights; lower tiles, reduced and
+      // mirrored
+      const SplitOp xo = split_in(ws, p.xos), xw = split_in(ws, p.xws);
+      const double* Xw = X;
+      if (w) {
+        Xw = (double*)(ws + p.xw);
+        DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_scale_cols(X, naux * nao * ncol, ncol, w, (double*)Xw, c->stream),
+                  "scale launch");
+      }
+      for (int64_t z = 0; z < ndm; ++z) {
+        for (int side = 0; side < (w ? 2 : 1); ++side) {
+          dfk::OpMap ox = dfk::op_map((side ? Xw : X) + z * nocc, nao, ncol, nocc, 1);
+          ox.kb_n = naux;
+          ox.s_kb = nao * ncol;
+          const SplitOp d = side ? xw : xo;
+          if (df_status s = split_of(c, ox, naux * nocc, c->nslice, SplitOp{d.planes + z * p.xplane, d.ex + z * nao}))
+            return s;
+        }
+      }
+      const SplitOp rb = w ? xw : xo;
+      const dfk::SliceBatch zs{p.xplane, nao, p.xplane, nao};
+      DF_LAUNCH(DF_KERNEL_K_SYRK,
+                dfk::launch_slice_gemm_batched(xo.planes, xo.ex, nao, rb.planes, rb.ex, nao, dfk::kpad64(naux * nocc),
+                                               c->nslice, dfk::out_plain(kpart, nao, nao, nao), true, p.nsplit, kpart,
+                                               ndm, zs, c->stream),
+                "slice product launch");
+      DF_LAUNCH(DF_KERNEL_K_REDUCE, dfk::launch_syrk_reduce(kpart, p.nsplit, nao, ndm, K, c->stream, acc),
+                "K reduce launch");
+    }
+  }
   return DF_OK;
+}
+
+// b^P_{lu} = sum_mu Cl[mu][l] X^act[mu][P][u] for every P into out [naux][nl][nac], from int8
+// slices: the rows l of Cl (planes ls, written here unless `have_ls`) against the rows (P, u) of
+// X_act (planes xas), both over mu.
+static df_status split_second(df_ctx* c, const double* Cl, int64_t nl, SplitOp ls, SplitOp xas, int64_t naux,
+                              int64_t nao, int64_t nac, double* out, bool have_ls = false) {
+  if (!have_ls)
+    if (df_status s = split_of(c, dfk::op_map(Cl, nl, 1, nao, nl), nao, c->nslice, ls)) return s;
+  dfk::OutMap O = dfk::out_plain(out, nl, naux * nac, nac);
+  O.nl = nac;
+  O.s_nh = nl * nac;
+  return slice_product(c, DF_KERNEL_MO_TRANSFORM, ls, nl, xas, naux * nac, nao, c->nslice, O);
+}
+
+// X_act AO-major [nao][naux][nac] from the registered planes of B (planes cas of the rows of Cact
+// written first), and the planes xas of its rows (P, u) over mu.
+static df_status split_xact(df_ctx* c, const df_ctx::SplitReg& r, const double* Cact, int64_t nac, double* X,
+                            SplitOp cas, SplitOp xas) {
+  const int64_t naux = r.naux, nao = r.nao;
+  if (df_status s = split_of(c, dfk::op_map(Cact, nac, 1, nao, nac), nao, c->nslice, cas)) return s;
+  dfk::OutMap OX = dfk::out_plain(X, naux * nao, nac, naux * nac);
+  OX.ml = nao;   // row (P, mu) at P * nac + mu * naux * nac
+  OX.s_mh = nac;
+  if (df_status s = split_half(c, r, cas, nac, OX)) return s;
+  return split_of(c, dfk::op_map(X, naux * nac, 1, nao, naux * nac), nao, c->nslice, xas);
 }
 
 df_status df_active_eri(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const double* Cact, int64_t nac,
@@ -922,16 +1281,20 @@ df_status df_active_eri(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
   df_ctx* c = ctx;
   if (check_ctx(c)) return DF_ERR_ARG;
   if (df_status s = check_core(c, B, naux, nao)) return s;
-  if (flags != 0) return fail(c, DF_ERR_UNSUPPORTED, "df_active_eri takes no flags");
+  if (flags & ~(DF_ACCUMULATE | DF_PREC_SPLIT)) return fail(c, DF_ERR_UNSUPPORTED, "df_active_eri: unknown flags");
   if (nac < 0) return fail(c, DF_ERR_SHAPE, "nac must be >= 0");
   if (nac > 0 && (!Cact || !eri)) return fail(c, DF_ERR_ARG, "Cact and eri are required");
-  const int64_t npair = nao * (nao + 1) / 2;
+  const bool acc = flags & DF_ACCUMULATE, sp = flags & DF_PREC_SPLIT;
+  const int64_t npair = nao * (nao + 1) / 2, n2 = nac * nac;
   std::vector<Range> rs = {{B, dbytes(naux * npair), "B", false},
                            {Cact, dbytes(nao * nac), "Cact", false},
-                           {eri, dbytes(nac * nac * nac * nac), "eri", true},
-                           {buv, dbytes(naux * nac * nac), "buv", true}};
+                           {eri, dbytes(n2 * n2), "eri", true},
+                           {buv, dbytes(naux * n2), "buv", true}};
+  const df_ctx::SplitReg* reg = nullptr;
+  if (sp && nac > 0)
+    if (df_status s = split_for_call(c, B, naux, nao, naux * nac, &reg, rs)) return s;
   Plan pl;
-  const ActPlan p = plan_act(pl, naux, nao, nac);
+  const ActPlan p = plan_act(pl, naux, nao, nac, flags, c->nslice);
   if (nac > 0) {
     if (!check_overlap(c, rs)) return DF_ERR_ARG;
     if (df_status s = need_ws(c, pl.total)) return s;
@@ -940,14 +1303,31 @@ df_status df_active_eri(df_ctx* ctx, const double* B, int64_t naux, int64_t nao,
   if (!check_overlap(c, rs)) return DF_ERR_ARG;
   if (nac == 0) return DF_OK;
   if (df_status s = enter(c)) return s;
-  double* X = (double*)(c->ws + p.x);
-  double* bu = buv ? buv : (double*)(c->ws + p.buv);
-  double* cpad = (double*)(c->ws + p.cpad);
-  const ColBlock blk{Cact, nac, nac, 0};
-  if (df_status s = pad_operand(c, cpad, nao, nac, &blk, 1)) return s;
-  if (df_status s = run_half(c, B, naux, nao, cpad, nac, out_split(nullptr, X, naux, nao, 0, nac))) return s;
-  if (df_status s = run_mo(c, Cact, nac, X, naux, nao, nac, bu)) return s;
-  return run_pgemm(c, DF_KERNEL_ERI, bu, nac * nac, bu, nac * nac, naux, eri);
+  char* ws = c->ws;
+  double* X = (double*)(ws + p.x);
+  double* bu = buv && !acc ? buv : (double*)(ws + p.buv);   // b_uv of this call
+  if (!sp) {
+    double* cpad = (double*)(ws + p.cpad);
+    const ColBlock blk{Cact, nac, nac, 0};
+    if (df_status s = pad_operand(c, cpad, nao, nac, &blk, 1)) return s;
+    if (df_status s = run_half(c, B, naux, nao, cpad, nac, out_split(nullptr, X, naux, nao, 0, nac))) return s;
+    if (df_status s = run_mo(c, Cact, nac, X, naux, nao, nac, bu)) return s;
+    if (df_status s = run_pgemm(c, DF_KERNEL_ERI, bu, n2, bu, n2, naux, eri, acc)) return s;
+  } else {
+    const SplitOp cas = split_in(ws, p.cas), xas = split_in(ws, p.xas), bvs = split_in(ws, p.buvs);
+    if (df_status s = split_xact(c, *reg, Cact, nac, X, cas, xas)) return s;
+    // b_uv: the planes of Cact's rows are already there
+    dfk::OutMap O = dfk::out_plain(bu, nac, naux * nac, nac);
+    O.nl = nac;
+    O.s_nh = n2;
+    if (df_status s = slice_product(c, DF_KERNEL_MO_TRANSFORM, cas, nac, xas, naux * nac, nao, c->nslice, O)) return s;
+    if (df_status s = split_of(c, dfk::op_map(bu, n2, 1, naux, n2), naux, c->nslice, bvs)) return s;
+    dfk::OutMap Oe = dfk::out_plain(eri, n2, n2, n2);
+    Oe.accumulate = acc;
+    if (df_status s = slice_product(c, DF_KERNEL_ERI, bvs, n2, bvs, n2, naux, c->nslice, Oe)) return s;
+  }
+  if (buv && acc) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_add(bu, naux * n2, buv, c->stream), "add launch");
+  return DF_OK;
 }
 
 df_status df_papa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const double* Cp, int64_t np,
@@ -955,8 +1335,8 @@ df_status df_papa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const
   df_ctx* c = ctx;
   if (check_ctx(c)) return DF_ERR_ARG;
   if (df_status s = check_core(c, B, naux, nao)) return s;
-  if (flags & ~DF_PAPA_FULL) return fail(c, DF_ERR_UNSUPPORTED, "unknown flag bits");
-  const bool full = (flags & DF_PAPA_FULL) != 0;
+  if (flags & ~(DF_PAPA_FULL | DF_ACCUMULATE | DF_PREC_SPLIT)) return fail(c, DF_ERR_UNSUPPORTED, "unknown flag bits");
+  const bool full = flags & DF_PAPA_FULL, acc = flags & DF_ACCUMULATE, sp = flags & DF_PREC_SPLIT;
   if (np < 0 || nac < 0 || nq < 0) return fail(c, DF_ERR_SHAPE, "sizes must be >= 0");
   if (full) {
     if (nq > 0 && !Cq) return fail(c, DF_ERR_ARG, "DF_PAPA_FULL needs Cq");
@@ -971,8 +1351,13 @@ df_status df_papa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const
                            {Cact, dbytes(nao * nac), "Cact", false},
                            {Cq, dbytes(nao * nq), "Cq", false},
                            {out, dbytes(nout), "out", true}};
+  const df_ctx::SplitReg* reg = nullptr;
+  if (sp && nout > 0)
+    if (df_status s = split_for_call(c, B, naux, nao, naux * nac, &reg, rs)) return s;
+  if (sp && nout > 0 && !split_sizes_ok(naux, nao, std::max(np, nq) * nac))
+    return fail(c, DF_ERR_SHAPE, "problem too large for the split path");
   Plan pl;
-  const PapaPlan p = plan_papa(pl, naux, nao, nac, np, nq, full);
+  const PapaPlan p = plan_papa(pl, naux, nao, nac, np, nq, flags, c->nslice);
   if (nout > 0) {
     if (!check_overlap(c, rs)) return DF_ERR_ARG;
     if (df_status s = need_ws(c, pl.total)) return s;
@@ -981,21 +1366,34 @@ df_status df_papa(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const
   if (!check_overlap(c, rs)) return DF_ERR_ARG;
   if (nout == 0) return DF_OK;
   if (df_status s = enter(c)) return s;
-  double* X = (double*)(c->ws + p.x);
-  double* bpu = (double*)(c->ws + p.bpu);
-  double* cpad = (double*)(c->ws + p.cpad);
-  const ColBlock blk{Cact, nac, nac, 0};
-  if (df_status s = pad_operand(c, cpad, nao, nac, &blk, 1)) return s;
-  if (df_status s = run_half(c, B, naux, nao, cpad, nac, out_split(nullptr, X, naux, nao, 0, nac))) return s;
-  if (df_status s = run_mo(c, Cp, np, X, naux, nao, nac, bpu)) return s;
-  if (full) {
-    double* bqv = (double*)(c->ws + p.bqv);
-    if (df_status s = run_mo(c, Cq, nq, X, naux, nao, nac, bqv)) return s;
-    return run_pgemm(c, DF_KERNEL_PAPA, bpu, np * nac, bqv, nq * nac, naux, out);
+  char* ws = c->ws;
+  double* X = (double*)(ws + p.x);
+  double* bpu = (double*)(ws + p.bpu);
+  // the right-hand factor: b_vw (default) or b_qv (DF_PAPA_FULL), [naux][nr][nac]
+  const double* Cr = full ? Cq : Cact;
+  const int64_t nr = full ? nq : nac;
+  double* br = (double*)(ws + (full ? p.bqv : p.bvw));
+  if (!sp) {
+    double* cpad = (double*)(ws + p.cpad);
+    const ColBlock blk{Cact, nac, nac, 0};
+    if (df_status s = pad_operand(c, cpad, nao, nac, &blk, 1)) return s;
+    if (df_status s = run_half(c, B, naux, nao, cpad, nac, out_split(nullptr, X, naux, nao, 0, nac))) return s;
+    if (df_status s = run_mo(c, Cp, np, X, naux, nao, nac, bpu)) return s;
+    if (df_status s = run_mo(c, Cr, nr, X, naux, nao, nac, br)) return s;
+    return run_pgemm(c, DF_KERNEL_PAPA, bpu, np * nac, br, nr * nac, naux, out, acc);
   }
-  double* bvw = (double*)(c->ws + p.bvw);
-  if (df_status s = run_mo(c, Cact, nac, X, naux, nao, nac, bvw)) return s;
-  return run_pgemm(c, DF_KERNEL_PAPA, bpu, np * nac, bvw, nac * nac, naux, out);
+  const SplitOp xas = split_in(ws, p.xas), cps = split_in(ws, p.cps), bps = split_in(ws, p.bpus);
+  const SplitOp cas = split_in(ws, p.cas), crs = full ? split_in(ws, p.cqs) : cas;
+  const SplitOp brs = split_in(ws, full ? p.bqvs : p.bvws);
+  if (df_status s = split_xact(c, *reg, Cact, nac, X, cas, xas)) return s;
+  if (df_status s = split_second(c, Cp, np, cps, xas, naux, nao, nac, bpu)) return s;
+  // the default form's right factor b_vw uses the planes of Cact's rows made for X_act
+  if (df_status s = split_second(c, Cr, nr, crs, xas, naux, nao, nac, br, !full)) return s;
+  if (df_status s = split_of(c, dfk::op_map(bpu, np * nac, 1, naux, np * nac), naux, c->nslice, bps)) return s;
+  if (df_status s = split_of(c, dfk::op_map(br, nr * nac, 1, naux, nr * nac), naux, c->nslice, brs)) return s;
+  dfk::OutMap O = dfk::out_plain(out, np * nac, nr * nac, nr * nac);
+  O.accumulate = acc;
+  return slice_product(c, DF_KERNEL_PAPA, bps, np * nac, brs, nr * nac, naux, c->nslice, O);
 }
 
 // (pq|uv) into out [nuv][np][nq] with the workspace pieces of p at ws (see plan_ppaa)
@@ -1285,28 +1683,37 @@ static df_status bwd_coulomb(df_ctx* c, char* ws, const BwdPlan& p, const double
   return DF_OK;
 }
 
-// dCact = sum_P X^act_P (Z_P + Z_P^T),  Z_P[uv] = sum_wx (geri[uvwx] + geri[wxuv]) b^P_wx
-// (the active-space part of the adjoint, FP64; Xa AO-major [nao][naux][nac])
-static df_status bwd_active(df_ctx* c, char* ws, const BwdPlan& p, int64_t naux, int64_t nao, const double* Cact,
-                            int64_t nac, const double* geri, const double* Xa, double* dCact) {
+// The active-space part of the adjoint for auxiliary rows [p0, p0 + pc) (FP64):
+//   dCact (+)= sum_P X^act_P (Z_P + Z_P^T),  Z_P[uv] = sum_wx Gs[uv][wx] b^P_wx,
+// with Gs = geri + geri^T already in ws + p.Gs.  Xa: those rows' X^act, AO-major (rows mu of
+// stride ld, columns (P, u) of the chunk).
+static df_status bwd_active_rows(df_ctx* c, char* ws, const BwdPlan& p, int64_t pc, int64_t nao, const double* Cact,
+                                 int64_t nac, const double* Xa, int64_t ld, double* dCact, int accumulate) {
   const int64_t n2 = nac * nac;
-  double* Gs = (double*)(ws + p.Gs);
+  const double* Gs = (const double*)(ws + p.Gs);
   double* buv = (double*)(ws + p.buv);
   double* Z = (double*)(ws + p.Z);
-  DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_symmetrize(geri, n2, 1, Gs, c->stream), "symmetrize");
-  if (df_status s = run_mo(c, Cact, nac, Xa, naux, nao, nac, buv)) return s;
-  const dfk::OpMap A = dfk::op_map(buv, naux, n2, n2, 1);
+  if (df_status s = run_mo_ld(c, Cact, nac, Xa, ld, pc, nao, nac, buv)) return s;
+  const dfk::OpMap A = dfk::op_map(buv, pc, n2, n2, 1);
   const dfk::OpMap Bm = dfk::op_map(Gs, n2, n2, n2, 1);
-  DF_LAUNCH(DF_KERNEL_ADJOINT, dfk::launch_gemm(A, Bm, dfk::out_plain(Z, naux, n2, n2), 1, c->stream),
+  DF_LAUNCH(DF_KERNEL_ADJOINT, dfk::launch_gemm(A, Bm, dfk::out_plain(Z, pc, n2, n2), 1, c->stream),
             "adjoint product");
-  DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_symmetrize(Z, nac, naux, Z, c->stream), "symmetrize");
-  const dfk::OpMap Ax = dfk::op_map(Xa, nao, naux * nac, naux * nac, 1);
-  const dfk::OpMap Bz = dfk::op_map(Z, nac, 1, naux * nac, nac);
-  DF_LAUNCH(DF_KERNEL_ADJOINT,
-            dfk::launch_gemm_split(Ax, Bz, dfk::out_plain(dCact, nao, nac, nac), p.nsa, (double*)(ws + p.apart),
-                                   c->stream),
+  DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_symmetrize(Z, nac, pc, Z, c->stream), "symmetrize");
+  const dfk::OpMap Ax = dfk::op_map(Xa, nao, ld, pc * nac, 1);
+  const dfk::OpMap Bz = dfk::op_map(Z, nac, 1, pc * nac, nac);
+  dfk::OutMap O = dfk::out_plain(dCact, nao, nac, nac);
+  O.accumulate = accumulate;
+  const int nsa = dfk::gemm_splits(nao, nac, (pc * nac + 15) / 16);
+  DF_LAUNCH(DF_KERNEL_ADJOINT, dfk::launch_gemm_split(Ax, Bz, O, nsa, (double*)(ws + p.apart), c->stream),
             "adjoint product");
   return DF_OK;
+}
+
+// The active-space part of the adjoint over all naux rows at once (Xa AO-major [nao][naux][nac]).
+static df_status bwd_active(df_ctx* c, char* ws, const BwdPlan& p, int64_t naux, int64_t nao, const double* Cact,
+                            int64_t nac, const double* geri, const double* Xa, double* dCact) {
+  DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_symmetrize(geri, nac * nac, 1, (double*)(ws + p.Gs), c->stream), "symmetrize");
+  return bwd_active_rows(c, ws, p, naux, nao, Cact, nac, Xa, naux * nac, dCact, 0);
 }
 
 df_status df_step_backward(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const double* Cocc,
@@ -1335,8 +1742,12 @@ df_status df_step_backward(df_ctx* ctx, const double* B, int64_t naux, int64_t n
                            {Xact, dbytes(naux * nao * nac), "Xact", false},
                            {dCocc, dbytes(nao * nocc), "dCocc", true},
                            {dCact, dbytes(nao * nac), "dCact", true}};
+  const int64_t rows = backward_rows(naux, nao, nocc, nac, pflags, c->scratch_limit);
+  if (rows == 0)
+    return fail(c, DF_ERR_WORKSPACE, "the scratch limit of " + std::to_string(c->scratch_limit) +
+                                         " bytes is below the workspace of one auxiliary row");
   Plan pl;
-  const BwdPlan p = plan_backward(pl, naux, nao, nocc, nac, pflags);
+  const BwdPlan p = plan_backward(pl, naux, nao, nocc, nac, pflags, rows);
   if (!check_overlap(c, rs)) return DF_ERR_ARG;
   if (df_status s = need_ws(c, pl.total)) return s;
   if (pl.total) rs.push_back({c->ws, pl.total, "workspace", true});
@@ -1347,51 +1758,70 @@ df_status df_step_backward(df_ctx* ctx, const double* B, int64_t naux, int64_t n
   if (nocc > 0 && !do_j && !do_k)
     DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(dCocc, nao * nocc, c->stream), "fill");
   if (nac > 0 && !do_e) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(dCact, nao * nac, c->stream), "fill");
-  // half transforms of the forward, recomputed when not supplied
-  const double* Xo = Xocc;
-  const double* Xa = Xact;
-  if (!caller_x && (do_k || do_e)) {
-    double* xo = do_k ? (double*)(ws + p.xo) : nullptr;
-    double* xa = do_e ? (double*)(ws + p.xa) : nullptr;
-    double* cc = (double*)(ws + p.ccat);
-    const int64_t no = do_k ? nocc : 0, na = do_e ? nac : 0;
-    const ColBlock blks[2] = {{Cocc, nocc, no, 0}, {Cact, nac, na, no}};
-    if (df_status s = pad_operand(c, cc, nao, no + na, blks, 2)) return s;
-    if (df_status s = run_half(c, B, naux, nao, cc, no + na, out_split(xo, xa, naux, nao, no, na))) return s;
-    Xo = xo;
-    Xa = xa;
-  }
   if (do_j)
     if (df_status s = bwd_coulomb(c, ws, p, B, naux, nao, gJ, Cocc, nocc, dCocc)) return s;
-  if (do_k) {
-    // dCocc += sum_P b^P Y_P,  Y_P = S X_P,  S = gK + gK^T
-    double* S = (double*)(ws + p.S);
-    double* Y = (double*)(ws + p.Y);
-    DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_symmetrize(gK, nao, 1, S, c->stream), "symmetrize");
-    const dfk::OpMap A = dfk::op_map(S, nao, nao, nao, 1);
-    dfk::OpMap Bm = dfk::op_map(Xo, naux * nocc, 1, nao, nocc);
-    Bm.rl = nocc;
-    Bm.s_rh = nao * nocc;
-    // Y [P][kpad16(nao)][nocc]: the packed product reads whole 16-row slabs of each Y_P
-    const int64_t kp = dfk::kpad16(nao);
-    dfk::OutMap O = dfk::out_plain(Y, nao, naux * nocc, nocc);
-    O.nl = nocc;
-    O.s_nh = kp * nocc;
-    DF_LAUNCH(DF_KERNEL_ADJOINT, dfk::launch_gemm(A, Bm, O, 1, c->stream), "adjoint product");
-    if (kp > nao)
-      DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero_strided(Y + nao * nocc, naux, kp * nocc, (kp - nao) * nocc, c->stream),
-                "fill");
-    dfk::OpMap Ym = dfk::op_map(Y, nocc, 1, nao, nocc);
-    Ym.kb_n = naux;
-    Ym.s_kb = kp * nocc;
-    dfk::OutMap Od = dfk::out_plain(dCocc, nao, nocc, nocc);
-    Od.accumulate = do_j ? 1 : 0;
-    DF_LAUNCH(DF_KERNEL_ADJOINT,
-              dfk::launch_half_reduce(B, naux, nao, Ym, Od, p.nsk, (double*)(ws + p.kpart), c->stream),
-              "adjoint packed product");
-  }
+  if (!do_k && !do_e) return DF_OK;
+  double* S = (double*)(ws + p.S);
+  if (do_k) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_symmetrize(gK, nao, 1, S, c->stream), "symmetrize");
   if (do_e)
-    if (df_status s = bwd_active(c, ws, p, naux, nao, Cact, nac, geri, Xa, dCact)) return s;
+    DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_symmetrize(geri, nac * nac, 1, (double*)(ws + p.Gs), c->stream),
+              "symmetrize");
+  // the forward's half transforms are recomputed, chunk by chunk, when not supplied
+  const bool recompute = !caller_x;
+  const int64_t no = do_k ? nocc : 0, na = do_e ? nac : 0;
+  double* cc = (double*)(ws + p.ccat);
+  if (recompute) {
+    const ColBlock blks[2] = {{Cocc, nocc, no, 0}, {Cact, nac, na, no}};
+    if (df_status s = pad_operand(c, cc, nao, no + na, blks, 2)) return s;
+  }
+  const int64_t kp = dfk::kpad16(nao);
+  // auxiliary rows in chunks of p.chunk; each chunk's share of dCocc and dCact is added in order
+  for (int64_t p0 = 0; p0 < naux; p0 += p.chunk) {
+    const int64_t pc = std::min(p.chunk, naux - p0);
+    const double* Bc = B + p0 * npair;
+    const double* Xo;
+    const double* Xa;
+    int64_t lda;   // row stride of the chunk's AO-major X^act
+    if (recompute) {
+      double* xo = do_k ? (double*)(ws + p.xo) : nullptr;
+      double* xa = do_e ? (double*)(ws + p.xa) : nullptr;
+      if (df_status s = run_half(c, Bc, pc, nao, cc, no + na, out_split(xo, xa, pc, nao, no, na))) return s;
+      Xo = xo;
+      Xa = xa;
+      lda = pc * nac;
+    } else {
+      Xo = Xocc ? Xocc + p0 * nao * nocc : nullptr;
+      Xa = Xact ? Xact + p0 * nac : nullptr;
+      lda = naux * nac;
+    }
+    if (do_k) {
+      // dCocc += sum_P b^P Y_P,  Y_P = S X_P,  S = gK + gK^T
+      double* Y = (double*)(ws + p.Y);
+      const dfk::OpMap A = dfk::op_map(S, nao, nao, nao, 1);
+      dfk::OpMap Bm = dfk::op_map(Xo, pc * nocc, 1, nao, nocc);
+      Bm.rl = nocc;
+      Bm.s_rh = nao * nocc;
+      // Y [P][kpad16(nao)][nocc]: the packed product reads whole 16-row slabs of each Y_P
+      dfk::OutMap O = dfk::out_plain(Y, nao, pc * nocc, nocc);
+      O.nl = nocc;
+      O.s_nh = kp * nocc;
+      DF_LAUNCH(DF_KERNEL_ADJOINT, dfk::launch_gemm(A, Bm, O, 1, c->stream), "adjoint product");
+      if (kp > nao)
+        DF_LAUNCH(DF_KERNEL_OTHER,
+                  dfk::launch_fill_zero_strided(Y + nao * nocc, pc, kp * nocc, (kp - nao) * nocc, c->stream), "fill");
+      dfk::OpMap Ym = dfk::op_map(Y, nocc, 1, nao, nocc);
+      Ym.kb_n = pc;
+      Ym.s_kb = kp * nocc;
+      dfk::OutMap Od = dfk::out_plain(dCocc, nao, nocc, nocc);
+      Od.accumulate = do_j || p0 > 0 ? 1 : 0;
+      const int nsk = dfk::half_reduce_splits(nao, nocc, pc);
+      DF_LAUNCH(DF_KERNEL_ADJOINT,
+                dfk::launch_half_reduce(Bc, pc, nao, Ym, Od, nsk, (double*)(ws + p.kpart), c->stream),
+                "adjoint packed product");
+    }
+    if (do_e)
+      if (df_status s = bwd_active_rows(c, ws, p, pc, nao, Cact, nac, Xa, lda, dCact, p0 > 0)) return s;
+  }
   return DF_OK;
 }
 

@@ -51,7 +51,7 @@ bool offsets_fit(const OpMap& o);
 inline int64_t kpad16(int64_t n) { return (n + 15) / 16 * 16; }
 
 // Half transform: for each P, T[m][c] = sum_k b^P_{mk} C[k][c], c in [0, ncol), written
-// through `out` with z = P (out.M = nao, out.N = ncol, alpha 1, no accumulate).  C has
+// through `out` with z = P (out.M = nao, out.N = ncol; alpha and accumulate honoured).  C has
 // kpad16(nao) rows (row stride ldc), rows nao.. zero.
 hipError_t launch_half_transform(const double* B, int64_t naux, int64_t nao, const double* C, int64_t ldc,
                                  int64_t ncol, const OutMap& out, hipStream_t s);
@@ -63,6 +63,8 @@ hipError_t launch_gemm(const OpMap& A, const OpMap& Bm, const OutMap& C, int64_t
 // partial sums go to part [nsplit][M][N] and a fixed-order reduction writes C.  gemm_splits()
 // is the split count the workspace is planned with (part needs nsplit*M*N doubles if > 1).
 int gemm_splits(int64_t M, int64_t N, int64_t nslab);
+// The most splits gemm_splits(M, N, s) gives for any s <= nslab (a bound for sizing partials).
+int gemm_splits_bound(int64_t M, int64_t N, int64_t nslab);
 int64_t gemm_slabs(const OpMap& A);
 hipError_t launch_gemm_split(const OpMap& A, const OpMap& Bm, const OutMap& C, int nsplit, double* part,
                              hipStream_t s);
@@ -74,6 +76,8 @@ hipError_t launch_split_reduce(const double* part, int nsplit, const OutMap& O, 
 // kc the AO index k (kc_n = nao); for every P the entries k in [nao, kpad16(nao)) must exist
 // and be zero.  Split over P ranges with partials [nsplit][nao][N] (half_reduce_splits()).
 int half_reduce_splits(int64_t nao, int64_t N, int64_t naux);
+// The most splits half_reduce_splits(nao, N, n) gives for any n <= naux.
+int half_reduce_splits_bound(int64_t nao, int64_t N, int64_t naux);
 hipError_t launch_half_reduce(const double* B, int64_t naux, int64_t nao, const OpMap& Y, const OutMap& C,
                               int nsplit, double* part, hipStream_t s);
 
@@ -101,17 +105,24 @@ int syrk_splits(int64_t n, int64_t kb_n, int64_t nz);
 int syrk_tile_for(int64_t n);
 hipError_t launch_syrk_partial(const OpMap& A, const OpMap& Bw, int64_t n, int64_t nz, int nsplit,
                                double* Kpart, hipStream_t s);
-// K[z][i][j] = sum_s Kpart[s][z][max(i,j)][min(i,j)]; both triangles written.
+// K[z][i][j] = sum_s Kpart[s][z][max(i,j)][min(i,j)]; both triangles written (added to K
+// when `accumulate`).
 hipError_t launch_syrk_reduce(const double* Kpart, int nsplit, int64_t n, int64_t nz, double* K,
-                              hipStream_t s);
+                              hipStream_t s, int accumulate = 0);
 
-// v[z][P] = sum_{m<nao, c<nocc} C[z][m][c] w[z][c] X[P][m][z*nocc + c]   (X row stride ldx)
+// v[z][P] = sum_{m<nao, c<nocc} C[z][m][c] w[z][c] X[P][m][z*nocc + c]   (X row stride ldx;
+// added to v when `accumulate`)
 hipError_t launch_jvec(const double* X, int64_t naux, int64_t nao, int64_t ldx, const double* C,
-                       const double* w, int64_t nocc, int64_t nz, double* v, hipStream_t s);
+                       const double* w, int64_t nocc, int64_t nz, double* v, hipStream_t s, int accumulate = 0);
 
-// J[z][i][j] = sum_P v[z][P] b^P_{ij}, both triangles written.
+// J[z][i][j] = sum_P v[z][P] b^P_{ij}, both triangles written (added to J when `accumulate`).
 hipError_t launch_coulomb(const double* B, int64_t naux, int64_t nao, const double* v,
-                          int64_t nz, double* J, hipStream_t s);
+                          int64_t nz, double* J, hipStream_t s, int accumulate = 0);
+
+// y[i] += x[i], i < n
+hipError_t launch_add(const double* x, int64_t n, double* y, hipStream_t s);
+// Xw[i] = X[i] * w[i % ncol], i < n (columns of a row-major [n / ncol][ncol] matrix scaled)
+hipError_t launch_scale_cols(const double* X, int64_t n, int64_t ncol, const double* w, double* Xw, hipStream_t s);
 
 // p[0..n) = 0
 hipError_t launch_fill_zero(double* p, int64_t n, hipStream_t s);

@@ -489,7 +489,8 @@ __global__ void __launch_bounds__(C::NT) syrk_group_kernel(SyrkGroup g) {
 }
 
 __global__ void __launch_bounds__(256) syrk_reduce_kernel(const double* __restrict__ Kpart, int nsplit,
-                                                          int64_t n, int64_t nz, double* __restrict__ K) {
+                                                          int64_t n, int64_t nz, double* __restrict__ K,
+                                                          int accumulate) {
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t nn = n * n;
   if (idx >= nn * nz) return;
@@ -497,7 +498,7 @@ __global__ void __launch_bounds__(256) syrk_reduce_kernel(const double* __restri
   const int64_t a = i >= j ? i : j, b = i >= j ? j : i;   // the lower element, computed by the SYRK tiles
   double s = 0.0;
   for (int sp = 0; sp < nsplit; ++sp) s += Kpart[((int64_t)sp * nz + z) * nn + a * n + b];
-  K[idx] = s;
+  K[idx] = accumulate ? K[idx] + s : s;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -594,7 +595,7 @@ struct HalfSrc {
 };
 
 // One output tile (item = P * tiles + tile) of the half transform.
-template <class C>
+template <class C, bool GEN = false>
 __device__ __forceinline__ void half_tile(const double* __restrict__ B, int nao, int64_t npair, const OpMap& Cm,
                                           const OutMap& out, int64_t tilesM, int64_t tilesN, int64_t item,
                                           double* smem) {
@@ -613,15 +614,16 @@ __device__ __forceinline__ void half_tile(const double* __restrict__ B, int nao,
   d4 acc[C::TM][C::TN];
   zero_acc<C>(acc);
   mainloop<C>(src, smem, nslab, acc, wm, wn, lane);
-  store_tile<C, false>(out, P, m0, n0, acc, wm, wn, lane);
+  store_tile<C, GEN>(out, P, m0, n0, acc, wm, wn, lane);
 }
 
-template <class C>
+// GEN: the epilogue applies out.alpha and out.accumulate (a separate instantiation, see store_tile)
+template <class C, bool GEN>
 __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) half_kernel(const double* __restrict__ B, int64_t naux, int nao,
                                                      int64_t npair, OpMap Cm, OutMap out, int64_t tilesM,
                                                      int64_t tilesN) {
   __shared__ double smem[2 * C::STAGE];
-  half_tile<C>(B, nao, npair, Cm, out, tilesM, tilesN, xcd_remap(blockIdx.x, tilesM * tilesN * naux), smem);
+  half_tile<C, GEN>(B, nao, npair, Cm, out, tilesM, tilesN, xcd_remap(blockIdx.x, tilesM * tilesN * naux), smem);
 }
 
 // Grouped half transform over several problems in one launch.  Work items of problem p are
@@ -695,7 +697,8 @@ __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2)))
 // fixed-order reduction (deterministic).
 __global__ void __launch_bounds__(256) jvec_kernel(const double* __restrict__ X, int64_t nao, int64_t ldx,
                                                    const double* __restrict__ Cm, const double* __restrict__ w,
-                                                   int64_t nocc, double* __restrict__ v, int64_t naux) {
+                                                   int64_t nocc, double* __restrict__ v, int64_t naux,
+                                                   int accumulate) {
   __shared__ double red[4];
   const int64_t P = blockIdx.x, z = blockIdx.y;
   const double* Xp = X + P * nao * ldx + z * nocc;
@@ -715,14 +718,18 @@ __global__ void __launch_bounds__(256) jvec_kernel(const double* __restrict__ X,
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) v[z * naux + P] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) {
+    const double r = (red[0] + red[1]) + (red[2] + red[3]);
+    v[z * naux + P] = accumulate ? v[z * naux + P] + r : r;
+  }
 }
 
 // J[z][i][j] = sum_P v[z][P] b^P_{ij}: one thread per packed pair, streaming B once.
 constexpr int kCoulombZ = 4;
 __global__ void __launch_bounds__(256) coulomb_kernel(const double* __restrict__ B, int64_t naux, int64_t nao,
                                                       int64_t npair, const double* __restrict__ v, int nz,
-                                                      int64_t vstride, double* __restrict__ J, int64_t jstride) {
+                                                      int64_t vstride, double* __restrict__ J, int64_t jstride,
+                                                      int accumulate) {
   __shared__ double vs[kCoulombZ][256];
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double acc[kCoulombZ] = {0.0, 0.0, 0.0, 0.0};
@@ -748,9 +755,21 @@ __global__ void __launch_bounds__(256) coulomb_kernel(const double* __restrict__
   while ((i + 1) * (i + 2) / 2 <= p) ++i;
   const int64_t j = p - i * (i + 1) / 2;
   for (int z = 0; z < nz; ++z) {
-    J[z * jstride + i * nao + j] = acc[z];
-    J[z * jstride + j * nao + i] = acc[z];
+    const double x = accumulate ? J[z * jstride + i * nao + j] + acc[z] : acc[z];   // J is symmetric
+    J[z * jstride + i * nao + j] = x;
+    J[z * jstride + j * nao + i] = x;
   }
+}
+
+__global__ void __launch_bounds__(256) add_kernel(const double* __restrict__ x, int64_t n, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] += x[i];
+}
+
+__global__ void __launch_bounds__(256) scale_cols_kernel(const double* __restrict__ X, int64_t n, int64_t ncol,
+                                                         const double* __restrict__ w, double* __restrict__ Xw) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) Xw[i] = X[i] * w[i % ncol];
 }
 
 // g[pair(i,j)] = G[i][j] + G[j][i] for i > j, G[i][i] on the diagonal
@@ -953,9 +972,13 @@ static hipError_t half_launch(const double* B, int64_t naux, int64_t nao, const 
   const int64_t tm = cdiv(nao, Cg::BM), tn = cdiv(cm.rows, Cg::BN);
   const int64_t nblk = tm * tn * naux;
   if (nblk == 0) return hipSuccess;
-  if (nblk > 0x7fffffffLL || !offsets_fit(cm) || out.alpha != 1.0 || out.accumulate) return hipErrorInvalidValue;
-  half_kernel<Cg><<<dim3((unsigned)nblk), dim3(Cg::NT), 0, s>>>(B, naux, (int)nao, nao * (nao + 1) / 2, cm, out,
-                                                                 tm, tn);
+  if (nblk > 0x7fffffffLL || !offsets_fit(cm)) return hipErrorInvalidValue;
+  if (out.alpha != 1.0 || out.accumulate)
+    half_kernel<Cg, true><<<dim3((unsigned)nblk), dim3(Cg::NT), 0, s>>>(B, naux, (int)nao, nao * (nao + 1) / 2, cm,
+                                                                       out, tm, tn);
+  else
+    half_kernel<Cg, false><<<dim3((unsigned)nblk), dim3(Cg::NT), 0, s>>>(B, naux, (int)nao, nao * (nao + 1) / 2, cm,
+                                                                        out, tm, tn);
   return hipGetLastError();
 }
 
@@ -1053,6 +1076,19 @@ static int balanced_splits(int64_t tiles, int64_t max_split) {
   return best;
 }
 
+// balanced_splits(tiles, m) for any m <= max_split is at most this: its search runs over
+// [lo, 4 lo] with lo <= kResident / tiles rounded up, and never past max_split.
+static int balanced_splits_bound(int64_t tiles, int64_t max_split) {
+  if (tiles <= 0 || max_split < 1) return 1;
+  const int64_t b = 4 * cdiv(kResident, tiles);
+  return (int)(max_split < b ? max_split : b);
+}
+
+int gemm_splits_bound(int64_t M, int64_t N, int64_t nslab) {
+  if (gemm_tall(M)) return balanced_splits_bound(2 * cdiv(M, CfgTall::BM) * cdiv(N, CfgTall::BN), nslab / 4);
+  return balanced_splits_bound(cdiv(M, CfgSq::BM) * cdiv(N, CfgSq::BN), nslab / 4);
+}
+
 int gemm_splits(int64_t M, int64_t N, int64_t nslab) {
   // at least four slabs per split; a tall tile takes the room of two resident workgroups
   if (gemm_tall(M)) return balanced_splits(2 * cdiv(M, CfgTall::BM) * cdiv(N, CfgTall::BN), nslab / 4);
@@ -1082,6 +1118,10 @@ static int half_reduce_tile_n(int64_t N) { return cdiv(N, 160) * 160 < cdiv(N, 1
 
 int half_reduce_splits(int64_t nao, int64_t N, int64_t naux) {
   return balanced_splits(cdiv(nao, CfgH176::BM) * cdiv(N, half_reduce_tile_n(N)), naux);
+}
+
+int half_reduce_splits_bound(int64_t nao, int64_t N, int64_t naux) {
+  return balanced_splits_bound(cdiv(nao, CfgH176::BM) * cdiv(N, half_reduce_tile_n(N)), naux);
 }
 
 template <class Cg>
@@ -1296,32 +1336,46 @@ hipError_t launch_syrk_group(const GroupSyrk* probs, int n, int tile, hipStream_
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_syrk_reduce(const double* Kpart, int nsplit, int64_t n, int64_t nz, double* K, hipStream_t s) {
+hipError_t launch_syrk_reduce(const double* Kpart, int nsplit, int64_t n, int64_t nz, double* K, hipStream_t s,
+                              int accumulate) {
   const int64_t tot = n * n * nz;
   if (tot == 0) return hipSuccess;
-  syrk_reduce_kernel<<<(unsigned)cdiv(tot, 256), 256, 0, s>>>(Kpart, nsplit, n, nz, K);
+  syrk_reduce_kernel<<<(unsigned)cdiv(tot, 256), 256, 0, s>>>(Kpart, nsplit, n, nz, K, accumulate);
   return hipGetLastError();
 }
 
 hipError_t launch_jvec(const double* X, int64_t naux, int64_t nao, int64_t ldx, const double* C, const double* w,
-                       int64_t nocc, int64_t nz, double* v, hipStream_t s) {
+                       int64_t nocc, int64_t nz, double* v, hipStream_t s, int accumulate) {
   if (naux == 0 || nz == 0) return hipSuccess;
   if (nz > 65535 || naux > 0x7fffffffLL) return hipErrorInvalidValue;
-  jvec_kernel<<<dim3((unsigned)naux, (unsigned)nz), 256, 0, s>>>(X, nao, ldx, C, w, nocc, v, naux);
+  jvec_kernel<<<dim3((unsigned)naux, (unsigned)nz), 256, 0, s>>>(X, nao, ldx, C, w, nocc, v, naux, accumulate);
   return hipGetLastError();
 }
 
 hipError_t launch_coulomb(const double* B, int64_t naux, int64_t nao, const double* v, int64_t nz, double* J,
-                          hipStream_t s) {
+                          hipStream_t s, int accumulate) {
   const int64_t npair = nao * (nao + 1) / 2;
   for (int64_t z0 = 0; z0 < nz; z0 += kCoulombZ) {
     const int nzc = (int)(nz - z0 < kCoulombZ ? nz - z0 : kCoulombZ);
     coulomb_kernel<<<(unsigned)cdiv(npair, 256), 256, 0, s>>>(B, naux, nao, npair, v + z0 * naux, nzc, naux,
-                                                               J + z0 * nao * nao, nao * nao);
+                                                               J + z0 * nao * nao, nao * nao, accumulate);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_add(const double* x, int64_t n, double* y, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  add_kernel<<<(unsigned)cdiv(n, 256), 256, 0, s>>>(x, n, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_cols(const double* X, int64_t n, int64_t ncol, const double* w, double* Xw, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (ncol <= 0) return hipErrorInvalidValue;
+  scale_cols_kernel<<<(unsigned)cdiv(n, 256), 256, 0, s>>>(X, n, ncol, w, Xw);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill_zero(double* p, int64_t n, hipStream_t s) {

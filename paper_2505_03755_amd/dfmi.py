@@ -36,11 +36,14 @@ DF_OP_BUILD_CHOLESKY = 11
 DF_OP_EMBED_CHOLESKY = 12
 
 DF_PAPA_FULL = 0x1
+DF_ACCUMULATE = 0x2
+DF_PREC_SPLIT = 0x4
 DF_CALLER_X = 0x10
 DF_BWD_GJ = 0x20
 DF_BWD_GK = 0x40
 DF_BWD_GERI = 0x80
 DF_SPLIT_K_FP64 = 0x100
+DF_WEIGHTED = 0x200
 
 KERNEL_KINDS = ["half_transform", "jvec", "coulomb", "k_syrk", "k_reduce", "mo_transform", "papa", "eri",
                 "other", "adjoint", "split", "build"]
@@ -51,7 +54,8 @@ EXPORTED = ["df_create", "df_destroy", "df_last_error", "df_set_stream", "df_set
             "df_split_cholesky", "df_step_split", "df_batched_workspace_size", "df_batched_step",
             "df_set_autotune", "df_batched_tuning", "df_batched_set_tuning", "df_split_cholesky_t",
             "df_step_backward_split", "df_batched_split_workspace_size", "df_batched_step_split",
-            "df_ppaa", "df_build_cholesky", "df_embed_cholesky"]
+            "df_ppaa", "df_build_cholesky", "df_embed_cholesky", "df_workspace_query", "df_set_scratch_limit",
+            "df_backward_chunk", "df_set_split_slices", "df_register_split"]
 
 
 class DFError(RuntimeError):
@@ -92,6 +96,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         L.df_set_stream.argtypes = [vp, vp]
         L.df_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
         L.df_workspace_size.argtypes = [i32, ctypes.POINTER(Dims), ctypes.POINTER(ctypes.c_size_t)]
+        L.df_workspace_query.argtypes = [vp, i32, ctypes.POINTER(Dims), ctypes.POINTER(ctypes.c_size_t)]
+        L.df_set_scratch_limit.argtypes = [vp, ctypes.c_size_t]
+        L.df_backward_chunk.argtypes = [vp, ctypes.POINTER(Dims), ctypes.POINTER(ctypes.c_int64)]
+        L.df_set_split_slices.argtypes = [vp, i32]
+        L.df_register_split.argtypes = [vp, dp, i64, i64, vp, vp, i32]
         L.df_set_timing.argtypes = [vp, i32]
         L.df_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), i32]
         L.df_half_transform.argtypes = [vp, dp, i64, i64, dp, i64, dp, dp, i64, dp, i32]
@@ -156,6 +165,8 @@ class Context:
         self._h = h
         self._ws = None
         self._lib = L
+        self.nslice = 7
+        self._splits = {}
 
     def close(self):
         if getattr(self, "_h", None):
@@ -182,11 +193,47 @@ class Context:
         stream = torch.cuda.current_stream(self.device)
         self.check(self._lib.df_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)))
 
+    def workspace_query(self, op: int, **dims) -> int:
+        """Workspace bytes of `op` for calls on this context (df_workspace_query: the context's
+        scratch limit and split slice count apply)."""
+        d = Dims(**{k: int(v) for k, v in dims.items()})
+        out = ctypes.c_size_t(0)
+        self.check(self._lib.df_workspace_query(self._h, op, ctypes.byref(d), ctypes.byref(out)))
+        return out.value
+
+    def set_scratch_limit(self, nbytes: int):
+        """Bound df_step_backward's workspace (0: none); the adjoint then runs in P chunks."""
+        self.check(self._lib.df_set_scratch_limit(self._h, int(nbytes)))
+
+    def backward_chunk(self, **dims) -> int:
+        """Auxiliary rows per chunk df_step_backward uses for these sizes (df_backward_chunk)."""
+        d = Dims(**{k: int(v) for k, v in dims.items()})
+        out = ctypes.c_int64(0)
+        self.check(self._lib.df_backward_chunk(self._h, ctypes.byref(d), ctypes.byref(out)))
+        return out.value
+
+    def set_split_slices(self, nslice: int):
+        """Slice count of the DF_PREC_SPLIT calls on this context."""
+        self.check(self._lib.df_set_split_slices(self._h, int(nslice)))
+        self.nslice = int(nslice)
+
+    def register_split(self, B, nao: int, Bs, Be):
+        """Register split_cholesky's planes of B for DF_PREC_SPLIT calls (nslice from Bs); Bs =
+        None removes the registration of B for the context's slice count."""
+        naux = _naux_of(B, nao)
+        if Bs is None:
+            self.check(self._lib.df_register_split(self._h, _ptr(B), naux, nao, None, None, self.nslice))
+            self._splits.pop((B.data_ptr(), self.nslice), None)
+            return
+        nslice = Bs.shape[0]
+        self.check(self._lib.df_register_split(self._h, _ptr(B), naux, nao, _ptr(Bs), _ptr(Be), nslice))
+        self._splits[(B.data_ptr(), nslice)] = (Bs, Be)   # kept alive while registered
+
     def prepare(self, op: int, **dims):
         """Bind the current torch stream and a workspace big enough for `op`."""
         import torch
         self.bind_stream()
-        need = workspace_size(op, **dims)
+        need = self.workspace_query(op, **dims)
         if need and (self._ws is None or self._ws.numel() < need):
             self._ws = None
             self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
@@ -247,29 +294,53 @@ def _naux_of(B, nao):
     return B.shape[0]
 
 
-def half_transform(B, nao: int, C, C2=None, ctx: Context | None = None):
-    """X[P] = b^P C (Eq. ao2mo_1); with C2 also Y[P] = C2^T X[P] (Eq. ao2mo_2)."""
+def _flags(accumulate: bool, split: bool) -> int:
+    return (DF_ACCUMULATE if accumulate else 0) | (DF_PREC_SPLIT if split else 0)
+
+
+def _out(name, t, shape, dev, accumulate):
+    """The caller's output tensor (required with accumulate) or a new one."""
     import torch
+    if t is None:
+        if accumulate:
+            raise ValueError(f"accumulate needs the output {name}")
+        return torch.empty(shape, dtype=torch.float64, device=dev)
+    _check_tensor(name, t, dev)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}")
+    return t
+
+
+def half_transform(B, nao: int, C, C2=None, out=None, accumulate=False, split=False, ctx: Context | None = None):
+    """X[P] = b^P C (Eq. ao2mo_1); with C2 also Y[P] = C2^T X[P] (Eq. ao2mo_2).
+
+    out: X, or (X, Y) with C2, to write into; accumulate adds to them (DF_ACCUMULATE).  split runs
+    the products in split precision against the planes registered for B (DF_PREC_SPLIT)."""
     ctx = ctx or context(B.device)
     for n, t in (("B", B), ("C", C), ("C2", C2)):
         _check_tensor(n, t, ctx.device)
     naux = _naux_of(B, nao)
     ncol = C.shape[1]
-    X = torch.empty((naux, nao, ncol), dtype=torch.float64, device=ctx.device)
+    Xo, Yo = (out if C2 is not None else (out, None)) if out is not None else (None, None)
+    X = _out("X", Xo, (naux, nao, ncol), ctx.device, accumulate)
     Y = None
     n2 = 0
     if C2 is not None:
         n2 = C2.shape[1]
-        Y = torch.empty((naux, n2, ncol), dtype=torch.float64, device=ctx.device)
-    ctx.prepare(DF_OP_HALF_TRANSFORM, naux=naux, nao=nao, ncol=ncol, n2=n2)
+        Y = _out("Y", Yo, (naux, n2, ncol), ctx.device, accumulate)
+    fl = _flags(accumulate, split)
+    ctx.prepare(DF_OP_HALF_TRANSFORM, naux=naux, nao=nao, ncol=ncol, n2=n2, flags=fl)
     ctx.check(ctx._lib.df_half_transform(ctx.handle, _ptr(B), naux, nao, _ptr(C), ncol, _ptr(X),
-                                         _ptr(C2), n2, _ptr(Y), 0))
+                                         _ptr(C2), n2, _ptr(Y), fl))
     return (X, Y) if C2 is not None else X
 
 
-def jk(B, nao: int, Cocc, w=None, want_j=True, want_k=True, want_v=True, ctx: Context | None = None):
-    """JK call for D_k = C_k diag(w_k) C_k^T; Cocc is [nao, nocc] or [ndm, nao, nocc]."""
-    import torch
+def jk(B, nao: int, Cocc, w=None, want_j=True, want_k=True, want_v=True, out=None, accumulate=False, split=False,
+       ctx: Context | None = None):
+    """JK call for D_k = C_k diag(w_k) C_k^T; Cocc is [nao, nocc] or [ndm, nao, nocc].
+
+    out: dict with any of "J", "K" [ndm, nao, nao] and "v" [ndm, naux] to write into (accumulate
+    adds to them); split: DF_PREC_SPLIT against the planes registered for B."""
     ctx = ctx or context(B.device)
     for n, t in (("B", B), ("Cocc", Cocc), ("w", w)):
         _check_tensor(n, t, ctx.device)
@@ -281,37 +352,46 @@ def jk(B, nao: int, Cocc, w=None, want_j=True, want_k=True, want_v=True, ctx: Co
         raise ValueError("Cocc rows must equal nao")
     if w is not None and w.numel() != ndm * nocc:
         raise ValueError("w must have ndm*nocc entries")
-    J = torch.empty((ndm, nao, nao), dtype=torch.float64, device=ctx.device) if want_j else None
-    K = torch.empty((ndm, nao, nao), dtype=torch.float64, device=ctx.device) if want_k else None
-    v = torch.empty((ndm, naux), dtype=torch.float64, device=ctx.device) if want_v else None
-    ctx.prepare(DF_OP_JK, naux=naux, nao=nao, ndm=ndm, nocc=nocc)
+    o = out or {}
+    dev = ctx.device
+    J = _out("J", o.get("J"), (ndm, nao, nao), dev, accumulate) if want_j else None
+    K = _out("K", o.get("K"), (ndm, nao, nao), dev, accumulate) if want_k else None
+    v = _out("v", o.get("v"), (ndm, naux), dev, accumulate) if want_v else None
+    fl = _flags(accumulate, split)
+    ctx.prepare(DF_OP_JK, naux=naux, nao=nao, ndm=ndm, nocc=nocc,
+                flags=fl | (DF_WEIGHTED if w is not None else 0))
     ctx.check(ctx._lib.df_jk(ctx.handle, _ptr(B), naux, nao, ndm, _ptr(C3), nocc, _ptr(w),
-                             _ptr(J), _ptr(K), _ptr(v), 0))
-    if single:
+                             _ptr(J), _ptr(K), _ptr(v), fl))
+    if single and out is None:
         J = J[0] if J is not None else None
         K = K[0] if K is not None else None
         v = v[0] if v is not None else None
     return J, K, v
 
 
-def active_eri(B, nao: int, Cact, return_buv=False, ctx: Context | None = None):
-    """(uv|wx) = sum_P b^P_uv b^P_wx with b^P_uv = (Cact^T b^P Cact)_uv."""
-    import torch
+def active_eri(B, nao: int, Cact, return_buv=False, out=None, accumulate=False, split=False,
+               ctx: Context | None = None):
+    """(uv|wx) = sum_P b^P_uv b^P_wx with b^P_uv = (Cact^T b^P Cact)_uv.
+
+    out: eri, or (eri, buv) with return_buv, to write into (accumulate adds to them); split:
+    DF_PREC_SPLIT against the planes registered for B."""
     ctx = ctx or context(B.device)
     for n, t in (("B", B), ("Cact", Cact)):
         _check_tensor(n, t, ctx.device)
     naux = _naux_of(B, nao)
     nac = Cact.shape[1]
-    eri = torch.empty((nac,) * 4, dtype=torch.float64, device=ctx.device)
-    buv = torch.empty((naux, nac, nac), dtype=torch.float64, device=ctx.device) if return_buv else None
-    ctx.prepare(DF_OP_ACTIVE_ERI, naux=naux, nao=nao, nac=nac)
-    ctx.check(ctx._lib.df_active_eri(ctx.handle, _ptr(B), naux, nao, _ptr(Cact), nac, _ptr(eri), _ptr(buv), 0))
+    eo, bo = (out if return_buv else (out, None)) if out is not None else (None, None)
+    eri = _out("eri", eo, (nac,) * 4, ctx.device, accumulate)
+    buv = _out("buv", bo, (naux, nac, nac), ctx.device, accumulate) if return_buv else None
+    fl = _flags(accumulate, split)
+    ctx.prepare(DF_OP_ACTIVE_ERI, naux=naux, nao=nao, nac=nac, flags=fl)
+    ctx.check(ctx._lib.df_active_eri(ctx.handle, _ptr(B), naux, nao, _ptr(Cact), nac, _ptr(eri), _ptr(buv), fl))
     return (eri, buv) if return_buv else eri
 
 
-def papa(B, nao: int, Cp, Cact, Cq=None, ctx: Context | None = None):
-    """(pu|vw) by default; with Cq the (pu|qv) block of Eq. (papa)."""
-    import torch
+def papa(B, nao: int, Cp, Cact, Cq=None, out=None, accumulate=False, split=False, ctx: Context | None = None):
+    """(pu|vw) by default; with Cq the (pu|qv) block of Eq. (papa).  out / accumulate / split as in
+    active_eri."""
     ctx = ctx or context(B.device)
     for n, t in (("B", B), ("Cp", Cp), ("Cact", Cact), ("Cq", Cq)):
         _check_tensor(n, t, ctx.device)
@@ -320,13 +400,15 @@ def papa(B, nao: int, Cp, Cact, Cq=None, ctx: Context | None = None):
     flags, nq = 0, 0
     if Cq is not None:
         flags, nq = DF_PAPA_FULL, Cq.shape[1]
-        out = torch.empty((np_, nac, nq, nac), dtype=torch.float64, device=ctx.device)
+        shape = (np_, nac, nq, nac)
     else:
-        out = torch.empty((np_, nac, nac, nac), dtype=torch.float64, device=ctx.device)
+        shape = (np_, nac, nac, nac)
+    res = _out("out", out, shape, ctx.device, accumulate)
+    flags |= _flags(accumulate, split)
     ctx.prepare(DF_OP_PAPA, naux=naux, nao=nao, nac=nac, np=np_, nq=nq, flags=flags)
     ctx.check(ctx._lib.df_papa(ctx.handle, _ptr(B), naux, nao, _ptr(Cp), np_, _ptr(Cact), nac, _ptr(Cq), nq,
-                               _ptr(out), flags))
-    return out
+                               _ptr(res), flags))
+    return res
 
 
 def ppaa(B, nao: int, Cp, Cact, Cq=None, ctx: Context | None = None):

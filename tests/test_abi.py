@@ -114,13 +114,13 @@ def test_active_eri_and_papa_argument_errors(L, ctx):
     B, C, E = fake(1 << 30), fake(2 << 30), fake(3 << 30)
     assert L.df_active_eri(ctx, B, 10, 7, None, 2, E, None, 0) == dfmi.DF_ERR_ARG
     assert L.df_active_eri(ctx, B, 10, 7, C, -1, E, None, 0) == dfmi.DF_ERR_SHAPE
-    assert L.df_active_eri(ctx, B, 10, 7, C, 2, E, None, 4) == dfmi.DF_ERR_UNSUPPORTED
+    assert L.df_active_eri(ctx, B, 10, 7, C, 2, E, None, dfmi.DF_PAPA_FULL) == dfmi.DF_ERR_UNSUPPORTED
     # nac = 0: nothing to compute, no workspace needed, no device touched
     assert L.df_active_eri(ctx, B, 10, 7, None, 0, None, None, 0) == dfmi.DF_OK
     Cp, Ca, O = fake(4 << 30), fake(5 << 30), fake(6 << 30)
     assert L.df_papa(ctx, B, 10, 7, Cp, 7, Ca, 2, fake(7 << 30), 3, O, 0) == dfmi.DF_ERR_ARG   # Cq without FULL
     assert L.df_papa(ctx, B, 10, 7, Cp, 7, Ca, 2, None, 3, O, dfmi.DF_PAPA_FULL) == dfmi.DF_ERR_ARG
-    assert L.df_papa(ctx, B, 10, 7, Cp, 7, Ca, 2, None, 0, O, 2) == dfmi.DF_ERR_UNSUPPORTED
+    assert L.df_papa(ctx, B, 10, 7, Cp, 7, Ca, 2, None, 0, O, 0x8) == dfmi.DF_ERR_UNSUPPORTED
     assert L.df_papa(ctx, B, 10, 7, Cp, 7, Ca, 2, None, 0, O, 0) == dfmi.DF_ERR_WORKSPACE
     assert L.df_papa(ctx, B, 10, 7, Cp, 0, Ca, 2, None, 0, O, 0) == dfmi.DF_OK      # empty output
 
@@ -365,3 +365,88 @@ def test_batched_split_argument_errors(L, ctx):
     assert L.df_batched_step_split(ctx, arr, bad, be, 2, 7, 0) == dfmi.DF_ERR_ARG
     bad = (ctypes.c_void_p * 2)(1 << 34, None)
     assert L.df_batched_step_split(ctx, arr, bad, be, 2, 7, 0) == dfmi.DF_ERR_ARG
+
+
+def test_accumulate_and_split_flags(L, ctx):
+    """DF_ACCUMULATE and DF_PREC_SPLIT on the four calls: flag checks, the registration of the split of
+    B per context and slice count, and the workspace each flag needs."""
+    B, C, J, K = fake(1 << 30), fake(2 << 30), fake(3 << 30), fake(4 << 30)
+    Bs, Be = fake(5 << 30), fake(6 << 30)
+    SP, AC = dfmi.DF_PREC_SPLIT, dfmi.DF_ACCUMULATE
+    assert L.df_jk(ctx, B, 10, 7, 1, C, 3, None, J, K, None, 0x8) == dfmi.DF_ERR_UNSUPPORTED
+    # split precision without a registered split of B
+    assert L.df_jk(ctx, B, 10, 7, 1, C, 3, None, J, K, None, SP) == dfmi.DF_ERR_ARG
+    assert b"df_register_split" in L.df_last_error(ctx)
+    assert L.df_half_transform(ctx, B, 10, 7, C, 2, J, None, 0, None, SP) == dfmi.DF_ERR_ARG
+    assert L.df_active_eri(ctx, B, 10, 7, C, 2, J, None, SP) == dfmi.DF_ERR_ARG
+    assert L.df_papa(ctx, B, 10, 7, C, 7, fake(7 << 30), 2, None, 0, J, SP) == dfmi.DF_ERR_ARG
+    # registration checks
+    reg = L.df_register_split
+    assert reg(ctx, None, 10, 7, Bs, Be, 7) == dfmi.DF_ERR_ARG
+    assert reg(ctx, B, 10, 7, Bs, Be, 3) == dfmi.DF_ERR_SHAPE
+    assert reg(ctx, B, 10, 7, fake((5 << 30) + 8), Be, 7) == dfmi.DF_ERR_ARG       # Bs unaligned
+    assert reg(ctx, B, 10, 7, Bs, None, 7) == dfmi.DF_ERR_ARG
+    assert reg(ctx, B, 10, 7, Bs, Be, 7) == dfmi.DF_OK
+    # registered: the call gets past the argument checks and stops at the missing workspace
+    assert L.df_jk(ctx, B, 10, 7, 1, C, 3, None, J, K, None, SP) == dfmi.DF_ERR_WORKSPACE
+    # the split planes are inputs: an output overlapping them is refused
+    assert L.df_jk(ctx, B, 10, 7, 1, C, 3, None, fake((5 << 30) + 64), K, None, SP) == dfmi.DF_ERR_ARG
+    # another slice count on the context: the 7-slice registration no longer applies
+    assert L.df_set_split_slices(ctx, 9) == dfmi.DF_ERR_SHAPE
+    assert L.df_set_split_slices(ctx, 5) == dfmi.DF_OK
+    assert L.df_jk(ctx, B, 10, 7, 1, C, 3, None, J, K, None, SP) == dfmi.DF_ERR_ARG
+    assert L.df_set_split_slices(ctx, 7) == dfmi.DF_OK
+    assert reg(ctx, B, 10, 7, None, None, 7) == dfmi.DF_OK                          # removed
+    assert L.df_jk(ctx, B, 10, 7, 1, C, 3, None, J, K, None, SP) == dfmi.DF_ERR_ARG
+    for i in range(16):
+        assert reg(ctx, fake((20 + i) << 30), 10, 7, Bs, Be, 7) == dfmi.DF_OK
+    assert reg(ctx, fake(40 << 30), 10, 7, Bs, Be, 7) == dfmi.DF_ERR_ARG            # at most 16
+    # accumulation with nothing to add (nocc = 0) touches nothing
+    assert L.df_jk(ctx, B, 10, 7, 1, C, 0, None, J, K, None, AC) == dfmi.DF_OK
+    # workspaces: the split forms need planes, accumulation with a second transform the new X
+    ws = lambda op, **d: dfmi.workspace_size(op, **d)
+    assert ws(dfmi.DF_OP_JK, naux=10, nao=7, ndm=2, nocc=3, flags=SP, nslice=7) > 0
+    assert (ws(dfmi.DF_OP_JK, naux=10, nao=7, ndm=2, nocc=3, flags=SP | dfmi.DF_WEIGHTED, nslice=7)
+            > ws(dfmi.DF_OP_JK, naux=10, nao=7, ndm=2, nocc=3, flags=SP, nslice=7))
+    with pytest.raises(dfmi.DFError):
+        ws(dfmi.DF_OP_JK, naux=10, nao=7, ndm=2, nocc=3, flags=SP)                 # nslice missing
+    h0 = ws(dfmi.DF_OP_HALF_TRANSFORM, naux=10, nao=7, ncol=3, n2=4)
+    assert ws(dfmi.DF_OP_HALF_TRANSFORM, naux=10, nao=7, ncol=3, n2=4, flags=AC) - h0 >= 10 * 7 * 3 * 8
+    assert ws(dfmi.DF_OP_HALF_TRANSFORM, naux=10, nao=7, ncol=3, flags=AC) == ws(
+        dfmi.DF_OP_HALF_TRANSFORM, naux=10, nao=7, ncol=3)
+    # df_workspace_query takes the context's slice count for nslice = 0
+    d = dfmi.Dims(naux=10, nao=7, nac=2, np=7, flags=SP)
+    n = ctypes.c_size_t(0)
+    assert L.df_workspace_query(ctx, dfmi.DF_OP_PAPA, ctypes.byref(d), ctypes.byref(n)) == dfmi.DF_OK
+    assert n.value == ws(dfmi.DF_OP_PAPA, naux=10, nao=7, nac=2, np=7, flags=SP, nslice=7)
+    assert L.df_set_split_slices(ctx, 5) == dfmi.DF_OK
+    assert L.df_workspace_query(ctx, dfmi.DF_OP_PAPA, ctypes.byref(d), ctypes.byref(n)) == dfmi.DF_OK
+    assert n.value == ws(dfmi.DF_OP_PAPA, naux=10, nao=7, nac=2, np=7, flags=SP, nslice=5)
+
+
+def test_scratch_limit_chunks_the_adjoint(L, ctx):
+    """df_set_scratch_limit: the adjoint's rows per chunk grow with the bound, the workspace stays
+    within it, and a bound below one row is refused before any launch."""
+    fl = dfmi.DF_BWD_GJ | dfmi.DF_BWD_GK | dfmi.DF_BWD_GERI
+    dims = dict(naux=37, nao=50, nocc=6, nac=3, flags=fl)
+    full = dfmi.workspace_size(dfmi.DF_OP_STEP_BACKWARD, **dims)
+    d = dfmi.Dims(**dims)
+    rows, n = ctypes.c_int64(0), ctypes.c_size_t(0)
+    assert L.df_backward_chunk(ctx, ctypes.byref(d), ctypes.byref(rows)) == dfmi.DF_OK and rows.value == 37
+    assert L.df_workspace_query(ctx, dfmi.DF_OP_STEP_BACKWARD, ctypes.byref(d), ctypes.byref(n)) == dfmi.DF_OK
+    assert n.value == full
+    last = 0
+    for limit in (full * 3 // 10, full // 2, full * 7 // 10, full):
+        assert L.df_set_scratch_limit(ctx, limit) == dfmi.DF_OK
+        assert L.df_backward_chunk(ctx, ctypes.byref(d), ctypes.byref(rows)) == dfmi.DF_OK
+        assert L.df_workspace_query(ctx, dfmi.DF_OP_STEP_BACKWARD, ctypes.byref(d), ctypes.byref(n)) == dfmi.DF_OK
+        assert 1 <= rows.value <= 37 and n.value <= limit and rows.value >= last
+        last = rows.value
+    assert last == 37
+    assert L.df_set_scratch_limit(ctx, 1024) == dfmi.DF_OK                          # below one row
+    assert L.df_backward_chunk(ctx, ctypes.byref(d), ctypes.byref(rows)) == dfmi.DF_ERR_WORKSPACE
+    assert L.df_workspace_query(ctx, dfmi.DF_OP_STEP_BACKWARD, ctypes.byref(d), ctypes.byref(n)) == dfmi.DF_ERR_WORKSPACE
+    B, Co, Ca, gJ, gK, dCo, dCa = (fake(k << 30) for k in range(1, 8))
+    assert L.df_step_backward(ctx, B, 37, 50, Co, 6, Ca, 3, gJ, gK, None, None, None, dCo, dCa, 0) == dfmi.DF_ERR_WORKSPACE
+    assert b"scratch limit" in L.df_last_error(ctx)
+    assert L.df_set_scratch_limit(ctx, 0) == dfmi.DF_OK
