@@ -95,3 +95,27 @@ def test_identity_active_columns_give_raw_eri_entries():
     eri, _ = O.active_eri(B, nao, Cact)
     eri4 = brute.eri4(B, nao)
     np.testing.assert_allclose(eri, eri4[np.ix_(idx, idx, idx, idx)], rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("nao,naux", [(1, 1), (3, 5), (7, 4), (12, 3)])
+def test_second_transform_against_explicit_loops(nao, naux):
+    """Eq. (ao2mo_2) after Eq. (ao2mo_1): Y[P, p, c] = sum_mu C2[mu, p] sum_nu b^P_{mu nu} C[nu, c], by
+    explicit loops over the brute-force unpacked b^P; and its contraction over P equals the
+    4-index transform of (mu nu|lam sig) (so the P index is not transposed with another)."""
+    B, C, rng = _inputs(nao, naux, 41)
+    ncol, n2 = max(1, nao // 2), max(1, nao - 1)
+    Cr, C2 = C[:, :ncol], rng.standard_normal((nao, n2))
+    Y = O.second_transform(O.half_transform(B, nao, Cr), C2)
+    Bd = brute.dense_B(B, nao)
+    ref = np.zeros((naux, n2, ncol))
+    for P in range(naux):
+        for p in range(n2):
+            for c in range(ncol):
+                s = 0.0
+                for mu in range(nao):
+                    for nu in range(nao):
+                        s += C2[mu, p] * Bd[P, mu, nu] * Cr[nu, c]
+                ref[P, p, c] = s
+    np.testing.assert_allclose(Y, ref, rtol=0, atol=1e-12 * max(1.0, np.abs(ref).max()))
+    eri = brute.transform4(brute.eri4(B, nao), C2, Cr, C2, Cr)
+    np.testing.assert_allclose(np.einsum("Ppc,Pqd->pcqd", Y, Y), eri, rtol=0, atol=1e-11 * max(1.0, np.abs(eri).max()))
