@@ -51,11 +51,16 @@ def unpack(bp: np.ndarray, nao: int) -> np.ndarray:
     bp = np.asarray(bp, dtype=np.float64)
     if bp.shape[-1] != npair(nao):
         raise ValueError("packed length does not match nao")
-    out = np.zeros(bp.shape[:-1] + (nao, nao))
-    il, jl = np.tril_indices(nao)       # row-major lower order: (0,0),(1,0),(1,1),(2,0)...
-    out[..., il, jl] = bp
-    out[..., jl, il] = bp
-    return out
+    lead = bp.shape[:-1]
+    flat = bp.reshape((-1, bp.shape[-1]))
+    out = np.zeros((flat.shape[0], nao, nao))
+    for i in range(nao):                # row i holds (i, 0), (i, 1), ..., (i, i)
+        out[:, i, :i + 1] = flat[:, i * (i + 1) // 2:i * (i + 1) // 2 + i + 1]
+    d = np.arange(nao)
+    for m in out:                       # lower + its transpose (upper zero): the mirror; the
+        m += m.T.copy()                 # doubled diagonal is halved again (both exact)
+        m[d, d] *= 0.5
+    return out.reshape(lead + (nao, nao))
 
 
 def iter_unpacked(B: np.ndarray, nao: int, chunk: int = DEFAULT_CHUNK):

@@ -68,16 +68,16 @@ def step_pass(chunks, naux: int, nao: int, C: np.ndarray, nocc: int, nac: int, h
         vb = np.einsum("pij,ij->p", Bd, D)                         # Eq. (J_1)
         v[p0:p0 + n] = vb
         J += np.tensordot(vb, Bd, axes=(0, 0))                     # Eq. (J_2)
-        X = np.matmul(Bd, Cocc)                                    # b^P C_occ
-        M = np.matmul(Cocc.T[None], X)                             # C_occ^T b^P C_occ
-        KC += np.matmul(X, M.transpose(0, 2, 1)).sum(axis=0)       # sum_P X_P X_P^T C_occ
+        X = np.tensordot(Bd, Cocc, axes=(2, 0))                   # X_P = b^P C_occ, [n, nao, nocc]
+        M = np.tensordot(Cocc, X, axes=(0, 1)).transpose(1, 0, 2)  # M_P = C_occ^T b^P C_occ
+        KC += np.tensordot(X, M, axes=([0, 2], [0, 2]))           # sum_P X_P M_P^T = sum_P X_P X_P^T C_occ
         trDK.extend((M * M).sum(axis=(1, 2)).tolist())
         if want_K:
             K += np.tensordot(X, X, axes=([0, 2], [0, 2]))
-        Xa = np.matmul(Bd, Cact)                                   # b^P C_act
-        bu = np.matmul(Cact.T[None], Xa)                           # b^P_uv
+        Xa = np.tensordot(Bd, Cact, axes=(2, 0))                  # b^P C_act
+        bu = np.tensordot(Cact, Xa, axes=(0, 1)).transpose(1, 0, 2)   # b^P_uv
         buv[p0:p0 + n] = bu
-        bpu[p0:p0 + n] = np.matmul(Cp.T[None], Xa)                 # b^P_pu, p in p_rows
+        bpu[p0:p0 + n] = np.tensordot(Cp, Xa, axes=(0, 1)).transpose(1, 0, 2)   # b^P_pu, p in p_rows
         Z = (bu.reshape(n, nac * nac) @ Gm.T).reshape(n, nac, nac)  # Z_P[u,v] = sum_wx Gamma_uvwx b_wx
         Gact += 2.0 * np.einsum("pmv,pvu->mu", Xa, Z)
         seen += n
