@@ -228,6 +228,24 @@ df_status df_jk(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int64_t
                 double* J, double* K, double* v, int flags);
 
 /*
+ * df_jk without any allocation, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments, results
+ * and checks as df_jk in FP64; flags: DF_ACCUMULATE only (DF_PREC_SPLIT is DF_ERR_UNSUPPORTED).
+ * No workspace is attached or used: the scratch is one 128 MiB device array inside the library
+ * (one copy per GPU, held until the process ends; its address is looked up once per device on the
+ * first call there).  The auxiliary rows run in blocks whose workspace fits it (J and K add up
+ * over the blocks, so the sums are ordered differently from df_jk's: equal to rounding);
+ * DF_ERR_WORKSPACE when a single auxiliary row does not fit (about ndm (nao^2 + 2 nao nocc) doubles
+ * must stay below 128 MiB).
+ * Every call on one GPU shares that array, and it keeps the last call's contents: calls that may
+ * overlap on one GPU (two streams, two contexts, two threads) race and must be serialised by the
+ * caller.  Calls no hipMalloc, hipFree or other allocating routine, and records no timing events.
+ */
+df_status df_jk_noalloc(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int64_t ndm,
+                        const double* Cocc, int64_t nocc, const double* w,
+                        double* J, double* K, double* v, int flags);
+
+/*
  * Active-space ERIs:  b_uv[P][u][v] = (Cact^T b^P Cact)_{uv},
  *                     eri[u][v][w][x] = sum_P b_uv[P][u][v] b_uv[P][w][x]
  *   Cact [nao][nac] (input); eri [nac]^4 (output); buv [naux][nac][nac] (output or NULL)

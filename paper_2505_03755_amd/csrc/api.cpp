@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -311,7 +312,9 @@ struct JkPlan {
   int64_t xplane;   // bytes of the planes of one density's X_occ
   int nsplit;
 };
-JkPlan plan_jk(Plan& pl, int64_t naux, int64_t nao, int64_t ndm, int64_t nocc, bool weighted, int flags, int nslice) {
+// nsplit_fp64 > 0 sizes the FP64 K partials for that many splits instead of the call's own count.
+JkPlan plan_jk(Plan& pl, int64_t naux, int64_t nao, int64_t ndm, int64_t nocc, bool weighted, int flags, int nslice,
+               int nsplit_fp64 = 0) {
   JkPlan p{};
   const bool sp = flags & DF_PREC_SPLIT;
   const int64_t ncol = ndm * nocc;
@@ -319,7 +322,7 @@ JkPlan plan_jk(Plan& pl, int64_t naux, int64_t nao, int64_t ndm, int64_t nocc, b
   p.x = pl.take(naux * nao * ncol);
   p.vtmp = pl.take(ndm * naux);
   if (!sp) {
-    p.nsplit = dfk::syrk_splits(nao, naux, ndm);
+    p.nsplit = nsplit_fp64 > 0 ? nsplit_fp64 : dfk::syrk_splits(nao, naux, ndm);
   } else {
     p.cs = take_split(pl, ncol, nao, nslice);
     p.xplane = nocc > 0 ? dfk::split_plane_bytes(nao, naux * nocc, nslice) : 0;
@@ -334,6 +337,41 @@ JkPlan plan_jk(Plan& pl, int64_t naux, int64_t nao, int64_t ndm, int64_t nocc, b
   }
   p.kpart = pl.take((int64_t)p.nsplit * ndm * nao * nao);
   return p;
+}
+
+// ---- the static scratch of df_jk_noalloc ----
+// df_jk_noalloc runs the JK call in blocks of auxiliary rows whose workspace fits this array, so it
+// never allocates.  Host code must not pass `scratch` itself to a kernel (its name is a host-side
+// stand-in there); it uses the address hipGetSymbolAddress returns on each device.
+constexpr size_t kNoallocBytes = size_t(128) << 20;
+static __device__ __align__(256) char scratch[kNoallocBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_addr;   // device -> address of `scratch` there
+
+// K split count of df_jk_noalloc's blocks of r auxiliary rows: at most 4, so that the K partials
+// leave room for X; non-decreasing in r.
+int noalloc_jk_splits(int64_t nao, int64_t r, int64_t ndm) {
+  return std::min(dfk::syrk_splits_bound(nao, r, ndm), 4);
+}
+
+// Auxiliary rows per block of df_jk_noalloc (FP64): the most whose workspace fits the scratch.  The
+// workspace grows with the rows (the split count does not fall), so every block, the ragged last
+// one too, fits; 0 when one row does not fit.
+int64_t noalloc_jk_rows(int64_t naux, int64_t nao, int64_t ndm, int64_t nocc, bool weighted) {
+  auto need = [&](int64_t r) {
+    Plan pl;
+    plan_jk(pl, r, nao, ndm, nocc, weighted, 0, 0, noalloc_jk_splits(nao, r, ndm));
+    return pl.total;
+  };
+  if (need(1) > kNoallocBytes) return 0;
+  int64_t lo = 1, hi = naux;   // need(lo) fits
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    if (need(mid) <= kNoallocBytes) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
 
 // df_active_eri: X_act AO-major [nao][naux][nac], b_uv of this call.  Split: planes of the rows u
@@ -1146,47 +1184,14 @@ df_status df_half_transform(df_ctx* ctx, const double* B, int64_t naux, int64_t 
   return DF_OK;
 }
 
-df_status df_jk(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int64_t ndm, const double* Cocc,
-                int64_t nocc, const double* w, double* J, double* K, double* v, int flags) {
-  df_ctx* c = ctx;
-  if (check_ctx(c)) return DF_ERR_ARG;
-  if (df_status s = check_core(c, B, naux, nao)) return s;
-  if (flags & ~(DF_ACCUMULATE | DF_PREC_SPLIT)) return fail(c, DF_ERR_UNSUPPORTED, "df_jk: unknown flags");
-  if (ndm < 1 || ndm > 65535) return fail(c, DF_ERR_SHAPE, "ndm must be in [1, 65535]");
-  if (nocc < 0) return fail(c, DF_ERR_SHAPE, "nocc must be >= 0");
-  if (nocc > 0 && !Cocc) return fail(c, DF_ERR_ARG, "Cocc is NULL");
-  const bool acc = flags & DF_ACCUMULATE, sp = flags & DF_PREC_SPLIT;
-  const int64_t npair = nao * (nao + 1) / 2, ncol = ndm * nocc;
-  std::vector<Range> rs = {{B, dbytes(naux * npair), "B", false},
-                           {Cocc, dbytes(ndm * nao * nocc), "Cocc", false},
-                           {w, dbytes(ndm * nocc), "w", false},
-                           {J, dbytes(ndm * nao * nao), "J", true},
-                           {K, dbytes(ndm * nao * nao), "K", true},
-                           {v, dbytes(ndm * naux), "v", true}};
-  const bool work = nocc > 0 && (J || K || v);
-  const df_ctx::SplitReg* reg = nullptr;
-  if (sp && work) {
-    if (df_status s = split_for_call(c, B, naux, nao, std::max(ncol, nao), &reg, rs)) return s;
-    if (naux * nocc > (int64_t(1) << 30)) return fail(c, DF_ERR_SHAPE, "naux * nocc too large for the split path");
-  }
-  Plan pl;
-  const JkPlan p = plan_jk(pl, naux, nao, ndm, nocc, w != nullptr, flags, c->nslice);
-  if (work) {
-    if (!check_overlap(c, rs)) return DF_ERR_ARG;
-    if (df_status s = need_ws(c, pl.total)) return s;
-    rs.push_back({c->ws, pl.total, "workspace", true});
-  }
-  if (!check_overlap(c, rs)) return DF_ERR_ARG;
-  if (nocc == 0 && acc) return DF_OK;   // nothing to add
-  if (df_status s = enter(c)) return s;
-  if (nocc == 0) {
-    if (J) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(J, ndm * nao * nao, c->stream), "fill");
-    if (K) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(K, ndm * nao * nao, c->stream), "fill");
-    if (v) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(v, ndm * naux, c->stream), "fill");
-    return DF_OK;
-  }
-  if (!work) return DF_OK;
-  char* ws = c->ws;
+// The JK call on workspace `ws` laid out by plan p (already checked): X of the densities, v of
+// this call (row stride ldv in v), J and K.  acc_jk adds J and K to the outputs, acc_v adds v; v of
+// this call alone feeds J.  reg: the registered planes of B (split precision) or null (FP64).
+static df_status jk_run(df_ctx* c, char* ws, const JkPlan& p, const double* B, int64_t naux, int64_t nao, int64_t ndm,
+                        const double* Cocc, int64_t nocc, const double* w, double* J, double* K, double* v,
+                        int64_t ldv, bool acc_jk, bool acc_v, const df_ctx::SplitReg* reg) {
+  const bool sp = reg != nullptr;
+  const int64_t ncol = ndm * nocc;
   double* X = (double*)(ws + p.x);
   if (!sp) {
     double* cc = (double*)(ws + p.ccat);
@@ -1205,16 +1210,21 @@ df_status df_jk(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int64_t
   }
   if (J || v) {
     // v of this call (into v itself unless it is to be added to v)
-    double* vv = v && !acc ? v : (double*)(ws + p.vtmp);
-    DF_LAUNCH(DF_KERNEL_JVEC, dfk::launch_jvec(X, naux, nao, ncol, Cocc, w, nocc, ndm, vv, c->stream), "J-vector launch");
+    const bool direct = v && !acc_v;
+    double* vv = direct ? v : (double*)(ws + p.vtmp);
+    const int64_t ldvv = direct ? ldv : naux;
+    DF_LAUNCH(DF_KERNEL_JVEC, dfk::launch_jvec(X, naux, nao, ncol, Cocc, w, nocc, ndm, vv, c->stream, 0, ldvv),
+              "J-vector launch");
     if (J)
-      DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_coulomb(B, naux, nao, vv, ndm, J, c->stream, acc), "Coulomb launch");
-    if (v && acc) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_add(vv, ndm * naux, v, c->stream), "add launch");
+      DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_coulomb(B, naux, nao, vv, ndm, J, c->stream, acc_jk, ldvv),
+                "Coulomb launch");
+    if (v && acc_v)
+      DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_copy_rows(vv, ndm, naux, v, ldv, 1, c->stream), "add launch");
   }
   if (K) {
     double* kpart = (double*)(ws + p.kpart);
     if (!sp) {
-      if (df_status s = run_k(c, X, w, naux, nao, ncol, nocc, ndm, p.nsplit, kpart, K, acc)) return s;
+      if (df_status s = run_k(c, X, w, naux, nao, ncol, nocc, ndm, p.nsplit, kpart, K, acc_jk)) return s;
     } else {
       // K_z = sum_{P, c} X[P][m][(z, c)] w_zc X[P][n][(z, c)]: the rows m of each density's X_occ
       // over (P, c), against those of X diag(w) when there are weights; lower tiles, reduced and
@@ -1243,11 +1253,126 @@ df_status df_jk(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int64_t
                                                c->nslice, dfk::out_plain(kpart, nao, nao, nao), true, p.nsplit, kpart,
                                                ndm, zs, c->stream),
                 "slice product launch");
-      DF_LAUNCH(DF_KERNEL_K_REDUCE, dfk::launch_syrk_reduce(kpart, p.nsplit, nao, ndm, K, c->stream, acc),
+      DF_LAUNCH(DF_KERNEL_K_REDUCE, dfk::launch_syrk_reduce(kpart, p.nsplit, nao, ndm, K, c->stream, acc_jk),
                 "K reduce launch");
     }
   }
   return DF_OK;
+}
+
+// Arguments of the JK call shared by df_jk and df_jk_noalloc; fills the ranges it reads and writes.
+static df_status jk_check(df_ctx* c, const double* B, int64_t naux, int64_t nao, int64_t ndm, const double* Cocc,
+                          int64_t nocc, const double* w, double* J, double* K, double* v, std::vector<Range>& rs) {
+  if (df_status s = check_core(c, B, naux, nao)) return s;
+  if (ndm < 1 || ndm > 65535) return fail(c, DF_ERR_SHAPE, "ndm must be in [1, 65535]");
+  if (nocc < 0) return fail(c, DF_ERR_SHAPE, "nocc must be >= 0");
+  if (nocc > 0 && !Cocc) return fail(c, DF_ERR_ARG, "Cocc is NULL");
+  const int64_t npair = nao * (nao + 1) / 2;
+  rs = {{B, dbytes(naux * npair), "B", false},
+        {Cocc, dbytes(ndm * nao * nocc), "Cocc", false},
+        {w, dbytes(ndm * nocc), "w", false},
+        {J, dbytes(ndm * nao * nao), "J", true},
+        {K, dbytes(ndm * nao * nao), "K", true},
+        {v, dbytes(ndm * naux), "v", true}};
+  return DF_OK;
+}
+
+// nocc = 0: every output is zero (or, accumulating, unchanged)
+static df_status jk_empty(df_ctx* c, int64_t naux, int64_t nao, int64_t ndm, double* J, double* K, double* v,
+                          bool acc) {
+  if (acc) return DF_OK;
+  if (J) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(J, ndm * nao * nao, c->stream), "fill");
+  if (K) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(K, ndm * nao * nao, c->stream), "fill");
+  if (v) DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_fill_zero(v, ndm * naux, c->stream), "fill");
+  return DF_OK;
+}
+
+df_status df_jk(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int64_t ndm, const double* Cocc,
+                int64_t nocc, const double* w, double* J, double* K, double* v, int flags) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (flags & ~(DF_ACCUMULATE | DF_PREC_SPLIT)) return fail(c, DF_ERR_UNSUPPORTED, "df_jk: unknown flags");
+  std::vector<Range> rs;
+  if (df_status s = jk_check(c, B, naux, nao, ndm, Cocc, nocc, w, J, K, v, rs)) return s;
+  const bool acc = flags & DF_ACCUMULATE, sp = flags & DF_PREC_SPLIT;
+  const int64_t ncol = ndm * nocc;
+  const bool work = nocc > 0 && (J || K || v);
+  const df_ctx::SplitReg* reg = nullptr;
+  if (sp && work) {
+    if (df_status s = split_for_call(c, B, naux, nao, std::max(ncol, nao), &reg, rs)) return s;
+    if (naux * nocc > (int64_t(1) << 30)) return fail(c, DF_ERR_SHAPE, "naux * nocc too large for the split path");
+  }
+  Plan pl;
+  const JkPlan p = plan_jk(pl, naux, nao, ndm, nocc, w != nullptr, flags, c->nslice);
+  if (work) {
+    if (!check_overlap(c, rs)) return DF_ERR_ARG;
+    if (df_status s = need_ws(c, pl.total)) return s;
+    rs.push_back({c->ws, pl.total, "workspace", true});
+  }
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (nocc == 0 && acc) return DF_OK;   // nothing to add
+  if (df_status s = enter(c)) return s;
+  if (nocc == 0) return jk_empty(c, naux, nao, ndm, J, K, v, acc);
+  if (!work) return DF_OK;
+  return jk_run(c, c->ws, p, B, naux, nao, ndm, Cocc, nocc, w, J, K, v, naux, acc, acc, reg);
+}
+
+// Address of the static scratch on the context's device (current after enter()), looked up once
+// per device.
+static df_status scratch_address(df_ctx* c, char** addr) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_addr.find(c->device);
+  if (it != g_scratch_addr.end()) {
+    *addr = it->second;
+    return DF_OK;
+  }
+  void* ptr = nullptr;
+  DF_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+  if (!ptr || (uintptr_t)ptr % kAlign != 0) return fail(c, DF_ERR_HIP, "the static scratch has no aligned address");
+  g_scratch_addr[c->device] = (char*)ptr;
+  *addr = (char*)ptr;
+  return DF_OK;
+}
+
+df_status df_jk_noalloc(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int64_t ndm, const double* Cocc,
+                        int64_t nocc, const double* w, double* J, double* K, double* v, int flags) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (flags & ~DF_ACCUMULATE) return fail(c, DF_ERR_UNSUPPORTED, "df_jk_noalloc takes DF_ACCUMULATE only");
+  std::vector<Range> rs;
+  if (df_status s = jk_check(c, B, naux, nao, ndm, Cocc, nocc, w, J, K, v, rs)) return s;
+  const bool acc = flags & DF_ACCUMULATE;
+  const bool work = nocc > 0 && (J || K || v);
+  int64_t rows = 0;
+  if (work) {
+    rows = noalloc_jk_rows(naux, nao, ndm, nocc, w != nullptr);
+    if (rows == 0)
+      return fail(c, DF_ERR_WORKSPACE, "df_jk_noalloc: one auxiliary row needs more than the " +
+                                           std::to_string(kNoallocBytes >> 20) + " MiB static scratch");
+  }
+  if (!check_overlap(c, rs)) return DF_ERR_ARG;
+  if (nocc == 0 && acc) return DF_OK;
+  if (df_status s = enter(c)) return s;
+  if (nocc == 0) return jk_empty(c, naux, nao, ndm, J, K, v, acc);
+  if (!work) return DF_OK;
+  char* ws = nullptr;
+  if (df_status s = scratch_address(c, &ws)) return s;
+  // no timing events here: the first ones of a context would be created (allocated) on demand
+  const bool timing = c->timing;
+  c->timing = false;
+  const int64_t npair = nao * (nao + 1) / 2;
+  const int nsplit = noalloc_jk_splits(nao, rows, ndm);
+  df_status st = DF_OK;
+  for (int64_t p0 = 0; p0 < naux && st == DF_OK; p0 += rows) {
+    const int64_t r = std::min(rows, naux - p0);
+    Plan pl;
+    const JkPlan p = plan_jk(pl, r, nao, ndm, nocc, w != nullptr, 0, c->nslice, nsplit);
+    // J and K add up over the blocks; each block writes its own columns of v
+    st = jk_run(c, ws, p, B + p0 * npair, r, nao, ndm, Cocc, nocc, w, J, K, v ? v + p0 : nullptr, naux,
+                acc || p0 > 0, acc, nullptr);
+  }
+  c->timing = timing;
+  return st;
 }
 
 // b^P_{lu} = sum_mu Cl[mu][l] X^act[mu][P][u] for every P into out [naux][nl][nac], from int8

@@ -100,6 +100,8 @@ hipError_t launch_symmetrize(const double* in, int64_t n, int64_t nz, double* ou
 // for tile(i) >= tile(j) (Bw = A with an optional per-kc weight).  Kpart is dense [nsplit][nz][n][n];
 // syrk_splits() gives the number of splits the workspace is planned for.
 int syrk_splits(int64_t n, int64_t kb_n, int64_t nz);
+// The most splits syrk_splits(n, k, nz) gives for any k <= kb_n.
+int syrk_splits_bound(int64_t n, int64_t kb_n, int64_t nz);
 // SYRK tile edge for an n x n result (64 up to n = 640, else 128); a group uses the edge of its
 // largest member.
 int syrk_tile_for(int64_t n);
@@ -110,14 +112,19 @@ hipError_t launch_syrk_partial(const OpMap& A, const OpMap& Bw, int64_t n, int64
 hipError_t launch_syrk_reduce(const double* Kpart, int nsplit, int64_t n, int64_t nz, double* K,
                               hipStream_t s, int accumulate = 0);
 
-// v[z][P] = sum_{m<nao, c<nocc} C[z][m][c] w[z][c] X[P][m][z*nocc + c]   (X row stride ldx;
-// added to v when `accumulate`)
+// v[z][P] = sum_{m<nao, c<nocc} C[z][m][c] w[z][c] X[P][m][z*nocc + c]   (X row stride ldx; v row
+// stride ldv, naux when 0; added to v when `accumulate`)
 hipError_t launch_jvec(const double* X, int64_t naux, int64_t nao, int64_t ldx, const double* C,
-                       const double* w, int64_t nocc, int64_t nz, double* v, hipStream_t s, int accumulate = 0);
+                       const double* w, int64_t nocc, int64_t nz, double* v, hipStream_t s, int accumulate = 0,
+                       int64_t ldv = 0);
 
-// J[z][i][j] = sum_P v[z][P] b^P_{ij}, both triangles written (added to J when `accumulate`).
+// J[z][i][j] = sum_P v[z][P] b^P_{ij}, both triangles written (added to J when `accumulate`; v row
+// stride ldv, naux when 0).
 hipError_t launch_coulomb(const double* B, int64_t naux, int64_t nao, const double* v,
-                          int64_t nz, double* J, hipStream_t s, int accumulate = 0);
+                          int64_t nz, double* J, hipStream_t s, int accumulate = 0, int64_t ldv = 0);
+// y[r][c] = x[r][c] (or += with `accumulate`) for x [rows][cols] contiguous, y of row stride ldy
+hipError_t launch_copy_rows(const double* x, int64_t rows, int64_t cols, double* y, int64_t ldy, int accumulate,
+                            hipStream_t s);
 
 // y[i] += x[i], i < n
 hipError_t launch_add(const double* x, int64_t n, double* y, hipStream_t s);

@@ -697,7 +697,7 @@ __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2)))
 // fixed-order reduction (deterministic).
 __global__ void __launch_bounds__(256) jvec_kernel(const double* __restrict__ X, int64_t nao, int64_t ldx,
                                                    const double* __restrict__ Cm, const double* __restrict__ w,
-                                                   int64_t nocc, double* __restrict__ v, int64_t naux,
+                                                   int64_t nocc, double* __restrict__ v, int64_t ldv,
                                                    int accumulate) {
   __shared__ double red[4];
   const int64_t P = blockIdx.x, z = blockIdx.y;
@@ -720,7 +720,7 @@ __global__ void __launch_bounds__(256) jvec_kernel(const double* __restrict__ X,
   __syncthreads();
   if (threadIdx.x == 0) {
     const double r = (red[0] + red[1]) + (red[2] + red[3]);
-    v[z * naux + P] = accumulate ? v[z * naux + P] + r : r;
+    v[z * ldv + P] = accumulate ? v[z * ldv + P] + r : r;
   }
 }
 
@@ -764,6 +764,15 @@ __global__ void __launch_bounds__(256) coulomb_kernel(const double* __restrict__
 __global__ void __launch_bounds__(256) add_kernel(const double* __restrict__ x, int64_t n, double* __restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) y[i] += x[i];
+}
+
+// y[r][c] (+)= x[r][c] for a contiguous x [rows][cols] and y of row stride ldy
+__global__ void __launch_bounds__(256) copy_rows_kernel(const double* __restrict__ x, int64_t rows, int64_t cols,
+                                                        double* __restrict__ y, int64_t ldy, int accumulate) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= rows * cols) return;
+  double* d = y + (i / cols) * ldy + i % cols;
+  *d = accumulate ? *d + x[i] : x[i];
 }
 
 __global__ void __launch_bounds__(256) scale_cols_kernel(const double* __restrict__ X, int64_t n, int64_t ncol,
@@ -1201,6 +1210,11 @@ int syrk_splits(int64_t n, int64_t kb_n, int64_t nz) {
   return balanced_splits(T * (T + 1) / 2 * (nz > 0 ? nz : 1), kb_n);
 }
 
+int syrk_splits_bound(int64_t n, int64_t kb_n, int64_t nz) {
+  const int64_t T = cdiv(n, syrk_tile_for(n));
+  return balanced_splits_bound(T * (T + 1) / 2 * (nz > 0 ? nz : 1), kb_n < 4096 ? kb_n : 4096);
+}
+
 template <class Cg>
 static hipError_t syrk_go(const OpMap& A, const OpMap& Bw, int64_t n, int64_t nz, int nsplit, double* Kpart,
                           hipStream_t s) {
@@ -1345,19 +1359,22 @@ hipError_t launch_syrk_reduce(const double* Kpart, int nsplit, int64_t n, int64_
 }
 
 hipError_t launch_jvec(const double* X, int64_t naux, int64_t nao, int64_t ldx, const double* C, const double* w,
-                       int64_t nocc, int64_t nz, double* v, hipStream_t s, int accumulate) {
+                       int64_t nocc, int64_t nz, double* v, hipStream_t s, int accumulate, int64_t ldv) {
   if (naux == 0 || nz == 0) return hipSuccess;
-  if (nz > 65535 || naux > 0x7fffffffLL) return hipErrorInvalidValue;
-  jvec_kernel<<<dim3((unsigned)naux, (unsigned)nz), 256, 0, s>>>(X, nao, ldx, C, w, nocc, v, naux, accumulate);
+  if (nz > 65535 || naux > 0x7fffffffLL || (ldv != 0 && ldv < naux)) return hipErrorInvalidValue;
+  jvec_kernel<<<dim3((unsigned)naux, (unsigned)nz), 256, 0, s>>>(X, nao, ldx, C, w, nocc, v, ldv ? ldv : naux,
+                                                                  accumulate);
   return hipGetLastError();
 }
 
 hipError_t launch_coulomb(const double* B, int64_t naux, int64_t nao, const double* v, int64_t nz, double* J,
-                          hipStream_t s, int accumulate) {
+                          hipStream_t s, int accumulate, int64_t ldv) {
   const int64_t npair = nao * (nao + 1) / 2;
+  if (ldv == 0) ldv = naux;
+  if (ldv < naux) return hipErrorInvalidValue;
   for (int64_t z0 = 0; z0 < nz; z0 += kCoulombZ) {
     const int nzc = (int)(nz - z0 < kCoulombZ ? nz - z0 : kCoulombZ);
-    coulomb_kernel<<<(unsigned)cdiv(npair, 256), 256, 0, s>>>(B, naux, nao, npair, v + z0 * naux, nzc, naux,
+    coulomb_kernel<<<(unsigned)cdiv(npair, 256), 256, 0, s>>>(B, naux, nao, npair, v + z0 * ldv, nzc, ldv,
                                                                J + z0 * nao * nao, nao * nao, accumulate);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1368,6 +1385,14 @@ hipError_t launch_coulomb(const double* B, int64_t naux, int64_t nao, const doub
 hipError_t launch_add(const double* x, int64_t n, double* y, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   add_kernel<<<(unsigned)cdiv(n, 256), 256, 0, s>>>(x, n, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_rows(const double* x, int64_t rows, int64_t cols, double* y, int64_t ldy, int accumulate,
+                            hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  if (ldy < cols) return hipErrorInvalidValue;
+  copy_rows_kernel<<<(unsigned)cdiv(rows * cols, 256), 256, 0, s>>>(x, rows, cols, y, ldy, accumulate);
   return hipGetLastError();
 }
 

@@ -55,7 +55,7 @@ EXPORTED = ["df_create", "df_destroy", "df_last_error", "df_set_stream", "df_set
             "df_set_autotune", "df_batched_tuning", "df_batched_set_tuning", "df_split_cholesky_t",
             "df_step_backward_split", "df_batched_split_workspace_size", "df_batched_step_split",
             "df_ppaa", "df_build_cholesky", "df_embed_cholesky", "df_workspace_query", "df_set_scratch_limit",
-            "df_backward_chunk", "df_set_split_slices", "df_register_split"]
+            "df_backward_chunk", "df_set_split_slices", "df_register_split", "df_jk_noalloc"]
 
 
 class DFError(RuntimeError):
@@ -105,6 +105,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         L.df_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), i32]
         L.df_half_transform.argtypes = [vp, dp, i64, i64, dp, i64, dp, dp, i64, dp, i32]
         L.df_jk.argtypes = [vp, dp, i64, i64, i64, dp, i64, dp, dp, dp, dp, i32]
+        L.df_jk_noalloc.argtypes = [vp, dp, i64, i64, i64, dp, i64, dp, dp, dp, dp, i32]
         L.df_active_eri.argtypes = [vp, dp, i64, i64, dp, i64, dp, dp, i32]
         L.df_papa.argtypes = [vp, dp, i64, i64, dp, i64, dp, i64, dp, i64, dp, i32]
         L.df_ppaa.argtypes = [vp, dp, i64, i64, dp, i64, dp, i64, dp, i64, dp, i32]
@@ -366,6 +367,27 @@ def jk(B, nao: int, Cocc, w=None, want_j=True, want_k=True, want_v=True, out=Non
         J = J[0] if J is not None else None
         K = K[0] if K is not None else None
         v = v[0] if v is not None else None
+    return J, K, v
+
+
+def jk_noalloc(B, nao: int, Cocc, w=None, out=None, accumulate=False, ctx: Context | None = None):
+    """df_jk_noalloc: the FP64 JK call on the library's static scratch (no workspace, no allocation in
+    the library).  Cocc is [ndm, nao, nocc]; out: dict with any of "J", "K" [ndm, nao, nao] and
+    "v" [ndm, naux], each written (or added to with accumulate); missing entries are not computed."""
+    ctx = ctx or context(B.device)
+    for n, t in (("B", B), ("Cocc", Cocc), ("w", w)):
+        _check_tensor(n, t, ctx.device)
+    naux = _naux_of(B, nao)
+    if Cocc.dim() != 3 or Cocc.shape[1] != nao:
+        raise ValueError("Cocc must be [ndm, nao, nocc]")
+    ndm, nocc = Cocc.shape[0], Cocc.shape[2]
+    o = out or {}
+    J = _out("J", o["J"], (ndm, nao, nao), ctx.device, accumulate) if "J" in o else None
+    K = _out("K", o["K"], (ndm, nao, nao), ctx.device, accumulate) if "K" in o else None
+    v = _out("v", o["v"], (ndm, naux), ctx.device, accumulate) if "v" in o else None
+    ctx.bind_stream()
+    ctx.check(ctx._lib.df_jk_noalloc(ctx.handle, _ptr(B), naux, nao, ndm, _ptr(Cocc), nocc, _ptr(w),
+                                     _ptr(J), _ptr(K), _ptr(v), DF_ACCUMULATE if accumulate else 0))
     return J, K, v
 
 

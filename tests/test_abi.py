@@ -450,3 +450,22 @@ def test_scratch_limit_chunks_the_adjoint(L, ctx):
     assert L.df_step_backward(ctx, B, 37, 50, Co, 6, Ca, 3, gJ, gK, None, None, None, dCo, dCa, 0) == dfmi.DF_ERR_WORKSPACE
     assert b"scratch limit" in L.df_last_error(ctx)
     assert L.df_set_scratch_limit(ctx, 0) == dfmi.DF_OK
+
+
+def test_jk_noalloc_argument_errors(L, ctx):
+    B, C, J = fake(1 << 20), fake(1 << 30), fake(1 << 34)
+    # only DF_ACCUMULATE is taken
+    assert L.df_jk_noalloc(ctx, B, 8, 5, 1, C, 2, None, J, None, None, dfmi.DF_PREC_SPLIT) == dfmi.DF_ERR_UNSUPPORTED
+    assert L.df_jk_noalloc(ctx, B, 8, 5, 0, C, 2, None, J, None, None, 0) == dfmi.DF_ERR_SHAPE
+    assert L.df_jk_noalloc(ctx, B, 8, 5, 1, C, -1, None, J, None, None, 0) == dfmi.DF_ERR_SHAPE
+    assert L.df_jk_noalloc(ctx, None, 8, 5, 1, C, 2, None, J, None, None, 0) == dfmi.DF_ERR_ARG
+    assert L.df_jk_noalloc(ctx, B, 8, 5, 1, None, 2, None, J, None, None, 0) == dfmi.DF_ERR_ARG
+    # one auxiliary row of two densities at nao 3000 needs 2 * 3000^2 doubles of K partials: more
+    # than the 128 MiB scratch, rejected before any HIP call
+    st = L.df_jk_noalloc(ctx, B, 1, 3000, 2, C, 1, None, None, fake(1 << 40), None, 0)
+    assert st == dfmi.DF_ERR_WORKSPACE
+    assert b"static scratch" in L.df_last_error(ctx)
+    # an output overlapping an input
+    assert L.df_jk_noalloc(ctx, B, 8, 5, 1, C, 2, None, fake((1 << 20) + 64), None, None, 0) == dfmi.DF_ERR_ARG
+    # nothing to add: returns before touching the device
+    assert L.df_jk_noalloc(ctx, B, 8, 5, 1, C, 0, None, J, None, None, dfmi.DF_ACCUMULATE) == dfmi.DF_OK
