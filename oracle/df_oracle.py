@@ -26,13 +26,15 @@ invariants.  Parity unpinned: none.
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
 __all__ = [
     "npair", "unpack", "iter_unpacked", "density", "half_transform",
     "second_transform", "jvec", "coulomb", "exchange", "exchange_paper_route",
-    "jk", "mo_vectors", "active_eri", "papa", "papa_full", "ppaa", "fsum_dot",
+    "jk", "jk_many", "mo_vectors", "active_eri", "papa", "papa_full", "ppaa", "fsum_dot",
 ]
 
 DEFAULT_CHUNK = 240   # the P-block size the paper keeps (PySCF default)
@@ -43,10 +45,31 @@ def npair(nao: int) -> int:
     return nao * (nao + 1) // 2
 
 
+def _unpack_rows(flat: np.ndarray, out: np.ndarray, nao: int) -> None:
+    """Fill out[k] (zeros on entry) with the symmetric matrix of packed row flat[k]."""
+    for i in range(nao):                # row i holds (i, 0), (i, 1), ..., (i, i)
+        out[:, i, :i + 1] = flat[:, i * (i + 1) // 2:i * (i + 1) // 2 + i + 1]
+    d = np.arange(nao)
+    for m in out:                       # lower + its transpose (upper zero): the mirror; the
+        m += m.T.copy()                 # doubled diagonal is halved again (both exact)
+        m[d, d] *= 0.5
+
+
+_POOL: ThreadPoolExecutor | None = None
+
+
+def _pool() -> ThreadPoolExecutor:
+    global _POOL
+    if _POOL is None:
+        _POOL = ThreadPoolExecutor(max(1, min(8, len(os.sched_getaffinity(0)))))
+    return _POOL
+
+
 def unpack(bp: np.ndarray, nao: int) -> np.ndarray:
     """Packed lower-triangular row(s) -> dense symmetric matrix/matrices.
 
-    bp has shape (..., npair); entry i*(i+1)//2 + j holds element (i, j), i >= j.
+    bp has shape (..., npair); entry i*(i+1)//2 + j holds element (i, j), i >= j.  Large batches
+    are unpacked by several threads, each on its own rows (a copy: the values do not depend on it).
     """
     bp = np.asarray(bp, dtype=np.float64)
     if bp.shape[-1] != npair(nao):
@@ -54,12 +77,14 @@ def unpack(bp: np.ndarray, nao: int) -> np.ndarray:
     lead = bp.shape[:-1]
     flat = bp.reshape((-1, bp.shape[-1]))
     out = np.zeros((flat.shape[0], nao, nao))
-    for i in range(nao):                # row i holds (i, 0), (i, 1), ..., (i, i)
-        out[:, i, :i + 1] = flat[:, i * (i + 1) // 2:i * (i + 1) // 2 + i + 1]
-    d = np.arange(nao)
-    for m in out:                       # lower + its transpose (upper zero): the mirror; the
-        m += m.T.copy()                 # doubled diagonal is halved again (both exact)
-        m[d, d] *= 0.5
+    n = flat.shape[0]
+    nw = min(_pool()._max_workers, n) if n * nao * nao >= (1 << 24) else 1
+    if nw > 1:
+        cuts = [n * k // nw for k in range(nw + 1)]
+        list(_pool().map(lambda k: _unpack_rows(flat[cuts[k]:cuts[k + 1]], out[cuts[k]:cuts[k + 1]], nao),
+                         range(nw)))
+    else:
+        _unpack_rows(flat, out, nao)
     return out.reshape(lead + (nao, nao))
 
 
@@ -148,6 +173,25 @@ def jk(B: np.ndarray, nao: int, Cocc: np.ndarray, w: np.ndarray | None = None,
     v = jvec(B, nao, D, chunk)
     J = coulomb(B, nao, v, chunk)
     K = exchange(B, nao, Cocc, w, chunk)
+    return J, K, v
+
+
+def jk_many(B: np.ndarray, nao: int, Cs, chunk: int = DEFAULT_CHUNK):
+    """The JK call of many densities D_k = C_k C_k^T at once, each b^P unpacked once: returns
+    (J, K, v) with J, K [ndm, nao, nao], v [ndm, naux], each density's as in jk() (Eqs. J_1, J_2
+    and the factored K)."""
+    Cs = [np.asarray(C, dtype=np.float64) for C in Cs]
+    ndm, naux = len(Cs), B.shape[0]
+    Ds = [C @ C.T for C in Cs]
+    J = np.zeros((ndm, nao, nao))
+    K = np.zeros((ndm, nao, nao))
+    v = np.empty((ndm, naux))
+    for p0, p1, Bd in iter_unpacked(B, nao, chunk):
+        for k in range(ndm):
+            v[k, p0:p1] = np.einsum("pij,ij->p", Bd, Ds[k])      # Eq. (J_1)
+            J[k] += np.tensordot(v[k, p0:p1], Bd, axes=(0, 0))    # Eq. (J_2)
+            X = np.matmul(Bd, Cs[k])                              # b^P C_k
+            K[k] += np.tensordot(X, X, axes=([0, 2], [0, 2]))     # sum_P (b^P C_k)(b^P C_k)^T
     return J, K, v
 
 

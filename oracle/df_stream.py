@@ -13,7 +13,7 @@ block at a time.  With C_occ, C_act the occupied and active columns of C and D =
   X_P        = b^P C_occ  (the half transform, Eq. ao2mo_1)
   K C_occ    = sum_P X_P (X_P^T C_occ)                               Eqs. (K_1)-(K_2), gamma = D
   tr(D K)    = sum_P || C_occ^T b^P C_occ ||_F^2
-  K (full, optional) = sum_P X_P X_P^T
+  K (full, optional) = sum_P X_P X_P^T, or rows of it: K[i, :] = sum_P X_P[i, :] X_P^T
   b_uv       = C_act^T b^P C_act,  (uv|wx) = sum_P b^P_uv b^P_wx      Eq. (ao2mo_2), the (aa|aa) block
   (pu|vw)    = sum_P b^P_pu b^P_vw for the requested rows p           the g^{pa}_{aa} pattern
   E          = tr(D h) + 1/2 tr(D J) - 1/4 tr(D K) + 1/2 sum (uv|wx) Gamma
@@ -40,10 +40,11 @@ def host_chunks(B: np.ndarray, chunk: int = O.DEFAULT_CHUNK):
 
 
 def step_pass(chunks, naux: int, nao: int, C: np.ndarray, nocc: int, nac: int, h: np.ndarray,
-              Gamma: np.ndarray, p_rows=(), want_K: bool = False) -> dict:
+              Gamma: np.ndarray, p_rows=(), want_K: bool = False, k_rows=()) -> dict:
     """The quantities listed in the module docstring from one pass over the blocks of B.
 
-    Returns a dict with v [naux], J, KC = K C_occ [nao, nocc], K (with want_K), buv [naux, nac, nac],
+    Returns a dict with v [naux], J, KC = K C_occ [nao, nocc], K (with want_K), K_rows = K[k_rows, :]
+    [len(k_rows), nao], buv [naux, nac, nac],
     eri [nac]^4, papa_rows [len(p_rows), nac, nac, nac] ((pu|vw) for p in p_rows), the energy terms
     E_h, E_J, E_K, E_eri and E, and G = dE/dC [nao, nmo] (columns past nocc + nac zero)."""
     C = np.asarray(C, dtype=np.float64)
@@ -55,6 +56,8 @@ def step_pass(chunks, naux: int, nao: int, C: np.ndarray, nocc: int, nac: int, h
     J = np.zeros((nao, nao))
     KC = np.zeros((nao, nocc))
     K = np.zeros((nao, nao)) if want_K else None
+    kr = list(k_rows)
+    Kr = np.zeros((len(kr), nao))
     buv = np.empty((naux, nac, nac))
     bpu = np.empty((naux, len(p_rows), nac))
     Gact = np.zeros((nao, nac))
@@ -74,6 +77,8 @@ def step_pass(chunks, naux: int, nao: int, C: np.ndarray, nocc: int, nac: int, h
         trDK.extend((M * M).sum(axis=(1, 2)).tolist())
         if want_K:
             K += np.tensordot(X, X, axes=([0, 2], [0, 2]))
+        if kr:
+            Kr += np.tensordot(X[:, kr, :], X, axes=([0, 2], [0, 2]))   # sum_P X_P[i, :] X_P^T
         Xa = np.tensordot(Bd, Cact, axes=(2, 0))                  # b^P C_act
         bu = np.tensordot(Cact, Xa, axes=(0, 1)).transpose(1, 0, 2)   # b^P_uv
         buv[p0:p0 + n] = bu
@@ -96,6 +101,8 @@ def step_pass(chunks, naux: int, nao: int, C: np.ndarray, nocc: int, nac: int, h
            "E_K": E_K, "E_eri": E_eri, "E": math.fsum([E_h, E_J, E_K, E_eri]), "G": G}
     if want_K:
         out["K"] = K
+    if kr:
+        out["K_rows"] = Kr
     return out
 
 

@@ -47,6 +47,22 @@ def test_jk_vs_bruteforce(nao, naux):
 
 
 @pytest.mark.parametrize("nao,naux", SIZES)
+def test_jk_many_vs_bruteforce(nao, naux):
+    """Several densities with one unpack per P block (a block size that splits the P range
+    unevenly): each J, K, v against the 4-index definitions of its own density."""
+    B, C, rng = _inputs(nao, naux, 3)
+    eri = brute.eri4(B, nao)
+    Cs = [np.linalg.qr(rng.standard_normal((nao, k)))[0] for k in (1, max(1, nao // 2), nao)]
+    J, K, v = O.jk_many(B, nao, Cs, chunk=2)
+    dense = brute.dense_B(B, nao)
+    for k, Ck in enumerate(Cs):
+        D = Ck @ Ck.T
+        np.testing.assert_allclose(J[k], brute.coulomb(eri, D), rtol=0, atol=1e-12 * max(1.0, np.abs(J[k]).max()))
+        np.testing.assert_allclose(K[k], brute.exchange(eri, D), rtol=0, atol=1e-12 * max(1.0, np.abs(K[k]).max()))
+        np.testing.assert_allclose(v[k], np.einsum("pij,ij->p", dense, D), rtol=0, atol=1e-12 * max(1.0, np.abs(v[k]).max()))
+
+
+@pytest.mark.parametrize("nao,naux", SIZES)
 def test_half_and_second_transform_vs_explicit(nao, naux):
     B, C, _ = _inputs(nao, naux, 3)
     Bd = brute.dense_B(B, nao)

@@ -43,8 +43,10 @@ def prob():
 def test_pass_against_bruteforce(prob, chunk):
     nao, naux, nocc, nac, B, C, h, Gam = prob
     p_rows = [0, 4, 8]
-    r = S.step_pass(S.host_chunks(B, chunk), naux, nao, C, nocc, nac, h, Gam, p_rows=p_rows, want_K=True)
+    r = S.step_pass(S.host_chunks(B, chunk), naux, nao, C, nocc, nac, h, Gam, p_rows=p_rows, want_K=True,
+                    k_rows=[8, 0, 5])
     E, J, K, eri = brute_energy(B, nao, C, nocc, nac, h, Gam)
+    np.testing.assert_allclose(r["K_rows"], K[[8, 0, 5]], atol=1e-12 * np.abs(K).max())
     Cocc, Cact = C[:, :nocc], C[:, nocc:nocc + nac]
     np.testing.assert_allclose(r["J"], J, atol=1e-12 * np.abs(J).max())
     np.testing.assert_allclose(r["K"], K, atol=1e-12 * np.abs(K).max())
