@@ -255,3 +255,56 @@ def test_fragment_shapes_with_ppaa():
         assert rel(o["ppaa"], packed_uv(O.ppaa(p["B"], p["nao"], p["Cp"], p["Cp"], p["Cact"]))) <= 1e-10
     for dp, o in zip(dps[3:], outs[3:]):
         assert torch.equal(o["ppaa"], dfmi.ppaa(dp["B"], dp["nao"], dp["Cp"], dp["Cact"]))
+
+
+# The fragment workload as the benchmark times it: 64 densities per problem.  The oracle covers
+# every density of the three smallest problems and densities 0, 31 and 63 of the others.
+SAMPLED_Z = (0, 31, 63)
+
+
+def fragment_probs(ndm):
+    probs = []
+    for f in synth.FRAGMENTS:
+        B, Cd, C = synth.fragment_problem(f, ndm=ndm)
+        probs.append({"B": B, "nao": f.nemb, "Cocc": Cd, "Cact": C[:, f.nocc:f.nocc + f.nac], "Cp": C})
+    return probs
+
+
+@pytest.fixture(scope="module")
+def frag64():
+    probs = fragment_probs(64)
+    refs = []
+    for i, p in enumerate(probs):
+        zs = list(range(64)) if i < 3 else list(SAMPLED_Z)
+        J, K, _ = O.jk_many(p["B"], p["nao"], [p["Cocc"][z] for z in zs])
+        jk = {z: (J[k], K[k]) for k, z in enumerate(zs)}
+        refs.append({"jk": jk, "eri": O.active_eri(p["B"], p["nao"], p["Cact"])[0],
+                     "papa": O.papa_full(p["B"], p["nao"], p["Cp"], p["Cact"], p["Cp"])})
+    return probs, [to_dev(p) for p in probs], refs
+
+
+def check_frag64(outs, refs, tol):
+    for i, (o, r) in enumerate(zip(outs, refs)):
+        for z, (J, K) in r["jk"].items():
+            assert rel(o["J"][z], J) <= tol, (i, z)
+            assert rel(o["K"][z], K) <= tol, (i, z)
+            assert torch.equal(o["K"][z], o["K"][z].T)
+        assert rel(o["eri"], r["eri"]) <= tol, i
+        assert rel(o["papa"], r["papa"]) <= tol, i
+
+
+def test_fragment_workload_64_densities(frag64):
+    """The benchmarked fragment batch (J of 64 densities through V B^T, K of each) in FP64."""
+    probs, dps, refs = frag64
+    outs = dfmi.batched_step(dps)
+    torch.cuda.synchronize()
+    check_frag64(outs, refs, 1e-10)
+
+
+@pytest.mark.parametrize("k_fp64", [False, True])
+def test_fragment_workload_64_densities_split(frag64, k_fp64):
+    """The same batch in split precision (7 slices), K from int8 slices or in FP64."""
+    probs, dps, refs = frag64
+    outs = dfmi.batched_step_split(with_split(dps), k_fp64=k_fp64)
+    torch.cuda.synchronize()
+    check_frag64(outs, refs, 1e-11)

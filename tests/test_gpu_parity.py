@@ -201,3 +201,18 @@ def test_full_papa_block():
     out = dfmi.papa(dev(B), nao, dev(C), dev(Cact), Cq=dev(Cq))
     torch.cuda.synchronize()
     close(out, O.papa_full(B, nao, C, Cact, Cq), what="papa full")
+
+
+def test_full_k_and_j_on_128_tiles():
+    """N_ao 700 (> 640) takes the 128 x 128 SYRK tiles the paper-scale K uses, with a ragged last
+    tile (700 = 5 * 128 + 60): full J, K and v against the oracle, K and J exactly symmetric."""
+    nao, naux, nocc = 700, 40, 75
+    B, C = rand_inputs(nao, naux, nocc, 0, seed=700)
+    Cocc = C[:, :nocc]
+    J, K, v = dfmi.jk(dev(B), nao, dev(Cocc))
+    torch.cuda.synchronize()
+    Jr, Kr, vr = O.jk(B, nao, Cocc)
+    close(K, Kr, what="K, 128-wide tiles")
+    close(J, Jr, what="J")
+    close(v, vr, what="v")
+    assert torch.equal(K, K.T) and torch.equal(J, J.T)
