@@ -837,6 +837,46 @@ def _autograd_function():
 
 
 _DFStep = None
+_RotationExp = None
+
+
+def _rotation_exp_function():
+    import torch
+
+    class RotationExp(torch.autograd.Function):
+        """U = exp(R), differentiable.  The backward is the adjoint of the Frechet derivative,
+        L_exp(R^T, G) = the upper-right block of exp([[R^T, G], [0, R^T]]).  The cotangent G is
+        scaled to a unit largest entry first (the derivative is linear in it), so that the block
+        matrix's norm, and with it the number of squarings, is R's own; torch's own backward of
+        matrix_exp takes G as it comes, and a G of norm 1e4 costs it several digits."""
+
+        @staticmethod
+        def forward(fctx, R):
+            fctx.save_for_backward(R)
+            return torch.linalg.matrix_exp(R)
+
+        @staticmethod
+        def backward(fctx, G):
+            (R,) = fctx.saved_tensors
+            n = R.shape[-1]
+            s = G.abs().max()
+            if s == 0:
+                return torch.zeros_like(R)
+            M = R.new_zeros((2 * n, 2 * n))
+            M[:n, :n] = R.T
+            M[n:, n:] = R.T
+            M[:n, n:] = G / s
+            return torch.linalg.matrix_exp(M)[:n, n:] * s
+
+    return RotationExp
+
+
+def rotation_exp(R):
+    """exp(R) for a square R, with an accurate adjoint for autograd (see RotationExp)."""
+    global _RotationExp
+    if _RotationExp is None:
+        _RotationExp = _rotation_exp_function()
+    return _RotationExp.apply(R)
 
 
 def dfstep_apply(B, nao: int, Cocc, Cact, keep_x=True):
@@ -850,10 +890,9 @@ def dfstep_apply(B, nao: int, Cocc, Cact, keep_x=True):
 def energy(B, nao: int, C0, kappa, nocc: int, nac: int, h, Gamma, keep_x=True):
     """E(kappa) = tr(D h) + 1/2 tr(D J) - 1/4 tr(D K) + 1/2 sum (uv|wx) Gamma, C = C0 exp(kappa - kappa^T).
 
-    Differentiable in kappa: torch's matrix exponential supplies dC/dkappa, the library's
-    adjoint supplies the contraction part."""
-    import torch
-    C = C0 @ torch.linalg.matrix_exp(kappa - kappa.T)
+    Differentiable in kappa: the matrix exponential (rotation_exp) supplies dC/dkappa, the
+    library's adjoint supplies the contraction part."""
+    C = C0 @ rotation_exp(kappa - kappa.T)
     Cocc = C[:, :nocc]
     Cact = C[:, nocc:nocc + nac]
     J, K, eri = dfstep_apply(B, nao, Cocc, Cact, keep_x)
