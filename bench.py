@@ -130,9 +130,11 @@ def cpu_baseline(wl, rows, seed, adjoint=True):
     from paper_2505_03755_amd import synth
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+        blas = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        threads = max([i.get("num_threads", 1) for i in blas] or [1])
+        vendor = ", ".join(f"{i.get('internal_api')} {i.get('version')} ({i.get('architecture')})" for i in blas)
     except Exception:
-        threads = os.cpu_count() or 1
+        threads, vendor = os.cpu_count() or 1, "unknown"
     B = synth.cholesky_vectors(rows, wl.nao, wl.L, seed=seed)
     C = synth.orbitals(wl.nao, seed=seed)
     Cocc, Cact = C[:, :wl.nocc], C[:, wl.nocc:wl.nocc + wl.nac]
@@ -149,9 +151,24 @@ def cpu_baseline(wl, rows, seed, adjoint=True):
     fl = sum(step_flops(rows, wl.nao, wl.nocc, wl.nac, wl.nmo, adjoint=adjoint).values())
     assert all(np.isfinite(o).all() for o in outs)
     what = "forward J, K, v, (uv|wx), (pu|vw)" + (" + adjoint" if adjoint else "")
-    return {"value": fl / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+    return {"value": fl / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle", "blas": vendor,
             "sample": f"{rows} of {wl.naux} auxiliary rows at N_ao={wl.nao}, N_occ={wl.nocc}, N_ac={wl.nac} "
                       f"({what}; rate in algorithmic FP64 FLOP/s of that sample); {dt:.2f} s"}
+
+
+# rows of K and of (pu|vw) the oracle check compares entry by entry (K C_occ and the rest in full)
+K_ROWS = (0, 1, 150, 299, 600, 1000, 1198, 1199)
+P_ROWS = (0, 1, 299, 300, 320, 339, 340, 777, 1199)
+
+
+def snapshot(o, Cocc, E):
+    """Host copies of a forward step's outputs that the oracle check compares."""
+    nao = Cocc.shape[0]
+    kr = [r for r in K_ROWS if r < nao]
+    pr = [r for r in P_ROWS if r < o["papa"].shape[0]]
+    return {"J": o["J"].cpu().numpy(), "v": o["v"].cpu().numpy(), "eri": o["eri"].cpu().numpy(),
+            "K_rows": o["K"][kr].cpu().numpy(), "KC": (o["K"] @ Cocc).cpu().numpy(),
+            "papa_rows": o["papa"][pr].cpu().numpy(), "E": E}
 
 
 def split_comparison(B, nao, Cocc, Cact, C, nslice, reps, ctx):
@@ -191,6 +208,7 @@ def split_comparison(B, nao, Cocc, Cact, C, nslice, reps, ctx):
 
     e64, es = energy(ref), energy(spl)
     rel = {k: ((spl[k] - ref[k]).norm() / ref[k].norm()).item() for k in ("J", "K", "v", "eri", "papa")}
+    host = {name: snapshot(o, Cocc, E) for name, o, E in (("fp64", ref, e64), ("split", spl, es))}
     del ref, spl
     # the adjoint for the model-energy cotangents (gJ = D/2, gK = -D/4, geri = Gamma/2), each
     # path on the factors its own forward kept
@@ -205,12 +223,94 @@ def split_comparison(B, nao, Cocc, Cact, C, nslice, reps, ctx):
                                                         xs["Xact"], ctx=ctx))
     grel = {name: ((a - b).norm() / b.norm()).item() for name, a, b in (("dCocc", gs[0], g64[0]),
                                                                        ("dCact", gs[1], g64[1]))}
+    for name, g in (("fp64", g64), ("split", gs)):
+        host[name]["dCocc"], host[name]["dCact"] = g[0].cpu().numpy(), g[1].cpu().numpy()
     del xs, x64, Bt, Bte, g64, gs
     torch.cuda.empty_cache()
     return {"nslice": nslice, "forward_ms_fp64": ms64, "forward_ms_split": mss, "speedup": ms64 / mss,
             "E_fp64": e64, "dE_split_minus_fp64": es - e64, "dE_bar": 1e-8, "meets_bar": abs(es - e64) <= 1e-8,
             "rel_diff": rel, "adjoint_ms_fp64": bms64, "adjoint_ms_split": bmss,
-            "adjoint_speedup": bms64 / bmss, "gradient_rel_diff": grel}
+            "adjoint_speedup": bms64 / bmss, "gradient_rel_diff": grel}, host
+
+
+def oracle_check(B, wl, host, chunk=96):
+    """Part of the CPU-baseline leg: the FP64 oracle's one pass over all of B at paper scale (the
+    rows copied from the device block by block; oracle/df_stream.py), and the error of the FP64 and
+    the split-precision GPU results against it: the model energy E and every output of the timed
+    step (J, v, rows of K, K C_occ, (uv|wx), rows of (pu|vw), and the gradient dC)."""
+    import math
+    import numpy as np
+    from oracle import df_stream as S
+    from paper_2505_03755_amd import synth
+    C = synth.orbitals(wl.nao, seed=wl.seed)
+    h = synth.symmetric_matrix(wl.nao, seed=wl.seed)
+    Gam = synth.two_body_density(wl.nac, seed=wl.seed)
+    kr = [r for r in K_ROWS if r < wl.nao]
+    pr = [r for r in P_ROWS if r < wl.nmo]
+
+    def chunks():
+        for p0 in range(0, B.shape[0], chunk):
+            yield p0, B[p0:p0 + chunk].cpu().numpy()
+
+    t0 = time.perf_counter()
+    r = S.step_pass(chunks(), wl.naux, wl.nao, C, wl.nocc, wl.nac, h, Gam, p_rows=pr, k_rows=kr)
+    dt = time.perf_counter() - t0
+    Cocc = C[:, :wl.nocc]
+    ref = {"J": r["J"], "v": r["v"], "K_rows": r["K_rows"], "KC": r["KC"], "eri": r["eri"],
+           "papa_rows": r["papa_rows"],
+           # the adjoint for the model-energy cotangents: (J - K/2) C_occ and dE/dC_act
+           "dCocc": r["J"] @ Cocc - 0.5 * r["KC"], "dCact": r["G"][:, wl.nocc:wl.nocc + wl.nac]}
+
+    def relerr(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    out = {"E_oracle": r["E"], "oracle_pass_s": dt, "dE_bar": 1e-8,
+           "outputs": "J and v in full, rows " + ",".join(map(str, kr)) + " of K, K C_occ, (uv|wx), rows "
+                      + ",".join(map(str, pr)) + " of (pu|vw), dC_occ and dC_act (normwise relative errors)"}
+    for name, g in host.items():
+        dE = g["E"] - r["E"]
+        out[name] = {"dE": dE, "dE_rel": abs(dE) / abs(r["E"]), "meets_bar": abs(dE) <= 1e-8,
+                     "rel_err": {k: relerr(g[k], ref[k]) for k in ref}}
+    return out
+
+
+def recompute_block(B, nao, Cocc, Cact, C, gJ, gK, geri, reps, ctx, limits=(0, 8 << 30)):
+    """The step with the half transforms recomputed in the adjoint instead of kept: df_step without
+    X, then df_step_backward forming X again (in one piece, and in P chunks under a scratch limit),
+    timed with HIP events on the library's stream."""
+    import torch
+    from paper_2505_03755_amd import dfmi
+    naux = B.shape[0]
+    nocc, nac, nmo = Cocc.shape[1], Cact.shape[1], C.shape[1]
+    stream = torch.cuda.current_stream(B.device)
+    out = dfmi.step(B, nao, Cocc, Cact, C, ctx=ctx)
+    fl = sum(step_flops(naux, nao, nocc, nac, nmo).values()) + 2 * naux * nao * nao * (nocc + nac)
+    res = {"flops_per_step": fl}
+    for lim in limits:
+        ctx.set_scratch_limit(lim)
+        try:
+            def run():
+                dfmi.step(B, nao, Cocc, Cact, C, outputs=out, ctx=ctx)
+                dfmi.step_backward(B, nao, Cocc, Cact, gJ, gK, geri, ctx=ctx)
+            run()
+            torch.cuda.synchronize()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+            ev[0].record(stream)
+            for i in range(reps):
+                run()
+                ev[i + 1].record(stream)
+            torch.cuda.synchronize()
+            ms = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(reps))[reps // 2]
+            rows = ctx.backward_chunk(naux=naux, nao=nao, nocc=nocc, nac=nac,
+                                      flags=dfmi.DF_BWD_GJ | dfmi.DF_BWD_GK | dfmi.DF_BWD_GERI)
+        finally:
+            ctx.set_scratch_limit(0)
+        key = "no_limit" if lim == 0 else f"limit_{lim >> 30}GiB"
+        res[key] = {"ms": ms, "tflops": fl / ms / 1e9, "chunk_rows": rows, "chunks": -(-naux // rows)}
+        torch.cuda.empty_cache()
+    del out
+    torch.cuda.empty_cache()
+    return res
 
 
 def ppaa_block(B, nao, Cact, C, reps, ctx):
@@ -395,6 +495,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched fragment workload")
     ap.add_argument("--no-ppaa", action="store_true", help="skip the (pq|uv) block")
     ap.add_argument("--no-build", action="store_true", help="skip forming B from the metric")
+    ap.add_argument("--no-recompute", action="store_true", help="skip the step with X recomputed in the adjoint")
+    ap.add_argument("--no-oracle-check", action="store_true",
+                    help="skip the oracle's full pass over B (errors of the GPU results against it)")
     ap.add_argument("--fragment-densities", type=int, default=64)
     ap.add_argument("--split-slices", type=int, default=7)
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
@@ -520,12 +623,19 @@ def main():
         "roofline": roof,
         "kernels": kernels,
     }
+    for k in ("Xocc", "Xact"):
+        out.pop(k, None)
+    torch.cuda.empty_cache()
+    if not args.forward_only and not args.no_recompute:
+        log("[bench] adjoint with the half transforms recomputed")
+        res["recompute_x"] = recompute_block(B, nao, Cocc, Cact, C, gJ, gK, geri, 3, ctx)
+    host = None
     if not args.no_split:
         log(f"[bench] split precision ({args.split_slices} slices) against FP64, forward and adjoint")
-        for k in ("Xocc", "Xact"):
-            out.pop(k, None)
-        torch.cuda.empty_cache()
-        res["split_precision"] = split_comparison(B, nao, Cocc, Cact, C, args.split_slices, 5, ctx)
+        res["split_precision"], host = split_comparison(B, nao, Cocc, Cact, C, args.split_slices, 5, ctx)
+    if host is not None and not args.no_cpu_baseline and not args.no_oracle_check:
+        log("[bench] CPU-baseline leg: the FP64 oracle's pass over all of B, against both GPU paths")
+        res["oracle_check"] = oracle_check(B, wl, host)
     if not args.no_ppaa:
         log("[bench] (pq|uv) over all MOs")
         for k in ("Xocc", "Xact"):
