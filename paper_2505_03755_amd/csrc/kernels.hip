@@ -565,7 +565,9 @@ struct HalfSrc {
       const unsigned kr = k0 + kw + (unsigned)(q * (C::NT / C::BM));   // uniform
       const unsigned kc = kr <= last ? kr : last;
       const unsigned Tk = kc * (kc + 1u) / 2u;
-      const unsigned other = mAc >= kc ? mAoff + kc : Tk + mAc;
+      // a bit-mask blend: a conditional here compiles to a divergent branch per load
+      const unsigned sel = 0u - (unsigned)(mAc >= kc);
+      const unsigned other = ((mAoff + kc) & sel) | ((Tk + mAc) & ~sel);
       va[q] = Bp[below ? offB[q] + k0 : other];
     } else {
       c.template load<q - EA>(*Cm, t);
@@ -705,6 +707,20 @@ __global__ void __launch_bounds__(256) jvec_kernel(const double* __restrict__ X,
   const double* Cz = Cm + z * nao * nocc;
   const double* wz = w ? w + z * nocc : nullptr;
   double s = 0.0;
+  if (ldx == nocc && !wz) {
+    // X_P and the factor are both contiguous [nao * nocc]: a dot product with four loads in flight
+    const int64_t n = nao * nocc;
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int64_t e = threadIdx.x;
+    for (; e + 768 < n; e += 1024) {
+      s = fma(Cz[e], Xp[e], s);
+      s1 = fma(Cz[e + 256], Xp[e + 256], s1);
+      s2 = fma(Cz[e + 512], Xp[e + 512], s2);
+      s3 = fma(Cz[e + 768], Xp[e + 768], s3);
+    }
+    for (; e < n; e += 256) s = fma(Cz[e], Xp[e], s);
+    s = (s + s1) + (s2 + s3);
+  } else {
   int64_t m = threadIdx.x / nocc, c = threadIdx.x % nocc;
   while (m < nao) {
     const double cw = wz ? Cz[m * nocc + c] * wz[c] : Cz[m * nocc + c];
@@ -715,6 +731,7 @@ __global__ void __launch_bounds__(256) jvec_kernel(const double* __restrict__ X,
       ++m;
     }
   }
+  }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
@@ -724,40 +741,59 @@ __global__ void __launch_bounds__(256) jvec_kernel(const double* __restrict__ X,
   }
 }
 
-// J[z][i][j] = sum_P v[z][P] b^P_{ij}: one thread per packed pair, streaming B once.
+// J[z][i][j] = sum_P v[z][P] b^P_{ij}, streaming B once.  A workgroup owns kCoulombPairs * 256
+// consecutive packed pairs (thread t the pairs t + 256 r) for every P, so each P row is read as
+// runs of 8 KB; v is staged through LDS in blocks of 256 P.
 constexpr int kCoulombZ = 4;
+constexpr int kCoulombPairs = 4;
 __global__ void __launch_bounds__(256) coulomb_kernel(const double* __restrict__ B, int64_t naux, int64_t nao,
                                                       int64_t npair, const double* __restrict__ v, int nz,
                                                       int64_t vstride, double* __restrict__ J, int64_t jstride,
                                                       int accumulate) {
   __shared__ double vs[kCoulombZ][256];
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  double acc[kCoulombZ] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t p0 = (int64_t)blockIdx.x * (256 * kCoulombPairs) + threadIdx.x;
+  int64_t pc[kCoulombPairs];   // the pairs, clamped to the last one (read, never stored)
+#pragma unroll
+  for (int r = 0; r < kCoulombPairs; ++r) pc[r] = p0 + 256 * r < npair ? p0 + 256 * r : npair - 1;
+  double acc[kCoulombPairs][kCoulombZ];
+#pragma unroll
+  for (int r = 0; r < kCoulombPairs; ++r)
+#pragma unroll
+    for (int z = 0; z < kCoulombZ; ++z) acc[r][z] = 0.0;
   for (int64_t P0 = 0; P0 < naux; P0 += 256) {
     const int64_t cnt = naux - P0 < 256 ? naux - P0 : 256;
     __syncthreads();
     for (int z = 0; z < nz; ++z) vs[z][threadIdx.x] = threadIdx.x < cnt ? v[z * vstride + P0 + threadIdx.x] : 0.0;
     __syncthreads();
-    if (p < npair) {
-      const double* Bc = B + P0 * npair + p;
-#pragma unroll 8
-      for (int q = 0; q < cnt; ++q) {
-        const double b = Bc[(int64_t)q * npair];
+    const double* Bp = B + P0 * npair;
+#pragma unroll 2
+    for (int q = 0; q < cnt; ++q) {
+      double b[kCoulombPairs];
 #pragma unroll
-        for (int z = 0; z < kCoulombZ; ++z)
-          if (z < nz) acc[z] = fma(vs[z][q], b, acc[z]);
+      for (int r = 0; r < kCoulombPairs; ++r) b[r] = Bp[(int64_t)q * npair + pc[r]];
+#pragma unroll
+      for (int z = 0; z < kCoulombZ; ++z) {
+        if (z < nz) {
+          const double w = vs[z][q];
+#pragma unroll
+          for (int r = 0; r < kCoulombPairs; ++r) acc[r][z] = fma(w, b[r], acc[r][z]);
+        }
       }
     }
   }
-  if (p >= npair) return;
-  int64_t i = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
-  while (i * (i + 1) / 2 > p) --i;
-  while ((i + 1) * (i + 2) / 2 <= p) ++i;
-  const int64_t j = p - i * (i + 1) / 2;
-  for (int z = 0; z < nz; ++z) {
-    const double x = accumulate ? J[z * jstride + i * nao + j] + acc[z] : acc[z];   // J is symmetric
-    J[z * jstride + i * nao + j] = x;
-    J[z * jstride + j * nao + i] = x;
+#pragma unroll
+  for (int r = 0; r < kCoulombPairs; ++r) {
+    const int64_t p = p0 + 256 * r;
+    if (p >= npair) break;
+    int64_t i = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+    while (i * (i + 1) / 2 > p) --i;
+    while ((i + 1) * (i + 2) / 2 <= p) ++i;
+    const int64_t j = p - i * (i + 1) / 2;
+    for (int z = 0; z < nz; ++z) {
+      const double x = accumulate ? J[z * jstride + i * nao + j] + acc[r][z] : acc[r][z];   // J is symmetric
+      J[z * jstride + i * nao + j] = x;
+      J[z * jstride + j * nao + i] = x;
+    }
   }
 }
 
@@ -796,12 +832,12 @@ __global__ void __launch_bounds__(256) pair_weights_kernel(const double* __restr
   g[p] = i == j ? G[i * nao + i] : G[i * nao + j] + G[j * nao + i];
 }
 
-// u[P] = sum_pair B[P][pair] g[pair]: eight rows of B per workgroup share each read of g; a
+// u[P] = sum_pair B[P][pair] g[pair]: four rows of B per workgroup share each read of g; a
 // fixed-order reduction keeps it deterministic.
-constexpr int kJvRows = 8;
+constexpr int kJvRows = 4;
 // Partial sums part[c][P] = sum_{pair in chunk c} B[P][pair] g[pair] for kJvRows rows per
-// workgroup (grid x) and kJvChunks chunks of the pairs (grid y): enough workgroups to keep HBM
-// busy; the chunks are summed in a fixed order afterwards.
+// workgroup (grid x) and kJvChunks chunks of the pairs (grid y).  Each step a thread takes the
+// pairs p + 256 u (u < 4) of every row: each row is read as runs of 8 KB per workgroup.
 constexpr int kJvChunks = 8;
 __global__ void __launch_bounds__(256) jvec_packed_kernel(const double* __restrict__ B, int64_t naux, int64_t npair,
                                                           const double* __restrict__ g, double* __restrict__ part) {
@@ -809,14 +845,22 @@ __global__ void __launch_bounds__(256) jvec_packed_kernel(const double* __restri
   const int64_t P0 = (int64_t)blockIdx.x * kJvRows;
   const int64_t c = blockIdx.y, chunk = (npair + kJvChunks - 1) / kJvChunks;
   const int64_t p0 = c * chunk, p1 = p0 + chunk < npair ? p0 + chunk : npair;
+  const double* rows[kJvRows];   // rows past the end read the last one (never stored)
+#pragma unroll
+  for (int r = 0; r < kJvRows; ++r) rows[r] = B + (P0 + r < naux ? P0 + r : naux - 1) * npair;
   double s[kJvRows];
 #pragma unroll
   for (int r = 0; r < kJvRows; ++r) s[r] = 0.0;
-  for (int64_t p = p0 + threadIdx.x; p < p1; p += 256) {
-    const double gp = g[p];
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += 1024) {
 #pragma unroll
-    for (int r = 0; r < kJvRows; ++r)
-      if (P0 + r < naux) s[r] = fma(B[(P0 + r) * npair + p], gp, s[r]);
+    for (int u = 0; u < 4; ++u) {
+      const int64_t q = p + 256 * u;
+      const bool ok = q < p1;
+      const int64_t qc = ok ? q : p1 - 1;
+      const double gq = ok ? g[qc] : 0.0;
+#pragma unroll
+      for (int r = 0; r < kJvRows; ++r) s[r] = fma(rows[r][qc], gq, s[r]);
+    }
   }
 #pragma unroll
   for (int r = 0; r < kJvRows; ++r) {
@@ -1374,7 +1418,7 @@ hipError_t launch_coulomb(const double* B, int64_t naux, int64_t nao, const doub
   if (ldv < naux) return hipErrorInvalidValue;
   for (int64_t z0 = 0; z0 < nz; z0 += kCoulombZ) {
     const int nzc = (int)(nz - z0 < kCoulombZ ? nz - z0 : kCoulombZ);
-    coulomb_kernel<<<(unsigned)cdiv(npair, 256), 256, 0, s>>>(B, naux, nao, npair, v + z0 * ldv, nzc, ldv,
+    coulomb_kernel<<<(unsigned)cdiv(npair, 256 * kCoulombPairs), 256, 0, s>>>(B, naux, nao, npair, v + z0 * ldv, nzc, ldv,
                                                                J + z0 * nao * nao, nao * nao, accumulate);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
