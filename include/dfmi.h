@@ -425,6 +425,26 @@ df_status df_batched_set_tuning(df_ctx* ctx, const df_problem* probs, int nprob,
                                 int k_rounds);
 
 /*
+ * The tuning table outlives the context in a file (JSON, format "dfmi-autotune/1"): one entry per
+ * problem-group shape with its operation ("df_batched_step"), precision ("fp64"), the device's gfx
+ * architecture ("gfx950"; empty for choices set with df_batched_set_tuning, which hold on any
+ * device) and the chosen half-transform tile, K tile and K split target.
+ *   df_autotune_save writes the context's whole table to path (a temporary file renamed into
+ *     place); DF_ERR_ARG if it cannot be written.
+ *   df_autotune_load merges the entries of path into the table (file entries replace stored ones
+ *     of the same architecture and shape; entries of other operations or precisions, or with a
+ *     configuration outside the candidate lists, are skipped); DF_ERR_ARG if the file cannot be
+ *     read or is not in this format.  Entries of another architecture stay unused.
+ * With the environment variable DFMI_AUTOTUNE_CACHE naming a file, df_create loads it when it
+ * exists (a file in another format fails df_create), and every df_batched_step that tunes merges
+ * the file's current entries and rewrites it with its new choice.  Neither call touches the GPU;
+ * df_batched_tuning, df_batched_set_tuning and df_batched_step ask the runtime for the device's
+ * architecture once per context (without a device only architecture-free entries apply).
+ */
+df_status df_autotune_save(df_ctx* ctx, const char* path);
+df_status df_autotune_load(df_ctx* ctx, const char* path);
+
+/*
  * df_batched_step in split precision: the same outputs of the same problems, with the half
  * transform, every density's K, the second transforms, (uv|wx) and the full (pu|qv) as int8
  * slice products (nslice slices, as in df_step_split); J and the J-vectors stay FP64.

@@ -7,6 +7,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <sstream>
 #include <map>
 #include <mutex>
 #include <string>
@@ -33,9 +36,13 @@ struct df_ctx {
   std::vector<hipEvent_t> ev_pool;
   std::vector<Timed> pending;
   hipEvent_t cur_a = nullptr;
-  // autotuning of df_batched_step (df_set_autotune): configuration per problem-group shape
+  // autotuning of df_batched_step (df_set_autotune): configuration per problem-group shape,
+  // keyed by "<gfx arch>|<shape>" (an empty arch: entries set by hand, valid on any device)
   bool autotune = false;
   std::map<std::string, BatchedTune> tune;
+  std::string arch;          // the device's gfx name, looked up on the first tuning call
+  bool arch_tried = false;
+  std::string cache_path;    // DFMI_AUTOTUNE_CACHE at creation: loaded then, rewritten after tuning
   // split precision of the DF_PREC_SPLIT calls: slice count and the registered planes of B
   struct SplitReg {
     const double* B;
@@ -563,6 +570,125 @@ std::string batched_key(const df_problem* probs, int n) {
   return k;
 }
 
+// ---- the autotuning table and its file ----
+// The device's gfx name ("gfx950"), asked of the runtime once; empty where there is no device.
+void resolve_arch(df_ctx* c) {
+  if (!c->arch.empty() || c->arch_tried) return;
+  c->arch_tried = true;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  const std::string name(prop.gcnArchName);
+  c->arch = name.substr(0, name.find(':'));
+}
+
+// An entry's key is "<arch>|<shape>": choices measured on a device carry its gfx name, choices set
+// by hand (df_batched_set_tuning) carry none and hold on any device.
+const BatchedTune* tune_find(const df_ctx* c, const std::string& shape) {
+  if (!c->arch.empty()) {
+    const auto it = c->tune.find(c->arch + "|" + shape);
+    if (it != c->tune.end()) return &it->second;
+  }
+  const auto it = c->tune.find("|" + shape);
+  return it != c->tune.end() ? &it->second : nullptr;
+}
+
+bool tune_valid(const BatchedTune& t) {
+  auto in = [](int v, const int* set, int n) { return std::find(set, set + n, v) != set + n; };
+  return in(t.half_n, kHalfTiles, 3) && in(t.k_tile, kKTiles, 2) && in(t.k_rounds, kKRounds, 3);
+}
+
+// The value of "name" in one flat JSON object (a string without escapes, or an integer).
+bool json_field(const std::string& obj, const char* name, std::string* str, long long* num) {
+  const std::string pat = std::string("\"") + name + "\"";
+  size_t p = obj.find(pat);
+  if (p == std::string::npos) return false;
+  p = obj.find(':', p + pat.size());
+  if (p == std::string::npos) return false;
+  ++p;
+  while (p < obj.size() && (obj[p] == ' ' || obj[p] == '\t' || obj[p] == '\n' || obj[p] == '\r')) ++p;
+  if (p >= obj.size()) return false;
+  if (obj[p] == '"') {
+    const size_t q = obj.find('"', p + 1);
+    if (q == std::string::npos || !str) return false;
+    *str = obj.substr(p + 1, q - p - 1);
+    return true;
+  }
+  if (!num) return false;
+  char* end = nullptr;
+  *num = std::strtoll(obj.c_str() + p, &end, 10);
+  return end != obj.c_str() + p;
+}
+
+// Entries of a tuning file (format dfmi-autotune/1) merged into the table; entries of other
+// operations, precisions or unknown configurations are skipped.  A missing file is an error.
+bool tune_read(df_ctx* c, const std::string& path, std::string* err) {
+  std::ifstream f(path);
+  if (!f) {
+    *err = "cannot open " + path;
+    return false;
+  }
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string text = ss.str();
+  if (text.find("\"dfmi-autotune/1\"") == std::string::npos) {
+    *err = path + " is not a dfmi-autotune/1 file";
+    return false;
+  }
+  const size_t list = text.find("\"entries\"");
+  for (size_t p = list == std::string::npos ? text.size() : text.find('{', list); p < text.size();
+       p = text.find('{', p + 1)) {
+    const size_t q = text.find('}', p);
+    if (q == std::string::npos) break;
+    const std::string obj = text.substr(p, q - p + 1);
+    std::string op, prec, arch, shape;
+    long long h = 0, kt = 0, kr = 0;
+    if (json_field(obj, "op", &op, nullptr) && op == "df_batched_step" && json_field(obj, "precision", &prec, nullptr) &&
+        prec == "fp64" && json_field(obj, "arch", &arch, nullptr) && json_field(obj, "shape", &shape, nullptr) &&
+        json_field(obj, "half_tile_n", nullptr, &h) && json_field(obj, "k_tile", nullptr, &kt) &&
+        json_field(obj, "k_rounds", nullptr, &kr)) {
+      const BatchedTune t{(int)h, (int)kt, (int)kr};
+      if (tune_valid(t)) c->tune[arch + "|" + shape] = t;
+    }
+    p = q;
+  }
+  return true;
+}
+
+// The whole table as a tuning file, written to a temporary name and renamed into place.
+bool tune_write(const df_ctx* c, const std::string& path, std::string* err) {
+  const std::string tmp = path + ".tmp" + std::to_string((unsigned long long)(uintptr_t)c);
+  {
+    std::ofstream f(tmp, std::ios::trunc);
+    if (!f) {
+      *err = "cannot write " + tmp;
+      return false;
+    }
+    f << "{\n  \"format\": \"dfmi-autotune/1\",\n  \"entries\": [";
+    bool first = true;
+    for (const auto& e : c->tune) {
+      const size_t bar = e.first.find('|');
+      f << (first ? "\n" : ",\n") << "    {\"op\": \"df_batched_step\", \"precision\": \"fp64\", \"arch\": \""
+        << e.first.substr(0, bar) << "\", \"shape\": \"" << e.first.substr(bar + 1) << "\", \"half_tile_n\": "
+        << e.second.half_n << ", \"k_tile\": " << e.second.k_tile << ", \"k_rounds\": " << e.second.k_rounds << "}";
+      first = false;
+    }
+    f << "\n  ]\n}\n";
+    if (!f) {
+      *err = "error writing " + tmp;
+      return false;
+    }
+  }
+  if (std::rename(tmp.c_str(), path.c_str()) != 0) {
+    std::remove(tmp.c_str());
+    *err = "cannot rename " + tmp + " to " + path;
+    return false;
+  }
+  return true;
+}
+
 // J of many densities as one product: Jp[z][pair] = sum_P v[z][P] b^P[pair] (then unpacked)
 bool batched_j_gemm(const df_problem& q) { return q.ndm > 4; }
 
@@ -922,6 +1048,18 @@ df_status df_create(df_ctx** ctx, int device, void* stream) {
   df_ctx* c = new df_ctx();
   c->device = device;
   c->stream = (hipStream_t)stream;
+  // a tuning file named by DFMI_AUTOTUNE_CACHE: read now when it exists, rewritten after each tuning
+  if (const char* path = std::getenv("DFMI_AUTOTUNE_CACHE")) {
+    if (*path) {
+      c->cache_path = path;
+      std::string err;
+      if (std::ifstream(path).good() && !tune_read(c, c->cache_path, &err)) {
+        g_create_err = "DFMI_AUTOTUNE_CACHE: " + err;
+        delete c;
+        return DF_ERR_ARG;
+      }
+    }
+  }
   *ctx = c;
   return DF_OK;
 }
@@ -2170,9 +2308,10 @@ df_status df_batched_tuning(df_ctx* ctx, const df_problem* probs, int nprob, int
   if (nprob < 0 || (nprob > 0 && !probs)) return fail(c, DF_ERR_ARG, "probs is NULL");
   if (!half_tile_n || !k_tile || !k_rounds || !tuned) return fail(c, DF_ERR_ARG, "output pointers are NULL");
   BatchedTune tu = batched_default_tune(probs, nprob);
-  const auto it = c->tune.find(batched_key(probs, nprob));
-  *tuned = it != c->tune.end();
-  if (*tuned) tu = it->second;
+  resolve_arch(c);
+  const BatchedTune* known = tune_find(c, batched_key(probs, nprob));
+  *tuned = known != nullptr;
+  if (known) tu = *known;
   *half_tile_n = tu.half_n;
   *k_tile = tu.k_tile;
   *k_rounds = tu.k_rounds;
@@ -2184,10 +2323,30 @@ df_status df_batched_set_tuning(df_ctx* ctx, const df_problem* probs, int nprob,
   df_ctx* c = ctx;
   if (check_ctx(c)) return DF_ERR_ARG;
   if (nprob < 0 || (nprob > 0 && !probs)) return fail(c, DF_ERR_ARG, "probs is NULL");
-  auto in = [](int v, const int* set, int n) { return std::find(set, set + n, v) != set + n; };
-  if (!in(half_tile_n, kHalfTiles, 3) || !in(k_tile, kKTiles, 2) || !in(k_rounds, kKRounds, 3))
-    return fail(c, DF_ERR_ARG, "not a candidate configuration");
-  c->tune[batched_key(probs, nprob)] = BatchedTune{half_tile_n, k_tile, k_rounds};
+  const BatchedTune t{half_tile_n, k_tile, k_rounds};
+  if (!tune_valid(t)) return fail(c, DF_ERR_ARG, "not a candidate configuration");
+  const std::string shape = batched_key(probs, nprob);
+  resolve_arch(c);
+  if (!c->arch.empty()) c->tune.erase(c->arch + "|" + shape);   // the stored choice is this one
+  c->tune["|" + shape] = t;
+  return DF_OK;
+}
+
+df_status df_autotune_save(df_ctx* ctx, const char* path) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (!path || !*path) return fail(c, DF_ERR_ARG, "path is empty");
+  std::string err;
+  if (!tune_write(c, path, &err)) return fail(c, DF_ERR_ARG, err);
+  return DF_OK;
+}
+
+df_status df_autotune_load(df_ctx* ctx, const char* path) {
+  df_ctx* c = ctx;
+  if (check_ctx(c)) return DF_ERR_ARG;
+  if (!path || !*path) return fail(c, DF_ERR_ARG, "path is empty");
+  std::string err;
+  if (!tune_read(c, path, &err)) return fail(c, DF_ERR_ARG, err);
   return DF_OK;
 }
 
@@ -2448,9 +2607,9 @@ df_status df_batched_step(df_ctx* ctx, const df_problem* probs, int nprob, int f
   };
   BatchedTune tu = batched_default_tune(probs, nprob);
   const std::string key = batched_key(probs, nprob);
-  const auto known = c->tune.find(key);
-  if (known != c->tune.end()) {
-    tu = known->second;
+  resolve_arch(c);
+  if (const BatchedTune* known = tune_find(c, key)) {
+    tu = *known;
   } else if (c->autotune) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     DF_HIP(hipStreamIsCapturing(c->stream, &cs), "hipStreamIsCapturing");
@@ -2505,7 +2664,16 @@ df_status df_batched_step(df_ctx* ctx, const df_problem* probs, int nprob, int f
       c->ev_pool.push_back(ea);
       c->ev_pool.push_back(eb);
       if (ts != DF_OK) return ts;
-      c->tune[key] = tu;
+      c->tune[c->arch + "|" + key] = tu;
+      if (!c->cache_path.empty()) {
+        // merge with what other processes wrote meanwhile, then rewrite; a cache that cannot be
+        // written costs only the next process a tuning call
+        std::string err;
+        const BatchedTune mine = tu;
+        if (std::ifstream(c->cache_path).good()) (void)tune_read(c, c->cache_path, &err);
+        c->tune[c->arch + "|" + key] = mine;
+        (void)tune_write(c, c->cache_path, &err);
+      }
     }
   }
   if (df_status s = run_half(tu.half_n)) return s;

@@ -55,7 +55,8 @@ EXPORTED = ["df_create", "df_destroy", "df_last_error", "df_set_stream", "df_set
             "df_set_autotune", "df_batched_tuning", "df_batched_set_tuning", "df_split_cholesky_t",
             "df_step_backward_split", "df_batched_split_workspace_size", "df_batched_step_split",
             "df_ppaa", "df_build_cholesky", "df_embed_cholesky", "df_workspace_query", "df_set_scratch_limit",
-            "df_backward_chunk", "df_set_split_slices", "df_register_split", "df_jk_noalloc"]
+            "df_backward_chunk", "df_set_split_slices", "df_register_split", "df_jk_noalloc",
+            "df_autotune_save", "df_autotune_load"]
 
 
 class DFError(RuntimeError):
@@ -119,6 +120,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         pi = ctypes.POINTER(ctypes.c_int)
         L.df_batched_tuning.argtypes = [vp, vp, i32, pi, pi, pi, pi]
         L.df_batched_set_tuning.argtypes = [vp, vp, i32, i32, i32, i32]
+        L.df_autotune_save.argtypes = [vp, ctypes.c_char_p]
+        L.df_autotune_load.argtypes = [vp, ctypes.c_char_p]
         L.df_batched_split_workspace_size.argtypes = [vp, i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
         L.df_batched_step_split.argtypes = [vp, vp, vp, vp, i32, i32, i32]
         L.df_split_matmul.argtypes = [vp, dp, i64, i64, dp, i64, i64, i64, i32, dp, i64, i32]
@@ -245,6 +248,14 @@ class Context:
     def set_autotune(self, on: bool):
         """Tune df_batched_step's tiles on the first call of each new problem-group shape."""
         self.check(self._lib.df_set_autotune(self._h, 1 if on else 0))
+
+    def autotune_save(self, path: str):
+        """Write the context's tuning table to a file (df_autotune_save)."""
+        self.check(self._lib.df_autotune_save(self._h, os.fsencode(path)))
+
+    def autotune_load(self, path: str):
+        """Merge a tuning file into the context's table (df_autotune_load)."""
+        self.check(self._lib.df_autotune_load(self._h, os.fsencode(path)))
 
     def set_timing(self, on: bool):
         self.check(self._lib.df_set_timing(self._h, 1 if on else 0))

@@ -469,3 +469,67 @@ def test_jk_noalloc_argument_errors(L, ctx):
     assert L.df_jk_noalloc(ctx, B, 8, 5, 1, C, 2, None, fake((1 << 20) + 64), None, None, 0) == dfmi.DF_ERR_ARG
     # nothing to add: returns before touching the device
     assert L.df_jk_noalloc(ctx, B, 8, 5, 1, C, 0, None, J, None, None, dfmi.DF_ACCUMULATE) == dfmi.DF_OK
+
+
+def test_autotune_file_round_trip(L, tmp_path, monkeypatch):
+    """The tuning table written to a file, read back into another context, and picked up at creation
+    through DFMI_AUTOTUNE_CACHE; bad files are refused, foreign entries skipped."""
+    import json
+    P = dfmi.Problem
+    arr = (P * 2)()
+    arr[0] = P(1 << 30, 10, 7, 2, 2 << 30, 3, 3 << 30, 2, 4 << 30, 7, 5 << 30, 6 << 30, None, None)
+    arr[1] = P(7 << 30, 12, 5, 1, 8 << 30, 2, None, 0, None, 0, 9 << 30, None, None, None)
+    v = [ctypes.c_int(-1) for _ in range(4)]
+    refs = [ctypes.byref(x) for x in v]
+
+    def new_ctx():
+        h = ctypes.c_void_p()
+        assert L.df_create(ctypes.byref(h), 0, None) == dfmi.DF_OK
+        return h
+
+    def read(h):
+        assert L.df_batched_tuning(h, arr, 2, *refs) == dfmi.DF_OK
+        return tuple(x.value for x in v)
+
+    monkeypatch.delenv("DFMI_AUTOTUNE_CACHE", raising=False)
+    a = new_ctx()
+    assert L.df_batched_set_tuning(a, arr, 2, 48, 128, 64) == dfmi.DF_OK
+    path = str(tmp_path / "tune.json")
+    assert L.df_autotune_save(a, path.encode()) == dfmi.DF_OK
+    doc = json.load(open(path))
+    assert doc["format"] == "dfmi-autotune/1"
+    (e,) = doc["entries"]
+    assert e["op"] == "df_batched_step" and e["precision"] == "fp64" and e["arch"] == ""
+    assert (e["half_tile_n"], e["k_tile"], e["k_rounds"]) == (48, 128, 64)
+    b = new_ctx()
+    assert read(b) == (176, 64, 16, 0)
+    assert L.df_autotune_load(b, path.encode()) == dfmi.DF_OK
+    assert read(b) == (48, 128, 64, 1)
+    # entries of another operation, precision or architecture, or outside the candidates, are skipped
+    doc["entries"] += [dict(e, op="df_step"), dict(e, precision="split", half_tile_n=96),
+                       dict(e, arch="gfx999", k_tile=64), dict(e, shape=e["shape"] + "x", k_rounds=5)]
+    doc["entries"][0]["k_rounds"] = 4
+    other = str(tmp_path / "other.json")
+    json.dump(doc, open(other, "w"))
+    c = new_ctx()
+    assert L.df_autotune_load(c, other.encode()) == dfmi.DF_OK
+    assert read(c) == (48, 128, 4, 1)
+    # the environment variable: loaded at creation
+    monkeypatch.setenv("DFMI_AUTOTUNE_CACHE", path)
+    d = new_ctx()
+    assert read(d) == (48, 128, 64, 1)
+    # refused: a missing file, a file in another format (also through the environment), an empty path
+    assert L.df_autotune_load(c, str(tmp_path / "none.json").encode()) == dfmi.DF_ERR_ARG
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"entries": []}')
+    assert L.df_autotune_load(c, str(bad).encode()) == dfmi.DF_ERR_ARG
+    assert b"dfmi-autotune/1" in L.df_last_error(c)
+    monkeypatch.setenv("DFMI_AUTOTUNE_CACHE", str(bad))
+    h = ctypes.c_void_p()
+    assert L.df_create(ctypes.byref(h), 0, None) == dfmi.DF_ERR_ARG
+    assert b"DFMI_AUTOTUNE_CACHE" in L.df_last_error(None)
+    monkeypatch.delenv("DFMI_AUTOTUNE_CACHE")
+    assert L.df_autotune_save(c, b"") == dfmi.DF_ERR_ARG
+    assert L.df_autotune_save(c, str(tmp_path / "no" / "dir.json").encode()) == dfmi.DF_ERR_ARG
+    for h in (a, b, c, d):
+        L.df_destroy(h)

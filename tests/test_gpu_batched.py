@@ -308,3 +308,35 @@ def test_fragment_workload_64_densities_split(frag64, k_fp64):
     outs = dfmi.batched_step_split(with_split(dps), k_fp64=k_fp64)
     torch.cuda.synchronize()
     check_frag64(outs, refs, 1e-11)
+
+
+def test_autotune_choice_persists_through_the_cache_file(tmp_path, monkeypatch):
+    """With DFMI_AUTOTUNE_CACHE set, a tuning call writes its choice (tagged with the device's gfx
+    architecture) to the file, and a context created afterwards uses it without measuring."""
+    import json
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("DFMI_AUTOTUNE_CACHE", str(path))
+    # (batched_tuning reads a group's shape with every output requested: no empty ones here)
+    probs = [make(*shape, seed=i + 71) for i, shape in enumerate(RAGGED[:3])]
+    dps = [to_dev(p) for p in probs]
+    a = dfmi.Context(0)
+    a.set_autotune(True)
+    outs = dfmi.batched_step(dps, ctx=a)
+    torch.cuda.synchronize()
+    t = dfmi.batched_tuning(dps, ctx=a)
+    assert t["tuned"]
+    doc = json.load(open(path))
+    (e,) = doc["entries"]
+    assert e["arch"].startswith("gfx") and e["op"] == "df_batched_step"
+    assert (e["half_tile_n"], e["k_tile"], e["k_rounds"]) == (t["half_tile_n"], t["k_tile"], t["k_rounds"])
+    b = dfmi.Context(0)                      # autotuning off: uses the file's choice
+    assert dfmi.batched_tuning(dps, ctx=b) == t
+    again = dfmi.batched_step(dps, ctx=b)
+    torch.cuda.synchronize()
+    for o1, o2 in zip(outs, again):
+        for k in o1:
+            assert torch.equal(o1[k], o2[k]), k
+    for p, o in zip(probs, outs):
+        check_problem(p, o)
+    a.close()
+    b.close()
