@@ -256,6 +256,7 @@ struct Operand {
   double sc[SCALE ? E : 1];
   int kval;             // valid k entries of the slab set up by begin()
   const double* base;
+  const double* cur;    // start of the next slab to load (kept up to date by finish: no multiplies per slab)
   const double* ksb;
   int64_t zoff, kso;
   int64_t kb, kb_last;  // cursor: next slab to load is (kb, kc0)
@@ -279,6 +280,7 @@ struct Operand {
     kc0 = (int)(s_begin % nkc) * C::BK;
     kb_last = (s_end - 1) / nkc;
     kc_last = (int)((s_end - 1) % nkc) * C::BK;
+    cur = o.p + zoff + kb * o.s_kb + (int64_t)kc0 * o.s_kc;
 #pragma unroll
     for (int q = 0; q < E; ++q) {
       const int64_t r = r0 + rr(t, q);
@@ -292,7 +294,7 @@ struct Operand {
     }
   }
   __device__ __forceinline__ void begin(const OpMap& o) {
-    base = o.p + zoff + kb * o.s_kb + (int64_t)kc0 * o.s_kc;
+    base = cur;
     kval = (int)o.kc_n - kc0;
     if constexpr (SCALE) ksb = o.ks + kso + kc0;
   }
@@ -314,12 +316,16 @@ struct Operand {
     const bool at_end = kb == kb_last && kc0 == kc_last;
     int nkc = kc0 + C::BK;
     int64_t nkb = kb;
+    // the next slab starts BK columns on, or at column 0 of the next kb block
+    int64_t step = (int64_t)C::BK * o.s_kc;
     if (nkc >= o.kc_n) {
       nkc = 0;
       ++nkb;
+      step = o.s_kb - (int64_t)kc0 * o.s_kc;
     }
     kc0 = at_end ? kc0 : nkc;
     kb = at_end ? kb : nkb;
+    cur = at_end ? cur : cur + step;
   }
   template <int q>
   __device__ __forceinline__ void store(double* Sm, int t) const {
@@ -542,6 +548,7 @@ struct HalfSrc {
     t = t_;
     nks = (nao + C::BK - 1) / C::BK;
     ks = 0;
+    Bp = Bbase + P * npair;
 #pragma unroll
     for (int q = 0; q < EA; ++q) {
       const unsigned m = (unsigned)(m0 + (t + C::NT * q) / C::BK);
@@ -554,7 +561,6 @@ struct HalfSrc {
     kw = (unsigned)__builtin_amdgcn_readfirstlane(t / C::BM);
   }
   __device__ __forceinline__ void begin() {
-    Bp = Bbase + P * npair;
     k0 = (unsigned)ks * C::BK;
     below = (int)k0 + C::BK - 1 <= m0;
     c.begin(*Cm);
@@ -565,10 +571,12 @@ struct HalfSrc {
       const unsigned kr = k0 + kw + (unsigned)(q * (C::NT / C::BM));   // uniform
       const unsigned kc = kr <= last ? kr : last;
       const unsigned Tk = kc * (kc + 1u) / 2u;
-      // a bit-mask blend: a conditional here compiles to a divergent branch per load
+      // bit-mask blends: conditionals here compile to a divergent branch (per lane) or to uniform
+      // branches (on `below`) per load
       const unsigned sel = 0u - (unsigned)(mAc >= kc);
       const unsigned other = ((mAoff + kc) & sel) | ((Tk + mAc) & ~sel);
-      va[q] = Bp[below ? offB[q] + k0 : other];
+      const unsigned bsel = 0u - (unsigned)below;
+      va[q] = Bp[((offB[q] + k0) & bsel) | (other & ~bsel)];
     } else {
       c.template load<q - EA>(*Cm, t);
     }
@@ -582,6 +590,7 @@ struct HalfSrc {
       ++nP;
     }
     ks = at_end ? ks : nk;
+    Bp = at_end || nP == P ? Bp : Bp + npair;
     P = at_end ? P : nP;
     c.finish(*Cm);
   }
