@@ -97,8 +97,9 @@ def kernel_table(kt, naux, nao, nocc, nac, nmo, steps):
         "adjoint": ("mfma", 4 * naux * nao * nao * nocc + 2 * nao * nao * nocc + 2 * naux * nac ** 4
                     + 2 * naux * nao * nac * nac),
         # HBM-bound kernels: bytes read + written
-        # forward J-vector reads X_occ, the adjoint's reads B; each Coulomb build streams B
-        "jvec": ("hbm", 8 * (naux * nao * nocc + nao * nocc + naux) + 8 * (naux * npair + npair + naux)),
+        # the forward J-vector comes out of the half transform's epilogue; the adjoint's reads B
+        # once; each Coulomb build streams B
+        "jvec": ("hbm", 8 * (naux * npair + npair + naux)),
         "coulomb": ("hbm", 2 * 8 * (naux * npair + naux + 2 * nao * nao)),
         "k_reduce": ("hbm", None),
         "other": ("hbm", None),

@@ -111,7 +111,7 @@ struct Plan {
 
 // Offsets of the workspace pieces of each operation.
 struct StepPlan {
-  size_t ccat, xo, xa, kpart, vtmp, bpu, buv;
+  size_t ccat, xo, xa, kpart, vtmp, vpart, bpu, buv;
   int nsplit;
 };
 
@@ -192,6 +192,7 @@ StepPlan plan_step(Plan& pl, int64_t naux, int64_t nao, int64_t nocc, int64_t na
   p.nsplit = dfk::syrk_splits(nao, naux, 1);
   p.kpart = pl.take((int64_t)p.nsplit * nao * nao);
   p.vtmp = pl.take(naux);
+  p.vpart = pl.take(nocc > 0 ? naux * dfk::half_tiles(nao, ncol) : 0);
   p.bpu = pl.take(naux * np * nac);
   p.buv = pl.take(naux * nac * nac);
   return p;
@@ -1902,14 +1903,17 @@ df_status df_step(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, const
   if (df_status s = pad_operand(c, cc, nao, ncol, blks, 2)) return s;
   double* Xo = caller_x ? Xocc : (double*)(c->ws + p.xo);
   double* Xa = caller_x ? Xact : (double*)(c->ws + p.xa);
-  if (df_status s = run_half(c, B, naux, nao, cc, ncol, out_split(Xo, Xa, naux, nao, nocc, nac))) return s;
+  const dfk::OutMap ox = out_split(Xo, Xa, naux, nao, nocc, nac);
+  double* vv = nocc > 0 && (J || v) ? (v ? v : (double*)(c->ws + p.vtmp)) : nullptr;
+  if (vv)   // v_P from the half transform's epilogue: X_occ is not read again for it
+    DF_LAUNCH(DF_KERNEL_HALF_TRANSFORM,
+              dfk::launch_half_transform_jvec(B, naux, nao, cc, ncol, ncol, ox, w, nocc, (double*)(c->ws + p.vpart),
+                                              vv, 0, c->stream),
+              "half transform launch");
+  else if (df_status s = run_half(c, B, naux, nao, cc, ncol, ox))
+    return s;
   if (nocc > 0) {
-    if (J || v) {
-      double* vv = v ? v : (double*)(c->ws + p.vtmp);
-      DF_LAUNCH(DF_KERNEL_JVEC, dfk::launch_jvec(Xo, naux, nao, nocc, Cocc, w, nocc, 1, vv, c->stream),
-                "J-vector launch");
-      if (J) DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_coulomb(B, naux, nao, vv, 1, J, c->stream), "Coulomb launch");
-    }
+    if (J) DF_LAUNCH(DF_KERNEL_COULOMB, dfk::launch_coulomb(B, naux, nao, vv, 1, J, c->stream), "Coulomb launch");
     if (K)
       if (df_status s = run_k(c, Xo, w, naux, nao, nocc, nocc, 1, p.nsplit, (double*)(c->ws + p.kpart), K))
         return s;

@@ -55,6 +55,14 @@ inline int64_t kpad16(int64_t n) { return (n + 15) / 16 * 16; }
 // kpad16(nao) rows (row stride ldc), rows nao.. zero.
 hipError_t launch_half_transform(const double* B, int64_t naux, int64_t nao, const double* C, int64_t ldc,
                                  int64_t ncol, const OutMap& out, hipStream_t s);
+// The same with the J-vector of Eq. (J_1) formed in its epilogue: v[P] = sum_{m<nao, c<nv}
+// T[m][c] C[m][c] w[c] over the first nv columns (w NULL: all ones; added to v when `accumulate`).
+// Per-tile partial sums go to part [naux][half_tiles(nao, ncol)] first.  out.alpha must be 1 and
+// out.accumulate 0.
+int64_t half_tiles(int64_t nao, int64_t ncol);
+hipError_t launch_half_transform_jvec(const double* B, int64_t naux, int64_t nao, const double* C, int64_t ldc,
+                                      int64_t ncol, const OutMap& out, const double* w, int64_t nv, double* part,
+                                      double* v, int accumulate, hipStream_t s);
 
 // C(m, n) = sum_k A(m, k) B(n, k) for a batch of nz problems (grid z).
 hipError_t launch_gemm(const OpMap& A, const OpMap& Bm, const OutMap& C, int64_t nz, hipStream_t s);

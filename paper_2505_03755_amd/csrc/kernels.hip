@@ -605,11 +605,23 @@ struct HalfSrc {
   }
 };
 
+// The J-vector of Eq. (J_1) formed in the half transform's epilogue: with X_P = b^P C the tile
+// just computed, v_P = sum_{m < nao, c < nv} X_P[m][c] C[m][c] w[c] (w NULL: all ones), since
+// sum_c X_P[m][c] C[m][c] w[c] summed over m is <b^P, C diag(w) C^T>.  Each tile leaves its
+// partial sum in part[P * tiles + tile]; jv_reduce_kernel adds them up in tile order.
+struct JvEpi {
+  const double* C;   // C[m * ldc + c], the operand of the half transform (L2-resident: the main loop read it)
+  int64_t ldc;
+  const double* w;
+  int nv;
+  double* part;
+};
+
 // One output tile (item = P * tiles + tile) of the half transform.
-template <class C, bool GEN = false>
+template <class C, bool GEN = false, bool JV = false>
 __device__ __forceinline__ void half_tile(const double* __restrict__ B, int nao, int64_t npair, const OpMap& Cm,
                                           const OutMap& out, int64_t tilesM, int64_t tilesN, int64_t item,
-                                          double* smem) {
+                                          double* smem, const JvEpi* jv = nullptr) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave % C::WM, wn = wave / C::WM;
   const int64_t ntile = tilesM * tilesN;
@@ -626,6 +638,36 @@ __device__ __forceinline__ void half_tile(const double* __restrict__ B, int nao,
   zero_acc<C>(acc);
   mainloop<C>(src, smem, nslab, acc, wm, wn, lane);
   store_tile<C, GEN>(out, P, m0, n0, acc, wm, wn, lane);
+  if constexpr (JV) {
+    const int lr = lane & 15, lg = lane >> 4;
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < C::TN; ++j) {
+      const int n = n0 + (wn * C::TN + j) * 16 + lr;
+      const bool nok = n < jv->nv;
+      const int nc = nok ? n : 0;
+      const double wc = nok ? (jv->w ? jv->w[nc] : 1.0) : 0.0;
+      double sj = 0.0;
+#pragma unroll
+      for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + (wm * C::TM + i) * 16 + 4 * r + lg;
+          const double cm = m < nao ? jv->C[(int64_t)m * jv->ldc + nc] : 0.0;
+          sj = fma(acc[i][j][r], cm, sj);
+        }
+      s = fma(sj, wc, s);
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    __syncthreads();   // the main loop's last LDS reads are done before smem is reused
+    if (lane == 0) smem[wave] = s;
+    __syncthreads();
+    if (t == 0) {
+      double r = 0.0;
+      for (int q = 0; q < C::WM * C::WN; ++q) r += smem[q];
+      jv->part[item] = r;
+    }
+  }
 }
 
 // GEN: the epilogue applies out.alpha and out.accumulate (a separate instantiation, see store_tile)
@@ -635,6 +677,27 @@ __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2)))
                                                      int64_t tilesN) {
   __shared__ double smem[2 * C::STAGE];
   half_tile<C, GEN>(B, nao, npair, Cm, out, tilesM, tilesN, xcd_remap(blockIdx.x, tilesM * tilesN * naux), smem);
+}
+
+// The half transform with the J-vector partials in its epilogue (JvEpi).
+template <class C>
+__global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) half_jv_kernel(const double* __restrict__ B, int64_t naux, int nao,
+                                                        int64_t npair, OpMap Cm, OutMap out, int64_t tilesM,
+                                                        int64_t tilesN, JvEpi jv) {
+  __shared__ double smem[2 * C::STAGE];
+  half_tile<C, false, true>(B, nao, npair, Cm, out, tilesM, tilesN, xcd_remap(blockIdx.x, tilesM * tilesN * naux),
+                            smem, &jv);
+}
+
+// v[P] (+)= sum_{t < tiles} part[P * tiles + t], in tile order.
+__global__ void __launch_bounds__(256) jv_reduce_kernel(const double* __restrict__ part, int64_t tiles, int64_t naux,
+                                                        double* __restrict__ v, int accumulate) {
+  const int64_t P = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (P >= naux) return;
+  const double* q = part + P * tiles;
+  double s = 0.0;
+  for (int64_t t = 0; t < tiles; ++t) s += q[t];
+  v[P] = accumulate ? v[P] + s : s;
 }
 
 // Grouped half transform over several problems in one launch.  Work items of problem p are
@@ -1044,6 +1107,21 @@ static hipError_t half_launch(const double* B, int64_t naux, int64_t nao, const 
   return hipGetLastError();
 }
 
+template <class Cg>
+static hipError_t half_jv_launch(const double* B, int64_t naux, int64_t nao, const OpMap& cm, const OutMap& out,
+                                 const JvEpi& jv, double* v, int accumulate, hipStream_t s) {
+  const int64_t tm = cdiv(nao, Cg::BM), tn = cdiv(cm.rows, Cg::BN);
+  const int64_t nblk = tm * tn * naux;
+  if (nblk == 0) return hipSuccess;
+  if (nblk > 0x7fffffffLL || !offsets_fit(cm) || out.alpha != 1.0 || out.accumulate) return hipErrorInvalidValue;
+  half_jv_kernel<Cg><<<dim3((unsigned)nblk), dim3(Cg::NT), 0, s>>>(B, naux, (int)nao, nao * (nao + 1) / 2, cm, out,
+                                                                   tm, tn, jv);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  jv_reduce_kernel<<<(unsigned)cdiv(naux, 256), 256, 0, s>>>(jv.part, tm * tn, naux, v, accumulate);
+  return hipGetLastError();
+}
+
 // Column tile of the half transform: the widest of {176, 96, 48} whose padded width is within 8%
 // of the least padded one.  A wider tile reads each band of b^P fewer times per column, which
 // outweighs a few percent of padded columns (at 1200 columns: 176 pads to 1232, 48 to 1200).
@@ -1064,6 +1142,27 @@ hipError_t launch_half_transform(const double* B, int64_t naux, int64_t nao, con
     case 176: return half_launch<CfgH176>(B, naux, nao, cm, out, s);
     case 96: return half_launch<CfgH96>(B, naux, nao, cm, out, s);
     default: return half_launch<CfgH48>(B, naux, nao, cm, out, s);
+  }
+}
+
+int64_t half_tiles(int64_t nao, int64_t ncol) {
+  switch (half_tile_n(ncol)) {
+    case 176: return cdiv(nao, CfgH176::BM) * cdiv(ncol, CfgH176::BN);
+    case 96: return cdiv(nao, CfgH96::BM) * cdiv(ncol, CfgH96::BN);
+    default: return cdiv(nao, CfgH48::BM) * cdiv(ncol, CfgH48::BN);
+  }
+}
+
+hipError_t launch_half_transform_jvec(const double* B, int64_t naux, int64_t nao, const double* C, int64_t ldc,
+                                      int64_t ncol, const OutMap& out, const double* w, int64_t nv, double* part,
+                                      double* v, int accumulate, hipStream_t s) {
+  if (nv < 0 || nv > ncol || nv > 0x7fffffffLL) return hipErrorInvalidValue;
+  const OpMap cm = op_map(C, ncol, 1, nao, ldc);
+  const JvEpi jv{C, ldc, w, (int)nv, part};
+  switch (half_tile_n(ncol)) {
+    case 176: return half_jv_launch<CfgH176>(B, naux, nao, cm, out, jv, v, accumulate, s);
+    case 96: return half_jv_launch<CfgH96>(B, naux, nao, cm, out, jv, v, accumulate, s);
+    default: return half_jv_launch<CfgH48>(B, naux, nao, cm, out, jv, v, accumulate, s);
   }
 }
 
