@@ -57,6 +57,10 @@ typedef Cfg<4, 1, 1, 11, true> CfgH176;
 typedef Cfg<4, 1, 1, 10, true> CfgH160;   // the P-summed packed product: 300 columns in 2 x 160
 typedef Cfg<4, 1, 2, 6> CfgH96;
 typedef Cfg<4, 1, 2, 3> CfgH48;
+// half transform on 2-D wave tiles: 128 rows x {128, 96, 64} columns, 2 x 2 waves of 4 x {4, 3, 2}
+typedef Cfg<2, 2, 4, 4, true> CfgQ128;
+typedef Cfg<2, 2, 4, 3, true> CfgQ96;
+typedef Cfg<2, 2, 4, 2, true> CfgQ64;
 
 // ---------------------------------------------------------------------------------------
 // Block index -> work item, keeping runs of consecutive work items on one XCD.  The
@@ -614,20 +618,21 @@ struct JvEpi {
   int64_t ldc;
   const double* w;
   int nv;
-  double* part;
+  double* part;      // partial of tile `tile` of P at part[P * T + toff + tile]
+  int64_t T, toff;
 };
 
-// One output tile (item = P * tiles + tile) of the half transform.
+// One output tile (item = P * tiles + tile) of the half transform; row bands start at row r0.
 template <class C, bool GEN = false, bool JV = false>
 __device__ __forceinline__ void half_tile(const double* __restrict__ B, int nao, int64_t npair, const OpMap& Cm,
-                                          const OutMap& out, int64_t tilesM, int64_t tilesN, int64_t item,
+                                          const OutMap& out, int64_t tilesM, int64_t tilesN, int64_t item, int r0,
                                           double* smem, const JvEpi* jv = nullptr) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave % C::WM, wn = wave / C::WM;
   const int64_t ntile = tilesM * tilesN;
   // row band major: the column tiles of one band of b^P run side by side and share its reads in L2
   const int64_t P = item / ntile, tile = item % ntile;
-  const int m0 = (int)((tile / tilesN) * C::BM), n0 = (int)((tile % tilesN) * C::BN);
+  const int m0 = r0 + (int)((tile / tilesN) * C::BM), n0 = (int)((tile % tilesN) * C::BN);
   const int nslab = (nao + C::BK - 1) / C::BK;
 
   HalfSrc<C> src;
@@ -665,7 +670,7 @@ __device__ __forceinline__ void half_tile(const double* __restrict__ B, int nao,
     if (t == 0) {
       double r = 0.0;
       for (int q = 0; q < C::WM * C::WN; ++q) r += smem[q];
-      jv->part[item] = r;
+      jv->part[P * jv->T + jv->toff + tile] = r;
     }
   }
 }
@@ -674,19 +679,19 @@ __device__ __forceinline__ void half_tile(const double* __restrict__ B, int nao,
 template <class C, bool GEN>
 __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) half_kernel(const double* __restrict__ B, int64_t naux, int nao,
                                                      int64_t npair, OpMap Cm, OutMap out, int64_t tilesM,
-                                                     int64_t tilesN) {
+                                                     int64_t tilesN, int r0) {
   __shared__ double smem[2 * C::STAGE];
-  half_tile<C, GEN>(B, nao, npair, Cm, out, tilesM, tilesN, xcd_remap(blockIdx.x, tilesM * tilesN * naux), smem);
+  half_tile<C, GEN>(B, nao, npair, Cm, out, tilesM, tilesN, xcd_remap(blockIdx.x, tilesM * tilesN * naux), r0, smem);
 }
 
 // The half transform with the J-vector partials in its epilogue (JvEpi).
 template <class C>
 __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) half_jv_kernel(const double* __restrict__ B, int64_t naux, int nao,
                                                         int64_t npair, OpMap Cm, OutMap out, int64_t tilesM,
-                                                        int64_t tilesN, JvEpi jv) {
+                                                        int64_t tilesN, int r0, JvEpi jv) {
   __shared__ double smem[2 * C::STAGE];
   half_tile<C, false, true>(B, nao, npair, Cm, out, tilesM, tilesN, xcd_remap(blockIdx.x, tilesM * tilesN * naux),
-                            smem, &jv);
+                            r0, smem, &jv);
 }
 
 // v[P] (+)= sum_{t < tiles} part[P * tiles + t], in tile order.
@@ -732,7 +737,7 @@ __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2)))
   int p = 0;
   while (p + 1 < g.n && item >= g.start[p + 1]) ++p;
   const HalfDesc& d = g.d[p];
-  half_tile<C>(d.B, d.nao, d.npair, d.Cm, d.out, d.tilesM, d.tilesN, item - g.start[p], smem);
+  half_tile<C>(d.B, d.nao, d.npair, d.Cm, d.out, d.tilesM, d.tilesN, item - g.start[p], 0, smem);
 }
 
 // part[split] (m, n) = sum_{P in split} sum_k b^P_{mk} Y(n, (P, k)): the packed half-transform
@@ -1091,40 +1096,10 @@ bool offsets_fit(const OpMap& o) {
   return o.rows < (1LL << 31) && o.rl < (1LL << 31) && top < (1LL << 32);
 }
 
-template <class Cg>
-static hipError_t half_launch(const double* B, int64_t naux, int64_t nao, const OpMap& cm, const OutMap& out,
-                              hipStream_t s) {
-  const int64_t tm = cdiv(nao, Cg::BM), tn = cdiv(cm.rows, Cg::BN);
-  const int64_t nblk = tm * tn * naux;
-  if (nblk == 0) return hipSuccess;
-  if (nblk > 0x7fffffffLL || !offsets_fit(cm)) return hipErrorInvalidValue;
-  if (out.alpha != 1.0 || out.accumulate)
-    half_kernel<Cg, true><<<dim3((unsigned)nblk), dim3(Cg::NT), 0, s>>>(B, naux, (int)nao, nao * (nao + 1) / 2, cm,
-                                                                       out, tm, tn);
-  else
-    half_kernel<Cg, false><<<dim3((unsigned)nblk), dim3(Cg::NT), 0, s>>>(B, naux, (int)nao, nao * (nao + 1) / 2, cm,
-                                                                        out, tm, tn);
-  return hipGetLastError();
-}
-
-template <class Cg>
-static hipError_t half_jv_launch(const double* B, int64_t naux, int64_t nao, const OpMap& cm, const OutMap& out,
-                                 const JvEpi& jv, double* v, int accumulate, hipStream_t s) {
-  const int64_t tm = cdiv(nao, Cg::BM), tn = cdiv(cm.rows, Cg::BN);
-  const int64_t nblk = tm * tn * naux;
-  if (nblk == 0) return hipSuccess;
-  if (nblk > 0x7fffffffLL || !offsets_fit(cm) || out.alpha != 1.0 || out.accumulate) return hipErrorInvalidValue;
-  half_jv_kernel<Cg><<<dim3((unsigned)nblk), dim3(Cg::NT), 0, s>>>(B, naux, (int)nao, nao * (nao + 1) / 2, cm, out,
-                                                                   tm, tn, jv);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  jv_reduce_kernel<<<(unsigned)cdiv(naux, 256), 256, 0, s>>>(jv.part, tm * tn, naux, v, accumulate);
-  return hipGetLastError();
-}
-
-// Column tile of the half transform: the widest of {176, 96, 48} whose padded width is within 8%
-// of the least padded one.  A wider tile reads each band of b^P fewer times per column, which
-// outweighs a few percent of padded columns (at 1200 columns: 176 pads to 1232, 48 to 1200).
+// Column tile of the half transform on one row of waves: the widest of {176, 96, 48} whose padded
+// width is within 8% of the least padded one.  A wider tile reads each band of b^P fewer times
+// per column, which outweighs a few percent of padded columns (at 1200 columns: 176 pads to
+// 1232, 48 to 1200).
 int half_tile_n(int64_t ncol) {
   const int cands[3] = {176, 96, 48};
   int64_t least = INT64_MAX;
@@ -1134,36 +1109,172 @@ int half_tile_n(int64_t ncol) {
   return cands[2];
 }
 
+// Tilings of the half transform.  One row of waves (4 x 1 waves of 1 x 11, 2 x 6 or 2 x 3 MFMA
+// blocks: 64 x 176, 128 x 96, 128 x 48) fits odd column counts (176 = 11 x 16), but its waves
+// issue one LDS read per MFMA.  2 x 2 waves of 4 x 4 blocks read half as much per MFMA and keep
+// the matrix cores busier (0.81 of the time against 0.73 for 1 x 11, both measured at N_ao =
+// 1200), at 128-row bands and 128-column tiles.  The 2-D tiling takes the columns in 128-wide
+// tiles plus one narrower remainder (96 or 64 wide: 2 x 2 waves of 4 x 3 or 4 x 2 blocks), the
+// rows in whole 128-row bands, and the rows past the last whole band (if any) on one row of
+// waves.  Each piece is a launch of its own; the choice is the tiling of least estimated time,
+// padded area over the matrix-core busy fraction of its tile shape.
+enum HalfCfg { kH176, kH96, kH48, kQ128, kQ96, kQ64 };
+struct HalfSeg {
+  int cfg;
+  int64_t r0, r1, c0, c1;   // rows [r0, r1) and columns [c0, c1) of the output
+};
+static int half_cfg_rows(int cfg) { return cfg == kH176 ? 64 : 128; }
+static int half_cfg_cols(int cfg) {
+  switch (cfg) {
+    case kH176: return 176;
+    case kH96: return 96;
+    case kH48: return 48;
+    case kQ128: return 128;
+    case kQ96: return 96;
+    default: return 64;
+  }
+}
+// matrix-core busy fraction of each tile shape (1 x 11 and 4 x 4 measured; the others estimated
+// from their LDS reads per MFMA)
+static double half_cfg_busy(int cfg) {
+  switch (cfg) {
+    case kH176: return 0.73;
+    case kH96: return 0.72;
+    case kH48: return 0.68;
+    case kQ128: return 0.81;
+    case kQ96: return 0.78;
+    default: return 0.72;
+  }
+}
+static double half_seg_cost(const HalfSeg& g) {
+  const int bm = half_cfg_rows(g.cfg), bn = half_cfg_cols(g.cfg);
+  return (double)(cdiv(g.r1 - g.r0, bm) * bm) * (double)(cdiv(g.c1 - g.c0, bn) * bn) / half_cfg_busy(g.cfg);
+}
+static int half_cfg_1d(int64_t ncol) {
+  const int n = half_tile_n(ncol);
+  return n == 176 ? kH176 : n == 96 ? kH96 : kH48;
+}
+
+// The pieces of the half transform of nao rows and ncol columns (at most 3).  `split_cols` says
+// whether the output map can be cut along its columns (no column blocking).
+static int half_scheme(int64_t nao, int64_t ncol, bool split_cols, HalfSeg* seg) {
+  seg[0] = HalfSeg{half_cfg_1d(ncol), 0, nao, 0, ncol};
+  if (!split_cols || nao < 128 || ncol < 64) return 1;
+  double best = half_seg_cost(seg[0]);
+  int nbest = 1;
+  HalfSeg cand[3];
+  for (int tail = 0; tail < 2; ++tail) {
+    const int64_t rq = tail ? nao / 128 * 128 : nao;
+    if (tail && (rq == nao || rq == 0)) continue;
+    int n = 0;
+    const int64_t cq = ncol / 128 * 128, rem = ncol - cq;
+    if (cq > 0) cand[n++] = HalfSeg{kQ128, 0, rq, 0, cq};
+    if (rem > 0) cand[n++] = HalfSeg{rem > 96 ? kQ128 : rem > 64 ? kQ96 : kQ64, 0, rq, cq, ncol};
+    if (tail) cand[n++] = HalfSeg{half_cfg_1d(ncol), rq, nao, 0, ncol};
+    double cost = 0.0;
+    for (int i = 0; i < n; ++i) cost += half_seg_cost(cand[i]);
+    if (cost < best) {
+      best = cost;
+      nbest = n;
+      for (int i = 0; i < n; ++i) seg[i] = cand[i];
+    }
+  }
+  return nbest;
+}
+
+// `o` restricted to columns [c0, c1) (no column blocking: s_nh == 0)
+static OutMap out_cols(OutMap o, int64_t c0, int64_t c1) {
+  if (c0 < o.nsplit) {
+    o.p += c0 * o.s_nl;
+    o.nsplit -= c0;
+  } else {
+    o.p2 += c0 - o.nsplit;
+    o.nsplit = 0;
+  }
+  o.N = std::min(o.N, c1) - c0;
+  return o;
+}
+
+template <class Cg>
+static hipError_t half_seg_go(const double* B, int64_t naux, int64_t nao, const double* C, int64_t ldc,
+                              const HalfSeg& g, const OutMap& out, const JvEpi* jv, hipStream_t s) {
+  const OpMap cm = op_map(C + g.c0, g.c1 - g.c0, 1, nao, ldc);
+  const OutMap o = out_cols(out, g.c0, g.c1);
+  const int64_t tm = cdiv(g.r1 - g.r0, Cg::BM), tn = cdiv(g.c1 - g.c0, Cg::BN);
+  const int64_t nblk = tm * tn * naux;
+  if (nblk == 0) return hipSuccess;
+  if (nblk > 0x7fffffffLL || !offsets_fit(cm)) return hipErrorInvalidValue;
+  const int64_t npair = nao * (nao + 1) / 2;
+  if (jv) {
+    if (o.alpha != 1.0 || o.accumulate) return hipErrorInvalidValue;
+    JvEpi j = *jv;
+    j.C = jv->C + g.c0;
+    j.nv = (int)std::max<int64_t>(0, std::min<int64_t>(jv->nv - g.c0, g.c1 - g.c0));
+    half_jv_kernel<Cg><<<dim3((unsigned)nblk), dim3(Cg::NT), 0, s>>>(B, naux, (int)nao, npair, cm, o, tm, tn,
+                                                                     (int)g.r0, j);
+  } else if (o.alpha != 1.0 || o.accumulate) {
+    half_kernel<Cg, true><<<dim3((unsigned)nblk), dim3(Cg::NT), 0, s>>>(B, naux, (int)nao, npair, cm, o, tm, tn,
+                                                                       (int)g.r0);
+  } else {
+    half_kernel<Cg, false><<<dim3((unsigned)nblk), dim3(Cg::NT), 0, s>>>(B, naux, (int)nao, npair, cm, o, tm, tn,
+                                                                        (int)g.r0);
+  }
+  return hipGetLastError();
+}
+
+static int64_t half_seg_tiles(const HalfSeg& g) {
+  return cdiv(g.r1 - g.r0, half_cfg_rows(g.cfg)) * cdiv(g.c1 - g.c0, half_cfg_cols(g.cfg));
+}
+
+static hipError_t half_run(const double* B, int64_t naux, int64_t nao, const double* C, int64_t ldc, int64_t ncol,
+                           const OutMap& out, JvEpi* jv, hipStream_t s) {
+  HalfSeg seg[3];
+  const int n = half_scheme(nao, ncol, out.s_nh == 0, seg);
+  if (jv) {
+    jv->T = 0;
+    for (int i = 0; i < n; ++i) jv->T += half_seg_tiles(seg[i]);
+    jv->toff = 0;
+  }
+  for (int i = 0; i < n; ++i) {
+    hipError_t e;
+    switch (seg[i].cfg) {
+      case kH176: e = half_seg_go<CfgH176>(B, naux, nao, C, ldc, seg[i], out, jv, s); break;
+      case kH96: e = half_seg_go<CfgH96>(B, naux, nao, C, ldc, seg[i], out, jv, s); break;
+      case kH48: e = half_seg_go<CfgH48>(B, naux, nao, C, ldc, seg[i], out, jv, s); break;
+      case kQ128: e = half_seg_go<CfgQ128>(B, naux, nao, C, ldc, seg[i], out, jv, s); break;
+      case kQ96: e = half_seg_go<CfgQ96>(B, naux, nao, C, ldc, seg[i], out, jv, s); break;
+      default: e = half_seg_go<CfgQ64>(B, naux, nao, C, ldc, seg[i], out, jv, s); break;
+    }
+    if (e != hipSuccess) return e;
+    if (jv) jv->toff += half_seg_tiles(seg[i]);
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_half_transform(const double* B, int64_t naux, int64_t nao, const double* C, int64_t ldc,
                                  int64_t ncol, const OutMap& out, hipStream_t s) {
-  // B operand: element (n = column of C, k = AO index) at C + k*ldc + n
-  const OpMap cm = op_map(C, ncol, 1, nao, ldc);
-  switch (half_tile_n(ncol)) {
-    case 176: return half_launch<CfgH176>(B, naux, nao, cm, out, s);
-    case 96: return half_launch<CfgH96>(B, naux, nao, cm, out, s);
-    default: return half_launch<CfgH48>(B, naux, nao, cm, out, s);
-  }
+  return half_run(B, naux, nao, C, ldc, ncol, out, nullptr, s);
 }
 
 int64_t half_tiles(int64_t nao, int64_t ncol) {
-  switch (half_tile_n(ncol)) {
-    case 176: return cdiv(nao, CfgH176::BM) * cdiv(ncol, CfgH176::BN);
-    case 96: return cdiv(nao, CfgH96::BM) * cdiv(ncol, CfgH96::BN);
-    default: return cdiv(nao, CfgH48::BM) * cdiv(ncol, CfgH48::BN);
-  }
+  HalfSeg seg[3];
+  const int n = half_scheme(nao, ncol, true, seg);
+  int64_t T = 0;
+  for (int i = 0; i < n; ++i) T += half_seg_tiles(seg[i]);
+  return T;
 }
 
 hipError_t launch_half_transform_jvec(const double* B, int64_t naux, int64_t nao, const double* C, int64_t ldc,
                                       int64_t ncol, const OutMap& out, const double* w, int64_t nv, double* part,
                                       double* v, int accumulate, hipStream_t s) {
-  if (nv < 0 || nv > ncol || nv > 0x7fffffffLL) return hipErrorInvalidValue;
-  const OpMap cm = op_map(C, ncol, 1, nao, ldc);
-  const JvEpi jv{C, ldc, w, (int)nv, part};
-  switch (half_tile_n(ncol)) {
-    case 176: return half_jv_launch<CfgH176>(B, naux, nao, cm, out, jv, v, accumulate, s);
-    case 96: return half_jv_launch<CfgH96>(B, naux, nao, cm, out, jv, v, accumulate, s);
-    default: return half_jv_launch<CfgH48>(B, naux, nao, cm, out, jv, v, accumulate, s);
-  }
+  if (nv < 0 || nv > ncol || nv > 0x7fffffffLL || out.s_nh != 0) return hipErrorInvalidValue;
+  if (naux == 0) return hipSuccess;
+  JvEpi jv{C, ldc, w, (int)nv, part, 0, 0};
+  hipError_t e = half_run(B, naux, nao, C, ldc, ncol, out, &jv, s);
+  if (e != hipSuccess) return e;
+  if (jv.T == 0) return hipErrorInvalidValue;
+  jv_reduce_kernel<<<(unsigned)cdiv(naux, 256), 256, 0, s>>>(part, jv.T, naux, v, accumulate);
+  return hipGetLastError();
 }
 
 // The 256-row tile when it pads the rows no more than the 128-row one.
