@@ -225,7 +225,7 @@ BwdPlan plan_backward(Plan& pl, int64_t naux, int64_t nao, int64_t nocc, int64_t
   p.M = pl.take(gj && nocc > 0 ? nao * nao : 0);
   p.S = pl.take(do_k ? nao * nao : 0);
   p.Y = pl.take(do_k ? ch * dfk::kpad16(nao) * nocc : 0);
-  p.kpart = pl.take(do_k ? (int64_t)dfk::half_reduce_splits_bound(nao, nocc, ch) * nao * nocc : 0);
+  p.kpart = pl.take(do_k ? dfk::half_reduce_part_bound(nao, nocc, ch) : 0);
   p.Gs = pl.take(do_e ? nac * nac * nac * nac : 0);
   p.buv = pl.take(do_e ? ch * nac * nac : 0);
   p.Z = pl.take(do_e ? ch * nac * nac : 0);
@@ -2081,9 +2081,7 @@ df_status df_step_backward(df_ctx* ctx, const double* B, int64_t naux, int64_t n
       Ym.s_kb = kp * nocc;
       dfk::OutMap Od = dfk::out_plain(dCocc, nao, nocc, nocc);
       Od.accumulate = do_j || p0 > 0 ? 1 : 0;
-      const int nsk = dfk::half_reduce_splits(nao, nocc, pc);
-      DF_LAUNCH(DF_KERNEL_ADJOINT,
-                dfk::launch_half_reduce(Bc, pc, nao, Ym, Od, nsk, (double*)(ws + p.kpart), c->stream),
+      DF_LAUNCH(DF_KERNEL_ADJOINT, dfk::launch_half_reduce(Bc, pc, nao, Ym, Od, (double*)(ws + p.kpart), c->stream),
                 "adjoint packed product");
     }
     if (do_e)

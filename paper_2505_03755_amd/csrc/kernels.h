@@ -82,12 +82,12 @@ hipError_t launch_split_reduce(const double* part, int nsplit, const OutMap& O, 
 
 // C(m, n) = sum_{P < naux} sum_k b^P_{mk} Y(n, (P, k)), Y given as an OpMap whose kb is P and
 // kc the AO index k (kc_n = nao); for every P the entries k in [nao, kpad16(nao)) must exist
-// and be zero.  Split over P ranges with partials [nsplit][nao][N] (half_reduce_splits()).
-int half_reduce_splits(int64_t nao, int64_t N, int64_t naux);
-// The most splits half_reduce_splits(nao, N, n) gives for any n <= naux.
-int half_reduce_splits_bound(int64_t nao, int64_t N, int64_t naux);
+// and be zero.  The P range is split over workgroups, each piece of the tiling with its own
+// split count, and the partials (in `part`, half_reduce_part_bound(nao, N, naux) doubles at most)
+// are added up in a fixed order.  C must have no row or column blocking (s_mh = s_nh = 0).
+int64_t half_reduce_part_bound(int64_t nao, int64_t N, int64_t naux);
 hipError_t launch_half_reduce(const double* B, int64_t naux, int64_t nao, const OpMap& Y, const OutMap& C,
-                              int nsplit, double* part, hipStream_t s);
+                              double* part, hipStream_t s);
 
 // g[pair(i,j)] = G[i][j] + G[j][i] (i > j), G[i][i] (i == j): <b^P, G> = sum_pair b^P[pair] g[pair]
 hipError_t launch_pair_weights(const double* G, int64_t nao, double* g, hipStream_t s);

@@ -54,7 +54,6 @@ typedef Cfg<2, 2, 4, 4, true> CfgSyrk;
 typedef Cfg<2, 2, 2, 2, true> CfgSyrk64;
 // half transform: {64, 128, 128} rows x {176, 96, 48} columns, 4 waves stacked along the rows
 typedef Cfg<4, 1, 1, 11, true> CfgH176;
-typedef Cfg<4, 1, 1, 10, true> CfgH160;   // the P-summed packed product: 300 columns in 2 x 160
 typedef Cfg<4, 1, 2, 6> CfgH96;
 typedef Cfg<4, 1, 2, 3> CfgH48;
 // half transform on 2-D wave tiles: 128 rows x {128, 96, 64} columns, 2 x 2 waves of 4 x {4, 3, 2}
@@ -742,10 +741,13 @@ __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2)))
 
 // part[split] (m, n) = sum_{P in split} sum_k b^P_{mk} Y(n, (P, k)): the packed half-transform
 // product with the right operand changing with P and the P sum split over grid y.
+// Row bands start at row r0; part[split] holds rows [r0, r0 + tilesM * BM) clipped to nao, as
+// [nao - r0 clipped][N] with N = Y.rows.
 template <class C>
 __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) half_reduce_kernel(const double* __restrict__ B, int64_t naux, int nao,
                                                             int64_t npair, OpMap Y, int64_t N, int64_t tilesM,
-                                                            int64_t tilesN, int nsplit, double* part) {
+                                                            int64_t tilesN, int nsplit, int r0, int64_t rows,
+                                                            double* part) {
   __shared__ double smem[2 * C::STAGE];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave % C::WM, wn = wave / C::WM;
@@ -755,7 +757,7 @@ __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2)))
   const int64_t item = xcd_remap(blockIdx.x, ntile * nsplit);
   const int split = (int)(item / ntile);
   const int64_t tile = item % ntile;
-  const int m0 = (int)((tile / tilesN) * C::BM), n0 = (int)((tile % tilesN) * C::BN);
+  const int m0 = r0 + (int)((tile / tilesN) * C::BM), n0 = (int)((tile % tilesN) * C::BN);
   const int64_t P0 = naux * split / nsplit, P1 = naux * (split + 1) / nsplit;
   const int nks = (nao + C::BK - 1) / C::BK;
   d4 acc[C::TM][C::TN];
@@ -767,8 +769,8 @@ __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2)))
     src.init(B, npair, P0, P1, nao, m0, t);
     mainloop<C>(src, smem, (P1 - P0) * nks, acc, wm, wn, lane);
   }
-  const OutMap po = out_plain(part + (int64_t)split * nao * N, nao, N, N);
-  store_tile<C, false>(po, 0, m0, n0, acc, wm, wn, lane);
+  const OutMap po = out_plain(part + (int64_t)split * rows * N, rows, N, N);
+  store_tile<C, false>(po, 0, m0 - r0, n0, acc, wm, wn, lane);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1385,40 +1387,67 @@ hipError_t launch_gemm_split(const OpMap& A, const OpMap& Bm, const OutMap& O, i
   return hipGetLastError();
 }
 
-// Column tile of the P-summed packed product: 176 or 160, whichever pads N less (176 on ties).
-static int half_reduce_tile_n(int64_t N) { return cdiv(N, 160) * 160 < cdiv(N, 176) * 176 ? 160 : 176; }
+// The P-summed packed product takes the half transform's tilings (half_scheme): each piece is a
+// launch of its own with its own P split (filling the resident workgroups) and its own partials
+// [splits][rows][cols], reduced into O piece by piece.
+static int half_reduce_seg_splits(const HalfSeg& g, int64_t naux) { return balanced_splits(half_seg_tiles(g), naux); }
 
-int half_reduce_splits(int64_t nao, int64_t N, int64_t naux) {
-  return balanced_splits(cdiv(nao, CfgH176::BM) * cdiv(N, half_reduce_tile_n(N)), naux);
-}
-
-int half_reduce_splits_bound(int64_t nao, int64_t N, int64_t naux) {
-  return balanced_splits_bound(cdiv(nao, CfgH176::BM) * cdiv(N, half_reduce_tile_n(N)), naux);
+int64_t half_reduce_part_bound(int64_t nao, int64_t N, int64_t naux) {
+  HalfSeg seg[3];
+  const int n = half_scheme(nao, N, true, seg);
+  int64_t total = 0;
+  for (int i = 0; i < n; ++i)
+    total += (int64_t)balanced_splits_bound(half_seg_tiles(seg[i]), naux) * (seg[i].r1 - seg[i].r0) *
+             (seg[i].c1 - seg[i].c0);
+  return total;
 }
 
 template <class Cg>
-static hipError_t half_reduce_go(const double* B, int64_t naux, int64_t nao, const OpMap& Y, const OutMap& O,
+static hipError_t half_reduce_go(const double* B, int64_t naux, int64_t nao, const OpMap& Y, const HalfSeg& g,
                                  int nsplit, double* part, hipStream_t s) {
-  const int64_t tm = cdiv(nao, Cg::BM), tn = cdiv(O.N, Cg::BN);
+  OpMap Yg = Y;
+  Yg.p = Y.p + g.c0;
+  Yg.rows = Yg.rl = g.c1 - g.c0;
+  const int64_t tm = cdiv(g.r1 - g.r0, Cg::BM), tn = cdiv(g.c1 - g.c0, Cg::BN);
   const int64_t nblk = tm * tn * nsplit;
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
-  half_reduce_kernel<Cg><<<dim3((unsigned)nblk), Cg::NT, 0, s>>>(B, naux, (int)nao, nao * (nao + 1) / 2, Y, O.N, tm,
-                                                                tn, nsplit, part);
+  half_reduce_kernel<Cg><<<dim3((unsigned)nblk), Cg::NT, 0, s>>>(B, naux, (int)nao, nao * (nao + 1) / 2, Yg,
+                                                                g.c1 - g.c0, tm, tn, nsplit, (int)g.r0,
+                                                                g.r1 - g.r0, part);
   return hipGetLastError();
 }
 
 hipError_t launch_half_reduce(const double* B, int64_t naux, int64_t nao, const OpMap& Y, const OutMap& O,
-                              int nsplit, double* part, hipStream_t s) {
+                              double* part, hipStream_t s) {
   if (nao <= 0 || O.N <= 0) return hipSuccess;
-  if (nsplit < 1 || nsplit > 65535 || !offsets_fit(Y)) return hipErrorInvalidValue;
-  hipError_t e = half_reduce_tile_n(O.N) == 160 ? half_reduce_go<CfgH160>(B, naux, nao, Y, O, nsplit, part, s)
-                                                 : half_reduce_go<CfgH176>(B, naux, nao, Y, O, nsplit, part, s);
-  if (e != hipSuccess) return e;
-  OutMap Oc = O;
-  Oc.M = nao;
-  const int64_t MN = nao * O.N;
-  split_reduce_kernel<<<(unsigned)cdiv(MN, 256), 256, 0, s>>>(part, nsplit, Oc);
-  return hipGetLastError();
+  if (naux < 1 || !offsets_fit(Y) || O.s_nh != 0 || O.s_mh != 0) return hipErrorInvalidValue;
+  HalfSeg seg[3];
+  const int n = half_scheme(nao, O.N, true, seg);
+  for (int i = 0; i < n; ++i) {
+    const HalfSeg& g = seg[i];
+    const int ns = half_reduce_seg_splits(g, naux);
+    hipError_t e;
+    switch (g.cfg) {
+      case kH176: e = half_reduce_go<CfgH176>(B, naux, nao, Y, g, ns, part, s); break;
+      case kH96: e = half_reduce_go<CfgH96>(B, naux, nao, Y, g, ns, part, s); break;
+      case kH48: e = half_reduce_go<CfgH48>(B, naux, nao, Y, g, ns, part, s); break;
+      case kQ128: e = half_reduce_go<CfgQ128>(B, naux, nao, Y, g, ns, part, s); break;
+      case kQ96: e = half_reduce_go<CfgQ96>(B, naux, nao, Y, g, ns, part, s); break;
+      default: e = half_reduce_go<CfgQ64>(B, naux, nao, Y, g, ns, part, s); break;
+    }
+    if (e != hipSuccess) return e;
+    // the piece's rows and columns of O
+    OutMap Oc = out_cols(O, g.c0, g.c1);
+    if (Oc.nsplit > 0) Oc.p += g.r0 * Oc.s_ml;
+    if (Oc.p2) Oc.p2 += g.r0 * Oc.s2_m;
+    Oc.M = g.r1 - g.r0;
+    const int64_t MN = Oc.M * Oc.N;
+    split_reduce_kernel<<<(unsigned)cdiv(MN, 256), 256, 0, s>>>(part, ns, Oc);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    part += (int64_t)ns * MN;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_pair_weights(const double* G, int64_t nao, double* g, hipStream_t s) {
