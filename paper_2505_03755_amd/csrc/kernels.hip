@@ -1171,7 +1171,18 @@ static int half_scheme(int64_t nao, int64_t ncol, bool split_cols, HalfSeg* seg)
     int n = 0;
     const int64_t cq = ncol / 128 * 128, rem = ncol - cq;
     if (cq > 0) cand[n++] = HalfSeg{kQ128, 0, rq, 0, cq};
-    if (rem > 0) cand[n++] = HalfSeg{rem > 96 ? kQ128 : rem > 64 ? kQ96 : kQ64, 0, rq, cq, ncol};
+    if (rem > 0) {   // the remainder columns on the cheapest tile of 128 rows
+      const int rc[5] = {kQ128, kQ96, kQ64, kH96, kH48};
+      double rbest = 0.0;
+      for (int q = 0; q < 5; ++q) {
+        const HalfSeg g{rc[q], 0, rq, cq, ncol};
+        if (q == 0 || half_seg_cost(g) < rbest) {
+          rbest = half_seg_cost(g);
+          cand[n] = g;
+        }
+      }
+      ++n;
+    }
     if (tail) cand[n++] = HalfSeg{half_cfg_1d(ncol), rq, nao, 0, ncol};
     double cost = 0.0;
     for (int i = 0; i < n; ++i) cost += half_seg_cost(cand[i]);
