@@ -404,8 +404,10 @@ df_status df_batched_step(df_ctx* ctx, const df_problem* probs, int nprob, int f
  * than by a fixed rule).  With enable != 0, the first df_batched_step on a problem group whose
  * shape the context has not seen runs every candidate of each phase twice on the call's own
  * buffers, timed with events on the context's stream.  The phases are the half-transform
- * column tile (176, 96, 48) and the K tile (64, 128) with its split target (16, 4, 64 rounds of
- * resident workgroups).  The call keeps the fastest of each phase in the context's table, keyed
+ * tile (176, 96, 48: the column width on one row of waves; 128: 128 x 128 tiles on 2 x 2 waves,
+ * with each problem's rows past its last whole 128-row band on 64 x 176 tiles where that pads
+ * less) and the K tile (64, 128) with its split target (16, 4, 64 rounds of resident
+ * workgroups).  The call keeps the fastest of each phase in the context's table, keyed
  * by every problem's (naux, nao, ndm, nocc, nac, np) and its requested outputs, then computes
  * its outputs with them.
  *   - Such a call waits for the GPU.  It is never made while the stream is being captured;

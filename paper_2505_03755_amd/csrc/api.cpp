@@ -509,7 +509,7 @@ int64_t batched_work(const df_problem& q) { return q.naux * q.nao * q.nao * batc
 // same number of 16-deep slabs, about sixteen rounds of resident workgroups in all, so that
 // the long contractions of the big problems do not run alone at the end.
 // Candidate configurations the autotuner times (the first of each is the default).
-constexpr int kHalfTiles[] = {176, 96, 48};
+constexpr int kHalfTiles[] = {176, 96, 48, 128};
 constexpr int kKTiles[] = {64, 128};
 constexpr int kKRounds[] = {16, 4, 64};
 
@@ -553,8 +553,18 @@ std::vector<int> batched_k_splits_max(const df_problem* probs, int n) {
   return m;
 }
 
+// The half-transform tile by the padded-area estimate: 2-D tiles (128) or one row of waves (176).
+int batched_default_half_tile(const df_problem* probs, int n) {
+  std::vector<int64_t> nao, ncol;
+  for (int i = 0; i < n; ++i) {
+    nao.push_back(probs[i].nao);
+    ncol.push_back(batched_ncol(probs[i]));
+  }
+  return n > 0 ? dfk::half_group_tile_for(nao.data(), ncol.data(), n) : kHalfTiles[0];
+}
+
 BatchedTune batched_default_tune(const df_problem* probs, int n) {
-  return BatchedTune{kHalfTiles[0], batched_default_k_tile(probs, n), kKRounds[0]};
+  return BatchedTune{batched_default_half_tile(probs, n), batched_default_k_tile(probs, n), kKRounds[0]};
 }
 
 // The shape of a problem group: what the work and hence the best configuration depend on.
@@ -598,7 +608,7 @@ const BatchedTune* tune_find(const df_ctx* c, const std::string& shape) {
 
 bool tune_valid(const BatchedTune& t) {
   auto in = [](int v, const int* set, int n) { return std::find(set, set + n, v) != set + n; };
-  return in(t.half_n, kHalfTiles, 3) && in(t.k_tile, kKTiles, 2) && in(t.k_rounds, kKRounds, 3);
+  return in(t.half_n, kHalfTiles, 4) && in(t.k_tile, kKTiles, 2) && in(t.k_rounds, kKRounds, 3);
 }
 
 // The value of "name" in one flat JSON object (a string without escapes, or an integer).

@@ -169,8 +169,14 @@ struct GroupHalf {
   int64_t ldc, ncol;
   OutMap out;
 };
-// tile_n: column tile of the launch, 176, 96 or 48 (0 = 176).
+// tile_n: column tile of the launch on one row of waves, 176, 96 or 48 (0 = 176); or 128: the
+// 2-D tiling (128 x 128 tiles on 2 x 2 waves of 4 x 4 MFMA blocks, and per problem, where the
+// padded area says it pays, the rows past its last whole 128-row band on 64 x 176 tiles in a
+// second grouped launch).
 hipError_t launch_half_group(const GroupHalf* probs, int n, int tile_n, hipStream_t s);
+// The tile_n of launch_half_group with the least estimated time (padded area over matrix-core
+// busy fraction) over problems of nao[i] rows and ncol[i] columns: 128 or 176.
+int half_group_tile_for(const int64_t* nao, const int64_t* ncol, int n);
 // Lower-tile SYRK partials of problem p: as launch_syrk_partial with (A, A, n, nz, nsplit, Kpart).
 struct GroupSyrk {
   OpMap A;

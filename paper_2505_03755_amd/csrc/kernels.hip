@@ -712,7 +712,7 @@ struct HalfDesc {
   int64_t npair, tilesM, tilesN;
   OpMap Cm;
   OutMap out;
-  int nao;
+  int nao, r0;   // row bands from row r0
 };
 struct HalfGroup {
   int n;
@@ -736,7 +736,7 @@ __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2)))
   int p = 0;
   while (p + 1 < g.n && item >= g.start[p + 1]) ++p;
   const HalfDesc& d = g.d[p];
-  half_tile<C>(d.B, d.nao, d.npair, d.Cm, d.out, d.tilesM, d.tilesN, item - g.start[p], 0, smem);
+  half_tile<C>(d.B, d.nao, d.npair, d.Cm, d.out, d.tilesM, d.tilesN, item - g.start[p], d.r0, smem);
 }
 
 // part[split] (m, n) = sum_{P in split} sum_k b^P_{mk} Y(n, (P, k)): the packed half-transform
@@ -1568,32 +1568,74 @@ static int64_t xcd_chunks(const int64_t* start, const double* cost, int n, int64
   return longest;
 }
 
+// rows [r0[p], r1[p]) of problem p (all rows when r0 is null); problems with no rows are skipped
 template <class Cg>
-static hipError_t half_group_go(const GroupHalf* probs, int n, hipStream_t s) {
+static hipError_t half_group_go(const GroupHalf* probs, int n, hipStream_t s, const int64_t* r0 = nullptr,
+                                const int64_t* r1 = nullptr) {
   HalfGroup g{};
-  g.n = n;
   g.start[0] = 0;
-  for (int p = 0; p < n; ++p) {
-    const GroupHalf& q = probs[p];
+  for (int i = 0; i < n; ++i) {
+    const GroupHalf& q = probs[i];
+    const int64_t a = r0 ? r0[i] : 0, b = r1 ? r1[i] : q.nao;
+    if (b <= a) continue;
+    const int p = g.n++;
     HalfDesc& d = g.d[p];
     d.B = q.B;
     d.nao = (int)q.nao;
+    d.r0 = (int)a;
     d.npair = q.nao * (q.nao + 1) / 2;
     d.Cm = op_map(q.C, q.ncol, 1, q.nao, q.ldc);
     d.out = q.out;
-    d.tilesM = cdiv(q.nao, Cg::BM);
+    d.tilesM = cdiv(b - a, Cg::BM);
     d.tilesN = cdiv(q.ncol, Cg::BN);
     if (!offsets_fit(d.Cm) || q.out.alpha != 1.0 || q.out.accumulate) return hipErrorInvalidValue;
     g.start[p + 1] = g.start[p] + d.tilesM * d.tilesN * q.naux;
   }
-  if (g.start[n] == 0) return hipSuccess;
-  if (g.start[n] > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (g.n == 0 || g.start[g.n] == 0) return hipSuccess;
+  if (g.start[g.n] > 0x7fffffffLL) return hipErrorInvalidValue;
   double cost[kMaxGroup];   // slabs per item, plus about two for the prologue and the epilogue
-  for (int p = 0; p < n; ++p) cost[p] = (double)cdiv(g.d[p].nao, Cg::BK) + 2.0;
-  const int64_t per = xcd_chunks(g.start, cost, n, g.xs);
+  for (int p = 0; p < g.n; ++p) cost[p] = (double)cdiv(g.d[p].nao, Cg::BK) + 2.0;
+  const int64_t per = xcd_chunks(g.start, cost, g.n, g.xs);
   if (8 * per > 0x7fffffffLL) return hipErrorInvalidValue;
   half_group_kernel<Cg><<<(unsigned)(8 * per), Cg::NT, 0, s>>>(g);
   return hipGetLastError();
+}
+
+// The 2-D tiling of a problem in a group: the cheaper (padded area over matrix-core busy
+// fraction, as in half_scheme) of all rows on 128 x 128 tiles and the whole 128-row bands on them
+// with the rest of the rows on 64 x 176 tiles.  Returns the rows on 128 x 128 tiles and the cost.
+static int64_t half_group_2d_rows(int64_t nao, int64_t ncol, double* cost) {
+  const int64_t rq = nao / 128 * 128;
+  const double all = half_seg_cost(HalfSeg{kQ128, 0, nao, 0, ncol});
+  const double split = rq > 0 && rq < nao ? half_seg_cost(HalfSeg{kQ128, 0, rq, 0, ncol}) +
+                                                 half_seg_cost(HalfSeg{kH176, rq, nao, 0, ncol})
+                                           : all;
+  *cost = std::min(all, split);
+  return split < all ? rq : nao;
+}
+
+int half_group_tile_for(const int64_t* nao, const int64_t* ncol, int n) {
+  double c2 = 0.0, c1 = 0.0, c;
+  for (int i = 0; i < n; ++i) {
+    half_group_2d_rows(nao[i], ncol[i], &c);
+    c2 += c * (double)nao[i];   // the contraction runs over nao
+    c1 += half_seg_cost(HalfSeg{kH176, 0, nao[i], 0, ncol[i]}) * (double)nao[i];
+  }
+  return c2 < c1 ? 128 : 176;
+}
+
+static hipError_t half_group_2d(const GroupHalf* probs, int n, hipStream_t s) {
+  int64_t q0[kMaxGroup], q1[kMaxGroup], t0[kMaxGroup], t1[kMaxGroup];
+  double c;
+  for (int i = 0; i < n; ++i) {
+    q0[i] = 0;
+    q1[i] = half_group_2d_rows(probs[i].nao, probs[i].ncol, &c);
+    t0[i] = q1[i];
+    t1[i] = probs[i].nao;
+  }
+  hipError_t e = half_group_go<CfgQ128>(probs, n, s, q0, q1);
+  if (e != hipSuccess) return e;
+  return half_group_go<CfgH176>(probs, n, s, t0, t1);
 }
 
 hipError_t launch_half_group(const GroupHalf* probs, int n, int tile_n, hipStream_t s) {
@@ -1603,6 +1645,7 @@ hipError_t launch_half_group(const GroupHalf* probs, int n, int tile_n, hipStrea
     case 176: return half_group_go<CfgH176>(probs, n, s);
     case 96: return half_group_go<CfgH96>(probs, n, s);
     case 48: return half_group_go<CfgH48>(probs, n, s);
+    case 128: return half_group_2d(probs, n, s);
     default: return hipErrorInvalidValue;
   }
 }

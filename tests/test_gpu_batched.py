@@ -161,7 +161,7 @@ def test_batched_every_candidate_configuration():
     dps = [to_dev(p) for p in probs]
     ctx = dfmi.context(dps[0]["B"].device)
     try:
-        for half_n in (176, 96, 48):
+        for half_n in (176, 96, 48, 128):
             for k_tile in (64, 128):
                 for k_rounds in (16, 4, 64):
                     dfmi.batched_set_tuning(dps, half_n, k_tile, k_rounds, ctx=ctx)
@@ -191,7 +191,7 @@ def test_batched_autotune_fragment_workload():
     finally:
         ctx.set_autotune(False)
     t = dfmi.batched_tuning(dps, ctx=ctx)
-    assert t["tuned"] and t["half_tile_n"] in (176, 96, 48) and t["k_tile"] in (64, 128)
+    assert t["tuned"] and t["half_tile_n"] in (176, 96, 48, 128) and t["k_tile"] in (64, 128)
     assert t["k_rounds"] in (16, 4, 64)
     second = dfmi.batched_step(dps, ctx=ctx)
     torch.cuda.synchronize()
@@ -297,6 +297,18 @@ def test_fragment_workload_64_densities(frag64):
     """The benchmarked fragment batch (J of 64 densities through V B^T, K of each) in FP64."""
     probs, dps, refs = frag64
     outs = dfmi.batched_step(dps)
+    torch.cuda.synchronize()
+    check_frag64(outs, refs, 1e-10)
+
+
+def test_fragment_workload_64_densities_2d_tiles(frag64):
+    """The same batch with the half transforms on the 2-D tiling (tuning candidate 128: 128 x 128
+    tiles, each fragment's rows past its last whole 128-row band on 64 x 176 tiles where that pads
+    less), in a context of its own."""
+    probs, dps, refs = frag64
+    ctx = dfmi.Context(dps[0]["B"].device)
+    dfmi.batched_set_tuning(dps, 128, 64, 16, ctx=ctx)
+    outs = dfmi.batched_step(dps, ctx=ctx)
     torch.cuda.synchronize()
     check_frag64(outs, refs, 1e-10)
 
