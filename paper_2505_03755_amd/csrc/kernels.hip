@@ -249,21 +249,30 @@ __device__ __forceinline__ void store_tile(const OutMap& o, int64_t z, int64_t m
 //   CLAMP     : kc_n need not be a multiple of 16: in a partial slab k is clamped to the last
 //               entry and entries past kc_n are zeroed.  Without CLAMP, every slab is read whole,
 //               so kc_n must be a multiple of 16 or the rows padded with zeros up to one.
+//   FLAT      : (KC only; no SCALE) the contraction index is flat, k = kb * kc_n + kc, and slab s
+//               holds k in [16 s, 16 s + 16), running across kb blocks (kc_n >= 16: at most one
+//               block boundary per slab), so kc_n need not be a multiple of 16 and no slab is
+//               padded but the last of the whole contraction; slab numbers s_begin, s_end count
+//               these flat slabs.
 // Element q of a thread sits at base + eoff[q] with base uniform per slab, so without CLAMP a
 // slab costs no per-element arithmetic.
-template <class C, int R, bool KC, bool SCALE = false, bool CLAMP = true>
+template <class C, int R, bool KC, bool SCALE = false, bool CLAMP = true, bool FLAT = false>
 struct Operand {
+  static_assert(!FLAT || (KC && !SCALE), "flat contraction: lanes along k, no weights");
   static constexpr int E = R * C::BK / C::NT;
   uint32_t eoff[E];     // offset of element q from the slab base (row clamped to the last one)
   double v[E];
   double sc[SCALE ? E : 1];
-  int kval;             // valid k entries of the slab set up by begin()
+  int kval;             // valid k entries of the slab set up by begin() (FLAT: entries before the block boundary)
   const double* base;
   const double* cur;    // start of the next slab to load (kept up to date by finish: no multiplies per slab)
   const double* ksb;
   int64_t zoff, kso;
   int64_t kb, kb_last;  // cursor: next slab to load is (kb, kc0)
   int kc0, kc_last;
+  int64_t krem;         // FLAT: entries of the contraction from the next slab's start to its end
+  int rem;              // FLAT: valid entries of the slab set up by begin()
+  uint32_t dwrap;       // FLAT: s_kb - kc_n s_kc, from entry (kb, kc_n + j) to (kb + 1, j)
 
   __device__ __forceinline__ static int rr(int t, int q) {
     const int e = t + C::NT * q;
@@ -278,11 +287,21 @@ struct Operand {
                                        int t) {
     zoff = z * o.s_z;
     kso = z * o.s_ksz;
-    const int64_t nkc = (o.kc_n + C::BK - 1) / C::BK;
-    kb = s_begin / nkc;
-    kc0 = (int)(s_begin % nkc) * C::BK;
-    kb_last = (s_end - 1) / nkc;
-    kc_last = (int)((s_end - 1) % nkc) * C::BK;
+    if constexpr (FLAT) {
+      const int64_t k0 = s_begin * C::BK, kl = (s_end - 1) * C::BK;
+      kb = k0 / o.kc_n;
+      kc0 = (int)(k0 - kb * o.kc_n);
+      kb_last = kl / o.kc_n;
+      kc_last = (int)(kl - kb_last * o.kc_n);
+      krem = o.kb_n * o.kc_n - k0;
+      dwrap = (uint32_t)(o.s_kb - o.kc_n * o.s_kc);
+    } else {
+      const int64_t nkc = (o.kc_n + C::BK - 1) / C::BK;
+      kb = s_begin / nkc;
+      kc0 = (int)(s_begin % nkc) * C::BK;
+      kb_last = (s_end - 1) / nkc;
+      kc_last = (int)((s_end - 1) % nkc) * C::BK;
+    }
     cur = o.p + zoff + kb * o.s_kb + (int64_t)kc0 * o.s_kc;
 #pragma unroll
     for (int q = 0; q < E; ++q) {
@@ -299,11 +318,18 @@ struct Operand {
   __device__ __forceinline__ void begin(const OpMap& o) {
     base = cur;
     kval = (int)o.kc_n - kc0;
+    if constexpr (FLAT) rem = krem < C::BK ? (int)krem : C::BK;
     if constexpr (SCALE) ksb = o.ks + kso + kc0;
   }
   template <int q>
   __device__ __forceinline__ void load(const OpMap& o, int t) {
-    if constexpr (!CLAMP) {
+    if constexpr (FLAT) {
+      // entries past the block boundary continue in the next kb block; entries past the end of
+      // the contraction read the slab's first entry (row 0, in bounds; zeroed in store)
+      const int kq = kk(t, q);
+      const uint32_t off = eoff[q] + (kq >= kval ? dwrap : 0u);
+      v[q] = base[kq < rem ? off : 0u];
+    } else if constexpr (!CLAMP) {
       v[q] = base[eoff[q]];
       if constexpr (SCALE) sc[q] = ksb[kk(t, q)];
     } else {
@@ -317,6 +343,20 @@ struct Operand {
   __device__ __forceinline__ void finish(const OpMap& o) {
     // advance the cursor, but never past the last slab
     const bool at_end = kb == kb_last && kc0 == kc_last;
+    if constexpr (FLAT) {
+      int nkc = kc0 + C::BK;
+      int64_t nkb = kb, step = (int64_t)C::BK * o.s_kc;
+      if (nkc >= o.kc_n) {
+        nkc -= (int)o.kc_n;
+        ++nkb;
+        step += o.s_kb - o.kc_n * o.s_kc;
+      }
+      kc0 = at_end ? kc0 : nkc;
+      kb = at_end ? kb : nkb;
+      cur = at_end ? cur : cur + step;
+      krem = at_end ? krem : krem - C::BK;
+      return;
+    }
     int nkc = kc0 + C::BK;
     int64_t nkb = kb;
     // the next slab starts BK columns on, or at column 0 of the next kb block
@@ -334,18 +374,19 @@ struct Operand {
   __device__ __forceinline__ void store(double* Sm, int t) const {
     const double x = SCALE ? v[q] * sc[q] : v[q];
     const int slot = rr(t, q) * C::LD + kk(t, q);
-    if constexpr (!CLAMP) Sm[slot] = x;
+    if constexpr (FLAT) Sm[slot] = kk(t, q) < rem ? x : 0.0;
+    else if constexpr (!CLAMP) Sm[slot] = x;
     else Sm[slot] = kk(t, q) < kval ? x : 0.0;
   }
 };
 
 // Source of a product with both operands from OpMaps over the same slab sequence.
-template <class C, bool AK, bool BK, bool SCALE, bool CLAMP>
+template <class C, bool AK, bool BK, bool SCALE, bool CLAMP, bool FLAT = false>
 struct PairSrc {
-  static constexpr int EA = Operand<C, C::BM, AK, false, CLAMP>::E;
-  static constexpr int NL = EA + Operand<C, C::BN, BK, SCALE, CLAMP>::E;
-  Operand<C, C::BM, AK, false, CLAMP> a;
-  Operand<C, C::BN, BK, SCALE, CLAMP> b;
+  static constexpr int EA = Operand<C, C::BM, AK, false, CLAMP, FLAT>::E;
+  static constexpr int NL = EA + Operand<C, C::BN, BK, SCALE, CLAMP, FLAT>::E;
+  Operand<C, C::BM, AK, false, CLAMP, FLAT> a;
+  Operand<C, C::BN, BK, SCALE, CLAMP, FLAT> b;
   const OpMap* A;
   const OpMap* B;
   int t;
@@ -426,8 +467,10 @@ __global__ void __launch_bounds__(256) split_reduce_kernel(const double* __restr
 // Lower-triangle tile SYRK with the kb range split over workgroups:
 // Kpart[split][z] tile (I, J), I >= J, = sum_{kb in split} sum_kc A(i, kb, kc) Bw(j, kb, kc),
 // where Bw is A times an optional per-kc weight.
-// One (tile pair, split) item of density z.
-template <class C, bool SCALE, bool CLAMP>
+// One (tile pair, split) item of density z.  FLAT: the contraction (kb, kc) runs as one flat
+// index in slabs of 16 (see Operand) and the flat slabs are split evenly, so no kb block is padded
+// to whole slabs; otherwise the kb range is split and each block padded.
+template <class C, bool SCALE, bool CLAMP, bool FLAT = false>
 __device__ __forceinline__ void syrk_tile(const OpMap& A, const OpMap& Bw, int64_t n, int64_t nz, int nsplit,
                                           int64_t npairs, double* Kpart, int64_t item, int64_t z, double* smem) {
   static_assert(C::BM == C::BN, "square tiles");
@@ -441,31 +484,39 @@ __device__ __forceinline__ void syrk_tile(const OpMap& A, const OpMap& Bw, int64
   while ((I + 1) * (I + 2) / 2 <= pair) ++I;
   const int64_t J = pair - I * (I + 1) / 2;
   const int64_t m0 = I * C::BM, n0 = J * C::BN;
-  const int64_t kb_lo = A.kb_n * split / nsplit, kb_hi = A.kb_n * (split + 1) / nsplit;
+  int64_t s_lo, s_hi;   // slabs of this split
+  if constexpr (FLAT) {
+    const int64_t S = (A.kb_n * A.kc_n + C::BK - 1) / C::BK;
+    s_lo = S * split / nsplit;
+    s_hi = S * (split + 1) / nsplit;
+  } else {
+    const int64_t nkc = (A.kc_n + C::BK - 1) / C::BK;
+    s_lo = A.kb_n * split / nsplit * nkc;
+    s_hi = A.kb_n * (split + 1) / nsplit * nkc;
+  }
 
   d4 acc[C::TM][C::TN];
   zero_acc<C>(acc);
-  const int64_t nslab = (kb_hi - kb_lo) * ((A.kc_n + C::BK - 1) / C::BK);
+  const int64_t nslab = s_hi - s_lo;
   if (nslab > 0) {
-    PairSrc<C, true, true, SCALE, CLAMP> src;
+    PairSrc<C, true, true, SCALE, CLAMP, FLAT> src;
     src.A = &A;
     src.B = &Bw;
     src.t = t;
-    const int64_t nkc = (A.kc_n + C::BK - 1) / C::BK;
-    src.a.init(A, m0, z, kb_lo * nkc, kb_hi * nkc, t);
-    src.b.init(Bw, n0, z, kb_lo * nkc, kb_hi * nkc, t);
+    src.a.init(A, m0, z, s_lo, s_hi, t);
+    src.b.init(Bw, n0, z, s_lo, s_hi, t);
     mainloop<C>(src, smem, nslab, acc, wm, wn, lane);
   }
   OutMap o = out_plain(Kpart + ((int64_t)split * nz + z) * n * n, n, n, n);
   store_tile<C, false>(o, 0, m0, n0, acc, wm, wn, lane);
 }
 
-template <class C, bool SCALE, bool CLAMP>
+template <class C, bool SCALE, bool CLAMP, bool FLAT = false>
 __global__ void __launch_bounds__(C::NT) syrk_kernel(OpMap A, OpMap Bw, int64_t n, int64_t nz, int nsplit,
                                                      int64_t npairs, double* Kpart) {
   __shared__ double smem[2 * C::STAGE];
-  syrk_tile<C, SCALE, CLAMP>(A, Bw, n, nz, nsplit, npairs, Kpart, xcd_remap(blockIdx.x, npairs * nsplit), blockIdx.z,
-                             smem);
+  syrk_tile<C, SCALE, CLAMP, FLAT>(A, Bw, n, nz, nsplit, npairs, Kpart, xcd_remap(blockIdx.x, npairs * nsplit),
+                                   blockIdx.z, smem);
 }
 
 // Grouped K SYRK: problem p owns items [start[p], start[p + 1]) = (density z, split, tile pair),
@@ -484,7 +535,7 @@ struct SyrkGroup {
 };
 
 // With the per-XCD chunks of half_group_kernel.
-template <class C, bool CLAMP>
+template <class C, bool CLAMP, bool FLAT = false>
 __global__ void __launch_bounds__(C::NT) syrk_group_kernel(SyrkGroup g) {
   __shared__ double smem[2 * C::STAGE];
   const int x = blockIdx.x % 8;
@@ -494,7 +545,8 @@ __global__ void __launch_bounds__(C::NT) syrk_group_kernel(SyrkGroup g) {
   while (p + 1 < g.n && it >= g.start[p + 1]) ++p;
   const SyrkDesc& d = g.d[p];
   const int64_t item = it - g.start[p], per_z = d.npairs * d.nsplit;
-  syrk_tile<C, false, CLAMP>(d.A, d.A, d.n, d.nz, d.nsplit, d.npairs, d.Kpart, item % per_z, item / per_z, smem);
+  syrk_tile<C, false, CLAMP, FLAT>(d.A, d.A, d.n, d.nz, d.nsplit, d.npairs, d.Kpart, item % per_z, item / per_z,
+                                   smem);
 }
 
 __global__ void __launch_bounds__(256) syrk_reduce_kernel(const double* __restrict__ Kpart, int nsplit,
@@ -1089,6 +1141,19 @@ __global__ void __launch_bounds__(256) fill_zero_strided_kernel(double* p, int64
 
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// A flat contraction pays where padding each kb block to whole slabs wastes more than 4% of the
+// slabs (at 300 per block, 1.3%, the padded loads measured faster than the flat ones).
+static bool flat_pays(const OpMap& o) { return o.kc_n >= 16 && cdiv(o.kc_n, 16) * 16 * 100 > o.kc_n * 104; }
+
+// A flat contraction adds the step from one kb block to the next to the within-slab offsets.
+static bool flat_fits(const OpMap& o) {
+  if (o.rows <= 0 || o.kc_n <= 0) return true;
+  const int64_t last = o.rows - 1;
+  const int64_t rh = o.s_rh ? last / o.rl : 0, rlo = o.s_rh ? o.rl - 1 : last;
+  const int64_t top = rh * o.s_rh + rlo * o.s_rlo + 15 * o.s_kc + (o.s_kb - o.kc_n * o.s_kc);
+  return o.s_kb >= o.kc_n * o.s_kc && top < (1LL << 32);
+}
+
 bool offsets_fit(const OpMap& o) {
   if (o.rows <= 0 || o.kc_n <= 0) return true;
   const int64_t last = o.rows - 1;
@@ -1527,8 +1592,12 @@ static hipError_t syrk_go(const OpMap& A, const OpMap& Bw, int64_t n, int64_t nz
   if (nz > 65535 || !offsets_fit(A)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(npairs * nsplit), 1, (unsigned)nz);
   const bool clamp = A.kc_n % 16 != 0;
+  // contraction chunks that are not whole slabs: one flat contraction (no padded slabs) unless
+  // weighted or shorter than a slab
+  const bool flat = clamp && !Bw.ks && flat_pays(A) && flat_fits(A);
   if (Bw.ks && clamp) syrk_kernel<Cg, true, true><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
   else if (Bw.ks) syrk_kernel<Cg, true, false><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
+  else if (flat) syrk_kernel<Cg, false, false, true><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
   else if (clamp) syrk_kernel<Cg, false, true><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
   else syrk_kernel<Cg, false, false><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
   return hipGetLastError();
@@ -1655,7 +1724,7 @@ static hipError_t syrk_group_go(const GroupSyrk* probs, int n, hipStream_t s) {
   SyrkGroup g{};
   g.n = n;
   g.start[0] = 0;
-  bool clamp = false;
+  bool clamp = false, flat_ok = true, flat_any = false;
   for (int p = 0; p < n; ++p) {
     const GroupSyrk& q = probs[p];
     SyrkDesc& d = g.d[p];
@@ -1668,16 +1737,25 @@ static hipError_t syrk_group_go(const GroupSyrk* probs, int n, hipStream_t s) {
     d.Kpart = q.Kpart;
     if (!offsets_fit(q.A) || q.nsplit < 1) return hipErrorInvalidValue;
     clamp = clamp || q.A.kc_n % 16 != 0;
+    flat_ok = flat_ok && q.A.kc_n >= 16 && flat_fits(q.A);
+    flat_any = flat_any || flat_pays(q.A);
     g.start[p + 1] = g.start[p] + d.npairs * d.nsplit * q.nz;
   }
   if (g.start[n] == 0) return hipSuccess;
   if (g.start[n] > 0x7fffffffLL) return hipErrorInvalidValue;
+  // contraction chunks that are not whole slabs: one flat contraction per density (no padded
+  // slabs) when every chunk is at least a slab long and the padding would cost
+  const bool flat = clamp && flat_ok && flat_any;
   double cost[kMaxGroup];   // slabs of one split, plus about two for the prologue and the epilogue
-  for (int p = 0; p < n; ++p)
-    cost[p] = (double)cdiv(g.d[p].A.kb_n, g.d[p].nsplit) * (double)cdiv(g.d[p].A.kc_n, Cg::BK) + 2.0;
+  for (int p = 0; p < n; ++p) {
+    const OpMap& A = g.d[p].A;
+    cost[p] = (flat ? (double)cdiv(A.kb_n * A.kc_n, Cg::BK) / g.d[p].nsplit
+                    : (double)cdiv(A.kb_n, g.d[p].nsplit) * (double)cdiv(A.kc_n, Cg::BK)) + 2.0;
+  }
   const int64_t per = xcd_chunks(g.start, cost, n, g.xs);
   if (8 * per > 0x7fffffffLL) return hipErrorInvalidValue;
-  if (clamp) syrk_group_kernel<Cg, true><<<(unsigned)(8 * per), Cg::NT, 0, s>>>(g);
+  if (flat) syrk_group_kernel<Cg, false, true><<<(unsigned)(8 * per), Cg::NT, 0, s>>>(g);
+  else if (clamp) syrk_group_kernel<Cg, true><<<(unsigned)(8 * per), Cg::NT, 0, s>>>(g);
   else syrk_group_kernel<Cg, false><<<(unsigned)(8 * per), Cg::NT, 0, s>>>(g);
   return hipGetLastError();
 }
