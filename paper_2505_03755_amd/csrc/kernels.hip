@@ -673,17 +673,13 @@ struct JvEpi {
   int64_t T, toff;
 };
 
-// One output tile (item = P * tiles + tile) of the half transform; row bands start at row r0.
+// The output tile of b^P at (m0, n0); with JV its J-vector partial goes to slot `tile` of P.
 template <class C, bool GEN = false, bool JV = false>
-__device__ __forceinline__ void half_tile(const double* __restrict__ B, int nao, int64_t npair, const OpMap& Cm,
-                                          const OutMap& out, int64_t tilesM, int64_t tilesN, int64_t item, int r0,
-                                          double* smem, const JvEpi* jv = nullptr) {
+__device__ __forceinline__ void half_tile_at(const double* __restrict__ B, int nao, int64_t npair, const OpMap& Cm,
+                                             const OutMap& out, int64_t P, int m0, int n0, int64_t tile,
+                                             double* smem, const JvEpi* jv) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave % C::WM, wn = wave / C::WM;
-  const int64_t ntile = tilesM * tilesN;
-  // row band major: the column tiles of one band of b^P run side by side and share its reads in L2
-  const int64_t P = item / ntile, tile = item % ntile;
-  const int m0 = r0 + (int)((tile / tilesN) * C::BM), n0 = (int)((tile % tilesN) * C::BN);
   const int nslab = (nao + C::BK - 1) / C::BK;
 
   HalfSrc<C> src;
@@ -724,6 +720,37 @@ __device__ __forceinline__ void half_tile(const double* __restrict__ B, int nao,
       jv->part[P * jv->T + jv->toff + tile] = r;
     }
   }
+}
+
+// One output tile (item = P * tiles + tile) of the half transform; row bands start at row r0.
+template <class C, bool GEN = false, bool JV = false>
+__device__ __forceinline__ void half_tile(const double* __restrict__ B, int nao, int64_t npair, const OpMap& Cm,
+                                          const OutMap& out, int64_t tilesM, int64_t tilesN, int64_t item, int r0,
+                                          double* smem, const JvEpi* jv = nullptr) {
+  const int64_t ntile = tilesM * tilesN;
+  // row band major: the column tiles of one band of b^P run side by side and share its reads in L2
+  const int64_t P = item / ntile, tile = item % ntile;
+  const int m0 = r0 + (int)((tile / tilesN) * C::BM), n0 = (int)((tile % tilesN) * C::BN);
+  half_tile_at<C, GEN, JV>(B, nao, npair, Cm, out, P, m0, n0, tile, smem, jv);
+}
+
+// Rows [r0, r0 + tilesM * 128) on two tile shapes in one launch: per row band, nA tiles of CA
+// (columns [0, nA CA::BN)) and one of CB (the remainder columns from nA CA::BN on).  The tiles of
+// one band of b^P run side by side and share its reads in L2, which two launches would not.
+template <class CA, class CB, bool GEN, bool JV>
+__global__ void __launch_bounds__(CA::NT) __attribute__((amdgpu_waves_per_eu(2))) half_pair_kernel(const double* __restrict__ B, int64_t naux, int nao,
+                                                          int64_t npair, OpMap Cm, OutMap out, int64_t tilesM,
+                                                          int64_t nA, int r0, JvEpi jv) {
+  static_assert(CA::BM == CB::BM && CA::NT == CB::NT, "one row band, one workgroup shape");
+  __shared__ double smem[2 * (CA::STAGE > CB::STAGE ? CA::STAGE : CB::STAGE)];
+  const int64_t per = nA + 1, ntile = tilesM * per;
+  const int64_t item = xcd_remap(blockIdx.x, ntile * naux);
+  const int64_t P = item / ntile, tile = item % ntile, j = tile % per;
+  const int m0 = r0 + (int)((tile / per) * CA::BM);
+  if (j < nA)
+    half_tile_at<CA, GEN, JV>(B, nao, npair, Cm, out, P, m0, (int)(j * CA::BN), tile, smem, &jv);
+  else
+    half_tile_at<CB, GEN, JV>(B, nao, npair, Cm, out, P, m0, (int)(nA * CA::BN), tile, smem, &jv);
 }
 
 // GEN: the epilogue applies out.alpha and out.accumulate (a separate instantiation, see store_tile)
@@ -1304,6 +1331,33 @@ static int64_t half_seg_tiles(const HalfSeg& g) {
   return cdiv(g.r1 - g.r0, half_cfg_rows(g.cfg)) * cdiv(g.c1 - g.c0, half_cfg_cols(g.cfg));
 }
 
+// Two pieces on the same rows, 128-wide tiles on columns [0, cq) and one tile of CB on the rest,
+// as one launch (half_pair_kernel).
+template <class CB>
+static hipError_t half_pair_go(const double* B, int64_t naux, int64_t nao, const double* C, int64_t ldc,
+                               int64_t ncol, const HalfSeg& a, const OutMap& out, JvEpi* jv, hipStream_t s) {
+  const OpMap cm = op_map(C, ncol, 1, nao, ldc);
+  const int64_t tm = cdiv(a.r1 - a.r0, CfgQ128::BM), nA = a.c1 / CfgQ128::BN;
+  const int64_t nblk = tm * (nA + 1) * naux;
+  if (nblk == 0) return hipSuccess;
+  if (nblk > 0x7fffffffLL || !offsets_fit(cm)) return hipErrorInvalidValue;
+  const int64_t npair = nao * (nao + 1) / 2;
+  const JvEpi j = jv ? *jv : JvEpi{};
+  const dim3 g((unsigned)nblk);
+  if (jv) {
+    if (out.alpha != 1.0 || out.accumulate) return hipErrorInvalidValue;
+    half_pair_kernel<CfgQ128, CB, false, true><<<g, CfgQ128::NT, 0, s>>>(B, naux, (int)nao, npair, cm, out, tm, nA,
+                                                                          (int)a.r0, j);
+  } else if (out.alpha != 1.0 || out.accumulate) {
+    half_pair_kernel<CfgQ128, CB, true, false><<<g, CfgQ128::NT, 0, s>>>(B, naux, (int)nao, npair, cm, out, tm, nA,
+                                                                          (int)a.r0, j);
+  } else {
+    half_pair_kernel<CfgQ128, CB, false, false><<<g, CfgQ128::NT, 0, s>>>(B, naux, (int)nao, npair, cm, out, tm, nA,
+                                                                           (int)a.r0, j);
+  }
+  return hipGetLastError();
+}
+
 static hipError_t half_run(const double* B, int64_t naux, int64_t nao, const double* C, int64_t ldc, int64_t ncol,
                            const OutMap& out, JvEpi* jv, hipStream_t s) {
   HalfSeg seg[3];
@@ -1314,6 +1368,23 @@ static hipError_t half_run(const double* B, int64_t naux, int64_t nao, const dou
     jv->toff = 0;
   }
   for (int i = 0; i < n; ++i) {
+    // 128-wide tiles from column 0 and a one-tile remainder on the same rows: one launch
+    if (i + 1 < n && seg[i].cfg == kQ128 && seg[i].c0 == 0 && seg[i].c1 % CfgQ128::BN == 0 &&
+        seg[i + 1].r0 == seg[i].r0 && seg[i + 1].r1 == seg[i].r1 && seg[i + 1].c0 == seg[i].c1 &&
+        seg[i + 1].c1 - seg[i + 1].c0 <= half_cfg_cols(seg[i + 1].cfg) && half_cfg_rows(seg[i + 1].cfg) == 128) {
+      hipError_t e;
+      switch (seg[i + 1].cfg) {
+        case kQ128: e = half_pair_go<CfgQ128>(B, naux, nao, C, ldc, ncol, seg[i], out, jv, s); break;
+        case kQ96: e = half_pair_go<CfgQ96>(B, naux, nao, C, ldc, ncol, seg[i], out, jv, s); break;
+        case kQ64: e = half_pair_go<CfgQ64>(B, naux, nao, C, ldc, ncol, seg[i], out, jv, s); break;
+        case kH96: e = half_pair_go<CfgH96>(B, naux, nao, C, ldc, ncol, seg[i], out, jv, s); break;
+        default: e = half_pair_go<CfgH48>(B, naux, nao, C, ldc, ncol, seg[i], out, jv, s); break;
+      }
+      if (e != hipSuccess) return e;
+      if (jv) jv->toff += half_seg_tiles(seg[i]) + half_seg_tiles(seg[i + 1]);
+      ++i;
+      continue;
+    }
     hipError_t e;
     switch (seg[i].cfg) {
       case kH176: e = half_seg_go<CfgH176>(B, naux, nao, C, ldc, seg[i], out, jv, s); break;
