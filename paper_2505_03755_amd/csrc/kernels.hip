@@ -414,17 +414,13 @@ struct PairSrc {
 // Generic tiled product  C(m, n) = sum_k A(m, k) B(n, k)  over a batch (grid z).  With grid
 // y = nsplit > 1 each workgroup set covers a contiguous range of k slabs and writes its partial
 // sums to part[split][M][N] (nz must be 1 then).
+// Output tile (m0, n0) of batch z, split `split` of nsplit (partials to part when given).
 template <class C, bool AK, bool BK, bool GEN, bool CLAMP>
-__global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) gemm_kernel(OpMap A, OpMap B, OutMap O, int64_t tilesM, int64_t tilesN,
-                                                     double* part) {
-  __shared__ double smem[2 * C::STAGE];
+__device__ __forceinline__ void gemm_tile(const OpMap& A, const OpMap& B, const OutMap& O, int64_t m0, int64_t n0,
+                                          int64_t z, int nsplit, int split, double* part, double* smem) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave % C::WM, wn = wave / C::WM;
-  const int64_t tile = xcd_remap(blockIdx.x, tilesM * tilesN);
-  const int64_t z = blockIdx.z;
-  const int64_t m0 = (tile % tilesM) * C::BM, n0 = (tile / tilesM) * C::BN;
   const int64_t nslab_all = A.kb_n * ((A.kc_n + C::BK - 1) / C::BK);
-  const int nsplit = gridDim.y, split = blockIdx.y;
   const int64_t s0 = nslab_all * split / nsplit, s1 = nslab_all * (split + 1) / nsplit;
 
   d4 acc[C::TM][C::TN];
@@ -444,6 +440,33 @@ __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2)))
   } else {
     store_tile<C, GEN>(O, z, m0, n0, acc, wm, wn, lane);
   }
+}
+
+template <class C, bool AK, bool BK, bool GEN, bool CLAMP>
+__global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2))) gemm_kernel(OpMap A, OpMap B, OutMap O, int64_t tilesM, int64_t tilesN,
+                                                     double* part) {
+  __shared__ double smem[2 * C::STAGE];
+  const int64_t tile = xcd_remap(blockIdx.x, tilesM * tilesN);
+  const int64_t m0 = (tile % tilesM) * C::BM, n0 = (tile / tilesM) * C::BN;
+  gemm_tile<C, AK, BK, GEN, CLAMP>(A, B, O, m0, n0, blockIdx.z, gridDim.y, blockIdx.y, part, smem);
+}
+
+// Rows in whole 128-row bands on 128 x 128 tiles and the rest (at most 64 rows) on 64 x 128 tiles
+// (4 waves of 64 x 32), in one launch: per column block the band tiles, then the tail tile.
+// Where the 256 x 128 or 128 x 128 tiles would pad the rows by more than 64 (1200 rows: 1280).
+typedef Cfg<1, 4, 4, 2, true> CfgRowTail;
+template <bool AK, bool BK>
+__global__ void __launch_bounds__(CfgSq::NT) __attribute__((amdgpu_waves_per_eu(2))) gemm_tail_kernel(OpMap A, OpMap B, OutMap O, int64_t nband, int64_t tilesN) {
+  static_assert(CfgRowTail::NT == CfgSq::NT && CfgRowTail::BN == CfgSq::BN && CfgRowTail::STAGE <= CfgSq::STAGE,
+                "one workgroup shape and column block");
+  __shared__ double smem[2 * CfgSq::STAGE];
+  const int64_t per = nband + 1;
+  const int64_t tile = xcd_remap(blockIdx.x, per * tilesN);
+  const int64_t i = tile % per, n0 = (tile / per) * CfgSq::BN;
+  if (i < nband)
+    gemm_tile<CfgSq, AK, BK, false, false>(A, B, O, i * CfgSq::BM, n0, 0, 1, 0, nullptr, smem);
+  else
+    gemm_tile<CfgRowTail, AK, BK, false, false>(A, B, O, nband * CfgSq::BM, n0, 0, 1, 0, nullptr, smem);
 }
 
 // C(m, n) = alpha * sum_s part[s][m][n] (+ C), fixed order over s.
@@ -1460,6 +1483,19 @@ static hipError_t gemm_launch_cfg(const OpMap& A, const OpMap& Bm, const OutMap&
 
 static hipError_t gemm_launch(const OpMap& A, const OpMap& Bm, const OutMap& O, int64_t nz, int nsplit,
                               double* part, hipStream_t s) {
+  const int64_t rem = O.M % CfgSq::BM, tn = cdiv(O.N, CfgSq::BN);
+  if (gemm_tall(O.M) && rem > 0 && rem <= CfgRowTail::BM && nz == 1 && nsplit == 1 && !part && O.alpha == 1.0 &&
+      !O.accumulate && A.kc_n % 16 == 0 && (O.M / CfgSq::BM + 1) * tn <= 0x7fffffffLL && offsets_fit(A) &&
+      offsets_fit(Bm) && A.kc_n == Bm.kc_n && A.kb_n == Bm.kb_n) {
+    const int64_t nband = O.M / CfgSq::BM;
+    const dim3 grid((unsigned)((nband + 1) * tn));
+    const bool ak = A.s_kc == 1, bk = Bm.s_kc == 1;
+    if (ak && bk) gemm_tail_kernel<true, true><<<grid, CfgSq::NT, 0, s>>>(A, Bm, O, nband, tn);
+    else if (ak) gemm_tail_kernel<true, false><<<grid, CfgSq::NT, 0, s>>>(A, Bm, O, nband, tn);
+    else if (bk) gemm_tail_kernel<false, true><<<grid, CfgSq::NT, 0, s>>>(A, Bm, O, nband, tn);
+    else gemm_tail_kernel<false, false><<<grid, CfgSq::NT, 0, s>>>(A, Bm, O, nband, tn);
+    return hipGetLastError();
+  }
   return gemm_tall(O.M) ? gemm_launch_cfg<CfgTall>(A, Bm, O, nz, nsplit, part, s)
                         : gemm_launch_cfg<CfgSq>(A, Bm, O, nz, nsplit, part, s);
 }
