@@ -1702,8 +1702,9 @@ static hipError_t syrk_go(const OpMap& A, const OpMap& Bw, int64_t n, int64_t nz
   // contraction chunks that are not whole slabs: one flat contraction (no padded slabs) unless
   // weighted or shorter than a slab
   const bool flat = clamp && !Bw.ks && flat_pays(A) && flat_fits(A);
-  if (Bw.ks && clamp) syrk_kernel<Cg, true, true><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
-  else if (Bw.ks) syrk_kernel<Cg, true, false><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
+  // weighted: the clamping loader in every case (without it the weighted 128-wide tiles need more
+  // than 256 registers per lane and run one wave per SIMD)
+  if (Bw.ks) syrk_kernel<Cg, true, true><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
   else if (flat) syrk_kernel<Cg, false, false, true><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
   else if (clamp) syrk_kernel<Cg, false, true><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
   else syrk_kernel<Cg, false, false><<<grid, Cg::NT, 0, s>>>(A, Bw, n, nz, nsplit, npairs, Kpart);
