@@ -311,14 +311,18 @@ __global__ void __launch_bounds__(256) split_packed_t_kernel(const double* __res
 }
 
 // ---------------------------------------------------------------------------------------
-// Slice product.  Workgroup tile 128 x 64 over 8 waves (4 x 2) of 32 x 32, one
-// v_mfma_i32_32x32x32_i8 per slice pair and 32-deep k step.  Each k step moves S (4 + 2) blocks
-// of 1 KB from HBM / L2 straight into LDS (global_load_lds, no staging registers), three LDS
-// stages deep; a wave reads its S + S operand fragments as one 16-byte LDS read per lane each.
-// One int32 accumulator per slice diagonal d = s + t (exact over kMaxSteps steps = 32768 k, so
-// every split is at most that long and no FP64 sums are kept in the loop).  About 200 registers
-// per lane: two waves per SIMD.  With `tri` (M == N), tiles wholly above the diagonal exit.
-constexpr int kGM = 128, kGN = 64, kKS = 32, kStages = 3;
+// Slice product.  Workgroup tile 64 x 64 over 4 waves (2 x 2) of 32 x 32, one
+// v_mfma_i32_32x32x32_i8 per slice pair and 32-deep k step.  Each k step moves S (2 + 2) blocks
+// of 1 KB from HBM / L2 straight into LDS (global_load_lds, no staging registers), two LDS
+// stages deep (56 KB at S = 7); a wave reads its S + S operand fragments as one 16-byte LDS read
+// per lane each.  One int32 accumulator per slice diagonal d = s + t (exact over kMaxSteps steps =
+// 32768 k, so every split is at most that long and no FP64 sums are kept in the loop).  About 170
+// registers per lane.  Two workgroups share each CU (two waves per SIMD from different
+// workgroups), so one workgroup's barrier and load waits hide behind the other's MFMAs; a single
+// workgroup of 8 waves on 128 x 64 tiles with three stages, every wave at the same barrier, took
+// 66.2 ms for the paper-scale half transform against 62.9 ms.  With `tri` (M == N), tiles wholly
+// above the diagonal exit.
+constexpr int kGM = 64, kGN = 64, kKS = 32, kStages = 2, kWaves = 4;
 constexpr int kMaxSteps = 1024;
 
 template <int S>
@@ -326,14 +330,14 @@ struct SliceTile {
   static constexpr int GA = kGM / 32, GB = kGN / 32;
   static constexpr int NBLK = S * (GA + GB);        // blocks per k step
   static constexpr int STAGE = NBLK * 1024;
-  static constexpr int LPW = (NBLK + 7) / 8;        // direct loads per wave and step (at most)
-  static constexpr int LPW_MIN = NBLK / 8;          // ... and at least
+  static constexpr int LPW = (NBLK + kWaves - 1) / kWaves;   // direct loads per wave and step (at most)
+  static constexpr int LPW_MIN = NBLK / kWaves;               // ... and at least
 };
 
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
 template <int S, bool GEN>
-__global__ void __launch_bounds__(512, 1) slice_gemm_kernel(const int8_t* __restrict__ Ap, const int* __restrict__ ea,
+__global__ void __launch_bounds__(64 * kWaves, 2) slice_gemm_kernel(const int8_t* __restrict__ Ap, const int* __restrict__ ea,
                                                             int64_t M, const int8_t* __restrict__ Bp,
                                                             const int* __restrict__ eb, int64_t N, int64_t KB,
                                                             OutMap O, int64_t tilesM, int64_t tilesN, int tri,
@@ -348,7 +352,7 @@ __global__ void __launch_bounds__(512, 1) slice_gemm_kernel(const int8_t* __rest
   eb += z * zs.eb;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int wm = wave & 3, wn = wave >> 2;
+  const int wm = wave % (kGM / 32), wn = wave / (kGM / 32);
   const int nsplit = gridDim.y, split = blockIdx.y;
   const int64_t tile = xcd_remap_i8(blockIdx.x, tilesM * tilesN);
   const int64_t I = tile / tilesN, J = tile % tilesN;   // column tiles of one row band side by side
@@ -356,12 +360,12 @@ __global__ void __launch_bounds__(512, 1) slice_gemm_kernel(const int8_t* __rest
   const int64_t GAn = (M + 31) / 32, GBn = (N + 31) / 32;
   const int64_t ks0 = KB * split / nsplit, ks1 = KB * (split + 1) / nsplit;
 
-  // this wave's direct loads: blocks j = wave + 8 i of the step (A blocks s * GA + g first)
+  // this wave's direct loads: blocks j = wave + kWaves i of the step (A blocks s * GA + g first)
   const int8_t* gp[T::LPW];
   int loff[T::LPW];
 #pragma unroll
   for (int i = 0; i < T::LPW; ++i) {
-    int j = wave + 8 * i;
+    int j = wave + kWaves * i;
     if (j >= T::NBLK) j = T::NBLK - 1;   // unused slot (never issued)
     loff[i] = j * 1024;
     if (j < S * T::GA) {
@@ -379,7 +383,7 @@ __global__ void __launch_bounds__(512, 1) slice_gemm_kernel(const int8_t* __rest
   auto issue = [&](int st, int64_t ks) {
 #pragma unroll
     for (int i = 0; i < T::LPW; ++i)
-      if (i < T::LPW_MIN || wave + 8 * i < T::NBLK)
+      if (i < T::LPW_MIN || wave + kWaves * i < T::NBLK)
         __builtin_amdgcn_global_load_lds((const void*)(gp[i] + ks * 1024), (lds_ptr_t)(lds + st * T::STAGE + loff[i]),
                                          16, 0, 0);
   };
@@ -399,8 +403,10 @@ __global__ void __launch_bounds__(512, 1) slice_gemm_kernel(const int8_t* __rest
     if (ks0 + p < ks1) issue(p, ks0 + p);
   int st = 0;
   for (int64_t ks = ks0; ks < ks1; ++ks) {
-    // this wave's loads of step ks have landed once at most the next step's are outstanding
-    if (ks + 1 < ks1) __builtin_amdgcn_s_waitcnt(kVmcnt<T::LPW_MIN>::imm);
+    // this wave's loads of step ks have landed once at most the later steps' are outstanding
+    // (with two stages none are: step ks + 1 is issued after this barrier)
+    constexpr int kLater = T::LPW_MIN * (kStages > 2 ? kStages - 2 : 0);
+    if (kLater > 0 && ks + 1 < ks1) __builtin_amdgcn_s_waitcnt(kVmcnt<kLater>::imm);
     else __builtin_amdgcn_s_waitcnt(kVmcnt<0>::imm);
     // every wave's loads of step ks are in LDS, and its reads of step ks - 1 (into the stage the
     // next issue overwrites) are done.  A plain barrier: a workgroup fence would also wait for
@@ -577,8 +583,8 @@ static void slice_gemm_s(const int8_t* A, const int* ea, int64_t M, const int8_t
   const int64_t tm = slice_tiles_m(M), tn = slice_tiles_n(N);
   const dim3 grid((unsigned)(tm * tn), (unsigned)nsplit, (unsigned)nz);
   const bool gen = !part && (O.alpha != 1.0 || O.accumulate);
-  if (gen) slice_gemm_kernel<S, true><<<grid, 512, 0, s>>>(A, ea, M, B, eb, N, kp / kKS, O, tm, tn, tri, part, zs);
-  else slice_gemm_kernel<S, false><<<grid, 512, 0, s>>>(A, ea, M, B, eb, N, kp / kKS, O, tm, tn, tri, part, zs);
+  if (gen) slice_gemm_kernel<S, true><<<grid, 64 * kWaves, 0, s>>>(A, ea, M, B, eb, N, kp / kKS, O, tm, tn, tri, part, zs);
+  else slice_gemm_kernel<S, false><<<grid, 64 * kWaves, 0, s>>>(A, ea, M, B, eb, N, kp / kKS, O, tm, tn, tri, part, zs);
 }
 
 hipError_t launch_slice_gemm(const int8_t* A, const int* ea, int64_t M, const int8_t* B, const int* eb, int64_t N,
