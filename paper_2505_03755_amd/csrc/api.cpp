@@ -2779,14 +2779,14 @@ static df_status split_problem_run(df_ctx* c, char* ws, const df_problem& q, con
     // for all densities in one batched launch, lower tiles, reduced and mirrored
     int8_t* xs = planes(b.xos);
     int* xe = exps(b.xos);
-    for (int64_t z = 0; z < q.ndm; ++z) {
-      dfk::OpMap ox = dfk::op_map(Xo + z * q.nocc, nao, no, q.nocc, 1);
-      ox.kb_n = naux;
-      ox.s_kb = nao * no;
-      DF_LAUNCH(DF_KERNEL_SPLIT,
-                dfk::launch_split_rows(ox, naux * q.nocc, nslice, xs + z * b.xplane, xe + z * nao, c->stream),
-                "split launch");
-    }
+    // every density's rows in one launch set: density z at Xo + z nocc
+    dfk::OpMap ox = dfk::op_map(Xo, nao, no, q.nocc, 1);
+    ox.kb_n = naux;
+    ox.s_kb = nao * no;
+    ox.s_z = q.nocc;
+    DF_LAUNCH(DF_KERNEL_SPLIT,
+              dfk::launch_split_rows_batched(ox, naux * q.nocc, nslice, xs, xe, q.ndm, b.xplane, nao, c->stream),
+              "split launch");
     double* kpart = (double*)(ws + b.kpart);
     const dfk::SliceBatch zs{b.xplane, nao, b.xplane, nao};
     DF_LAUNCH(DF_KERNEL_K_SYRK,

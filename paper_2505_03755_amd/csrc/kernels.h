@@ -199,6 +199,10 @@ int64_t split_plane_bytes(int64_t rows, int64_t K, int nslice);
 // Splits each row r < o.rows of the operand (k over kb_n * kc_n = K) into nslice int8 planes
 // (zeros past K and past o.rows) and its exponent ex[r].  nslice in [4, 8].
 hipError_t launch_split_rows(const OpMap& o, int64_t K, int nslice, int8_t* planes, int* ex, hipStream_t s);
+// The same for nz operands in one launch set (grid z): operand z at o.p + z o.s_z, its planes at
+// planes + z plane_stride, its exponents at ex + z ex_stride (ex_stride >= o.rows).  nz <= 65535.
+hipError_t launch_split_rows_batched(const OpMap& o, int64_t K, int nslice, int8_t* planes, int* ex, int64_t nz,
+                                     int64_t plane_stride, int64_t ex_stride, hipStream_t s);
 // The same for the rows (P, m) of the unpacked b^P (rows naux*nao, K = nao).
 hipError_t launch_split_packed(const double* B, int64_t naux, int64_t nao, int nslice, int8_t* planes, int* ex,
                                hipStream_t s);

@@ -110,7 +110,10 @@ __global__ void __launch_bounds__(256) fill_int_kernel(int* p, int64_t n, int v)
   if (i < n) p[i] = v;
 }
 
-__global__ void __launch_bounds__(256) split_max_kernel(OpMap o, int64_t K, int64_t r0, int* ex) {
+// grid z: operand z of a batch at o.p + z o.s_z, exponents at ex + z exs
+__global__ void __launch_bounds__(256) split_max_kernel(OpMap o, int64_t K, int64_t r0, int* ex, int64_t exs) {
+  o.p += (int64_t)blockIdx.z * o.s_z;
+  ex += (int64_t)blockIdx.z * exs;
   const int64_t r = r0 + blockIdx.y, k0 = (int64_t)blockIdx.x * kSplitChunk;
   const double* row = opmap_row(o, r);
   double m = 0.0;
@@ -127,7 +130,9 @@ __global__ void __launch_bounds__(256) split_max_kernel(OpMap o, int64_t K, int6
 // apart): 32 rows x kSplitChunkR k per workgroup with the lanes along the rows, so that every
 // load reads 32 consecutive rows.
 constexpr int kSplitChunkR = 256;
-__global__ void __launch_bounds__(256) split_max_rows_kernel(OpMap o, int64_t K, int64_t y0, int* ex) {
+__global__ void __launch_bounds__(256) split_max_rows_kernel(OpMap o, int64_t K, int64_t y0, int* ex, int64_t exs) {
+  o.p += (int64_t)blockIdx.z * o.s_z;
+  ex += (int64_t)blockIdx.z * exs;
   const int t = threadIdx.x, rr = t & 31, kk = t >> 5;
   const int64_t r = 32 * (int64_t)blockIdx.x + rr, k0 = (y0 + blockIdx.y) * kSplitChunkR;
   double m = 0.0;
@@ -171,7 +176,10 @@ __device__ __forceinline__ void write_slot(double (&x)[16], int8_t* planes, int6
 // 16 k at 16 (t / 32)) of its block in every plane; rows past o.rows are zero.
 template <int S>
 __global__ void __launch_bounds__(256) split_slice_kernel(OpMap o, int64_t K, int64_t kp, int64_t y0, int8_t* planes,
-                                                          const int* ex) {
+                                                          const int* ex, int64_t ps, int64_t exs) {
+  o.p += (int64_t)blockIdx.z * o.s_z;
+  planes += (int64_t)blockIdx.z * ps;
+  ex += (int64_t)blockIdx.z * exs;
   const int t = threadIdx.x, rr = t & 31;
   const int64_t g = blockIdx.x, kq = (y0 + blockIdx.y) * 8 + (t >> 5);   // 16-k chunk
   if (16 * kq >= kp) return;
@@ -197,8 +205,12 @@ __global__ void __launch_bounds__(256) split_slice_kernel(OpMap o, int64_t K, in
 // the workgroup are first read along k into LDS (coalesced), then cut slot by slot.
 template <int S>
 __global__ void __launch_bounds__(256) split_slice_kmajor_kernel(OpMap o, int64_t K, int64_t kp, int64_t y0,
-                                                                 int8_t* planes, const int* ex) {
+                                                                 int8_t* planes, const int* ex, int64_t ps,
+                                                                 int64_t exs) {
   __shared__ double tile[32][129];
+  o.p += (int64_t)blockIdx.z * o.s_z;
+  planes += (int64_t)blockIdx.z * ps;
+  ex += (int64_t)blockIdx.z * exs;
   const int t = threadIdx.x;
   const int64_t g = blockIdx.x, k0 = (y0 + blockIdx.y) * 128;
   {
@@ -466,45 +478,60 @@ int64_t rpad32(int64_t n) { return (n + 31) / 32 * 32; }
 int64_t split_plane_bytes(int64_t rows, int64_t K, int nslice) { return (int64_t)nslice * rpad32(rows) * kpad64(K); }
 
 template <int S>
-static hipError_t split_rows_s(const OpMap& o, int64_t K, int8_t* planes, int* ex, hipStream_t s) {
+static hipError_t split_rows_s(const OpMap& o, int64_t K, int8_t* planes, int* ex, int64_t nz, int64_t ps,
+                               int64_t exs, hipStream_t s) {
   const int64_t kp = kpad64(K);
-  const unsigned ng = (unsigned)(rpad32(o.rows) / 32);
+  const unsigned ng = (unsigned)(rpad32(o.rows) / 32), z = (unsigned)nz;
   // rows adjacent in memory with the contraction index elsewhere: lanes along the rows
   const bool rows_adjacent = o.s_rlo == 1 && o.s_kc != 1;
-  fill_int_kernel<<<(unsigned)((o.rows + 255) / 256), 256, 0, s>>>(ex, o.rows, kNoExponent);
+  if (exs == o.rows || nz == 1) {
+    fill_int_kernel<<<(unsigned)((o.rows * nz + 255) / 256), 256, 0, s>>>(ex, o.rows * nz, kNoExponent);
+  } else {
+    for (int64_t i = 0; i < nz; ++i)
+      fill_int_kernel<<<(unsigned)((o.rows + 255) / 256), 256, 0, s>>>(ex + i * exs, o.rows, kNoExponent);
+  }
   if (rows_adjacent) {
     const int64_t ny = (K + kSplitChunkR - 1) / kSplitChunkR;
     for (int64_t y0 = 0; y0 < ny; y0 += 65535) {
       const unsigned n = (unsigned)(ny - y0 < 65535 ? ny - y0 : 65535);
-      split_max_rows_kernel<<<dim3(ng, n), 256, 0, s>>>(o, K, y0, ex);
+      split_max_rows_kernel<<<dim3(ng, n, z), 256, 0, s>>>(o, K, y0, ex, exs);
     }
   } else {
     for (int64_t r0 = 0; r0 < o.rows; r0 += 65535) {   // grid y carries the row
       const unsigned nr = (unsigned)(o.rows - r0 < 65535 ? o.rows - r0 : 65535);
-      split_max_kernel<<<dim3((unsigned)((K + kSplitChunk - 1) / kSplitChunk), nr), 256, 0, s>>>(o, K, r0, ex);
+      split_max_kernel<<<dim3((unsigned)((K + kSplitChunk - 1) / kSplitChunk), nr, z), 256, 0, s>>>(o, K, r0, ex,
+                                                                                                    exs);
     }
   }
   const int64_t ny = (kp + 127) / 128;   // grid y carries 128 k
   for (int64_t y0 = 0; y0 < ny; y0 += 65535) {
     const unsigned n = (unsigned)(ny - y0 < 65535 ? ny - y0 : 65535);
-    if (o.s_kc == 1) split_slice_kmajor_kernel<S><<<dim3(ng, n), 256, 0, s>>>(o, K, kp, y0, planes, ex);
-    else split_slice_kernel<S><<<dim3(ng, n), 256, 0, s>>>(o, K, kp, y0, planes, ex);
+    if (o.s_kc == 1) split_slice_kmajor_kernel<S><<<dim3(ng, n, z), 256, 0, s>>>(o, K, kp, y0, planes, ex, ps, exs);
+    else split_slice_kernel<S><<<dim3(ng, n, z), 256, 0, s>>>(o, K, kp, y0, planes, ex, ps, exs);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_split_rows(const OpMap& o, int64_t K, int nslice, int8_t* planes, int* ex, hipStream_t s) {
-  if (o.rows <= 0) return hipSuccess;
-  if (rpad32(o.rows) > 0x7fffffffLL || K <= 0 || (K + kSplitChunk - 1) / kSplitChunk > 0x7fffffffLL)
+hipError_t launch_split_rows_batched(const OpMap& o, int64_t K, int nslice, int8_t* planes, int* ex, int64_t nz,
+                                     int64_t plane_stride, int64_t ex_stride, hipStream_t s) {
+  if (o.rows <= 0 || nz == 0) return hipSuccess;
+  if (rpad32(o.rows) > 0x7fffffffLL || K <= 0 || (K + kSplitChunk - 1) / kSplitChunk > 0x7fffffffLL || nz < 0 ||
+      nz > 65535 || (nz > 1 && ex_stride < o.rows))
     return hipErrorInvalidValue;
   switch (nslice) {
-    case 4: return split_rows_s<4>(o, K, planes, ex, s);
-    case 5: return split_rows_s<5>(o, K, planes, ex, s);
-    case 6: return split_rows_s<6>(o, K, planes, ex, s);
-    case 7: return split_rows_s<7>(o, K, planes, ex, s);
-    case 8: return split_rows_s<8>(o, K, planes, ex, s);
+    case 4: return split_rows_s<4>(o, K, planes, ex, nz, plane_stride, ex_stride, s);
+    case 5: return split_rows_s<5>(o, K, planes, ex, nz, plane_stride, ex_stride, s);
+    case 6: return split_rows_s<6>(o, K, planes, ex, nz, plane_stride, ex_stride, s);
+    case 7: return split_rows_s<7>(o, K, planes, ex, nz, plane_stride, ex_stride, s);
+    case 8: return split_rows_s<8>(o, K, planes, ex, nz, plane_stride, ex_stride, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_split_rows(const OpMap& o, int64_t K, int nslice, int8_t* planes, int* ex, hipStream_t s) {
+  OpMap o1 = o;
+  o1.s_z = 0;
+  return launch_split_rows_batched(o1, K, nslice, planes, ex, 1, 0, 0, s);
 }
 
 template <int S>
