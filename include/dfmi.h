@@ -523,9 +523,9 @@ df_status df_step_split(df_ctx* ctx, const double* B, const int8_t* Bs, const in
                         double* Xocc, double* Xact, int flags);
 
 /*
- * df_step_backward in split precision: the exchange part, Y_P = S X_P and sum_P b^P Y_P with
- * S = gK + gK^T, as slice products against Bt, Bte (df_split_cholesky_t, same nslice).  The
- * Coulomb part (2 M Cocc) and the active-space part stay FP64, as in df_step_backward.
+ * df_step_backward in split precision: in the exchange part, Y_P = S X_P (S = gK + gK^T) in
+ * FP64 and sum_P b^P Y_P as a slice product against Bt, Bte (df_split_cholesky_t, same nslice).
+ * The Coulomb part (2 M Cocc) and the active-space part stay FP64, as in df_step_backward.
  * Xocc is required with gK and Xact with geri; there is no recomputation here.  Arguments,
  * outputs and cotangent rules are otherwise as in df_step_backward; nao <= 32768.
  * Workspace: df_workspace_size(DF_OP_STEP_BACKWARD_SPLIT, {naux, nao, 1, nocc, nac, nslice,

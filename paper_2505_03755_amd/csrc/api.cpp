@@ -476,7 +476,7 @@ StepSplitPlan plan_step_split(Plan& pl, int64_t naux, int64_t nao, int64_t nocc,
 struct BwdSplitPlan {
   BwdPlan f;
   size_t S, Y, part;
-  SplitBuf ss, xs, ys;
+  SplitBuf ys;
   int nsk;
 };
 BwdSplitPlan plan_backward_split(Plan& pl, int64_t naux, int64_t nao, int64_t nocc, int64_t nac, int flags,
@@ -487,8 +487,6 @@ BwdSplitPlan plan_backward_split(Plan& pl, int64_t naux, int64_t nao, int64_t no
   if ((flags & DF_BWD_GK) && nocc > 0) {
     p.S = pl.take(nao * nao);
     p.Y = pl.take(naux * nao * nocc);   // P-major [naux][nao][nocc]
-    p.ss = take_split(pl, nao, nao, nslice);
-    p.xs = take_split(pl, naux * nocc, nao, nslice);
     p.ys = take_split(pl, nocc, naux * nao, nslice);
     p.nsk = slice_splits(dfk::slice_gemm_tiles(nao, nocc, false), dfk::slice_gemm_steps(dfk::kpad64(naux * nao)));
     p.part = pl.take(p.nsk > 1 ? (int64_t)p.nsk * nao * nocc : 0);
@@ -2427,31 +2425,24 @@ df_status df_step_backward_split(df_ctx* ctx, const double* B, const int8_t* Bt,
   if (do_j)
     if (df_status s = bwd_coulomb(c, ws, p.f, B, naux, nao, gJ, Cocc, nocc, dCocc)) return s;
   if (do_k) {
-    // dCocc += sum_P b^P Y_P,  Y_P = S X_P,  S = gK + gK^T, both products from int8 slices
+    // dCocc += sum_P b^P Y_P,  Y_P = S X_P,  S = gK + gK^T.  Y_P in FP64 (the tall product of
+    // the FP64 adjoint: it takes about what the slice product takes, and needs no split of S and
+    // X), the sum over (P, nu) from int8 slices of B and Y
     double* S = (double*)(ws + p.S);
     double* Y = (double*)(ws + p.Y);
     DF_LAUNCH(DF_KERNEL_OTHER, dfk::launch_symmetrize(gK, nao, 1, S, c->stream), "symmetrize");
-    const int64_t kpo = dfk::kpad64(nao), kpb = dfk::kpad64(naux * nao);
-    int8_t* ss = (int8_t*)(ws + p.ss.planes);
-    int* se = (int*)(ws + p.ss.ex);
-    int8_t* xs = (int8_t*)(ws + p.xs.planes);
-    int* xe = (int*)(ws + p.xs.ex);
+    const int64_t kpb = dfk::kpad64(naux * nao);
     int8_t* ys = (int8_t*)(ws + p.ys.planes);
     int* ye = (int*)(ws + p.ys.ex);
-    // rows mu of S over nu; rows (P, i) of X over nu
-    DF_LAUNCH(DF_KERNEL_SPLIT, dfk::launch_split_rows(dfk::op_map(S, nao, nao, nao, 1), nao, nslice, ss, se, c->stream),
-              "split launch");
-    dfk::OpMap ox = dfk::op_map(Xocc, naux * nocc, 1, nao, nocc);
-    ox.rl = nocc;
-    ox.s_rh = nao * nocc;
-    DF_LAUNCH(DF_KERNEL_SPLIT, dfk::launch_split_rows(ox, nao, nslice, xs, xe, c->stream), "split launch");
     // Y[P][mu][i] = sum_nu S[mu][nu] X[P][nu][i]
+    dfk::OpMap Xm = dfk::op_map(Xocc, naux * nocc, 1, nao, nocc);
+    Xm.rl = nocc;
+    Xm.s_rh = nao * nocc;
     dfk::OutMap OY = dfk::out_plain(Y, nao, naux * nocc, nocc);
     OY.nl = nocc;
     OY.s_nh = nao * nocc;
-    DF_LAUNCH(DF_KERNEL_ADJOINT,
-              dfk::launch_slice_gemm(ss, se, nao, xs, xe, naux * nocc, kpo, nslice, OY, false, 1, nullptr, c->stream),
-              "slice product launch");
+    DF_LAUNCH(DF_KERNEL_ADJOINT, dfk::launch_gemm(dfk::op_map(S, nao, nao, nao, 1), Xm, OY, 1, c->stream),
+              "adjoint product");
     // rows i of Y over (P, nu); then dCocc[mu][i] += sum_{P, nu} b^P_{mu nu} Y[P][nu][i]
     dfk::OpMap oy = dfk::op_map(Y, nocc, 1, nao, nocc);
     oy.kb_n = naux;

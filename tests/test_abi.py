@@ -268,7 +268,7 @@ def test_split_adjoint_argument_errors(L, ctx):
     assert s(ctx, B, Bs, Be, 7, 10, 7, Co, 3, Ca, 2, Cp, 7, J, K, None, None, None, Xo, None, 0) == dfmi.DF_ERR_ARG
     w = dfmi.workspace_size(dfmi.DF_OP_STEP_BACKWARD_SPLIT, naux=20, nao=9, nocc=4, nac=2, nslice=7,
                             flags=dfmi.DF_BWD_GK)
-    assert w >= 7 * 32 * 192 + 7 * 96 * 64      # planes of Y (rows i over (P, nu)) and of X
+    assert w >= 7 * 32 * 192 + 8 * 20 * 9 * 4   # planes of Y (rows i over (P, nu)) and Y itself (FP64)
     assert dfmi.workspace_size(dfmi.DF_OP_STEP_BACKWARD_SPLIT, naux=20, nao=9, nocc=4, nac=2, nslice=7) < w
 
 
