@@ -143,7 +143,9 @@ const char* df_last_error(const df_ctx* ctx);
 /* Change the stream later calls enqueue onto. */
 df_status df_set_stream(df_ctx* ctx, void* stream);
 
-/* Attach caller-owned device memory of `bytes` bytes as the workspace (NULL, 0 detaches). */
+/* Attach caller-owned device memory of `bytes` bytes as the workspace (NULL, 0 detaches).
+ * ptr must be 256-byte aligned (DF_ERR_ARG otherwise); 4096-byte alignment keeps the int8
+ * planes of the split-precision calls, placed on 4 KB offsets, in whole 1 KB blocks per page. */
 df_status df_set_workspace(df_ctx* ctx, void* ptr, size_t bytes);
 
 /* Per-kernel timing.  While enabled, every launch the context makes is bracketed by two HIP
@@ -492,7 +494,8 @@ df_status df_split_matmul(df_ctx* ctx, const double* A, int64_t lda, int64_t M, 
  *   16-byte slot rr + 32 c holding k = 32 b + 16 c + [0, 16) of row 32 g + rr; zeros past the
  *   last row and past nao.  Row r = P * nao + mu is b^P_{mu, k} over k.
  *   Be [naux * nao] int32 exponents; both caller-owned device buffers, overwritten; Bs 16-byte
- *   aligned (DF_ERR_ARG otherwise).  naux * nao <= 2^31 - 32.  No workspace.
+ *   aligned (DF_ERR_ARG otherwise; 1 KB alignment, no block across a page, reads fastest).
+ *   naux * nao <= 2^31 - 32.  No workspace.
  */
 df_status df_split_cholesky(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int nslice, int8_t* Bs,
                             int* Be, int flags);
@@ -502,7 +505,7 @@ df_status df_split_cholesky(df_ctx* ctx, const double* B, int64_t naux, int64_t 
  * k = P * nao + nu (element b^P_{mu nu}), for df_step_backward_split.
  *   Bt: nslice * rpad32(nao) * kpad64(naux * nao) int8 in the block layout of Bs (rows mu),
  *   Bte [nao] int32 exponents (of max over P and nu of |b^P_{mu nu}|); caller-owned device
- *   buffers, overwritten; Bt 16-byte aligned.  naux * nao <= 2^30.  No workspace.
+ *   buffers, overwritten; Bt 16-byte aligned (1 KB reads fastest).  naux * nao <= 2^30.  No workspace.
  */
 df_status df_split_cholesky_t(df_ctx* ctx, const double* B, int64_t naux, int64_t nao, int nslice, int8_t* Bt,
                               int* Bte, int flags);
