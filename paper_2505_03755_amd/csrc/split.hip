@@ -110,11 +110,15 @@ __global__ void __launch_bounds__(256) fill_int_kernel(int* p, int64_t n, int v)
   if (i < n) p[i] = v;
 }
 
-// grid z: operand z of a batch at o.p + z o.s_z, exponents at ex + z exs
-__global__ void __launch_bounds__(256) split_max_kernel(OpMap o, int64_t K, int64_t r0, int* ex, int64_t exs) {
-  o.p += (int64_t)blockIdx.z * o.s_z;
-  ex += (int64_t)blockIdx.z * exs;
-  const int64_t r = r0 + blockIdx.y, k0 = (int64_t)blockIdx.x * kSplitChunk;
+// Operand z of a batch at o.p + z o.s_z, exponents at ex + z exs.  Grid (k chunk, row, z), or with
+// zfast (z, row, k chunk): then the workgroups dispatched together read the same rows and k of
+// adjacent operands, which for the densities of one X_occ are adjacent column runs.
+__global__ void __launch_bounds__(256) split_max_kernel(OpMap o, int64_t K, int64_t r0, int* ex, int64_t exs,
+                                                        int zfast) {
+  const int64_t z = zfast ? blockIdx.x : blockIdx.z, chunk = zfast ? blockIdx.z : blockIdx.x;
+  o.p += z * o.s_z;
+  ex += z * exs;
+  const int64_t r = r0 + blockIdx.y, k0 = chunk * kSplitChunk;
   const double* row = opmap_row(o, r);
   double m = 0.0;
   KWalk w(o, k0 + threadIdx.x, 256);
@@ -202,17 +206,19 @@ __global__ void __launch_bounds__(256) split_slice_kernel(OpMap o, int64_t K, in
 }
 
 // The same for operands whose contraction index is contiguous (s_kc = 1): the 32 rows x 128 k of
-// the workgroup are first read along k into LDS (coalesced), then cut slot by slot.
+// the workgroup are first read along k into LDS (coalesced), then cut slot by slot.  Grid
+// (row group, 128 k, z), or with zfast (z, 128 k, row group), as in split_max_kernel.
 template <int S>
 __global__ void __launch_bounds__(256) split_slice_kmajor_kernel(OpMap o, int64_t K, int64_t kp, int64_t y0,
                                                                  int8_t* planes, const int* ex, int64_t ps,
-                                                                 int64_t exs) {
+                                                                 int64_t exs, int zfast) {
   __shared__ double tile[32][129];
-  o.p += (int64_t)blockIdx.z * o.s_z;
-  planes += (int64_t)blockIdx.z * ps;
-  ex += (int64_t)blockIdx.z * exs;
+  const int64_t z = zfast ? blockIdx.x : blockIdx.z;
+  o.p += z * o.s_z;
+  planes += z * ps;
+  ex += z * exs;
   const int t = threadIdx.x;
-  const int64_t g = blockIdx.x, k0 = (y0 + blockIdx.y) * 128;
+  const int64_t g = zfast ? blockIdx.z : blockIdx.x, k0 = (y0 + blockIdx.y) * 128;
   {
     // element (32 g + (t >> 7) + 2 j, k0 + (t & 127)): one column k per thread
     const int64_t k = k0 + (t & 127);
@@ -497,16 +503,21 @@ static hipError_t split_rows_s(const OpMap& o, int64_t K, int8_t* planes, int* e
       split_max_rows_kernel<<<dim3(ng, n, z), 256, 0, s>>>(o, K, y0, ex, exs);
     }
   } else {
+    const int64_t nc = (K + kSplitChunk - 1) / kSplitChunk;
+    const bool zfast = nz > 1 && nc <= 65535;
     for (int64_t r0 = 0; r0 < o.rows; r0 += 65535) {   // grid y carries the row
       const unsigned nr = (unsigned)(o.rows - r0 < 65535 ? o.rows - r0 : 65535);
-      split_max_kernel<<<dim3((unsigned)((K + kSplitChunk - 1) / kSplitChunk), nr, z), 256, 0, s>>>(o, K, r0, ex,
-                                                                                                    exs);
+      const dim3 grid = zfast ? dim3(z, nr, (unsigned)nc) : dim3((unsigned)nc, nr, z);
+      split_max_kernel<<<grid, 256, 0, s>>>(o, K, r0, ex, exs, zfast ? 1 : 0);
     }
   }
   const int64_t ny = (kp + 127) / 128;   // grid y carries 128 k
+  const bool zfast = nz > 1 && ng <= 65535;
   for (int64_t y0 = 0; y0 < ny; y0 += 65535) {
     const unsigned n = (unsigned)(ny - y0 < 65535 ? ny - y0 : 65535);
-    if (o.s_kc == 1) split_slice_kmajor_kernel<S><<<dim3(ng, n, z), 256, 0, s>>>(o, K, kp, y0, planes, ex, ps, exs);
+    if (o.s_kc == 1)
+      split_slice_kmajor_kernel<S><<<zfast ? dim3(z, n, ng) : dim3(ng, n, z), 256, 0, s>>>(o, K, kp, y0, planes, ex,
+                                                                                          ps, exs, zfast ? 1 : 0);
     else split_slice_kernel<S><<<dim3(ng, n, z), 256, 0, s>>>(o, K, kp, y0, planes, ex, ps, exs);
   }
   return hipGetLastError();
