@@ -228,3 +228,35 @@ def test_step_backward_split_exchange_medium():
     torch.cuda.synchronize()
     K = O.exchange(Bp, wl.nao, Co)
     close(dCo, K @ Co, 1e-11)
+
+
+def test_split_results_do_not_depend_on_workspace_alignment():
+    """The slice planes sit on 4 KB offsets of the workspace; a workspace 256 bytes past such a
+    boundary (the least alignment the ABI takes) only moves them, so the split forward and the
+    split adjoint give the same bits."""
+    nao, naux, nocc, nac = 130, 90, 20, 5
+    Bp, C, gB, Bs, Be = split_problem(nao, naux, nocc, nac, 7, seed=3)
+    Bt, Bte = dfmi.split_cholesky_t(gB, nao, nslice=7)
+    Co, Ca = dev(C[:, :nocc].copy()), dev(C[:, nocc:nocc + nac].copy())
+    rng = np.random.default_rng(3)
+    gJ, gK, ge = dev(rng.standard_normal((nao, nao))), dev(rng.standard_normal((nao, nao))), \
+        dev(rng.standard_normal((nac,) * 4))
+    ctx = dfmi.Context(torch.device("cuda", 0))
+
+    def run():
+        out = dfmi.step_split(gB, Bs, Be, nao, Co, Ca, dev(C), keep_x=True, ctx=ctx)
+        dCo, dCa = dfmi.step_backward_split(gB, Bt, Bte, nao, Co, Ca, gJ, gK, ge, out["Xocc"], out["Xact"],
+                                            ctx=ctx)
+        torch.cuda.synchronize()
+        return [out[k].clone() for k in ("J", "K", "eri", "papa", "Xocc", "Xact")] + [dCo.clone(), dCa.clone()]
+
+    ref = run()
+    need = ctx._ws.numel()
+    big = torch.empty(need + 8192, dtype=torch.uint8, device="cuda")
+    base = (-big.data_ptr()) % 4096 + 256                 # 256 bytes past a 4 KB boundary
+    ctx._ws = big[base:base + need]
+    assert ctx._ws.data_ptr() % 4096 == 256
+    got = run()
+    assert ctx._ws.data_ptr() % 4096 == 256               # the call kept the offset workspace
+    for a, b in zip(ref, got):
+        assert torch.equal(a, b)
