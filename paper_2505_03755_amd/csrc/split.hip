@@ -371,8 +371,23 @@ __global__ void __launch_bounds__(64 * kWaves, 2) slice_gemm_kernel(const int8_t
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave % (kGM / 32), wn = wave / (kGM / 32);
-  const int nsplit = gridDim.y, split = blockIdx.y;
-  const int64_t tile = xcd_remap_i8(blockIdx.x, tilesM * tilesN);
+  // (tile, split) of this workgroup.  With the split count a multiple of 8, whole splits are dealt
+  // to the XCDs (workgroup L of the dispatch order runs on XCD L % 8): XCD x runs splits x, x + 8,
+  // ... each with all its tiles side by side, which stream the same operand rows of one k range
+  // through that XCD's L2 at about the same time.  Otherwise the tiles of each split are grouped
+  // per XCD.  Both are bijections of [0, tiles x nsplit).
+  const int nsplit = gridDim.y;
+  const int64_t ntile = tilesM * tilesN;
+  int split;
+  int64_t tile;
+  if (nsplit >= 8 && nsplit % 8 == 0) {
+    const int64_t L = blockIdx.x + (int64_t)gridDim.x * blockIdx.y, j = L / 8;
+    split = (int)(L % 8 + 8 * (j / ntile));
+    tile = j % ntile;
+  } else {
+    split = blockIdx.y;
+    tile = xcd_remap_i8(blockIdx.x, ntile);
+  }
   const int64_t I = tile / tilesN, J = tile % tilesN;   // column tiles of one row band side by side
   if (tri && J * kGN > I * kGM + kGM - 1) return;       // no element on or below the diagonal
   const int64_t GAn = (M + 31) / 32, GBn = (N + 31) / 32;
